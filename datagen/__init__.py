@@ -1,0 +1,331 @@
+"""Seeded synthetic inputs for the split-search path and its CPU oracle.
+
+This module only draws random numbers and arranges them into arrays. It holds
+none of the boosting arithmetic (no borders, bins, statistics, gradients or
+scores), so both the HIP path and the oracle may consume what it produces.
+
+The paper benchmarks on Epsilon, Criteo and eight public classification sets
+(Sec. 6, Tables 1-3), none of which are available here. The five workloads
+below are synthetic stand-ins with the shapes, value distributions and
+category-frequency skew of those workloads: dense numeric columns (Epsilon-like)
+and Zipf-distributed high-cardinality categorical columns (Criteo-like).
+
+Every stream is ``numpy.random.default_rng(SeedSequence([181011363, cfg, k]))``
+with k = 0 for numeric features, 1 for categorical values, 2 for labels,
+3 + r for permutation r and 100 + p for problem p of a batch.
+
+Arrays are feature-major: ``x_num`` is float32 ``[F_num][n]``, ``cat`` is raw
+int32 category values ``[F_cat][n]`` (arbitrary, non-dense values, so the
+consumer has to build its own dense ids), ``perms`` is int32 ``[s][n]`` with
+``perm[p]`` = row placed at position p, ``label`` is float32 ``[n]`` (0/1 for
+Logloss, class index for MultiClass, real value for RMSE).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BASE_SEED = 181011363
+
+RMSE, LOGLOSS, MULTICLASS = 0, 1, 2
+LOSS_NAMES = {RMSE: "RMSE", LOGLOSS: "Logloss", MULTICLASS: "MultiClass"}
+
+# Fixed-point exponent for regression labels fed to the ordered statistic:
+# y_num = llrint(y * 2**Y_SHIFT) so that per-category sums are exact integers.
+Y_SHIFT = 32
+
+
+def rng_for(cfg: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([BASE_SEED, cfg, stream]))
+
+
+@dataclass
+class Problem:
+    """One boosting problem: raw inputs plus the training parameters."""
+    name: str
+    x_num: np.ndarray            # float32 [F_num][n]
+    cat: np.ndarray              # int32 [F_cat][n] raw category values
+    label: np.ndarray            # float32 [n]
+    perms: np.ndarray            # int32 [s][n]
+    loss: int
+    K: int                       # approx width (1, or number of classes)
+    depth: int
+    iterations: int
+    lr: float
+    l2: float
+    num_bins: int                # bins per numeric feature (borders = bins - 1)
+    ts_bins: int                 # bins per ordered-statistic column
+    a: float                     # prior weight
+    priors: list = field(default_factory=list)   # one prior per target column
+    y_num: np.ndarray | None = None   # int64 [T][n] targets for the statistic
+    y_shift: int = 0
+    ts_lo: float = 0.0
+    ts_hi: float = 1.0
+
+    @property
+    def n(self) -> int:
+        return int(self.label.shape[0])
+
+    @property
+    def n_num(self) -> int:
+        return int(self.x_num.shape[0])
+
+    @property
+    def n_cat(self) -> int:
+        return int(self.cat.shape[0])
+
+    @property
+    def n_targets(self) -> int:
+        return int(self.y_num.shape[0]) if self.y_num is not None else 0
+
+    @property
+    def n_features(self) -> int:
+        """Histogram features a tree sees: numeric + one permutation's TS columns."""
+        return self.n_num + self.n_cat * self.n_targets
+
+
+def zipf_ids(g: np.random.Generator, n: int, C: int, s: float) -> np.ndarray:
+    """Dense ids in [0, C) with P(rank r) proportional to (r+1)^-s; ids are a
+    seeded shuffle of the ranks so that frequency is unrelated to the id."""
+    w = (np.arange(1, C + 1, dtype=np.float64)) ** (-s)
+    w /= w.sum()
+    ranks = g.choice(C, size=n, p=w)
+    shuffle = g.permutation(C)
+    return shuffle[ranks].astype(np.int64)
+
+
+def raw_values(g: np.random.Generator, C: int) -> np.ndarray:
+    """C distinct, non-dense, non-negative int32 values standing for category names."""
+    vals = g.choice(2**31 - 1, size=C, replace=False)
+    return vals.astype(np.int32)
+
+
+def _finish_targets(p: Problem) -> Problem:
+    """Encode the statistic targets as int64 numerators, one row per target."""
+    y = p.label.astype(np.float64)
+    if p.loss == RMSE:
+        p.y_shift = Y_SHIFT
+        p.y_num = np.rint(y * float(2**Y_SHIFT)).astype(np.int64)[None, :]
+        p.priors = [float(np.mean(y))]
+        p.ts_lo, p.ts_hi = float(y.min()), float(y.max())
+    elif p.loss == LOGLOSS:
+        p.y_shift = 0
+        p.y_num = (y > 0.5).astype(np.int64)[None, :]
+        if not p.priors:
+            p.priors = [float(np.mean(y > 0.5))]
+        p.ts_lo, p.ts_hi = 0.0, 1.0
+    else:
+        p.y_shift = 0
+        rows = [(p.label == c).astype(np.int64) for c in range(p.K - 1)]
+        p.y_num = np.stack(rows) if rows else np.zeros((0, p.n), np.int64)
+        p.priors = [float(np.mean(p.label == c)) for c in range(p.K - 1)]
+        p.ts_lo, p.ts_hi = 0.0, 1.0
+    return p
+
+
+def _perms(cfg: int, n: int, s: int, base_stream: int = 3) -> np.ndarray:
+    return np.stack([rng_for(cfg, base_stream + r).permutation(n).astype(np.int32)
+                     for r in range(s)]) if s else np.zeros((0, n), np.int32)
+
+
+def _sigmoid(z):
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def make_c1(n: int = 10_000) -> Problem:
+    """Small Logloss problem: 20 N(0,1) numeric features with 32 quantile
+    borders, 2 categorical features of cardinality 50 with Zipf(1.2)
+    frequencies, one permutation, depth 4, 10 iterations."""
+    cfg = 1
+    gx, gc, gy = rng_for(cfg, 0), rng_for(cfg, 1), rng_for(cfg, 2)
+    x = gx.standard_normal((20, n), dtype=np.float32)
+    ids, cats = [], []
+    for _ in range(2):
+        d = zipf_ids(gc, n, 50, 1.2)
+        vals = raw_values(gc, 50)
+        ids.append(d)
+        cats.append(vals[d])
+    w = gy.standard_normal(20)
+    offs = [gy.normal(0.0, 0.5, 50) for _ in range(2)]
+    logit = x.astype(np.float64).T @ w + offs[0][ids[0]] + offs[1][ids[1]]
+    y = (gy.random(n) < _sigmoid(logit)).astype(np.float32)
+    p = Problem("c1_small_logloss", x, np.stack(cats), y, _perms(cfg, n, 1),
+                LOGLOSS, 1, depth=4, iterations=10, lr=0.1, l2=3.0,
+                num_bins=33, ts_bins=33, a=1.0, priors=[0.5])
+    return _finish_targets(p)
+
+
+def _step_function(g, x, n_feat_total, n_numeric):
+    """A random oblivious depth-3 step function of 3 distinct numeric features."""
+    feats = g.choice(n_numeric, 3, replace=False)
+    out_idx = np.zeros(x.shape[1], np.int64)
+    for lvl, f in enumerate(feats):
+        q = g.uniform(0.1, 0.9)
+        thr = np.quantile(x[f], q)
+        out_idx |= (x[f] > thr).astype(np.int64) << lvl
+    vals = g.standard_normal(8)
+    return vals[out_idx]
+
+
+def make_c2(n: int = 1_000_000, s: int = 4) -> Problem:
+    """RMSE at scale: 50 N(0,1) + 50 lognormal(0,1) numeric features at 128
+    bins, 10 Zipf(1.1) categorical features of cardinality 10..1e5, label =
+    sum of 5 random depth-3 step functions + category effects + N(0, 0.1^2),
+    4 permutations, depth 6, 500 iterations."""
+    cfg = 2
+    gx, gc, gy = rng_for(cfg, 0), rng_for(cfg, 1), rng_for(cfg, 2)
+    x = np.empty((100, n), np.float32)
+    x[:50] = gx.standard_normal((50, n), dtype=np.float32)
+    x[50:] = np.exp(gx.standard_normal((50, n), dtype=np.float32))
+    cards = [10, 10, 100, 100, 1000, 1000, 10_000, 10_000, 100_000, 100_000]
+    ids, cats = [], []
+    for C in cards:
+        C = min(C, max(2, n))
+        d = zipf_ids(gc, n, C, 1.1)
+        vals = raw_values(gc, C)
+        ids.append(d)
+        cats.append(vals[d])
+    y = np.zeros(n, np.float64)
+    for _ in range(5):
+        y += _step_function(gy, x, 100, 100)
+    for d in ids:
+        eff = gy.normal(0.0, 0.5, int(d.max()) + 1)
+        y += eff[d]
+    y += gy.normal(0.0, 0.1, n)
+    p = Problem("c2_scale_rmse", x, np.stack(cats), y.astype(np.float32),
+                _perms(cfg, n, s), RMSE, 1, depth=6, iterations=500, lr=0.1,
+                l2=3.0, num_bins=128, ts_bins=128, a=1.0)
+    return _finish_targets(p)
+
+
+def make_c3(n: int = 10_000_000, F: int = 200) -> Problem:
+    """Precision workload: F uniform(0,1) numeric features at 255 bins, with
+    5% of each column overwritten by exact duplicates of other rows; Logloss
+    with a 1% positive rate; depth 8, 200 iterations; no categorical data."""
+    cfg = 3
+    gx, gy = rng_for(cfg, 0), rng_for(cfg, 2)
+    x = gx.random((F, n), dtype=np.float32)
+    k = max(1, n // 20)
+    for f in range(F):
+        dst = gx.choice(n, k, replace=False)
+        src = gx.integers(0, n, k)
+        x[f, dst] = x[f, src]
+    w = gy.standard_normal(F)
+    z = (x.astype(np.float64).T - 0.5) @ w / math.sqrt(F)
+    lo, hi = -20.0, 20.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if np.mean(_sigmoid(z + mid)) > 0.01:
+            hi = mid
+        else:
+            lo = mid
+    b = 0.5 * (lo + hi)
+    y = (gy.random(n) < _sigmoid(z + b)).astype(np.float32)
+    p = Problem("c3_precision_logloss", x, np.zeros((0, n), np.int32), y,
+                np.zeros((0, n), np.int32), LOGLOSS, 1, depth=8,
+                iterations=200, lr=0.1, l2=3.0, num_bins=255, ts_bins=255,
+                a=1.0)
+    return _finish_targets(p)
+
+
+def _c4_problem(cfg: int, stream: int, n: int, name: str) -> Problem:
+    g = rng_for(cfg, stream)
+    x = g.standard_normal((50, n), dtype=np.float32)
+    ids, cats = [], []
+    for _ in range(4):
+        d = zipf_ids(g, n, 1000, 1.1)
+        vals = raw_values(g, 1000)
+        ids.append(d)
+        cats.append(vals[d])
+    w = g.standard_normal(50)
+    y = x.astype(np.float64).T @ w
+    for _ in range(10):
+        a_, b_ = g.choice(50, 2, replace=False)
+        y += g.standard_normal() * x[a_].astype(np.float64) * x[b_]
+    for d in ids:
+        y += g.normal(0.0, 0.5, 1000)[d]
+    y += g.normal(0.0, 0.1, n)
+    perm = g.permutation(n).astype(np.int32)[None, :]
+    p = Problem(name, x, np.stack(cats), y.astype(np.float32), perm, RMSE, 1,
+                depth=6, iterations=100, lr=0.1, l2=3.0, num_bins=64,
+                ts_bins=64, a=1.0)
+    return _finish_targets(p)
+
+
+def c4_sizes(P: int = 64, lo: int = 5_000, hi: int = 2_000_000, scale: float = 1.0):
+    g = rng_for(4, 0)
+    n = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), P))).astype(np.int64)
+    return [max(16, int(v * scale)) for v in n]
+
+
+def make_c4(P: int = 64, scale: float = 1.0) -> list[Problem]:
+    """Batch of P independent RMSE problems with log-uniform row counts in
+    [5e3, 2e6] (optionally scaled down), 50 numeric features at 64 bins and 4
+    categorical features of cardinality 1000, depth 6, 100 iterations."""
+    return [_c4_problem(4, 100 + i, n, f"c4_problem_{i}")
+            for i, n in enumerate(c4_sizes(P, scale=scale))]
+
+
+def make_c5(n: int = 50_000_000, n_cat: int = 20, K: int = 10) -> Problem:
+    """Large MultiClass problem: 50 N(0,1) numeric features at 255 bins, 20
+    Zipf(1.05) categorical features with cardinalities 10..1e6, K-class
+    softmax labels from a seeded linear model, depth 10, 100 iterations."""
+    cfg = 5
+    gx, gc, gy = rng_for(cfg, 0), rng_for(cfg, 1), rng_for(cfg, 2)
+    x = gx.standard_normal((50, n), dtype=np.float32)
+    ids, cats = [], []
+    for j in range(n_cat):
+        C = int(round(10 ** (1 + 5 * j / max(1, n_cat - 1))))
+        C = min(C, max(2, n))
+        d = zipf_ids(gc, n, C, 1.05)
+        ids.append(d)
+        cats.append(raw_values(gc, C)[d])
+    W = gy.standard_normal((50, K)) / math.sqrt(50)
+    logits = x.astype(np.float64).T @ W
+    for d in ids:
+        E = gy.normal(0.0, 0.5, (int(d.max()) + 1, K))
+        logits += E[d]
+    logits -= logits.max(axis=1, keepdims=True)
+    pr = np.exp(logits)
+    pr /= pr.sum(axis=1, keepdims=True)
+    u = gy.random(n)[:, None]
+    y = (np.cumsum(pr, axis=1) < u).sum(axis=1).clip(0, K - 1).astype(np.float32)
+    p = Problem("c5_large_multiclass", x, np.stack(cats), y, _perms(cfg, n, 1),
+                MULTICLASS, K, depth=10, iterations=100, lr=0.1, l2=3.0,
+                num_bins=255, ts_bins=255, a=1.0)
+    return _finish_targets(p)
+
+
+def random_small(seed: int, n: int, F_num: int = 3, F_cat: int = 1, C: int = 5,
+                 loss: int = RMSE, K: int = 1, depth: int = 3, num_bins: int = 8,
+                 s: int = 1, dup: bool = True) -> Problem:
+    """Tiny random problems for brute-force pins and ragged-size parity."""
+    g = np.random.default_rng(np.random.SeedSequence([BASE_SEED, 999, seed]))
+    if dup:
+        x = g.integers(0, max(2, num_bins + 3), (F_num, n)).astype(np.float32) * 0.5
+    else:
+        x = g.standard_normal((F_num, n), dtype=np.float32)
+    cats = [raw_values(g, C)[g.integers(0, C, n)] for _ in range(F_cat)]
+    cat = np.stack(cats) if cats else np.zeros((0, n), np.int32)
+    if loss == RMSE:
+        y = g.standard_normal(n).astype(np.float32)
+    elif loss == LOGLOSS:
+        y = (g.random(n) < 0.4).astype(np.float32)
+    else:
+        y = g.integers(0, K, n).astype(np.float32)
+    perms = np.stack([g.permutation(n).astype(np.int32) for _ in range(s)])
+    p = Problem(f"small_{seed}", x, cat, y, perms, loss, K, depth=depth,
+                iterations=3, lr=0.1, l2=1.0, num_bins=num_bins,
+                ts_bins=num_bins, a=1.0)
+    return _finish_targets(p)
+
+
+CONFIGS = {
+    "c1": make_c1,
+    "c2": make_c2,
+    "c3": make_c3,
+    "c4": make_c4,
+    "c5": make_c5,
+}

@@ -1,0 +1,116 @@
+"""Classic (non-ordered) boosting of oblivious trees on the CPU oracle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Follows the paper's plain scheme: binarize numeric features (Sec. 5), replace
+every categorical feature by its ordered target statistic for a permutation
+(Sec. 2, Eq. 1), start from the zero model (Algorithm 1 initialises M to 0),
+and per tree choose one split per level for the whole level (oblivious trees,
+Sec. 4), then set leaf values and add the tree to the model (Sec. 3, two-phase
+tree building; the second phase is the ordinary GBDT step).
+
+Readings the paper leaves open (border rule, score, regulariser, which
+permutation a tree sees) are the ones documented in ``oracle.c``; tree t uses
+the statistic columns of permutation t mod s.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import (apply_split, best_split, gradients, histogram, leaf_values,
+               ordered_ts, quantize, score, select_borders, ts_borders,
+               update_approx)
+
+
+@dataclass
+class Prepared:
+    num_bins: np.ndarray                 # uint8 [F_num][n]
+    num_borders: list                    # per numeric feature, float32 borders
+    ts_bins: np.ndarray                  # uint8 [s][F_cat*T][n]
+    ts_num: np.ndarray                   # int64 [s][F_cat*T][n]
+    ts_den: np.ndarray                   # int32 [s][F_cat][n]
+    ts_borders: np.ndarray               # float64 [ts_bins-1]
+    nb_num: np.ndarray                   # int32 bins per numeric feature
+    nb_ts: int
+    timings: dict = field(default_factory=dict)
+
+    def tree_features(self, t: int):
+        """Histogram features of tree t: numeric bins then TS bins of perm t mod s."""
+        s = self.ts_bins.shape[0]
+        if s == 0 or self.ts_bins.shape[1] == 0:
+            return self.num_bins, self.nb_num
+        r = t % s
+        bins = np.concatenate([self.num_bins, self.ts_bins[r]], axis=0)
+        nb = np.concatenate([self.nb_num,
+                             np.full(self.ts_bins.shape[1], self.nb_ts, np.int32)])
+        return bins, nb
+
+
+def prepare(p) -> Prepared:
+    t0 = time.perf_counter()
+    borders = [select_borders(p.x_num[f], p.num_bins) for f in range(p.n_num)]
+    t1 = time.perf_counter()
+    num_bins = np.stack([quantize(p.x_num[f], borders[f]) for f in range(p.n_num)]) \
+        if p.n_num else np.zeros((0, p.n), np.uint8)
+    t2 = time.perf_counter()
+    tb = ts_borders(p.ts_lo, p.ts_hi, p.ts_bins)
+    s = p.perms.shape[0] if p.n_cat else 0
+    T = p.n_targets
+    ts_bins = np.zeros((s, p.n_cat * T, p.n), np.uint8)
+    ts_num = np.zeros((s, p.n_cat * T, p.n), np.int64)
+    ts_den = np.zeros((s, p.n_cat, p.n), np.int32)
+    for r in range(s):
+        for c in range(p.n_cat):
+            for j in range(T):
+                num, den, _, tbin = ordered_ts(p.cat[c], p.perms[r], p.y_num[j], p.y_shift,
+                                               p.a, p.priors[j], tb)
+                ts_bins[r, c * T + j] = tbin
+                ts_num[r, c * T + j] = num
+                ts_den[r, c] = den
+    t3 = time.perf_counter()
+    nb_num = np.array([len(b) + 1 for b in borders], np.int32)
+    return Prepared(num_bins, borders, ts_bins, ts_num, ts_den, tb, nb_num, p.ts_bins,
+                    {"borders_s": t1 - t0, "quantize_s": t2 - t1, "ordered_ts_s": t3 - t2})
+
+
+@dataclass
+class Tree:
+    splits: list            # [(feature, border, best score, second score)] per level
+    values: np.ndarray      # float64 [2^d][K]
+    counts: np.ndarray      # int64 [2^d]
+
+
+def fit_tree(bins, nb, approx, label, loss: int, K: int, depth: int, lr: float,
+             l2: float, B: int) -> Tree:
+    """One oblivious tree on FP64 gradients of the current approx (updated in place)."""
+    n = label.size
+    g, h = gradients(loss, K, approx, label)
+    leaf = np.zeros(n, np.uint16)
+    splits = []
+    for lvl in range(depth):
+        hist = histogram(bins, g, h, leaf, 1 << lvl, B)
+        sc = score(hist, nb, l2)
+        f, k, s1, s2 = best_split(sc, nb)
+        splits.append((f, k, s1, s2))
+        if f >= 0:
+            apply_split(bins[f], k, lvl, leaf)
+    vals, G, H, cnt = leaf_values(leaf, g, h, 1 << depth, l2)
+    update_approx(approx, leaf, vals, lr)
+    return Tree(splits, vals, cnt)
+
+
+def fit(p, iterations: int | None = None, prep: Prepared | None = None):
+    """Full classic boosting; returns (trees, approx [K][n], prepared)."""
+    prep = prep or prepare(p)
+    iters = p.iterations if iterations is None else iterations
+    approx = np.zeros((p.K, p.n), np.float64)
+    B = max(int(prep.nb_num.max()) if prep.nb_num.size else 1,
+            prep.nb_ts if prep.ts_bins.shape[1] else 1)
+    trees = []
+    for t in range(iters):
+        bins, nb = prep.tree_features(t)
+        trees.append(fit_tree(bins, nb, approx, p.label, p.loss, p.K, p.depth, p.lr, p.l2, B))
+    return trees, approx, prep

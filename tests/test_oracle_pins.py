@@ -1,0 +1,398 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle through a route other than its own code: hand-
+worked values (tests/golden/, derived from the equations they cite), closed
+forms, invariants, library routines for special cases, finite differences and
+brute force on tiny inputs. A dropped term, a flipped sign, a wrong index or a
+transposed operand in the oracle fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+from tests import brute
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- ordered TS
+def test_ordered_ts_hand_examples(oracle_lib):
+    """Sec. 2, Eq. (1) on the hand-worked examples."""
+    o = oracle_lib
+    for case in _gold("ordered_ts_hand.json")["cases"]:
+        num, den, ts, _ = o.ordered_ts(case["cat"], case["perm"], np.array(case["y"]), 0,
+                                       case["a"], case["prior"])
+        assert num.tolist() == case["num"], case["name"]
+        assert den.tolist() == case["den"], case["name"]
+        np.testing.assert_allclose(ts, case["ts"], rtol=0, atol=1e-15)
+
+
+def _rand_ts_inputs(seed, n=300, C=7):
+    g = np.random.default_rng(seed)
+    vals = g.choice(10**6, C, replace=False).astype(np.int32)
+    cat = vals[g.integers(0, C, n)]
+    perm = g.permutation(n).astype(np.int32)
+    y = g.integers(0, 2, n).astype(np.int64)
+    return cat, perm, y
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ordered_ts_invariants(oracle_lib, seed):
+    o = oracle_lib
+    cat, perm, y = _rand_ts_inputs(seed)
+    n = cat.size
+    num, den, ts, _ = o.ordered_ts(cat, perm, y, 0, 1.0, 0.3)
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    for c in np.unique(cat):
+        rows = np.nonzero(cat == c)[0]
+        rows = rows[np.argsort(pos[rows])]       # rows of c in permutation order
+        # den enumerates 0..n_c-1 along the permutation
+        assert den[rows].tolist() == list(range(rows.size))
+        # num is the exclusive running total of y along the permutation
+        assert num[rows].tolist() == np.concatenate([[0], np.cumsum(y[rows])[:-1]]).tolist()
+        # closed form for the total: each y_j is counted by every later row
+        nc = rows.size
+        assert int(num[rows].sum()) == int(sum(y[r] * (nc - 1 - i) for i, r in enumerate(rows)))
+
+
+def test_ordered_ts_excludes_own_and_later_rows(oracle_lib):
+    """The statistic of the row at position p uses only positions < p: changing
+    the label of that row or of any later row leaves its value unchanged."""
+    o = oracle_lib
+    cat, perm, y = _rand_ts_inputs(5, n=200, C=4)
+    _, _, ts, _ = o.ordered_ts(cat, perm, y, 0, 1.0, 0.5)
+    for p in (0, 17, 100, 199):
+        y2 = y.copy()
+        later = perm[p:]
+        y2[later] = 1 - y2[later]
+        _, _, ts2, _ = o.ordered_ts(cat, perm, y2, 0, 1.0, 0.5)
+        assert np.array_equal(ts[perm[: p + 1]], ts2[perm[: p + 1]])
+
+
+def test_ordered_ts_limits(oracle_lib):
+    o = oracle_lib
+    cat, perm, y = _rand_ts_inputs(7)
+    # a -> infinity: the prior dominates
+    _, _, ts, _ = o.ordered_ts(cat, perm, y, 0, 1e12, 0.37)
+    np.testing.assert_allclose(ts, 0.37, atol=1e-9)
+    # all categories distinct: no earlier row shares a category, TS == P exactly
+    n = 50
+    distinct = np.arange(n, dtype=np.int32) * 7919
+    _, den, ts, _ = o.ordered_ts(distinct, np.random.default_rng(1).permutation(n), np.ones(n), 0,
+                                 2.0, 0.25)
+    assert np.all(den == 0) and np.all(ts == 0.25)
+
+
+def test_ordered_ts_fixed_point_targets(oracle_lib):
+    """Regression targets as int64 numerators with value y_num * 2^-e."""
+    o = oracle_lib
+    cat = np.array([1, 1, 1, 2], np.int32)
+    perm = np.array([0, 1, 2, 3], np.int32)
+    y = np.array([0.75, -1.5, 2.0, 9.0])
+    y_num = np.rint(y * 2.0**32).astype(np.int64)
+    num, den, ts, _ = o.ordered_ts(cat, perm, y_num, 32, 1.0, 0.5)
+    assert num.tolist() == [0, int(0.75 * 2**32), int(-0.75 * 2**32), 0]
+    np.testing.assert_allclose(ts, [0.5, (0.75 + 0.5) / 2, (-0.75 + 0.5) / 3, 0.5], rtol=0, atol=1e-15)
+
+
+def test_ts_bins_from_uniform_borders(oracle_lib):
+    o = oracle_lib
+    b = o.ts_borders(0.0, 1.0, 4)
+    assert b.tolist() == [0.25, 0.5, 0.75]
+    cat, perm, y = _rand_ts_inputs(9)
+    _, _, ts, tb = o.ordered_ts(cat, perm, y, 0, 1.0, 0.5, b)
+    assert np.array_equal(tb, np.searchsorted(b, ts, side="left"))
+
+
+# ----------------------------------------------------------- borders / bins
+@pytest.mark.parametrize("max_bins", [2, 5, 33, 128, 255, 256])
+def test_borders_properties(oracle_lib, max_bins):
+    o = oracle_lib
+    g = np.random.default_rng(max_bins)
+    for x in (g.standard_normal(3000).astype(np.float32),
+              np.exp(g.standard_normal(3000)).astype(np.float32),
+              (g.integers(0, 40, 3000) * 0.5).astype(np.float32)):
+        b = o.select_borders(x, max_bins)
+        assert b.size <= max_bins - 1
+        assert np.all(np.diff(b) > 0)
+        assert np.all(np.isin(b, x))                   # borders are data values
+        bins = o.quantize(x, b)
+        assert np.array_equal(bins, np.searchsorted(b, x, side="left"))
+        counts = np.bincount(bins, minlength=b.size + 1)
+        assert counts.size == b.size + 1 and np.all(counts > 0)   # no empty bin
+        assert np.array_equal(o.quantize(b, b), np.arange(b.size))  # bin(c_k) = k
+        uniq = np.unique(x)
+        if uniq.size <= max_bins:                      # one bin per distinct value
+            assert np.array_equal(b, uniq[:-1])
+
+
+def test_borders_value_at_rank(oracle_lib):
+    o = oracle_lib
+    x = np.arange(1, 101, dtype=np.float32)            # 100 distinct values, 4 bins
+    assert o.select_borders(x, 4).tolist() == [25.0, 50.0, 75.0]
+    assert o.select_borders(np.full(10, 3.0, np.float32), 8).size == 0
+    with pytest.raises(ValueError):
+        o.select_borders(np.array([1.0, np.nan], np.float32), 4)
+
+
+# --------------------------------------------------------------- gradients
+@pytest.mark.parametrize("loss", [datagen.RMSE, datagen.LOGLOSS])
+def test_gradients_finite_difference(oracle_lib, loss):
+    o = oracle_lib
+    g0 = np.random.default_rng(3)
+    a = g0.normal(0, 2, 50)
+    y = (g0.random(50) < 0.5).astype(np.float32) if loss else g0.normal(0, 1, 50).astype(np.float32)
+    yd = y.astype(np.float64)
+
+    def L(v):
+        if loss == datagen.RMSE:
+            return 0.5 * (yd - v) ** 2
+        p = 1 / (1 + np.exp(-v))
+        return -(yd * np.log(p) + (1 - yd) * np.log(1 - p))
+
+    g, h = o.gradients(loss, 1, a[None, :], y)
+    e = 1e-4
+    np.testing.assert_allclose(g[0], (L(a + e) - L(a - e)) / (2 * e), rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(h[0], (L(a + e) - 2 * L(a) + L(a - e)) / e**2, rtol=1e-4, atol=1e-6)
+
+
+def test_gradients_multiclass_finite_difference(oracle_lib):
+    o = oracle_lib
+    K, n = 4, 30
+    g0 = np.random.default_rng(4)
+    a = g0.normal(0, 2, (K, n))
+    y = g0.integers(0, K, n).astype(np.float32)
+
+    def L(A):
+        z = A - A.max(axis=0)
+        return -(z[y.astype(int), np.arange(n)] - np.log(np.exp(z).sum(axis=0)))
+
+    g, h = o.gradients(datagen.MULTICLASS, K, a, y)
+    e = 1e-4
+    for k in range(K):
+        ap, am = a.copy(), a.copy()
+        ap[k] += e
+        am[k] -= e
+        np.testing.assert_allclose(g[k], (L(ap) - L(am)) / (2 * e), rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(h[k], (L(ap) - 2 * L(a) + L(am)) / e**2, rtol=1e-4, atol=1e-6)
+
+
+# -------------------------------------------------------------- histograms
+def test_histogram_equals_one_hot_product(oracle_lib):
+    """hist[L][f][b] = sum over rows with leaf L and bin b (Sec. 5), computed
+    here as a one-hot matrix product, plus per-leaf totals and counts."""
+    o = oracle_lib
+    g0 = np.random.default_rng(11)
+    n, F, B, K, Lv = 500, 3, 9, 2, 4
+    bins = g0.integers(0, B, (F, n)).astype(np.uint8)
+    g = g0.normal(size=(K, n))
+    h = g0.random((K, n))
+    leaf = g0.integers(0, Lv, n).astype(np.uint16)
+    hist = o.histogram(bins, g, h, leaf, Lv, B)
+    for f in range(F):
+        onehot = np.zeros((n, Lv * B))
+        onehot[np.arange(n), leaf.astype(int) * B + bins[f]] = 1.0
+        for c in range(K):
+            np.testing.assert_allclose(hist[:, f, :, 2 * c].ravel(), onehot.T @ g[c], atol=1e-12)
+            np.testing.assert_allclose(hist[:, f, :, 2 * c + 1].ravel(), onehot.T @ h[c], atol=1e-12)
+    # every feature's histogram sums to the leaf's gradient total
+    for L in range(Lv):
+        for c in range(K):
+            tot = g[c][leaf == L].sum()
+            np.testing.assert_allclose(hist[L, :, :, 2 * c].sum(axis=1), tot, atol=1e-10)
+    # with h = 1 the second statistic is the row count; counts sum to n
+    hc = o.histogram(bins, g[:1], np.ones((1, n)), leaf, Lv, B)
+    assert hc[..., 1].sum(axis=(0, 2)).tolist() == [n] * F
+
+
+def test_histogram_int_exact(oracle_lib):
+    o = oracle_lib
+    g0 = np.random.default_rng(12)
+    n, F, B, Lv = 400, 2, 7, 2
+    bins = g0.integers(0, B, (F, n)).astype(np.uint8)
+    gq = g0.integers(-32767, 32768, (1, n)).astype(np.int16)
+    hq = g0.integers(0, 32768, (1, n)).astype(np.int16)
+    leaf = g0.integers(0, Lv, n).astype(np.uint16)
+    hist = o.histogram_int(bins, gq, hq, leaf, Lv, B)
+    for f in range(F):
+        for L in range(Lv):
+            for b in range(B):
+                m = (leaf == L) & (bins[f] == b)
+                assert hist[L, f, b, 0] == int(gq[0][m].astype(np.int64).sum())
+                assert hist[L, f, b, 1] == int(hq[0][m].astype(np.int64).sum())
+
+
+def test_grad_codes_bounds(oracle_lib):
+    o = oracle_lib
+    g0 = np.random.default_rng(13)
+    g = g0.normal(size=(2, 1000)).astype(np.float32)
+    h = g0.random((2, 1000)).astype(np.float32)
+    gq, hq, sc = o.grad_codes(g, h, True)
+    for c in range(2):
+        s = np.float32(np.abs(g[c]).max()) / np.float32(32767)
+        assert sc[c, 0] == s
+        assert np.abs(gq[c]).max() == 32767
+        assert np.all(np.abs(g[c].astype(np.float64) - gq[c] * np.float64(s)) <= 0.5 * s * (1 + 1e-6))
+        assert np.all(hq[c] >= 0)
+    _, hq1, _ = o.grad_codes(g[:1], None, False)
+    assert np.all(hq1 == 1)
+
+
+# -------------------------------------------------------- score and argmax
+def test_depth2_hand_tree(oracle_lib):
+    """Hand-worked depth-2 oblivious tree: scores, argmax, leaf bits, values."""
+    o = oracle_lib
+    d = _gold("tree_hand.json")["depth2"]
+    bins = np.array(d["bins"], np.uint8)
+    nb = np.array(d["n_bins"], np.int32)
+    g = np.array(d["g"], np.float64)[None, :]
+    h = np.ones_like(g)
+    leaf = np.zeros(8, np.uint16)
+    for lvl in range(2):
+        hist = o.histogram(bins, g, h, leaf, 1 << lvl, 4)
+        sc = o.score(hist, nb, d["l2"])
+        want = np.array([[np.nan if v is None else v for v in row] for row in d["level_scores"][lvl]])
+        m = ~np.isnan(want)
+        np.testing.assert_allclose(sc[m], want[m], rtol=1e-12)
+        assert np.all(np.isneginf(sc[~m]))
+        f, k, s1, s2 = o.best_split(sc, nb)
+        assert [f, k] == d["best"][lvl]
+        if lvl == 0:
+            np.testing.assert_allclose(s1 - s2, d["margin0"], rtol=1e-12)
+        o.apply_split(bins[f], k, lvl, leaf)
+        assert leaf.tolist() == d["leaf_after"][lvl]
+    vals, G, H, cnt = o.leaf_values(leaf, g, h, 4, d["l2"])
+    assert G[:, 0].tolist() == d["G"] and H[:, 0].tolist() == d["H"] and cnt.tolist() == d["counts"]
+    np.testing.assert_allclose(vals[:, 0], d["values"], rtol=1e-15)
+    approx = np.zeros((1, 8))
+    o.update_approx(approx, leaf, vals, d["lr"])
+    np.testing.assert_allclose(approx[0], np.array(d["approx_delta"])[leaf], rtol=1e-15)
+
+
+def test_tie_break_and_clear_case(oracle_lib):
+    o = oracle_lib
+    d = _gold("tree_hand.json")["tie"]
+    bins = np.array(d["bins"], np.uint8)
+    nb = np.array(d["n_bins"], np.int32)
+    leaf = np.zeros(4, np.uint16)
+    for gk, sk in (("g_tie", "scores_tie"), ("g_clear", "scores_clear")):
+        g = np.array(d[gk], np.float64)[None, :]
+        hist = o.histogram(bins, g, np.ones_like(g), leaf, 1, 3)
+        sc = o.score(hist, nb, d["l2"])
+        np.testing.assert_allclose(sc[0], d[sk], rtol=1e-15)
+        f, k, s1, s2 = o.best_split(sc, nb)
+        assert (f, k) == (0, 0)
+    assert s1 - s2 > 0
+    lf = leaf.copy()
+    o.apply_split(bins[0], 0, 0, lf)
+    vals, *_ = o.leaf_values(lf, g, np.ones_like(g), 2, d["l2"])
+    np.testing.assert_allclose(vals[:, 0], d["values_clear"], rtol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_best_split_matches_brute_force(oracle_lib, seed):
+    """Brute force (rows collected per child, objective minimised numerically)
+    agrees with histogram + score + argmax on tiny random problems."""
+    o = oracle_lib
+    g0 = np.random.default_rng(100 + seed)
+    n, F, K = 40, 3, 1 + seed % 2
+    nb = g0.integers(2, 6, F).astype(np.int32)
+    bins = np.stack([g0.integers(0, nb[f], n) for f in range(F)]).astype(np.uint8)
+    g = g0.normal(size=(K, n))
+    h = g0.random((K, n)) + 0.1
+    n_leaves = 1 << (seed % 3)
+    leaf = g0.integers(0, n_leaves, n).astype(np.uint16)
+    l2 = [0.5, 1.0, 3.0][seed % 3]
+    hist = o.histogram(bins, g, h, leaf, n_leaves, int(nb.max()))
+    sc = o.score(hist, nb, l2)
+    f, k, s1, s2 = o.best_split(sc, nb)
+    objs = brute.split_objectives(bins, nb, g, h, leaf, n_leaves, l2)
+    (bf, bk), bobj = brute.best_by_objective(objs)
+    assert (f, k) == (bf, bk)
+    # the score is -2 x the minimised objective of the split
+    for (ff, kk), v in objs.items():
+        np.testing.assert_allclose(sc[ff, kk], -2.0 * v, rtol=1e-7, atol=1e-9)
+
+
+def test_rmse_stump_is_least_squares(oracle_lib):
+    """Depth 1, RMSE from approx 0, l2 -> 0: the chosen split minimises the
+    sum of squared errors around the child means, and with lr 1 the model
+    becomes those means."""
+    o = oracle_lib
+    from oracle import boost
+    g0 = np.random.default_rng(21)
+    n = 60
+    x = g0.integers(0, 6, (2, n)).astype(np.uint8)
+    y = (g0.normal(size=n) + 2.0 * (x[1] > 2)).astype(np.float32)
+    nb = np.array([6, 6], np.int32)
+    sse = {}
+    for f in range(2):
+        for k in range(5):
+            m = x[f] > k
+            sse[(f, k)] = sum(float(((y[s] - y[s].mean()) ** 2).sum()) for s in (m, ~m) if s.any())
+    best = min(sse, key=lambda t: (sse[t], t))
+    approx = np.zeros((1, n))
+    tree = boost.fit_tree(x, nb, approx, y, datagen.RMSE, 1, 1, 1.0, 1e-300, 6)
+    assert tree.splits[0][:2] == best
+    m = x[best[0]] > best[1]
+    yd = y.astype(np.float64)
+    np.testing.assert_allclose(approx[0][m], yd[m].mean(), rtol=1e-9)
+    np.testing.assert_allclose(approx[0][~m], yd[~m].mean(), rtol=1e-9)
+
+
+def test_leaf_value_minimises_objective(oracle_lib):
+    o = oracle_lib
+    g0 = np.random.default_rng(22)
+    g = g0.normal(size=(1, 30))
+    h = g0.random((1, 30))
+    leaf = np.zeros(30, np.uint16)
+    vals, *_ = o.leaf_values(leaf, g, h, 1, 2.0)
+    _, v = brute.leaf_objective(g[0], h[0], 2.0)
+    np.testing.assert_allclose(vals[0, 0], v, rtol=1e-7)
+
+
+def test_leaf_bits_follow_levels(oracle_lib):
+    """Sec. 4: bit i of the leaf index is the binary feature of depth i."""
+    o = oracle_lib
+    g0 = np.random.default_rng(23)
+    n = 200
+    bins = g0.integers(0, 10, (4, n)).astype(np.uint8)
+    leaf = np.zeros(n, np.uint16)
+    chosen = [(2, 3), (0, 7), (3, 1), (2, 5)]
+    for lvl, (f, k) in enumerate(chosen):
+        o.apply_split(bins[f], k, lvl, leaf)
+    want = sum(((bins[f] > k).astype(np.int64) << i) for i, (f, k) in enumerate(chosen))
+    assert np.array_equal(leaf, want)
+
+
+def test_update_approx_gathers_leaf_values(oracle_lib):
+    o = oracle_lib
+    g0 = np.random.default_rng(24)
+    K, n = 3, 50
+    leaf = g0.integers(0, 8, n).astype(np.uint16)
+    vals = g0.normal(size=(8, K))
+    a = g0.normal(size=(K, n))
+    b = a.copy()
+    o.update_approx(b, leaf, vals, 0.25)
+    np.testing.assert_allclose(b, a + 0.25 * vals[leaf].T, rtol=0, atol=1e-15)
+
+
+def test_boosting_reduces_training_loss(oracle_lib):
+    from oracle import boost
+    p = datagen.make_c1(n=3000)
+    p.iterations = 5
+    trees, approx, _ = boost.fit(p)
+    y = p.label.astype(np.float64)
+    pr = 1 / (1 + np.exp(-approx[0]))
+    ll = -np.mean(y * np.log(pr) + (1 - y) * np.log(1 - pr))
+    assert ll < np.log(2) - 0.01
+    assert all(t.counts.sum() == p.n for t in trees)
