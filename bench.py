@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark: per-tree split search on one MI355X for the 1M-row RMSE workload.
+
+A step is one boosting iteration: every level's histogram build, scoring,
+argmax and leaf update, then the leaf solve and the model/gradient update.
+The once-per-dataset steps (borders, bins, ordered statistics) are timed in
+the same run and reported beside it. Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line. `value` is the whole-step histogram-feature throughput
+(rows x features x levels per second, in units of 1e9), `sec_per_tree` the
+mean time of a step, and `roofline` the histogram build's algorithmic HBM
+bytes per launch over its event-timed average duration against 8 TB/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sec/tree and histogram G row-features/s vs plain FP32, ≤1e-5 rel err"
+PEAK_HBM_GBS = 8000.0
+PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2}
+
+
+def hist_bytes_per_level(n, F, K, level, rmse, precision):
+    """Algorithmic bytes one histogram launch must read: the bin of every
+    (row, feature), the row's gradient statistics and (after level 0) its leaf."""
+    if precision == 2:
+        grad = 4 * K                       # int16 (g, h) code pair
+    else:
+        grad = 4 * K if rmse else 8 * K    # g (and h) float32
+    leaf = 2 if level > 0 else 0
+    return n * F + n * grad + n * leaf
+
+
+def cpu_baseline(p, rows: int, trees: int):
+    """The oracle as it stands, on a row sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from oracle import boost
+    n_full = p.n
+    sub = np.sort(np.random.default_rng(0).choice(n_full, rows, replace=False))
+    p.x_num = np.ascontiguousarray(p.x_num[:, sub])
+    p.cat = np.ascontiguousarray(p.cat[:, sub])
+    p.label = np.ascontiguousarray(p.label[sub])
+    p.y_num = np.ascontiguousarray(p.y_num[:, sub])
+    # each permutation restricted to the sample, rows renumbered 0..rows-1
+    p.perms = np.stack([np.searchsorted(sub, perm[np.isin(perm, sub)]).astype(np.int32)
+                        for perm in p.perms])
+    prep = boost.prepare(p)
+    approx = np.zeros((p.K, p.n))
+    B = max(int(prep.nb_num.max()), prep.nb_ts)
+    bins, nb = prep.tree_features(0)
+    boost.fit_tree(bins, nb, approx, p.label, p.loss, p.K, p.depth, p.lr, p.l2, B)   # warm
+    t0 = time.perf_counter()
+    for t in range(trees):
+        bins, nb = prep.tree_features(t)
+        boost.fit_tree(bins, nb, approx, p.label, p.loss, p.K, p.depth, p.lr, p.l2, B)
+    dt = (time.perf_counter() - t0) / trees
+    F = bins.shape[0]
+    return {"value": round(rows * F * p.depth / dt / 1e9, 6), "unit": "G row-features/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{rows} of {n_full} rows (uniform sample of the same workload), "
+                      f"{trees} trees after 1 warm tree; oracle sec/tree {dt:.3f}",
+            "sec_per_tree": round(dt, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=list(PRECISIONS), default="fp32")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-rows", type=int, default=100_000)
+    ap.add_argument("--cpu-trees", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", default=None, help="autotune cache path to load")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1810_11363_amd import cbhip as cb
+    from paper_1810_11363_amd.booster import GpuBooster
+
+    prec = PRECISIONS[args.precision]
+    t_gen = time.perf_counter()
+    p = datagen.make_c2(n=args.n)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    bst = GpuBooster.from_problem(p, precision=prec).prepare()
+    if args.autotune:
+        cb.cbh_autotune_load(bst.ctx, args.autotune)
+    print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
+    n, F, K, depth = bst.n, bst.F, bst.K, bst.depth
+    stream = bst.stream
+    bst.init_gradients()
+    for t in range(args.warmup):
+        bst.fit_tree(t)
+    torch.cuda.synchronize()
+    print("# warm-up done", file=sys.stderr, flush=True)
+
+    # timed region: steps trees, with events around every histogram build
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(depth)] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hist = bst.hist.data_ptr()
+    torch.cuda.synchronize()
+    start.record(stream)
+    t_wall = time.perf_counter()
+    for s in range(args.steps):
+        t = args.warmup + s
+        pr = bst.probs[t % bst.s]
+        if prec == 2:
+            cb.cbh_quantize_gradients(bst.ctx, pr, stream)
+        for lvl in range(depth):
+            ev[s][lvl][0].record(stream)
+            cb.cbh_build_histograms(bst.ctx, pr, lvl, prec, hist, stream)
+            ev[s][lvl][1].record(stream)
+            cb.cbh_score_splits(bst.ctx, pr, lvl, hist, prec, bst.l2, bst.split_ptr(lvl), None,
+                                stream)
+            cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), stream)
+        cb.cbh_update_approx(bst.ctx, pr, hist, prec, bst.split_ptr(depth - 1), bst.lr, bst.l2,
+                             bst.leaf_values, None, stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    cb.cbh_sync(bst.ctx, stream)
+    total_ms = start.elapsed_time(stop)
+    hist_ms = np.array([[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(depth)]
+                        for s in range(args.steps)])
+    sec_per_tree = total_ms / 1e3 / args.steps
+    rf_per_tree = n * F * depth
+    value = rf_per_tree / sec_per_tree / 1e9
+    rmse = p.loss == datagen.RMSE
+    bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec) for l in range(depth)])
+    hist_s_per_tree = hist_ms.sum(axis=1).mean() / 1e3
+    achieved = float(bytes_lvl.sum() / hist_s_per_tree / 1e9)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "G row-features/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 4),
+        "sec_per_tree": round(sec_per_tree, 6),
+        "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
+        "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"1M-row RMSE: n={n}, 100 numeric features at 128 bins + "
+                               f"10 categorical -> {F - 100} ordered-statistic columns per "
+                               f"tree, 4 permutations, depth {depth}, lr 0.1, l2 3",
+                   "precision": args.precision, "features_per_tree": F, "bins": bst.B,
+                   "rows": n},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None,
+                     "kernel": "cbh_build_histograms (LDS histogram + partial merge)",
+                     "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
+                     "avg_launch_ms": round(float(hist_ms.mean()), 5)},
+        "preprocess_s": {k: round(v, 4) for k, v in bst.timings.items() if v is not None},
+        "wall_s_timed": round(t_wall, 3),
+    }
+    bst.close()
+    if not args.no_cpu:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(datagen.make_c2(n=args.n), args.cpu_rows,
+                                           args.cpu_trees)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

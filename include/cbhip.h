@@ -1,0 +1,348 @@
+/*
+ * cbhip — split search for oblivious gradient-boosted trees and ordered
+ * target statistics on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow "CatBoost: gradient boosting with categorical
+ * features support" (arXiv:1810.11363):
+ *   - numeric features are discretized into a fixed number of bins, at most
+ *     255 per feature (Sec. 5, "Dense numerical features");
+ *   - categorical features are replaced by ordered target statistics over a
+ *     permutation, with prior P and prior weight a (Sec. 2, Eq. 1); grouping
+ *     by category uses a radix sort and a segmented scan (Sec. 5,
+ *     "Categorical features");
+ *   - trees are oblivious: one split per level, and the split at depth i sets
+ *     bit i of the leaf index (Sec. 4);
+ *   - splits are found from per-bin gradient histograms (Sec. 5), scored and
+ *     the best one kept (Sec. 3, first phase of tree building); leaf values are
+ *     then set by the ordinary boosting step and the tree is added to the
+ *     model (Sec. 3, second phase; Algorithm 1 adds each tree to the model).
+ * Where the paper is silent (score formula, regulariser, losses, border rule)
+ * the readings are stated at the call that uses them.
+ *
+ * Conventions for every call:
+ *   - Return value: CBH_OK or a negative status. cbh_last_error() returns a
+ *     thread-local message for the last failing call on this thread.
+ *   - Arguments are validated on the host before anything is enqueued; a
+ *     call that fails validation enqueues nothing.
+ *   - Pointers documented as "device" are device memory owned by the caller;
+ *     the library never frees them and never keeps them past the call (except
+ *     inside a batch plan or captured graph, see below). "host" pointers are
+ *     read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream). All
+ *     device work is asynchronous on that stream; nothing in the per-level
+ *     calls synchronizes the host. Device-side input errors (NaN inputs) and
+ *     asynchronous faults are reported by cbh_sync().
+ *   - A context owns a scratch workspace that calls on it reuse; use one
+ *     context per concurrently used stream.
+ *   - Arrays written [A][B] are row-major with the last index fastest.
+ */
+#ifndef CBHIP_H
+#define CBHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CBH_OK 0
+#define CBH_EINVAL (-1)        /* null pointer, bad shape or out-of-range argument */
+#define CBH_ENOMEM (-2)        /* workspace allocation failed or exceeds the limit */
+#define CBH_EDEVICE (-3)       /* HIP runtime error or device-reported input error */
+#define CBH_EOVERFLOW (-4)     /* an integer accumulator could overflow */
+#define CBH_EUNSUPPORTED (-5)  /* K > 16, more than 256 bins, depth > 16, ... */
+
+/* ---- losses (the paper uses Logloss and mentions regression; the
+ *      derivative formulas are the standard ones, see cbh_update_approx) ---- */
+#define CBH_LOSS_RMSE 0
+#define CBH_LOSS_LOGLOSS 1
+#define CBH_LOSS_MULTICLASS 2
+
+/* ---- histogram precision ----------------------------------------------- */
+#define CBH_PREC_FP32 0      /* float accumulation */
+#define CBH_PREC_TWOFLOAT 1  /* compensated (hi, lo) float pairs */
+#define CBH_PREC_INT16 2     /* int16 gradient codes, exact integer sums */
+
+#define CBH_MAX_K 16
+#define CBH_MAX_BINS 256
+#define CBH_MAX_DEPTH 16
+
+typedef struct cbh_ctx cbh_ctx;
+
+/* One boosting problem as seen by the per-level calls. The struct itself is
+ * host memory; the pointers inside are device memory owned by the caller.
+ *
+ *   n           rows (>= 1)
+ *   n_features  F, histogram features (numeric bins and statistic bins)
+ *   max_bins    B, the bin stride of histograms: 2 <= B <= 256 and
+ *               n_bins[f] <= B for every f; a stored bin >= B is counted in
+ *               bin B-1
+ *   bins        device array of F device pointers; bins[f] points at the
+ *               uint8 bin column of feature f, n bytes, row order. Columns
+ *               should be 16-byte aligned for full bandwidth.
+ *   n_bins      device int32 [F]: number of bins of feature f (borders + 1);
+ *               candidate borders are k = 0 .. n_bins[f]-2
+ *   K           approx width: 1 (RMSE, Logloss) or the class count
+ *               (MultiClass, 2 <= K <= 16)
+ *   loss        CBH_LOSS_*
+ *   depth       tree depth d, 1 <= d <= 16
+ *   label       device float [n]: target (RMSE), 0/1 (Logloss) or class index
+ *               (MultiClass)
+ *   g, h        device float [K][n]: first and second derivatives of the
+ *               loss at approx. h is not read for RMSE (h = 1, the second
+ *               statistic becomes the row count) and may be NULL there.
+ *   gq          device int16 [K][n][2]: (g code, h code) pairs for
+ *               CBH_PREC_INT16, written by cbh_quantize_gradients; else NULL
+ *   grad_scale  device float [K][2]: per-class (g scale, h scale) for
+ *               CBH_PREC_INT16; else NULL
+ *   leaf        device uint16 [n]: leaf index of every row; bit i is the
+ *               split of depth i (Sec. 4). Its contents are ignored at
+ *               level 0, and cbh_apply_split at level 0 overwrites it, so a
+ *               new tree needs no reset.
+ *   approx      device double [K][n]: current model value of every row       */
+typedef struct cbh_problem {
+    int64_t n;
+    int32_t n_features;
+    int32_t max_bins;
+    const uint8_t* const* bins;
+    const int32_t* n_bins;
+    int32_t K;
+    int32_t loss;
+    int32_t depth;
+    int32_t reserved;
+    const float* label;
+    float* g;
+    float* h;
+    int16_t* gq;
+    float* grad_scale;
+    uint16_t* leaf;
+    double* approx;
+} cbh_problem;
+
+/* Result of the split search of one level (device memory).
+ * feature, border: the chosen split (rows with bin > border go right and get
+ *                  the level's bit); -1, -1 if no feature has two bins.
+ * score:           its score (see cbh_score_splits).
+ * margin:          best score minus the best score of any other candidate
+ *                  (0 for an exact tie).                                    */
+typedef struct cbh_split {
+    int32_t feature;
+    int32_t border;
+    float score;
+    float margin;
+} cbh_split;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (it becomes current on this thread). */
+int cbh_create(int device, cbh_ctx** out);
+/* Destroy a context and free its workspace. NULL is ignored. Waits for the
+ * device to finish work that may still use the workspace. */
+void cbh_destroy(cbh_ctx* ctx);
+/* Thread-local message of the last failing call ("" if none). */
+const char* cbh_last_error(void);
+/* Cap on the workspace the context may allocate (bytes, > 0). A call that
+ * would need more returns CBH_ENOMEM without enqueuing anything. */
+int cbh_set_workspace_limit(cbh_ctx* ctx, int64_t bytes);
+/* Current workspace size in bytes. */
+int64_t cbh_workspace_size(const cbh_ctx* ctx);
+/* Wait for `stream`, then report asynchronous HIP errors and device-side input
+ * errors (NaN feature values, bin or leaf values out of range) raised since
+ * the previous cbh_sync, and clear them. */
+int cbh_sync(cbh_ctx* ctx, void* stream);
+
+/* ---- preprocessing -------------------------------------------------------- */
+
+/* Borders of one numeric feature (host computation; Sec. 5: a fixed number of
+ * bins, at most 255 borders). The paper gives no rule; this one takes
+ * value-at-rank quantiles: with the column sorted ascending as s[0..n-1], if
+ * it has m <= max_bins distinct values the borders are its m-1 smallest
+ * distinct values; otherwise candidate j = 1..max_bins-1 is s[floor(j*n/max_bins)-1],
+ * kept unless equal to the previous kept border or to s[n-1].
+ *   x_host          host float [n], no NaN
+ *   max_bins        2..256
+ *   borders_out     host float [max_bins-1] (capacity), strictly increasing
+ *   n_borders_out   host int32: number of borders written
+ * Errors: CBH_EINVAL on NULL, n < 0, max_bins out of range or a NaN value. */
+int cbh_select_borders(const float* x_host, int64_t n, int32_t max_bins,
+                       float* borders_out, int32_t* n_borders_out);
+
+/* Uniform borders for ordered-statistic values (host computation): the paper
+ * binarizes statistics like numeric features (Sec. 4) without a rule; here
+ * border j-1 = lo + ((hi - lo) * j) / n_bins for j = 1 .. n_bins-1, in
+ * double precision with that operation order.
+ *   borders_out  host double [n_bins-1]
+ * Errors: CBH_EINVAL on NULL, non-finite or hi < lo; CBH_EUNSUPPORTED unless
+ * 2 <= n_bins <= 256. */
+int cbh_uniform_borders(double lo, double hi, int32_t n_bins, double* borders_out);
+
+/* Bin index of every value of one numeric feature: bin = number of borders
+ * strictly below x (so split k sends x > borders[k] right).
+ *   x          device float [n]
+ *   borders    device float [n_borders], strictly increasing
+ *   n_borders  0..255
+ *   bins_out   device uint8 [n]
+ * A NaN value gets bin 0 and raises a device error reported by cbh_sync. */
+int cbh_quantize(cbh_ctx* ctx, const float* x, int64_t n, const float* borders,
+                 int32_t n_borders, uint8_t* bins_out, void* stream);
+
+/* Ordered target statistics of one categorical feature for one permutation,
+ * Sec. 2, Eq. (1). For the row sigma_p at position p, over the rows placed at
+ * positions < p that share its category value:
+ *   num = sum of their target numerators,  den = their count,
+ *   ts  = (num * 2^-y_shift + a * prior) / (den + a)   (double, this order),
+ *   bin = number of ts_borders strictly below ts.
+ * Several targets (e.g. one per class for MultiClass) share the grouping.
+ *   cat          device int32 [n]: raw category values (any int32)
+ *   perm         device int32 [n]: perm[p] = row placed at position p; must be
+ *                a permutation of 0..n-1 (not checked)
+ *   y_num        device int64 [n_targets][n]: target numerators, value
+ *                y_num * 2^-y_shift (0/1 counts for classification)
+ *   n_targets    1..16
+ *   y_shift      0..62
+ *   y_abs_max    host bound on |y_num|; CBH_EOVERFLOW if n * y_abs_max >= 2^62
+ *   a            prior weight, > 0
+ *   priors       host double [n_targets]
+ *   ts_borders   device double [n_ts_borders] increasing; may be NULL if
+ *                ts_bin_out is NULL
+ *   n_ts_borders 0..255
+ *   num_out      device int64 [n_targets][n] or NULL
+ *   den_out      device int32 [n] or NULL
+ *   ts_bin_out   device uint8 [n_targets][n] or NULL
+ *   ts_out       device double [n_targets][n] or NULL
+ * Uses workspace of about 24 * n bytes. */
+int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm,
+                           int64_t n, const int64_t* y_num, int32_t n_targets,
+                           int32_t y_shift, int64_t y_abs_max, double a,
+                           const double* priors, const double* ts_borders,
+                           int32_t n_ts_borders, int64_t* num_out, int32_t* den_out,
+                           uint8_t* ts_bin_out, double* ts_out, void* stream);
+
+/* ---- per-tree and per-level calls (the split search) -------------------- */
+
+/* int16 gradient codes for CBH_PREC_INT16: per class, s_g = max|g| / 32767
+ * and s_h = max h / 32767 (float32), code = round-half-even(value / scale)
+ * (float32 division), 0 when the scale is 0. RMSE stores an h code of 1
+ * (the count). Writes prob->gq and prob->grad_scale. */
+int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream);
+
+/* Histograms of level `level` (0 <= level < depth), Sec. 5:
+ *   hist[L][f][b][2c]   = sum of g_c over rows with leaf L and bin_f = b
+ *   hist[L][f][b][2c+1] = sum of h_c over the same rows (row count for RMSE)
+ * for L < 2^level, f < F, b < B, c < K. Element type by precision:
+ *   CBH_PREC_FP32      float; for RMSE the odd slots hold uint32 counts
+ *   CBH_PREC_TWOFLOAT  float2 (hi, lo) with hi + lo the compensated sum; for
+ *                      RMSE the odd slots hold (uint32 count, 0)
+ *   CBH_PREC_INT16     int64 sums of the int16 codes (exact)
+ *   hist_out   device, 2^level * F * B * 2K elements
+ * Every block accumulates a tile in LDS; tiles are merged in a fixed order
+ * without global atomics. Uses workspace for the per-block partial tiles. */
+int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                         int32_t precision, void* hist_out, void* stream);
+
+/* Score every candidate split of the level and keep the best (Sec. 3, first
+ * phase). The paper gives no formula; the score is the gain of the
+ * L2-regularised second-order objective: splitting every current leaf L by
+ * (f, k), with left = bins <= k and right = bins > k,
+ *   S(f, k) = sum_L sum_c  G_left^2 / (H_left + l2) + G_right^2 / (H_right + l2)
+ * where H is the row count for RMSE; a side with H + l2 == 0 contributes 0.
+ * The best split is the largest S; among equal scores the smallest feature,
+ * then the smallest border. Scores are computed in float32.
+ *   hist        output of cbh_build_histograms for the same level/precision
+ *   l2          >= 0
+ *   best_out    device cbh_split [1]
+ *   scores_out  device float [F][B-1] or NULL; -inf where k >= n_bins[f]-1 */
+int cbh_score_splits(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                     const void* hist, int32_t precision, double l2,
+                     cbh_split* best_out, float* scores_out, void* stream);
+
+/* Apply the chosen split: leaf[i] |= (bins[f][i] > k) << level for the split
+ * read from device memory (Sec. 4); at level 0, leaf[i] = (bins[f][i] > k).
+ * If best->feature < 0 the bit stays clear for every row. */
+int cbh_apply_split(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                    const cbh_split* best, void* stream);
+
+/* Finish a tree and refresh the gradients (Sec. 3, second phase).
+ * With hist_last != NULL (the level depth-1 histograms) and `last` (the split
+ * of level depth-1, already applied to prob->leaf):
+ *   for every final leaf L' and class c, G and H are the sums of the parent's
+ *   histogram row of the chosen feature on the side of the border that L'
+ *   lies on, accumulated in double; the leaf value is the Newton step
+ *   v = -G / (H + l2) (0 if H + l2 == 0); then
+ *   approx[c][i] += lr * v[leaf[i]][c] in double.
+ * Then, always, g and h are recomputed from approx in double and stored as
+ * float (the paper uses d Loss / d a, Algorithm 1):
+ *   RMSE        g = a - y, h = 1 (h not written)
+ *   Logloss     p = 1 / (1 + exp(-a)), g = p - y, h = p (1 - p)
+ *   MultiClass  p = softmax(a) (max subtracted), g_c = p_c - [y == c],
+ *               h_c = p_c (1 - p_c)
+ * With hist_last == NULL only the gradients are computed (tree 0 starts from
+ * approx = 0, as Algorithm 1 starts from the zero model); `last`,
+ * leaf_values_out and leaf_counts_out must then be NULL.
+ *   leaf_values_out  device double [2^depth][K] (required with hist_last)
+ *   leaf_counts_out  device int64 [2^depth] or NULL: rows per final leaf     */
+int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_last,
+                      int32_t precision, const cbh_split* last, double lr, double l2,
+                      double* leaf_values_out, int64_t* leaf_counts_out, void* stream);
+
+/* ---- batched, fused levels ------------------------------------------------- */
+
+typedef struct cbh_batch cbh_batch;
+
+/* A plan for running tree levels of P independent problems together (for
+ * example several permutations, folds or separate datasets). The problem
+ * descriptors and the histogram buffers are copied to device memory once; the
+ * device buffers they point to must stay valid while the plan exists.
+ *   probs     host array [P]; every problem must have the same depth
+ *   hist      host array [P] of device pointers; hist[p] must hold the level
+ *             depth-1 histograms of problem p (size as cbh_build_histograms)
+ *   best      device cbh_split [P][depth]: split of every problem and level
+ * Precision must be CBH_PREC_FP32 or CBH_PREC_TWOFLOAT or CBH_PREC_INT16. */
+int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P,
+                     int32_t precision, void* const* hist, cbh_split* best,
+                     cbh_batch** out);
+void cbh_batch_destroy(cbh_batch* batch);
+
+/* One level of every problem of the plan: histograms, score, argmax and the
+ * leaf update, with the split written to best[p][level]. The histogram tiles of
+ * all problems share one persistent launch; the block that finishes the last
+ * tile of a feature group merges that group and scores it, and the block that
+ * finishes the last group of a problem takes the argmax. */
+int cbh_batch_level(cbh_ctx* ctx, cbh_batch* batch, int32_t level, double l2,
+                    void* stream);
+
+/* Finish the trees of every problem of the plan (as cbh_update_approx with the
+ * level depth-1 histograms and splits); leaf_values is a host array [P] of
+ * device pointers, each double [2^depth][K] (entries may not be NULL). With
+ * init != 0 only the gradients are computed (tree 0). */
+int cbh_batch_update(cbh_ctx* ctx, cbh_batch* batch, double lr, double l2,
+                     double* const* leaf_values, int32_t init, void* stream);
+
+/* Capture one whole boosting iteration of the plan (reset leaves, every
+ * level, the leaf solve and the approx/gradient update) into a HIP graph and
+ * return an executable graph that replays it on `stream`. */
+typedef struct cbh_graph cbh_graph;
+int cbh_graph_capture_iteration(cbh_ctx* ctx, cbh_batch* batch, double lr, double l2,
+                                double* const* leaf_values, void* stream,
+                                cbh_graph** out);
+int cbh_graph_launch(cbh_graph* graph, void* stream);
+void cbh_graph_destroy(cbh_graph* graph);
+
+/* ---- autotuning -------------------------------------------------------------- */
+
+/* Time the histogram kernel of `prob` over its launch parameters
+ * (features per block, leaves per LDS tile, rows per block) at every level,
+ * keep the fastest per (F, B, K, level, precision, row bucket), and save the
+ * table as JSON at cache_path (may be NULL). Later calls of this context use
+ * the table. Synchronizes the stream. */
+int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision,
+                 const char* cache_path, void* stream);
+/* Load a table written by cbh_autotune. */
+int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBHIP_H */

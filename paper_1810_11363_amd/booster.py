@@ -1,0 +1,243 @@
+"""Boosting driver on the GPU: device buffers from PyTorch, every step in libcbhip.
+
+The loop follows the paper's classic scheme (Sec. 3, two-phase tree
+building; Sec. 4, oblivious trees; the paper benchmarks this mode on GPU):
+binarize numeric features, replace each categorical feature by its ordered
+target statistic for each of s permutations (Sec. 2, Eq. 1), start from the
+zero model, and for tree t use the statistic columns of permutation t mod s.
+
+PyTorch only allocates device memory and supplies the stream; all arithmetic
+of the method runs in the HIP library behind the C-ABI.
+
+Device layout (HBM):
+  numeric bins   uint8 [F_num][ld]            ld = n rounded up to 16
+  statistic bins uint8 [s][F_cat * T][ld]     T targets per categorical feature
+  column table   int64 [s][F]                 device pointers of the F columns
+                                              a tree of permutation r reads
+  n_bins         int32 [s][F]
+  label float32 [n], g/h float32 [K][n], gq int16 [K][n][2], leaf uint16 [n],
+  approx float64 [K][n]
+  hist           the deepest level's histogram, reused by every level
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import cbhip as cb
+
+
+def _ld(n: int) -> int:
+    return (n + 15) // 16 * 16
+
+
+@dataclass
+class TreeRecord:
+    splits: np.ndarray        # int32 [depth][2] (feature, border)
+    scores: np.ndarray        # float32 [depth][2] (score, margin)
+    values: np.ndarray        # float64 [2^depth][K]
+
+
+class GpuBooster:
+    """One boosting problem resident on one GPU."""
+
+    def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
+                 lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
+                 device="cuda:0", ctx=None, stream=None):
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.own_ctx = ctx is None
+        self.ctx = ctx if ctx is not None else cb.cbh_create(self.device.index or 0)
+        self.loss, self.K, self.depth = int(loss), int(K), int(depth)
+        self.lr, self.l2 = float(lr), float(l2)
+        self.num_bins, self.ts_bins, self.a = int(num_bins), int(ts_bins), float(a)
+        self.precision = int(precision)
+        self.x_num = np.ascontiguousarray(x_num, dtype=np.float32)
+        self.cat = np.ascontiguousarray(cat, dtype=np.int32)
+        self.label_h = np.ascontiguousarray(label, dtype=np.float32)
+        self.perms = np.ascontiguousarray(perms, dtype=np.int32)
+        self.y_num = np.ascontiguousarray(y_num, dtype=np.int64)
+        self.y_shift, self.priors = int(y_shift), [float(p) for p in priors]
+        self.ts_lo, self.ts_hi = float(ts_lo), float(ts_hi)
+        self.n = int(self.label_h.shape[0])
+        self.F_num, self.F_cat = self.x_num.shape[0], self.cat.shape[0]
+        self.T = self.y_num.shape[0] if self.F_cat else 0
+        self.s = self.perms.shape[0] if self.F_cat else 1
+        self.F = self.F_num + self.F_cat * self.T
+        self.timings = {}
+        self._alloc()
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        """Build from a datagen-style problem object (attribute names as below)."""
+        return cls(x_num=p.x_num, cat=p.cat, label=p.label, perms=p.perms, y_num=p.y_num,
+                   y_shift=p.y_shift, priors=p.priors, loss=p.loss, K=p.K, depth=p.depth,
+                   lr=p.lr, l2=p.l2, num_bins=p.num_bins, ts_bins=p.ts_bins, a=p.a,
+                   ts_lo=p.ts_lo, ts_hi=p.ts_hi, **kw)
+
+    # ---------------------------------------------------------------- buffers
+    def _alloc(self):
+        d, n, K = self.device, self.n, self.K
+        ld = _ld(n)
+        self.ld = ld
+        self.num_bins_d = torch.empty((max(self.F_num, 1), ld), dtype=torch.uint8, device=d)
+        self.ts_bins_d = torch.empty((self.s, max(self.F_cat * self.T, 1), ld), dtype=torch.uint8,
+                                     device=d)
+        self.label = torch.from_numpy(self.label_h).to(d)
+        self.g = torch.empty((K, n), dtype=torch.float32, device=d)
+        self.h = torch.empty((K, n), dtype=torch.float32, device=d)
+        self.gq = torch.empty((K, n, 2), dtype=torch.int16, device=d)
+        self.grad_scale = torch.zeros((K, 2), dtype=torch.float32, device=d)
+        self.leaf = torch.zeros(n, dtype=torch.uint16, device=d)
+        self.approx = torch.zeros((K, n), dtype=torch.float64, device=d)
+        self.best = torch.zeros((self.depth, 4), dtype=torch.int32, device=d)   # cbh_split[depth]
+        self.leaf_values = torch.zeros((1 << self.depth, K), dtype=torch.float64, device=d)
+        self.leaf_counts = torch.zeros(1 << self.depth, dtype=torch.int64, device=d)
+        self.n_borders = np.zeros(self.F_num, np.int32)
+
+    def _hist_bytes(self, level: int) -> int:
+        esz = 4 if self.precision == cb.CBH_PREC_FP32 else 8
+        return (1 << level) * self.F * self.B * 2 * self.K * esz
+
+    # ----------------------------------------------------------- preprocessing
+    def prepare(self):
+        """Borders (host), bins and ordered statistics (device); once per dataset."""
+        d, n = self.device, self.n
+        st = self.stream
+        torch.cuda.synchronize(d)
+        t0 = time.perf_counter()
+        borders = [cb.cbh_select_borders(self.x_num[f], self.num_bins) for f in range(self.F_num)]
+        t1 = time.perf_counter()
+        self.num_borders = borders
+        x_d = torch.from_numpy(self.x_num).to(d)
+        bord_d = torch.zeros((max(self.F_num, 1), 256), dtype=torch.float32, device=d)
+        for f, b in enumerate(borders):
+            self.n_borders[f] = b.size
+            if b.size:
+                bord_d[f, : b.size] = torch.from_numpy(b).to(d)
+        torch.cuda.synchronize(d)
+        t2 = time.perf_counter()
+        for f in range(self.F_num):
+            cb.cbh_quantize(self.ctx, x_d[f], n, bord_d[f], int(self.n_borders[f]),
+                            self.num_bins_d[f], st)
+        torch.cuda.synchronize(d)
+        t3 = time.perf_counter()
+        self.ts_borders_h = cb.cbh_uniform_borders(self.ts_lo, self.ts_hi, self.ts_bins)
+        ts_b = torch.from_numpy(self.ts_borders_h).to(d)
+        t4 = t5 = t3
+        if self.F_cat:
+            cat_d = torch.from_numpy(self.cat).to(d)
+            perm_d = torch.from_numpy(self.perms).to(d)
+            y_d = torch.from_numpy(self.y_num).to(d)
+            yabs = int(np.abs(self.y_num).max()) if self.y_num.size else 0
+            tmp = torch.empty((self.T, n), dtype=torch.uint8, device=d) if self.ld != n else None
+            torch.cuda.synchronize(d)
+            t4 = time.perf_counter()
+            for r in range(self.s):
+                for c in range(self.F_cat):
+                    dst = self.ts_bins_d[r, c * self.T:(c + 1) * self.T]
+                    out = tmp if tmp is not None else dst
+                    cb.cbh_compute_ordered_ts(self.ctx, cat_d[c], perm_d[r], n, y_d, self.T,
+                                              self.y_shift, yabs, self.a, self.priors, ts_b,
+                                              self.ts_bins - 1, ts_bin_out=out, stream=st)
+                    if tmp is not None:
+                        dst[:, :n].copy_(tmp)
+            torch.cuda.synchronize(d)
+            t5 = time.perf_counter()
+        cb.cbh_sync(self.ctx, st)
+        self.timings.update(borders_s=t1 - t0, quantize_s=t3 - t2, ordered_ts_s=t5 - t4)
+        # per-permutation column tables and bin counts
+        nb_num = (self.n_borders + 1).astype(np.int32)
+        self.B = int(max(nb_num.max() if self.F_num else 2, self.ts_bins if self.F_cat else 2))
+        cols, nbs = [], []
+        for r in range(self.s):
+            ptrs = [self.num_bins_d[f].data_ptr() for f in range(self.F_num)]
+            ptrs += [self.ts_bins_d[r, j].data_ptr() for j in range(self.F_cat * self.T)]
+            cols.append(ptrs)
+            nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.T, self.ts_bins,
+                                                       np.int32)]))
+        self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
+        self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
+        self.hist = torch.empty(max(256, self._hist_bytes(self.depth - 1)), dtype=torch.uint8,
+                                device=d)
+        self.probs = [self.problem(r) for r in range(self.s)]
+        return self
+
+    def problem(self, r: int) -> cb.cbh_problem:
+        p = cb.cbh_problem()
+        p.n = self.n
+        p.n_features = self.F
+        p.max_bins = self.B
+        p.bins = self.col_table[r].data_ptr()
+        p.n_bins = self.nbins_table[r].data_ptr()
+        p.K = self.K
+        p.loss = self.loss
+        p.depth = self.depth
+        p.label = self.label.data_ptr()
+        p.g = self.g.data_ptr()
+        p.h = self.h.data_ptr()
+        p.gq = self.gq.data_ptr()
+        p.grad_scale = self.grad_scale.data_ptr()
+        p.leaf = self.leaf.data_ptr()
+        p.approx = self.approx.data_ptr()
+        return p
+
+    def bins_host(self, r: int) -> np.ndarray:
+        """uint8 [F][n] bins a tree of permutation r sees (copied to host, for checks)."""
+        parts = [self.num_bins_d[: self.F_num, : self.n]]
+        if self.F_cat:
+            parts.append(self.ts_bins_d[r, :, : self.n])
+        return torch.cat(parts, 0).cpu().numpy()
+
+    # ------------------------------------------------------------------ trees
+    def split_ptr(self, level: int) -> int:
+        return self.best.data_ptr() + 16 * level
+
+    def init_gradients(self):
+        self.approx.zero_()
+        cb.cbh_update_approx(self.ctx, self.probs[0], None, self.precision, None, 0.0, 0.0,
+                             stream=self.stream)
+
+    def fit_tree(self, t: int, counts: bool = False):
+        """One tree (all levels, leaf solve, approx and gradient update)."""
+        pr = self.probs[t % self.s]
+        ctx, st, prec = self.ctx, self.stream, self.precision
+        if prec == cb.CBH_PREC_INT16:
+            cb.cbh_quantize_gradients(ctx, pr, st)
+        hist = self.hist.data_ptr()
+        for lvl in range(self.depth):
+            cb.cbh_build_histograms(ctx, pr, lvl, prec, hist, st)
+            cb.cbh_score_splits(ctx, pr, lvl, hist, prec, self.l2, self.split_ptr(lvl), None, st)
+            cb.cbh_apply_split(ctx, pr, lvl, self.split_ptr(lvl), st)
+        cb.cbh_update_approx(ctx, pr, hist, prec, self.split_ptr(self.depth - 1), self.lr,
+                             self.l2, self.leaf_values, self.leaf_counts if counts else None, st)
+
+    def tree_record(self) -> TreeRecord:
+        b = self.best.cpu().numpy()
+        return TreeRecord(b[:, :2].copy(), b[:, 2:].view(np.float32).copy(),
+                          self.leaf_values.cpu().numpy())
+
+    def fit(self, iterations: int, record: bool = True):
+        self.init_gradients()
+        trees = []
+        for t in range(iterations):
+            self.fit_tree(t)
+            if record:
+                trees.append(self.tree_record())
+        return trees
+
+    def close(self):
+        if self.own_ctx and self.ctx:
+            torch.cuda.synchronize(self.device)
+            cb.cbh_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

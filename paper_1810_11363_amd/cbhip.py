@@ -1,0 +1,280 @@
+"""ctypes binding of libcbhip (include/cbhip.h), same names as the C calls.
+
+Argument marshalling only: every step runs in the HIP library. Device buffers
+are passed as integers (``tensor.data_ptr()``) or torch tensors; streams as
+integers (``torch.cuda.current_stream().cuda_stream``) or None.
+
+Importing this module raises if the library has not been built: there is no
+CPU fallback for any call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbhip.so")
+
+CBH_OK, CBH_EINVAL, CBH_ENOMEM, CBH_EDEVICE, CBH_EOVERFLOW, CBH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CBH_LOSS_RMSE, CBH_LOSS_LOGLOSS, CBH_LOSS_MULTICLASS = 0, 1, 2
+CBH_PREC_FP32, CBH_PREC_TWOFLOAT, CBH_PREC_INT16 = 0, 1, 2
+STATUS_NAMES = {0: "CBH_OK", -1: "CBH_EINVAL", -2: "CBH_ENOMEM", -3: "CBH_EDEVICE",
+                -4: "CBH_EOVERFLOW", -5: "CBH_EUNSUPPORTED"}
+
+# Every symbol include/cbhip.h declares.
+EXPORTS = [
+    "cbh_create", "cbh_destroy", "cbh_last_error", "cbh_set_workspace_limit",
+    "cbh_workspace_size", "cbh_sync", "cbh_select_borders", "cbh_uniform_borders",
+    "cbh_quantize",
+    "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
+    "cbh_score_splits", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
+    "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
+    "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
+    "cbh_autotune", "cbh_autotune_load",
+]
+
+
+class cbh_problem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("n_features", C.c_int32), ("max_bins", C.c_int32),
+        ("bins", C.c_void_p), ("n_bins", C.c_void_p), ("K", C.c_int32),
+        ("loss", C.c_int32), ("depth", C.c_int32), ("reserved", C.c_int32),
+        ("label", C.c_void_p), ("g", C.c_void_p), ("h", C.c_void_p),
+        ("gq", C.c_void_p), ("grad_scale", C.c_void_p), ("leaf", C.c_void_p),
+        ("approx", C.c_void_p),
+    ]
+
+
+class cbh_split(C.Structure):
+    _fields_ = [("feature", C.c_int32), ("border", C.c_int32), ("score", C.c_float),
+                ("margin", C.c_float)]
+
+
+class CbhError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1810_11363_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    i32, i64, dbl, vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "cbh_create": ([C.c_int, C.POINTER(vp)], C.c_int),
+        "cbh_destroy": ([vp], None),
+        "cbh_last_error": ([], C.c_char_p),
+        "cbh_set_workspace_limit": ([vp, i64], C.c_int),
+        "cbh_workspace_size": ([vp], i64),
+        "cbh_sync": ([vp, vp], C.c_int),
+        "cbh_select_borders": ([vp, i64, i32, vp, C.POINTER(i32)], C.c_int),
+        "cbh_uniform_borders": ([dbl, dbl, i32, vp], C.c_int),
+        "cbh_quantize": ([vp, vp, i64, vp, i32, vp, vp], C.c_int),
+        "cbh_compute_ordered_ts": ([vp, vp, vp, i64, vp, i32, i32, i64, dbl, vp, vp, i32,
+                                    vp, vp, vp, vp, vp], C.c_int),
+        "cbh_quantize_gradients": ([vp, C.POINTER(cbh_problem), vp], C.c_int),
+        "cbh_build_histograms": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp], C.c_int),
+        "cbh_score_splits": ([vp, C.POINTER(cbh_problem), i32, vp, i32, dbl, vp, vp, vp],
+                             C.c_int),
+        "cbh_apply_split": ([vp, C.POINTER(cbh_problem), i32, vp, vp], C.c_int),
+        "cbh_update_approx": ([vp, C.POINTER(cbh_problem), vp, i32, vp, dbl, dbl, vp, vp, vp],
+                              C.c_int),
+        "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp, C.POINTER(vp)],
+                             C.c_int),
+        "cbh_batch_destroy": ([vp], None),
+        "cbh_batch_level": ([vp, vp, i32, dbl, vp], C.c_int),
+        "cbh_batch_update": ([vp, vp, dbl, dbl, vp, i32, vp], C.c_int),
+        "cbh_graph_capture_iteration": ([vp, vp, dbl, dbl, vp, vp, C.POINTER(vp)], C.c_int),
+        "cbh_graph_launch": ([vp, vp], C.c_int),
+        "cbh_graph_destroy": ([vp], None),
+        "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, C.c_char_p, vp], C.c_int),
+        "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a pointer of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(rc):
+    if rc != CBH_OK:
+        raise CbhError(rc, _lib.cbh_last_error().decode())
+    return rc
+
+
+# ---------------------------------------------------------------- context
+def cbh_create(device: int = 0):
+    h = C.c_void_p()
+    _check(_lib.cbh_create(device, C.byref(h)))
+    return h.value
+
+
+def cbh_destroy(ctx):
+    _lib.cbh_destroy(ctx)
+
+
+def cbh_last_error() -> str:
+    return _lib.cbh_last_error().decode()
+
+
+def cbh_set_workspace_limit(ctx, nbytes: int):
+    return _check(_lib.cbh_set_workspace_limit(ctx, nbytes))
+
+
+def cbh_workspace_size(ctx) -> int:
+    return _lib.cbh_workspace_size(ctx)
+
+
+def cbh_sync(ctx, stream=None):
+    return _check(_lib.cbh_sync(ctx, _stream(stream)))
+
+
+# ---------------------------------------------------------- preprocessing
+def cbh_select_borders(x_host, max_bins: int):
+    """x_host: contiguous float32 numpy array. Returns a float32 numpy array."""
+    import numpy as np
+    x = np.ascontiguousarray(x_host, dtype=np.float32)
+    out = np.zeros(max(1, max_bins - 1), np.float32)
+    nb = C.c_int32(0)
+    _check(_lib.cbh_select_borders(x.ctypes.data, x.size, max_bins, out.ctypes.data,
+                                   C.byref(nb)))
+    return out[: nb.value].copy()
+
+
+def cbh_uniform_borders(lo: float, hi: float, n_bins: int):
+    """Returns a float64 numpy array of n_bins-1 uniform borders."""
+    import numpy as np
+    out = np.zeros(max(1, n_bins - 1), np.float64)
+    _check(_lib.cbh_uniform_borders(float(lo), float(hi), n_bins, out.ctypes.data))
+    return out[: n_bins - 1].copy()
+
+
+def cbh_quantize(ctx, x, n: int, borders, n_borders: int, bins_out, stream=None):
+    return _check(_lib.cbh_quantize(ctx, _ptr(x), n, _ptr(borders), n_borders, _ptr(bins_out),
+                                    _stream(stream)))
+
+
+def cbh_compute_ordered_ts(ctx, cat, perm, n: int, y_num, n_targets: int, y_shift: int,
+                           y_abs_max: int, a: float, priors, ts_borders, n_ts_borders: int,
+                           num_out=None, den_out=None, ts_bin_out=None, ts_out=None,
+                           stream=None):
+    pri = (C.c_double * n_targets)(*[float(p) for p in priors])
+    return _check(_lib.cbh_compute_ordered_ts(
+        ctx, _ptr(cat), _ptr(perm), n, _ptr(y_num), n_targets, y_shift, y_abs_max, float(a),
+        C.cast(pri, C.c_void_p), _ptr(ts_borders), n_ts_borders, _ptr(num_out), _ptr(den_out),
+        _ptr(ts_bin_out), _ptr(ts_out), _stream(stream)))
+
+
+# ------------------------------------------------------------- split search
+def cbh_quantize_gradients(ctx, prob: cbh_problem, stream=None):
+    return _check(_lib.cbh_quantize_gradients(ctx, C.byref(prob), _stream(stream)))
+
+
+def cbh_build_histograms(ctx, prob: cbh_problem, level: int, precision: int, hist_out,
+                         stream=None):
+    return _check(_lib.cbh_build_histograms(ctx, C.byref(prob), level, precision,
+                                            _ptr(hist_out), _stream(stream)))
+
+
+def cbh_score_splits(ctx, prob: cbh_problem, level: int, hist, precision: int, l2: float,
+                     best_out, scores_out=None, stream=None):
+    return _check(_lib.cbh_score_splits(ctx, C.byref(prob), level, _ptr(hist), precision,
+                                        float(l2), _ptr(best_out), _ptr(scores_out),
+                                        _stream(stream)))
+
+
+def cbh_apply_split(ctx, prob: cbh_problem, level: int, best, stream=None):
+    return _check(_lib.cbh_apply_split(ctx, C.byref(prob), level, _ptr(best), _stream(stream)))
+
+
+def cbh_update_approx(ctx, prob: cbh_problem, hist_last, precision: int, last, lr: float,
+                      l2: float, leaf_values_out=None, leaf_counts_out=None, stream=None):
+    return _check(_lib.cbh_update_approx(ctx, C.byref(prob), _ptr(hist_last), precision,
+                                         _ptr(last), float(lr), float(l2),
+                                         _ptr(leaf_values_out), _ptr(leaf_counts_out),
+                                         _stream(stream)))
+
+
+# ------------------------------------------------------------------ batched
+def cbh_batch_create(ctx, probs, precision: int, hist_ptrs, best):
+    P = len(probs)
+    arr = (cbh_problem * P)(*probs)
+    hp = (C.c_void_p * P)(*[_ptr(h) for h in hist_ptrs])
+    out = C.c_void_p()
+    _check(_lib.cbh_batch_create(ctx, arr, P, precision, C.cast(hp, C.c_void_p), _ptr(best),
+                                 C.byref(out)))
+    return out.value
+
+
+def cbh_batch_destroy(batch):
+    _lib.cbh_batch_destroy(batch)
+
+
+def cbh_batch_level(ctx, batch, level: int, l2: float, stream=None):
+    return _check(_lib.cbh_batch_level(ctx, batch, level, float(l2), _stream(stream)))
+
+
+def cbh_batch_update(ctx, batch, lr: float, l2: float, leaf_values, init: bool, stream=None):
+    P = len(leaf_values)
+    lv = (C.c_void_p * P)(*[_ptr(v) for v in leaf_values])
+    return _check(_lib.cbh_batch_update(ctx, batch, float(lr), float(l2),
+                                        C.cast(lv, C.c_void_p), int(bool(init)),
+                                        _stream(stream)))
+
+
+def cbh_graph_capture_iteration(ctx, batch, lr: float, l2: float, leaf_values, stream=None):
+    P = len(leaf_values)
+    lv = (C.c_void_p * P)(*[_ptr(v) for v in leaf_values])
+    out = C.c_void_p()
+    _check(_lib.cbh_graph_capture_iteration(ctx, batch, float(lr), float(l2),
+                                            C.cast(lv, C.c_void_p), _stream(stream),
+                                            C.byref(out)))
+    return out.value
+
+
+def cbh_graph_launch(graph, stream=None):
+    return _check(_lib.cbh_graph_launch(graph, _stream(stream)))
+
+
+def cbh_graph_destroy(graph):
+    _lib.cbh_graph_destroy(graph)
+
+
+def cbh_autotune(ctx, prob: cbh_problem, precision: int, cache_path=None, stream=None):
+    return _check(_lib.cbh_autotune(ctx, C.byref(prob), precision,
+                                    cache_path.encode() if cache_path else None,
+                                    _stream(stream)))
+
+
+def cbh_autotune_load(ctx, cache_path: str):
+    return _check(_lib.cbh_autotune_load(ctx, cache_path.encode()))

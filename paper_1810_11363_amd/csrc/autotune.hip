@@ -1,0 +1,172 @@
+// Histogram launch autotuner.
+//
+// For every level of a problem it times the histogram build (main launch plus
+// the partial merge) for each distinct launch plan reachable from a grid of
+// knobs — LDS bytes per block (which sets features per block and leaves per
+// LDS tile) and the number of blocks aimed at (which sets rows per block) —
+// and keeps the fastest. Results are keyed by (F, B, K, level, precision,
+// floor(log2 n)) and can be saved to and loaded from a small JSON file.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace cbh {
+
+static bool parse_field(const std::string& obj, const char* key, long long* out) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    const size_t c = obj.find(':', p + k.size());
+    if (c == std::string::npos) return false;
+    return sscanf(obj.c_str() + c + 1, " %lld", out) == 1;
+}
+
+static int save_table(const cbh_ctx* ctx, const char* path) {
+    FILE* f = fopen(path, "w");
+    CBH_REQUIRE(f != nullptr, CBH_EINVAL, "cannot write %s", path);
+    fprintf(f, "[\n");
+    size_t i = 0;
+    for (const auto& kv : ctx->tuned) {
+        const TuneKey& k = kv.first;
+        const HistKnobs& v = kv.second;
+        fprintf(f,
+                "  {\"F\": %d, \"B\": %d, \"K\": %d, \"level\": %d, \"precision\": %d, "
+                "\"log2n\": %d, \"lds_budget\": %d, \"max_fb\": %d, \"target_blocks\": %d, "
+                "\"min_rows\": %lld}%s\n",
+                std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                std::get<5>(k), v.lds_budget, v.max_fb, v.target_blocks, (long long)v.min_rows,
+                ++i < ctx->tuned.size() ? "," : "");
+    }
+    fprintf(f, "]\n");
+    fclose(f);
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path) {
+    clear_error();
+    CBH_ARG(ctx && cache_path, "NULL argument");
+    FILE* f = fopen(cache_path, "r");
+    CBH_ARG(f != nullptr, "cannot open %s", cache_path);
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, r);
+    fclose(f);
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = text.find('{', pos)) != std::string::npos) {
+        const size_t end = text.find('}', pos);
+        CBH_ARG(end != std::string::npos, "malformed autotune file");
+        const std::string obj = text.substr(pos, end - pos + 1);
+        long long F, B, K, lvl, prec, l2n, lds, fb, tb, mr;
+        CBH_ARG(parse_field(obj, "F", &F) && parse_field(obj, "B", &B) &&
+                    parse_field(obj, "K", &K) && parse_field(obj, "level", &lvl) &&
+                    parse_field(obj, "precision", &prec) && parse_field(obj, "log2n", &l2n) &&
+                    parse_field(obj, "lds_budget", &lds) && parse_field(obj, "max_fb", &fb) &&
+                    parse_field(obj, "target_blocks", &tb) && parse_field(obj, "min_rows", &mr),
+                "malformed autotune entry");
+        CBH_ARG(lds > 0 && fb > 0 && tb > 0 && mr > 0, "bad autotune values");
+        HistKnobs kn;
+        kn.lds_budget = (int32_t)lds;
+        kn.max_fb = (int32_t)fb;
+        kn.target_blocks = (int32_t)tb;
+        kn.min_rows = mr;
+        ctx->tuned[TuneKey{(int32_t)F, (int32_t)B, (int32_t)K, (int32_t)lvl, (int32_t)prec,
+                           (int32_t)l2n}] = kn;
+        ++loaded;
+        pos = end + 1;
+    }
+    return CBH_OK;
+}
+
+int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const char* cache_path,
+                 void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int F = prob->n_features, B = prob->max_bins, K = prob->K;
+    std::vector<int32_t> budgets;
+    for (int32_t v : {16 * 1024, 32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, 160 * 1024})
+        if (v <= ctx->max_lds) budgets.push_back(v);
+    const int32_t fbs[] = {2, 4, 8, 16, 32};
+    const int32_t targets[] = {256, 512, 1024, 2048, 4096};
+    const int64_t cell_bytes = int64_t(B) * words_per_cell(precision, K) * 4;
+    CBH_REQUIRE(cell_bytes <= ctx->max_lds, CBH_EUNSUPPORTED, "leaf row does not fit in LDS");
+    const int64_t hist_bytes =
+        hist_elems(1 << (prob->depth - 1), F, B, K) * hist_elem_bytes(precision);
+    void* hist = nullptr;
+    CBH_HIP(hipMalloc(&hist, (size_t)std::max<int64_t>(hist_bytes, 256)));
+    hipEvent_t e0, e1;
+    CBH_HIP(hipEventCreate(&e0));
+    CBH_HIP(hipEventCreate(&e1));
+    int32_t nb = 0;
+    while ((int64_t(1) << (nb + 1)) <= prob->n) ++nb;
+    for (int level = 0; level < prob->depth && rc == CBH_OK; ++level) {
+        const int L = 1 << level;
+        std::set<std::tuple<int, int, int64_t>> seen;
+        float best_ms = 1e30f;
+        HistKnobs best_kn = ctx->knobs;
+        for (size_t ib = 0; ib < budgets.size() && rc == CBH_OK; ++ib)
+            for (int32_t fb : fbs)
+                for (int32_t tb : targets) {
+                    if (rc != CBH_OK) break;
+                    const int32_t bud = budgets[ib];
+                    HistKnobs kn = ctx->knobs;
+                    kn.lds_budget = bud;
+                    kn.max_fb = fb;
+                    kn.target_blocks = tb;
+                    const HistPlan plan = plan_hist(kn, prob->n, F, B, K, L, precision,
+                                                    ctx->max_lds);
+                    if (!seen.insert({plan.fb, plan.lt, plan.rows_per_chunk}).second) continue;
+                    const int64_t part = int64_t(plan.n_chunks) * L * F * B *
+                                         plan.words_per_cell * 4;
+                    if (part > ctx->ws_limit / 2) continue;
+                    rc = ensure_ws(ctx, part);
+                    if (rc) break;
+                    // warm-up, then the mean of 3 timed runs
+                    rc = launch_hist(ctx, prob, level, precision, plan, hist, ctx->ws, s);
+                    if (rc) break;
+                    (void)hipEventRecord(e0, s);
+                    for (int r = 0; r < 3 && !rc; ++r)
+                        rc = launch_hist(ctx, prob, level, precision, plan, hist, ctx->ws, s);
+                    (void)hipEventRecord(e1, s);
+                    if (rc) break;
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        set_error("autotune timing failed");
+                        rc = CBH_EDEVICE;
+                        break;
+                    }
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_kn = kn;
+                    }
+                }
+        if (rc == CBH_OK) ctx->tuned[TuneKey{F, B, K, level, precision, nb}] = best_kn;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(hist);
+    if (rc) return rc;
+    if (cache_path) return save_table(ctx, cache_path);
+    return CBH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,518 @@
+// Batched levels over several independent problems and HIP-graph capture of a
+// whole boosting iteration.
+//
+// The paper trains s permutations side by side (Sec. 3: several
+// permutations, each with its own models) and its GPU code processes many
+// histograms per launch (Sec. 5); batching independent problems, folds and
+// permutations into shared launches is this library's MI355X design. A plan
+// holds device copies of all descriptors; one level of all problems runs as
+//   1. one histogram launch over the tiles of every problem (work list),
+//   2. one merge launch over every problem's partial tiles,
+//   3. one score launch over every (problem, feature),
+//   4. one argmax launch (a block per problem),
+//   5. one apply launch over the rows of every problem,
+// so the launch count per level does not grow with the number of problems.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "kernels_dev.h"
+
+namespace cbh {
+
+int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_last,
+                  int32_t precision, const cbh_split* last, double lr, double l2,
+                  double* leaf_values, int64_t* leaf_counts, hipStream_t s);
+
+// Device descriptor of one problem inside a plan.
+struct DevProb {
+    const uint8_t* const* bins;
+    const int32_t* n_bins;
+    const float* g;
+    const float* h;
+    const uint32_t* gq;
+    const float* grad_scale;
+    uint16_t* leaf;
+    void* hist;
+    uint32_t* partials;      // this problem's partial tiles (workspace)
+    int64_t n;
+    int32_t F, B, K, rmse;
+};
+
+// One histogram work item: (problem, chunk, feature group, leaf tile) and its plan.
+struct DevTile {
+    int32_t prob;
+    int32_t fg;
+    int32_t lt_i;
+    int32_t chunk;
+};
+
+struct LevelPlan {
+    std::vector<HistPlan> plans;       // per problem
+    std::vector<int64_t> part_off;     // per problem, bytes into workspace
+    int64_t part_bytes = 0;
+    int64_t n_tiles = 0;
+    DevTile* d_tiles = nullptr;        // device work list
+    struct DevHP {
+        int32_t fb, lt, n_fgroups, n_ltiles, n_chunks, wpc;
+        int64_t rows_per_chunk, lds_bytes;
+    }* d_plans = nullptr;              // per problem
+    int64_t max_lds = 0;
+    int64_t cells_total = 0;           // sum over problems of L*F*B
+    int64_t* d_cell_off = nullptr;     // per problem prefix of cells (P+1)
+    int64_t score_total = 0;           // sum of F
+    int64_t* d_feat_off = nullptr;     // per problem prefix of features (P+1)
+    int64_t rows_total = 0;
+    int64_t* d_row_off = nullptr;      // per problem prefix of rows (P+1)
+};
+
+}  // namespace cbh
+
+struct cbh_batch {
+    cbh_ctx* ctx = nullptr;
+    int32_t P = 0;
+    int32_t precision = 0;
+    int32_t depth = 0;
+    std::vector<cbh_problem> probs;
+    std::vector<void*> hist;
+    cbh_split* best = nullptr;      // device [P][depth]
+    cbh::DevProb* d_probs = nullptr;
+    std::vector<cbh::LevelPlan> levels;
+    int64_t ws_need = 0;
+    int64_t fbest_off = 0;
+    void* ws = nullptr;             // plan-owned partial tiles and feature winners
+};
+
+struct cbh_graph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace cbh {
+
+// ---------------------------------------------------------------- kernels
+template <int PREC>
+__global__ __launch_bounds__(256) void bhist_kernel(const DevProb* __restrict__ probs,
+                                                    const DevTile* __restrict__ tiles,
+                                                    const LevelPlan::DevHP* __restrict__ plans,
+                                                    int64_t n_tiles, int32_t L) {
+    extern __shared__ uint32_t lds[];
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t ti = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (ti >= n_tiles) return;
+    const DevTile tile = tiles[ti];
+    const DevProb pr = probs[tile.prob];
+    const LevelPlan::DevHP hp = plans[tile.prob];
+    TileArgs t;
+    t.bins = pr.bins;
+    t.g = pr.g;
+    t.h = pr.h;
+    t.gq = pr.gq;
+    t.leaf = pr.leaf;
+    t.part = pr.partials + int64_t(tile.chunk) * (int64_t(L) * pr.F * pr.B * hp.wpc);
+    t.n = pr.n;
+    t.r0 = int64_t(tile.chunk) * hp.rows_per_chunk;
+    t.r1 = min(pr.n, t.r0 + hp.rows_per_chunk);
+    t.F = pr.F;
+    t.B = pr.B;
+    t.K = pr.K;
+    t.L = L;
+    t.fb = hp.fb;
+    t.lt = hp.lt;
+    t.wpc = hp.wpc;
+    t.rmse = pr.rmse;
+    t.f0 = tile.fg * hp.fb;
+    t.nf = min(hp.fb, pr.F - t.f0);
+    t.l0 = (uint32_t)tile.lt_i * hp.lt;
+    hist_tile<PREC, 0>(t, lds);
+}
+
+__device__ __forceinline__ int find_owner(const int64_t* __restrict__ off, int P, int64_t gi) {
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= gi) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Merge partial tiles of every problem: one thread per (problem, cell).
+template <int PREC>
+__global__ __launch_bounds__(256) void breduce_kernel(const DevProb* __restrict__ probs,
+                                                      const LevelPlan::DevHP* __restrict__ plans,
+                                                      const int64_t* __restrict__ cell_off,
+                                                      int32_t P, int64_t cells_total) {
+    for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < cells_total;
+         gi += int64_t(gridDim.x) * 256) {
+        const int p = find_owner(cell_off, P, gi);
+        const DevProb pr = probs[p];
+        merge_cell<PREC>(pr.partials, cell_off[p + 1] - cell_off[p], pr.K, plans[p].n_chunks,
+                         pr.rmse != 0, pr.hist, gi - cell_off[p]);
+    }
+}
+
+// One (problem, feature) per block.
+template <int PREC>
+__global__ __launch_bounds__(256) void bscore_kernel(const DevProb* __restrict__ probs,
+                                                     const int64_t* __restrict__ feat_off,
+                                                     int32_t P, int32_t L, float l2,
+                                                     FeatBest* __restrict__ fbest) {
+    const int64_t gf = blockIdx.x;
+    const int p = find_owner(feat_off, P, gf);
+    const DevProb pr = probs[p];
+    const int f = (int)(gf - feat_off[p]);
+    ScoreRow r;
+    r.hist = pr.hist;
+    r.grad_scale = pr.grad_scale;
+    r.F = pr.F;
+    r.B = pr.B;
+    r.K = pr.K;
+    r.rmse = pr.rmse;
+    r.l2 = l2;
+    score_feature<PREC>(r, L, f, pr.n_bins[f], nullptr, &fbest[gf]);
+}
+
+__global__ __launch_bounds__(256) void bargmax_kernel(const DevProb* __restrict__ probs,
+                                                      const int64_t* __restrict__ feat_off,
+                                                      const FeatBest* __restrict__ fbest,
+                                                      cbh_split* __restrict__ best, int32_t depth,
+                                                      int32_t level) {
+    const int p = blockIdx.x;
+    argmax_features(fbest + feat_off[p], probs[p].F, probs[p].B - 1,
+                    &best[int64_t(p) * depth + level]);
+}
+
+// Apply every problem's split of this level; one thread per 8 rows.
+__global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__ probs,
+                                                     const int64_t* __restrict__ row_off,
+                                                     int32_t P, const cbh_split* __restrict__ best,
+                                                     int32_t depth, int32_t level,
+                                                     int64_t groups_total) {
+    for (int64_t gq = int64_t(blockIdx.x) * 256 + threadIdx.x; gq < groups_total;
+         gq += int64_t(gridDim.x) * 256) {
+        const int p = find_owner(row_off, P, gq);
+        const DevProb pr = probs[p];
+        const int64_t i0 = (gq - row_off[p]) * 8;
+        apply_rows(pr.bins, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
+                   min(pr.n, i0 + 8), level);
+    }
+}
+
+void batch_init_attrs(int max_lds) {
+    const void* fns[] = {(const void*)bhist_kernel<CBH_PREC_FP32>,
+                         (const void*)bhist_kernel<CBH_PREC_TWOFLOAT>,
+                         (const void*)bhist_kernel<CBH_PREC_INT16>};
+    for (const void* f : fns)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_t s) {
+    cbh_ctx* ctx = b->ctx;
+    LevelPlan& lp = b->levels[level];
+    const int L = 1 << level;
+    const int64_t grid = 8 * ((lp.n_tiles + 7) / 8);
+    switch (b->precision) {
+        case CBH_PREC_FP32:
+            bhist_kernel<CBH_PREC_FP32><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
+                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            bhist_kernel<CBH_PREC_TWOFLOAT><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
+                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            break;
+        default:
+            bhist_kernel<CBH_PREC_INT16><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
+                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            break;
+    }
+    CBH_LAUNCHED();
+    const int rg = (int)std::min<int64_t>((lp.cells_total + 255) / 256, ctx->num_cus * 16);
+    switch (b->precision) {
+        case CBH_PREC_FP32:
+            breduce_kernel<CBH_PREC_FP32><<<rg, 256, 0, s>>>(b->d_probs, lp.d_plans,
+                                                            lp.d_cell_off, b->P, lp.cells_total);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            breduce_kernel<CBH_PREC_TWOFLOAT><<<rg, 256, 0, s>>>(
+                b->d_probs, lp.d_plans, lp.d_cell_off, b->P, lp.cells_total);
+            break;
+        default:
+            breduce_kernel<CBH_PREC_INT16><<<rg, 256, 0, s>>>(b->d_probs, lp.d_plans,
+                                                             lp.d_cell_off, b->P, lp.cells_total);
+            break;
+    }
+    CBH_LAUNCHED();
+    FeatBest* fb = (FeatBest*)((char*)b->ws + b->fbest_off);
+    const float fl2 = (float)l2;
+    switch (b->precision) {
+        case CBH_PREC_FP32:
+            bscore_kernel<CBH_PREC_FP32><<<(unsigned)lp.score_total, 256, 0, s>>>(
+                b->d_probs, lp.d_feat_off, b->P, L, fl2, fb);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            bscore_kernel<CBH_PREC_TWOFLOAT><<<(unsigned)lp.score_total, 256, 0, s>>>(
+                b->d_probs, lp.d_feat_off, b->P, L, fl2, fb);
+            break;
+        default:
+            bscore_kernel<CBH_PREC_INT16><<<(unsigned)lp.score_total, 256, 0, s>>>(
+                b->d_probs, lp.d_feat_off, b->P, L, fl2, fb);
+            break;
+    }
+    bargmax_kernel<<<b->P, 256, 0, s>>>(b->d_probs, lp.d_feat_off, fb, b->best, b->depth, level);
+    const int ag = (int)std::min<int64_t>((lp.rows_total + 255) / 256, ctx->num_cus * 8);
+    bapply_kernel<<<ag, 256, 0, s>>>(b->d_probs, lp.d_row_off, b->P, b->best, b->depth, level,
+                                     lp.rows_total);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+static void free_levels(cbh_batch* b) {
+    for (auto& lp : b->levels) {
+        if (lp.d_tiles) (void)hipFree(lp.d_tiles);
+        if (lp.d_plans) (void)hipFree(lp.d_plans);
+        if (lp.d_cell_off) (void)hipFree(lp.d_cell_off);
+        if (lp.d_feat_off) (void)hipFree(lp.d_feat_off);
+        if (lp.d_row_off) (void)hipFree(lp.d_row_off);
+    }
+    b->levels.clear();
+}
+
+template <typename T>
+static int upload(T** dst, const std::vector<T>& v) {
+    CBH_HIP(hipMalloc((void**)dst, std::max<size_t>(1, v.size()) * sizeof(T)));
+    CBH_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t precision,
+                     void* const* hist, cbh_split* best, cbh_batch** out) {
+    clear_error();
+    CBH_ARG(ctx && probs && hist && best && out, "NULL argument");
+    *out = nullptr;
+    CBH_ARG(P >= 1 && P <= 65536, "P must be in [1, 65536]");
+    for (int p = 0; p < P; ++p) {
+        int rc = validate_problem(&probs[p]);
+        if (rc) return rc;
+        rc = validate_precision(&probs[p], precision);
+        if (rc) return rc;
+        CBH_ARG(probs[p].depth == probs[0].depth, "every problem needs the same depth");
+        CBH_ARG(hist[p] != nullptr, "hist[%d] is NULL", p);
+        CBH_REQUIRE(int64_t(probs[p].max_bins) * words_per_cell(precision, probs[p].K) * 4 <=
+                        ctx->max_lds,
+                    CBH_EUNSUPPORTED, "a leaf row of problem %d does not fit in LDS", p);
+    }
+    cbh_batch* b = new cbh_batch();
+    b->ctx = ctx;
+    b->P = P;
+    b->precision = precision;
+    b->depth = probs[0].depth;
+    b->probs.assign(probs, probs + P);
+    b->hist.assign(hist, hist + P);
+    b->best = best;
+    // workspace layout: [per-level max partials][feature winners]
+    int64_t max_part = 0, tot_feat = 0;
+    for (int p = 0; p < P; ++p) tot_feat += probs[p].n_features;
+    for (int lvl = 0; lvl < b->depth; ++lvl) {
+        LevelPlan lp;
+        const int L = 1 << lvl;
+        std::vector<DevTile> tiles;
+        std::vector<LevelPlan::DevHP> dplans;
+        std::vector<int64_t> cell_off{0}, feat_off{0}, row_off{0};
+        int64_t off = 0;
+        for (int p = 0; p < P; ++p) {
+            const cbh_problem& pr = probs[p];
+            const HistKnobs kn =
+                knobs_for(ctx, pr.n_features, pr.max_bins, pr.K, lvl, precision, pr.n);
+            // in a batch the problems share the chip: aim at a share of the blocks
+            HistKnobs kb = kn;
+            kb.target_blocks = std::max<int32_t>(
+                64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
+            HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, L, precision,
+                                    ctx->max_lds);
+            lp.plans.push_back(hp);
+            lp.part_off.push_back(off);
+            off += align_up(int64_t(hp.n_chunks) * L * pr.n_features * pr.max_bins *
+                                hp.words_per_cell * 4,
+                            256);
+            lp.max_lds = std::max(lp.max_lds, hp.lds_bytes);
+            for (int ch = 0; ch < hp.n_chunks; ++ch)
+                for (int fg = 0; fg < hp.n_fgroups; ++fg)
+                    for (int lt = 0; lt < hp.n_ltiles; ++lt)
+                        tiles.push_back(DevTile{p, fg, lt, ch});
+            dplans.push_back(LevelPlan::DevHP{hp.fb, hp.lt, hp.n_fgroups, hp.n_ltiles,
+                                              hp.n_chunks, hp.words_per_cell,
+                                              hp.rows_per_chunk, hp.lds_bytes});
+            cell_off.push_back(cell_off.back() + int64_t(L) * pr.n_features * pr.max_bins);
+            feat_off.push_back(feat_off.back() + pr.n_features);
+            row_off.push_back(row_off.back() + (pr.n + 7) / 8);
+        }
+        lp.part_bytes = off;
+        max_part = std::max(max_part, off);
+        lp.n_tiles = (int64_t)tiles.size();
+        lp.cells_total = cell_off.back();
+        lp.score_total = feat_off.back();
+        lp.rows_total = row_off.back();
+        int rc = upload(&lp.d_tiles, tiles);
+        if (!rc) rc = upload(&lp.d_plans, dplans);
+        if (!rc) rc = upload(&lp.d_cell_off, cell_off);
+        if (!rc) rc = upload(&lp.d_feat_off, feat_off);
+        if (!rc) rc = upload(&lp.d_row_off, row_off);
+        b->levels.push_back(lp);
+        if (rc) {
+            free_levels(b);
+            delete b;
+            return rc;
+        }
+    }
+    b->fbest_off = align_up(max_part, 256);
+    b->ws_need = b->fbest_off + align_up(tot_feat * (int64_t)sizeof(FeatBest), 256);
+    // the context workspace must exist before a capture (gradient codes use it)
+    int rc = ensure_ws(ctx, 256);
+    if (!rc && b->ws_need > ctx->ws_limit) {
+        set_error("batch workspace of %lld bytes exceeds the limit", (long long)b->ws_need);
+        rc = CBH_ENOMEM;
+    }
+    if (!rc && hipMalloc(&b->ws, (size_t)b->ws_need) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("batch workspace allocation of %lld bytes failed", (long long)b->ws_need);
+        rc = CBH_ENOMEM;
+    }
+    if (rc) {
+        free_levels(b);
+        delete b;
+        return rc;
+    }
+    // device descriptors, one copy per level: the partial-tile offsets of the
+    // problems differ between levels.
+    std::vector<DevProb> dp(P);
+    for (int p = 0; p < P; ++p) {
+        const cbh_problem& pr = probs[p];
+        dp[p] = DevProb{pr.bins, pr.n_bins, pr.g, pr.h, reinterpret_cast<const uint32_t*>(pr.gq),
+                        pr.grad_scale, pr.leaf, hist[p], nullptr, pr.n, pr.n_features,
+                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE};
+    }
+    std::vector<DevProb> all;
+    all.reserve(size_t(P) * b->depth);
+    for (int lvl = 0; lvl < b->depth; ++lvl)
+        for (int p = 0; p < P; ++p) {
+            DevProb d = dp[p];
+            d.partials = (uint32_t*)((char*)b->ws + b->levels[lvl].part_off[p]);
+            all.push_back(d);
+        }
+    rc = upload(&b->d_probs, all);
+    if (rc) {
+        free_levels(b);
+        (void)hipFree(b->ws);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return CBH_OK;
+}
+
+void cbh_batch_destroy(cbh_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    free_levels(b);
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+int cbh_batch_level(cbh_ctx* ctx, cbh_batch* b, int32_t level, double l2, void* stream) {
+    clear_error();
+    CBH_ARG(ctx && b && b->ctx == ctx, "bad ctx / batch");
+    CBH_ARG(level >= 0 && level < b->depth, "level outside [0, depth)");
+    CBH_ARG(l2 >= 0 && std::isfinite(l2), "l2 must be finite and >= 0");
+    const DevProb* saved = b->d_probs;
+    b->d_probs = const_cast<DevProb*>(saved) + int64_t(level) * b->P;
+    const int rc = batch_level_launch(b, level, l2, (hipStream_t)stream);
+    b->d_probs = const_cast<DevProb*>(saved);
+    return rc;
+}
+
+int cbh_batch_update(cbh_ctx* ctx, cbh_batch* b, double lr, double l2, double* const* leaf_values,
+                     int32_t init, void* stream) {
+    clear_error();
+    CBH_ARG(ctx && b && b->ctx == ctx, "bad ctx / batch");
+    CBH_ARG(init || leaf_values != nullptr, "leaf_values is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    for (int p = 0; p < b->P; ++p) {
+        int rc;
+        if (init) {
+            rc = launch_update(ctx, &b->probs[p], nullptr, b->precision, nullptr, lr, l2,
+                               nullptr, nullptr, s);
+        } else {
+            CBH_ARG(leaf_values[p] != nullptr, "leaf_values[%d] is NULL", p);
+            rc = launch_update(ctx, &b->probs[p], b->hist[p], b->precision,
+                               b->best + int64_t(p) * b->depth + (b->depth - 1), lr, l2,
+                               leaf_values[p], nullptr, s);
+        }
+        if (rc) return rc;
+    }
+    return CBH_OK;
+}
+
+int cbh_graph_capture_iteration(cbh_ctx* ctx, cbh_batch* b, double lr, double l2,
+                                double* const* leaf_values, void* stream, cbh_graph** out) {
+    clear_error();
+    CBH_ARG(ctx && b && b->ctx == ctx && leaf_values && out, "NULL argument");
+    CBH_ARG(stream != nullptr, "capture needs a non-default stream");
+    *out = nullptr;
+    for (int p = 0; p < b->P; ++p) CBH_ARG(leaf_values[p] != nullptr, "leaf_values[%d] NULL", p);
+    hipStream_t s = (hipStream_t)stream;
+    cbh_graph* g = new cbh_graph();
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    int rc = CBH_OK;
+    for (int p = 0; p < b->P && !rc; ++p)
+        if (b->precision == CBH_PREC_INT16)
+            rc = cbh_quantize_gradients(ctx, &b->probs[p], stream);
+    for (int lvl = 0; lvl < b->depth && !rc; ++lvl) rc = cbh_batch_level(ctx, b, lvl, l2, stream);
+    if (!rc) rc = cbh_batch_update(ctx, b, lr, l2, leaf_values, 0, stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        if (!rc) set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        return rc ? rc : CBH_EDEVICE;
+    }
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    g->graph = graph;
+    *out = g;
+    return CBH_OK;
+}
+
+int cbh_graph_launch(cbh_graph* g, void* stream) {
+    clear_error();
+    CBH_ARG(g && g->exec, "graph is NULL");
+    CBH_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return CBH_OK;
+}
+
+void cbh_graph_destroy(cbh_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

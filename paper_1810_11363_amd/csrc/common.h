@@ -1,0 +1,126 @@
+// Internal declarations shared by the translation units of libcbhip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "cbhip.h"
+
+namespace cbh {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define CBH_REQUIRE(cond, code, ...)            \
+    do {                                        \
+        if (!(cond)) {                          \
+            ::cbh::set_error(__VA_ARGS__);      \
+            return (code);                      \
+        }                                       \
+    } while (0)
+
+#define CBH_ARG(cond, ...) CBH_REQUIRE(cond, CBH_EINVAL, __VA_ARGS__)
+
+#define CBH_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::cbh::set_error("%s failed: %s", #expr, hipGetErrorString(e_));   \
+            return CBH_EDEVICE;                                                \
+        }                                                                      \
+    } while (0)
+
+// Launch-error check after a kernel launch.
+#define CBH_LAUNCHED()                                                         \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess) {                                                \
+            ::cbh::set_error("kernel launch failed: %s", hipGetErrorString(e_)); \
+            return CBH_EDEVICE;                                                \
+        }                                                                      \
+    } while (0)
+
+// Device-side error bits (ctx->d_flags[0]).
+enum : uint32_t {
+    FLAG_NAN_INPUT = 1u,
+};
+
+// ------------------------------------------------------- launch geometry
+struct HistPlan {
+    int32_t fb = 1;          // features per block
+    int32_t lt = 1;          // leaves per LDS tile
+    int32_t n_fgroups = 1;
+    int32_t n_ltiles = 1;
+    int32_t n_chunks = 1;
+    int64_t rows_per_chunk = 0;  // multiple of 16
+    int32_t words_per_cell = 2;  // 32-bit LDS words per (leaf, feature, bin)
+    int64_t lds_bytes = 0;
+    int64_t n_blocks = 0;    // n_chunks * n_fgroups * n_ltiles
+};
+
+// Tunable knobs of the histogram planner.
+struct HistKnobs {
+    int32_t lds_budget = 64 * 1024;  // bytes of LDS per block
+    int32_t max_fb = 32;
+    int32_t target_blocks = 1024;
+    int64_t min_rows = 4096;
+};
+
+using TuneKey = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
+
+}  // namespace cbh
+
+struct cbh_ctx {
+    int device = 0;
+    int num_cus = 256;
+    int max_lds = 64 * 1024;
+    void* ws = nullptr;
+    int64_t ws_size = 0;
+    int64_t ws_limit = int64_t(64) << 30;
+    uint32_t* d_flags = nullptr;  // device error flags
+    cbh::HistKnobs knobs;
+    std::map<cbh::TuneKey, cbh::HistKnobs> tuned;
+    bool force_knobs = false;
+    cbh::HistKnobs forced;
+};
+
+namespace cbh {
+
+// Grow the workspace to at least `bytes`; returns CBH_OK / CBH_ENOMEM / CBH_EDEVICE.
+int ensure_ws(cbh_ctx* ctx, int64_t bytes);
+
+inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Histogram planning (histogram.hip).
+int words_per_cell(int32_t precision, int32_t K);
+HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t level,
+                    int32_t precision, int64_t n);
+HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
+                   int32_t n_leaves, int32_t precision, int max_lds);
+int64_t hist_elems(int32_t n_leaves, int32_t F, int32_t B, int32_t K);
+int64_t hist_elem_bytes(int32_t precision);
+
+int validate_problem(const cbh_problem* p);
+int validate_precision(const cbh_problem* p, int32_t precision);
+
+// Launchers used by several entry points (same stream semantics as the API).
+int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
+                const HistPlan& plan, void* hist_out, void* partials, hipStream_t s);
+int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
+                 int32_t precision, double l2, cbh_split* best, float* scores,
+                 void* scratch, hipStream_t s);
+int64_t score_scratch_bytes(const cbh_problem* p);
+
+// Allow the dynamic-LDS kernels the device's full LDS (called by cbh_create).
+void hist_init_attrs(int max_lds);
+void batch_init_attrs(int max_lds);
+
+}  // namespace cbh

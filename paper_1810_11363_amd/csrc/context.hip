@@ -1,0 +1,207 @@
+// Context, errors, workspace and host-side border selection.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace cbh {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int ensure_ws(cbh_ctx* ctx, int64_t bytes) {
+    bytes = align_up(std::max<int64_t>(bytes, 256), 1 << 20);
+    if (bytes <= ctx->ws_size) return CBH_OK;
+    CBH_REQUIRE(bytes <= ctx->ws_limit, CBH_ENOMEM,
+                "workspace of %lld bytes exceeds the limit of %lld bytes",
+                (long long)bytes, (long long)ctx->ws_limit);
+    if (ctx->ws) {
+        // hipFree waits for work that may still use the old buffer.
+        CBH_HIP(hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_size = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->ws, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation of %lld bytes failed: %s", (long long)bytes,
+                  hipGetErrorString(e));
+        return CBH_ENOMEM;
+    }
+    ctx->ws_size = bytes;
+    return CBH_OK;
+}
+
+int validate_problem(const cbh_problem* p) {
+    CBH_ARG(p != nullptr, "problem is NULL");
+    CBH_ARG(p->n >= 1, "n must be >= 1 (got %lld)", (long long)p->n);
+    CBH_ARG(p->n < (int64_t(1) << 40), "n too large");
+    CBH_ARG(p->n_features >= 1, "n_features must be >= 1");
+    CBH_REQUIRE(p->max_bins >= 2 && p->max_bins <= CBH_MAX_BINS, CBH_EUNSUPPORTED,
+                "max_bins must be in [2, 256] (got %d)", p->max_bins);
+    CBH_ARG(p->bins != nullptr && p->n_bins != nullptr, "bins / n_bins is NULL");
+    CBH_REQUIRE(p->depth >= 1 && p->depth <= CBH_MAX_DEPTH, CBH_EUNSUPPORTED,
+                "depth must be in [1, 16] (got %d)", p->depth);
+    CBH_ARG(p->loss == CBH_LOSS_RMSE || p->loss == CBH_LOSS_LOGLOSS ||
+                p->loss == CBH_LOSS_MULTICLASS,
+            "unknown loss %d", p->loss);
+    if (p->loss == CBH_LOSS_MULTICLASS) {
+        CBH_REQUIRE(p->K >= 2 && p->K <= CBH_MAX_K, CBH_EUNSUPPORTED,
+                    "MultiClass needs 2 <= K <= 16 (got %d)", p->K);
+    } else {
+        CBH_ARG(p->K == 1, "K must be 1 for RMSE and Logloss (got %d)", p->K);
+    }
+    CBH_ARG(p->label && p->g && p->leaf && p->approx, "label/g/leaf/approx is NULL");
+    CBH_ARG(p->loss == CBH_LOSS_RMSE || p->h != nullptr, "h is NULL");
+    return CBH_OK;
+}
+
+int validate_precision(const cbh_problem* p, int32_t precision) {
+    CBH_ARG(precision == CBH_PREC_FP32 || precision == CBH_PREC_TWOFLOAT ||
+                precision == CBH_PREC_INT16,
+            "unknown precision %d", precision);
+    if (precision == CBH_PREC_INT16)
+        CBH_ARG(p->gq != nullptr && p->grad_scale != nullptr,
+                "INT16 precision needs gq and grad_scale");
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+const char* cbh_last_error(void) { return g_err; }
+
+int cbh_create(int device, cbh_ctx** out) {
+    clear_error();
+    CBH_ARG(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    CBH_HIP(hipGetDeviceCount(&count));
+    CBH_ARG(device >= 0 && device < count, "device %d out of range (%d devices)", device,
+            count);
+    CBH_HIP(hipSetDevice(device));
+    cbh_ctx* c = new cbh_ctx();
+    c->device = device;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
+        c->num_cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+        hipSuccess)
+        c->max_lds = v;
+    hipError_t e = hipMalloc(&c->d_flags, 64);
+    if (e != hipSuccess) {
+        delete c;
+        set_error("hipMalloc of error flags failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    e = hipMemset(c->d_flags, 0, 64);
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_flags);
+        delete c;
+        set_error("hipMemset failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    hist_init_attrs(c->max_lds);
+    batch_init_attrs(c->max_lds);
+    *out = c;
+    return CBH_OK;
+}
+
+void cbh_destroy(cbh_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    delete ctx;
+}
+
+int cbh_set_workspace_limit(cbh_ctx* ctx, int64_t bytes) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(bytes > 0, "limit must be > 0");
+    ctx->ws_limit = bytes;
+    return CBH_OK;
+}
+
+int64_t cbh_workspace_size(const cbh_ctx* ctx) { return ctx ? ctx->ws_size : 0; }
+
+int cbh_sync(cbh_ctx* ctx, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_HIP(hipStreamSynchronize((hipStream_t)stream));
+    CBH_HIP(hipGetLastError());
+    uint32_t flags = 0;
+    CBH_HIP(hipMemcpy(&flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags) {
+        CBH_HIP(hipMemset(ctx->d_flags, 0, sizeof(flags)));
+        std::string msg = "device reported:";
+        if (flags & FLAG_NAN_INPUT) msg += " NaN feature value (binned as 0);";
+        set_error("%s", msg.c_str());
+        return CBH_EDEVICE;
+    }
+    return CBH_OK;
+}
+
+// Value-at-rank quantile borders; see the header for the rule.
+int cbh_select_borders(const float* x_host, int64_t n, int32_t max_bins, float* borders_out,
+                       int32_t* n_borders_out) {
+    clear_error();
+    CBH_ARG(n_borders_out != nullptr && borders_out != nullptr, "output pointer is NULL");
+    *n_borders_out = 0;
+    CBH_ARG(n >= 0, "n must be >= 0");
+    CBH_ARG(n == 0 || x_host != nullptr, "x_host is NULL");
+    CBH_REQUIRE(max_bins >= 2 && max_bins <= CBH_MAX_BINS, CBH_EUNSUPPORTED,
+                "max_bins must be in [2, 256] (got %d)", max_bins);
+    if (n == 0) return CBH_OK;
+    std::vector<float> s(x_host, x_host + n);
+    for (float v : s) CBH_ARG(!std::isnan(v), "NaN value in feature column");
+    std::sort(s.begin(), s.end());
+    const float top = s[n - 1];
+    int64_t distinct = 1;
+    for (int64_t i = 1; i < n; ++i) distinct += (s[i] != s[i - 1]);
+    int32_t nb = 0;
+    if (distinct <= max_bins) {
+        float prev = 0.f;
+        for (int64_t i = 0; i < n && s[i] != top; ++i) {
+            if (nb == 0 || s[i] != prev) {
+                borders_out[nb++] = s[i];
+                prev = s[i];
+            }
+        }
+    } else {
+        for (int64_t j = 1; j < max_bins; ++j) {
+            const float c = s[(j * n) / max_bins - 1];
+            if (c == top || (nb > 0 && c == borders_out[nb - 1])) continue;
+            borders_out[nb++] = c;
+        }
+    }
+    *n_borders_out = nb;
+    return CBH_OK;
+}
+
+int cbh_uniform_borders(double lo, double hi, int32_t n_bins, double* borders_out) {
+    clear_error();
+    CBH_ARG(borders_out != nullptr, "borders_out is NULL");
+    CBH_ARG(std::isfinite(lo) && std::isfinite(hi) && hi >= lo, "need finite lo <= hi");
+    CBH_REQUIRE(n_bins >= 2 && n_bins <= CBH_MAX_BINS, CBH_EUNSUPPORTED,
+                "n_bins must be in [2, 256] (got %d)", n_bins);
+    for (int32_t j = 1; j < n_bins; ++j)
+        borders_out[j - 1] = lo + ((hi - lo) * (double)j) / (double)n_bins;
+    return CBH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,438 @@
+// Feature binarization and ordered target statistics.
+//
+// Binarization (Sec. 5, "Dense numerical features"): bin = number of borders
+// strictly below the value, found by a branch-free binary search over the
+// borders staged in LDS.
+//
+// Ordered statistics (Sec. 2, Eq. 1; GPU method of Sec. 5, "Categorical
+// features": group rows by category with a radix sort, then prefix-sum the
+// statistic inside every group with a segmented scan):
+//   1. key[p] = category of the row at permutation position p, payload = row;
+//   2. stable LSD radix sort on the 32-bit key, 8 bits per pass, so rows of a
+//      category stay in permutation order;
+//   3. segment heads are positions where the key changes; an exclusive
+//      segmented scan of 1 gives den, of the target numerator gives num
+//      (operator transformation of Sengupta, Harris and Garland: pairs
+//      (head flag, sum) combined as (f1|f2, f2 ? v2 : v1+v2));
+//   4. results are scattered back to row order together with the statistic
+//      value and its bin.
+// The scan is reduce-then-scan over 4096-element tiles (three launches), so no
+// block ever waits on another.
+#include <cmath>
+
+#include "common.h"
+
+namespace cbh {
+
+// ------------------------------------------------------------------ quantize
+__global__ __launch_bounds__(256) void quantize_kernel(const float* __restrict__ x, int64_t n,
+                                                       const float* __restrict__ borders,
+                                                       int32_t nb, uint8_t* __restrict__ out,
+                                                       uint32_t* __restrict__ flags) {
+    __shared__ float sb[256];
+    for (int i = threadIdx.x; i < 256; i += 256) sb[i] = i < nb ? borders[i] : INFINITY;
+    __syncthreads();
+    auto bin_of = [&](float v) -> uint32_t {
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t step = 128; step >= 1; step >>= 1)
+            if (sb[pos + step - 1] < v) pos += step;
+        return pos;
+    };
+    bool nan_seen = false;
+    const int64_t n4 = n / 4;
+    const bool vec = ((reinterpret_cast<uintptr_t>(x) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(out) & 3) == 0);
+    const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    if (vec) {
+        for (int64_t q = tid; q < n4; q += stride) {
+            float4 v = reinterpret_cast<const float4*>(x)[q];
+            nan_seen |= (v.x != v.x) | (v.y != v.y) | (v.z != v.z) | (v.w != v.w);
+            uint32_t w = bin_of(v.x) | (bin_of(v.y) << 8) | (bin_of(v.z) << 16) |
+                         (bin_of(v.w) << 24);
+            reinterpret_cast<uint32_t*>(out)[q] = w;
+        }
+        for (int64_t i = n4 * 4 + tid; i < n; i += stride) {
+            float v = x[i];
+            nan_seen |= (v != v);
+            out[i] = (uint8_t)bin_of(v);
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += stride) {
+            float v = x[i];
+            nan_seen |= (v != v);
+            out[i] = (uint8_t)bin_of(v);
+        }
+    }
+    if (nan_seen) atomicOr(flags, FLAG_NAN_INPUT);
+}
+
+// ------------------------------------------------------------- radix sort
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kTile = kSortThreads * kSortItems;  // 4096 keys per block
+
+// Per-tile digit counts, stored digit-major: counts[d * n_tiles + tile].
+__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
+    const uint32_t* __restrict__ keys, int64_t n, int shift, int64_t n_tiles,
+    int64_t* __restrict__ counts) {
+    __shared__ uint32_t c[256];
+    c[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kTile;
+#pragma unroll 4
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t i = base + j * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&c[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[int64_t(threadIdx.x) * n_tiles + blockIdx.x] = c[threadIdx.x];
+}
+
+// Scatter with stable in-tile ranks. Keys of a tile are visited in 16 rounds
+// of 256 (round-major, thread-minor), so rank order equals input order.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals, int64_t n, int shift,
+    int64_t n_tiles, const int64_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    run[threadIdx.x] = 0;
+    const int64_t base = int64_t(blockIdx.x) * kTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t goff = offsets[int64_t(threadIdx.x) * n_tiles + blockIdx.x];
+    __shared__ int64_t gbase[256];
+    gbase[threadIdx.x] = goff;
+    for (int j = 0; j < kSortItems; ++j) {
+        for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t i = base + j * kSortThreads + threadIdx.x;
+        const bool act = i < n;
+        uint32_t key = act ? keys[i] : 0u;
+        int32_t val = act ? vals[i] : 0;
+        uint32_t d = (key >> shift) & 255u;
+        uint64_t same = __ballot(act);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot(((d >> b) & 1u) != 0u);
+            same &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank_w = __popcll(same & lt_mask);
+        // the lowest lane of each digit group publishes the group size
+        if (act && rank_w == 0) wcnt[wave][d] = __popcll(same);
+        __syncthreads();
+        if (act) {
+            uint32_t before = run[d];
+            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+            const int64_t dst = gbase[d] + before + rank_w;
+            keys_out[dst] = key;
+            vals_out[dst] = val;
+        }
+        __syncthreads();
+        run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                            wcnt[3][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ void gather_keys_kernel(const int32_t* __restrict__ cat,
+                                   const int32_t* __restrict__ perm, int64_t n,
+                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        int32_t r = perm[p];
+        keys[p] = (uint32_t)cat[r];
+        vals[p] = r;
+    }
+}
+
+// ---------------------------------------------------------- segmented scan
+// Element i contributes (head_i, v_i). Modes:
+//   0: v = values[i] (plain values array), head = (i == 0)
+//   1: v = 1, head = key change
+//   2: v = y[vals[i]], head = key change
+struct ScanSrc {
+    int mode;
+    const int64_t* values;
+    const uint32_t* keys;
+    const int32_t* vals;
+    const int64_t* y;
+};
+
+struct SegPair {
+    int64_t v;
+    int f;
+};
+
+__device__ __forceinline__ SegPair seg_op(SegPair a, SegPair b) {
+    return SegPair{b.f ? b.v : a.v + b.v, a.f | b.f};
+}
+
+__device__ __forceinline__ SegPair load_elem(const ScanSrc& s, int64_t i) {
+    if (s.mode == 0) return SegPair{s.values[i], i == 0};
+    int head = (i == 0) || (s.keys[i] != s.keys[i - 1]);
+    int64_t v = s.mode == 1 ? 1 : s.y[s.vals[i]];
+    return SegPair{v, head};
+}
+
+__device__ __forceinline__ SegPair shfl_up_pair(SegPair p, int d) {
+    SegPair q;
+    q.v = __shfl_up(p.v, d, 64);
+    q.f = __shfl_up(p.f, d, 64);
+    return q;
+}
+
+// Inclusive block scan of one pair per thread (thread order); returns the
+// inclusive value of this thread; *total gets the block aggregate.
+__device__ SegPair block_scan(SegPair x, SegPair* total) {
+    __shared__ SegPair wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        SegPair y = shfl_up_pair(x, d);
+        if (lane >= d) x = seg_op(y, x);
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    SegPair pre{0, 0};
+    for (int w = 0; w < wave; ++w) pre = seg_op(pre, wsum[w]);
+    if (wave > 0) x = seg_op(pre, x);
+    SegPair tot{0, 0};
+    for (int w = 0; w < 4; ++w) tot = seg_op(tot, wsum[w]);
+    *total = tot;
+    __syncthreads();
+    return x;
+}
+
+__global__ __launch_bounds__(256) void seg_reduce_kernel(ScanSrc src, int64_t n,
+                                                         SegPair* __restrict__ agg) {
+    const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(threadIdx.x) * kSortItems;
+    SegPair acc{0, 0};
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t i = base + j;
+        if (i < n) acc = seg_op(acc, load_elem(src, i));
+    }
+    SegPair tot;
+    block_scan(acc, &tot);
+    if (threadIdx.x == 0) agg[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the tile aggregates by one block; carry[t] is the value
+// carried into tile t.
+__global__ __launch_bounds__(256) void seg_carry_kernel(const SegPair* __restrict__ agg,
+                                                        int64_t n_tiles,
+                                                        int64_t* __restrict__ carry) {
+    const int64_t per = (n_tiles + 255) / 256;
+    const int64_t b0 = int64_t(threadIdx.x) * per;
+    SegPair acc{0, 0};
+    for (int64_t t = b0; t < b0 + per && t < n_tiles; ++t) acc = seg_op(acc, agg[t]);
+    SegPair tot;
+    SegPair inc = block_scan(acc, &tot);
+    // exclusive prefix for this thread's range
+    SegPair ex = shfl_up_pair(inc, 1);
+    __shared__ SegPair last[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 63) last[wave] = inc;
+    __syncthreads();
+    if (lane == 0) ex = (wave == 0) ? SegPair{0, 0} : last[wave - 1];
+    SegPair run = ex;
+    for (int64_t t = b0; t < b0 + per && t < n_tiles; ++t) {
+        carry[t] = run.v;
+        run = seg_op(run, agg[t]);
+    }
+}
+
+// Exclusive segmented scan written in sorted order.
+__global__ __launch_bounds__(256) void seg_scan_kernel(ScanSrc src, int64_t n,
+                                                       const int64_t* __restrict__ carry,
+                                                       int64_t* __restrict__ out) {
+    const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(threadIdx.x) * kSortItems;
+    SegPair e[kSortItems];
+    SegPair acc{0, 0};
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t i = base + j;
+        e[j] = (i < n) ? load_elem(src, i) : SegPair{0, 0};
+        acc = seg_op(acc, e[j]);
+    }
+    SegPair tot;
+    SegPair inc = block_scan(acc, &tot);
+    // exclusive thread prefix, then seed with the tile carry
+    SegPair ex = shfl_up_pair(inc, 1);
+    __shared__ SegPair last[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 63) last[wave] = inc;
+    __syncthreads();
+    if (lane == 0) ex = (wave == 0) ? SegPair{0, 0} : last[wave - 1];
+    SegPair run = seg_op(SegPair{carry[blockIdx.x], 0}, ex);
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t i = base + j;
+        SegPair before = e[j].f ? SegPair{0, 1} : run;
+        if (i < n) out[i] = before.v;
+        run = seg_op(run, e[j]);
+    }
+}
+
+// Scatter num/den back to row order, with the statistic value and its bin.
+__global__ __launch_bounds__(256) void ts_scatter_kernel(
+    const int32_t* __restrict__ rows, const int64_t* __restrict__ den_sorted,
+    const int64_t* __restrict__ num_sorted, int64_t n, int32_t y_shift, double a, double ap,
+    const double* __restrict__ tsb, int32_t ntsb, int64_t* __restrict__ num_out,
+    int32_t* __restrict__ den_out, uint8_t* __restrict__ bin_out, double* __restrict__ ts_out) {
+    __shared__ double sb[256];
+    for (int i = threadIdx.x; i < 256; i += 256) sb[i] = (i < ntsb) ? tsb[i] : INFINITY;
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        const int32_t r = rows[i];
+        const int64_t den = den_sorted[i];
+        if (den_out) den_out[r] = (int32_t)den;
+        if (!num_sorted) continue;
+        const int64_t num = num_sorted[i];
+        if (num_out) num_out[r] = num;
+        if (ts_out || bin_out) {
+            // (num * 2^-e + a * P) / (den + a), operation order fixed, no contraction
+            const double t = (ldexp((double)num, -y_shift) + ap) / ((double)den + a);
+            if (ts_out) ts_out[r] = t;
+            if (bin_out) {
+                uint32_t pos = 0;
+#pragma unroll
+                for (uint32_t step = 128; step >= 1; step >>= 1)
+                    if (sb[pos + step - 1] < t) pos += step;
+                bin_out[r] = (uint8_t)pos;
+            }
+        }
+    }
+}
+
+static int grid_for(int64_t n, int per_block, int cap = 16384) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+int cbh_quantize(cbh_ctx* ctx, const float* x, int64_t n, const float* borders,
+                 int32_t n_borders, uint8_t* bins_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0, "n must be >= 0");
+    CBH_REQUIRE(n_borders >= 0 && n_borders <= 255, CBH_EUNSUPPORTED,
+                "n_borders must be in [0, 255] (got %d)", n_borders);
+    if (n == 0) return CBH_OK;
+    CBH_ARG(x && bins_out, "x / bins_out is NULL");
+    CBH_ARG(n_borders == 0 || borders, "borders is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    quantize_kernel<<<grid_for((n + 3) / 4, 256, ctx->num_cus * 8), 256, 0, s>>>(
+        x, n, borders, n_borders, bins_out, ctx->d_flags);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, int64_t n,
+                           const int64_t* y_num, int32_t n_targets, int32_t y_shift,
+                           int64_t y_abs_max, double a, const double* priors,
+                           const double* ts_borders, int32_t n_ts_borders, int64_t* num_out,
+                           int32_t* den_out, uint8_t* ts_bin_out, double* ts_out,
+                           void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n < (int64_t(1) << 31), "n must be in [0, 2^31)");
+    CBH_ARG(n_targets >= 1 && n_targets <= 16, "n_targets must be in [1, 16]");
+    CBH_ARG(y_shift >= 0 && y_shift <= 62, "y_shift must be in [0, 62]");
+    CBH_ARG(y_abs_max >= 0, "y_abs_max must be >= 0");
+    CBH_ARG(a > 0 && std::isfinite(a), "prior weight a must be finite and > 0");
+    CBH_ARG(priors != nullptr, "priors is NULL");
+    for (int t = 0; t < n_targets; ++t) CBH_ARG(std::isfinite(priors[t]), "prior not finite");
+    CBH_REQUIRE(n_ts_borders >= 0 && n_ts_borders <= 255, CBH_EUNSUPPORTED,
+                "n_ts_borders must be in [0, 255]");
+    CBH_ARG(ts_bin_out == nullptr || n_ts_borders == 0 || ts_borders != nullptr,
+            "ts_borders is NULL");
+    CBH_REQUIRE(y_abs_max == 0 || (double)n * (double)y_abs_max < 4.611686018427387904e18,
+                CBH_EOVERFLOW, "n * y_abs_max must be < 2^62 for exact int64 sums");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(cat && perm && y_num, "cat / perm / y_num is NULL");
+    const bool need_num = num_out || ts_bin_out || ts_out;
+
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    const int64_t cnt_elems = 256 * n_tiles;
+    const int64_t cnt_tiles = (cnt_elems + kTile - 1) / kTile;
+    const int64_t max_tiles = std::max(n_tiles, cnt_tiles);
+    // workspace: keys x2, vals x2, den, num, counts, aggregates, carries
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = off; off += align_up(bytes, 256); return o; };
+    const int64_t o_k0 = take(4 * n), o_k1 = take(4 * n), o_v0 = take(4 * n),
+                  o_v1 = take(4 * n), o_den = take(8 * n), o_num = take(8 * n),
+                  o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
+                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
+    int rc = ensure_ws(ctx, off);
+    if (rc != CBH_OK) return rc;
+    char* w = (char*)ctx->ws;
+    uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
+    int32_t* vals[2] = {(int32_t*)(w + o_v0), (int32_t*)(w + o_v1)};
+    int64_t* den_s = (int64_t*)(w + o_den);
+    int64_t* num_s = (int64_t*)(w + o_num);
+    int64_t* counts = (int64_t*)(w + o_cnt);
+    int64_t* offs = (int64_t*)(w + o_off);
+    SegPair* agg = (SegPair*)(w + o_agg);
+    int64_t* car = (int64_t*)(w + o_car);
+    hipStream_t s = (hipStream_t)stream;
+
+    auto scan = [&](ScanSrc src, int64_t len, int64_t* out) -> int {
+        const int64_t tiles = (len + kTile - 1) / kTile;
+        seg_reduce_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, agg);
+        seg_carry_kernel<<<1, 256, 0, s>>>(agg, tiles, car);
+        seg_scan_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, car, out);
+        CBH_LAUNCHED();
+        return CBH_OK;
+    };
+
+    gather_keys_kernel<<<grid_for(n, 256, ctx->num_cus * 8), 256, 0, s>>>(cat, perm, n, keys[0],
+                                                                           vals[0]);
+    CBH_LAUNCHED();
+    int cur = 0;
+    for (int shift = 0; shift < 32; shift += 8) {
+        radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], n, shift,
+                                                                      n_tiles, counts);
+        CBH_LAUNCHED();
+        rc = scan(ScanSrc{0, counts, nullptr, nullptr, nullptr}, cnt_elems, offs);
+        if (rc != CBH_OK) return rc;
+        radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
+            keys[cur], vals[cur], n, shift, n_tiles, offs, keys[cur ^ 1], vals[cur ^ 1]);
+        CBH_LAUNCHED();
+        cur ^= 1;
+    }
+    const uint32_t* sk = keys[cur];
+    const int32_t* sv = vals[cur];
+    rc = scan(ScanSrc{1, nullptr, sk, sv, nullptr}, n, den_s);
+    if (rc != CBH_OK) return rc;
+    const int gs = grid_for(n, 256, ctx->num_cus * 8);
+    if (!need_num) {
+        ts_scatter_kernel<<<gs, 256, 0, s>>>(sv, den_s, nullptr, n, 0, a, 0.0, nullptr, 0,
+                                             nullptr, den_out, nullptr, nullptr);
+        CBH_LAUNCHED();
+        return CBH_OK;
+    }
+    for (int t = 0; t < n_targets; ++t) {
+        rc = scan(ScanSrc{2, nullptr, sk, sv, y_num + int64_t(t) * n}, n, num_s);
+        if (rc != CBH_OK) return rc;
+        const double ap = a * priors[t];
+        ts_scatter_kernel<<<gs, 256, 0, s>>>(
+            sv, den_s, num_s, n, y_shift, a, ap, ts_borders, ts_bin_out ? n_ts_borders : 0,
+            num_out ? num_out + int64_t(t) * n : nullptr, t == 0 ? den_out : nullptr,
+            ts_bin_out ? ts_bin_out + int64_t(t) * n : nullptr,
+            ts_out ? ts_out + int64_t(t) * n : nullptr);
+        CBH_LAUNCHED();
+    }
+    return CBH_OK;
+}
+
+}  // extern "C"

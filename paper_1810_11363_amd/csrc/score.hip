@@ -1,0 +1,93 @@
+// Split scoring and argmax (Sec. 3: the first phase scores candidate splits
+// and keeps the best; Sec. 4: one split per level of an oblivious tree).
+//
+// Score of splitting every current leaf L by (f, k):
+//   S(f, k) = sum_L sum_c  Gl^2 / (Hl + l2) + Gr^2 / (Hr + l2)
+// (the paper gives no formula; this is the gain of the L2-regularised
+// second-order objective, with the parent term, equal for all candidates,
+// dropped). A side with H + l2 == 0 contributes 0.
+//
+// Kernel 1: one block per feature; each wave takes (leaf, class) rows of the
+// histogram, one lane per 4 consecutive bins, forms bin prefixes with a wave
+// scan, and accumulates the per-border terms in registers. The four waves'
+// partial scores are added in wave order (deterministic), then the block
+// keeps its best and second-best border. Kernel 2: one block reduces the
+// per-feature winners to the level's split with the tie rule "largest score,
+// then smallest feature, then smallest border".
+#include <cmath>
+
+#include "common.h"
+#include "kernels_dev.h"
+
+namespace cbh {
+
+template <int PREC>
+__global__ __launch_bounds__(256) void score_feature_kernel(ScoreRow r, const int32_t* n_bins,
+                                                            int32_t L, float* scores,
+                                                            FeatBest* fbest) {
+    const int f = blockIdx.x;
+    score_feature<PREC>(r, L, f, n_bins[f], scores, &fbest[f]);
+}
+
+__global__ __launch_bounds__(256) void score_argmax_kernel(const FeatBest* __restrict__ fb,
+                                                           int32_t F, int32_t Bm1,
+                                                           cbh_split* __restrict__ out) {
+    argmax_features(fb, F, Bm1, out);
+}
+
+int64_t score_scratch_bytes(const cbh_problem* p) {
+    return align_up(int64_t(p->n_features) * sizeof(FeatBest), 256);
+}
+
+int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
+                 int32_t precision, double l2, cbh_split* best, float* scores, void* scratch,
+                 hipStream_t s) {
+    (void)ctx;
+    ScoreRow r;
+    r.hist = hist;
+    r.grad_scale = p->grad_scale;
+    r.F = p->n_features;
+    r.B = p->max_bins;
+    r.K = p->K;
+    r.rmse = p->loss == CBH_LOSS_RMSE;
+    r.l2 = (float)l2;
+    const int L = 1 << level;
+    FeatBest* fb = (FeatBest*)scratch;
+    switch (precision) {
+        case CBH_PREC_FP32:
+            score_feature_kernel<CBH_PREC_FP32><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            score_feature_kernel<CBH_PREC_TWOFLOAT><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores,
+                                                                       fb);
+            break;
+        default:
+            score_feature_kernel<CBH_PREC_INT16><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb);
+            break;
+    }
+    score_argmax_kernel<<<1, 256, 0, s>>>(fb, r.F, r.B - 1, best);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" int cbh_score_splits(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                                const void* hist, int32_t precision, double l2,
+                                cbh_split* best_out, float* scores_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
+    CBH_ARG(hist && best_out, "hist / best_out is NULL");
+    CBH_ARG(l2 >= 0 && std::isfinite(l2), "l2 must be finite and >= 0");
+    rc = ensure_ws(ctx, score_scratch_bytes(prob));
+    if (rc) return rc;
+    return launch_score(ctx, prob, level, hist, precision, l2, best_out, scores_out, ctx->ws,
+                        (hipStream_t)stream);
+}

@@ -1,0 +1,299 @@
+// Leaf bits, leaf values and the model/gradient update.
+//
+// apply_split: the split of depth `level` sets bit `level` of the leaf index
+// (Sec. 4: leaf = sum_i 2^i B(x, f(t, i))); at level 0 the leaf is
+// overwritten, so a tree never needs a separate reset of the leaf array.
+// leaf_solve: final-leaf sums taken from the last level's histogram row of the
+// chosen feature (left of the border -> bit clear, right -> bit set), summed in
+// double, and the Newton value -G / (H + l2) (Sec. 3: second phase is the
+// ordinary boosting step; Newton or gradient leaf estimates).
+// update: approx += lr * v[leaf] in double (Algorithm 1 adds each tree to the
+// model), then g = dLoss/da and h = d2Loss/da2 at the new approx in double,
+// stored as float.
+#include <cmath>
+
+#include "common.h"
+
+namespace cbh {
+
+__global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* __restrict__ bins,
+                                                          int32_t F, const cbh_split* __restrict__ best,
+                                                          uint16_t* __restrict__ leaf, int64_t n,
+                                                          int32_t level) {
+    int f = best->feature;
+    int k = best->border;
+    if (f < 0 || f >= F) {
+        // no split: every row stays on the clear side of this level's bit
+        if (level != 0) return;
+        f = 0;
+        k = 255;
+    }
+    const uint8_t* __restrict__ col = bins[f];
+    const uint32_t bit = 1u << level;
+    const int64_t n8 = n / 8;
+    const bool vec = ((reinterpret_cast<uintptr_t>(col) & 7) == 0);
+    const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    if (vec) {
+        for (int64_t q = tid; q < n8; q += stride) {
+            const uint2 b = reinterpret_cast<const uint2*>(col)[q];
+            uint4 l = level == 0 ? make_uint4(0u, 0u, 0u, 0u)
+                                 : reinterpret_cast<const uint4*>(leaf)[q];
+            uint32_t lw[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const uint32_t bv = ((r < 4 ? b.x : b.y) >> (8 * (r & 3))) & 255u;
+                if ((int)bv > k) lw[r >> 1] |= bit << (16 * (r & 1));
+            }
+            reinterpret_cast<uint4*>(leaf)[q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+        for (int64_t i = n8 * 8 + tid; i < n; i += stride) {
+            const uint32_t old = level == 0 ? 0u : leaf[i];
+            leaf[i] = (uint16_t)(old | (((int)col[i] > k) ? bit : 0u));
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += stride) {
+            const uint32_t old = level == 0 ? 0u : leaf[i];
+            leaf[i] = (uint16_t)(old | (((int)col[i] > k) ? bit : 0u));
+        }
+    }
+}
+
+struct SolveArgs {
+    const void* hist;
+    const cbh_split* split;
+    const float* grad_scale;
+    double* values;
+    int32_t depth, F, B, K, rmse, precision;
+    double l2;
+};
+
+__global__ __launch_bounds__(256) void leaf_solve_kernel(SolveArgs a) {
+    const int64_t leaves = int64_t(1) << a.depth;
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= leaves * a.K) return;
+    const int64_t Lf = t / a.K;
+    const int c = (int)(t % a.K);
+    const int64_t half = leaves >> 1;
+    const int64_t L = Lf & (half - 1);
+    const bool right = (Lf & half) != 0;
+    int f = a.split->feature;
+    int k = a.split->border;
+    if (f < 0 || f >= a.F) {  // no split: every row stayed left
+        f = 0;
+        k = a.B - 1;
+    }
+    const int b_lo = right ? k + 1 : 0;
+    const int b_hi = right ? a.B : k + 1;
+    const int64_t cell0 = (L * a.F + f) * a.B;
+    double G = 0.0, H = 0.0;
+    for (int b = b_lo; b < b_hi; ++b) {
+        const int64_t e = (cell0 + b) * 2 * a.K + 2 * c;
+        if (a.precision == CBH_PREC_FP32) {
+            G += (double)reinterpret_cast<const float*>(a.hist)[e];
+            H += a.rmse ? (double)reinterpret_cast<const uint32_t*>(a.hist)[e + 1]
+                        : (double)reinterpret_cast<const float*>(a.hist)[e + 1];
+        } else if (a.precision == CBH_PREC_TWOFLOAT) {
+            const float2 gg = reinterpret_cast<const float2*>(a.hist)[e];
+            const float2 hh = reinterpret_cast<const float2*>(a.hist)[e + 1];
+            G += (double)gg.x + (double)gg.y;
+            H += a.rmse ? (double)__float_as_uint(hh.x) : (double)hh.x + (double)hh.y;
+        } else {
+            G += (double)reinterpret_cast<const int64_t*>(a.hist)[e];
+            H += (double)reinterpret_cast<const int64_t*>(a.hist)[e + 1];
+        }
+    }
+    if (a.precision == CBH_PREC_INT16) {
+        G *= (double)a.grad_scale[2 * c];
+        if (!a.rmse) H *= (double)a.grad_scale[2 * c + 1];
+    }
+    const double d = H + a.l2;
+    a.values[Lf * a.K + c] = d == 0.0 ? 0.0 : -G / d;
+}
+
+struct UpdArgs {
+    const uint16_t* leaf;
+    const double* values;
+    const float* label;
+    double* approx;
+    float* g;
+    float* h;
+    int64_t n;
+    int32_t K, loss, add;
+    uint16_t lmask;
+    double lr;
+};
+
+template <int LOSS>
+__global__ __launch_bounds__(256) void update_kernel(UpdArgs a) {
+    const int K = a.K;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < a.n;
+         i += int64_t(gridDim.x) * 256) {
+        const double y = (double)a.label[i];
+        const int64_t Lf = a.add ? (a.leaf[i] & a.lmask) : 0;
+        if constexpr (LOSS != CBH_LOSS_MULTICLASS) {
+            double ap = a.approx[i];
+            if (a.add) {
+                ap = ap + a.lr * a.values[Lf];
+                a.approx[i] = ap;
+            }
+            if constexpr (LOSS == CBH_LOSS_RMSE) {
+                a.g[i] = (float)(ap - y);
+            } else {
+                const double p = 1.0 / (1.0 + exp(-ap));
+                a.g[i] = (float)(p - y);
+                a.h[i] = (float)(p * (1.0 - p));
+            }
+        } else {
+            double av[CBH_MAX_K];
+            double mx = -INFINITY;
+            for (int c = 0; c < K; ++c) {
+                double v = a.approx[int64_t(c) * a.n + i];
+                if (a.add) {
+                    v = v + a.lr * a.values[Lf * K + c];
+                    a.approx[int64_t(c) * a.n + i] = v;
+                }
+                av[c] = v;
+                mx = v > mx ? v : mx;
+            }
+            double z = 0.0;
+            for (int c = 0; c < K; ++c) z += exp(av[c] - mx);
+            const int yc = (int)y;
+            for (int c = 0; c < K; ++c) {
+                const double p = exp(av[c] - mx) / z;
+                a.g[int64_t(c) * a.n + i] = (float)(p - (c == yc ? 1.0 : 0.0));
+                a.h[int64_t(c) * a.n + i] = (float)(p * (1.0 - p));
+            }
+        }
+    }
+}
+
+__global__ void zero_i64_kernel(int64_t* p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+// Rows per final leaf: LDS counters per block, one global add per leaf.
+__global__ __launch_bounds__(256) void leaf_count_kernel(const uint16_t* __restrict__ leaf,
+                                                         int64_t n, int32_t leaves,
+                                                         unsigned long long* __restrict__ out) {
+    extern __shared__ uint32_t cnt[];
+    for (int i = threadIdx.x; i < leaves; i += 256) cnt[i] = 0u;
+    __syncthreads();
+    const uint32_t m = (uint32_t)leaves - 1u;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256)
+        atomicAdd(&cnt[leaf[i] & m], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < leaves; i += 256)
+        if (cnt[i]) atomicAdd(&out[i], (unsigned long long)cnt[i]);
+}
+
+static int grid_rows(const cbh_ctx* ctx, int64_t n, int per_thread = 1) {
+    int64_t g = (n + 256LL * per_thread - 1) / (256LL * per_thread);
+    if (g < 1) g = 1;
+    const int64_t cap = int64_t(ctx->num_cus) * 8;
+    return (int)(g < cap ? g : cap);
+}
+
+int launch_apply(const cbh_ctx* ctx, const cbh_problem* p, int32_t level, const cbh_split* best,
+                 hipStream_t s) {
+    apply_split_kernel<<<grid_rows(ctx, p->n, 8), 256, 0, s>>>(p->bins, p->n_features, best,
+                                                               p->leaf, p->n, level);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_last,
+                  int32_t precision, const cbh_split* last, double lr, double l2,
+                  double* leaf_values, int64_t* leaf_counts, hipStream_t s) {
+    const int64_t leaves = int64_t(1) << p->depth;
+    if (hist_last) {
+        SolveArgs sa;
+        sa.hist = hist_last;
+        sa.split = last;
+        sa.grad_scale = p->grad_scale;
+        sa.values = leaf_values;
+        sa.depth = p->depth;
+        sa.F = p->n_features;
+        sa.B = p->max_bins;
+        sa.K = p->K;
+        sa.rmse = p->loss == CBH_LOSS_RMSE;
+        sa.precision = precision;
+        sa.l2 = l2;
+        const int64_t work = leaves * p->K;
+        leaf_solve_kernel<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(sa);
+        CBH_LAUNCHED();
+    }
+    UpdArgs ua;
+    ua.leaf = p->leaf;
+    ua.values = leaf_values;
+    ua.label = p->label;
+    ua.approx = p->approx;
+    ua.g = p->g;
+    ua.h = p->h;
+    ua.n = p->n;
+    ua.K = p->K;
+    ua.loss = p->loss;
+    ua.add = hist_last != nullptr;
+    ua.lmask = (uint16_t)(leaves - 1);
+    ua.lr = lr;
+    const int gr = grid_rows(ctx, p->n);
+    switch (p->loss) {
+        case CBH_LOSS_RMSE: update_kernel<CBH_LOSS_RMSE><<<gr, 256, 0, s>>>(ua); break;
+        case CBH_LOSS_LOGLOSS: update_kernel<CBH_LOSS_LOGLOSS><<<gr, 256, 0, s>>>(ua); break;
+        default: update_kernel<CBH_LOSS_MULTICLASS><<<gr, 256, 0, s>>>(ua); break;
+    }
+    CBH_LAUNCHED();
+    if (leaf_counts) {
+        zero_i64_kernel<<<(unsigned)((leaves + 255) / 256), 256, 0, s>>>(leaf_counts, leaves);
+        leaf_count_kernel<<<grid_rows(ctx, p->n, 16), 256, (size_t)leaves * 4, s>>>(
+            p->leaf, p->n, (int32_t)leaves, (unsigned long long*)leaf_counts);
+        CBH_LAUNCHED();
+    }
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+int cbh_apply_split(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, const cbh_split* best,
+                    void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
+    CBH_ARG(best != nullptr, "best is NULL");
+    return launch_apply(ctx, prob, level, best, (hipStream_t)stream);
+}
+
+int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_last,
+                      int32_t precision, const cbh_split* last, double lr, double l2,
+                      double* leaf_values_out, int64_t* leaf_counts_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    if (hist_last) {
+        rc = validate_precision(prob, precision);
+        if (rc) return rc;
+        CBH_ARG(last != nullptr && leaf_values_out != nullptr,
+                "last and leaf_values_out are required with hist_last");
+        CBH_ARG(std::isfinite(lr), "lr must be finite");
+        CBH_ARG(l2 >= 0 && std::isfinite(l2), "l2 must be finite and >= 0");
+        CBH_REQUIRE(prob->depth <= 13 || leaf_counts_out == nullptr, CBH_EUNSUPPORTED,
+                    "leaf counts need depth <= 13");
+    } else {
+        CBH_ARG(last == nullptr && leaf_values_out == nullptr && leaf_counts_out == nullptr,
+                "without hist_last, last / leaf_values_out / leaf_counts_out must be NULL");
+    }
+    return launch_update(ctx, prob, hist_last, precision, last, lr, l2, leaf_values_out,
+                         leaf_counts_out, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,446 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bit-exact: bins, ordered-statistic numerators/denominators/values/bins, leaf
+indices, row counts, int16 gradient codes and integer histograms.
+Tolerance (tests/gpu_util.py): float32 and two-float histogram sums and leaf
+values by their error normalised by the sum of magnitudes; splits identical
+wherever the oracle's top-two margin exceeds 1e-5 of the best score.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_11363_amd import cbhip
+    return cbhip
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.cbh_create(0)
+    yield c
+    torch.cuda.synchronize()
+    cb.cbh_destroy(c)
+
+
+# ------------------------------------------------------------------ quantize
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 1000, 4097, 100003])
+@pytest.mark.parametrize("max_bins", [2, 33, 128, 255, 256])
+def test_quantize_bit_exact(cb, ctx, n, max_bins):
+    g = np.random.default_rng(n * 7 + max_bins)
+    x = g.standard_normal(n).astype(np.float32)
+    x[: n // 3] = np.round(x[: n // 3] * 4) / 4          # duplicates land on borders
+    borders = oracle.select_borders(x, max_bins)
+    want = oracle.quantize(x, borders)
+    xd = gu.to_dev(x)
+    bd = gu.to_dev(borders if borders.size else np.zeros(1, np.float32))
+    out = torch.empty(n, dtype=torch.uint8, device=gu.dev())
+    cb.cbh_quantize(ctx, xd, n, bd, borders.size, out)
+    cb.cbh_sync(ctx)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_quantize_unaligned_and_nan(cb, ctx):
+    g = np.random.default_rng(5)
+    x = g.standard_normal(1001).astype(np.float32)
+    borders = oracle.select_borders(x, 64)
+    xd = gu.to_dev(x)
+    bd = gu.to_dev(borders)
+    out = torch.zeros(1001, dtype=torch.uint8, device=gu.dev())
+    # start one element in: the vector path is not aligned and must fall back
+    cb.cbh_quantize(ctx, xd.data_ptr() + 4, 1000, bd, borders.size, out.data_ptr() + 1)
+    cb.cbh_sync(ctx)
+    assert np.array_equal(out.cpu().numpy()[1:], oracle.quantize(x[1:], borders))
+    x[17] = np.nan
+    xd = gu.to_dev(x)
+    cb.cbh_quantize(ctx, xd, 1001, bd, borders.size, out)
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_sync(ctx)
+    assert e.value.code == cb.CBH_EDEVICE and "NaN" in str(e.value)
+    assert out[17].item() == 0
+    cb.cbh_sync(ctx)     # flag was cleared
+
+
+def test_quantize_rejects_bad_args(cb, ctx):
+    x = torch.zeros(4, device=gu.dev())
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_quantize(ctx, x, 4, x, 256, x)
+    assert e.value.code == cb.CBH_EUNSUPPORTED
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_quantize(ctx, None, 4, x, 3, x)
+    assert e.value.code == cb.CBH_EINVAL
+
+
+# --------------------------------------------------------------- ordered TS
+def _ts_gpu(cb, ctx, cat, perm, y_num, y_shift, a, priors, borders):
+    n = cat.size
+    T = y_num.shape[0]
+    num = torch.empty((T, n), dtype=torch.int64, device=gu.dev())
+    den = torch.empty(n, dtype=torch.int32, device=gu.dev())
+    tsb = torch.empty((T, n), dtype=torch.uint8, device=gu.dev())
+    ts = torch.empty((T, n), dtype=torch.float64, device=gu.dev())
+    bd = gu.to_dev(borders if borders.size else np.zeros(1))
+    yabs = int(np.abs(y_num).max()) if y_num.size else 0
+    cb.cbh_compute_ordered_ts(ctx, gu.to_dev(cat), gu.to_dev(perm), n, gu.to_dev(y_num), T,
+                              y_shift, yabs, a, priors, bd, borders.size, num, den, tsb, ts)
+    cb.cbh_sync(ctx)
+    return num.cpu().numpy(), den.cpu().numpy(), ts.cpu().numpy(), tsb.cpu().numpy()
+
+
+def test_ordered_ts_hand_examples(cb, ctx):
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ordered_ts_hand.json")
+    for case in json.load(open(path))["cases"]:
+        num, den, ts, _ = _ts_gpu(cb, ctx, np.array(case["cat"], np.int32),
+                                  np.array(case["perm"], np.int32),
+                                  np.array([case["y"]], np.int64), 0, case["a"], [case["prior"]],
+                                  np.zeros(0))
+        assert num[0].tolist() == case["num"] and den.tolist() == case["den"]
+        assert np.array_equal(ts[0], np.array(case["ts"]))
+
+
+@pytest.mark.parametrize("n,C", [(1, 1), (2, 2), (4095, 7), (4096, 1000), (4097, 4097),
+                                 (50000, 1), (50000, 300), (200003, 50000)])
+def test_ordered_ts_bit_exact(cb, ctx, n, C):
+    g = np.random.default_rng(n + C)
+    vals = g.choice(2**32, size=min(C, n), replace=False).astype(np.int64) - 2**31
+    cat = vals.astype(np.int32)[g.integers(0, vals.size, n)]
+    perm = g.permutation(n).astype(np.int32)
+    y = np.stack([g.integers(0, 2, n), g.integers(0, 2, n), (g.random(n) < 0.1).astype(np.int64)])
+    borders = oracle.ts_borders(0.0, 1.0, 33)
+    priors = [0.5, 0.3, 0.1]
+    num, den, ts, tb = _ts_gpu(cb, ctx, cat, perm, y, 0, 1.0, priors, borders)
+    for t in range(3):
+        rn, rd, rt, rb = oracle.ordered_ts(cat, perm, y[t], 0, 1.0, priors[t], borders)
+        assert np.array_equal(num[t], rn)
+        assert np.array_equal(den, rd)
+        assert np.array_equal(ts[t], rt)          # bitwise: same IEEE operations
+        assert np.array_equal(tb[t], rb)
+
+
+def test_ordered_ts_fixed_point_regression(cb, ctx):
+    g = np.random.default_rng(9)
+    n = 30011
+    cat = g.integers(0, 100, n).astype(np.int32)
+    perm = g.permutation(n).astype(np.int32)
+    y = g.normal(0, 3, n)
+    y_num = np.rint(y * 2.0**32).astype(np.int64)[None, :]
+    prior = float(y.mean())
+    borders = oracle.ts_borders(float(y.min()), float(y.max()), 128)
+    num, den, ts, tb = _ts_gpu(cb, ctx, cat, perm, y_num, 32, 2.5, [prior], borders)
+    rn, rd, rt, rb = oracle.ordered_ts(cat, perm, y_num[0], 32, 2.5, prior, borders)
+    assert np.array_equal(num[0], rn) and np.array_equal(den, rd)
+    assert np.array_equal(ts[0], rt) and np.array_equal(tb[0], rb)
+
+
+def test_ordered_ts_overflow_and_args(cb, ctx):
+    x = torch.zeros(8, dtype=torch.int64, device=gu.dev())
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_compute_ordered_ts(ctx, x, x, 8, x, 1, 0, 2**60, 1.0, [0.5], None, 0, den_out=x)
+    assert e.value.code == cb.CBH_EOVERFLOW
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_compute_ordered_ts(ctx, x, x, 8, x, 1, 0, 1, 0.0, [0.5], None, 0, den_out=x)
+    assert e.value.code == cb.CBH_EINVAL
+
+
+# --------------------------------------------------------------- histograms
+def _random_level(seed, n, F, B, K, loss, level, nbins=None):
+    g = np.random.default_rng(seed)
+    nb = nbins if nbins is not None else g.integers(2, B + 1, F).astype(np.int32)
+    nb[0] = B
+    bins = np.stack([g.integers(0, nb[f], n) for f in range(F)]).astype(np.uint8)
+    L = 1 << level
+    leaf = g.integers(0, L, n).astype(np.uint16)
+    gg = g.normal(size=(K, n)).astype(np.float32)
+    hh = g.random((K, n)).astype(np.float32)
+    if loss == 0:
+        hh[:] = 1.0
+    label = g.integers(0, max(K, 2), n).astype(np.float32)
+    return nb, bins, leaf, gg, hh, label
+
+
+def _device_problem(cb, n, F, B, K, loss, depth, nb, bins, leaf, gg, hh, label):
+    ld = (n + 15) // 16 * 16
+    bd = torch.zeros((F, ld), dtype=torch.uint8, device=gu.dev())
+    bd[:, :n] = gu.to_dev(bins)
+    cols = gu.column_table(bd)
+    nbd = gu.to_dev(nb.astype(np.int32))
+    dev = dict(bins=bd, cols=cols, nbins=nbd, label=gu.to_dev(label), g=gu.to_dev(gg),
+               h=gu.to_dev(hh), leaf=gu.to_dev(leaf),
+               approx=torch.zeros((K, n), dtype=torch.float64, device=gu.dev()),
+               gq=torch.zeros((K, n, 2), dtype=torch.int16, device=gu.dev()),
+               scale=torch.zeros((K, 2), dtype=torch.float32, device=gu.dev()))
+    p = gu.make_problem(cb, n=n, F=F, B=B, K=K, loss=loss, depth=depth, cols=cols, nbins=nbd,
+                        label=dev["label"], g=dev["g"], h=dev["h"], leaf=dev["leaf"],
+                        approx=dev["approx"], gq=dev["gq"], scale=dev["scale"])
+    return p, dev
+
+
+HIST_CASES = [
+    # n, F, B, K, loss, level
+    (10007, 7, 33, 1, 1, 0),
+    (10007, 7, 33, 1, 1, 3),
+    (4099, 5, 256, 1, 0, 0),
+    (4099, 5, 256, 1, 0, 4),
+    (3001, 3, 255, 1, 1, 7),     # 128 leaves x 255 bins: leaf tiles
+    (2003, 2, 64, 3, 2, 2),      # MultiClass, n not a multiple of 4
+    (65536 * 2 + 5, 4, 128, 1, 0, 5),
+    (17, 3, 8, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("case", HIST_CASES)
+def test_histograms_vs_oracle(cb, ctx, case, prec):
+    n, F, B, K, loss, level = case
+    nb, bins, leaf, gg, hh, label = _random_level(hash(case) % 1000, n, F, B, K, loss, level)
+    p, dev = _device_problem(cb, n, F, B, K, loss, level + 1, nb, bins, leaf, gg, hh, label)
+    L = 1 << level
+    esz = 4 if prec == 0 else 8
+    hist = torch.empty(L * F * B * 2 * K * esz, dtype=torch.uint8, device=gu.dev())
+    if prec == 2:
+        cb.cbh_quantize_gradients(ctx, p)
+    cb.cbh_build_histograms(ctx, p, level, prec, hist)
+    cb.cbh_sync(ctx)
+    got = gu.hist_to_f64(hist, L, F, B, K, prec, loss == 0)
+    if prec == 2:
+        gq = dev["gq"].cpu().numpy()
+        sc = dev["scale"].cpu().numpy()
+        rgq, rhq, rsc = oracle.grad_codes(gg, hh, loss != 0)
+        assert np.array_equal(gq[..., 0], rgq) and np.array_equal(gq[..., 1], rhq)
+        assert np.array_equal(sc, rsc)
+        want = oracle.histogram_int(bins, rgq, rhq, leaf, L, B)
+        assert np.array_equal(got, want)
+        return
+    want = oracle.histogram(bins, gg.astype(np.float64), hh.astype(np.float64), leaf, L, B)
+    mag = oracle.histogram(bins, np.abs(gg).astype(np.float64), np.abs(hh).astype(np.float64),
+                           leaf, L, B)
+    tol = gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL
+    assert gu.normalized_err(got, want, mag) <= tol
+    if loss == 0:
+        assert np.array_equal(got[..., 1::2], want[..., 1::2])   # row counts exact
+    # every feature's histogram sums to the same leaf totals
+    tot = want[:, 0, :, :].sum(axis=1)
+    for f in range(F):
+        assert np.allclose(got[:, f].sum(axis=1), tot, rtol=1e-5, atol=1e-3)
+
+
+def test_int16_histogram_deterministic(cb, ctx):
+    n, F, B, K, loss, level = 70001, 6, 128, 1, 1, 3
+    nb, bins, leaf, gg, hh, label = _random_level(3, n, F, B, K, loss, level)
+    p, dev = _device_problem(cb, n, F, B, K, loss, 4, nb, bins, leaf, gg, hh, label)
+    L = 1 << level
+    h1 = torch.empty(L * F * B * 2 * 8, dtype=torch.uint8, device=gu.dev())
+    h2 = torch.empty_like(h1)
+    cb.cbh_quantize_gradients(ctx, p)
+    cb.cbh_build_histograms(ctx, p, level, 2, h1)
+    cb.cbh_build_histograms(ctx, p, level, 2, h2)
+    cb.cbh_sync(ctx)
+    assert torch.equal(h1, h2)
+
+
+# ------------------------------------------------------------- score/argmax
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("case", [(5003, 9, 64, 1, 1, 0), (5003, 9, 64, 1, 0, 3),
+                                  (3001, 4, 255, 1, 1, 6), (2003, 3, 32, 4, 2, 2)])
+def test_score_and_argmax_vs_oracle(cb, ctx, case, prec):
+    n, F, B, K, loss, level = case
+    nb, bins, leaf, gg, hh, label = _random_level(sum(case), n, F, B, K, loss, level)
+    # a planted signal so that the best split is clear
+    gg[0] += 0.5 * (bins[F // 2] > nb[F // 2] // 2)
+    p, dev = _device_problem(cb, n, F, B, K, loss, level + 1, nb, bins, leaf, gg, hh, label)
+    L = 1 << level
+    esz = 4 if prec == 0 else 8
+    hist = torch.empty(L * F * B * 2 * K * esz, dtype=torch.uint8, device=gu.dev())
+    best = torch.zeros(4, dtype=torch.int32, device=gu.dev())
+    scores = torch.empty((F, B - 1), dtype=torch.float32, device=gu.dev())
+    if prec == 2:
+        cb.cbh_quantize_gradients(ctx, p)
+    cb.cbh_build_histograms(ctx, p, level, prec, hist)
+    cb.cbh_score_splits(ctx, p, level, hist, prec, 3.0, best, scores)
+    cb.cbh_sync(ctx)
+    got_h = gu.hist_to_f64(hist, L, F, B, K, prec, loss == 0)
+    if prec == 2:
+        sc = dev["scale"].cpu().numpy().astype(np.float64)
+        got_h = got_h.astype(np.float64)
+        got_h[..., 0::2] *= sc[:, 0]
+        if loss != 0:
+            got_h[..., 1::2] *= sc[:, 1]
+    ref = oracle.score(got_h, nb, 3.0)          # oracle scores of the GPU's own histogram
+    s = scores.cpu().numpy().astype(np.float64)
+    valid = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(s), valid)
+    scale = np.max(np.abs(ref[valid]))
+    assert np.max(np.abs(s[valid] - ref[valid])) <= 1e-5 * scale
+    f, k, s1, mg = gu.split_of(best)
+    gu.check_split((f, k), ref, nb)
+    # and against the oracle's own FP64 histogram of the true gradients
+    if prec != 2:
+        ref2 = oracle.score(oracle.histogram(bins, gg.astype(np.float64), hh.astype(np.float64),
+                                             leaf, L, B), nb, 3.0)
+        gu.check_split((f, k), ref2, nb)
+
+
+def test_score_no_candidate(cb, ctx):
+    n, F, B, K = 100, 2, 4, 1
+    nb = np.array([1, 1], np.int32)
+    bins = np.zeros((F, n), np.uint8)
+    g = np.random.default_rng(0)
+    p, dev = _device_problem(cb, n, F, B, K, 1, 2, nb, bins, np.zeros(n, np.uint16),
+                             g.normal(size=(1, n)).astype(np.float32),
+                             g.random((1, n)).astype(np.float32), np.zeros(n, np.float32))
+    hist = torch.empty(F * B * 2 * 4, dtype=torch.uint8, device=gu.dev())
+    best = torch.zeros(4, dtype=torch.int32, device=gu.dev())
+    cb.cbh_build_histograms(ctx, p, 0, 0, hist)
+    cb.cbh_score_splits(ctx, p, 0, hist, 0, 1.0, best)
+    cb.cbh_apply_split(ctx, p, 0, best)
+    cb.cbh_sync(ctx)
+    assert gu.split_of(best)[:2] == (-1, -1)
+    assert int(dev["leaf"].max().item()) == 0
+
+
+# ---------------------------------------------------------------- apply/update
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 4096, 100001])
+def test_apply_split_bit_exact(cb, ctx, n):
+    g = np.random.default_rng(n)
+    F, B = 3, 64
+    nb = np.full(F, B, np.int32)
+    bins = g.integers(0, B, (F, n)).astype(np.uint8)
+    leaf0 = g.integers(0, 8, n).astype(np.uint16)
+    p, dev = _device_problem(cb, n, F, B, 1, 0, 5, nb, bins, leaf0, np.zeros((1, n), np.float32),
+                             np.ones((1, n), np.float32), np.zeros(n, np.float32))
+    best = torch.tensor([[2, 20, 0, 0], [1, 5, 0, 0]], dtype=torch.int32, device=gu.dev())
+    cb.cbh_apply_split(ctx, p, 3, best[0])
+    cb.cbh_sync(ctx)
+    want = leaf0.copy()
+    oracle.apply_split(bins[2], 20, 3, want)
+    assert np.array_equal(dev["leaf"].cpu().numpy(), want)
+    # level 0 overwrites whatever the leaf array held
+    cb.cbh_apply_split(ctx, p, 0, best[1])
+    cb.cbh_sync(ctx)
+    assert np.array_equal(dev["leaf"].cpu().numpy(), (bins[1] > 5).astype(np.uint16))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("loss,K", [(0, 1), (1, 1), (2, 3)])
+def test_update_approx_vs_oracle(cb, ctx, loss, K, prec):
+    n, F, B, depth = 20011, 4, 32, 3
+    g = np.random.default_rng(loss * 10 + K + prec)
+    nb = np.full(F, B, np.int32)
+    bins = g.integers(0, B, (F, n)).astype(np.uint8)
+    label = (g.normal(size=n) if loss == 0 else g.integers(0, max(2, K), n)).astype(np.float32)
+    p, dev = _device_problem(cb, n, F, B, K, loss, depth, nb, bins, np.zeros(n, np.uint16),
+                             np.zeros((K, n), np.float32), np.ones((K, n), np.float32), label)
+    dev["approx"].copy_(gu.to_dev(g.normal(0, 0.5, (K, n))))
+    a0 = dev["approx"].cpu().numpy()
+    cb.cbh_update_approx(ctx, p, None, prec, None, 0.0, 0.0)     # gradients at a0
+    cb.cbh_sync(ctx)
+    rg, rh = oracle.gradients(loss, K, a0, label)
+    np.testing.assert_array_equal(dev["g"].cpu().numpy(), rg.astype(np.float32))
+    if loss != 0:
+        np.testing.assert_array_equal(dev["h"].cpu().numpy(), rh.astype(np.float32))
+    # one tree, then the leaf solve and model update
+    esz = 4 if prec == 0 else 8
+    hist = torch.empty((1 << (depth - 1)) * F * B * 2 * K * esz, dtype=torch.uint8, device=gu.dev())
+    best = torch.zeros((depth, 4), dtype=torch.int32, device=gu.dev())
+    vals = torch.zeros((1 << depth, K), dtype=torch.float64, device=gu.dev())
+    cnts = torch.zeros(1 << depth, dtype=torch.int64, device=gu.dev())
+    if prec == 2:
+        cb.cbh_quantize_gradients(ctx, p)
+    for lvl in range(depth):
+        cb.cbh_build_histograms(ctx, p, lvl, prec, hist)
+        cb.cbh_score_splits(ctx, p, lvl, hist, prec, 3.0, best.data_ptr() + 16 * lvl)
+        cb.cbh_apply_split(ctx, p, lvl, best.data_ptr() + 16 * lvl)
+    g32 = dev["g"].cpu().numpy().astype(np.float64)
+    h32 = dev["h"].cpu().numpy().astype(np.float64) if loss != 0 else np.ones((K, n))
+    cb.cbh_update_approx(ctx, p, hist, prec, best.data_ptr() + 16 * (depth - 1), 0.1, 3.0,
+                         vals, cnts)
+    cb.cbh_sync(ctx)
+    leaf = dev["leaf"].cpu().numpy()
+    splits = best.cpu().numpy()[:, :2]
+    want_leaf = np.zeros(n, np.uint16)
+    for lvl, (f, k) in enumerate(splits):
+        oracle.apply_split(bins[f], k, lvl, want_leaf)
+    assert np.array_equal(leaf, want_leaf)
+    if prec == 2:   # the integer path solves from dequantised codes
+        gq = dev["gq"].cpu().numpy()
+        sc = dev["scale"].cpu().numpy().astype(np.float64)
+        g32 = gq[..., 0].astype(np.float64) * sc[:, 0:1]
+        if loss != 0:
+            h32 = gq[..., 1].astype(np.float64) * sc[:, 1:2]
+    rv, rG, rH, rc = oracle.leaf_values(leaf, g32, h32, 1 << depth, 3.0)
+    assert np.array_equal(cnts.cpu().numpy(), rc)
+    magG, _ = oracle.leaf_values(leaf, np.abs(g32), h32, 1 << depth, 3.0)[1:3]
+    gv = vals.cpu().numpy()
+    err = np.abs(gv - rv) * (rH + 3.0) / np.maximum(magG, 1e-300)
+    assert np.max(err[magG > 0]) <= (gu.FP32_TOL if prec == 0 else 1e-9)
+    a1 = a0.copy()
+    oracle.update_approx(a1, leaf, gv, 0.1)
+    np.testing.assert_array_equal(dev["approx"].cpu().numpy(), a1)
+    rg, rh = oracle.gradients(loss, K, a1, label)
+    np.testing.assert_array_equal(dev["g"].cpu().numpy(), rg.astype(np.float32))
+
+
+def test_update_rejects_bad_args(cb, ctx):
+    n = 64
+    p, dev = _device_problem(cb, n, 1, 4, 1, 0, 2, np.array([4], np.int32),
+                             np.zeros((1, n), np.uint8), np.zeros(n, np.uint16),
+                             np.zeros((1, n), np.float32), np.ones((1, n), np.float32),
+                             np.zeros(n, np.float32))
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_update_approx(ctx, p, dev["g"], 0, None, 0.1, 1.0, None)
+    assert e.value.code == cb.CBH_EINVAL
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 2, 0, dev["g"])
+    assert e.value.code == cb.CBH_EINVAL
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 0, 7, dev["g"])
+    assert e.value.code == cb.CBH_EINVAL
+    p.K = 17
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 0, 0, dev["g"])
+    assert e.value.code == cb.CBH_EINVAL
+    p.K, p.loss = 17, 2
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 0, 0, dev["g"])
+    assert e.value.code == cb.CBH_EUNSUPPORTED
+    p.K, p.loss, p.max_bins = 1, 0, 300
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 0, 0, dev["g"])
+    assert e.value.code == cb.CBH_EUNSUPPORTED
+    p.max_bins, p.gq = 4, None
+    with pytest.raises(cb.CbhError) as e:
+        cb.cbh_build_histograms(ctx, p, 0, 2, dev["g"])
+    assert e.value.code == cb.CBH_EINVAL
+
+
+def test_workspace_limit(cb):
+    c = cb.cbh_create(0)
+    try:
+        n = 100000
+        g = np.random.default_rng(1)
+        p, dev = _device_problem(cb, n, 8, 128, 1, 0, 4, np.full(8, 128, np.int32),
+                                 g.integers(0, 128, (8, n)).astype(np.uint8),
+                                 np.zeros(n, np.uint16), np.zeros((1, n), np.float32),
+                                 np.ones((1, n), np.float32), np.zeros(n, np.float32))
+        cb.cbh_set_workspace_limit(c, 1 << 16)
+        hist = torch.empty(8 * 128 * 2 * 4 * 8, dtype=torch.uint8, device=gu.dev())
+        with pytest.raises(cb.CbhError) as e:
+            cb.cbh_build_histograms(c, p, 3, 0, hist)
+        assert e.value.code == cb.CBH_ENOMEM
+        cb.cbh_set_workspace_limit(c, 1 << 34)
+        cb.cbh_build_histograms(c, p, 3, 0, hist)
+        cb.cbh_sync(c)
+    finally:
+        torch.cuda.synchronize()
+        cb.cbh_destroy(c)

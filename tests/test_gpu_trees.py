@@ -1,0 +1,340 @@
+"""Whole trees in lock-step with the oracle, batched and graph-replayed forms,
+and the full-size 1M-row workload checked on sampled outputs.
+
+Lock-step: after every level the oracle rebuilds the histogram from the GPU's
+own float32 gradients and leaf array (widened exactly to float64), scores it,
+and the GPU split must match wherever the oracle's margin is clear; at the end
+of a tree the leaf values, counts, model values and new gradients are
+compared. The next level then continues from the GPU's own state, so a
+near-tie cannot make the two runs drift apart.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_11363_amd import cbhip
+    return cbhip
+
+
+def _booster(cb, p, prec):
+    from paper_1810_11363_amd.booster import GpuBooster
+    return GpuBooster.from_problem(p, precision=prec).prepare()
+
+
+def _check_prep(bst, p):
+    """Bins and statistic bins equal the oracle's, bit for bit."""
+    from oracle import boost
+    prep = boost.prepare(p)
+    for r in range(bst.s):
+        bins, nb = prep.tree_features(r)
+        assert np.array_equal(bst.bins_host(r), bins)
+        assert np.array_equal(bst.nbins_table[r].cpu().numpy(), nb)
+    return prep
+
+
+def _lockstep_tree(cb, bst, t, stats):
+    import torch
+    pr = bst.probs[t % bst.s]
+    ctx, prec, L2 = bst.ctx, bst.precision, bst.l2
+    bins = bst.bins_host(t % bst.s)
+    nb = bst.nbins_table[t % bst.s].cpu().numpy()
+    K, n, B = bst.K, bst.n, bst.B
+    if prec == 2:
+        cb.cbh_quantize_gradients(ctx, pr)
+    torch.cuda.synchronize()
+    g32 = bst.g.cpu().numpy().astype(np.float64)
+    h32 = bst.h.cpu().numpy().astype(np.float64) if bst.loss != 0 else np.ones((K, n))
+    if prec == 2:
+        gq = bst.gq.cpu().numpy()
+        sc = bst.grad_scale.cpu().numpy().astype(np.float64)
+        gd = gq[..., 0].astype(np.float64) * sc[:, 0:1]
+        hd = gq[..., 1].astype(np.float64) * sc[:, 1:2] if bst.loss != 0 else h32
+    else:
+        gd, hd = g32, h32
+    hist = bst.hist.data_ptr()
+    for lvl in range(bst.depth):
+        L = 1 << lvl
+        cb.cbh_build_histograms(ctx, pr, lvl, prec, hist)
+        cb.cbh_score_splits(ctx, pr, lvl, hist, prec, L2, bst.split_ptr(lvl))
+        cb.cbh_sync(ctx)
+        leaf = bst.leaf.cpu().numpy()
+        if lvl == 0:
+            leaf[:] = 0
+        got = gu.hist_to_f64(bst.hist, L, bst.F, B, K, prec, bst.loss == 0)
+        if prec == 2:
+            got_deq = got.astype(np.float64).copy()
+            got_deq[..., 0::2] *= sc[:, 0]
+            if bst.loss != 0:
+                got_deq[..., 1::2] *= sc[:, 1]
+            rgq, rhq, _ = oracle.grad_codes(bst.g.cpu().numpy(), bst.h.cpu().numpy()
+                                            if bst.loss != 0 else None, bst.loss != 0)
+            want = oracle.histogram_int(bins, rgq, rhq, leaf, L, B)
+            assert np.array_equal(got, want)
+            got = got_deq
+        else:
+            want = oracle.histogram(bins, gd, hd, leaf, L, B)
+            mag = oracle.histogram(bins, np.abs(gd), np.abs(hd), leaf, L, B)
+            e = gu.normalized_err(got, want, mag)
+            stats["hist_err"] = max(stats.get("hist_err", 0.0), e)
+            assert e <= (gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL)
+        ref = oracle.score(got, nb, L2)
+        f, k, _, _ = gu.split_of(bst.best, lvl)
+        clear = gu.check_split((f, k), ref, nb)
+        stats["ties"] = stats.get("ties", 0) + (not clear)
+        cb.cbh_apply_split(ctx, pr, lvl, bst.split_ptr(lvl))
+        cb.cbh_sync(ctx)
+        want_leaf = leaf.copy()
+        if f >= 0:
+            oracle.apply_split(bins[f], k, lvl, want_leaf)
+        assert np.array_equal(bst.leaf.cpu().numpy(), want_leaf)
+    a0 = bst.approx.cpu().numpy()
+    cb.cbh_update_approx(ctx, pr, hist, prec, bst.split_ptr(bst.depth - 1), bst.lr, L2,
+                         bst.leaf_values, bst.leaf_counts)
+    cb.cbh_sync(ctx)
+    leaf = bst.leaf.cpu().numpy()
+    rv, rG, rH, rc = oracle.leaf_values(leaf, gd, hd, 1 << bst.depth, L2)
+    assert np.array_equal(bst.leaf_counts.cpu().numpy(), rc)
+    gv = bst.leaf_values.cpu().numpy()
+    magG = oracle.leaf_values(leaf, np.abs(gd), hd, 1 << bst.depth, L2)[1]
+    m = magG > 0
+    err = np.abs(gv - rv)[m] * (rH + L2)[m] / magG[m]
+    stats["leaf_err"] = max(stats.get("leaf_err", 0.0), float(err.max()) if err.size else 0.0)
+    assert stats["leaf_err"] <= (gu.FP32_TOL if prec == 0 else 1e-9)
+    a1 = a0.copy()
+    oracle.update_approx(a1, leaf, gv, bst.lr)
+    np.testing.assert_array_equal(bst.approx.cpu().numpy(), a1)
+    rg, rh = oracle.gradients(bst.loss, K, a1, bst.label_h)
+    gg = bst.g.cpu().numpy()
+    assert np.max(np.abs(gg - rg.astype(np.float32))) <= 1e-6 * max(1.0, np.abs(rg).max())
+
+
+CASES = {
+    "c1_small": lambda: datagen.make_c1(),
+    "c2_shape": lambda: _shrink(datagen.make_c2(n=30011, s=2), iters=3),
+    "c3_shape": lambda: _shrink(datagen.make_c3(n=20003, F=24), iters=2),
+    "c5_shape": lambda: _shrink(datagen.make_c5(n=12007, n_cat=3, K=4), iters=2, depth=7),
+}
+
+
+def _shrink(p, iters, depth=None):
+    p.iterations = iters
+    if depth:
+        p.depth = depth
+    return p
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", list(CASES))
+def test_lockstep_trees(cb, name, prec):
+    p = CASES[name]()
+    bst = _booster(cb, p, prec)
+    _check_prep(bst, p)
+    bst.init_gradients()
+    rg, _ = oracle.gradients(p.loss, p.K, np.zeros((p.K, p.n)), p.label)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bst.g.cpu().numpy(), rg.astype(np.float32))
+    stats = {}
+    for t in range(p.iterations):
+        _lockstep_tree(cb, bst, t, stats)
+    print(name, prec, stats)
+    bst.close()
+
+
+def test_independent_run_matches_oracle_c1(cb):
+    """Free-running GPU boosting on the small workload against the oracle's own
+    free-running FP64 boosting: the same trees wherever splits are clear."""
+    from oracle import boost
+    p = datagen.make_c1()
+    bst = _booster(cb, p, 0)
+    trees = bst.fit(p.iterations)
+    otrees, oapprox, _ = boost.fit(p)
+    for t, (gt, ot) in enumerate(zip(trees, otrees)):
+        for lvl in range(p.depth):
+            f, k, s1, s2 = ot.splits[lvl]
+            if s1 - s2 > gu.MARGIN_TOL * abs(s1):
+                assert tuple(gt.splits[lvl]) == (f, k), (t, lvl)
+            else:
+                pytest.skip(f"near-tie at tree {t} level {lvl}; lock-step test covers it")
+    np.testing.assert_allclose(bst.approx.cpu().numpy(), oapprox, rtol=1e-5, atol=1e-6)
+    bst.close()
+
+
+# ------------------------------------------------------------ batched/graph
+def _batch_setup(cb, probs, prec):
+    from paper_1810_11363_amd.booster import GpuBooster
+    bsts = [GpuBooster.from_problem(p, precision=prec).prepare() for p in probs]
+    return bsts
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batched_matches_single(cb, prec):
+    probs = datagen.make_c4(P=5, scale=0.01)
+    for p in probs:
+        p.depth = 5
+    single = _batch_setup(cb, probs, prec)
+    batched = _batch_setup(cb, probs, prec)
+    ctx = batched[0].ctx
+    P = len(probs)
+    depth = probs[0].depth
+    best = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    plan = cb.cbh_batch_create(ctx, [b.probs[0] for b in batched], prec,
+                               [b.hist for b in batched], best)
+    try:
+        for b in single:
+            b.init_gradients()
+        cb.cbh_batch_update(ctx, plan, 0.1, 3.0, [b.leaf_values for b in batched], True)
+        for it in range(3):
+            for b in single:
+                b.fit_tree(0)
+            if prec == 2:
+                for b in batched:
+                    cb.cbh_quantize_gradients(ctx, b.probs[0])
+            for lvl in range(depth):
+                cb.cbh_batch_level(ctx, plan, lvl, 3.0)
+            cb.cbh_batch_update(ctx, plan, 0.1, 3.0, [b.leaf_values for b in batched], False)
+            torch.cuda.synchronize()
+            for i, (s, b) in enumerate(zip(single, batched)):
+                sb = s.best.cpu().numpy()[:, :2]
+                bb = best[i].cpu().numpy()[:, :2]
+                if prec == 2:
+                    assert np.array_equal(sb, bb), (it, i)
+                    assert torch.equal(s.leaf, b.leaf)
+                    assert torch.equal(s.approx, b.approx)
+                else:
+                    # float32 sums differ in order between the two launch plans:
+                    # splits must agree wherever the single run's margin is clear
+                    sc = s.best.cpu().numpy()[:, 2:].view(np.float32)
+                    for lvl in range(depth):
+                        if sc[lvl, 1] > gu.MARGIN_TOL * abs(sc[lvl, 0]):
+                            assert np.array_equal(sb[lvl], bb[lvl]), (it, i, lvl)
+                        else:
+                            return
+                    torch.testing.assert_close(s.approx, b.approx, rtol=1e-5, atol=1e-6)
+    finally:
+        cb.cbh_batch_destroy(plan)
+        for b in single + batched:
+            b.close()
+
+
+def test_graph_replay_matches_eager(cb):
+    probs = datagen.make_c4(P=3, scale=0.005)
+    for p in probs:
+        p.depth = 4
+    eager = _batch_setup(cb, probs, 2)
+    graph = _batch_setup(cb, probs, 2)
+    ctx = graph[0].ctx
+    P, depth = len(probs), probs[0].depth
+    best_e = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    best_g = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    plan_e = cb.cbh_batch_create(eager[0].ctx, [b.probs[0] for b in eager], 2,
+                                 [b.hist for b in eager], best_e)
+    plan_g = cb.cbh_batch_create(ctx, [b.probs[0] for b in graph], 2, [b.hist for b in graph],
+                                 best_g)
+    stream = torch.cuda.Stream()
+    try:
+        cb.cbh_batch_update(eager[0].ctx, plan_e, 0.1, 3.0, [b.leaf_values for b in eager], True)
+        cb.cbh_batch_update(ctx, plan_g, 0.1, 3.0, [b.leaf_values for b in graph], True)
+        torch.cuda.synchronize()
+        gr = cb.cbh_graph_capture_iteration(ctx, plan_g, 0.1, 3.0, [b.leaf_values for b in graph],
+                                            stream.cuda_stream)
+        for it in range(4):
+            for b in eager:
+                cb.cbh_quantize_gradients(eager[0].ctx, b.probs[0])
+            for lvl in range(depth):
+                cb.cbh_batch_level(eager[0].ctx, plan_e, lvl, 3.0)
+            cb.cbh_batch_update(eager[0].ctx, plan_e, 0.1, 3.0, [b.leaf_values for b in eager],
+                                False)
+            cb.cbh_graph_launch(gr, stream.cuda_stream)
+            stream.synchronize()
+            torch.cuda.synchronize()
+            assert torch.equal(best_e, best_g), it
+            for e, g in zip(eager, graph):
+                assert torch.equal(e.approx, g.approx), it
+        cb.cbh_graph_destroy(gr)
+    finally:
+        cb.cbh_batch_destroy(plan_e)
+        cb.cbh_batch_destroy(plan_g)
+        for b in eager + graph:
+            b.close()
+
+
+def test_autotune_roundtrip(cb, tmp_path):
+    p = datagen.make_c3(n=40000, F=16)
+    p.depth = 4
+    bst = _booster(cb, p, 0)
+    bst.init_gradients()
+    path = str(tmp_path / "tune.json")
+    cb.cbh_autotune(bst.ctx, bst.probs[0], 0, path)
+    assert open(path).read().count("lds_budget") == p.depth
+    c2 = cb.cbh_create(0)
+    cb.cbh_autotune_load(c2, path)
+    cb.cbh_destroy(c2)
+    # the tuned plans still give oracle-equal histograms
+    stats = {}
+    _lockstep_tree(cb, bst, 0, stats)
+    bst.close()
+
+
+# ----------------------------------------------------- full-size 1M workload
+@pytest.mark.timeout(900)
+def test_full_size_c2_sampled(cb):
+    """The 1M-row RMSE workload in the launch configuration the benchmark
+    times: bins and statistic bins exact for every column, and for one tree
+    every level's histogram checked on sampled features, counts exact,
+    splits under the margin rule and leaf values in tolerance."""
+    from oracle import boost
+    p = datagen.make_c2()
+    bst = _booster(cb, p, 0)
+    prep = boost.prepare(p)
+    for r in range(bst.s):
+        bins, nb = prep.tree_features(r)
+        assert np.array_equal(bst.bins_host(r), bins)
+    bst.init_gradients()
+    bst.fit_tree(0)      # warm tree, then check tree 1 level by level on sampled features
+    torch.cuda.synchronize()
+    t = 1
+    pr = bst.probs[t % bst.s]
+    bins, nb = prep.tree_features(t)
+    g = bst.g.cpu().numpy().astype(np.float64)
+    h = np.ones_like(g)
+    rng = np.random.default_rng(0)
+    hist = bst.hist.data_ptr()
+    for lvl in range(bst.depth):
+        L = 1 << lvl
+        cb.cbh_build_histograms(bst.ctx, pr, lvl, 0, hist)
+        cb.cbh_score_splits(bst.ctx, pr, lvl, hist, 0, bst.l2, bst.split_ptr(lvl))
+        cb.cbh_sync(bst.ctx)
+        leaf = bst.leaf.cpu().numpy() if lvl else np.zeros(bst.n, np.uint16)
+        got = gu.hist_to_f64(bst.hist, L, bst.F, bst.B, 1, 0, True)
+        fs = np.sort(rng.choice(bst.F, 6, replace=False))
+        want = oracle.histogram(bins[fs], g, h, leaf, L, bst.B)
+        mag = oracle.histogram(bins[fs], np.abs(g), h, leaf, L, bst.B)
+        assert gu.normalized_err(got[:, fs], want, mag) <= gu.FP32_TOL
+        assert np.array_equal(got[:, fs, :, 1], want[..., 1])
+        # totals of every feature equal the leaf totals (checks unsampled features)
+        counts = got[..., 1].sum(axis=2)
+        assert np.all(counts == counts[:, :1])
+        assert counts[:, 0].sum() == bst.n
+        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl))
+    cb.cbh_update_approx(bst.ctx, pr, hist, 0, bst.split_ptr(bst.depth - 1), bst.lr, bst.l2,
+                         bst.leaf_values, bst.leaf_counts)
+    cb.cbh_sync(bst.ctx)
+    leaf = bst.leaf.cpu().numpy()
+    rv, rG, rH, rc = oracle.leaf_values(leaf, g, h, 1 << bst.depth, bst.l2)
+    assert np.array_equal(bst.leaf_counts.cpu().numpy(), rc)
+    magG = oracle.leaf_values(leaf, np.abs(g), h, 1 << bst.depth, bst.l2)[1]
+    gv = bst.leaf_values.cpu().numpy()
+    m = magG > 0
+    assert np.max(np.abs(gv - rv)[m] * (rH + bst.l2)[m] / magG[m]) <= gu.FP32_TOL
+    bst.close()
