@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=list(PRECISIONS), default="fp32")
+    ap.add_argument("--subtract", choices=["auto", "on", "off"], default="auto",
+                    help="histogram subtraction at levels >= 1 (auto: on except fp32)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-rows", type=int, default=100_000)
     ap.add_argument("--cpu-trees", type=int, default=2)
@@ -101,7 +103,8 @@ def main():
     p = datagen.make_c2(n=args.n)
     t_gen = time.perf_counter() - t_gen
     print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
-    bst = GpuBooster.from_problem(p, precision=prec).prepare()
+    sub = None if args.subtract == "auto" else args.subtract == "on"
+    bst = GpuBooster.from_problem(p, precision=prec, subtract=sub).prepare()
     if args.autotune:
         cb.cbh_autotune_load(bst.ctx, args.autotune)
     print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
@@ -117,24 +120,11 @@ def main():
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(depth)] for _ in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    hist = bst.hist.data_ptr()
     torch.cuda.synchronize()
     start.record(stream)
     t_wall = time.perf_counter()
     for s in range(args.steps):
-        t = args.warmup + s
-        pr = bst.probs[t % bst.s]
-        if prec == 2:
-            cb.cbh_quantize_gradients(bst.ctx, pr, stream)
-        for lvl in range(depth):
-            ev[s][lvl][0].record(stream)
-            cb.cbh_build_histograms(bst.ctx, pr, lvl, prec, hist, stream)
-            ev[s][lvl][1].record(stream)
-            cb.cbh_score_splits(bst.ctx, pr, lvl, hist, prec, bst.l2, bst.split_ptr(lvl), None,
-                                stream)
-            cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), stream)
-        cb.cbh_update_approx(bst.ctx, pr, hist, prec, bst.split_ptr(depth - 1), bst.lr, bst.l2,
-                             bst.leaf_values, None, stream)
+        bst.fit_tree(args.warmup + s, events=ev[s])
     stop.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall

@@ -241,6 +241,24 @@ int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream);
 int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
                          int32_t precision, void* hist_out, void* stream);
 
+/* Histograms of level `level` >= 1 by subtraction: for every parent leaf p of
+ * the previous level, only the rows of its smaller child (judged from the
+ * parent histogram at the parent's split: row counts for RMSE, sums of h
+ * otherwise) are accumulated; the sibling is the parent's histogram minus that
+ * child. The output equals cbh_build_histograms exactly for CBH_PREC_INT16 and
+ * RMSE counts; for CBH_PREC_TWOFLOAT the difference is taken in two-float
+ * arithmetic (error about 2^-44 of the parent's sums); for CBH_PREC_FP32 it is
+ * a float difference, so a bin whose mass sits mostly in the smaller child can
+ * carry the parent's float rounding error (use it when that is acceptable).
+ * Histogram subtraction is not described in the paper.
+ *   parent_hist   level-1 output of either build call, same precision; must
+ *                 not be hist_out
+ *   parent_split  the split chosen at level-1 (device cbh_split)
+ *   hist_out      as cbh_build_histograms for `level` */
+int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                             int32_t precision, const void* parent_hist,
+                             const cbh_split* parent_split, void* hist_out, void* stream);
+
 /* Score every candidate split of the level and keep the best (Sec. 3, first
  * phase). The paper gives no formula; the score is the gain of the
  * L2-regularised second-order objective: splitting every current leaf L by
@@ -294,7 +312,7 @@ typedef struct cbh_batch cbh_batch;
  * example several permutations, folds or separate datasets). The problem
  * descriptors and the histogram buffers are copied to device memory once; the
  * device buffers they point to must stay valid while the plan exists.
- *   probs     host array [P]; every problem must have the same depth
+ *   probs     host array [P]; every problem must have the same depth and loss
  *   hist      host array [P] of device pointers; hist[p] must hold the level
  *             depth-1 histograms of problem p (size as cbh_build_histograms)
  *   best      device cbh_split [P][depth]: split of every problem and level

@@ -47,7 +47,7 @@ class GpuBooster:
 
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
-                 device="cuda:0", ctx=None, stream=None):
+                 subtract=None, device="cuda:0", ctx=None, stream=None):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.own_ctx = ctx is None
@@ -56,6 +56,9 @@ class GpuBooster:
         self.lr, self.l2 = float(lr), float(l2)
         self.num_bins, self.ts_bins, self.a = int(num_bins), int(ts_bins), float(a)
         self.precision = int(precision)
+        # histogram subtraction at levels >= 1: exact for int16, two-float
+        # difference for the compensated form; off for plain float32 by default
+        self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
         self.x_num = np.ascontiguousarray(x_num, dtype=np.float32)
         self.cat = np.ascontiguousarray(cat, dtype=np.int32)
         self.label_h = np.ascontiguousarray(label, dtype=np.float32)
@@ -162,8 +165,9 @@ class GpuBooster:
                                                        np.int32)]))
         self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
-        self.hist = torch.empty(max(256, self._hist_bytes(self.depth - 1)), dtype=torch.uint8,
-                                device=d)
+        hb = max(256, self._hist_bytes(self.depth - 1))
+        self.hists = [torch.empty(hb, dtype=torch.uint8, device=d) for _ in range(2)]
+        self.hist = self.hists[(self.depth - 1) % 2]     # the last level's histogram
         self.probs = [self.problem(r) for r in range(self.s)]
         return self
 
@@ -202,19 +206,38 @@ class GpuBooster:
         cb.cbh_update_approx(self.ctx, self.probs[0], None, self.precision, None, 0.0, 0.0,
                              stream=self.stream)
 
-    def fit_tree(self, t: int, counts: bool = False):
-        """One tree (all levels, leaf solve, approx and gradient update)."""
+    def hist_ptr(self, level: int) -> int:
+        """Level `level` writes buffer level % 2 (its parent is the other one)."""
+        return self.hists[level % 2].data_ptr()
+
+    def build_level_histograms(self, pr, level: int):
+        ctx, st, prec = self.ctx, self.stream, self.precision
+        if level > 0 and self.subtract:
+            cb.cbh_build_histograms_sub(ctx, pr, level, prec, self.hist_ptr(level - 1),
+                                        self.split_ptr(level - 1), self.hist_ptr(level), st)
+        else:
+            cb.cbh_build_histograms(ctx, pr, level, prec, self.hist_ptr(level), st)
+
+    def fit_tree(self, t: int, counts: bool = False, events=None):
+        """One tree (all levels, leaf solve, approx and gradient update).
+        `events`: optional list of (start, end) CUDA events per level recorded
+        around each histogram build."""
         pr = self.probs[t % self.s]
         ctx, st, prec = self.ctx, self.stream, self.precision
         if prec == cb.CBH_PREC_INT16:
             cb.cbh_quantize_gradients(ctx, pr, st)
-        hist = self.hist.data_ptr()
         for lvl in range(self.depth):
-            cb.cbh_build_histograms(ctx, pr, lvl, prec, hist, st)
-            cb.cbh_score_splits(ctx, pr, lvl, hist, prec, self.l2, self.split_ptr(lvl), None, st)
+            if events is not None:
+                events[lvl][0].record(st)
+            self.build_level_histograms(pr, lvl)
+            if events is not None:
+                events[lvl][1].record(st)
+            cb.cbh_score_splits(ctx, pr, lvl, self.hist_ptr(lvl), prec, self.l2,
+                                self.split_ptr(lvl), None, st)
             cb.cbh_apply_split(ctx, pr, lvl, self.split_ptr(lvl), st)
-        cb.cbh_update_approx(ctx, pr, hist, prec, self.split_ptr(self.depth - 1), self.lr,
-                             self.l2, self.leaf_values, self.leaf_counts if counts else None, st)
+        cb.cbh_update_approx(ctx, pr, self.hist_ptr(self.depth - 1), prec,
+                             self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
+                             self.leaf_counts if counts else None, st)
 
     def tree_record(self) -> TreeRecord:
         b = self.best.cpu().numpy()

@@ -2,9 +2,10 @@
 //
 // For every level of a problem it times the histogram build (main launch plus
 // the partial merge) for each distinct launch plan reachable from a grid of
-// knobs — LDS bytes per block (which sets features per block and leaves per
-// LDS tile) and the number of blocks aimed at (which sets rows per block) —
-// and keeps the fastest. Results are keyed by (F, B, K, level, precision,
+// knobs — LDS bytes per block (which bounds features per block and sets
+// leaves per LDS tile), the number of blocks aimed at, the least rows per
+// block and the cap on partial-tile volume (which set rows per block) — and
+// keeps the fastest. Results are keyed by (F, B, K, level, precision,
 // floor(log2 n)) and can be saved to and loaded from a small JSON file.
 #include <algorithm>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "common.h"
+#include "kernels_dev.h"
 
 namespace cbh {
 
@@ -37,10 +39,10 @@ static int save_table(const cbh_ctx* ctx, const char* path) {
         fprintf(f,
                 "  {\"F\": %d, \"B\": %d, \"K\": %d, \"level\": %d, \"precision\": %d, "
                 "\"log2n\": %d, \"lds_budget\": %d, \"max_fb\": %d, \"target_blocks\": %d, "
-                "\"min_rows\": %lld}%s\n",
+                "\"min_rows\": %lld, \"partial_pct\": %d}%s\n",
                 std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
                 std::get<5>(k), v.lds_budget, v.max_fb, v.target_blocks, (long long)v.min_rows,
-                ++i < ctx->tuned.size() ? "," : "");
+                v.partial_pct, ++i < ctx->tuned.size() ? "," : "");
     }
     fprintf(f, "]\n");
     fclose(f);
@@ -69,19 +71,21 @@ int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path) {
         const size_t end = text.find('}', pos);
         CBH_ARG(end != std::string::npos, "malformed autotune file");
         const std::string obj = text.substr(pos, end - pos + 1);
-        long long F, B, K, lvl, prec, l2n, lds, fb, tb, mr;
+        long long F, B, K, lvl, prec, l2n, lds, fb, tb, mr, pp;
         CBH_ARG(parse_field(obj, "F", &F) && parse_field(obj, "B", &B) &&
                     parse_field(obj, "K", &K) && parse_field(obj, "level", &lvl) &&
                     parse_field(obj, "precision", &prec) && parse_field(obj, "log2n", &l2n) &&
                     parse_field(obj, "lds_budget", &lds) && parse_field(obj, "max_fb", &fb) &&
-                    parse_field(obj, "target_blocks", &tb) && parse_field(obj, "min_rows", &mr),
+                    parse_field(obj, "target_blocks", &tb) && parse_field(obj, "min_rows", &mr) &&
+                    parse_field(obj, "partial_pct", &pp),
                 "malformed autotune entry");
-        CBH_ARG(lds > 0 && fb > 0 && tb > 0 && mr > 0, "bad autotune values");
+        CBH_ARG(lds > 0 && fb > 0 && tb > 0 && mr > 0 && pp > 0, "bad autotune values");
         HistKnobs kn;
         kn.lds_budget = (int32_t)lds;
         kn.max_fb = (int32_t)fb;
         kn.target_blocks = (int32_t)tb;
         kn.min_rows = mr;
+        kn.partial_pct = (int32_t)pp;
         ctx->tuned[TuneKey{(int32_t)F, (int32_t)B, (int32_t)K, (int32_t)lvl, (int32_t)prec,
                            (int32_t)l2n}] = kn;
         ++loaded;
@@ -103,10 +107,11 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const
     std::vector<int32_t> budgets;
     for (int32_t v : {16 * 1024, 32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, 160 * 1024})
         if (v <= ctx->max_lds) budgets.push_back(v);
-    const int32_t fbs[] = {2, 4, 8, 16, 32};
-    const int32_t targets[] = {256, 512, 1024, 2048, 4096};
-    const int64_t cell_bytes = int64_t(B) * words_per_cell(precision, K) * 4;
-    CBH_REQUIRE(cell_bytes <= ctx->max_lds, CBH_EUNSUPPORTED, "leaf row does not fit in LDS");
+    const int32_t targets[] = {256, 512, 1024};
+    const int64_t min_rows[] = {16384, 32768, 65536};
+    const int32_t pcts[] = {12, 25, 50};
+    CBH_REQUIRE(tile_lds_bytes(precision, prob->loss == CBH_LOSS_RMSE, K, B, 1) <= ctx->max_lds,
+                CBH_EUNSUPPORTED, "leaf row does not fit in LDS");
     const int64_t hist_bytes =
         hist_elems(1 << (prob->depth - 1), F, B, K) * hist_elem_bytes(precision);
     void* hist = nullptr;
@@ -122,16 +127,17 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const
         float best_ms = 1e30f;
         HistKnobs best_kn = ctx->knobs;
         for (size_t ib = 0; ib < budgets.size() && rc == CBH_OK; ++ib)
-            for (int32_t fb : fbs)
-                for (int32_t tb : targets) {
+            for (int32_t tb : targets)
+                for (int64_t mr : min_rows)
+                for (int32_t pp : pcts) {
                     if (rc != CBH_OK) break;
-                    const int32_t bud = budgets[ib];
                     HistKnobs kn = ctx->knobs;
-                    kn.lds_budget = bud;
-                    kn.max_fb = fb;
+                    kn.lds_budget = budgets[ib];
                     kn.target_blocks = tb;
+                    kn.min_rows = mr;
+                    kn.partial_pct = pp;
                     const HistPlan plan = plan_hist(kn, prob->n, F, B, K, L, precision,
-                                                    ctx->max_lds);
+                                                    prob->loss == CBH_LOSS_RMSE, ctx->max_lds);
                     if (!seen.insert({plan.fb, plan.lt, plan.rows_per_chunk}).second) continue;
                     const int64_t part = int64_t(plan.n_chunks) * L * F * B *
                                          plan.words_per_cell * 4;

@@ -92,12 +92,12 @@ struct cbh_graph {
 namespace cbh {
 
 // ---------------------------------------------------------------- kernels
-template <int PREC>
-__global__ __launch_bounds__(256) void bhist_kernel(const DevProb* __restrict__ probs,
+template <int PREC, int RM>
+__global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __restrict__ probs,
                                                     const DevTile* __restrict__ tiles,
                                                     const LevelPlan::DevHP* __restrict__ plans,
                                                     int64_t n_tiles, int32_t L) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     const int64_t per_xcd = (n_tiles + 7) / 8;
     const int64_t ti = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (ti >= n_tiles) return;
@@ -125,7 +125,9 @@ __global__ __launch_bounds__(256) void bhist_kernel(const DevProb* __restrict__ 
     t.f0 = tile.fg * hp.fb;
     t.nf = min(hp.fb, pr.F - t.f0);
     t.l0 = (uint32_t)tile.lt_i * hp.lt;
-    hist_tile<PREC, 0>(t, lds);
+    t.side = nullptr;
+    t.sub_shift = 0;
+    hist_tile<PREC, 0, RM>(t, lds);
 }
 
 __device__ __forceinline__ int find_owner(const int64_t* __restrict__ off, int P, int64_t gi) {
@@ -200,9 +202,11 @@ __global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__
 }
 
 void batch_init_attrs(int max_lds) {
-    const void* fns[] = {(const void*)bhist_kernel<CBH_PREC_FP32>,
-                         (const void*)bhist_kernel<CBH_PREC_TWOFLOAT>,
-                         (const void*)bhist_kernel<CBH_PREC_INT16>};
+    const void* fns[] = {
+        (const void*)bhist_kernel<CBH_PREC_FP32, 0>, (const void*)bhist_kernel<CBH_PREC_FP32, 1>,
+        (const void*)bhist_kernel<CBH_PREC_TWOFLOAT, 0>,
+        (const void*)bhist_kernel<CBH_PREC_TWOFLOAT, 1>,
+        (const void*)bhist_kernel<CBH_PREC_INT16, 0>, (const void*)bhist_kernel<CBH_PREC_INT16, 1>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
@@ -212,18 +216,21 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     LevelPlan& lp = b->levels[level];
     const int L = 1 << level;
     const int64_t grid = 8 * ((lp.n_tiles + 7) / 8);
+    const bool rm = b->probs[0].loss == CBH_LOSS_RMSE;
+    const dim3 grd((unsigned)grid), blk(kHistThreads);
+    const size_t lds = (size_t)lp.max_lds;
     switch (b->precision) {
         case CBH_PREC_FP32:
-            bhist_kernel<CBH_PREC_FP32><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
-                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            if (rm) bhist_kernel<CBH_PREC_FP32, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            else bhist_kernel<CBH_PREC_FP32, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             break;
         case CBH_PREC_TWOFLOAT:
-            bhist_kernel<CBH_PREC_TWOFLOAT><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
-                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            if (rm) bhist_kernel<CBH_PREC_TWOFLOAT, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            else bhist_kernel<CBH_PREC_TWOFLOAT, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             break;
         default:
-            bhist_kernel<CBH_PREC_INT16><<<(unsigned)grid, 256, (size_t)lp.max_lds, s>>>(
-                b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            if (rm) bhist_kernel<CBH_PREC_INT16, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            else bhist_kernel<CBH_PREC_INT16, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             break;
     }
     CBH_LAUNCHED();
@@ -303,10 +310,11 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         rc = validate_precision(&probs[p], precision);
         if (rc) return rc;
         CBH_ARG(probs[p].depth == probs[0].depth, "every problem needs the same depth");
+        CBH_ARG(probs[p].loss == probs[0].loss, "every problem needs the same loss");
         CBH_ARG(hist[p] != nullptr, "hist[%d] is NULL", p);
-        CBH_REQUIRE(int64_t(probs[p].max_bins) * words_per_cell(precision, probs[p].K) * 4 <=
-                        ctx->max_lds,
-                    CBH_EUNSUPPORTED, "a leaf row of problem %d does not fit in LDS", p);
+        CBH_REQUIRE(tile_lds_bytes(precision, probs[p].loss == CBH_LOSS_RMSE, probs[p].K,
+                                   probs[p].max_bins, 1) <= ctx->max_lds,
+                    CBH_EUNSUPPORTED, "a (leaf, feature) tile of problem %d does not fit in LDS", p);
     }
     cbh_batch* b = new cbh_batch();
     b->ctx = ctx;
@@ -335,7 +343,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             kb.target_blocks = std::max<int32_t>(
                 64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
             HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, L, precision,
-                                    ctx->max_lds);
+                                    pr.loss == CBH_LOSS_RMSE, ctx->max_lds);
             lp.plans.push_back(hp);
             lp.part_off.push_back(off);
             off += align_up(int64_t(hp.n_chunks) * L * pr.n_features * pr.max_bins *

@@ -51,6 +51,7 @@ void clear_error();
 // Device-side error bits (ctx->d_flags[0]).
 enum : uint32_t {
     FLAG_NAN_INPUT = 1u,
+    FLAG_BAD_INDEX = 2u,
 };
 
 // ------------------------------------------------------- launch geometry
@@ -66,12 +67,17 @@ struct HistPlan {
     int64_t n_blocks = 0;    // n_chunks * n_fgroups * n_ltiles
 };
 
+// Threads per histogram block (16 waves): one block per CU holds a large LDS
+// tile while keeping enough waves resident to hide memory latency.
+constexpr int kHistThreads = 1024;
+
 // Tunable knobs of the histogram planner.
 struct HistKnobs {
-    int32_t lds_budget = 64 * 1024;  // bytes of LDS per block
-    int32_t max_fb = 32;
-    int32_t target_blocks = 1024;
-    int64_t min_rows = 4096;
+    int32_t lds_budget = 96 * 1024;  // bytes of LDS per block
+    int32_t max_fb = 32;             // features per block at most
+    int32_t target_blocks = 512;     // blocks aimed at per launch
+    int64_t min_rows = 32768;        // rows per block at least (2 steps of 16 rows/thread)
+    int32_t partial_pct = 25;        // partial tiles at most this % of the bin bytes
 };
 
 using TuneKey = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
@@ -104,7 +110,7 @@ int words_per_cell(int32_t precision, int32_t K);
 HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t level,
                     int32_t precision, int64_t n);
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
-                   int32_t n_leaves, int32_t precision, int max_lds);
+                   int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds);
 int64_t hist_elems(int32_t n_leaves, int32_t F, int32_t B, int32_t K);
 int64_t hist_elem_bytes(int32_t precision);
 
@@ -112,8 +118,10 @@ int validate_problem(const cbh_problem* p);
 int validate_precision(const cbh_problem* p, int32_t precision);
 
 // Launchers used by several entry points (same stream semantics as the API).
+// parent / side: subtraction mode (level >= 1), else NULL.
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
-                const HistPlan& plan, void* hist_out, void* partials, hipStream_t s);
+                const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
+                const void* parent = nullptr, const uint8_t* side = nullptr);
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores,
                  void* scratch, hipStream_t s);

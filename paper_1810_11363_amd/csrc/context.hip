@@ -150,6 +150,7 @@ int cbh_sync(cbh_ctx* ctx, void* stream) {
         CBH_HIP(hipMemset(ctx->d_flags, 0, sizeof(flags)));
         std::string msg = "device reported:";
         if (flags & FLAG_NAN_INPUT) msg += " NaN feature value (binned as 0);";
+        if (flags & FLAG_BAD_INDEX) msg += " permutation entry outside [0, n);";
         set_error("%s", msg.c_str());
         return CBH_EDEVICE;
     }

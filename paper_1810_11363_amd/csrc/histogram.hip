@@ -55,36 +55,54 @@ HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t
     return ctx->knobs;
 }
 
+// Launch plan of one histogram level.
+//   leaves per tile lt: all leaves if one leaf row per feature fits the LDS
+//     budget, else the largest power of two that does (extra tiles re-read
+//     the rows from cache, not from HBM);
+//   chunks C (row ranges): bounded by the rows a block needs to be efficient
+//     (min_rows) and by the partial-tile volume C * L * F * B * wpc * 4, kept
+//     under partial_pct % of the n * F bin bytes;
+//   feature groups: as many as needed to reach target_blocks, at least enough
+//     to respect the LDS bound on features per block.
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
-                   int32_t n_leaves, int32_t precision, int max_lds) {
+                   int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds) {
     HistPlan p;
     p.words_per_cell = words_per_cell(precision, K);
-    const int64_t cell_bytes = int64_t(B) * p.words_per_cell * 4;
-    const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
+    const int64_t cell_bytes = tile_lds_bytes(precision, rmse, K, B, 1);   // LDS per cell
+    const int64_t out_cell_bytes = int64_t(B) * p.words_per_cell * 4;     // partial per cell
+    const int64_t budget = std::max<int64_t>(cell_bytes, std::min<int64_t>(kn.lds_budget, max_lds));
+    int64_t fb_max;
     if (int64_t(n_leaves) * cell_bytes <= budget) {
         p.lt = n_leaves;
-        int64_t fb = budget / (int64_t(n_leaves) * cell_bytes);
-        fb = std::min<int64_t>(fb, std::min<int64_t>(F, std::max(1, kn.max_fb)));
-        p.fb = (int32_t)std::max<int64_t>(1, fb);
+        fb_max = budget / (int64_t(n_leaves) * cell_bytes);
     } else {
         int32_t lt = 1;
         while (int64_t(lt) * 2 * cell_bytes <= budget && lt * 2 <= n_leaves) lt *= 2;
         p.lt = lt;
-        p.fb = 1;
+        fb_max = 1;
     }
-    // balance features over groups so the last group is not nearly empty
-    p.n_fgroups = (F + p.fb - 1) / p.fb;
-    p.fb = (F + p.n_fgroups - 1) / p.n_fgroups;
+    fb_max = std::max<int64_t>(1, std::min<int64_t>(fb_max, std::min<int64_t>(F, kn.max_fb)));
     p.n_ltiles = (n_leaves + p.lt - 1) / p.lt;
-    const int64_t base = int64_t(p.n_fgroups) * p.n_ltiles;
-    int64_t chunks = std::max<int64_t>(1, (kn.target_blocks + base - 1) / base);
+    const int64_t g_min = (F + fb_max - 1) / fb_max;
+    const int64_t tiles = p.n_ltiles;
+    const int64_t part_per_chunk = int64_t(n_leaves) * F * out_cell_bytes;
+    const int64_t c_part = std::max<int64_t>(1, (int64_t(kn.partial_pct) * n * F / 100) /
+                                                    std::max<int64_t>(1, part_per_chunk));
+    const int64_t c_rows = std::max<int64_t>(1, n / std::max<int64_t>(1, kn.min_rows));
+    const int64_t c_fill = std::max<int64_t>(1, (kn.target_blocks + g_min * tiles - 1) /
+                                                    (g_min * tiles));
+    int64_t chunks = std::min(std::min(c_part, c_rows), c_fill);
     int64_t rows = align_up((n + chunks - 1) / chunks, 16);
-    rows = std::max<int64_t>(rows, align_up(std::min<int64_t>(kn.min_rows, n), 16));
     if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);
     p.rows_per_chunk = rows;
     p.n_chunks = (int32_t)((n + rows - 1) / rows);
+    int64_t groups = std::max<int64_t>(
+        g_min, (kn.target_blocks + int64_t(p.n_chunks) * tiles - 1) / (int64_t(p.n_chunks) * tiles));
+    groups = std::min<int64_t>(groups, F);
+    p.fb = (int32_t)((F + groups - 1) / groups);
+    p.n_fgroups = (F + p.fb - 1) / p.fb;
     p.lds_bytes = int64_t(p.lt) * p.fb * cell_bytes;
-    p.n_blocks = int64_t(p.n_chunks) * base;
+    p.n_blocks = int64_t(p.n_chunks) * p.n_fgroups * p.n_ltiles;
     return p;
 }
 
@@ -102,11 +120,13 @@ struct HistArgs {
     int32_t fb, lt, n_fgroups, n_ltiles;
     int32_t wpc;
     int32_t rmse;
+    const uint8_t* side;    // subtraction mode (see TileArgs), else NULL
+    uint32_t sub_shift;
 };
 
-template <int PREC, int KT>
-__global__ __launch_bounds__(256) void hist_kernel(HistArgs a) {
-    extern __shared__ uint32_t lds[];
+template <int PREC, int KT, int RM>
+__global__ __launch_bounds__(kHistThreads) void hist_kernel(HistArgs a) {
+    extern __shared__ __align__(16) uint32_t lds[];
     // XCD-contiguous work: hardware deals consecutive block ids to the 8 XCDs in
     // turn, so block b works on item (b % 8) * per_xcd + b / 8.
     const int64_t per_xcd = (a.n_blocks + 7) / 8;
@@ -137,27 +157,210 @@ __global__ __launch_bounds__(256) void hist_kernel(HistArgs a) {
     t.f0 = fg * a.fb;
     t.nf = min(a.fb, a.F - t.f0);
     t.l0 = (uint32_t)lt_i * a.lt;
-    hist_tile<PREC, KT>(t, lds);
+    t.side = a.side;
+    t.sub_shift = a.sub_shift;
+    hist_tile<PREC, KT, RM>(t, lds);
 }
 
-// Merge the partial tiles of all chunks in chunk order, one thread per cell.
+// Merge the partial tiles of all chunks. A block takes 64 consecutive output
+// units (a word for FP32, a (hi, lo) pair for TWOFLOAT, a packed u64 for
+// INT16); wave w sums chunks w, w + 4, w + 8, ... and the four slice sums are
+// added in slice order, so the result does not depend on scheduling.
+//
+// Subtraction mode (parent != NULL): the partials hold, for every parent leaf
+// p < half, the histogram of its smaller child (bit side[p]); the merged value
+// is written to that child and parent - value to its sibling: exact for
+// integer sums and counts, a two-float difference for TWOFLOAT.
+struct SubArgs {
+    const void* parent;     // level-1 histogram in the output format, or NULL
+    const uint8_t* side;    // [half] child whose rows were accumulated
+    int64_t fb_cells;       // F * B
+    int64_t half;           // number of parents
+};
+
 template <int PREC>
-__global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __restrict__ partials,
+__global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __restrict__ part,
                                                           int64_t cells, int32_t K,
                                                           int32_t n_chunks, int32_t rmse,
-                                                          void* __restrict__ out) {
-    for (int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x; cell < cells;
-         cell += int64_t(gridDim.x) * 256)
-        merge_cell<PREC>(partials, cells, K, n_chunks, rmse != 0, out, cell);
+                                                          void* __restrict__ out, SubArgs sub) {
+    __shared__ int64_t acc_a[4][64];
+    __shared__ int64_t acc_b[4][64];
+    const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int wpc = PREC == CBH_PREC_TWOFLOAT ? 4 * K : 2 * K;
+    const int64_t cw = cells * wpc;     // words per chunk partial
+    const int64_t upc = PREC == CBH_PREC_INT16 ? K : 2 * K;   // units per cell
+    const int64_t units = cells * upc;
+    for (int64_t u0 = int64_t(blockIdx.x) * 64; u0 < units; u0 += int64_t(gridDim.x) * 64) {
+        const int64_t u = u0 + lane;
+        const bool ok = u < units;
+        // destination units: the merged value and, in subtraction mode, its sibling
+        int64_t u_small = u, u_big = -1;
+        if (sub.parent && ok) {
+            const int64_t cell = u / upc, within = u % upc;
+            const int64_t p = cell / sub.fb_cells, rest = cell % sub.fb_cells;
+            const int64_t sd = sub.side[p];
+            u_small = ((p + sd * sub.half) * sub.fb_cells + rest) * upc + within;
+            u_big = ((p + (1 - sd) * sub.half) * sub.fb_cells + rest) * upc + within;
+        }
+        if constexpr (PREC == CBH_PREC_FP32) {
+            const bool is_count = rmse && (u & 1);
+            float fs = 0.f;
+            uint32_t cs = 0;
+            if (ok)
+                for (int ch = slice; ch < n_chunks; ch += 4) {
+                    const uint32_t v = part[ch * cw + u];
+                    if (is_count) cs += v; else fs += __uint_as_float(v);
+                }
+            acc_a[slice][lane] = is_count ? (int64_t)cs : (int64_t)__float_as_uint(fs);
+            __syncthreads();
+            if (slice == 0 && ok) {
+                if (is_count) {
+                    uint32_t t = 0;
+                    for (int sl = 0; sl < 4; ++sl) t += (uint32_t)acc_a[sl][lane];
+                    reinterpret_cast<uint32_t*>(out)[u_small] = t;
+                    if (u_big >= 0)
+                        reinterpret_cast<uint32_t*>(out)[u_big] =
+                            reinterpret_cast<const uint32_t*>(sub.parent)[u] - t;
+                } else {
+                    float t = 0.f;
+                    for (int sl = 0; sl < 4; ++sl) t += __uint_as_float((uint32_t)acc_a[sl][lane]);
+                    reinterpret_cast<float*>(out)[u_small] = t;
+                    if (u_big >= 0)
+                        reinterpret_cast<float*>(out)[u_big] =
+                            reinterpret_cast<const float*>(sub.parent)[u] - t;
+                }
+            }
+        } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
+            const bool is_count = rmse && (u & 1);
+            float S = 0.f, E = 0.f;
+            uint32_t cs = 0;
+            if (ok)
+                for (int ch = slice; ch < n_chunks; ch += 4) {
+                    const uint32_t hi_w = part[ch * cw + 2 * u];
+                    if (is_count) {
+                        cs += hi_w;
+                        continue;
+                    }
+                    const float hi = __uint_as_float(hi_w);
+                    const float lo = __uint_as_float(part[ch * cw + 2 * u + 1]);
+                    const float t = S + hi;
+                    const float bp = t - S;
+                    E += ((S - (t - bp)) + (hi - bp)) + lo;
+                    S = t;
+                }
+            acc_a[slice][lane] = is_count ? (int64_t)cs : (int64_t)__float_as_uint(S);
+            acc_b[slice][lane] = (int64_t)__float_as_uint(E);
+            __syncthreads();
+            if (slice == 0 && ok) {
+                float2 r;
+                if (is_count) {
+                    uint32_t t = 0;
+                    for (int sl = 0; sl < 4; ++sl) t += (uint32_t)acc_a[sl][lane];
+                    r = make_float2(__uint_as_float(t), 0.f);
+                    if (u_big >= 0) {
+                        const uint32_t pc =
+                            __float_as_uint(reinterpret_cast<const float2*>(sub.parent)[u].x);
+                        reinterpret_cast<float2*>(out)[u_big] = make_float2(__uint_as_float(pc - t), 0.f);
+                    }
+                } else {
+                    float S2 = 0.f, E2 = 0.f;
+                    for (int sl = 0; sl < 4; ++sl) {
+                        const float hi = __uint_as_float((uint32_t)acc_a[sl][lane]);
+                        const float lo = __uint_as_float((uint32_t)acc_b[sl][lane]);
+                        const float t = S2 + hi;
+                        const float bp = t - S2;
+                        E2 += ((S2 - (t - bp)) + (hi - bp)) + lo;
+                        S2 = t;
+                    }
+                    const float hs = S2 + E2;
+                    r = make_float2(hs, E2 - (hs - S2));
+                    if (u_big >= 0) {
+                        // (P_hi, P_lo) - (hs, lo) with TwoSum on the leading parts
+                        const float2 P = reinterpret_cast<const float2*>(sub.parent)[u];
+                        const float t = P.x - r.x;
+                        const float bp = t - P.x;
+                        const float e = ((P.x - (t - bp)) + (-r.x - bp)) + (P.y - r.y);
+                        const float dh = t + e;
+                        reinterpret_cast<float2*>(out)[u_big] = make_float2(dh, e - (dh - t));
+                    }
+                }
+                reinterpret_cast<float2*>(out)[u_small] = r;
+            }
+        } else {
+            const uint64_t* P64 = reinterpret_cast<const uint64_t*>(part);
+            int64_t gs = 0, hs = 0;
+            if (ok)
+                for (int ch = slice; ch < n_chunks; ch += 4) {
+                    const uint64_t v = P64[ch * (cw / 2) + u];
+                    hs += (int64_t)(uint32_t)(v & 0xffffffffull);
+                    gs += (int64_t)(int32_t)(uint32_t)(v >> 32);
+                }
+            acc_a[slice][lane] = gs;
+            acc_b[slice][lane] = hs;
+            __syncthreads();
+            if (slice == 0 && ok) {
+                int64_t tg = 0, th = 0;
+                for (int sl = 0; sl < 4; ++sl) {
+                    tg += acc_a[sl][lane];
+                    th += acc_b[sl][lane];
+                }
+                int64_t* o = reinterpret_cast<int64_t*>(out);
+                o[2 * u_small] = tg;
+                o[2 * u_small + 1] = th;
+                if (u_big >= 0) {
+                    const int64_t* P = reinterpret_cast<const int64_t*>(sub.parent);
+                    o[2 * u_big] = P[2 * u] - tg;
+                    o[2 * u_big + 1] = P[2 * u + 1] - th;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Smaller child of every parent leaf p at the parent level's split, judged by
+// the parent histogram's second statistic (row count for RMSE, sum of h
+// otherwise) on the split feature; side[p] = 1 if the bit-set side is smaller.
+// With no split every row stayed on the clear side, so the set side is empty.
+template <int PREC>
+__global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ parent,
+                                                       const cbh_split* __restrict__ split,
+                                                       int64_t half, int32_t F, int32_t B,
+                                                       int32_t K, int32_t rmse,
+                                                       uint8_t* __restrict__ side) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= half) return;
+    const int f = split->feature, k = split->border;
+    if (f < 0 || f >= F) {
+        side[p] = 1;
+        return;
+    }
+    double left = 0.0, right = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const int64_t e = ((p * F + f) * B + b) * 2 * K + 1;   // statistic 1 of class 0
+        double v;
+        if constexpr (PREC == CBH_PREC_FP32)
+            v = rmse ? (double)reinterpret_cast<const uint32_t*>(parent)[e]
+                     : (double)reinterpret_cast<const float*>(parent)[e];
+        else if constexpr (PREC == CBH_PREC_TWOFLOAT)
+            v = rmse ? (double)__float_as_uint(reinterpret_cast<const float2*>(parent)[e].x)
+                     : (double)reinterpret_cast<const float2*>(parent)[e].x;
+        else
+            v = (double)reinterpret_cast<const int64_t*>(parent)[e];
+        if (b <= k) left += v; else right += v;
+    }
+    side[p] = right < left ? 1 : 0;
 }
 
 void hist_init_attrs(int max_lds) {
-    const void* fns[] = {(const void*)hist_kernel<CBH_PREC_FP32, 1>,
-                         (const void*)hist_kernel<CBH_PREC_FP32, 0>,
-                         (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 1>,
-                         (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 0>,
-                         (const void*)hist_kernel<CBH_PREC_INT16, 1>,
-                         (const void*)hist_kernel<CBH_PREC_INT16, 0>};
+    const void* fns[] = {
+        (const void*)hist_kernel<CBH_PREC_FP32, 1, 0>, (const void*)hist_kernel<CBH_PREC_FP32, 1, 1>,
+        (const void*)hist_kernel<CBH_PREC_FP32, 0, 0>,
+        (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 1, 0>,
+        (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 1, 1>,
+        (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 0, 0>,
+        (const void*)hist_kernel<CBH_PREC_INT16, 1, 0>, (const void*)hist_kernel<CBH_PREC_INT16, 1, 1>,
+        (const void*)hist_kernel<CBH_PREC_INT16, 0, 0>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
@@ -167,14 +370,19 @@ static void launch_hist_prec(const HistArgs& a, const HistPlan& plan, int max_ld
                              hipStream_t s) {
     const int64_t grid = 8 * ((plan.n_blocks + 7) / 8);
     (void)max_lds;
-    if (a.K == 1)
-        hist_kernel<PREC, 1><<<(unsigned)grid, 256, (size_t)plan.lds_bytes, s>>>(a);
+    // MultiClass (K > 1) is never RMSE; K = 1 has an RMSE (count) and a
+    // second-derivative form
+    if (a.K > 1)
+        hist_kernel<PREC, 0, 0><<<(unsigned)grid, kHistThreads, (size_t)plan.lds_bytes, s>>>(a);
+    else if (a.rmse)
+        hist_kernel<PREC, 1, 1><<<(unsigned)grid, kHistThreads, (size_t)plan.lds_bytes, s>>>(a);
     else
-        hist_kernel<PREC, 0><<<(unsigned)grid, 256, (size_t)plan.lds_bytes, s>>>(a);
+        hist_kernel<PREC, 1, 0><<<(unsigned)grid, kHistThreads, (size_t)plan.lds_bytes, s>>>(a);
 }
 
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
-                const HistPlan& plan, void* hist_out, void* partials, hipStream_t s) {
+                const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
+                const void* parent, const uint8_t* side) {
     HistArgs a;
     a.bins = p->bins;
     a.g = p->g;
@@ -188,7 +396,10 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     a.F = p->n_features;
     a.B = p->max_bins;
     a.K = p->K;
-    a.L = 1 << level;
+    // subtraction mode accumulates per parent leaf (half as many tile leaves)
+    a.L = parent ? 1 << (level - 1) : 1 << level;
+    a.side = parent ? side : nullptr;
+    a.sub_shift = parent ? (uint32_t)(level - 1) : 0u;
     a.fb = plan.fb;
     a.lt = plan.lt;
     a.n_fgroups = plan.n_fgroups;
@@ -204,19 +415,21 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     }
     CBH_LAUNCHED();
     const int64_t cells = int64_t(a.L) * a.F * a.B;
-    const int grid = (int)std::min<int64_t>((cells + 255) / 256, int64_t(ctx->num_cus) * 16);
+    const int64_t units = precision == CBH_PREC_INT16 ? cells * a.K : cells * 2 * a.K;
+    const int grid = (int)std::min<int64_t>((units + 63) / 64, int64_t(ctx->num_cus) * 16);
+    const SubArgs sub{parent, side, int64_t(a.F) * a.B, int64_t(a.L)};
     switch (precision) {
         case CBH_PREC_FP32:
             hist_reduce_kernel<CBH_PREC_FP32><<<grid, 256, 0, s>>>(
-                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out);
+                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out, sub);
             break;
         case CBH_PREC_TWOFLOAT:
             hist_reduce_kernel<CBH_PREC_TWOFLOAT><<<grid, 256, 0, s>>>(
-                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out);
+                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out, sub);
             break;
         default:
             hist_reduce_kernel<CBH_PREC_INT16><<<grid, 256, 0, s>>>(
-                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out);
+                (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out, sub);
             break;
     }
     CBH_LAUNCHED();
@@ -228,6 +441,7 @@ __global__ __launch_bounds__(256) void grad_max_kernel(const float* __restrict__
                                                        const float* __restrict__ h, int64_t n,
                                                        int32_t K, int32_t with_h,
                                                        uint32_t* __restrict__ maxbits) {
+    __shared__ float wm[2][4];
     const int c = blockIdx.y;
     float mg = 0.f, mh = 0.f;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
@@ -240,7 +454,14 @@ __global__ __launch_bounds__(256) void grad_max_kernel(const float* __restrict__
         mh = fmaxf(mh, __shfl_xor(mh, d, 64));
     }
     if ((threadIdx.x & 63) == 0) {
-        // non-negative floats order like their bit patterns
+        wm[0][threadIdx.x >> 6] = mg;
+        wm[1][threadIdx.x >> 6] = mh;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mg = fmaxf(fmaxf(wm[0][0], wm[0][1]), fmaxf(wm[0][2], wm[0][3]));
+        mh = fmaxf(fmaxf(wm[1][0], wm[1][1]), fmaxf(wm[1][2], wm[1][3]));
+        // one atomic per block; non-negative floats order like their bit patterns
         atomicMax(&maxbits[2 * c], __float_as_uint(mg));
         atomicMax(&maxbits[2 * c + 1], __float_as_uint(mh));
     }
@@ -296,7 +517,8 @@ int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream) 
     const int with_h = prob->loss != CBH_LOSS_RMSE;
     zero_u32_kernel<<<1, 64, 0, s>>>(maxbits, 2 * prob->K);
     const int gx = (int)std::min<int64_t>((prob->n + 255) / 256, ctx->num_cus * 4);
-    grad_max_kernel<<<dim3(gx, prob->K), 256, 0, s>>>(prob->g, prob->h, prob->n, prob->K,
+    const int gm = (int)std::min<int64_t>((prob->n + 255) / 256, ctx->num_cus);
+    grad_max_kernel<<<dim3(gm, prob->K), 256, 0, s>>>(prob->g, prob->h, prob->n, prob->K,
                                                       with_h, maxbits);
     grad_code_kernel<<<dim3(gx, prob->K), 256, 0, s>>>(prob->g, prob->h, prob->n, prob->K,
                                                        with_h, maxbits,
@@ -318,17 +540,68 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
     const int L = 1 << level;
     const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
                                    precision, prob->n);
+    const int rmse = prob->loss == CBH_LOSS_RMSE;
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, L,
-                                    precision, ctx->max_lds);
-    CBH_REQUIRE(int64_t(prob->max_bins) * plan.words_per_cell * 4 <= ctx->max_lds,
-                CBH_EUNSUPPORTED, "one leaf row of %d bins x %d words does not fit in LDS",
-                prob->max_bins, plan.words_per_cell);
+                                    precision, rmse, ctx->max_lds);
+    CBH_REQUIRE(tile_lds_bytes(precision, rmse, prob->K, prob->max_bins, 1) <= ctx->max_lds,
+                CBH_EUNSUPPORTED, "one (leaf, feature) tile of %d bins does not fit in LDS",
+                prob->max_bins);
     const int64_t part_bytes =
         int64_t(plan.n_chunks) * L * prob->n_features * prob->max_bins * plan.words_per_cell * 4;
     rc = ensure_ws(ctx, part_bytes);
     if (rc) return rc;
     return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws,
                        (hipStream_t)stream);
+}
+
+int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                             int32_t precision, const void* parent_hist,
+                             const cbh_split* parent_split, void* hist_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    CBH_ARG(level >= 1 && level < prob->depth, "level %d outside [1, depth)", level);
+    CBH_ARG(parent_hist && parent_split && hist_out, "NULL histogram or split");
+    CBH_ARG(parent_hist != hist_out, "parent_hist and hist_out must not be the same buffer");
+    const int half = 1 << (level - 1);
+    const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
+                                   precision, prob->n);
+    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, half,
+                                    precision, rmse, ctx->max_lds);
+    CBH_REQUIRE(tile_lds_bytes(precision, rmse, prob->K, prob->max_bins, 1) <= ctx->max_lds,
+                CBH_EUNSUPPORTED, "one (leaf, feature) tile of %d bins does not fit in LDS",
+                prob->max_bins);
+    const int64_t part_bytes = align_up(
+        int64_t(plan.n_chunks) * half * prob->n_features * prob->max_bins * plan.words_per_cell * 4,
+        256);
+    rc = ensure_ws(ctx, part_bytes + align_up(half, 256));
+    if (rc) return rc;
+    uint8_t* side = (uint8_t*)ctx->ws + part_bytes;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned gs = (unsigned)((half + 255) / 256);
+    switch (precision) {
+        case CBH_PREC_FP32:
+            sub_side_kernel<CBH_PREC_FP32><<<gs, 256, 0, s>>>(parent_hist, parent_split, half,
+                                                              prob->n_features, prob->max_bins,
+                                                              prob->K, rmse, side);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            sub_side_kernel<CBH_PREC_TWOFLOAT><<<gs, 256, 0, s>>>(
+                parent_hist, parent_split, half, prob->n_features, prob->max_bins, prob->K, rmse,
+                side);
+            break;
+        default:
+            sub_side_kernel<CBH_PREC_INT16><<<gs, 256, 0, s>>>(parent_hist, parent_split, half,
+                                                               prob->n_features, prob->max_bins,
+                                                               prob->K, rmse, side);
+            break;
+    }
+    CBH_LAUNCHED();
+    return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side);
 }
 
 }  // extern "C"

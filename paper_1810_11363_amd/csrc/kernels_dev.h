@@ -14,8 +14,23 @@ namespace cbh {
 
 // ------------------------------------------------------------ histogram tile
 // One block accumulates rows [r0, r1) of features [f0, f0 + nf) for leaves
-// [l0, l0 + lt) into an LDS tile [lt][fb][B][wpc words], then writes the tile
-// into `part`, the chunk's partial histogram laid out as [L][F][B][wpc].
+// [l0, l0 + lt) into an LDS tile, then writes the tile into `part`, the
+// chunk's partial histogram laid out as [L][F][B][wpc words] in the output
+// format of the precision.
+//
+// On gfx950 the LDS float32 atomic add is serialised (measured about 0.3 lane
+// updates per clock per CU against about 5 for u32 and 4 for f64 with random
+// addresses), so the tile of the float-valued forms accumulates in float64
+// (ds_add_f64) and is rounded once per tile when written out; counts use u32
+// atomics and the int16 form one u64 atomic of packed codes. A "cell" is one
+// (leaf, feature) pair of the tile, cell = leaf_in_tile * fb + feature_in_block.
+//   FP32 / TWOFLOAT, K classes, h statistic:   f64 [cells][K][2][B]
+//   FP32 / TWOFLOAT, RMSE (K = 1, count):      f64 [cells][B], then u32 [cells][B]
+//   INT16:                                     u64 [cells][K][B]
+// Each thread streams 8 or 16 consecutive rows per step: one 8- or 16-byte
+// load of bins per feature (a wave reads 512 B or 1 KB contiguous per
+// feature), and loads for 4 features are issued before their LDS updates so
+// that memory latency overlaps.
 struct TileArgs {
     const uint8_t* const* bins;
     const float* g;
@@ -28,151 +43,276 @@ struct TileArgs {
     int32_t fb, lt, wpc, rmse;
     int32_t f0, nf;
     uint32_t l0;
+    // Histogram subtraction: when `side` is set, the tile is indexed by the
+    // parent leaf p = leaf & (L - 1) (L = number of parents) and only rows of
+    // the child whose bit `sub_shift` equals side[p] are accumulated.
+    const uint8_t* side = nullptr;
+    uint32_t sub_shift = 0;
 };
 
-template <int PREC>
-__device__ __forceinline__ void add_row(uint32_t* lds, uint32_t w, int c, float gv, float hv,
-                                        uint32_t qv, bool rmse) {
-    if constexpr (PREC == CBH_PREC_FP32) {
-        __hip_atomic_fetch_add((float*)&lds[w + 2 * c], gv, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (rmse)
-            __hip_atomic_fetch_add(&lds[w + 2 * c + 1], 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            __hip_atomic_fetch_add((float*)&lds[w + 2 * c + 1], hv, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
-        // TwoSum on the value the atomic returned: fl(old + v) is what the LDS
-        // now holds, err is the exact rounding error of that addition, and the
-        // "lo" word collects the errors, so hi + lo tracks the exact sum.
-        const float old = __hip_atomic_fetch_add((float*)&lds[w + 4 * c], gv, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-        const float s = old + gv;
-        const float bp = s - old;
-        const float err = (old - (s - bp)) + (gv - bp);
-        if (err != 0.0f)
-            __hip_atomic_fetch_add((float*)&lds[w + 4 * c + 1], err, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (rmse) {
-            __hip_atomic_fetch_add(&lds[w + 4 * c + 2], 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            const float oh = __hip_atomic_fetch_add((float*)&lds[w + 4 * c + 2], hv,
-                                                    __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-            const float sh = oh + hv;
-            const float bh = sh - oh;
-            const float eh = (oh - (sh - bh)) + (hv - bh);
-            if (eh != 0.0f)
-                __hip_atomic_fetch_add((float*)&lds[w + 4 * c + 3], eh, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    } else {
+// Tile leaf slot of a row with leaf value v (>= lt: not in this tile).
+__device__ __forceinline__ uint32_t tile_slot(const TileArgs& a, uint32_t v, uint32_t lmask) {
+    if (a.side) {
+        const uint32_t p = v & lmask;
+        if (((v >> a.sub_shift) & 1u) != (uint32_t)a.side[p]) return 0xffffffffu;
+        return p - a.l0;
+    }
+    return (v & lmask) - a.l0;
+}
+
+// LDS bytes of a tile of `cells` cells.
+__host__ __device__ inline int64_t tile_lds_bytes(int precision, int rmse, int K, int B,
+                                                  int64_t cells) {
+    if (precision == CBH_PREC_INT16) return cells * K * B * 8;
+    if (rmse) return cells * B * 12;
+    return cells * K * 2 * B * 8;
+}
+
+template <int PREC, int RM>
+__device__ __forceinline__ void add_row(uint32_t* lds, uint32_t ncells, uint32_t cell,
+                                        uint32_t B, uint32_t bin, int c, int K, float gv,
+                                        float hv, uint32_t qv) {
+    if constexpr (PREC == CBH_PREC_INT16) {
         // (g code << 32) + h code: with <= 65536 rows per tile neither half
         // overflows, so one 64-bit LDS add updates both sums exactly.
         const int64_t gcode = (int16_t)(qv & 0xffffu);
         const uint64_t hcode = (qv >> 16) & 0x7fffu;
         const uint64_t packed = ((uint64_t)gcode << 32) + hcode;
-        __hip_atomic_fetch_add((unsigned long long*)&lds[w + 2 * c], (unsigned long long)packed,
+        unsigned long long* l64 = reinterpret_cast<unsigned long long*>(lds);
+        __hip_atomic_fetch_add(l64 + (cell * K + c) * B + bin, (unsigned long long)packed,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        double* l64 = reinterpret_cast<double*>(lds);
+        if constexpr (RM != 0) {
+            __hip_atomic_fetch_add(l64 + cell * B + bin, (double)gv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(lds + 2 * ncells * B + cell * B + bin, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            const uint32_t d = ((cell * K + c) * 2) * B + bin;
+            __hip_atomic_fetch_add(l64 + d, (double)gv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(l64 + d + B, (double)hv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
 }
 
-template <int PREC, int KT>
-__device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
-    const int K = KT > 0 ? KT : a.K;
-    const uint32_t lmask = (uint32_t)a.L - 1u;
-    const uint32_t ltn = (uint32_t)a.lt;
-    const uint32_t Bm1 = (uint32_t)a.B - 1u;
-    const int wpc = a.wpc;
-    const int tile_words = a.lt * a.fb * a.B * wpc;
-    for (int i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
-    __syncthreads();
-    const bool rmse = a.rmse != 0;
-    const bool vec = (a.n & 3) == 0 || K == 1;
-    const int64_t ngroups = (a.r1 - a.r0) >> 2;
-    for (int64_t q = threadIdx.x; q < ngroups; q += blockDim.x) {
-        const int64_t i = a.r0 + 4 * q;
-        const uint2 lf = a.L == 1 ? make_uint2(0u, 0u)
-                                  : *reinterpret_cast<const uint2*>(a.leaf + i);
-        uint32_t lv[4] = {lf.x & 0xffffu, lf.x >> 16, lf.y & 0xffffu, lf.y >> 16};
+// ROWS (8 or 16) bins of rows i.. of one column (any alignment of the column),
+// in .x .y (.z .w) little-endian order.
+template <int ROWS>
+__device__ __forceinline__ uint4 load_bins(const uint8_t* col, int64_t i) {
+    const uint8_t* p = col + i;
+    if constexpr (ROWS == 16) {
+        if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) return *reinterpret_cast<const uint4*>(p);
+    } else {
+        if ((reinterpret_cast<uintptr_t>(p) & 7) == 0) {
+            const uint2 v = *reinterpret_cast<const uint2*>(p);
+            return make_uint4(v.x, v.y, 0u, 0u);
+        }
+    }
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) lv[r] = (lv[r] & lmask) - a.l0;  // >= lt: not in tile
-        for (int c = 0; c < K; ++c) {
-            float gv[4] = {0.f, 0.f, 0.f, 0.f}, hv[4] = {1.f, 1.f, 1.f, 1.f};
-            uint32_t qv[4] = {0u, 0u, 0u, 0u};
-            const int64_t ci = int64_t(c) * a.n + i;
-            if constexpr (PREC == CBH_PREC_INT16) {
-                if (vec) {
-                    const uint4 t = *reinterpret_cast<const uint4*>(a.gq + ci);
-                    qv[0] = t.x; qv[1] = t.y; qv[2] = t.z; qv[3] = t.w;
-                } else {
+    for (int k = 0; k < ROWS / 4; ++k)
+        w[k] = (uint32_t)p[4 * k] | ((uint32_t)p[4 * k + 1] << 8) |
+               ((uint32_t)p[4 * k + 2] << 16) | ((uint32_t)p[4 * k + 3] << 24);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4& v, int r) {
+    const uint32_t w = r < 4 ? v.x : r < 8 ? v.y : r < 12 ? v.z : v.w;
+    return (w >> (8 * (r & 3))) & 255u;
+}
+
+template <int PREC, int ROWS>
+__device__ __forceinline__ void load_grad(const TileArgs& a, int c, int64_t i, bool vec,
+                                          bool rmse, float gv[ROWS], float hv[ROWS],
+                                          uint32_t qv[ROWS]) {
+    const int64_t ci = int64_t(c) * a.n + i;
+    if constexpr (PREC == CBH_PREC_INT16) {
+        if (vec) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) qv[r] = a.gq[ci + r];
-                }
-            } else {
-                if (vec) {
-                    const float4 t = *reinterpret_cast<const float4*>(a.g + ci);
-                    gv[0] = t.x; gv[1] = t.y; gv[2] = t.z; gv[3] = t.w;
-                    if (!rmse) {
-                        const float4 u = *reinterpret_cast<const float4*>(a.h + ci);
-                        hv[0] = u.x; hv[1] = u.y; hv[2] = u.z; hv[3] = u.w;
-                    }
-                } else {
+            for (int k = 0; k < ROWS / 4; ++k) {
+                const uint4 t = *reinterpret_cast<const uint4*>(a.gq + ci + 4 * k);
+                qv[4 * k] = t.x; qv[4 * k + 1] = t.y; qv[4 * k + 2] = t.z; qv[4 * k + 3] = t.w;
+            }
+        } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        gv[r] = a.g[ci + r];
-                        if (!rmse) hv[r] = a.h[ci + r];
-                    }
+            for (int r = 0; r < ROWS; ++r) qv[r] = a.gq[ci + r];
+        }
+    } else {
+        if (vec) {
+#pragma unroll
+            for (int k = 0; k < ROWS / 4; ++k) {
+                const float4 t = *reinterpret_cast<const float4*>(a.g + ci + 4 * k);
+                gv[4 * k] = t.x; gv[4 * k + 1] = t.y; gv[4 * k + 2] = t.z; gv[4 * k + 3] = t.w;
+                if (!rmse) {
+                    const float4 u = *reinterpret_cast<const float4*>(a.h + ci + 4 * k);
+                    hv[4 * k] = u.x; hv[4 * k + 1] = u.y; hv[4 * k + 2] = u.z;
+                    hv[4 * k + 3] = u.w;
                 }
             }
-            for (int j = 0; j < a.nf; ++j) {
-                const uint32_t b4 = *reinterpret_cast<const uint32_t*>(a.bins[a.f0 + j] + i);
+        } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (lv[r] < ltn) {
-                        const uint32_t bin = min((b4 >> (8 * r)) & 255u, Bm1);
-                        const uint32_t w = ((lv[r] * a.fb + j) * a.B + bin) * wpc;
-                        add_row<PREC>(lds, w, c, gv[r], hv[r], qv[r], rmse);
+            for (int r = 0; r < ROWS; ++r) {
+                gv[r] = a.g[ci + r];
+                if (!rmse) hv[r] = a.h[ci + r];
+            }
+        }
+    }
+}
+
+// Rows per thread per step: 16 for the int16 form (one u64 atomic per row and
+// feature, few live registers), 8 for the float forms, whose float64 LDS
+// updates need twice the registers per row.
+template <int PREC>
+constexpr int rows_per_step() { return PREC == CBH_PREC_INT16 ? 16 : 8; }
+
+template <int PREC, int KT, int RM>
+__device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
+    constexpr int ROWS = rows_per_step<PREC>();
+    constexpr int LOG_ROWS = ROWS == 16 ? 4 : 3;
+    const int K = KT > 0 ? KT : a.K;
+    const int nthr = blockDim.x;
+    const uint32_t lmask = (uint32_t)a.L - 1u;
+    const uint32_t ltn = (uint32_t)a.lt;
+    const uint32_t B = (uint32_t)a.B;
+    const uint32_t Bm1 = B - 1u;
+    const uint32_t ncells = (uint32_t)(a.lt * a.fb);
+    const int tile_words = (int)(tile_lds_bytes(PREC, RM, K, a.B, ncells) / 4);
+    for (int i = threadIdx.x; i < tile_words; i += nthr) lds[i] = 0u;
+    __syncthreads();
+    constexpr bool rmse = RM != 0;
+    const bool vec = ((a.n & 3) == 0 || K == 1) &&
+                     ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.h) |
+                       reinterpret_cast<uintptr_t>(a.gq)) & 15) == 0;
+    const bool leaf_vec = (reinterpret_cast<uintptr_t>(a.leaf) & 15) == 0;
+    const int64_t nq = (a.r1 - a.r0) >> LOG_ROWS;
+    constexpr uint32_t kSkip = 0xffffffffu;
+    float gv[ROWS], hv[ROWS];
+    uint32_t qv[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        gv[r] = 0.f;
+        hv[r] = 1.f;
+        qv[r] = 0u;
+    }
+    const uint32_t fbu = (uint32_t)a.fb;
+    for (int64_t q = threadIdx.x; q < nq; q += nthr) {
+        const int64_t i = a.r0 + (int64_t)ROWS * q;
+        // lb[r]: first cell of row r's leaf in the tile, kSkip if outside it
+        uint32_t lb[ROWS];
+        if (a.L == 1 && !a.side) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) lb[r] = 0u;
+        } else if (leaf_vec) {
+            uint32_t w[ROWS / 2];
+#pragma unroll
+            for (int k = 0; k < ROWS / 8; ++k) {
+                const uint4 x = *reinterpret_cast<const uint4*>(a.leaf + i + 8 * k);
+                w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
+            }
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const uint32_t l = tile_slot(a, (w[r >> 1] >> (16 * (r & 1))) & 0xffffu, lmask);
+                lb[r] = l < ltn ? l * fbu : kSkip;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const uint32_t l = tile_slot(a, (uint32_t)a.leaf[i + r], lmask);
+                lb[r] = l < ltn ? l * fbu : kSkip;
+            }
+        }
+        if constexpr (KT == 1) load_grad<PREC, ROWS>(a, 0, i, vec, rmse, gv, hv, qv);
+        for (int j0 = 0; j0 < a.nf; j0 += 4) {
+            uint4 bb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                bb[u] = (j0 + u < a.nf) ? load_bins<ROWS>(a.bins[a.f0 + j0 + u], i)
+                                        : make_uint4(0u, 0u, 0u, 0u);
+            for (int c = 0; c < K; ++c) {
+                if constexpr (KT != 1) load_grad<PREC, ROWS>(a, c, i, vec, rmse, gv, hv, qv);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (j0 + u < a.nf) {
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r) {
+                            if (lb[r] != kSkip) {
+                                const uint32_t bin = min(byte_of(bb[u], r), Bm1);
+                                add_row<PREC, RM>(lds, ncells, lb[r] + (uint32_t)(j0 + u), B,
+                                                  bin, c, K, gv[r], hv[r], qv[r]);
+                            }
+                        }
                     }
                 }
             }
         }
     }
-    // rows of the chunk after the last full group of 4
-    const int64_t tail0 = a.r0 + 4 * ngroups;
+    // rows after the last full group (only in the last chunk)
+    const int64_t tail0 = a.r0 + (int64_t)ROWS * nq;
     if (threadIdx.x < a.r1 - tail0) {
         const int64_t i = tail0 + threadIdx.x;
-        const uint32_t l = ((a.L == 1 ? 0u : (uint32_t)a.leaf[i]) & lmask) - a.l0;
+        const uint32_t l = (a.L == 1 && !a.side) ? 0u - a.l0 : tile_slot(a, a.leaf[i], lmask);
         if (l < ltn) {
             for (int c = 0; c < K; ++c) {
                 const int64_t ci = int64_t(c) * a.n + i;
-                float gv = 0.f, hv = 1.f;
-                uint32_t qv = 0u;
+                float g1 = 0.f, h1 = 1.f;
+                uint32_t q1 = 0u;
                 if constexpr (PREC == CBH_PREC_INT16) {
-                    qv = a.gq[ci];
+                    q1 = a.gq[ci];
                 } else {
-                    gv = a.g[ci];
-                    if (!rmse) hv = a.h[ci];
+                    g1 = a.g[ci];
+                    if (!rmse) h1 = a.h[ci];
                 }
                 for (int j = 0; j < a.nf; ++j) {
                     const uint32_t bin = min((uint32_t)a.bins[a.f0 + j][i], Bm1);
-                    const uint32_t w = ((l * a.fb + j) * a.B + bin) * wpc;
-                    add_row<PREC>(lds, w, c, gv, hv, qv, rmse);
+                    add_row<PREC, RM>(lds, ncells, l * fbu + (uint32_t)j, B, bin, c, K, g1, h1,
+                                      q1);
                 }
             }
         }
     }
     __syncthreads();
+    // write the tile in the partial's [L][F][B][wpc] order (coalesced stores),
+    // converting to the output format: FP32 rounds each sum once, TWOFLOAT
+    // splits it into (hi, lo) floats, counts and INT16 sums are copied
+    const int wpc = a.wpc;
     const int row_words = a.B * wpc;
-    for (int idx = threadIdx.x; idx < tile_words; idx += blockDim.x) {
-        const int s = idx % row_words;
+    const int out_words = a.lt * a.nf * row_words;
+    const double* l64 = reinterpret_cast<const double*>(lds);
+    for (int idx = threadIdx.x; idx < out_words; idx += nthr) {
+        const int s = idx % wpc;
+        const int bin = (idx / wpc) % a.B;
         const int rest = idx / row_words;
-        const int j = rest % a.fb;
-        const int ll = rest / a.fb;
-        if (j < a.nf)
-            a.part[((int64_t)(a.l0 + ll) * a.F + (a.f0 + j)) * row_words + s] = lds[idx];
+        const int j = rest % a.nf;
+        const int ll = rest / a.nf;
+        const uint32_t cell = (uint32_t)(ll * a.fb + j);
+        uint32_t v;
+        if constexpr (PREC == CBH_PREC_INT16) {
+            v = lds[2 * ((cell * K + (s >> 1)) * a.B + bin) + (s & 1)];
+        } else if constexpr (PREC == CBH_PREC_FP32) {
+            // s = 2c (g) or 2c + 1 (h, or the count for RMSE)
+            if (rmse && (s & 1)) {
+                v = lds[2 * ncells * a.B + cell * a.B + bin];
+            } else if (rmse) {
+                v = __float_as_uint((float)l64[cell * a.B + bin]);
+            } else {
+                v = __float_as_uint((float)l64[((cell * K + (s >> 1)) * 2 + (s & 1)) * a.B + bin]);
+            }
+        } else {
+            // s = 4c + 2t + part: statistic t (0 g, 1 h), part 0 hi, 1 lo
+            const int t = (s >> 1) & 1, hi_lo = s & 1;
+            if (rmse && t == 1) {
+                v = hi_lo ? 0u : lds[2 * ncells * a.B + cell * a.B + bin];
+            } else {
+                const double d = rmse ? l64[cell * a.B + bin]
+                                      : l64[((cell * K + (s >> 2)) * 2 + t) * a.B + bin];
+                const float hi = (float)d;
+                v = __float_as_uint(hi_lo ? (float)(d - (double)hi) : hi);
+            }
+        }
+        a.part[((int64_t)(a.l0 + ll) * a.F + (a.f0 + j)) * row_words + bin * wpc + s] = v;
     }
 }
 

@@ -128,8 +128,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
             uint32_t before = run[d];
             for (int w = 0; w < wave; ++w) before += wcnt[w][d];
             const int64_t dst = gbase[d] + before + rank_w;
-            keys_out[dst] = key;
-            vals_out[dst] = val;
+            if (dst >= 0 && dst < n) {   // always true when the offsets are consistent
+                keys_out[dst] = key;
+                vals_out[dst] = val;
+            }
         }
         __syncthreads();
         run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
@@ -140,13 +142,20 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 __global__ void gather_keys_kernel(const int32_t* __restrict__ cat,
                                    const int32_t* __restrict__ perm, int64_t n,
-                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                   uint32_t* __restrict__ flags) {
+    bool bad = false;
     for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
          p += int64_t(gridDim.x) * blockDim.x) {
         int32_t r = perm[p];
+        if (r < 0 || r >= n) {   // not a permutation: report, and keep every access in bounds
+            bad = true;
+            r = 0;
+        }
         keys[p] = (uint32_t)cat[r];
         vals[p] = r;
     }
+    if (bad) atomicOr(flags, FLAG_BAD_INDEX);
 }
 
 // ---------------------------------------------------------- segmented scan
@@ -287,6 +296,7 @@ __global__ __launch_bounds__(256) void ts_scatter_kernel(
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * 256) {
         const int32_t r = rows[i];
+        if (r < 0 || r >= n) continue;
         const int64_t den = den_sorted[i];
         if (den_out) den_out[r] = (int32_t)den;
         if (!num_sorted) continue;
@@ -396,7 +406,7 @@ int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm
     };
 
     gather_keys_kernel<<<grid_for(n, 256, ctx->num_cus * 8), 256, 0, s>>>(cat, perm, n, keys[0],
-                                                                           vals[0]);
+                                                                           vals[0], ctx->d_flags);
     CBH_LAUNCHED();
     int cur = 0;
     for (int shift = 0; shift < 32; shift += 8) {

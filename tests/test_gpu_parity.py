@@ -306,7 +306,7 @@ def test_score_no_candidate(cb, ctx):
     cb.cbh_apply_split(ctx, p, 0, best)
     cb.cbh_sync(ctx)
     assert gu.split_of(best)[:2] == (-1, -1)
-    assert int(dev["leaf"].max().item()) == 0
+    assert int(dev["leaf"].cpu().numpy().max()) == 0
 
 
 # ---------------------------------------------------------------- apply/update

@@ -27,9 +27,9 @@ def cb():
     return cbhip
 
 
-def _booster(cb, p, prec):
+def _booster(cb, p, prec, subtract=None):
     from paper_1810_11363_amd.booster import GpuBooster
-    return GpuBooster.from_problem(p, precision=prec).prepare()
+    return GpuBooster.from_problem(p, precision=prec, subtract=subtract).prepare()
 
 
 def _check_prep(bst, p):
@@ -62,16 +62,16 @@ def _lockstep_tree(cb, bst, t, stats):
         hd = gq[..., 1].astype(np.float64) * sc[:, 1:2] if bst.loss != 0 else h32
     else:
         gd, hd = g32, h32
-    hist = bst.hist.data_ptr()
     for lvl in range(bst.depth):
         L = 1 << lvl
-        cb.cbh_build_histograms(ctx, pr, lvl, prec, hist)
+        bst.build_level_histograms(pr, lvl)      # subtraction at levels >= 1 if enabled
+        hist = bst.hist_ptr(lvl)
         cb.cbh_score_splits(ctx, pr, lvl, hist, prec, L2, bst.split_ptr(lvl))
         cb.cbh_sync(ctx)
         leaf = bst.leaf.cpu().numpy()
         if lvl == 0:
             leaf[:] = 0
-        got = gu.hist_to_f64(bst.hist, L, bst.F, B, K, prec, bst.loss == 0)
+        got = gu.hist_to_f64(bst.hists[lvl % 2], L, bst.F, B, K, prec, bst.loss == 0)
         if prec == 2:
             got_deq = got.astype(np.float64).copy()
             got_deq[..., 0::2] *= sc[:, 0]
@@ -99,8 +99,8 @@ def _lockstep_tree(cb, bst, t, stats):
             oracle.apply_split(bins[f], k, lvl, want_leaf)
         assert np.array_equal(bst.leaf.cpu().numpy(), want_leaf)
     a0 = bst.approx.cpu().numpy()
-    cb.cbh_update_approx(ctx, pr, hist, prec, bst.split_ptr(bst.depth - 1), bst.lr, L2,
-                         bst.leaf_values, bst.leaf_counts)
+    cb.cbh_update_approx(ctx, pr, bst.hist_ptr(bst.depth - 1), prec, bst.split_ptr(bst.depth - 1),
+                         bst.lr, L2, bst.leaf_values, bst.leaf_counts)
     cb.cbh_sync(ctx)
     leaf = bst.leaf.cpu().numpy()
     rv, rG, rH, rc = oracle.leaf_values(leaf, gd, hd, 1 << bst.depth, L2)
@@ -148,6 +148,46 @@ def test_lockstep_trees(cb, name, prec):
     for t in range(p.iterations):
         _lockstep_tree(cb, bst, t, stats)
     print(name, prec, stats)
+    bst.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_subtraction_matches_direct(cb, prec):
+    """Level histograms by subtraction equal the direct build: bit for bit for
+    int16 sums and counts, within two-float rounding for the compensated form,
+    within float rounding of the parent for plain float32."""
+    p = _shrink(datagen.make_c2(n=20011, s=1), iters=1)
+    bst = _booster(cb, p, prec, subtract=True)
+    bst.init_gradients()
+    pr = bst.probs[0]
+    if prec == 2:
+        cb.cbh_quantize_gradients(bst.ctx, pr)
+    direct = torch.empty_like(bst.hists[0])
+    g = bst.g.cpu().numpy().astype(np.float64)
+    for lvl in range(p.depth):
+        bst.build_level_histograms(pr, lvl)
+        cb.cbh_build_histograms(bst.ctx, pr, lvl, prec, direct)
+        cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), prec, bst.l2, bst.split_ptr(lvl))
+        cb.cbh_sync(bst.ctx)
+        L = 1 << lvl
+        a = gu.hist_to_f64(bst.hists[lvl % 2], L, bst.F, bst.B, 1, prec, True)
+        b = gu.hist_to_f64(direct, L, bst.F, bst.B, 1, prec, True)
+        assert np.array_equal(a[..., 1], b[..., 1])              # counts exact
+        if prec == 2:
+            assert np.array_equal(a, b)
+        else:
+            leaf = bst.leaf.cpu().numpy() if lvl else np.zeros(bst.n, np.uint16)
+            mag = oracle.histogram(bst.bins_host(0), np.abs(g), np.ones_like(g), leaf, L, bst.B)
+            if prec == 1:
+                assert gu.normalized_err(a[..., 0], b[..., 0], mag[..., 0]) <= 1e-9
+            else:
+                # float differences carry the rounding of every ancestor level:
+                # judge them against the bin's mass over all rows (level 0)
+                root = oracle.histogram(bst.bins_host(0), np.abs(g), np.ones_like(g),
+                                        np.zeros(bst.n, np.uint16), 1, bst.B)
+                err = np.abs(a[..., 0] - b[..., 0])
+                assert np.all(err <= 1e-5 * root[..., 0] + 1e-30)
+        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl))
     bst.close()
 
 
@@ -321,7 +361,7 @@ def test_full_size_c2_sampled(cb):
         want = oracle.histogram(bins[fs], g, h, leaf, L, bst.B)
         mag = oracle.histogram(bins[fs], np.abs(g), h, leaf, L, bst.B)
         assert gu.normalized_err(got[:, fs], want, mag) <= gu.FP32_TOL
-        assert np.array_equal(got[:, fs, :, 1], want[..., 1])
+        assert np.array_equal(got[:, fs][..., 1], want[..., 1])
         # totals of every feature equal the leaf totals (checks unsampled features)
         counts = got[..., 1].sum(axis=2)
         assert np.all(counts == counts[:, :1])
