@@ -349,12 +349,29 @@ void cbh_graph_destroy(cbh_graph* graph);
 
 /* ---- autotuning -------------------------------------------------------------- */
 
-/* Time the histogram kernel of `prob` over its launch parameters
- * (features per block, leaves per LDS tile, rows per block) at every level,
- * keep the fastest per (F, B, K, level, precision, row bucket), and save the
- * table as JSON at cache_path (may be NULL). Later calls of this context use
- * the table. Synchronizes the stream. */
-int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision,
+/* Launch knobs of the histogram planner for every later call of this context
+ * (overriding the autotune table); all must be > 0, or pass lds_budget = 0 to
+ * return to the defaults and the table.
+ *   lds_budget     LDS bytes per block
+ *   target_blocks  blocks aimed at per launch
+ *   min_rows       rows per block at least
+ *   partial_pct    partial tiles at most this % of the level's bin bytes
+ *   max_rep        LDS replicas per (leaf, feature) cell at most (power of two)
+ *   rep_target     replicas the planner reserves LDS for before adding features */
+int cbh_set_hist_knobs(cbh_ctx* ctx, int32_t lds_budget, int32_t target_blocks,
+                       int64_t min_rows, int32_t partial_pct, int32_t max_rep,
+                       int32_t rep_target);
+
+/* Tune the histogram launch plan of every level of `prob`: one tree is grown
+ * level by level from the problem's current gradients (prob->leaf is
+ * overwritten); at each level every distinct plan reachable from a grid of
+ * knobs (LDS bytes per block, blocks per launch, rows per block, partial-tile
+ * volume, LDS replicas per cell) is timed in the mode the tree will use —
+ * subtract != 0: levels >= 1 by cbh_build_histograms_sub — and the fastest is
+ * kept per (F, B, K, level, precision, floor(log2 n), mode). The table is
+ * saved as JSON at cache_path (may be NULL); later calls of this context use
+ * it. Synchronizes the stream. */
+int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32_t subtract,
                  const char* cache_path, void* stream);
 /* Load a table written by cbh_autotune. */
 int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path);

@@ -31,7 +31,7 @@ EXPORTS = [
     "cbh_score_splits", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
     "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
-    "cbh_autotune", "cbh_autotune_load",
+    "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
 ]
 
 
@@ -92,8 +92,9 @@ def _load():
         "cbh_graph_capture_iteration": ([vp, vp, dbl, dbl, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_launch": ([vp, vp], C.c_int),
         "cbh_graph_destroy": ([vp], None),
-        "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, C.c_char_p, vp], C.c_int),
+        "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, i32, C.c_char_p, vp], C.c_int),
         "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
+        "cbh_set_hist_knobs": ([vp, i32, i32, i64, i32, i32, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -280,10 +281,17 @@ def cbh_graph_destroy(graph):
     _lib.cbh_graph_destroy(graph)
 
 
-def cbh_autotune(ctx, prob: cbh_problem, precision: int, cache_path=None, stream=None):
-    return _check(_lib.cbh_autotune(ctx, C.byref(prob), precision,
+def cbh_autotune(ctx, prob: cbh_problem, precision: int, subtract: bool = False,
+                 cache_path=None, stream=None):
+    return _check(_lib.cbh_autotune(ctx, C.byref(prob), precision, int(bool(subtract)),
                                     cache_path.encode() if cache_path else None,
                                     _stream(stream)))
+
+
+def cbh_set_hist_knobs(ctx, lds_budget=0, target_blocks=512, min_rows=32768, partial_pct=25,
+                       max_rep=32, rep_target=32):
+    return _check(_lib.cbh_set_hist_knobs(ctx, lds_budget, target_blocks, min_rows,
+                                          partial_pct, max_rep, rep_target))
 
 
 def cbh_autotune_load(ctx, cache_path: str):

@@ -1,12 +1,14 @@
 // Histogram launch autotuner.
 //
-// For every level of a problem it times the histogram build (main launch plus
-// the partial merge) for each distinct launch plan reachable from a grid of
-// knobs — LDS bytes per block (which bounds features per block and sets
-// leaves per LDS tile), the number of blocks aimed at, the least rows per
-// block and the cap on partial-tile volume (which set rows per block) — and
-// keeps the fastest. Results are keyed by (F, B, K, level, precision,
-// floor(log2 n)) and can be saved to and loaded from a small JSON file.
+// It walks one tree of a problem level by level. At every level it times the
+// histogram build (main launch plus the partial merge) in the mode the tree
+// uses (direct, or by subtraction from the previous level) for each distinct
+// launch plan reachable from a grid of knobs — LDS bytes per block, the
+// number of blocks aimed at, the least rows per block, the cap on partial-tile
+// volume and the LDS replicas per cell — keeps the fastest, then builds that
+// level with it, scores it and applies the split so the next level sees real
+// leaves. Results are keyed by (F, B, K, level, precision, floor(log2 n),
+// mode) and can be saved to and loaded from a small JSON file.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -38,11 +40,13 @@ static int save_table(const cbh_ctx* ctx, const char* path) {
         const HistKnobs& v = kv.second;
         fprintf(f,
                 "  {\"F\": %d, \"B\": %d, \"K\": %d, \"level\": %d, \"precision\": %d, "
+                "\"sub\": %d, "
                 "\"log2n\": %d, \"lds_budget\": %d, \"max_fb\": %d, \"target_blocks\": %d, "
-                "\"min_rows\": %lld, \"partial_pct\": %d}%s\n",
+                "\"min_rows\": %lld, \"partial_pct\": %d, \"max_rep\": %d, "
+                "\"rep_target\": %d}%s\n",
                 std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
-                std::get<5>(k), v.lds_budget, v.max_fb, v.target_blocks, (long long)v.min_rows,
-                v.partial_pct, ++i < ctx->tuned.size() ? "," : "");
+                std::get<6>(k), std::get<5>(k), v.lds_budget, v.max_fb, v.target_blocks, (long long)v.min_rows,
+                v.partial_pct, v.max_rep, v.rep_target, ++i < ctx->tuned.size() ? "," : "");
     }
     fprintf(f, "]\n");
     fclose(f);
@@ -54,6 +58,30 @@ static int save_table(const cbh_ctx* ctx, const char* path) {
 using namespace cbh;
 
 extern "C" {
+
+int cbh_set_hist_knobs(cbh_ctx* ctx, int32_t lds_budget, int32_t target_blocks,
+                       int64_t min_rows, int32_t partial_pct, int32_t max_rep,
+                       int32_t rep_target) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    if (lds_budget == 0) {
+        ctx->force_knobs = false;
+        return CBH_OK;
+    }
+    CBH_ARG(lds_budget > 0 && target_blocks > 0 && min_rows > 0 && partial_pct > 0 &&
+                max_rep > 0 && rep_target > 0 && (max_rep & (max_rep - 1)) == 0,
+            "knobs must be > 0 and max_rep a power of two");
+    HistKnobs kn;
+    kn.lds_budget = lds_budget;
+    kn.target_blocks = target_blocks;
+    kn.min_rows = min_rows;
+    kn.partial_pct = partial_pct;
+    kn.max_rep = max_rep;
+    kn.rep_target = rep_target;
+    ctx->forced = kn;
+    ctx->force_knobs = true;
+    return CBH_OK;
+}
 
 int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path) {
     clear_error();
@@ -71,7 +99,7 @@ int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path) {
         const size_t end = text.find('}', pos);
         CBH_ARG(end != std::string::npos, "malformed autotune file");
         const std::string obj = text.substr(pos, end - pos + 1);
-        long long F, B, K, lvl, prec, l2n, lds, fb, tb, mr, pp;
+        long long F, B, K, lvl, prec, l2n, lds, fb, tb, mr, pp, mrep = 32, rtg = 32, sub = 0;
         CBH_ARG(parse_field(obj, "F", &F) && parse_field(obj, "B", &B) &&
                     parse_field(obj, "K", &K) && parse_field(obj, "level", &lvl) &&
                     parse_field(obj, "precision", &prec) && parse_field(obj, "log2n", &l2n) &&
@@ -79,23 +107,29 @@ int cbh_autotune_load(cbh_ctx* ctx, const char* cache_path) {
                     parse_field(obj, "target_blocks", &tb) && parse_field(obj, "min_rows", &mr) &&
                     parse_field(obj, "partial_pct", &pp),
                 "malformed autotune entry");
-        CBH_ARG(lds > 0 && fb > 0 && tb > 0 && mr > 0 && pp > 0, "bad autotune values");
+        parse_field(obj, "max_rep", &mrep);      // optional
+        parse_field(obj, "rep_target", &rtg);    // optional
+        parse_field(obj, "sub", &sub);           // optional
+        CBH_ARG(lds > 0 && fb > 0 && tb > 0 && mr > 0 && pp > 0 && mrep > 0,
+                "bad autotune values");
         HistKnobs kn;
         kn.lds_budget = (int32_t)lds;
         kn.max_fb = (int32_t)fb;
         kn.target_blocks = (int32_t)tb;
         kn.min_rows = mr;
         kn.partial_pct = (int32_t)pp;
+        kn.max_rep = (int32_t)mrep;
+        kn.rep_target = (int32_t)std::max<long long>(1, rtg);
         ctx->tuned[TuneKey{(int32_t)F, (int32_t)B, (int32_t)K, (int32_t)lvl, (int32_t)prec,
-                           (int32_t)l2n}] = kn;
+                           (int32_t)l2n, (int32_t)(sub != 0)}] = kn;
         ++loaded;
         pos = end + 1;
     }
     return CBH_OK;
 }
 
-int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const char* cache_path,
-                 void* stream) {
+int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32_t subtract,
+                 const char* cache_path, void* stream) {
     clear_error();
     CBH_ARG(ctx != nullptr, "ctx is NULL");
     int rc = validate_problem(prob);
@@ -104,52 +138,74 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int F = prob->n_features, B = prob->max_bins, K = prob->K;
+    const int rmse = prob->loss == CBH_LOSS_RMSE;
     std::vector<int32_t> budgets;
-    for (int32_t v : {16 * 1024, 32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, 160 * 1024})
+    for (int32_t v : {32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, 160 * 1024})
         if (v <= ctx->max_lds) budgets.push_back(v);
     const int32_t targets[] = {256, 512, 1024};
     const int64_t min_rows[] = {16384, 32768, 65536};
     const int32_t pcts[] = {12, 25, 50};
-    CBH_REQUIRE(tile_lds_bytes(precision, prob->loss == CBH_LOSS_RMSE, K, B, 1) <= ctx->max_lds,
-                CBH_EUNSUPPORTED, "leaf row does not fit in LDS");
+    const int32_t reps[] = {1, 8, 32};
+    CBH_REQUIRE(tile_lds_bytes(precision, rmse, K, B, 1) <= ctx->max_lds, CBH_EUNSUPPORTED,
+                "leaf row does not fit in LDS");
     const int64_t hist_bytes =
         hist_elems(1 << (prob->depth - 1), F, B, K) * hist_elem_bytes(precision);
-    void* hist = nullptr;
-    CBH_HIP(hipMalloc(&hist, (size_t)std::max<int64_t>(hist_bytes, 256)));
+    // two level histograms (current, parent), the split of every level, parent sides
+    void* hbuf[2] = {nullptr, nullptr};
+    cbh_split* splits = nullptr;
+    uint8_t* side = nullptr;
+    const int64_t max_half = int64_t(1) << std::max(0, prob->depth - 2);
+    CBH_HIP(hipMalloc(&hbuf[0], (size_t)std::max<int64_t>(hist_bytes, 256)));
+    CBH_HIP(hipMalloc(&hbuf[1], (size_t)std::max<int64_t>(hist_bytes, 256)));
+    CBH_HIP(hipMalloc((void**)&splits, sizeof(cbh_split) * prob->depth));
+    CBH_HIP(hipMalloc((void**)&side, (size_t)std::max<int64_t>(max_half, 256)));
     hipEvent_t e0, e1;
     CBH_HIP(hipEventCreate(&e0));
     CBH_HIP(hipEventCreate(&e1));
     int32_t nb = 0;
     while ((int64_t(1) << (nb + 1)) <= prob->n) ++nb;
     for (int level = 0; level < prob->depth && rc == CBH_OK; ++level) {
-        const int L = 1 << level;
-        std::set<std::tuple<int, int, int64_t>> seen;
+        const int sub = (subtract && level > 0) ? 1 : 0;
+        const int L = sub ? 1 << (level - 1) : 1 << level;
+        void* out = hbuf[level & 1];
+        const void* parent = sub ? hbuf[(level - 1) & 1] : nullptr;
+        if (sub) {
+            rc = launch_side(parent, splits + level - 1, L, F, B, K, rmse, precision, side, s);
+            if (rc) break;
+        }
+        std::set<std::tuple<int, int, int64_t, int>> seen;
         float best_ms = 1e30f;
         HistKnobs best_kn = ctx->knobs;
         for (size_t ib = 0; ib < budgets.size() && rc == CBH_OK; ++ib)
             for (int32_t tb : targets)
                 for (int64_t mr : min_rows)
-                for (int32_t pp : pcts) {
+                for (int32_t pp : pcts)
+                for (int32_t mrp : reps) {
                     if (rc != CBH_OK) break;
                     HistKnobs kn = ctx->knobs;
                     kn.lds_budget = budgets[ib];
                     kn.target_blocks = tb;
                     kn.min_rows = mr;
                     kn.partial_pct = pp;
-                    const HistPlan plan = plan_hist(kn, prob->n, F, B, K, L, precision,
-                                                    prob->loss == CBH_LOSS_RMSE, ctx->max_lds);
-                    if (!seen.insert({plan.fb, plan.lt, plan.rows_per_chunk}).second) continue;
+                    kn.max_rep = mrp;
+                    kn.rep_target = mrp;
+                    const HistPlan plan = plan_hist(kn, prob->n, F, B, K, L, precision, rmse,
+                                                    ctx->max_lds);
+                    if (!seen.insert({plan.fb, plan.lt, plan.rows_per_chunk, plan.rep}).second)
+                        continue;
                     const int64_t part = int64_t(plan.n_chunks) * L * F * B *
                                          plan.words_per_cell * 4;
                     if (part > ctx->ws_limit / 2) continue;
                     rc = ensure_ws(ctx, part);
                     if (rc) break;
                     // warm-up, then the mean of 3 timed runs
-                    rc = launch_hist(ctx, prob, level, precision, plan, hist, ctx->ws, s);
+                    rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
+                                     sub ? side : nullptr);
                     if (rc) break;
                     (void)hipEventRecord(e0, s);
                     for (int r = 0; r < 3 && !rc; ++r)
-                        rc = launch_hist(ctx, prob, level, precision, plan, hist, ctx->ws, s);
+                        rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s,
+                                         parent, sub ? side : nullptr);
                     (void)hipEventRecord(e1, s);
                     if (rc) break;
                     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -164,12 +220,26 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, const
                         best_kn = kn;
                     }
                 }
-        if (rc == CBH_OK) ctx->tuned[TuneKey{F, B, K, level, precision, nb}] = best_kn;
+        if (rc) break;
+        ctx->tuned[TuneKey{F, B, K, level, precision, nb, sub}] = best_kn;
+        // build this level with the chosen plan, score it and apply its split
+        const HistPlan plan = plan_hist(best_kn, prob->n, F, B, K, L, precision, rmse,
+                                        ctx->max_lds);
+        rc = ensure_ws(ctx, int64_t(plan.n_chunks) * L * F * B * plan.words_per_cell * 4 +
+                                score_scratch_bytes(prob) + 256);
+        if (!rc) rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
+                                  sub ? side : nullptr);
+        if (!rc) rc = launch_score(ctx, prob, level, out, precision, 1.0, splits + level, nullptr,
+                                   ctx->ws, s);
+        if (!rc) rc = launch_apply(ctx, prob, level, splits + level, s);
     }
+    (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(hist);
+    (void)hipFree(hbuf[0]);
+    (void)hipFree(hbuf[1]);
+    (void)hipFree(splits);
+    (void)hipFree(side);
     if (rc) return rc;
     if (cache_path) return save_table(ctx, cache_path);
     return CBH_OK;

@@ -55,7 +55,7 @@ struct LevelPlan {
     int64_t n_tiles = 0;
     DevTile* d_tiles = nullptr;        // device work list
     struct DevHP {
-        int32_t fb, lt, n_fgroups, n_ltiles, n_chunks, wpc;
+        int32_t fb, lt, n_fgroups, n_ltiles, n_chunks, wpc, rep, pad;
         int64_t rows_per_chunk, lds_bytes;
     }* d_plans = nullptr;              // per problem
     int64_t max_lds = 0;
@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __re
     t.l0 = (uint32_t)tile.lt_i * hp.lt;
     t.side = nullptr;
     t.sub_shift = 0;
+    t.rep = hp.rep;
     hist_tile<PREC, 0, RM>(t, lds);
 }
 
@@ -337,7 +338,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         for (int p = 0; p < P; ++p) {
             const cbh_problem& pr = probs[p];
             const HistKnobs kn =
-                knobs_for(ctx, pr.n_features, pr.max_bins, pr.K, lvl, precision, pr.n);
+                knobs_for(ctx, pr.n_features, pr.max_bins, pr.K, lvl, precision, pr.n, 0);
             // in a batch the problems share the chip: aim at a share of the blocks
             HistKnobs kb = kn;
             kb.target_blocks = std::max<int32_t>(
@@ -355,7 +356,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                     for (int lt = 0; lt < hp.n_ltiles; ++lt)
                         tiles.push_back(DevTile{p, fg, lt, ch});
             dplans.push_back(LevelPlan::DevHP{hp.fb, hp.lt, hp.n_fgroups, hp.n_ltiles,
-                                              hp.n_chunks, hp.words_per_cell,
+                                              hp.n_chunks, hp.words_per_cell, hp.rep, 0,
                                               hp.rows_per_chunk, hp.lds_bytes});
             cell_off.push_back(cell_off.back() + int64_t(L) * pr.n_features * pr.max_bins);
             feat_off.push_back(feat_off.back() + pr.n_features);

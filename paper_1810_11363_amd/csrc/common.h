@@ -62,7 +62,8 @@ struct HistPlan {
     int32_t n_ltiles = 1;
     int32_t n_chunks = 1;
     int64_t rows_per_chunk = 0;  // multiple of 16
-    int32_t words_per_cell = 2;  // 32-bit LDS words per (leaf, feature, bin)
+    int32_t words_per_cell = 2;  // 32-bit output words per (leaf, feature, bin)
+    int32_t rep = 1;             // LDS replicas per (leaf, feature) cell
     int64_t lds_bytes = 0;
     int64_t n_blocks = 0;    // n_chunks * n_fgroups * n_ltiles
 };
@@ -78,9 +79,12 @@ struct HistKnobs {
     int32_t target_blocks = 512;     // blocks aimed at per launch
     int64_t min_rows = 32768;        // rows per block at least (2 steps of 16 rows/thread)
     int32_t partial_pct = 25;        // partial tiles at most this % of the bin bytes
+    int32_t max_rep = 32;            // LDS replicas per cell at most
+    int32_t rep_target = 32;         // replicas the planner reserves LDS for first
 };
 
-using TuneKey = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
+// (F, B, K, level, precision, floor(log2 n), subtraction mode)
+using TuneKey = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
 
 }  // namespace cbh
 
@@ -108,7 +112,12 @@ inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 // Histogram planning (histogram.hip).
 int words_per_cell(int32_t precision, int32_t K);
 HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t level,
-                    int32_t precision, int64_t n);
+                    int32_t precision, int64_t n, int32_t sub);
+int launch_side(const void* parent_hist, const cbh_split* parent_split, int64_t half, int32_t F,
+                int32_t B, int32_t K, int32_t rmse, int32_t precision, uint8_t* side,
+                hipStream_t s);
+int launch_apply(const cbh_ctx* ctx, const cbh_problem* p, int32_t level, const cbh_split* best,
+                 hipStream_t s);
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                    int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds);
 int64_t hist_elems(int32_t n_leaves, int32_t F, int32_t B, int32_t K);

@@ -46,11 +46,11 @@ int64_t hist_elem_bytes(int32_t precision) {
 }
 
 HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t level,
-                    int32_t precision, int64_t n) {
+                    int32_t precision, int64_t n, int32_t sub) {
     if (ctx->force_knobs) return ctx->forced;
     int32_t nb = 0;
     while ((int64_t(1) << (nb + 1)) <= n) ++nb;
-    auto it = ctx->tuned.find(TuneKey{F, B, K, level, precision, nb});
+    auto it = ctx->tuned.find(TuneKey{F, B, K, level, precision, nb, sub});
     if (it != ctx->tuned.end()) return it->second;
     return ctx->knobs;
 }
@@ -74,7 +74,10 @@ HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t
     int64_t fb_max;
     if (int64_t(n_leaves) * cell_bytes <= budget) {
         p.lt = n_leaves;
-        fb_max = budget / (int64_t(n_leaves) * cell_bytes);
+        // reserve room for rep_target replicas of every cell where possible
+        int64_t want = std::max<int32_t>(1, std::min(kn.rep_target, kn.max_rep));
+        while (want > 1 && int64_t(n_leaves) * cell_bytes * want > budget) want /= 2;
+        fb_max = budget / (int64_t(n_leaves) * cell_bytes * want);
     } else {
         int32_t lt = 1;
         while (int64_t(lt) * 2 * cell_bytes <= budget && lt * 2 <= n_leaves) lt *= 2;
@@ -101,7 +104,13 @@ HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t
     groups = std::min<int64_t>(groups, F);
     p.fb = (int32_t)((F + groups - 1) / groups);
     p.n_fgroups = (F + p.fb - 1) / p.fb;
-    p.lds_bytes = int64_t(p.lt) * p.fb * cell_bytes;
+    // spare LDS goes to replicas of every cell
+    const int64_t cells = int64_t(p.lt) * p.fb;
+    p.rep = 1;
+    while (p.rep * 2 <= kn.max_rep &&
+           tile_lds_bytes(precision, rmse, K, B, cells * p.rep * 2) <= budget)
+        p.rep *= 2;
+    p.lds_bytes = tile_lds_bytes(precision, rmse, K, B, cells * p.rep);
     p.n_blocks = int64_t(p.n_chunks) * p.n_fgroups * p.n_ltiles;
     return p;
 }
@@ -122,6 +131,7 @@ struct HistArgs {
     int32_t rmse;
     const uint8_t* side;    // subtraction mode (see TileArgs), else NULL
     uint32_t sub_shift;
+    int32_t rep;
 };
 
 template <int PREC, int KT, int RM>
@@ -159,6 +169,7 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(HistArgs a) {
     t.l0 = (uint32_t)lt_i * a.lt;
     t.side = a.side;
     t.sub_shift = a.sub_shift;
+    t.rep = a.rep;
     hist_tile<PREC, KT, RM>(t, lds);
 }
 
@@ -328,15 +339,17 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
                                                        int64_t half, int32_t F, int32_t B,
                                                        int32_t K, int32_t rmse,
                                                        uint8_t* __restrict__ side) {
-    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // one wave per parent leaf, lanes over bins
+    const int64_t p = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (p >= half) return;
     const int f = split->feature, k = split->border;
     if (f < 0 || f >= F) {
-        side[p] = 1;
+        if (lane == 0) side[p] = 1;
         return;
     }
     double left = 0.0, right = 0.0;
-    for (int b = 0; b < B; ++b) {
+    for (int b = lane; b < B; b += 64) {
         const int64_t e = ((p * F + f) * B + b) * 2 * K + 1;   // statistic 1 of class 0
         double v;
         if constexpr (PREC == CBH_PREC_FP32)
@@ -349,7 +362,11 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
             v = (double)reinterpret_cast<const int64_t*>(parent)[e];
         if (b <= k) left += v; else right += v;
     }
-    side[p] = right < left ? 1 : 0;
+    for (int d = 32; d >= 1; d >>= 1) {
+        left += __shfl_xor(left, d, 64);
+        right += __shfl_xor(right, d, 64);
+    }
+    if (lane == 0) side[p] = right < left ? 1 : 0;
 }
 
 void hist_init_attrs(int max_lds) {
@@ -406,6 +423,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     a.n_ltiles = plan.n_ltiles;
     a.wpc = plan.words_per_cell;
     a.rmse = p->loss == CBH_LOSS_RMSE;
+    a.rep = plan.rep;
     switch (precision) {
         case CBH_PREC_FP32: launch_hist_prec<CBH_PREC_FP32>(a, plan, ctx->max_lds, s); break;
         case CBH_PREC_TWOFLOAT:
@@ -430,6 +448,28 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
         default:
             hist_reduce_kernel<CBH_PREC_INT16><<<grid, 256, 0, s>>>(
                 (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out, sub);
+            break;
+    }
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int launch_side(const void* parent_hist, const cbh_split* parent_split, int64_t half, int32_t F,
+                int32_t B, int32_t K, int32_t rmse, int32_t precision, uint8_t* side,
+                hipStream_t s) {
+    const unsigned gs = (unsigned)((half + 3) / 4);
+    switch (precision) {
+        case CBH_PREC_FP32:
+            sub_side_kernel<CBH_PREC_FP32><<<gs, 256, 0, s>>>(parent_hist, parent_split, half, F,
+                                                              B, K, rmse, side);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            sub_side_kernel<CBH_PREC_TWOFLOAT><<<gs, 256, 0, s>>>(parent_hist, parent_split,
+                                                                  half, F, B, K, rmse, side);
+            break;
+        default:
+            sub_side_kernel<CBH_PREC_INT16><<<gs, 256, 0, s>>>(parent_hist, parent_split, half,
+                                                               F, B, K, rmse, side);
             break;
     }
     CBH_LAUNCHED();
@@ -539,7 +579,7 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
     CBH_ARG(hist_out != nullptr, "hist_out is NULL");
     const int L = 1 << level;
     const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
-                                   precision, prob->n);
+                                   precision, prob->n, 0);
     const int rmse = prob->loss == CBH_LOSS_RMSE;
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, L,
                                     precision, rmse, ctx->max_lds);
@@ -568,7 +608,7 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
     CBH_ARG(parent_hist != hist_out, "parent_hist and hist_out must not be the same buffer");
     const int half = 1 << (level - 1);
     const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
-                                   precision, prob->n);
+                                   precision, prob->n, 1);
     const int rmse = prob->loss == CBH_LOSS_RMSE;
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, half,
                                     precision, rmse, ctx->max_lds);
@@ -582,25 +622,9 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
     if (rc) return rc;
     uint8_t* side = (uint8_t*)ctx->ws + part_bytes;
     hipStream_t s = (hipStream_t)stream;
-    const unsigned gs = (unsigned)((half + 255) / 256);
-    switch (precision) {
-        case CBH_PREC_FP32:
-            sub_side_kernel<CBH_PREC_FP32><<<gs, 256, 0, s>>>(parent_hist, parent_split, half,
-                                                              prob->n_features, prob->max_bins,
-                                                              prob->K, rmse, side);
-            break;
-        case CBH_PREC_TWOFLOAT:
-            sub_side_kernel<CBH_PREC_TWOFLOAT><<<gs, 256, 0, s>>>(
-                parent_hist, parent_split, half, prob->n_features, prob->max_bins, prob->K, rmse,
-                side);
-            break;
-        default:
-            sub_side_kernel<CBH_PREC_INT16><<<gs, 256, 0, s>>>(parent_hist, parent_split, half,
-                                                               prob->n_features, prob->max_bins,
-                                                               prob->K, rmse, side);
-            break;
-    }
-    CBH_LAUNCHED();
+    rc = launch_side(parent_hist, parent_split, half, prob->n_features, prob->max_bins, prob->K,
+                     rmse, precision, side, s);
+    if (rc) return rc;
     return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side);
 }
 

@@ -48,6 +48,10 @@ struct TileArgs {
     // the child whose bit `sub_shift` equals side[p] are accumulated.
     const uint8_t* side = nullptr;
     uint32_t sub_shift = 0;
+    // LDS replicas per cell (power of two): lane l updates replica l % rep, so
+    // lanes of a wave that hit the same bin of the same cell mostly update
+    // different words; the flush adds the replicas.
+    int32_t rep = 1;
 };
 
 // Tile leaf slot of a row with leaf value v (>= lt: not in this tile).
@@ -60,18 +64,33 @@ __device__ __forceinline__ uint32_t tile_slot(const TileArgs& a, uint32_t v, uin
     return (v & lmask) - a.l0;
 }
 
-// LDS bytes of a tile of `cells` cells.
+// Bins per cell row in LDS: padded to an odd count so that consecutive cells
+// (and replicas) start in different banks.
+__host__ __device__ inline int32_t lds_stride(int32_t B) { return B | 1; }
+
+// LDS bytes of a tile of `cells` cells (replicas counted as cells).
 __host__ __device__ inline int64_t tile_lds_bytes(int precision, int rmse, int K, int B,
                                                   int64_t cells) {
-    if (precision == CBH_PREC_INT16) return cells * K * B * 8;
-    if (rmse) return cells * B * 12;
-    return cells * K * 2 * B * 8;
+    const int64_t Bs = lds_stride(B);
+    if (precision == CBH_PREC_INT16) return cells * K * Bs * 8;
+    if (rmse) return cells * Bs * 12;
+    return cells * K * 2 * Bs * 8;
 }
 
+// LDS element of (plane row, bin, replica): replicas innermost, so the lanes
+// of a half-wave (replica = lane % rep with rep = 32) fall in distinct banks.
+__device__ __forceinline__ uint32_t lds_elem(uint32_t plane_row, uint32_t Bs, uint32_t bin,
+                                             uint32_t rep, uint32_t replica) {
+    return (plane_row * Bs + bin) * rep + replica;
+}
+
+// Add one row's statistics of class c to (cell, bin). Plane rows:
+//   INT16: cell * K + c (u64); FP RMSE: cell (f64) and, after all f64 planes,
+//   cell (u32 count); FP otherwise: (cell * K + c) * 2 + t (f64, t = 0 g, 1 h).
 template <int PREC, int RM>
 __device__ __forceinline__ void add_row(uint32_t* lds, uint32_t ncells, uint32_t cell,
-                                        uint32_t B, uint32_t bin, int c, int K, float gv,
-                                        float hv, uint32_t qv) {
+                                        uint32_t Bs, uint32_t bin, int c, int K, uint32_t rep,
+                                        uint32_t replica, float gv, float hv, uint32_t qv) {
     if constexpr (PREC == CBH_PREC_INT16) {
         // (g code << 32) + h code: with <= 65536 rows per tile neither half
         // overflows, so one 64-bit LDS add updates both sums exactly.
@@ -79,21 +98,23 @@ __device__ __forceinline__ void add_row(uint32_t* lds, uint32_t ncells, uint32_t
         const uint64_t hcode = (qv >> 16) & 0x7fffu;
         const uint64_t packed = ((uint64_t)gcode << 32) + hcode;
         unsigned long long* l64 = reinterpret_cast<unsigned long long*>(lds);
-        __hip_atomic_fetch_add(l64 + (cell * K + c) * B + bin, (unsigned long long)packed,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(l64 + lds_elem(cell * K + c, Bs, bin, rep, replica),
+                               (unsigned long long)packed, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
         double* l64 = reinterpret_cast<double*>(lds);
         if constexpr (RM != 0) {
-            __hip_atomic_fetch_add(l64 + cell * B + bin, (double)gv, __ATOMIC_RELAXED,
+            const uint32_t e = lds_elem(cell, Bs, bin, rep, replica);
+            __hip_atomic_fetch_add(l64 + e, (double)gv, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(lds + 2 * ncells * B + cell * B + bin, 1u, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(lds + 2 * ncells * Bs * rep + e, 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
-            const uint32_t d = ((cell * K + c) * 2) * B + bin;
-            __hip_atomic_fetch_add(l64 + d, (double)gv, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(l64 + d + B, (double)hv, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t pr = (cell * K + c) * 2;
+            __hip_atomic_fetch_add(l64 + lds_elem(pr, Bs, bin, rep, replica), (double)gv,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(l64 + lds_elem(pr + 1, Bs, bin, rep, replica), (double)hv,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
 }
@@ -177,9 +198,11 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
     const uint32_t lmask = (uint32_t)a.L - 1u;
     const uint32_t ltn = (uint32_t)a.lt;
     const uint32_t B = (uint32_t)a.B;
+    const uint32_t Bs = (uint32_t)lds_stride(a.B);
     const uint32_t Bm1 = B - 1u;
+    const uint32_t rep = (uint32_t)a.rep;
     const uint32_t ncells = (uint32_t)(a.lt * a.fb);
-    const int tile_words = (int)(tile_lds_bytes(PREC, RM, K, a.B, ncells) / 4);
+    const int tile_words = (int)(tile_lds_bytes(PREC, RM, K, a.B, ncells * rep) / 4);
     for (int i = threadIdx.x; i < tile_words; i += nthr) lds[i] = 0u;
     __syncthreads();
     constexpr bool rmse = RM != 0;
@@ -197,7 +220,8 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
         hv[r] = 1.f;
         qv[r] = 0u;
     }
-    const uint32_t fbu = (uint32_t)a.fb;
+    const uint32_t fbu = (uint32_t)a.fb;            // cells per tile leaf
+    const uint32_t replica = (uint32_t)threadIdx.x & (rep - 1u);
     for (int64_t q = threadIdx.x; q < nq; q += nthr) {
         const int64_t i = a.r0 + (int64_t)ROWS * q;
         // lb[r]: first cell of row r's leaf in the tile, kSkip if outside it
@@ -240,8 +264,8 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
                         for (int r = 0; r < ROWS; ++r) {
                             if (lb[r] != kSkip) {
                                 const uint32_t bin = min(byte_of(bb[u], r), Bm1);
-                                add_row<PREC, RM>(lds, ncells, lb[r] + (uint32_t)(j0 + u), B,
-                                                  bin, c, K, gv[r], hv[r], qv[r]);
+                                add_row<PREC, RM>(lds, ncells, lb[r] + (uint32_t)(j0 + u), Bs,
+                                                  bin, c, K, rep, replica, gv[r], hv[r], qv[r]);
                             }
                         }
                     }
@@ -267,8 +291,8 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
                 }
                 for (int j = 0; j < a.nf; ++j) {
                     const uint32_t bin = min((uint32_t)a.bins[a.f0 + j][i], Bm1);
-                    add_row<PREC, RM>(lds, ncells, l * fbu + (uint32_t)j, B, bin, c, K, g1, h1,
-                                      q1);
+                    add_row<PREC, RM>(lds, ncells, l * fbu + (uint32_t)j, Bs, bin, c, K, rep,
+                                      replica, g1, h1, q1);
                 }
             }
         }
@@ -281,6 +305,8 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
     const int row_words = a.B * wpc;
     const int out_words = a.lt * a.nf * row_words;
     const double* l64 = reinterpret_cast<const double*>(lds);
+    const uint64_t* u64 = reinterpret_cast<const uint64_t*>(lds);
+    const uint32_t* cnt = lds + 2 * ncells * Bs * rep;      // RMSE count planes
     for (int idx = threadIdx.x; idx < out_words; idx += nthr) {
         const int s = idx % wpc;
         const int bin = (idx / wpc) % a.B;
@@ -290,24 +316,26 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
         const uint32_t cell = (uint32_t)(ll * a.fb + j);
         uint32_t v;
         if constexpr (PREC == CBH_PREC_INT16) {
-            v = lds[2 * ((cell * K + (s >> 1)) * a.B + bin) + (s & 1)];
-        } else if constexpr (PREC == CBH_PREC_FP32) {
-            // s = 2c (g) or 2c + 1 (h, or the count for RMSE)
-            if (rmse && (s & 1)) {
-                v = lds[2 * ncells * a.B + cell * a.B + bin];
-            } else if (rmse) {
-                v = __float_as_uint((float)l64[cell * a.B + bin]);
-            } else {
-                v = __float_as_uint((float)l64[((cell * K + (s >> 1)) * 2 + (s & 1)) * a.B + bin]);
-            }
+            // the two 32-bit halves of the packed sum, replicas added as u64
+            const uint32_t e0 = lds_elem(cell * K + (s >> 1), Bs, bin, rep, 0);
+            uint64_t t = 0;
+            for (uint32_t rp = 0; rp < rep; ++rp) t += u64[e0 + rp];
+            v = (s & 1) ? (uint32_t)(t >> 32) : (uint32_t)t;
         } else {
-            // s = 4c + 2t + part: statistic t (0 g, 1 h), part 0 hi, 1 lo
-            const int t = (s >> 1) & 1, hi_lo = s & 1;
+            // statistic t (0 g, 1 h or count) of class c; TWOFLOAT has (hi, lo) parts
+            const int c = PREC == CBH_PREC_FP32 ? (s >> 1) : (s >> 2);
+            const int t = PREC == CBH_PREC_FP32 ? (s & 1) : ((s >> 1) & 1);
+            const int hi_lo = PREC == CBH_PREC_FP32 ? 0 : (s & 1);
             if (rmse && t == 1) {
-                v = hi_lo ? 0u : lds[2 * ncells * a.B + cell * a.B + bin];
+                const uint32_t e0 = lds_elem(cell, Bs, bin, rep, 0);
+                uint32_t tc = 0;
+                for (uint32_t rp = 0; rp < rep; ++rp) tc += cnt[e0 + rp];
+                v = hi_lo ? 0u : tc;
             } else {
-                const double d = rmse ? l64[cell * a.B + bin]
-                                      : l64[((cell * K + (s >> 2)) * 2 + t) * a.B + bin];
+                const uint32_t e0 = rmse ? lds_elem(cell, Bs, bin, rep, 0)
+                                         : lds_elem((cell * K + c) * 2 + t, Bs, bin, rep, 0);
+                double d = 0.0;
+                for (uint32_t rp = 0; rp < rep; ++rp) d += l64[e0 + rp];
                 const float hi = (float)d;
                 v = __float_as_uint(hi_lo ? (float)(d - (double)hi) : hi);
             }

@@ -68,9 +68,12 @@ struct SolveArgs {
     double l2;
 };
 
+// One wave per (final leaf, class); lanes sum the bins of the chosen side in
+// double, then a wave reduction in a fixed order.
 __global__ __launch_bounds__(256) void leaf_solve_kernel(SolveArgs a) {
     const int64_t leaves = int64_t(1) << a.depth;
-    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= leaves * a.K) return;
     const int64_t Lf = t / a.K;
     const int c = (int)(t % a.K);
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(256) void leaf_solve_kernel(SolveArgs a) {
     const int b_hi = right ? a.B : k + 1;
     const int64_t cell0 = (L * a.F + f) * a.B;
     double G = 0.0, H = 0.0;
-    for (int b = b_lo; b < b_hi; ++b) {
+    for (int b = b_lo + lane; b < b_hi; b += 64) {
         const int64_t e = (cell0 + b) * 2 * a.K + 2 * c;
         if (a.precision == CBH_PREC_FP32) {
             G += (double)reinterpret_cast<const float*>(a.hist)[e];
@@ -103,6 +106,11 @@ __global__ __launch_bounds__(256) void leaf_solve_kernel(SolveArgs a) {
             H += (double)reinterpret_cast<const int64_t*>(a.hist)[e + 1];
         }
     }
+    for (int d = 32; d >= 1; d >>= 1) {
+        G += __shfl_xor(G, d, 64);
+        H += __shfl_xor(H, d, 64);
+    }
+    if (lane != 0) return;
     if (a.precision == CBH_PREC_INT16) {
         G *= (double)a.grad_scale[2 * c];
         if (!a.rmse) H *= (double)a.grad_scale[2 * c + 1];
@@ -223,7 +231,7 @@ int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_las
         sa.precision = precision;
         sa.l2 = l2;
         const int64_t work = leaves * p->K;
-        leaf_solve_kernel<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(sa);
+        leaf_solve_kernel<<<(unsigned)((work + 3) / 4), 256, 0, s>>>(sa);
         CBH_LAUNCHED();
     }
     UpdArgs ua;

@@ -309,14 +309,19 @@ def test_graph_replay_matches_eager(cb):
             b.close()
 
 
-def test_autotune_roundtrip(cb, tmp_path):
+@pytest.mark.parametrize("prec,subtract", [(0, False), (2, True)])
+def test_autotune_roundtrip(cb, tmp_path, prec, subtract):
     p = datagen.make_c3(n=40000, F=16)
     p.depth = 4
-    bst = _booster(cb, p, 0)
+    bst = _booster(cb, p, prec, subtract=subtract)
     bst.init_gradients()
+    if prec == 2:
+        cb.cbh_quantize_gradients(bst.ctx, bst.probs[0])
     path = str(tmp_path / "tune.json")
-    cb.cbh_autotune(bst.ctx, bst.probs[0], 0, path)
-    assert open(path).read().count("lds_budget") == p.depth
+    cb.cbh_autotune(bst.ctx, bst.probs[0], prec, subtract, path)
+    text = open(path).read()
+    assert text.count("lds_budget") == p.depth
+    assert text.count('"sub": 1') == (p.depth - 1 if subtract else 0)
     c2 = cb.cbh_create(0)
     cb.cbh_autotune_load(c2, path)
     cb.cbh_destroy(c2)
