@@ -7,10 +7,21 @@ The once-per-dataset steps (borders, bins, ordered statistics) are timed in
 the same run and reported beside it. Inputs are resident in HBM before the
 timed region starts.
 
-Prints one JSON line. `value` is the whole-step histogram-feature throughput
-(rows x features x levels per second, in units of 1e9), `sec_per_tree` the
-mean time of a step, and `roofline` the histogram build's algorithmic HBM
-bytes per launch over its event-timed average duration against 8 TB/s.
+The data are prepared once; then every histogram form is timed on them in
+turn: the headline form (default: compensated two-float, which meets the
+1e-5 error bar) and, beside it, plain float32 and int16. Each form is
+autotuned first (untimed), then `--warmup` trees run, one tree per permutation
+is captured into a HIP graph, and `--steps` trees are replayed and timed with
+events around the whole loop. The histogram build is then timed on its own:
+each level's build repeated back to back with events around the repeats.
+After timing, one more tree is grown level by level and its histograms on
+sampled features are kept; the oracle leg at the end (with the CPU timing of
+the oracle) compares them with FP64 and reports the largest normalised error.
+
+Prints one JSON line. `value` is the headline form's whole-step throughput
+in 1e9 (rows x features x levels) per second; `roofline` gives the
+histogram build's algorithmic HBM bytes over its event-timed duration
+against 8 TB/s.
 """
 from __future__ import annotations
 
@@ -26,10 +37,11 @@ sys.path.insert(0, ROOT)
 METRIC = "sec/tree and histogram G row-features/s vs plain FP32, ≤1e-5 rel err"
 PEAK_HBM_GBS = 8000.0
 PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2}
+DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64"}
 
 
 def hist_bytes_per_level(n, F, K, level, rmse, precision):
-    """Algorithmic bytes one histogram launch must read: the bin of every
+    """Algorithmic bytes one histogram build must read: the bin of every
     (row, feature), the row's gradient statistics and (after level 0) its leaf."""
     if precision == 2:
         grad = 4 * K                       # int16 (g, h) code pair
@@ -39,6 +51,28 @@ def hist_bytes_per_level(n, F, K, level, rmse, precision):
     return n * F + n * grad + n * leaf
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "hist_c2_1m_rmse_counters.json")
+COUNTED_SOURCES = ("paper_1810_11363_amd/csrc/kernels_dev.h",
+                   "paper_1810_11363_amd/csrc/histogram.hip")
+
+
+def measured_traffic(form: str):
+    """HBM bytes per histogram build (fetch + write, hardware counters scaled
+    by a plain copy's reading), as recorded beside the kernel sources they
+    were taken on; None when the sources have changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(COUNTERS))
+        h = hashlib.sha256()
+        for f in COUNTED_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return int(rec["forms"][form]["build_hbm_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(p, rows: int, trees: int):
     """The oracle as it stands, on a row sample of the same workload."""
     import numpy as np
@@ -46,6 +80,7 @@ def cpu_baseline(p, rows: int, trees: int):
     import oracle
     from oracle import boost
     n_full = p.n
+    rows = min(rows, n_full)
     sub = np.sort(np.random.default_rng(0).choice(n_full, rows, replace=False))
     p.x_num = np.ascontiguousarray(p.x_num[:, sub])
     p.cat = np.ascontiguousarray(p.cat[:, sub])
@@ -67,49 +102,98 @@ def cpu_baseline(p, rows: int, trees: int):
     F = bins.shape[0]
     return {"value": round(rows * F * p.depth / dt / 1e9, 6), "unit": "G row-features/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{rows} of {n_full} rows (uniform sample of the same workload), "
-                      f"{trees} trees after 1 warm tree; oracle sec/tree {dt:.3f}",
+            "sample": (f"{rows} of {n_full} rows" + (" (uniform sample)" if rows < n_full
+                                                         else " (the whole workload)") +
+                       f", {trees} trees after 1 warm tree; oracle sec/tree {dt:.3f}; "
+                       f"borders/bins/statistics before it are not timed"),
             "sec_per_tree": round(dt, 4)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", choices=list(PRECISIONS), default="fp32")
-    ap.add_argument("--subtract", choices=["auto", "on", "off"], default="auto",
-                    help="histogram subtraction at levels >= 1 (auto: on except fp32)")
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--cpu-rows", type=int, default=100_000)
-    ap.add_argument("--cpu-trees", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--autotune", default="run",
-                    help="'run' tunes launch plans before the timed region, 'off' keeps "
-                         "the defaults, anything else is a cache file to load")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
-        sys.exit(2)
+def hist_f64(raw, L, F, B, K, precision, rmse):
+    """Device histogram bytes -> float64 [L][F][B][2K] (counts as integers)."""
+    import numpy as np
+    import torch
+    if precision == 0:
+        u = raw[: L * F * B * 2 * K * 4].view(torch.int32).cpu().numpy()
+        out = u.view(np.float32).astype(np.float64).reshape(L, F, B, 2 * K)
+        if rmse:
+            out[..., 1::2] = u.reshape(L, F, B, 2 * K)[..., 1::2].astype(np.uint32)
+        return out
+    if precision == 1:
+        u = raw[: L * F * B * 2 * K * 8].view(torch.int32).cpu().numpy()
+        pair = u.view(np.float32).reshape(L, F, B, 2 * K, 2).astype(np.float64)
+        out = pair[..., 0] + pair[..., 1]
+        if rmse:
+            out[..., 1::2] = u.reshape(L, F, B, 2 * K, 2)[..., 0][..., 1::2].astype(np.uint32)
+        return out
+    return raw[: L * F * B * 2 * K * 8].view(torch.int64).cpu().numpy().reshape(L, F, B, 2 * K)
 
+
+def snapshot_tree(bst, t, rng, n_feat=4):
+    """Grow tree t level by level with the booster's own calls and keep, for
+    sampled features, every level's GPU histogram with the inputs that define
+    it (bins, the GPU's float32 gradients, leaf indices); the oracle leg
+    compares them with FP64 later."""
     import numpy as np
     import torch
 
-    import datagen
     from paper_1810_11363_amd import cbhip as cb
-    from paper_1810_11363_amd.booster import GpuBooster
+    pr = bst.probs[t % bst.s]
+    if bst.precision == 2:
+        cb.cbh_quantize_gradients(bst.ctx, pr, bst.stream)
+    torch.cuda.synchronize()
+    bins = bst.bins_host(t % bst.s)
+    g = bst.g.cpu().numpy().astype(np.float64)
+    h = bst.h.cpu().numpy().astype(np.float64) if bst.loss != 0 else np.ones_like(g)
+    levels = []
+    for lvl in range(bst.depth):
+        L = 1 << lvl
+        leaf = bst.leaf.cpu().numpy() if lvl else np.zeros(bst.n, np.uint16)
+        bst.build_level_histograms(pr, lvl)
+        cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), bst.precision, bst.l2,
+                            bst.split_ptr(lvl), None, bst.stream)
+        torch.cuda.synchronize()
+        got = hist_f64(bst.hists[lvl % 2], L, bst.F, bst.B, bst.K, bst.precision, bst.loss == 0)
+        if bst.precision == 2:
+            sc = bst.grad_scale.cpu().numpy().astype(np.float64)
+            got = got.astype(np.float64)
+            got[..., 0::2] *= sc[:, 0]
+            if bst.loss != 0:
+                got[..., 1::2] *= sc[:, 1]
+        fs = np.sort(rng.choice(bst.F, n_feat, replace=False))
+        levels.append((L, fs, leaf, got[:, fs]))
+        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), bst.stream)
+    cb.cbh_update_approx(bst.ctx, pr, bst.hist_ptr(bst.depth - 1), bst.precision,
+                         bst.split_ptr(bst.depth - 1), bst.lr, bst.l2, bst.leaf_values, None,
+                         bst.stream)
+    torch.cuda.synchronize()
+    return {"bins": bins, "g": g, "h": h, "B": bst.B, "levels": levels}
 
-    prec = PRECISIONS[args.precision]
-    t_gen = time.perf_counter()
-    p = datagen.make_c2(n=args.n)
-    t_gen = time.perf_counter() - t_gen
-    print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
-    sub = None if args.subtract == "auto" else args.subtract == "on"
-    bst = GpuBooster.from_problem(p, precision=prec, subtract=sub).prepare()
-    print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
-    n, F, K, depth = bst.n, bst.F, bst.K, bst.depth
-    stream = bst.stream
+
+def oracle_error(snap):
+    """Largest error of the snapshot's histograms against the FP64 oracle,
+    normalised by the sum of magnitudes of each bin's terms."""
+    import numpy as np
+
+    import oracle
+    worst = 0.0
+    for L, fs, leaf, got in snap["levels"]:
+        want = oracle.histogram(snap["bins"][fs], snap["g"], snap["h"], leaf, L, snap["B"])
+        mag = oracle.histogram(snap["bins"][fs], np.abs(snap["g"]), np.abs(snap["h"]), leaf, L,
+                               snap["B"])
+        m = mag > 0
+        worst = max(worst, float((np.abs(got - want)[m] / mag[m]).max()))
+    return worst
+
+
+def time_form(bst, name, args, rmse):
+    import numpy as np
+    import torch
+
+    from paper_1810_11363_amd import cbhip as cb
+    prec = PRECISIONS[name]
+    bst.set_precision(prec)
+    n, F, K, depth, stream = bst.n, bst.F, bst.K, bst.depth, bst.stream
     bst.init_gradients()
     t_tune = 0.0
     if args.autotune == "run":
@@ -118,70 +202,170 @@ def main():
             cb.cbh_quantize_gradients(bst.ctx, bst.probs[0], stream)
         cb.cbh_autotune(bst.ctx, bst.probs[0], prec, bst.subtract, None, stream)
         t_tune = time.perf_counter() - t_tune
-        print(f"# autotuned in {t_tune:.1f}s", file=sys.stderr, flush=True)
     elif args.autotune != "off":
         cb.cbh_autotune_load(bst.ctx, args.autotune)
     for t in range(args.warmup):
         bst.fit_tree(t)
     torch.cuda.synchronize()
-    print("# warm-up done", file=sys.stderr, flush=True)
-
-    # timed region: steps trees, with events around every histogram build
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(depth)] for _ in range(args.steps)]
+    # timed region: whole trees replayed from HIP graphs (one per permutation)
+    if not args.no_graph:
+        bst.capture_trees()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    start.record(stream)
-    t_wall = time.perf_counter()
-    for s in range(args.steps):
-        bst.fit_tree(args.warmup + s, events=ev[s])
-    stop.record(stream)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        t_wall = time.perf_counter()
+        for s in range(args.steps):
+            if args.no_graph:
+                bst.fit_tree(args.warmup + s)
+            else:
+                bst.replay_tree(args.warmup + s)
+        stop.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     cb.cbh_sync(bst.ctx, stream)
     total_ms = start.elapsed_time(stop)
-    hist_ms = np.array([[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(depth)]
-                        for s in range(args.steps)])
+    # the histogram build alone: every level's build repeated back to back
+    # with events around the repeats (builds are idempotent for a fixed leaf
+    # state), then scored and applied to move to the next level
+    reps = args.hist_repeats
+    pr = bst.probs[(args.warmup + args.steps) % bst.s]
+    if prec == 2:
+        cb.cbh_quantize_gradients(bst.ctx, pr, stream)
+    hist_ms = np.zeros((1, depth))
+    for lvl in range(depth):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        bst.build_level_histograms(pr, lvl)
+        e0.record(stream)
+        for _ in range(reps):
+            bst.build_level_histograms(pr, lvl)
+        e1.record(stream)
+        cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), prec, bst.l2,
+                            bst.split_ptr(lvl), None, stream)
+        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), stream)
+        torch.cuda.synchronize()
+        hist_ms[0, lvl] = e0.elapsed_time(e1) / reps
+    cb.cbh_update_approx(bst.ctx, pr, bst.hist_ptr(depth - 1), prec, bst.split_ptr(depth - 1),
+                         bst.lr, bst.l2, bst.leaf_values, None, stream)
     sec_per_tree = total_ms / 1e3 / args.steps
     rf_per_tree = n * F * depth
-    value = rf_per_tree / sec_per_tree / 1e9
-    rmse = p.loss == datagen.RMSE
     bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec) for l in range(depth)])
     hist_s_per_tree = hist_ms.sum(axis=1).mean() / 1e3
     achieved = float(bytes_lvl.sum() / hist_s_per_tree / 1e9)
+    snap = snapshot_tree(bst, args.warmup + args.steps, np.random.default_rng(1)) \
+        if not args.no_cpu else None
+    print(f"# {name}: {sec_per_tree * 1e3:.3f} ms/tree, hist {hist_s_per_tree * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    return {
+        "sec_per_tree": round(sec_per_tree, 6),
+        "ms_per_step": round(total_ms / args.steps, 4),
+        "G_row_features_per_s": round(rf_per_tree / sec_per_tree / 1e9, 3),
+        "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
+        "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
+        "hist_subtraction": bool(bst.subtract),
+        "graph_replay": not args.no_graph,
+        "max_norm_err_vs_fp64": None,      # filled by the oracle leg
+        "_snapshot": snap,
+        "autotune_s": round(t_tune, 2),
+        "wall_s_timed": round(t_wall, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(name),
+                     "kernel": "cbh_build_histograms / cbh_build_histograms_sub "
+                               "(LDS histogram + partial merge)",
+                     "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
+                     "avg_launch_ms": round(float(hist_ms.mean()), 5)},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=list(PRECISIONS), default="twofloat",
+                    help="headline histogram form")
+    ap.add_argument("--compare", default="fp32,int16",
+                    help="other forms timed in the same run ('' for none)")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-rows", type=int, default=1_000_000)
+    ap.add_argument("--cpu-trees", type=int, default=20)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every call from Python instead of replaying captured trees")
+    ap.add_argument("--hist-repeats", type=int, default=20,
+                    help="back-to-back builds per level for the histogram timing")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU timing and error vs FP64)")
+    ap.add_argument("--autotune", default="run",
+                    help="'run' tunes launch plans before each timed region, 'off' keeps "
+                         "the defaults, anything else is a cache file to load")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB five times (reference "
+                         "for hardware byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 5}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch  # noqa: F401
+
+    import datagen
+    from paper_1810_11363_amd.booster import GpuBooster
+
+    t_gen = time.perf_counter()
+    p = datagen.make_c2(n=args.n)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    bst = GpuBooster.from_problem(p).prepare()
+    print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
+    rmse = p.loss == datagen.RMSE
+    forms = [args.precision] + [f for f in args.compare.split(",") if f and f != args.precision]
+    results = {f: time_form(bst, f, args, rmse) for f in forms}
+    head = results[args.precision]
+    n, F, depth = bst.n, bst.F, bst.depth
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": head["G_row_features_per_s"],
         "unit": "G row-features/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(total_ms / args.steps, 4),
-        "sec_per_tree": round(sec_per_tree, 6),
-        "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
-        "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
+        "ms_per_step": head["ms_per_step"],
+        "sec_per_tree": head["sec_per_tree"],
+        "hist_G_row_features_per_s": head["hist_G_row_features_per_s"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64"}[args.precision],
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": f"1M-row RMSE: n={n}, 100 numeric features at 128 bins + "
                                f"10 categorical -> {F - 100} ordered-statistic columns per "
                                f"tree, 4 permutations, depth {depth}, lr 0.1, l2 3",
                    "precision": args.precision, "features_per_tree": F, "bins": bst.B,
                    "rows": n},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None,
-                     "kernel": "cbh_build_histograms (LDS histogram + partial merge)",
-                     "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
-                     "avg_launch_ms": round(float(hist_ms.mean()), 5)},
+        "roofline": head["roofline"],
+        "forms": results,
+        "vs_plain_fp32": (round(results["fp32"]["sec_per_tree"] / head["sec_per_tree"], 3)
+                          if "fp32" in results else None),
         "preprocess_s": {k: round(v, 4) for k, v in bst.timings.items() if v is not None},
-        "autotune_s": round(t_tune, 2),
-        "histogram_subtraction": bool(bst.subtract),
-        "wall_s_timed": round(t_wall, 3),
     }
     bst.close()
+    # the oracle leg: FP64 error of every form's sampled histograms, then the
+    # oracle timed on a row sample of the same workload
+    for f, r in results.items():
+        snap = r.pop("_snapshot")
+        if snap is not None:
+            r["max_norm_err_vs_fp64"] = oracle_error(snap)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(datagen.make_c2(n=args.n), args.cpu_rows,

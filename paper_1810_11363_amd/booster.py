@@ -50,6 +50,7 @@ class GpuBooster:
                  subtract=None, device="cuda:0", ctx=None, stream=None):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
+        self.graphs = []
         self.own_ctx = ctx is None
         self.ctx = ctx if ctx is not None else cb.cbh_create(self.device.index or 0)
         self.loss, self.K, self.depth = int(loss), int(K), int(depth)
@@ -165,11 +166,21 @@ class GpuBooster:
                                                        np.int32)]))
         self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
-        hb = max(256, self._hist_bytes(self.depth - 1))
-        self.hists = [torch.empty(hb, dtype=torch.uint8, device=d) for _ in range(2)]
-        self.hist = self.hists[(self.depth - 1) % 2]     # the last level's histogram
+        self._alloc_hists()
         self.probs = [self.problem(r) for r in range(self.s)]
         return self
+
+    def _alloc_hists(self):
+        hb = max(256, self._hist_bytes(self.depth - 1))
+        self.hists = [torch.empty(hb, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.hist = self.hists[(self.depth - 1) % 2]     # the last level's histogram
+
+    def set_precision(self, precision: int, subtract=None):
+        """Switch the histogram form; keeps the prepared bins and statistics."""
+        self.precision = int(precision)
+        self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
+        self.graphs = []      # captured trees point at the old buffers
+        self._alloc_hists()
 
     def problem(self, r: int) -> cb.cbh_problem:
         p = cb.cbh_problem()
@@ -238,6 +249,32 @@ class GpuBooster:
         cb.cbh_update_approx(ctx, pr, self.hist_ptr(self.depth - 1), prec,
                              self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
                              self.leaf_counts if counts else None, st)
+
+    def capture_trees(self):
+        """Capture one tree per permutation into HIP graphs; tree t replays
+        graph t mod s on the current stream. Grow at least one tree of every
+        permutation first: the library's workspace must have reached its size,
+        since a capture may not allocate and a later growth of the workspace
+        (or a change of form, which drops the graphs) frees memory the graphs
+        point at."""
+        self.graphs = []
+        cap = torch.cuda.Stream(self.device)       # default priority
+        eager = self.stream
+        torch.cuda.synchronize(self.device)
+        try:
+            self.stream = cap
+            for r in range(self.s):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=cap):
+                    self.fit_tree(r)
+                self.graphs.append(g)
+        finally:
+            self.stream = eager
+        torch.cuda.synchronize(self.device)
+        return self.graphs
+
+    def replay_tree(self, t: int):
+        self.graphs[t % self.s].replay()
 
     def tree_record(self) -> TreeRecord:
         b = self.best.cpu().numpy()

@@ -309,6 +309,48 @@ def test_graph_replay_matches_eager(cb):
             b.close()
 
 
+@pytest.mark.parametrize("prec", [2, 1])
+def test_tree_graph_matches_eager(cb, prec):
+    """Whole trees captured once per permutation and replayed (the benchmark's
+    timed form) give the trees that eager calls give: bit for bit for int16;
+    for the compensated form, whose FP64 LDS sums may round differently run to
+    run, the same splits and leaf values within 1e-9. Every replay is checked,
+    with eager reads and synchronisations between replays."""
+    p = datagen.make_c2(n=60000)
+    p.depth = 5
+    eager = _booster(cb, p, prec)
+    graph = _booster(cb, p, prec)
+    try:
+        eager.init_gradients()
+        graph.init_gradients()
+        s = graph.s
+        for t in range(s):
+            eager.fit_tree(t)
+            graph.fit_tree(t)
+        graph.capture_trees()
+        for t in range(s, 3 * s):
+            eager.fit_tree(t)
+            graph.replay_tree(t)
+            torch.cuda.synchronize()
+            re, rg = eager.tree_record(), graph.tree_record()
+            if prec == 2:
+                assert np.array_equal(re.splits, rg.splits), t
+                assert np.array_equal(re.values, rg.values), t
+                assert torch.equal(eager.approx, graph.approx), t
+            else:
+                for lvl in range(p.depth):
+                    if not np.array_equal(re.splits[lvl], rg.splits[lvl]):
+                        assert re.scores[lvl, 1] < gu.MARGIN_TOL * abs(re.scores[lvl, 0]), t
+                        return
+                np.testing.assert_allclose(rg.values, re.values, rtol=1e-9, atol=1e-12)
+                torch.testing.assert_close(graph.approx, eager.approx, rtol=1e-9, atol=1e-12)
+            # eager work between replays
+            assert int(graph.leaf.to(torch.int32).max().item()) < (1 << p.depth)
+    finally:
+        eager.close()
+        graph.close()
+
+
 @pytest.mark.parametrize("prec,subtract", [(0, False), (2, True)])
 def test_autotune_roundtrip(cb, tmp_path, prec, subtract):
     p = datagen.make_c3(n=40000, F=16)
