@@ -4,27 +4,36 @@
 // second statistic h, the row count for RMSE).
 //
 // MI355X design. The paper's kernel keeps per-warp copies in shared memory and
-// rotates lanes over features to avoid atomics; on CDNA4 the LDS has native
-// float/int atomics (ds_add_f32, ds_add_u32, ds_add_u64) and 160 KB per CU,
-// so one LDS tile per block is updated with LDS atomics and no global atomics
-// are used anywhere:
+// rotates lanes over features to avoid atomics. On CDNA4 the LDS has native
+// 64-bit atomics (ds_add_f64, ds_add_u64) and ds_add_u32 at full rate, while
+// ds_add_f32 is serialised (measured about 0.3 lane-ops per clock per CU
+// against 7.5 for ds_add_f64), and a CU has 160 KB of LDS. So one LDS tile per
+// block is updated with LDS atomics, and no global atomics are used anywhere:
 //   - a block owns (row chunk, feature group, leaf tile); every thread streams
-//     4 consecutive rows per step: one dword of bins per feature (coalesced,
-//     feature-major columns), a float4 of g, a float4 of h and 8 bytes of leaf;
-//   - the tile is [leaf][feature][bin][stat] in LDS;
-//   - the block writes its tile to a partial buffer; a second launch merges
-//     the partial tiles of all row chunks in chunk order (deterministic merge);
+//     ROWS consecutive rows per step (16 for int16 codes, 8 for float forms):
+//     ROWS bins of each of its features (coalesced, feature-major columns),
+//     the rows' gradient statistics and, from level 1 on, their leaf indices;
+//   - the tile is [leaf][feature][stat][bin][replica] in LDS with the bin
+//     stride padded to an odd number of words; spare LDS holds up to 32
+//     replicas of every cell, replica = lane mod rep, so lanes that hit one
+//     bin mostly update different words;
+//   - the block sums the replicas and writes its tile to a partial buffer; a
+//     second launch merges the partial tiles of all row chunks in a fixed
+//     order (deterministic merge);
 //   - block ids map to work XCD-contiguously: consecutive work items (same row
 //     chunk, different feature groups) land on one XCD and share its L2.
-// Precision variants:
-//   FP32      ds_add_f32 for g (and h), ds_add_u32 for RMSE counts;
-//   TWOFLOAT  ds_add_rtn_f32 returns the old value, from which the exact
-//             rounding error of that addition is recomputed (TwoSum) and
-//             added to a second, "lo" word; chunk partials are merged with
-//             TwoSum as well;
+// Precision variants (the LDS sum is exact or FP64; the output rounding is
+// the variant's):
+//   FP32      ds_add_f64 for g (and h), ds_add_u32 for RMSE counts; each
+//             tile sum is rounded once to float, chunk partials are added in
+//             float;
+//   TWOFLOAT  the same FP64 tiles, each sum split into a (hi, lo) float pair;
+//             chunk partials are added with TwoSum;
 //   INT16     one ds_add_u64 per row, feature and class of the packed word
 //             (g code << 32) + h code; at most 65536 rows per chunk keep
 //             both halves exact; partials are decoded and summed in int64.
+// Histogram subtraction (levels >= 1, optional): only the smaller child of
+// every parent leaf is accumulated; its sibling is the parent minus it.
 #include <algorithm>
 #include <cmath>
 
