@@ -79,8 +79,12 @@ typedef struct cbh_ctx cbh_ctx;
  *               n_bins[f] <= B for every f; a stored bin >= B is counted in
  *               bin B-1
  *   bins        device array of F device pointers; bins[f] points at the
- *               uint8 bin column of feature f, n bytes, row order. Columns
- *               should be 16-byte aligned for full bandwidth.
+ *               uint8 bins of feature f. Rows are grouped in segments of 16
+ *               consecutive rows: the bin of row i is the byte at
+ *               bins[f] + (i / 16) * seg_stride[f] + i % 16. With seg_stride
+ *               NULL every stride is 16, i.e. bins[f] is a plain column of
+ *               n bytes in row order. Bins should be 16-byte aligned for full
+ *               bandwidth.
  *   n_bins      device int32 [F]: number of bins of feature f (borders + 1);
  *               candidate borders are k = 0 .. n_bins[f]-2
  *   K           approx width: 1 (RMSE, Logloss) or the class count
@@ -100,7 +104,15 @@ typedef struct cbh_ctx cbh_ctx;
  *               split of depth i (Sec. 4). Its contents are ignored at
  *               level 0, and cbh_apply_split at level 0 overwrites it, so a
  *               new tree needs no reset.
- *   approx      device double [K][n]: current model value of every row       */
+ *   approx      device double [K][n]: current model value of every row
+ *   seg_stride  device int64 [F] or NULL: bytes between consecutive 16-row
+ *               segments of feature f (a multiple of 16, at least 16; bins[f]
+ *               16-byte aligned when it is not 16). A tiled matrix
+ *               [ceil(n/16)][F][16] (see cbh_tile_bins) has bins[f] = base +
+ *               16 f and seg_stride[f] = 16 F: then the 16-row segments of
+ *               consecutive features are adjacent, which the histogram
+ *               kernel that gives lanes of a wave different features reads
+ *               with full coalescing. The values are not checked.          */
 typedef struct cbh_problem {
     int64_t n;
     int32_t n_features;
@@ -118,6 +130,7 @@ typedef struct cbh_problem {
     float* grad_scale;
     uint16_t* leaf;
     double* approx;
+    const int64_t* seg_stride;
 } cbh_problem;
 
 /* Result of the split search of one level (device memory).
@@ -186,6 +199,20 @@ int cbh_uniform_borders(double lo, double hi, int32_t n_bins, double* borders_ou
  * A NaN value gets bin 0 and raises a device error reported by cbh_sync. */
 int cbh_quantize(cbh_ctx* ctx, const float* x, int64_t n, const float* borders,
                  int32_t n_borders, uint8_t* bins_out, void* stream);
+
+/* Copy bin columns into the row-tiled layout (a data layout step of this
+ * library, not of the method): segment t of column c, the bins of rows
+ * 16t .. 16t+15, lands at out + (t * n_cols + c) * 16, so the segments of
+ * all columns for the same 16 rows are adjacent.
+ *   cols    device array of n_cols device pointers to uint8 columns of n
+ *           bytes (row order)
+ *   n_cols  1 .. 65535
+ *   out     device uint8 [ceil(n/16)][n_cols][16]; the bytes of the last
+ *           segment past row n-1 are set to 0
+ * Feature c then reads as bins[c] = out + 16 c, seg_stride[c] = 16 n_cols.
+ * Errors: CBH_EINVAL on NULL or n < 1 or n_cols out of range. */
+int cbh_tile_bins(cbh_ctx* ctx, const uint8_t* const* cols, int32_t n_cols, int64_t n,
+                  uint8_t* out, void* stream);
 
 /* Ordered target statistics of one categorical feature for one permutation,
  * Sec. 2, Eq. (1). For the row sigma_p at position p, over the rows placed at
@@ -357,10 +384,17 @@ void cbh_graph_destroy(cbh_graph* graph);
  *   min_rows       rows per block at least
  *   partial_pct    partial tiles at most this % of the level's bin bytes
  *   max_rep        LDS replicas per (leaf, feature) cell at most (power of two)
- *   rep_target     replicas the planner reserves LDS for before adding features */
+ *   rep_target     replicas the planner reserves LDS for before adding features
+ *   kernel         1: for K = 1 use the kernel that spreads the features of a
+ *                  group over the lanes of a wave (conflict-free LDS tile, no
+ *                  replicas); 0: always the kernel that spreads rows over lanes
+ *                  (replicated LDS tile)
+ *   lpf_w          features per lane group of kernel 1: 4, 8, 16 or 32 (the
+ *                  widest whose tile fits if the tile does not), 0: widest that
+ *                  fits                                                         */
 int cbh_set_hist_knobs(cbh_ctx* ctx, int32_t lds_budget, int32_t target_blocks,
                        int64_t min_rows, int32_t partial_pct, int32_t max_rep,
-                       int32_t rep_target);
+                       int32_t rep_target, int32_t kernel, int32_t lpf_w);
 
 /* Tune the histogram launch plan of every level of `prob`: one tree is grown
  * level by level from the problem's current gradients (prob->leaf is

@@ -12,8 +12,14 @@ of the method runs in the HIP library behind the C-ABI.
 Device layout (HBM):
   numeric bins   uint8 [F_num][ld]            ld = n rounded up to 16
   statistic bins uint8 [s][F_cat * T][ld]     T targets per categorical feature
-  column table   int64 [s][F]                 device pointers of the F columns
+  tiled bins     uint8 [s][ceil(n/16)][F][16] layout "tiled" (default): for
+                                              permutation r, the 16-row
+                                              segments of all F features a tree
+                                              reads, side by side
+  column table   int64 [s][F]                 device pointers of the F features
                                               a tree of permutation r reads
+  segment table  int64 [s][F]                 bytes between their 16-row
+                                              segments (16 F tiled; 16 columns)
   n_bins         int32 [s][F]
   label float32 [n], g/h float32 [K][n], gq int16 [K][n][2], leaf uint16 [n],
   approx float64 [K][n]
@@ -47,7 +53,7 @@ class GpuBooster:
 
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
-                 subtract=None, device="cuda:0", ctx=None, stream=None):
+                 subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled"):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -57,6 +63,9 @@ class GpuBooster:
         self.lr, self.l2 = float(lr), float(l2)
         self.num_bins, self.ts_bins, self.a = int(num_bins), int(ts_bins), float(a)
         self.precision = int(precision)
+        if layout not in ("tiled", "columns"):
+            raise ValueError(f"layout must be 'tiled' or 'columns', not {layout!r}")
+        self.layout = layout
         # histogram subtraction at levels >= 1: exact for int16, two-float
         # difference for the compensated form; off for plain float32 by default
         self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
@@ -165,6 +174,24 @@ class GpuBooster:
             nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.T, self.ts_bins,
                                                        np.int32)]))
         self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
+        self.seg_table = None
+        if self.layout == "tiled":
+            # one tiled matrix per permutation: the numeric segments are
+            # repeated in each, so every lane group of features reads one
+            # contiguous run of 16-byte segments
+            T = (n + 15) // 16
+            self.tiled = torch.empty((self.s, T, self.F, 16), dtype=torch.uint8, device=d)
+            torch.cuda.synchronize(d)
+            t6 = time.perf_counter()
+            for r in range(self.s):
+                cb.cbh_tile_bins(self.ctx, self.col_table[r], self.F, n, self.tiled[r], st)
+            cb.cbh_sync(self.ctx, st)
+            self.timings["tile_s"] = time.perf_counter() - t6
+            base = [self.tiled[r].data_ptr() for r in range(self.s)]
+            self.col_table = torch.tensor([[b + 16 * f for f in range(self.F)] for b in base],
+                                          dtype=torch.int64, device=d)
+            self.seg_table = torch.full((self.s, self.F), 16 * self.F, dtype=torch.int64,
+                                        device=d)
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
         self._alloc_hists()
         self.probs = [self.problem(r) for r in range(self.s)]
@@ -199,10 +226,15 @@ class GpuBooster:
         p.grad_scale = self.grad_scale.data_ptr()
         p.leaf = self.leaf.data_ptr()
         p.approx = self.approx.data_ptr()
+        p.seg_stride = self.seg_table[r].data_ptr() if self.seg_table is not None else None
         return p
 
     def bins_host(self, r: int) -> np.ndarray:
-        """uint8 [F][n] bins a tree of permutation r sees (copied to host, for checks)."""
+        """uint8 [F][n] bins a tree of permutation r reads (copied to host, for
+        checks): from the tiled matrix when the problem uses it."""
+        if self.seg_table is not None:
+            t = self.tiled[r].cpu().numpy()                      # [T][F][16]
+            return np.ascontiguousarray(t.transpose(1, 0, 2).reshape(self.F, -1)[:, : self.n])
         parts = [self.num_bins_d[: self.F_num, : self.n]]
         if self.F_cat:
             parts.append(self.ts_bins_d[r, :, : self.n])

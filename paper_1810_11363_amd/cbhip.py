@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "CBH_OK", -1: "CBH_EINVAL", -2: "CBH_ENOMEM", -3: "CBH_EDEVIC
 EXPORTS = [
     "cbh_create", "cbh_destroy", "cbh_last_error", "cbh_set_workspace_limit",
     "cbh_workspace_size", "cbh_sync", "cbh_select_borders", "cbh_uniform_borders",
-    "cbh_quantize",
+    "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
     "cbh_build_histograms_sub",
     "cbh_score_splits", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
@@ -42,7 +42,7 @@ class cbh_problem(C.Structure):
         ("loss", C.c_int32), ("depth", C.c_int32), ("reserved", C.c_int32),
         ("label", C.c_void_p), ("g", C.c_void_p), ("h", C.c_void_p),
         ("gq", C.c_void_p), ("grad_scale", C.c_void_p), ("leaf", C.c_void_p),
-        ("approx", C.c_void_p),
+        ("approx", C.c_void_p), ("seg_stride", C.c_void_p),
     ]
 
 
@@ -73,6 +73,7 @@ def _load():
         "cbh_select_borders": ([vp, i64, i32, vp, C.POINTER(i32)], C.c_int),
         "cbh_uniform_borders": ([dbl, dbl, i32, vp], C.c_int),
         "cbh_quantize": ([vp, vp, i64, vp, i32, vp, vp], C.c_int),
+        "cbh_tile_bins": ([vp, vp, i32, i64, vp, vp], C.c_int),
         "cbh_compute_ordered_ts": ([vp, vp, vp, i64, vp, i32, i32, i64, dbl, vp, vp, i32,
                                     vp, vp, vp, vp, vp], C.c_int),
         "cbh_quantize_gradients": ([vp, C.POINTER(cbh_problem), vp], C.c_int),
@@ -94,7 +95,7 @@ def _load():
         "cbh_graph_destroy": ([vp], None),
         "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, i32, C.c_char_p, vp], C.c_int),
         "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
-        "cbh_set_hist_knobs": ([vp, i32, i32, i64, i32, i32, i32], C.c_int),
+        "cbh_set_hist_knobs": ([vp, i32, i32, i64, i32, i32, i32, i32, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -186,6 +187,11 @@ def cbh_uniform_borders(lo: float, hi: float, n_bins: int):
 def cbh_quantize(ctx, x, n: int, borders, n_borders: int, bins_out, stream=None):
     return _check(_lib.cbh_quantize(ctx, _ptr(x), n, _ptr(borders), n_borders, _ptr(bins_out),
                                     _stream(stream)))
+
+
+def cbh_tile_bins(ctx, cols, n_cols: int, n: int, out, stream=None):
+    """cols: device int64 tensor (or address) of n_cols column pointers."""
+    return _check(_lib.cbh_tile_bins(ctx, _ptr(cols), n_cols, n, _ptr(out), _stream(stream)))
 
 
 def cbh_compute_ordered_ts(ctx, cat, perm, n: int, y_num, n_targets: int, y_shift: int,
@@ -289,9 +295,9 @@ def cbh_autotune(ctx, prob: cbh_problem, precision: int, subtract: bool = False,
 
 
 def cbh_set_hist_knobs(ctx, lds_budget=0, target_blocks=512, min_rows=32768, partial_pct=25,
-                       max_rep=32, rep_target=32):
+                       max_rep=32, rep_target=32, kernel=1, lpf_w=0):
     return _check(_lib.cbh_set_hist_knobs(ctx, lds_budget, target_blocks, min_rows,
-                                          partial_pct, max_rep, rep_target))
+                                          partial_pct, max_rep, rep_target, kernel, lpf_w))
 
 
 def cbh_autotune_load(ctx, cache_path: str):

@@ -38,6 +38,7 @@ struct DevProb {
     uint32_t* partials;      // this problem's partial tiles (workspace)
     int64_t n;
     int32_t F, B, K, rmse;
+    const int64_t* seg;      // per-feature segment strides, NULL = columns
 };
 
 // One histogram work item: (problem, chunk, feature group, leaf tile) and its plan.
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __re
     const LevelPlan::DevHP hp = plans[tile.prob];
     TileArgs t;
     t.bins = pr.bins;
+    t.seg = pr.seg;
     t.g = pr.g;
     t.h = pr.h;
     t.gq = pr.gq;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__
         const int p = find_owner(row_off, P, gq);
         const DevProb pr = probs[p];
         const int64_t i0 = (gq - row_off[p]) * 8;
-        apply_rows(pr.bins, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
+        apply_rows(pr.bins, pr.seg, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
                    min(pr.n, i0 + 8), level);
     }
 }
@@ -341,6 +343,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                 knobs_for(ctx, pr.n_features, pr.max_bins, pr.K, lvl, precision, pr.n, 0);
             // in a batch the problems share the chip: aim at a share of the blocks
             HistKnobs kb = kn;
+            kb.kernel = 0;      // the batched tile kernel takes rows over lanes
             kb.target_blocks = std::max<int32_t>(
                 64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
             HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, L, precision,
@@ -405,7 +408,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         const cbh_problem& pr = probs[p];
         dp[p] = DevProb{pr.bins, pr.n_bins, pr.g, pr.h, reinterpret_cast<const uint32_t*>(pr.gq),
                         pr.grad_scale, pr.leaf, hist[p], nullptr, pr.n, pr.n_features,
-                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE};
+                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE, pr.seg_stride};
     }
     std::vector<DevProb> all;
     all.reserve(size_t(P) * b->depth);

@@ -56,7 +56,8 @@ enum : uint32_t {
 
 // ------------------------------------------------------- launch geometry
 struct HistPlan {
-    int32_t fb = 1;          // features per block
+    int32_t kind = 0;        // 0: rows over lanes with LDS replicas; 1: features over lanes
+    int32_t fb = 1;          // features per block (kind 1: the lane group width W)
     int32_t lt = 1;          // leaves per LDS tile
     int32_t n_fgroups = 1;
     int32_t n_ltiles = 1;
@@ -81,6 +82,8 @@ struct HistKnobs {
     int32_t partial_pct = 25;        // partial tiles at most this % of the bin bytes
     int32_t max_rep = 32;            // LDS replicas per cell at most
     int32_t rep_target = 32;         // replicas the planner reserves LDS for first
+    int32_t kernel = 1;              // 1: features over lanes where it applies (K == 1), 0: never
+    int32_t lpf_w = 0;               // features per lane group for kernel 1, 0: widest that fits
 };
 
 // (F, B, K, level, precision, floor(log2 n), subtraction mode)
@@ -98,6 +101,7 @@ struct cbh_ctx {
     uint32_t* d_flags = nullptr;  // device error flags
     cbh::HistKnobs knobs;
     std::map<cbh::TuneKey, cbh::HistKnobs> tuned;
+    std::map<cbh::TuneKey, std::string> tuned_note;   // chosen plan and its time, for the cache file
     bool force_knobs = false;
     cbh::HistKnobs forced;
 };
@@ -128,9 +132,13 @@ int validate_precision(const cbh_problem* p, int32_t precision);
 
 // Launchers used by several entry points (same stream semantics as the API).
 // parent / side: subtraction mode (level >= 1), else NULL.
+// codes: n uint16 of scratch, needed (hist_code_bytes) by the lanes-over-features
+// kernel in subtraction mode.
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
-                const void* parent = nullptr, const uint8_t* side = nullptr);
+                const void* parent = nullptr, const uint8_t* side = nullptr,
+                uint16_t* codes = nullptr);
+int64_t hist_code_bytes(const HistPlan& plan, int64_t n, bool sub);
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores,
                  void* scratch, hipStream_t s);

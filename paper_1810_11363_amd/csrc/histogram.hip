@@ -73,8 +73,47 @@ HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t
 //     under partial_pct % of the n * F bin bytes;
 //   feature groups: as many as needed to reach target_blocks, at least enough
 //     to respect the LDS bound on features per block.
+// Plan of the lanes-over-features kernel: the widest lane group W (at most
+// the requested one) whose tile of all slots fits the LDS budget; if even
+// W = 4 does not fit, the slots are split into tiles (rows re-read per tile).
+// Chunks as for the other kernel.
+static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t n_slots,
+                         int32_t precision, int max_lds) {
+    HistPlan p;
+    p.kind = 1;
+    p.words_per_cell = words_per_cell(precision, 1);
+    const int64_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
+    const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
+    int32_t W = kn.lpf_w > 0 ? std::min(kn.lpf_w, 32) : 32;
+    while (W > 4 && int64_t(n_slots) * B * W * cs > budget) W /= 2;
+    p.fb = W;
+    // slots per tile: all if they fit, at most 64 (one bit each in the
+    // kernel's mask of subtraction sides)
+    int32_t lt = std::min<int32_t>(n_slots, 64);
+    while (lt > 1 && int64_t(lt) * B * W * cs > std::max<int64_t>(budget, B * W * cs)) lt = (lt + 1) / 2;
+    p.lt = lt;
+    p.n_ltiles = (n_slots + lt - 1) / lt;
+    p.n_fgroups = (F + W - 1) / W;
+    const int64_t tiles = int64_t(p.n_fgroups) * p.n_ltiles;
+    const int64_t part_per_chunk = int64_t(n_slots) * F * B * p.words_per_cell * 4;
+    const int64_t c_part = std::max<int64_t>(1, (int64_t(kn.partial_pct) * n * F / 100) /
+                                                    std::max<int64_t>(1, part_per_chunk));
+    const int64_t c_rows = std::max<int64_t>(1, n / std::max<int64_t>(1, kn.min_rows));
+    const int64_t c_fill = std::max<int64_t>(1, (kn.target_blocks + tiles - 1) / tiles);
+    const int64_t chunks = std::min(std::min(c_part, c_rows), c_fill);
+    int64_t rows = align_up((n + chunks - 1) / chunks, 16);
+    if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);
+    p.rows_per_chunk = rows;
+    p.n_chunks = (int32_t)((n + rows - 1) / rows);
+    p.rep = 1;
+    p.lds_bytes = int64_t(lt) * B * W * cs;
+    p.n_blocks = int64_t(p.n_chunks) * tiles;
+    return p;
+}
+
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                    int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds) {
+    if (kn.kernel == 1 && K == 1) return plan_lpf(kn, n, F, B, n_leaves, precision, max_lds);
     HistPlan p;
     p.words_per_cell = words_per_cell(precision, K);
     const int64_t cell_bytes = tile_lds_bytes(precision, rmse, K, B, 1);   // LDS per cell
@@ -126,6 +165,7 @@ HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t
 
 struct HistArgs {
     const uint8_t* const* bins;
+    const int64_t* seg;
     const float* g;
     const float* h;
     const uint32_t* gq;
@@ -141,6 +181,9 @@ struct HistArgs {
     const uint8_t* side;    // subtraction mode (see TileArgs), else NULL
     uint32_t sub_shift;
     int32_t rep;
+    // lanes-over-features kernel: per-row slot codes (the leaf in a direct
+    // build; the parent, or 0xffff for the larger child's rows, in subtraction)
+    const uint16_t* rowcode;
 };
 
 template <int PREC, int KT, int RM>
@@ -157,6 +200,7 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(HistArgs a) {
     const int64_t chunk = item / a.n_fgroups;
     TileArgs t;
     t.bins = a.bins;
+    t.seg = a.seg;
     t.g = a.g;
     t.h = a.h;
     t.gq = a.gq;
@@ -378,6 +422,255 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
     if (lane == 0) side[p] = right < left ? 1 : 0;
 }
 
+// ------------------------------------------- lanes-over-features variant
+// For one class (K = 1). Lane l of a wave owns feature f0 + l % W of the
+// block's group of W features and the 16-row segment l / W of the wave's
+// current group of 64 / W segments. The LDS tile is [slot][bin][stat][W] of
+// 8-byte elements (one stat, the packed int16 codes; or two, FP64 g and then
+// the count or the FP64 h), so in one atomic instruction the lanes with
+// distinct features touch distinct banks whatever their bins are, with no
+// replicas. With the bins in
+// the tiled layout the W segments of one row group are adjacent in memory and
+// a wave's bin load is fully coalesced; plain columns work too.
+// bytes per (slot, bin, feature) over all stats
+template <int PREC>
+__host__ __device__ constexpr uint32_t lpf_cell_bytes() { return PREC == CBH_PREC_INT16 ? 8u : 16u; }
+
+// LDS byte offset, in slot 0, of the first stat of (bin of row r of the
+// segment's words, this lane's feature): bin * W * CS + lane_off, where
+// lane_off = 8 * feature; the second stat is W * 8 bytes further.
+template <int W, int CS>
+__device__ __forceinline__ uint32_t lpf_addr(const uint32_t (&bw)[4], int r, uint32_t lane_off) {
+    const uint32_t word = bw[r >> 2];
+    if constexpr (W * CS == 256) {
+        // byte 1 <- bin, byte 0 <- lane_off (< 256), bytes 2 and 3 <- 0
+        return __builtin_amdgcn_perm(word, lane_off, 0x0c0c0000u | ((4u + (r & 3)) << 8));
+    } else if constexpr (W * CS == 512) {
+        return __builtin_amdgcn_perm(word, lane_off >> 1, 0x0c0c0000u | ((4u + (r & 3)) << 8))
+               << 1;
+    } else {
+        return ((word >> (8 * (r & 3))) & 255u) * (uint32_t)(W * CS) + lane_off;
+    }
+}
+
+// Add rows r0 .. r0+7 of one 16-row segment (bins in bw) to the tile.
+// off[k]: slot byte offset of row r0 + k, or kLpfSkip; CHECK = false when every
+// row is known to be valid.
+constexpr uint32_t kLpfSkip = 0xffffffffu;
+
+template <int PREC, int RM, int W, bool CHECK>
+__device__ __forceinline__ void lpf_rows8(char* tile, const uint32_t (&bw)[4], int r0,
+                                          uint32_t lane_off, const uint32_t (&off)[8],
+                                          const float (&gv)[8], const float (&hv)[8],
+                                          const uint32_t (&qv)[8]) {
+    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (CHECK && off[k] == kLpfSkip) continue;
+        const uint32_t ad = lpf_addr<W, CS>(bw, r0 + k, lane_off) + off[k];
+        if constexpr (PREC == CBH_PREC_INT16) {
+            // (g code << 32) + h code: both halves stay exact for <= 65536
+            // rows per chunk. The h code (high half of the word) is in
+            // [0, 32767]; the g code (low half) is sign-extended.
+            const uint32_t hq = qv[k] >> 16;
+            const uint32_t gq = (uint32_t)((int32_t)(qv[k] << 16) >> 16);
+            const uint64_t packed = ((uint64_t)gq << 32) | hq;
+            __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(tile + ad),
+                                   (unsigned long long)packed, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad), (double)gv[k],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if constexpr (RM != 0)
+                __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad + W * 8), 1u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+                __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad + W * 8),
+                                       (double)hv[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
+// MODE 0: one slot (level 0, direct): no per-row reads, no checks.
+// MODE 1: all slots of a direct build in one tile: slot = row code (the leaf).
+// MODE 2: subtraction and/or several slot tiles: slot = row code - first slot
+//         of the tile, rows outside the tile (or with code 0xffff) skipped.
+template <int PREC, int RM, int W, int MODE>
+__global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+    constexpr int RG = 64 / W;                  // segments per wave step
+    const int64_t per_xcd = (a.n_blocks + 7) / 8;
+    int64_t item = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (item >= a.n_blocks) return;
+    const int lt_i = (int)(item % a.n_ltiles);
+    item /= a.n_ltiles;
+    const int fg = (int)(item % a.n_fgroups);
+    const int64_t chunk = item / a.n_fgroups;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int fl = lane & (W - 1), rq = lane / W;
+    const int f0 = fg * W;
+    const int nf = min(W, a.F - f0);
+    const bool fok = fl < nf;
+    const int f = f0 + (fok ? fl : 0);
+    const uint8_t* col = a.bins[f];
+    const int64_t sstride = a.seg ? a.seg[f] : 16;
+    const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;               // first slot of the tile
+    const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);       // slots in the tile (<= 64)
+    const uint32_t slot_bytes = (uint32_t)a.B * W * CS;
+    const uint32_t tile_words = ns * slot_bytes / 4;
+    for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
+    __syncthreads();
+    char* tile = reinterpret_cast<char*>(lds);
+    const int64_t r0 = chunk * a.rows_per_chunk;
+    const int64_t r1 = min(a.n, r0 + a.rows_per_chunk);
+    const int64_t t_full = r1 >> 4;            // segments before this one are full
+    const uint32_t lane_off = (uint32_t)fl * 8u;
+    const uint16_t* rowcode = a.rowcode;
+    const bool vec = ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(a.g) |
+                       reinterpret_cast<uintptr_t>(a.h) | reinterpret_cast<uintptr_t>(a.gq) |
+                       reinterpret_cast<uintptr_t>(rowcode)) & 15) == 0;
+    float gv[8], hv[8];
+    uint32_t qv[8], off[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        gv[k] = 0.f;
+        hv[k] = 0.f;
+        qv[k] = 0u;
+        off[k] = 0u;
+    }
+    int64_t t = (r0 >> 4) + int64_t(wave) * RG + rq;
+    if (vec) {
+        for (; t < t_full; t += int64_t(nwaves) * RG) {
+            const int64_t i = t << 4;
+            const uint4 v = *reinterpret_cast<const uint4*>(col + t * sstride);
+            const uint32_t bw[4] = {v.x, v.y, v.z, v.w};
+            uint4 lv;
+            if constexpr (MODE != 0) lv = *reinterpret_cast<const uint4*>(rowcode + i);
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int64_t ih = i + 8 * h2;
+                if constexpr (MODE != 0) {
+                    if (h2 == 1) lv = *reinterpret_cast<const uint4*>(rowcode + ih);
+                    const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const uint32_t code = (lw[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                        const uint32_t sl = code - s0;
+                        off[k] = MODE == 1 ? code * slot_bytes
+                                           : (sl < ns ? sl * slot_bytes : kLpfSkip);
+                    }
+                }
+                if constexpr (PREC == CBH_PREC_INT16) {
+                    const uint4 x = *reinterpret_cast<const uint4*>(a.gq + ih);
+                    const uint4 y = *reinterpret_cast<const uint4*>(a.gq + ih + 4);
+                    qv[0] = x.x; qv[1] = x.y; qv[2] = x.z; qv[3] = x.w;
+                    qv[4] = y.x; qv[5] = y.y; qv[6] = y.z; qv[7] = y.w;
+                } else {
+                    const float4 x = *reinterpret_cast<const float4*>(a.g + ih);
+                    const float4 y = *reinterpret_cast<const float4*>(a.g + ih + 4);
+                    gv[0] = x.x; gv[1] = x.y; gv[2] = x.z; gv[3] = x.w;
+                    gv[4] = y.x; gv[5] = y.y; gv[6] = y.z; gv[7] = y.w;
+                    if constexpr (RM == 0) {
+                        const float4 u = *reinterpret_cast<const float4*>(a.h + ih);
+                        const float4 w = *reinterpret_cast<const float4*>(a.h + ih + 4);
+                        hv[0] = u.x; hv[1] = u.y; hv[2] = u.z; hv[3] = u.w;
+                        hv[4] = w.x; hv[5] = w.y; hv[6] = w.z; hv[7] = w.w;
+                    }
+                }
+                if (fok) lpf_rows8<PREC, RM, W, MODE == 2>(tile, bw, 8 * h2, lane_off, off, gv, hv, qv);
+            }
+        }
+    }
+    // the ragged last segment, and everything when a pointer is unaligned:
+    // one row at a time
+    for (; t < ((r1 + 15) >> 4); t += int64_t(nwaves) * RG) {
+        const int64_t i = t << 4;
+        const uint8_t* pb = col + t * sstride;
+        for (int r = 0; r < 16 && i + r < r1; ++r) {
+            const uint32_t bwr[4] = {(uint32_t)pb[r], 0u, 0u, 0u};
+            uint32_t o1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+            float g1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float h1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            uint32_t q1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+            if constexpr (MODE != 0) {
+                const uint32_t code = rowcode[i + r];
+                const uint32_t sl = code - s0;
+                o1[0] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
+            }
+            if constexpr (PREC == CBH_PREC_INT16) {
+                q1[0] = a.gq[i + r];
+            } else {
+                g1[0] = a.g[i + r];
+                if constexpr (RM == 0) h1[0] = a.h[i + r];
+            }
+            if (fok && o1[0] != kLpfSkip) {
+                // one row: use the per-row routine on a segment holding only this bin
+                constexpr uint32_t CSz = lpf_cell_bytes<PREC>();
+                const uint32_t ad = lpf_addr<W, CSz>(bwr, 0, lane_off) + o1[0];
+                if constexpr (PREC == CBH_PREC_INT16) {
+                    const uint64_t packed =
+                        ((uint64_t)(int64_t)(int16_t)(q1[0] & 0xffffu) << 32) +
+                        ((q1[0] >> 16) & 0x7fffu);
+                    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(tile + ad),
+                                           (unsigned long long)packed, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad), (double)g1[0],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if constexpr (RM != 0)
+                        __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad + W * 8), 1u,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    else
+                        __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad + W * 8),
+                                               (double)h1[0], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // write the tile in the partial's [L][F][B][wpc] order; consecutive threads
+    // take consecutive features of one (slot, bin), so the LDS reads are
+    // conflict-free and every thread writes one whole cell
+    uint32_t* part = a.partials + chunk * (int64_t(a.L) * a.F * a.B * a.wpc);
+    const uint32_t cells = ns * (uint32_t)a.B * W;
+    for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) {
+        const uint32_t cfl = c & (W - 1);
+        if ((int)cfl >= nf) continue;
+        const uint32_t sb = c / W;                 // slot * B + bin
+        const uint32_t bin = sb % (uint32_t)a.B, sl = sb / (uint32_t)a.B;
+        const char* cell = tile + (size_t)sb * W * CS + cfl * 8u;   // first stat; second at + W * 8
+        const int64_t o = ((int64_t(s0 + sl) * a.F + f0 + cfl) * a.B + bin) * a.wpc;
+        if constexpr (PREC == CBH_PREC_INT16) {
+            *reinterpret_cast<uint2*>(part + o) = *reinterpret_cast<const uint2*>(cell);
+        } else {
+            const double gs = *reinterpret_cast<const double*>(cell);
+            const float ghi = (float)gs;
+            uint32_t w1;                               // count or h, as stored in the output
+            float hlo = 0.f;
+            if constexpr (RM != 0) {
+                w1 = *reinterpret_cast<const uint32_t*>(cell + W * 8);
+            } else {
+                const double hs = *reinterpret_cast<const double*>(cell + W * 8);
+                const float hhi = (float)hs;
+                hlo = (float)(hs - (double)hhi);
+                w1 = __float_as_uint(hhi);
+            }
+            if constexpr (PREC == CBH_PREC_FP32) {
+                *reinterpret_cast<uint2*>(part + o) = make_uint2(__float_as_uint(ghi), w1);
+            } else {
+                const float glo = (float)(gs - (double)ghi);
+                *reinterpret_cast<uint4*>(part + o) =
+                    make_uint4(__float_as_uint(ghi), __float_as_uint(glo), w1,
+                               RM != 0 ? 0u : __float_as_uint(hlo));
+            }
+        }
+    }
+}
+
 void hist_init_attrs(int max_lds) {
     const void* fns[] = {
         (const void*)hist_kernel<CBH_PREC_FP32, 1, 0>, (const void*)hist_kernel<CBH_PREC_FP32, 1, 1>,
@@ -389,6 +682,62 @@ void hist_init_attrs(int max_lds) {
         (const void*)hist_kernel<CBH_PREC_INT16, 0, 0>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+#define CBH_LPF_ATTR(P, R, M)                                                                \
+    {                                                                                        \
+        const void* l[] = {(const void*)hist_lpf_kernel<P, R, 32, M>,                        \
+                           (const void*)hist_lpf_kernel<P, R, 16, M>,                        \
+                           (const void*)hist_lpf_kernel<P, R, 8, M>,                         \
+                           (const void*)hist_lpf_kernel<P, R, 4, M>};                        \
+        for (const void* f : l)                                                              \
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds); \
+    }
+#define CBH_LPF_ATTR3(P, R) CBH_LPF_ATTR(P, R, 0) CBH_LPF_ATTR(P, R, 1) CBH_LPF_ATTR(P, R, 2)
+    CBH_LPF_ATTR3(CBH_PREC_FP32, 0)
+    CBH_LPF_ATTR3(CBH_PREC_FP32, 1)
+    CBH_LPF_ATTR3(CBH_PREC_TWOFLOAT, 0)
+    CBH_LPF_ATTR3(CBH_PREC_TWOFLOAT, 1)
+    CBH_LPF_ATTR3(CBH_PREC_INT16, 0)
+#undef CBH_LPF_ATTR3
+#undef CBH_LPF_ATTR
+}
+
+// Row codes for a lanes-over-features build by subtraction: the parent
+// p = leaf & lmask if the row is on the parent's accumulated side
+// (bit `shift` of the leaf equals side[p]), else 0xffff.
+__global__ __launch_bounds__(256) void slot_code_kernel(const uint16_t* __restrict__ leaf,
+                                                        const uint8_t* __restrict__ side,
+                                                        int64_t n, uint32_t lmask, uint32_t shift,
+                                                        uint16_t* __restrict__ code) {
+    const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i = tid; i < n; i += stride) {
+        const uint32_t v = leaf[i];
+        const uint32_t p = v & lmask;
+        code[i] = (uint16_t)((((v >> shift) & 1u) == (uint32_t)side[p]) ? p : 0xffffu);
+    }
+}
+
+template <int PREC, int RM, int MODE>
+static void launch_lpf_mode(const HistArgs& a, const HistPlan& plan, hipStream_t s) {
+    const unsigned grid = (unsigned)(8 * ((plan.n_blocks + 7) / 8));
+    const size_t lds = (size_t)plan.lds_bytes;
+    switch (plan.fb) {
+        case 32: hist_lpf_kernel<PREC, RM, 32, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 16: hist_lpf_kernel<PREC, RM, 16, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 8: hist_lpf_kernel<PREC, RM, 8, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
+        default: hist_lpf_kernel<PREC, RM, 4, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
+    }
+}
+
+template <int PREC, int RM>
+static void launch_lpf(const HistArgs& a, const HistPlan& plan, hipStream_t s) {
+    if (a.L == 1 && !a.side) launch_lpf_mode<PREC, RM, 0>(a, plan, s);
+    else if (!a.side && plan.n_ltiles == 1) launch_lpf_mode<PREC, RM, 1>(a, plan, s);
+    else launch_lpf_mode<PREC, RM, 2>(a, plan, s);
+}
+
+int64_t hist_code_bytes(const HistPlan& plan, int64_t n, bool sub) {
+    return plan.kind == 1 && sub ? align_up(n * 2, 256) : 0;
 }
 
 template <int PREC>
@@ -396,6 +745,16 @@ static void launch_hist_prec(const HistArgs& a, const HistPlan& plan, int max_ld
                              hipStream_t s) {
     const int64_t grid = 8 * ((plan.n_blocks + 7) / 8);
     (void)max_lds;
+    if (plan.kind == 1) {
+        if constexpr (PREC != CBH_PREC_INT16) {
+            if (a.rmse) {
+                launch_lpf<PREC, 1>(a, plan, s);
+                return;
+            }
+        }
+        launch_lpf<PREC, 0>(a, plan, s);
+        return;
+    }
     // MultiClass (K > 1) is never RMSE; K = 1 has an RMSE (count) and a
     // second-derivative form
     if (a.K > 1)
@@ -408,9 +767,23 @@ static void launch_hist_prec(const HistArgs& a, const HistPlan& plan, int max_ld
 
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
-                const void* parent, const uint8_t* side) {
+                const void* parent, const uint8_t* side, uint16_t* codes) {
     HistArgs a;
+    a.rowcode = p->leaf;
+    if (plan.kind == 1 && parent) {
+        if (!codes) {
+            set_error("internal: no row-code buffer for a build by subtraction");
+            return CBH_EINVAL;
+        }
+        slot_code_kernel<<<(unsigned)std::min<int64_t>((p->n + 255) / 256,
+                                                       int64_t(ctx->num_cus) * 8),
+                           256, 0, s>>>(p->leaf, side, p->n, (uint32_t)(1 << (level - 1)) - 1u,
+                                        (uint32_t)(level - 1), codes);
+        CBH_LAUNCHED();
+        a.rowcode = codes;
+    }
     a.bins = p->bins;
+    a.seg = p->seg_stride;
     a.g = p->g;
     a.h = p->h;
     a.gq = reinterpret_cast<const uint32_t*>(p->gq);
@@ -627,14 +1000,18 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
     const int64_t part_bytes = align_up(
         int64_t(plan.n_chunks) * half * prob->n_features * prob->max_bins * plan.words_per_cell * 4,
         256);
-    rc = ensure_ws(ctx, part_bytes + align_up(half, 256));
+    const int64_t code_bytes = hist_code_bytes(plan, prob->n, true);
+    rc = ensure_ws(ctx, part_bytes + align_up(half, 256) + code_bytes);
     if (rc) return rc;
     uint8_t* side = (uint8_t*)ctx->ws + part_bytes;
+    uint16_t* codes =
+        code_bytes ? (uint16_t*)((uint8_t*)ctx->ws + part_bytes + align_up(half, 256)) : nullptr;
     hipStream_t s = (hipStream_t)stream;
     rc = launch_side(parent_hist, parent_split, half, prob->n_features, prob->max_bins, prob->K,
                      rmse, precision, side, s);
     if (rc) return rc;
-    return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side);
+    return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side,
+                       codes);
 }
 
 }  // extern "C"

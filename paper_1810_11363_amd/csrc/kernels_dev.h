@@ -31,8 +31,19 @@ namespace cbh {
 // load of bins per feature (a wave reads 512 B or 1 KB contiguous per
 // feature), and loads for 4 features are issued before their LDS updates so
 // that memory latency overlaps.
+// Bin of row i of a feature whose 16-row segments start `stride` bytes apart
+// (16 for a plain column).
+__device__ __forceinline__ const uint8_t* seg_ptr(const uint8_t* base, int64_t stride,
+                                                   int64_t i) {
+    return base + (i >> 4) * stride + (i & 15);
+}
+__device__ __forceinline__ int64_t seg_stride_of(const int64_t* seg, int f) {
+    return seg ? seg[f] : 16;
+}
+
 struct TileArgs {
     const uint8_t* const* bins;
+    const int64_t* seg = nullptr;   // per-feature segment strides, NULL = columns
     const float* g;
     const float* h;
     const uint32_t* gq;
@@ -122,8 +133,9 @@ __device__ __forceinline__ void add_row(uint32_t* lds, uint32_t ncells, uint32_t
 // ROWS (8 or 16) bins of rows i.. of one column (any alignment of the column),
 // in .x .y (.z .w) little-endian order.
 template <int ROWS>
-__device__ __forceinline__ uint4 load_bins(const uint8_t* col, int64_t i) {
-    const uint8_t* p = col + i;
+__device__ __forceinline__ uint4 load_bins(const uint8_t* col, int64_t stride, int64_t i) {
+    // i is a multiple of ROWS (8 or 16), so the ROWS rows share one segment
+    const uint8_t* p = seg_ptr(col, stride, i);
     if constexpr (ROWS == 16) {
         if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) return *reinterpret_cast<const uint4*>(p);
     } else {
@@ -253,8 +265,10 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
             uint4 bb[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                bb[u] = (j0 + u < a.nf) ? load_bins<ROWS>(a.bins[a.f0 + j0 + u], i)
-                                        : make_uint4(0u, 0u, 0u, 0u);
+                bb[u] = (j0 + u < a.nf)
+                            ? load_bins<ROWS>(a.bins[a.f0 + j0 + u],
+                                              seg_stride_of(a.seg, a.f0 + j0 + u), i)
+                            : make_uint4(0u, 0u, 0u, 0u);
             for (int c = 0; c < K; ++c) {
                 if constexpr (KT != 1) load_grad<PREC, ROWS>(a, c, i, vec, rmse, gv, hv, qv);
 #pragma unroll
@@ -290,7 +304,9 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
                     if (!rmse) h1 = a.h[ci];
                 }
                 for (int j = 0; j < a.nf; ++j) {
-                    const uint32_t bin = min((uint32_t)a.bins[a.f0 + j][i], Bm1);
+                    const uint32_t bin = min(
+                        (uint32_t)*seg_ptr(a.bins[a.f0 + j], seg_stride_of(a.seg, a.f0 + j), i),
+                        Bm1);
                     add_row<PREC, RM>(lds, ncells, l * fbu + (uint32_t)j, Bs, bin, c, K, rep,
                                       replica, g1, h1, q1);
                 }
@@ -682,8 +698,9 @@ __device__ inline void argmax_features(const FeatBest* __restrict__ fb, int F, i
 
 // leaf |= [bin > k] << level for rows [i0, i1) (level 0 overwrites); a
 // missing split (f < 0) leaves the bit clear.
-__device__ __forceinline__ void apply_rows(const uint8_t* const* bins, int F, cbh_split sp,
-                                           uint16_t* leaf, int64_t i0, int64_t i1, int level) {
+__device__ __forceinline__ void apply_rows(const uint8_t* const* bins, const int64_t* seg,
+                                           int F, cbh_split sp, uint16_t* leaf, int64_t i0,
+                                           int64_t i1, int level) {
     int f = sp.feature, k = sp.border;
     if (f < 0 || f >= F) {
         if (level != 0) return;
@@ -691,10 +708,11 @@ __device__ __forceinline__ void apply_rows(const uint8_t* const* bins, int F, cb
         k = 255;
     }
     const uint8_t* col = bins[f];
+    const int64_t stride = seg_stride_of(seg, f);
     const uint32_t bit = 1u << level;
     for (int64_t i = i0; i < i1; ++i) {
         const uint32_t old = level == 0 ? 0u : leaf[i];
-        leaf[i] = (uint16_t)(old | (((int)col[i] > k) ? bit : 0u));
+        leaf[i] = (uint16_t)(old | (((int)*seg_ptr(col, stride, i) > k) ? bit : 0u));
     }
 }
 

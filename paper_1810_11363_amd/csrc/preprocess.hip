@@ -317,6 +317,31 @@ __global__ __launch_bounds__(256) void ts_scatter_kernel(
     }
 }
 
+// ------------------------------------------------------------- tile bins
+// Unit u = (column c, segment t), t fastest, so a wave reads one column
+// contiguously; each unit writes its 16 bytes to out + (t * n_cols + c) * 16.
+__global__ __launch_bounds__(256) void tile_bins_kernel(const uint8_t* const* __restrict__ cols,
+                                                        int32_t n_cols, int64_t n, int64_t T,
+                                                        uint8_t* __restrict__ out) {
+    const int64_t units = T * n_cols;
+    for (int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x; u < units;
+         u += int64_t(gridDim.x) * 256) {
+        const int32_t c = (int32_t)(u / T);
+        const int64_t t = u - int64_t(c) * T;
+        const uint8_t* src = cols[c] + 16 * t;
+        uint4 v;
+        if (16 * t + 16 <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            v = *reinterpret_cast<const uint4*>(src);
+        } else {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (int r = 0; r < 16; ++r)
+                if (16 * t + r < n) w[r >> 2] |= (uint32_t)src[r] << (8 * (r & 3));
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        *reinterpret_cast<uint4*>(out + (t * n_cols + c) * 16) = v;
+    }
+}
+
 static int grid_for(int64_t n, int per_block, int cap = 16384) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -343,6 +368,21 @@ int cbh_quantize(cbh_ctx* ctx, const float* x, int64_t n, const float* borders,
     hipStream_t s = (hipStream_t)stream;
     quantize_kernel<<<grid_for((n + 3) / 4, 256, ctx->num_cus * 8), 256, 0, s>>>(
         x, n, borders, n_borders, bins_out, ctx->d_flags);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_tile_bins(cbh_ctx* ctx, const uint8_t* const* cols, int32_t n_cols, int64_t n,
+                  uint8_t* out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(cols && out, "cols / out is NULL");
+    CBH_ARG(n >= 1, "n must be >= 1");
+    CBH_ARG(n_cols >= 1 && n_cols <= 65535, "n_cols must be in [1, 65535] (got %d)", n_cols);
+    CBH_ARG((reinterpret_cast<uintptr_t>(out) & 15) == 0, "out must be 16-byte aligned");
+    const int64_t T = (n + 15) / 16;
+    tile_bins_kernel<<<grid_for(T * n_cols, 256, ctx->num_cus * 8), 256, 0,
+                       (hipStream_t)stream>>>(cols, n_cols, n, T, out);
     CBH_LAUNCHED();
     return CBH_OK;
 }

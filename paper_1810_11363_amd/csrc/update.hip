@@ -17,6 +17,7 @@
 namespace cbh {
 
 __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* __restrict__ bins,
+                                                          const int64_t* __restrict__ seg,
                                                           int32_t F, const cbh_split* __restrict__ best,
                                                           uint16_t* __restrict__ leaf, int64_t n,
                                                           int32_t level) {
@@ -29,6 +30,7 @@ __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* 
         k = 255;
     }
     const uint8_t* __restrict__ col = bins[f];
+    const int64_t sstride = seg ? seg[f] : 16;   // bytes between 16-row segments
     const uint32_t bit = 1u << level;
     const int64_t n8 = n / 8;
     const bool vec = ((reinterpret_cast<uintptr_t>(col) & 7) == 0);
@@ -36,7 +38,8 @@ __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* 
     const int64_t stride = int64_t(gridDim.x) * 256;
     if (vec) {
         for (int64_t q = tid; q < n8; q += stride) {
-            const uint2 b = reinterpret_cast<const uint2*>(col)[q];
+            // rows 8q .. 8q+7 lie in one 16-row segment
+            const uint2 b = *reinterpret_cast<const uint2*>(col + (q >> 1) * sstride + 8 * (q & 1));
             uint4 l = level == 0 ? make_uint4(0u, 0u, 0u, 0u)
                                  : reinterpret_cast<const uint4*>(leaf)[q];
             uint32_t lw[4] = {l.x, l.y, l.z, l.w};
@@ -49,12 +52,12 @@ __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* 
         }
         for (int64_t i = n8 * 8 + tid; i < n; i += stride) {
             const uint32_t old = level == 0 ? 0u : leaf[i];
-            leaf[i] = (uint16_t)(old | (((int)col[i] > k) ? bit : 0u));
+            leaf[i] = (uint16_t)(old | (((int)col[(i >> 4) * sstride + (i & 15)] > k) ? bit : 0u));
         }
     } else {
         for (int64_t i = tid; i < n; i += stride) {
             const uint32_t old = level == 0 ? 0u : leaf[i];
-            leaf[i] = (uint16_t)(old | (((int)col[i] > k) ? bit : 0u));
+            leaf[i] = (uint16_t)(old | (((int)col[(i >> 4) * sstride + (i & 15)] > k) ? bit : 0u));
         }
     }
 }
@@ -207,7 +210,7 @@ static int grid_rows(const cbh_ctx* ctx, int64_t n, int per_thread = 1) {
 
 int launch_apply(const cbh_ctx* ctx, const cbh_problem* p, int32_t level, const cbh_split* best,
                  hipStream_t s) {
-    apply_split_kernel<<<grid_rows(ctx, p->n, 8), 256, 0, s>>>(p->bins, p->n_features, best,
+    apply_split_kernel<<<grid_rows(ctx, p->n, 8), 256, 0, s>>>(p->bins, p->seg_stride, p->n_features, best,
                                                                p->leaf, p->n, level);
     CBH_LAUNCHED();
     return CBH_OK;

@@ -235,6 +235,127 @@ def test_histograms_vs_oracle(cb, ctx, case, prec):
         assert np.allclose(got[:, f].sum(axis=1), tot, rtol=1e-5, atol=1e-3)
 
 
+# ---------------------------------------------- tiled layout and both kernels
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 100003])
+def test_tile_bins_bit_exact(cb, ctx, n):
+    F = 5
+    g = np.random.default_rng(n)
+    cols = g.integers(0, 256, (F, n + 3)).astype(np.uint8)
+    bd = gu.to_dev(cols)
+    # column 2 starts one byte into its row: an unaligned column
+    ptrs = torch.tensor([bd[f].data_ptr() + (1 if f == 2 else 0) for f in range(F)],
+                        dtype=torch.int64, device=gu.dev())
+    src = np.stack([cols[f, 1:n + 1] if f == 2 else cols[f, :n] for f in range(F)])
+    T = (n + 15) // 16
+    out = torch.full((T, F, 16), 7, dtype=torch.uint8, device=gu.dev())
+    cb.cbh_tile_bins(ctx, ptrs, F, n, out)
+    cb.cbh_sync(ctx)
+    want = np.zeros((F, T * 16), np.uint8)
+    want[:, :n] = src
+    assert np.array_equal(out.cpu().numpy(), want.reshape(F, T, 16).transpose(1, 0, 2))
+    with pytest.raises(cb.CbhError):
+        cb.cbh_tile_bins(ctx, ptrs, 0, n, out)
+    with pytest.raises(cb.CbhError):
+        cb.cbh_tile_bins(ctx, ptrs, F, n, out.view(-1)[1:])     # unaligned output
+
+
+def _tiled_problem(cb, ctx, p, dev, n, F):
+    """Re-point a column problem at a tiled copy of its bins."""
+    T = (n + 15) // 16
+    tiled = torch.empty((T, F, 16), dtype=torch.uint8, device=gu.dev())
+    cb.cbh_tile_bins(ctx, dev["cols"], F, n, tiled)
+    cols = torch.tensor([tiled.data_ptr() + 16 * f for f in range(F)], dtype=torch.int64,
+                        device=gu.dev())
+    seg = torch.full((F,), 16 * F, dtype=torch.int64, device=gu.dev())
+    dev.update(tiled=tiled, tcols=cols, seg=seg)
+    p.bins = cols.data_ptr()
+    p.seg_stride = seg.data_ptr()
+    return p
+
+
+KERNEL_CONFIGS = [(0, 0), (1, 32), (1, 16), (1, 8), (1, 4)]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("layout", ["columns", "tiled"])
+@pytest.mark.parametrize("kcfg", KERNEL_CONFIGS)
+@pytest.mark.parametrize("case", [(20011, 37, 128, 0, 0), (20011, 37, 128, 1, 3),
+                                  (9001, 21, 255, 0, 5)])
+def test_histogram_kernels_and_layouts(cb, ctx, case, kcfg, layout, prec):
+    """Both histogram kernels, every lane-group width, plain columns and the
+    tiled layout, several chunks (small rows per block) and a ragged tail."""
+    n, F, B, loss, level = case
+    nb, bins, leaf, gg, hh, label = _random_level(n + level, n, F, B, 1, loss, level)
+    p, dev = _device_problem(cb, n, F, B, 1, loss, level + 1, nb, bins, leaf, gg, hh, label)
+    if layout == "tiled":
+        p = _tiled_problem(cb, ctx, p, dev, n, F)
+    L = 1 << level
+    esz = 4 if prec == 0 else 8
+    hist = torch.empty(L * F * B * 2 * esz, dtype=torch.uint8, device=gu.dev())
+    kernel, w = kcfg
+    cb.cbh_set_hist_knobs(ctx, 160 * 1024, 512, 2048, 100, 8, 8, kernel, w)
+    try:
+        if prec == 2:
+            cb.cbh_quantize_gradients(ctx, p)
+        cb.cbh_build_histograms(ctx, p, level, prec, hist)
+        cb.cbh_sync(ctx)
+    finally:
+        cb.cbh_set_hist_knobs(ctx, 0)
+    got = gu.hist_to_f64(hist, L, F, B, 1, prec, loss == 0)
+    if prec == 2:
+        rgq, rhq, _ = oracle.grad_codes(gg, hh, loss != 0)
+        assert np.array_equal(got, oracle.histogram_int(bins, rgq, rhq, leaf, L, B))
+        return
+    want = oracle.histogram(bins, gg.astype(np.float64), hh.astype(np.float64), leaf, L, B)
+    mag = oracle.histogram(bins, np.abs(gg).astype(np.float64), np.abs(hh).astype(np.float64),
+                           leaf, L, B)
+    assert gu.normalized_err(got, want, mag) <= (gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL)
+    if loss == 0:
+        assert np.array_equal(got[..., 1::2], want[..., 1::2])
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("kcfg", [(0, 0), (1, 32), (1, 8)])
+def test_subtraction_kernels_vs_oracle(cb, ctx, kcfg, prec):
+    """A level built by subtraction (smaller child accumulated, sibling =
+    parent - child) with each kernel, on the tiled layout, against the oracle
+    on the leaves the parent's split produced."""
+    n, F, B, loss, level = 30011, 19, 64, 0, 3
+    nb, bins, leaf, gg, hh, label = _random_level(11, n, F, B, 1, loss, level - 1)
+    p, dev = _device_problem(cb, n, F, B, 1, loss, level + 1, nb, bins, leaf, gg, hh, label)
+    p = _tiled_problem(cb, ctx, p, dev, n, F)
+    esz = 8
+    parent = torch.empty((1 << (level - 1)) * F * B * 2 * esz, dtype=torch.uint8,
+                         device=gu.dev())
+    child = torch.empty((1 << level) * F * B * 2 * esz, dtype=torch.uint8, device=gu.dev())
+    best = torch.zeros((level + 1, 4), dtype=torch.int32, device=gu.dev())
+    kernel, w = kcfg
+    cb.cbh_set_hist_knobs(ctx, 160 * 1024, 512, 2048, 100, 8, 8, kernel, w)
+    try:
+        if prec == 2:
+            cb.cbh_quantize_gradients(ctx, p)
+        cb.cbh_build_histograms(ctx, p, level - 1, prec, parent)
+        sp = best.data_ptr() + 16 * (level - 1)
+        cb.cbh_score_splits(ctx, p, level - 1, parent, prec, 3.0, sp)
+        cb.cbh_apply_split(ctx, p, level - 1, sp)
+        cb.cbh_build_histograms_sub(ctx, p, level, prec, parent, sp, child)
+        cb.cbh_sync(ctx)
+    finally:
+        cb.cbh_set_hist_knobs(ctx, 0)
+    L = 1 << level
+    leaf2 = dev["leaf"].cpu().numpy()
+    got = gu.hist_to_f64(child, L, F, B, 1, prec, True)
+    if prec == 2:
+        rgq, rhq, _ = oracle.grad_codes(gg, hh, False)
+        assert np.array_equal(got, oracle.histogram_int(bins, rgq, rhq, leaf2, L, B))
+        return
+    want = oracle.histogram(bins, gg.astype(np.float64), hh.astype(np.float64), leaf2, L, B)
+    mag = oracle.histogram(bins, np.abs(gg).astype(np.float64), np.abs(hh).astype(np.float64),
+                           leaf2, L, B)
+    assert gu.normalized_err(got, want, mag) <= gu.TWOFLOAT_TOL
+    assert np.array_equal(got[..., 1::2], want[..., 1::2])
+
+
 def test_int16_histogram_deterministic(cb, ctx):
     n, F, B, K, loss, level = 70001, 6, 128, 1, 1, 3
     nb, bins, leaf, gg, hh, label = _random_level(3, n, F, B, K, loss, level)
