@@ -12,8 +12,9 @@ turn: the headline form (default: compensated two-float, which meets the
 1e-5 error bar) and, beside it, plain float32 and int16. Each form is
 autotuned first (untimed), then `--warmup` trees run, one tree per permutation
 is captured into a HIP graph, and `--steps` trees are replayed and timed with
-events around the whole loop. The histogram build is then timed on its own:
-each level's build repeated back to back with events around the repeats.
+events around the whole loop. The histogram build is then timed inside
+trees: `--hist-trees` more trees are replayed from graphs that hold event nodes
+around every build (each tree read back before the next replay).
 After timing, one more tree is grown level by level and its histograms on
 sampled features are kept; the oracle leg at the end (with the CPU timing of
 the oracle) compares them with FP64 and reports the largest normalised error.
@@ -38,6 +39,19 @@ METRIC = "sec/tree and histogram G row-features/s vs plain FP32, ≤1e-5 rel err
 PEAK_HBM_GBS = 8000.0
 PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2}
 DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64"}
+
+
+class Stamp:
+    """Duck-typed event for the booster's fit_tree: record() enqueues the
+    library's device-clock stamp into one slot of a device buffer, which a
+    stream capture turns into a graph node (events cannot be recorded inside
+    a HIP graph)."""
+
+    def __init__(self, cb, ctx, buf, idx):
+        self.cb, self.ctx, self.ptr = cb, ctx, buf.data_ptr() + 8 * idx
+
+    def record(self, stream):
+        self.cb.cbh_device_timestamp(self.ctx, self.ptr, stream)
 
 
 def hist_bytes_per_level(n, F, K, level, rmse, precision):
@@ -167,23 +181,34 @@ def snapshot_tree(bst, t, rng, n_feat=4):
                          bst.split_ptr(bst.depth - 1), bst.lr, bst.l2, bst.leaf_values, None,
                          bst.stream)
     torch.cuda.synchronize()
-    return {"bins": bins, "g": g, "h": h, "B": bst.B, "levels": levels}
+    scale = bst.grad_scale.cpu().numpy().astype(np.float64) if bst.precision == 2 else None
+    return {"bins": bins, "g": g, "h": h, "B": bst.B, "levels": levels, "scale": scale,
+            "rmse": bst.loss == 0}
 
 
 def oracle_error(snap):
     """Largest error of the snapshot's histograms against the FP64 oracle,
-    normalised by the sum of magnitudes of each bin's terms."""
+    normalised by the sum of magnitudes of each bin's terms; for int16 codes
+    also the largest g-sum error over its quantisation bound n_bin * s_g / 2
+    (each code rounds g to the nearest multiple of s_g), which must be <= 1."""
     import numpy as np
 
     import oracle
-    worst = 0.0
+    worst, worst_q = 0.0, None
     for L, fs, leaf, got in snap["levels"]:
-        want = oracle.histogram(snap["bins"][fs], snap["g"], snap["h"], leaf, L, snap["B"])
-        mag = oracle.histogram(snap["bins"][fs], np.abs(snap["g"]), np.abs(snap["h"]), leaf, L,
-                               snap["B"])
+        bins = snap["bins"][fs]
+        want = oracle.histogram(bins, snap["g"], snap["h"], leaf, L, snap["B"])
+        mag = oracle.histogram(bins, np.abs(snap["g"]), np.abs(snap["h"]), leaf, L, snap["B"])
         m = mag > 0
         worst = max(worst, float((np.abs(got - want)[m] / mag[m]).max()))
-    return worst
+        if snap["scale"] is not None:
+            one = np.ones_like(snap["g"])
+            cnt = oracle.histogram(bins, one, one, leaf, L, snap["B"])[..., 1::2]
+            bound = cnt * snap["scale"][:, 0] / 2
+            err = np.abs(got[..., 0::2] - want[..., 0::2])
+            q = float((err[bound > 0] / bound[bound > 0]).max())
+            worst_q = q if worst_q is None else max(worst_q, q)
+    return worst, worst_q
 
 
 def time_form(bst, name, args, rmse):
@@ -225,34 +250,42 @@ def time_form(bst, name, args, rmse):
     t_wall = time.perf_counter() - t_wall
     cb.cbh_sync(bst.ctx, stream)
     total_ms = start.elapsed_time(stop)
-    # the histogram build alone: every level's build repeated back to back
-    # with events around the repeats (builds are idempotent for a fixed leaf
-    # state), then scored and applied to move to the next level
-    reps = args.hist_repeats
-    pr = bst.probs[(args.warmup + args.steps) % bst.s]
-    if prec == 2:
-        cb.cbh_quantize_gradients(bst.ctx, pr, stream)
-    hist_ms = np.zeros((1, depth))
-    for lvl in range(depth):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        bst.build_level_histograms(pr, lvl)
-        e0.record(stream)
-        for _ in range(reps):
-            bst.build_level_histograms(pr, lvl)
-        e1.record(stream)
-        cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), prec, bst.l2,
-                            bst.split_ptr(lvl), None, stream)
-        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), stream)
+    # the histogram build alone, inside real trees: one more graph per
+    # permutation with event nodes around every build; each replay is a whole
+    # tree, read back before the next replay of the same graph
+    n_hist = max(1, args.hist_trees)
+    hist_ms = np.zeros((n_hist, depth))
+    if not args.no_graph:
+        timing = "device-clock stamps around every build, captured in the tree graphs"
+        khz = cb.cbh_device_clock_khz(bst.ctx)
+        buf = torch.zeros(bst.s * depth * 2, dtype=torch.int64, device=bst.device)
+        stamps = [[(Stamp(cb, bst.ctx, buf, (r * depth + l) * 2),
+                    Stamp(cb, bst.ctx, buf, (r * depth + l) * 2 + 1)) for l in range(depth)]
+                  for r in range(bst.s)]
+        timed = bst.capture_trees(events=stamps)
+        with torch.cuda.stream(stream):
+            for s in range(n_hist):
+                t = args.warmup + args.steps + s
+                timed[t % bst.s].replay()
+                torch.cuda.synchronize()
+                v = buf.view(bst.s, depth, 2)[t % bst.s].cpu().numpy()
+                hist_ms[s] = (v[:, 1] - v[:, 0]) / khz
+    else:
+        timing = "events around the builds of eagerly launched trees"
+        ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(depth)] for _ in range(n_hist)]
+        with torch.cuda.stream(stream):
+            for s in range(n_hist):
+                bst.fit_tree(args.warmup + args.steps + s, events=ev[s])
         torch.cuda.synchronize()
-        hist_ms[0, lvl] = e0.elapsed_time(e1) / reps
-    cb.cbh_update_approx(bst.ctx, pr, bst.hist_ptr(depth - 1), prec, bst.split_ptr(depth - 1),
-                         bst.lr, bst.l2, bst.leaf_values, None, stream)
+        hist_ms[:] = [[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(depth)]
+                      for s in range(n_hist)]
     sec_per_tree = total_ms / 1e3 / args.steps
     rf_per_tree = n * F * depth
     bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec) for l in range(depth)])
     hist_s_per_tree = hist_ms.sum(axis=1).mean() / 1e3
     achieved = float(bytes_lvl.sum() / hist_s_per_tree / 1e9)
-    snap = snapshot_tree(bst, args.warmup + args.steps, np.random.default_rng(1)) \
+    snap = snapshot_tree(bst, args.warmup + args.steps + n_hist, np.random.default_rng(1)) \
         if not args.no_cpu else None
     print(f"# {name}: {sec_per_tree * 1e3:.3f} ms/tree, hist {hist_s_per_tree * 1e3:.3f} ms",
           file=sys.stderr, flush=True)
@@ -264,6 +297,7 @@ def time_form(bst, name, args, rmse):
         "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
         "hist_subtraction": bool(bst.subtract),
         "graph_replay": not args.no_graph,
+        "hist_timing": timing,
         "max_norm_err_vs_fp64": None,      # filled by the oracle leg
         "_snapshot": snap,
         "autotune_s": round(t_tune, 2),
@@ -292,8 +326,8 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=20)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every call from Python instead of replaying captured trees")
-    ap.add_argument("--hist-repeats", type=int, default=20,
-                    help="back-to-back builds per level for the histogram timing")
+    ap.add_argument("--hist-trees", type=int, default=40,
+                    help="trees replayed from graphs with event nodes around every build")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle leg (CPU timing and error vs FP64)")
     ap.add_argument("--autotune", default="run",
@@ -365,7 +399,9 @@ def main():
     for f, r in results.items():
         snap = r.pop("_snapshot")
         if snap is not None:
-            r["max_norm_err_vs_fp64"] = oracle_error(snap)
+            r["max_norm_err_vs_fp64"], q = oracle_error(snap)
+            if q is not None:
+                r["max_g_err_over_quant_bound"] = q
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(datagen.make_c2(n=args.n), args.cpu_rows,

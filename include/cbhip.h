@@ -165,6 +165,15 @@ int64_t cbh_workspace_size(const cbh_ctx* ctx);
  * the previous cbh_sync, and clear them. */
 int cbh_sync(cbh_ctx* ctx, void* stream);
 
+/* Instrumentation (not part of the method): write the device's constant-rate
+ * clock (cbh_device_clock_khz ticks per millisecond) to *slot when the stream
+ * reaches this point. Two stamps around other calls on the same stream time
+ * them, also inside a captured graph, where events cannot be recorded.
+ *   slot  device uint64 [1]
+ * Errors: CBH_EINVAL on NULL. */
+int cbh_device_timestamp(cbh_ctx* ctx, uint64_t* slot, void* stream);
+int cbh_device_clock_khz(cbh_ctx* ctx, int64_t* khz);
+
 /* ---- preprocessing -------------------------------------------------------- */
 
 /* Borders of one numeric feature (host computation; Sec. 5: a fixed number of

@@ -282,14 +282,17 @@ class GpuBooster:
                              self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
                              self.leaf_counts if counts else None, st)
 
-    def capture_trees(self):
+    def capture_trees(self, events=None):
         """Capture one tree per permutation into HIP graphs; tree t replays
         graph t mod s on the current stream. Grow at least one tree of every
         permutation first: the library's workspace must have reached its size,
         since a capture may not allocate and a later growth of the workspace
         (or a change of form, which drops the graphs) frees memory the graphs
-        point at."""
-        self.graphs = []
+        point at. `events[r]`: optional per-level (start, end) pairs recorded
+        around the builds of permutation r's tree (objects with a
+        record(stream) method that a capture turns into graph nodes).
+        Returns the list of graphs."""
+        graphs = []
         cap = torch.cuda.Stream(self.device)       # default priority
         eager = self.stream
         torch.cuda.synchronize(self.device)
@@ -298,12 +301,14 @@ class GpuBooster:
             for r in range(self.s):
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=cap):
-                    self.fit_tree(r)
-                self.graphs.append(g)
+                    self.fit_tree(r, events=None if events is None else events[r])
+                graphs.append(g)
         finally:
             self.stream = eager
         torch.cuda.synchronize(self.device)
-        return self.graphs
+        if events is None:
+            self.graphs = graphs
+        return graphs
 
     def replay_tree(self, t: int):
         self.graphs[t % self.s].replay()

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "CBH_OK", -1: "CBH_EINVAL", -2: "CBH_ENOMEM", -3: "CBH_EDEVIC
 # Every symbol include/cbhip.h declares.
 EXPORTS = [
     "cbh_create", "cbh_destroy", "cbh_last_error", "cbh_set_workspace_limit",
-    "cbh_workspace_size", "cbh_sync", "cbh_select_borders", "cbh_uniform_borders",
+    "cbh_workspace_size", "cbh_sync", "cbh_device_timestamp", "cbh_device_clock_khz",
+    "cbh_select_borders", "cbh_uniform_borders",
     "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
     "cbh_build_histograms_sub",
@@ -70,6 +71,8 @@ def _load():
         "cbh_set_workspace_limit": ([vp, i64], C.c_int),
         "cbh_workspace_size": ([vp], i64),
         "cbh_sync": ([vp, vp], C.c_int),
+        "cbh_device_timestamp": ([vp, vp, vp], C.c_int),
+        "cbh_device_clock_khz": ([vp, C.POINTER(i64)], C.c_int),
         "cbh_select_borders": ([vp, i64, i32, vp, C.POINTER(i32)], C.c_int),
         "cbh_uniform_borders": ([dbl, dbl, i32, vp], C.c_int),
         "cbh_quantize": ([vp, vp, i64, vp, i32, vp, vp], C.c_int),
@@ -187,6 +190,16 @@ def cbh_uniform_borders(lo: float, hi: float, n_bins: int):
 def cbh_quantize(ctx, x, n: int, borders, n_borders: int, bins_out, stream=None):
     return _check(_lib.cbh_quantize(ctx, _ptr(x), n, _ptr(borders), n_borders, _ptr(bins_out),
                                     _stream(stream)))
+
+
+def cbh_device_timestamp(ctx, slot, stream=None):
+    return _check(_lib.cbh_device_timestamp(ctx, _ptr(slot), _stream(stream)))
+
+
+def cbh_device_clock_khz(ctx) -> int:
+    v = C.c_int64()
+    _check(_lib.cbh_device_clock_khz(ctx, C.byref(v)))
+    return v.value
 
 
 def cbh_tile_bins(ctx, cols, n_cols: int, n: int, out, stream=None):

@@ -184,10 +184,6 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
         const int L = sub ? 1 << (level - 1) : 1 << level;
         void* out = hbuf[level & 1];
         const void* parent = sub ? hbuf[(level - 1) & 1] : nullptr;
-        if (sub) {
-            rc = launch_side(parent, splits + level - 1, L, F, B, K, rmse, precision, side, s);
-            if (rc) break;
-        }
         float best_ms = 1e30f;
         HistKnobs best_kn = ctx->knobs;
         // candidate knob sets: the rows-over-lanes kernel over LDS budget x
@@ -234,12 +230,13 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
             if (rc) break;
             // warm-up, then the mean of 3 timed runs
             rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
-                             sub ? side : nullptr, codes);
+                             sub ? side : nullptr, codes, sub ? splits + level - 1 : nullptr);
             if (rc) break;
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < 3 && !rc; ++r)
                 rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s,
-                                 parent, sub ? side : nullptr, codes);
+                                 parent, sub ? side : nullptr, codes,
+                                 sub ? splits + level - 1 : nullptr);
             (void)hipEventRecord(e1, s);
             if (rc) break;
             if (hipEventSynchronize(e1) != hipSuccess) {
@@ -272,7 +269,8 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
         rc = ensure_ws(ctx, int64_t(plan.n_chunks) * L * F * B * plan.words_per_cell * 4 +
                                 score_scratch_bytes(prob) + 256);
         if (!rc) rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
-                                  sub ? side : nullptr, codes);
+                                  sub ? side : nullptr, codes,
+                                  sub ? splits + level - 1 : nullptr);
         if (!rc) rc = launch_score(ctx, prob, level, out, precision, 1.0, splits + level, nullptr,
                                    ctx->ws, s);
         if (!rc) rc = launch_apply(ctx, prob, level, splits + level, s);

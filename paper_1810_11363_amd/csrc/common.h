@@ -98,7 +98,7 @@ struct cbh_ctx {
     void* ws = nullptr;
     int64_t ws_size = 0;
     int64_t ws_limit = int64_t(64) << 30;
-    uint32_t* d_flags = nullptr;  // device error flags
+    uint32_t* d_flags = nullptr;  // [0] device error flags, [1] score blocks done (self-resetting)
     cbh::HistKnobs knobs;
     std::map<cbh::TuneKey, cbh::HistKnobs> tuned;
     std::map<cbh::TuneKey, std::string> tuned_note;   // chosen plan and its time, for the cache file
@@ -134,10 +134,13 @@ int validate_precision(const cbh_problem* p, int32_t precision);
 // parent / side: subtraction mode (level >= 1), else NULL.
 // codes: n uint16 of scratch, needed (hist_code_bytes) by the lanes-over-features
 // kernel in subtraction mode.
+// Subtraction mode (parent != NULL): the call derives the smaller child of
+// every parent from `parent` and `parent_split` into `side` (2^(level-1)
+// bytes) before the build.
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
-                const void* parent = nullptr, const uint8_t* side = nullptr,
-                uint16_t* codes = nullptr);
+                const void* parent = nullptr, uint8_t* side = nullptr,
+                uint16_t* codes = nullptr, const cbh_split* parent_split = nullptr);
 int64_t hist_code_bytes(const HistPlan& plan, int64_t n, bool sub);
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores,

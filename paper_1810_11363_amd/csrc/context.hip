@@ -17,7 +17,13 @@ void set_error(const char* fmt, ...) {
     va_end(ap);
 }
 
-void clear_error() { g_err[0] = 0; }
+// Every entry point starts here: the message is reset, and so is the HIP
+// runtime's last-error state, so that a launch check after our own launches
+// reports our launches only.
+void clear_error() {
+    g_err[0] = 0;
+    (void)hipGetLastError();
+}
 
 int ensure_ws(cbh_ctx* ctx, int64_t bytes) {
     bytes = align_up(std::max<int64_t>(bytes, 256), 1 << 20);
@@ -80,6 +86,13 @@ int validate_precision(const cbh_problem* p, int32_t precision) {
 
 using namespace cbh;
 
+namespace cbh {
+// Device clock stamp (instrumentation).
+__global__ void stamp_kernel(uint64_t* slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+}  // namespace cbh
+
 extern "C" {
 
 const char* cbh_last_error(void) { return g_err; }
@@ -138,6 +151,23 @@ int cbh_set_workspace_limit(cbh_ctx* ctx, int64_t bytes) {
 }
 
 int64_t cbh_workspace_size(const cbh_ctx* ctx) { return ctx ? ctx->ws_size : 0; }
+
+int cbh_device_timestamp(cbh_ctx* ctx, uint64_t* slot, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && slot != nullptr, "NULL argument");
+    stamp_kernel<<<1, 64, 0, (hipStream_t)stream>>>(slot);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_device_clock_khz(cbh_ctx* ctx, int64_t* khz) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && khz != nullptr, "NULL argument");
+    int v = 0;
+    CBH_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, ctx->device));
+    *khz = v;
+    return CBH_OK;
+}
 
 int cbh_sync(cbh_ctx* ctx, void* stream) {
     clear_error();

@@ -73,6 +73,18 @@ HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t
 //     under partial_pct % of the n * F bin bytes;
 //   feature groups: as many as needed to reach target_blocks, at least enough
 //     to respect the LDS bound on features per block.
+// bytes per (slot, bin, feature) over all stats
+template <int PREC>
+__host__ __device__ constexpr uint32_t lpf_cell_bytes() { return PREC == CBH_PREC_INT16 ? 8u : 16u; }
+
+// Bytes of one (slot, bin) record of the tile (W features x all stats). For
+// narrow groups (W * CS <= 128) several lanes share a feature, and their bins
+// decide the bank: an 8-byte pad makes the record an odd number of 8-byte
+// words, so different bins fall on different banks.
+__host__ __device__ constexpr uint32_t lpf_record_bytes(uint32_t W, uint32_t CS) {
+    return W * CS <= 128 ? W * CS + 8 : W * CS;
+}
+
 // Plan of the lanes-over-features kernel: the widest lane group W (at most
 // the requested one) whose tile of all slots fits the LDS budget; if even
 // W = 4 does not fit, the slots are split into tiles (rows re-read per tile).
@@ -82,15 +94,15 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
     HistPlan p;
     p.kind = 1;
     p.words_per_cell = words_per_cell(precision, 1);
-    const int64_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
+    const uint32_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
     const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
     int32_t W = kn.lpf_w > 0 ? std::min(kn.lpf_w, 32) : 32;
-    while (W > 4 && int64_t(n_slots) * B * W * cs > budget) W /= 2;
+    while (W > 4 && int64_t(n_slots) * B * lpf_record_bytes(W, cs) > budget) W /= 2;
     p.fb = W;
-    // slots per tile: all if they fit, at most 64 (one bit each in the
-    // kernel's mask of subtraction sides)
+    const int64_t slot_bytes = int64_t(B) * lpf_record_bytes(W, cs);
+    // slots per tile: all if they fit, at most 64
     int32_t lt = std::min<int32_t>(n_slots, 64);
-    while (lt > 1 && int64_t(lt) * B * W * cs > std::max<int64_t>(budget, B * W * cs)) lt = (lt + 1) / 2;
+    while (lt > 1 && lt * slot_bytes > std::max<int64_t>(budget, slot_bytes)) lt = (lt + 1) / 2;
     p.lt = lt;
     p.n_ltiles = (n_slots + lt - 1) / lt;
     p.n_fgroups = (F + W - 1) / W;
@@ -106,7 +118,7 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
     p.rows_per_chunk = rows;
     p.n_chunks = (int32_t)((n + rows - 1) / rows);
     p.rep = 1;
-    p.lds_bytes = int64_t(lt) * B * W * cs;
+    p.lds_bytes = lt * slot_bytes;
     p.n_blocks = int64_t(p.n_chunks) * tiles;
     return p;
 }
@@ -386,21 +398,12 @@ __global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __rest
 // the parent histogram's second statistic (row count for RMSE, sum of h
 // otherwise) on the split feature; side[p] = 1 if the bit-set side is smaller.
 // With no split every row stayed on the clear side, so the set side is empty.
+// One wave: side of parent p (1 if the bit-set child is the smaller one).
 template <int PREC>
-__global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ parent,
-                                                       const cbh_split* __restrict__ split,
-                                                       int64_t half, int32_t F, int32_t B,
-                                                       int32_t K, int32_t rmse,
-                                                       uint8_t* __restrict__ side) {
-    // one wave per parent leaf, lanes over bins
-    const int64_t p = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (p >= half) return;
-    const int f = split->feature, k = split->border;
-    if (f < 0 || f >= F) {
-        if (lane == 0) side[p] = 1;
-        return;
-    }
+__device__ __forceinline__ uint8_t parent_side(const void* __restrict__ parent, int64_t p, int f,
+                                               int k, int32_t F, int32_t B, int32_t K,
+                                               int32_t rmse, int lane) {
+    if (f < 0 || f >= F) return 1;
     double left = 0.0, right = 0.0;
     for (int b = lane; b < B; b += 64) {
         const int64_t e = ((p * F + f) * B + b) * 2 * K + 1;   // statistic 1 of class 0
@@ -419,7 +422,82 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
         left += __shfl_xor(left, d, 64);
         right += __shfl_xor(right, d, 64);
     }
-    if (lane == 0) side[p] = right < left ? 1 : 0;
+    return right < left ? 1 : 0;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ parent,
+                                                       const cbh_split* __restrict__ split,
+                                                       int64_t half, int32_t F, int32_t B,
+                                                       int32_t K, int32_t rmse,
+                                                       uint8_t* __restrict__ side) {
+    // one wave per parent leaf, lanes over bins
+    const int64_t p = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= half) return;
+    const uint8_t sd = parent_side<PREC>(parent, p, split->feature, split->border, F, B, K, rmse,
+                                         lane);
+    if (lane == 0) side[p] = sd;
+}
+
+// Sides and row codes in one launch (lanes-over-features builds by
+// subtraction with few parents): every block first derives the side of every
+// parent into LDS (block 0 also stores them for the merge), then writes
+// code[i] = p = leaf & (half - 1) for rows on the parent's accumulated side,
+// 0xffff otherwise.
+template <int PREC>
+__global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__ parent,
+                                                        const cbh_split* __restrict__ split,
+                                                        int64_t half, int32_t F, int32_t B,
+                                                        int32_t K, int32_t rmse,
+                                                        const uint16_t* __restrict__ leaf, int64_t n,
+                                                        int64_t rows_per_block, uint32_t shift,
+                                                        uint8_t* __restrict__ side,
+                                                        uint16_t* __restrict__ code) {
+    extern __shared__ uint8_t sd[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int f = split->feature, k = split->border;
+    for (int64_t p = wave; p < half; p += 4) {
+        const uint8_t v = parent_side<PREC>(parent, p, f, k, F, B, K, rmse, lane);
+        if (lane == 0) {
+            sd[p] = v;
+            if (blockIdx.x == 0) side[p] = v;
+        }
+    }
+    __syncthreads();
+    const uint32_t lmask = (uint32_t)half - 1u;
+    const int64_t i0 = int64_t(blockIdx.x) * rows_per_block;
+    const int64_t i1 = min(n, i0 + rows_per_block);
+    // 8 rows per thread and step where the block's rows are 8-aligned
+    const bool vec = ((reinterpret_cast<uintptr_t>(leaf) | reinterpret_cast<uintptr_t>(code)) & 15) == 0;
+    int64_t i = i0;
+    if (vec) {
+        const int64_t i8 = i0 + ((i1 - i0) & ~int64_t(7));
+        for (int64_t j = i0 + 8 * int64_t(threadIdx.x); j < i8; j += 8 * 256) {
+            const uint4 lv = *reinterpret_cast<const uint4*>(leaf + j);
+            const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w};
+            uint32_t cw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t out = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t v = (lw[q] >> (16 * h)) & 0xffffu;
+                    const uint32_t pp = v & lmask;
+                    const uint32_t c = (((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu;
+                    out |= c << (16 * h);
+                }
+                cw[q] = out;
+            }
+            *reinterpret_cast<uint4*>(code + j) = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+        }
+        i = i8;
+    }
+    for (int64_t j = i + threadIdx.x; j < i1; j += 256) {
+        const uint32_t v = leaf[j];
+        const uint32_t pp = v & lmask;
+        code[j] = (uint16_t)((((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu);
+    }
 }
 
 // ------------------------------------------- lanes-over-features variant
@@ -432,10 +510,6 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
 // replicas. With the bins in
 // the tiled layout the W segments of one row group are adjacent in memory and
 // a wave's bin load is fully coalesced; plain columns work too.
-// bytes per (slot, bin, feature) over all stats
-template <int PREC>
-__host__ __device__ constexpr uint32_t lpf_cell_bytes() { return PREC == CBH_PREC_INT16 ? 8u : 16u; }
-
 // LDS byte offset, in slot 0, of the first stat of (bin of row r of the
 // segment's words, this lane's feature): bin * W * CS + lane_off, where
 // lane_off = 8 * feature; the second stat is W * 8 bytes further.
@@ -449,7 +523,7 @@ __device__ __forceinline__ uint32_t lpf_addr(const uint32_t (&bw)[4], int r, uin
         return __builtin_amdgcn_perm(word, lane_off >> 1, 0x0c0c0000u | ((4u + (r & 3)) << 8))
                << 1;
     } else {
-        return ((word >> (8 * (r & 3))) & 255u) * (uint32_t)(W * CS) + lane_off;
+        return ((word >> (8 * (r & 3))) & 255u) * lpf_record_bytes(W, CS) + lane_off;
     }
 }
 
@@ -492,6 +566,76 @@ __device__ __forceinline__ void lpf_rows8(char* tile, const uint32_t (&bw)[4], i
     }
 }
 
+// One 16-row segment of the lanes-over-features kernel: its bins (this
+// lane's feature), row codes and gradient statistics, loaded with 16-byte
+// loads; add() puts its rows into the tile, 8 at a time.
+template <int PREC, int RM, int MODE>
+struct LpfSeg {
+    uint4 b;
+    uint4 c[2];      // row codes (MODE != 0)
+    uint4 q[4];      // int16 codes
+    float4 g[4], h[4];
+    __device__ __forceinline__ void load(const uint8_t* col, int64_t sstride,
+                                         const uint16_t* rowcode, const HistArgs& a, int64_t t) {
+        const int64_t i = t << 4;
+        b = *reinterpret_cast<const uint4*>(col + t * sstride);
+        if constexpr (MODE != 0) {
+            c[0] = *reinterpret_cast<const uint4*>(rowcode + i);
+            c[1] = *reinterpret_cast<const uint4*>(rowcode + i + 8);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (PREC == CBH_PREC_INT16) {
+                q[k] = *reinterpret_cast<const uint4*>(a.gq + i + 4 * k);
+            } else {
+                g[k] = *reinterpret_cast<const float4*>(a.g + i + 4 * k);
+                if constexpr (RM == 0) h[k] = *reinterpret_cast<const float4*>(a.h + i + 4 * k);
+            }
+        }
+    }
+    template <int W>
+    __device__ __forceinline__ void add(char* tile, uint32_t lane_off, uint32_t s0, uint32_t ns,
+                                        uint32_t slot_bytes) const {
+        const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            uint32_t off[8];
+            float gv[8], hv[8];
+            uint32_t qv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                off[k] = 0u;
+                if constexpr (MODE != 0) {
+                    const uint4 cc = c[h2];
+                    const uint32_t lw[4] = {cc.x, cc.y, cc.z, cc.w};
+                    const uint32_t code = (lw[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                    const uint32_t sl = code - s0;
+                    off[k] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
+                }
+                const int r = 8 * h2 + k;
+                if constexpr (PREC == CBH_PREC_INT16) {
+                    const uint4 qq = q[r >> 2];
+                    const uint32_t qw[4] = {qq.x, qq.y, qq.z, qq.w};
+                    qv[k] = qw[r & 3];
+                    gv[k] = hv[k] = 0.f;
+                } else {
+                    const float4 gg = g[r >> 2];
+                    const float gw[4] = {gg.x, gg.y, gg.z, gg.w};
+                    gv[k] = gw[r & 3];
+                    hv[k] = 0.f;
+                    if constexpr (RM == 0) {
+                        const float4 hh = h[r >> 2];
+                        const float hw[4] = {hh.x, hh.y, hh.z, hh.w};
+                        hv[k] = hw[r & 3];
+                    }
+                    qv[k] = 0u;
+                }
+            }
+            lpf_rows8<PREC, RM, W, MODE == 2>(tile, bw, 8 * h2, lane_off, off, gv, hv, qv);
+        }
+    }
+};
+
 // MODE 0: one slot (level 0, direct): no per-row reads, no checks.
 // MODE 1: all slots of a direct build in one tile: slot = row code (the leaf).
 // MODE 2: subtraction and/or several slot tiles: slot = row code - first slot
@@ -519,7 +663,7 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     const int64_t sstride = a.seg ? a.seg[f] : 16;
     const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;               // first slot of the tile
     const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);       // slots in the tile (<= 64)
-    const uint32_t slot_bytes = (uint32_t)a.B * W * CS;
+    const uint32_t slot_bytes = (uint32_t)a.B * lpf_record_bytes(W, CS);
     const uint32_t tile_words = ns * slot_bytes / 4;
     for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
     __syncthreads();
@@ -532,56 +676,24 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     const bool vec = ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(a.g) |
                        reinterpret_cast<uintptr_t>(a.h) | reinterpret_cast<uintptr_t>(a.gq) |
                        reinterpret_cast<uintptr_t>(rowcode)) & 15) == 0;
-    float gv[8], hv[8];
-    uint32_t qv[8], off[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        gv[k] = 0.f;
-        hv[k] = 0.f;
-        qv[k] = 0u;
-        off[k] = 0u;
-    }
     int64_t t = (r0 >> 4) + int64_t(wave) * RG + rq;
-    if (vec) {
-        for (; t < t_full; t += int64_t(nwaves) * RG) {
-            const int64_t i = t << 4;
-            const uint4 v = *reinterpret_cast<const uint4*>(col + t * sstride);
-            const uint32_t bw[4] = {v.x, v.y, v.z, v.w};
-            uint4 lv;
-            if constexpr (MODE != 0) lv = *reinterpret_cast<const uint4*>(rowcode + i);
-#pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                const int64_t ih = i + 8 * h2;
-                if constexpr (MODE != 0) {
-                    if (h2 == 1) lv = *reinterpret_cast<const uint4*>(rowcode + ih);
-                    const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w};
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const uint32_t code = (lw[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                        const uint32_t sl = code - s0;
-                        off[k] = MODE == 1 ? code * slot_bytes
-                                           : (sl < ns ? sl * slot_bytes : kLpfSkip);
-                    }
-                }
-                if constexpr (PREC == CBH_PREC_INT16) {
-                    const uint4 x = *reinterpret_cast<const uint4*>(a.gq + ih);
-                    const uint4 y = *reinterpret_cast<const uint4*>(a.gq + ih + 4);
-                    qv[0] = x.x; qv[1] = x.y; qv[2] = x.z; qv[3] = x.w;
-                    qv[4] = y.x; qv[5] = y.y; qv[6] = y.z; qv[7] = y.w;
-                } else {
-                    const float4 x = *reinterpret_cast<const float4*>(a.g + ih);
-                    const float4 y = *reinterpret_cast<const float4*>(a.g + ih + 4);
-                    gv[0] = x.x; gv[1] = x.y; gv[2] = x.z; gv[3] = x.w;
-                    gv[4] = y.x; gv[5] = y.y; gv[6] = y.z; gv[7] = y.w;
-                    if constexpr (RM == 0) {
-                        const float4 u = *reinterpret_cast<const float4*>(a.h + ih);
-                        const float4 w = *reinterpret_cast<const float4*>(a.h + ih + 4);
-                        hv[0] = u.x; hv[1] = u.y; hv[2] = u.z; hv[3] = u.w;
-                        hv[4] = w.x; hv[5] = w.y; hv[6] = w.z; hv[7] = w.w;
-                    }
-                }
-                if (fok) lpf_rows8<PREC, RM, W, MODE == 2>(tile, bw, 8 * h2, lane_off, off, gv, hv, qv);
-            }
+    const int64_t step = int64_t(nwaves) * RG;
+    if (vec && t < t_full) {
+        // software pipeline: the loads of the next segment are issued before
+        // the atomics of the current one (two register sets, A and B)
+        LpfSeg<PREC, RM, MODE> A, B;
+        A.load(col, sstride, rowcode, a, t);
+        for (;;) {
+            int64_t tn = t + step;
+            if (tn < t_full) B.load(col, sstride, rowcode, a, tn);
+            if (fok) A.template add<W>(tile, lane_off, s0, ns, slot_bytes);
+            t = tn;
+            if (t >= t_full) break;
+            tn = t + step;
+            if (tn < t_full) A.load(col, sstride, rowcode, a, tn);
+            if (fok) B.template add<W>(tile, lane_off, s0, ns, slot_bytes);
+            t = tn;
+            if (t >= t_full) break;
         }
     }
     // the ragged last segment, and everything when a pointer is unaligned:
@@ -642,7 +754,8 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
         if ((int)cfl >= nf) continue;
         const uint32_t sb = c / W;                 // slot * B + bin
         const uint32_t bin = sb % (uint32_t)a.B, sl = sb / (uint32_t)a.B;
-        const char* cell = tile + (size_t)sb * W * CS + cfl * 8u;   // first stat; second at + W * 8
+        // first stat; the second is W * 8 bytes further
+        const char* cell = tile + (size_t)sb * lpf_record_bytes(W, CS) + cfl * 8u;
         const int64_t o = ((int64_t(s0 + sl) * a.F + f0 + cfl) * a.B + bin) * a.wpc;
         if constexpr (PREC == CBH_PREC_INT16) {
             *reinterpret_cast<uint2*>(part + o) = *reinterpret_cast<const uint2*>(cell);
@@ -765,22 +878,69 @@ static void launch_hist_prec(const HistArgs& a, const HistPlan& plan, int max_ld
         hist_kernel<PREC, 1, 0><<<(unsigned)grid, kHistThreads, (size_t)plan.lds_bytes, s>>>(a);
 }
 
+template <int PREC>
+static void launch_side_code(const void* parent, const cbh_split* split, int64_t half, int32_t F,
+                             int32_t B, int32_t K, int32_t rmse, const uint16_t* leaf, int64_t n,
+                             uint32_t shift, uint8_t* side, uint16_t* codes, int num_cus,
+                             hipStream_t s) {
+    const int64_t rpb = std::max<int64_t>(8192, align_up((n + num_cus - 1) / num_cus, 8));
+    const unsigned grid = (unsigned)((n + rpb - 1) / rpb);
+    side_code_kernel<PREC><<<grid, 256, (size_t)half, s>>>(parent, split, half, F, B, K, rmse, leaf,
+                                                           n, rpb, shift, side, codes);
+}
+
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
-                const void* parent, const uint8_t* side, uint16_t* codes) {
+                const void* parent, uint8_t* side, uint16_t* codes,
+                const cbh_split* parent_split) {
     HistArgs a;
     a.rowcode = p->leaf;
-    if (plan.kind == 1 && parent) {
-        if (!codes) {
-            set_error("internal: no row-code buffer for a build by subtraction");
-            return CBH_EINVAL;
+    if (parent) {
+        const int64_t half = int64_t(1) << (level - 1);
+        const int rmse = p->loss == CBH_LOSS_RMSE;
+        if (plan.kind == 1) {
+            if (!codes) {
+                set_error("internal: no row-code buffer for a build by subtraction");
+                return CBH_EINVAL;
+            }
+            const uint32_t shift = (uint32_t)(level - 1);
+            if (half * p->max_bins <= 16384) {
+                // few parents: sides and codes in one launch
+                switch (precision) {
+                    case CBH_PREC_FP32:
+                        launch_side_code<CBH_PREC_FP32>(parent, parent_split, half, p->n_features,
+                                                        p->max_bins, p->K, rmse, p->leaf, p->n,
+                                                        shift, side, codes, ctx->num_cus, s);
+                        break;
+                    case CBH_PREC_TWOFLOAT:
+                        launch_side_code<CBH_PREC_TWOFLOAT>(
+                            parent, parent_split, half, p->n_features, p->max_bins, p->K, rmse,
+                            p->leaf, p->n, shift, side, codes, ctx->num_cus, s);
+                        break;
+                    default:
+                        launch_side_code<CBH_PREC_INT16>(parent, parent_split, half,
+                                                         p->n_features, p->max_bins, p->K, rmse,
+                                                         p->leaf, p->n, shift, side, codes,
+                                                         ctx->num_cus, s);
+                        break;
+                }
+                CBH_LAUNCHED();
+            } else {
+                const int rc = launch_side(parent, parent_split, half, p->n_features, p->max_bins,
+                                           p->K, rmse, precision, side, s);
+                if (rc) return rc;
+                slot_code_kernel<<<(unsigned)std::min<int64_t>((p->n + 255) / 256,
+                                                               int64_t(ctx->num_cus) * 8),
+                                   256, 0, s>>>(p->leaf, side, p->n, (uint32_t)half - 1u, shift,
+                                                codes);
+                CBH_LAUNCHED();
+            }
+            a.rowcode = codes;
+        } else {
+            const int rc = launch_side(parent, parent_split, half, p->n_features, p->max_bins,
+                                       p->K, rmse, precision, side, s);
+            if (rc) return rc;
         }
-        slot_code_kernel<<<(unsigned)std::min<int64_t>((p->n + 255) / 256,
-                                                       int64_t(ctx->num_cus) * 8),
-                           256, 0, s>>>(p->leaf, side, p->n, (uint32_t)(1 << (level - 1)) - 1u,
-                                        (uint32_t)(level - 1), codes);
-        CBH_LAUNCHED();
-        a.rowcode = codes;
     }
     a.bins = p->bins;
     a.seg = p->seg_stride;
@@ -1007,11 +1167,8 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
     uint16_t* codes =
         code_bytes ? (uint16_t*)((uint8_t*)ctx->ws + part_bytes + align_up(half, 256)) : nullptr;
     hipStream_t s = (hipStream_t)stream;
-    rc = launch_side(parent_hist, parent_split, half, prob->n_features, prob->max_bins, prob->K,
-                     rmse, precision, side, s);
-    if (rc) return rc;
     return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side,
-                       codes);
+                       codes, parent_split);
 }
 
 }  // extern "C"

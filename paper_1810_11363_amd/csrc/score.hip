@@ -11,9 +11,11 @@
 // histogram, one lane per 4 consecutive bins, forms bin prefixes with a wave
 // scan, and accumulates the per-border terms in registers. The four waves'
 // partial scores are added in wave order (deterministic), then the block
-// keeps its best and second-best border. Kernel 2: one block reduces the
-// per-feature winners to the level's split with the tie rule "largest score,
-// then smallest feature, then smallest border".
+// keeps its best and second-best border. The last block to finish (a
+// device counter, reset by that block, so the launch needs no clearing and
+// can be replayed from a graph) reduces the per-feature winners to the
+// level's split with the tie rule "largest score, then smallest feature, then
+// smallest border".
 #include <cmath>
 
 #include "common.h"
@@ -22,17 +24,26 @@
 namespace cbh {
 
 template <int PREC>
-__global__ __launch_bounds__(256) void score_feature_kernel(ScoreRow r, const int32_t* n_bins,
-                                                            int32_t L, float* scores,
-                                                            FeatBest* fbest) {
+__global__ __launch_bounds__(256) void score_split_kernel(ScoreRow r, const int32_t* n_bins,
+                                                          int32_t L, float* scores,
+                                                          FeatBest* fbest,
+                                                          uint32_t* __restrict__ counter,
+                                                          cbh_split* __restrict__ out) {
     const int f = blockIdx.x;
     score_feature<PREC>(r, L, f, n_bins[f], scores, &fbest[f]);
-}
-
-__global__ __launch_bounds__(256) void score_argmax_kernel(const FeatBest* __restrict__ fb,
-                                                           int32_t F, int32_t Bm1,
-                                                           cbh_split* __restrict__ out) {
-    argmax_features(fb, F, Bm1, out);
+    __shared__ uint32_t last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // publish this block's winner, then count the block in
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        argmax_features(fbest, r.F, r.B - 1, out);
+        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    }
 }
 
 int64_t score_scratch_bytes(const cbh_problem* p) {
@@ -53,19 +64,21 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     r.l2 = (float)l2;
     const int L = 1 << level;
     FeatBest* fb = (FeatBest*)scratch;
+    uint32_t* counter = ctx->d_flags + 1;
     switch (precision) {
         case CBH_PREC_FP32:
-            score_feature_kernel<CBH_PREC_FP32><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb);
+            score_split_kernel<CBH_PREC_FP32><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb,
+                                                                  counter, best);
             break;
         case CBH_PREC_TWOFLOAT:
-            score_feature_kernel<CBH_PREC_TWOFLOAT><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores,
-                                                                       fb);
+            score_split_kernel<CBH_PREC_TWOFLOAT><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores,
+                                                                      fb, counter, best);
             break;
         default:
-            score_feature_kernel<CBH_PREC_INT16><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb);
+            score_split_kernel<CBH_PREC_INT16><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb,
+                                                                   counter, best);
             break;
     }
-    score_argmax_kernel<<<1, 256, 0, s>>>(fb, r.F, r.B - 1, best);
     CBH_LAUNCHED();
     return CBH_OK;
 }
