@@ -1,5 +1,7 @@
 #!/usr/bin/env python3
-"""Benchmark: per-tree split search on one MI355X for the 1M-row RMSE workload.
+"""Benchmark: per-tree split search on one MI355X for the 1M-row RMSE workload
+(default; `--workload c3` runs the 10M-row, 200-feature, 255-bin Logloss
+precision workload instead).
 
 A step is one boosting iteration: every level's histogram build, scoring,
 argmax and leaf update, then the leaf solve and the model/gradient update.
@@ -27,6 +29,7 @@ against 8 TB/s.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -65,18 +68,41 @@ def hist_bytes_per_level(n, F, K, level, rmse, precision):
     return n * F + n * grad + n * leaf
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "hist_c2_1m_rmse_counters.json")
+# Workloads: the default is the 1M-row RMSE one the headline metric is quoted
+# on; the others are the 10M-row precision workload and reduced runs of it.
+WORKLOADS = {
+    "c2": dict(tag="c2_1m_rmse", n=1_000_000, steps=200, cpu_rows=1_000_000, cpu_trees=20),
+    "c3": dict(tag="c3_10m_logloss", n=10_000_000, steps=20, cpu_rows=250_000, cpu_trees=2),
+}
+
+
+def describe(workload, p, bst):
+    n, F, depth = bst.n, bst.F, bst.depth
+    if workload == "c2":
+        return (f"1M-row RMSE: n={n}, 100 numeric features at 128 bins + 10 categorical -> "
+                f"{F - 100} ordered-statistic columns per tree, 4 permutations, depth {depth}, "
+                f"lr 0.1, l2 3")
+    return (f"10M-row precision Logloss: n={n}, {F} uniform numeric features at {bst.B} bins "
+            f"(5% exact duplicates), 1% positives, depth {depth}, lr 0.1, l2 3")
+
+
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"hist_{WORKLOADS[workload]['tag']}_counters.json")
+
+
+COUNTERS = counters_path("c2")
 COUNTED_SOURCES = ("paper_1810_11363_amd/csrc/kernels_dev.h",
                    "paper_1810_11363_amd/csrc/histogram.hip")
 
 
-def measured_traffic(form: str):
+def measured_traffic(form: str, workload: str = "c2"):
     """HBM bytes per histogram build (fetch + write, hardware counters scaled
     by a plain copy's reading), as recorded beside the kernel sources they
-    were taken on; None when the sources have changed since."""
+    were taken on; None when the sources have changed since or when no
+    counters were recorded for the workload."""
     import hashlib
     try:
-        rec = json.load(open(COUNTERS))
+        rec = json.load(open(counters_path(workload)))
         h = hashlib.sha256()
         for f in COUNTED_SOURCES:
             h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -101,8 +127,11 @@ def cpu_baseline(p, rows: int, trees: int):
     p.label = np.ascontiguousarray(p.label[sub])
     p.y_num = np.ascontiguousarray(p.y_num[:, sub])
     # each permutation restricted to the sample, rows renumbered 0..rows-1
-    p.perms = np.stack([np.searchsorted(sub, perm[np.isin(perm, sub)]).astype(np.int32)
-                        for perm in p.perms])
+    if p.perms.shape[0]:
+        p.perms = np.stack([np.searchsorted(sub, perm[np.isin(perm, sub)]).astype(np.int32)
+                            for perm in p.perms])
+    else:
+        p.perms = np.zeros((0, rows), np.int32)
     prep = boost.prepare(p)
     approx = np.zeros((p.K, p.n))
     B = max(int(prep.nb_num.max()), prep.nb_ts)
@@ -211,6 +240,21 @@ def oracle_error(snap):
     return worst, worst_q
 
 
+def warm_for(bst, seconds, t0, eager):
+    """Replay (or grow, if eager) trees for `seconds` of wall time."""
+    import torch
+    t_end = time.perf_counter() + seconds
+    k = t0
+    while time.perf_counter() < t_end:
+        for _ in range(8):
+            if eager:
+                bst.fit_tree(k)
+            else:
+                bst.replay_tree(k)
+            k += 1
+        torch.cuda.synchronize()
+
+
 def time_form(bst, name, args, rmse):
     import numpy as np
     import torch
@@ -232,9 +276,13 @@ def time_form(bst, name, args, rmse):
     for t in range(args.warmup):
         bst.fit_tree(t)
     torch.cuda.synchronize()
-    # timed region: whole trees replayed from HIP graphs (one per permutation)
+    # timed region: whole trees replayed from HIP graphs (one per permutation),
+    # after `--warmup-s` seconds of the same replays: the clocks settle below
+    # their first-burst level within about a second of sustained work, and the
+    # timed figure is the sustained one
     if not args.no_graph:
         bst.capture_trees()
+    warm_for(bst, args.warmup_s, args.warmup, args.no_graph)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
@@ -250,27 +298,34 @@ def time_form(bst, name, args, rmse):
     t_wall = time.perf_counter() - t_wall
     cb.cbh_sync(bst.ctx, stream)
     total_ms = start.elapsed_time(stop)
-    # the histogram build alone, inside real trees: one more graph per
-    # permutation with event nodes around every build; each replay is a whole
-    # tree, read back before the next replay of the same graph
+    # the histogram build alone, inside real trees: one more graph per tree
+    # with device-clock stamps around every build, the trees replayed back to
+    # back as in the timed loop, the stamps read once at the end
     n_hist = max(1, args.hist_trees)
     hist_ms = np.zeros((n_hist, depth))
     if not args.no_graph:
         timing = "device-clock stamps around every build, captured in the tree graphs"
         khz = cb.cbh_device_clock_khz(bst.ctx)
-        buf = torch.zeros(bst.s * depth * 2, dtype=torch.int64, device=bst.device)
-        stamps = [[(Stamp(cb, bst.ctx, buf, (r * depth + l) * 2),
-                    Stamp(cb, bst.ctx, buf, (r * depth + l) * 2 + 1)) for l in range(depth)]
-                  for r in range(bst.s)]
-        timed = bst.capture_trees(events=stamps)
+        buf = torch.zeros(n_hist * depth * 2, dtype=torch.int64, device=bst.device)
+        timed = []
+        for s in range(n_hist):
+            stamps = [(Stamp(cb, bst.ctx, buf, (s * depth + l) * 2),
+                       Stamp(cb, bst.ctx, buf, (s * depth + l) * 2 + 1)) for l in range(depth)]
+            timed.append(bst.capture_tree(args.warmup + args.steps + s, events=stamps))
+        warm_for(bst, args.warmup_s, args.warmup, False)   # settle again after the captures
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(stream):
-            for s in range(n_hist):
-                t = args.warmup + args.steps + s
-                timed[t % bst.s].replay()
-                torch.cuda.synchronize()
-                v = buf.view(bst.s, depth, 2)[t % bst.s].cpu().numpy()
-                hist_ms[s] = (v[:, 1] - v[:, 0]) / khz
+            e0.record(stream)
+            for g in timed:
+                g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        stamped_tree_ms = e0.elapsed_time(e1) / n_hist
+        v = buf.view(n_hist, depth, 2).cpu().numpy()
+        hist_ms[:] = (v[:, :, 1] - v[:, :, 0]) / khz
+        del timed
     else:
+        stamped_tree_ms = None
         timing = "events around the builds of eagerly launched trees"
         ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(depth)] for _ in range(n_hist)]
@@ -298,13 +353,15 @@ def time_form(bst, name, args, rmse):
         "hist_subtraction": bool(bst.subtract),
         "graph_replay": not args.no_graph,
         "hist_timing": timing,
+        "ms_per_tree_while_timing_builds": (round(stamped_tree_ms, 4)
+                                            if stamped_tree_ms is not None else None),
         "max_norm_err_vs_fp64": None,      # filled by the oracle leg
         "_snapshot": snap,
         "autotune_s": round(t_tune, 2),
         "wall_s_timed": round(t_wall, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(name),
+                     "traffic": measured_traffic(name, args.workload),
                      "kernel": "cbh_build_histograms / cbh_build_histograms_sub "
                                "(LDS histogram + partial merge)",
                      "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
@@ -315,15 +372,19 @@ def time_form(bst, name, args, rmse):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="c2")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="trees grown before the graphs are captured")
+    ap.add_argument("--warmup-s", type=float, default=1.0,
+                    help="seconds of replayed trees before the timed region")
     ap.add_argument("--precision", choices=list(PRECISIONS), default="twofloat",
                     help="headline histogram form")
     ap.add_argument("--compare", default="fp32,int16",
                     help="other forms timed in the same run ('' for none)")
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--cpu-rows", type=int, default=1_000_000)
-    ap.add_argument("--cpu-trees", type=int, default=20)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--cpu-rows", type=int, default=None)
+    ap.add_argument("--cpu-trees", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every call from Python instead of replaying captured trees")
     ap.add_argument("--hist-trees", type=int, default=40,
@@ -337,6 +398,10 @@ def main():
                     help="only run a device-to-device copy of MIB MiB five times (reference "
                          "for hardware byte counters) and exit")
     args = ap.parse_args()
+    wl = WORKLOADS[args.workload]
+    for k in ("steps", "n", "cpu_rows", "cpu_trees"):
+        if getattr(args, k) is None:
+            setattr(args, k, wl[k])
     if args.copy_calibration:
         import torch
         x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
@@ -357,7 +422,7 @@ def main():
     from paper_1810_11363_amd.booster import GpuBooster
 
     t_gen = time.perf_counter()
-    p = datagen.make_c2(n=args.n)
+    p = datagen.make_c2(n=args.n) if args.workload == "c2" else datagen.make_c3(n=args.n)
     t_gen = time.perf_counter() - t_gen
     print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
     bst = GpuBooster.from_problem(p).prepare()
@@ -382,9 +447,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPES[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"1M-row RMSE: n={n}, 100 numeric features at 128 bins + "
-                               f"10 categorical -> {F - 100} ordered-statistic columns per "
-                               f"tree, 4 permutations, depth {depth}, lr 0.1, l2 3",
+        "config": {"workload": describe(args.workload, p, bst),
                    "precision": args.precision, "features_per_tree": F, "bins": bst.B,
                    "rows": n},
         "roofline": head["roofline"],
@@ -404,8 +467,7 @@ def main():
                 r["max_g_err_over_quant_bound"] = q
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(datagen.make_c2(n=args.n), args.cpu_rows,
-                                           args.cpu_trees)
+        out["cpu_baseline"] = cpu_baseline(copy.copy(p), args.cpu_rows, args.cpu_trees)
     print(json.dumps(out), flush=True)
 
 

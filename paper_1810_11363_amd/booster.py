@@ -28,7 +28,9 @@ Device layout (HBM):
 from __future__ import annotations
 
 import ctypes as C
+import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -123,7 +125,11 @@ class GpuBooster:
         st = self.stream
         torch.cuda.synchronize(d)
         t0 = time.perf_counter()
-        borders = [cb.cbh_select_borders(self.x_num[f], self.num_bins) for f in range(self.F_num)]
+        # host border selection, one feature per task (the library call runs
+        # without the interpreter lock)
+        with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+            borders = list(ex.map(lambda f: cb.cbh_select_borders(self.x_num[f], self.num_bins),
+                                  range(self.F_num)))
         t1 = time.perf_counter()
         self.num_borders = borders
         x_d = torch.from_numpy(self.x_num).to(d)
@@ -309,6 +315,22 @@ class GpuBooster:
         if events is None:
             self.graphs = graphs
         return graphs
+
+    def capture_tree(self, t: int, events=None):
+        """One graph of tree t (permutation t mod s), with optional per-level
+        (start, end) records around the builds (see capture_trees)."""
+        cap = torch.cuda.Stream(self.device)
+        eager = self.stream
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        try:
+            self.stream = cap
+            with torch.cuda.graph(g, stream=cap):
+                self.fit_tree(t, events=events)
+        finally:
+            self.stream = eager
+        torch.cuda.synchronize(self.device)
+        return g
 
     def replay_tree(self, t: int):
         self.graphs[t % self.s].replay()
