@@ -73,6 +73,7 @@ def hist_bytes_per_level(n, F, K, level, rmse, precision):
 WORKLOADS = {
     "c2": dict(tag="c2_1m_rmse", n=1_000_000, steps=200, cpu_rows=1_000_000, cpu_trees=20),
     "c3": dict(tag="c3_10m_logloss", n=10_000_000, steps=20, cpu_rows=250_000, cpu_trees=2),
+    "c4": dict(tag="c4_batch_rmse", n=0, steps=20, cpu_rows=1_000_000, cpu_trees=1),
 }
 
 
@@ -369,6 +370,124 @@ def time_form(bst, name, args, rmse):
     }
 
 
+def run_batch(args):
+    """The batching workload: P independent RMSE problems (row counts
+    log-uniform in [5e3, 2e6]) trained together, one boosting iteration of
+    all of them replayed from the graph cbh_graph_capture_iteration returns;
+    beside it the same problems grown one after another, each tree replayed
+    from its own graph."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1810_11363_amd import cbhip as cb
+    from paper_1810_11363_amd.booster import GpuBooster
+    t_gen = time.perf_counter()
+    probs = datagen.make_c4(P=args.batch_p, scale=args.batch_scale)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {len(probs)} problems in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    prec = PRECISIONS[args.precision]
+    ctx = cb.cbh_create(0)
+    bsts = [GpuBooster.from_problem(p, precision=prec, ctx=ctx).prepare() for p in probs]
+    P, depth, F = len(bsts), bsts[0].depth, bsts[0].F
+    rows = sum(b.n for b in bsts)
+    rf_per_iter = rows * F * depth
+    lr, l2 = bsts[0].lr, bsts[0].l2
+    dev = bsts[0].device
+    side = torch.cuda.Stream(dev)
+    # sequential: eager trees first (the shared workspace reaches its largest
+    # size before any graph is captured), then one graph per problem
+    for b in bsts:
+        b.init_gradients()
+        b.fit_tree(0)
+    torch.cuda.synchronize()
+    graphs = [b.capture_tree(1) for b in bsts]
+
+    def seq_iter():
+        for g in graphs:
+            g.replay()
+    # batched
+    best = torch.zeros((P, depth, 4), dtype=torch.int32, device=dev)
+    plan = cb.cbh_batch_create(ctx, [b.probs[0] for b in bsts], prec, [b.hist for b in bsts],
+                               best)
+    lvs = [b.leaf_values for b in bsts]
+    cb.cbh_batch_update(ctx, plan, lr, l2, lvs, True, side.cuda_stream)
+    gr = cb.cbh_graph_capture_iteration(ctx, plan, lr, l2, lvs, side.cuda_stream)
+
+    def batch_iter():
+        cb.cbh_graph_launch(gr, side.cuda_stream)
+
+    def timed(fn, stream_obj):
+        t_end = time.perf_counter() + args.warmup_s
+        while time.perf_counter() < t_end:
+            fn()
+            torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream_obj):
+            e0.record(stream_obj)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream_obj)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    with torch.cuda.stream(side):
+        ms_batch = timed(batch_iter, side)
+        ms_seq = timed(seq_iter, side)
+    cb.cbh_sync(ctx, side.cuda_stream)
+    out = {
+        "metric": "batched boosting iteration (all problems) and per-tree time",
+        "value": round(rf_per_iter / (ms_batch / 1e3) / 1e9, 3),
+        "unit": "G row-features/s",
+        "n_gpus": 1, "steps": args.steps, "warmup_s": args.warmup_s,
+        "ms_per_step": round(ms_batch, 4),
+        "ms_per_tree": round(ms_batch / P, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[args.precision], "data": "synthetic",
+        "config": {"workload": f"{P} independent RMSE problems, {rows} rows in all "
+                               f"(log-uniform 5e3..2e6 x {args.batch_scale}), 50 numeric features "
+                               f"at 64 bins + 4 categorical (C=1000) -> {F} columns, depth {depth}",
+                   "precision": args.precision, "problems": P, "rows": rows},
+        "sequential_ms_per_iteration": round(ms_seq, 4),
+        "batched_vs_sequential": round(ms_seq / ms_batch, 3),
+    }
+    cb.cbh_graph_destroy(gr)
+    cb.cbh_batch_destroy(plan)
+    for b in bsts:
+        b.close()
+    cb.cbh_destroy(ctx)
+    if not args.no_cpu:
+        # the oracle on the smallest problems whose rows add up to ~1e6
+        import oracle
+        from oracle import boost
+        order = np.argsort([p.n for p in probs])
+        picked, tot = [], 0
+        for i in order:
+            if tot + probs[i].n > args.cpu_rows and picked:
+                break
+            picked.append(i)
+            tot += probs[i].n
+        ready = []
+        for i in picked:
+            p = probs[i]
+            prep = boost.prepare(p)
+            bins, nb = prep.tree_features(0)
+            ready.append((p, bins, nb, max(int(prep.nb_num.max()), prep.nb_ts)))
+        t0 = time.perf_counter()
+        rf = 0
+        for p, bins, nb, B in ready:
+            approx = np.zeros((p.K, p.n))
+            boost.fit_tree(bins, nb, approx, p.label, p.loss, p.K, p.depth, p.lr, p.l2, B)
+            rf += p.n * bins.shape[0] * p.depth
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(rf / dt / 1e9, 6), "unit": "G row-features/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"one tree of each of the {len(picked)} smallest "
+                                         f"problems ({tot} rows); borders, bins and statistics "
+                                         f"before it are not timed"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +502,9 @@ def main():
     ap.add_argument("--compare", default="fp32,int16",
                     help="other forms timed in the same run ('' for none)")
     ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--batch-p", type=int, default=64, help="problems of the batching workload")
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="row-count scale of the batching workload")
     ap.add_argument("--cpu-rows", type=int, default=None)
     ap.add_argument("--cpu-trees", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true",
@@ -415,6 +537,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(multi-GPU sharding is described in DESIGN.md, not built)"}))
         sys.exit(2)
+    if args.workload == "c4":
+        run_batch(args)
+        return
 
     import torch  # noqa: F401
 

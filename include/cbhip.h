@@ -359,10 +359,11 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P,
 void cbh_batch_destroy(cbh_batch* batch);
 
 /* One level of every problem of the plan: histograms, score, argmax and the
- * leaf update, with the split written to best[p][level]. The histogram tiles of
- * all problems share one persistent launch; the block that finishes the last
- * tile of a feature group merges that group and scores it, and the block that
- * finishes the last group of a problem takes the argmax. */
+ * leaf update, with the split written to best[p][level]. The level runs as
+ * five launches shared by all problems (histogram tiles of every problem from
+ * one work list, partial merge, score of every (problem, feature), argmax per
+ * problem, leaf-bit update over every row), so the launch count does not grow
+ * with P. The plan uses the rows-over-lanes histogram kernel. */
 int cbh_batch_level(cbh_ctx* ctx, cbh_batch* batch, int32_t level, double l2,
                     void* stream);
 
