@@ -60,6 +60,9 @@ struct LevelPlan {
         int64_t rows_per_chunk, lds_bytes;
     }* d_plans = nullptr;              // per problem
     int64_t max_lds = 0;
+    int32_t kind = 0;                  // 0 rows over lanes, 1 lanes over features
+    int32_t W = 0;                     // lanes-over-features group width (all problems)
+    int32_t mode = 0;                  // lanes-over-features slot mode (all problems)
     int64_t cells_total = 0;           // sum over problems of L*F*B
     int64_t* d_cell_off = nullptr;     // per problem prefix of cells (P+1)
     int64_t score_total = 0;           // sum of F
@@ -131,6 +134,38 @@ __global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __re
     t.sub_shift = 0;
     t.rep = hp.rep;
     hist_tile<PREC, 0, RM>(t, lds);
+}
+
+// The same work list with the lanes-over-features tile: every problem of the
+// level shares W and the slot mode; the slot codes are the leaf indices.
+template <int PREC, int RM, int W, int MODE>
+__global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __restrict__ probs,
+                                                   const DevTile* __restrict__ tiles,
+                                                   const LevelPlan::DevHP* __restrict__ plans,
+                                                   int64_t n_tiles, int32_t L) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t ti = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (ti >= n_tiles) return;
+    const DevTile tile = tiles[ti];
+    const DevProb pr = probs[tile.prob];
+    const LevelPlan::DevHP hp = plans[tile.prob];
+    LpfBlock b;
+    b.bins = pr.bins;
+    b.seg = pr.seg;
+    b.g = pr.g;
+    b.h = pr.h;
+    b.gq = pr.gq;
+    b.rowcode = pr.leaf;
+    b.partials = pr.partials;
+    b.n = pr.n;
+    b.rows_per_chunk = hp.rows_per_chunk;
+    b.F = pr.F;
+    b.B = pr.B;
+    b.L = L;
+    b.lt = hp.lt;
+    b.wpc = hp.wpc;
+    lpf_block<PREC, RM, W, MODE>(b, tile.chunk, tile.fg, tile.lt_i, lds);
 }
 
 __device__ __forceinline__ int find_owner(const int64_t* __restrict__ off, int P, int64_t gi) {
@@ -212,6 +247,42 @@ void batch_init_attrs(int max_lds) {
         (const void*)bhist_kernel<CBH_PREC_INT16, 0>, (const void*)bhist_kernel<CBH_PREC_INT16, 1>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+#define CBH_BLPF_ATTR(P, R, M)                                                               \
+    {                                                                                        \
+        const void* l[] = {(const void*)blpf_kernel<P, R, 32, M>,                            \
+                           (const void*)blpf_kernel<P, R, 16, M>,                            \
+                           (const void*)blpf_kernel<P, R, 8, M>,                             \
+                           (const void*)blpf_kernel<P, R, 4, M>};                            \
+        for (const void* f : l)                                                              \
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds); \
+    }
+#define CBH_BLPF_ATTR3(P, R) CBH_BLPF_ATTR(P, R, 0) CBH_BLPF_ATTR(P, R, 1) CBH_BLPF_ATTR(P, R, 2)
+    CBH_BLPF_ATTR3(CBH_PREC_FP32, 0)
+    CBH_BLPF_ATTR3(CBH_PREC_FP32, 1)
+    CBH_BLPF_ATTR3(CBH_PREC_TWOFLOAT, 0)
+    CBH_BLPF_ATTR3(CBH_PREC_TWOFLOAT, 1)
+    CBH_BLPF_ATTR3(CBH_PREC_INT16, 0)
+#undef CBH_BLPF_ATTR3
+#undef CBH_BLPF_ATTR
+}
+
+template <int PREC, int RM, int MODE>
+static void launch_blpf_mode(const cbh_batch* b, const LevelPlan& lp, int L, dim3 grd,
+                             size_t lds, hipStream_t s) {
+    switch (lp.W) {
+        case 32: blpf_kernel<PREC, RM, 32, MODE><<<grd, kHistThreads, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L); break;
+        case 16: blpf_kernel<PREC, RM, 16, MODE><<<grd, kHistThreads, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L); break;
+        case 8: blpf_kernel<PREC, RM, 8, MODE><<<grd, kHistThreads, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L); break;
+        default: blpf_kernel<PREC, RM, 4, MODE><<<grd, kHistThreads, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L); break;
+    }
+}
+
+template <int PREC, int RM>
+static void launch_blpf(const cbh_batch* b, const LevelPlan& lp, int L, dim3 grd, size_t lds,
+                        hipStream_t s) {
+    if (lp.mode == 0) launch_blpf_mode<PREC, RM, 0>(b, lp, L, grd, lds, s);
+    else if (lp.mode == 1) launch_blpf_mode<PREC, RM, 1>(b, lp, L, grd, lds, s);
+    else launch_blpf_mode<PREC, RM, 2>(b, lp, L, grd, lds, s);
 }
 
 static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_t s) {
@@ -222,7 +293,21 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     const bool rm = b->probs[0].loss == CBH_LOSS_RMSE;
     const dim3 grd((unsigned)grid), blk(kHistThreads);
     const size_t lds = (size_t)lp.max_lds;
-    switch (b->precision) {
+    if (lp.kind == 1) {
+        switch (b->precision) {
+            case CBH_PREC_FP32:
+                if (rm) launch_blpf<CBH_PREC_FP32, 1>(b, lp, L, grd, lds, s);
+                else launch_blpf<CBH_PREC_FP32, 0>(b, lp, L, grd, lds, s);
+                break;
+            case CBH_PREC_TWOFLOAT:
+                if (rm) launch_blpf<CBH_PREC_TWOFLOAT, 1>(b, lp, L, grd, lds, s);
+                else launch_blpf<CBH_PREC_TWOFLOAT, 0>(b, lp, L, grd, lds, s);
+                break;
+            default:
+                launch_blpf<CBH_PREC_INT16, 0>(b, lp, L, grd, lds, s);
+                break;
+        }
+    } else switch (b->precision) {
         case CBH_PREC_FP32:
             if (rm) bhist_kernel<CBH_PREC_FP32, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             else bhist_kernel<CBH_PREC_FP32, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
@@ -337,17 +422,47 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         std::vector<LevelPlan::DevHP> dplans;
         std::vector<int64_t> cell_off{0}, feat_off{0}, row_off{0};
         int64_t off = 0;
-        for (int p = 0; p < P; ++p) {
-            const cbh_problem& pr = probs[p];
+        // in a batch the problems share the chip: aim at a share of the blocks
+        auto batch_knobs = [&](const cbh_problem& pr) {
             const HistKnobs kn =
                 knobs_for(ctx, pr.n_features, pr.max_bins, pr.K, lvl, precision, pr.n, 0);
-            // in a batch the problems share the chip: aim at a share of the blocks
             HistKnobs kb = kn;
-            kb.kernel = 0;      // the batched tile kernel takes rows over lanes
             kb.target_blocks = std::max<int32_t>(
                 64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
+            return kb;
+        };
+        // One histogram kernel serves the whole level: lanes over features
+        // when every problem has one class and its knobs ask for that kernel,
+        // with the narrowest group width any problem needs; else rows over
+        // lanes.
+        lp.kind = 1;
+        lp.W = 32;
+        for (int p = 0; p < P; ++p) {
+            const HistKnobs kb = batch_knobs(probs[p]);
+            if (probs[p].K != 1 || kb.kernel != 1) {
+                lp.kind = 0;
+                break;
+            }
+            const HistPlan hp = plan_hist(kb, probs[p].n, probs[p].n_features, probs[p].max_bins,
+                                          1, L, precision, probs[p].loss == CBH_LOSS_RMSE,
+                                          ctx->max_lds);
+            lp.W = std::min(lp.W, hp.fb);
+        }
+        lp.mode = L == 1 ? 0 : 1;
+        for (int p = 0; p < P; ++p) {
+            const cbh_problem& pr = probs[p];
+            HistKnobs kb = batch_knobs(pr);
+            kb.kernel = lp.kind;
+            kb.lpf_w = lp.W;
             HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, L, precision,
                                     pr.loss == CBH_LOSS_RMSE, ctx->max_lds);
+            if (lp.kind == 1 && hp.fb != lp.W) {
+                set_error("batched group width %d differs from %d", hp.fb, lp.W);
+                free_levels(b);
+                delete b;
+                return CBH_EUNSUPPORTED;
+            }
+            if (lp.kind == 1 && hp.n_ltiles > 1 && L > 1) lp.mode = 2;
             lp.plans.push_back(hp);
             lp.part_off.push_back(off);
             off += align_up(int64_t(hp.n_chunks) * L * pr.n_features * pr.max_bins *

@@ -64,27 +64,6 @@ HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t
     return ctx->knobs;
 }
 
-// Launch plan of one histogram level.
-//   leaves per tile lt: all leaves if one leaf row per feature fits the LDS
-//     budget, else the largest power of two that does (extra tiles re-read
-//     the rows from cache, not from HBM);
-//   chunks C (row ranges): bounded by the rows a block needs to be efficient
-//     (min_rows) and by the partial-tile volume C * L * F * B * wpc * 4, kept
-//     under partial_pct % of the n * F bin bytes;
-//   feature groups: as many as needed to reach target_blocks, at least enough
-//     to respect the LDS bound on features per block.
-// bytes per (slot, bin, feature) over all stats
-template <int PREC>
-__host__ __device__ constexpr uint32_t lpf_cell_bytes() { return PREC == CBH_PREC_INT16 ? 8u : 16u; }
-
-// Bytes of one (slot, bin) record of the tile (W features x all stats). For
-// narrow groups (W * CS <= 128) several lanes share a feature, and their bins
-// decide the bank: an 8-byte pad makes the record an odd number of 8-byte
-// words, so different bins fall on different banks.
-__host__ __device__ constexpr uint32_t lpf_record_bytes(uint32_t W, uint32_t CS) {
-    return W * CS <= 128 ? W * CS + 8 : W * CS;
-}
-
 // Plan of the lanes-over-features kernel: the widest lane group W (at most
 // the requested one) whose tile of all slots fits the LDS budget; if even
 // W = 4 does not fit, the slots are split into tiles (rows re-read per tile).
@@ -123,6 +102,15 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
     return p;
 }
 
+// Launch plan of one histogram level.
+//   leaves per tile lt: all leaves if one leaf row per feature fits the LDS
+//     budget, else the largest power of two that does (extra tiles re-read
+//     the rows from cache, not from HBM);
+//   chunks C (row ranges): bounded by the rows a block needs to be efficient
+//     (min_rows) and by the partial-tile volume C * L * F * B * wpc * 4, kept
+//     under partial_pct % of the n * F bin bytes;
+//   feature groups: as many as needed to reach target_blocks, at least enough
+//     to respect the LDS bound on features per block.
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                    int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds) {
     if (kn.kernel == 1 && K == 1) return plan_lpf(kn, n, F, B, n_leaves, precision, max_lds);
@@ -500,151 +488,10 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
     }
 }
 
-// ------------------------------------------- lanes-over-features variant
-// For one class (K = 1). Lane l of a wave owns feature f0 + l % W of the
-// block's group of W features and the 16-row segment l / W of the wave's
-// current group of 64 / W segments. The LDS tile is [slot][bin][stat][W] of
-// 8-byte elements (one stat, the packed int16 codes; or two, FP64 g and then
-// the count or the FP64 h), so in one atomic instruction the lanes with
-// distinct features touch distinct banks whatever their bins are, with no
-// replicas. With the bins in
-// the tiled layout the W segments of one row group are adjacent in memory and
-// a wave's bin load is fully coalesced; plain columns work too.
-// LDS byte offset, in slot 0, of the first stat of (bin of row r of the
-// segment's words, this lane's feature): bin * W * CS + lane_off, where
-// lane_off = 8 * feature; the second stat is W * 8 bytes further.
-template <int W, int CS>
-__device__ __forceinline__ uint32_t lpf_addr(const uint32_t (&bw)[4], int r, uint32_t lane_off) {
-    const uint32_t word = bw[r >> 2];
-    if constexpr (W * CS == 256) {
-        // byte 1 <- bin, byte 0 <- lane_off (< 256), bytes 2 and 3 <- 0
-        return __builtin_amdgcn_perm(word, lane_off, 0x0c0c0000u | ((4u + (r & 3)) << 8));
-    } else if constexpr (W * CS == 512) {
-        return __builtin_amdgcn_perm(word, lane_off >> 1, 0x0c0c0000u | ((4u + (r & 3)) << 8))
-               << 1;
-    } else {
-        return ((word >> (8 * (r & 3))) & 255u) * lpf_record_bytes(W, CS) + lane_off;
-    }
-}
-
-// Add rows r0 .. r0+7 of one 16-row segment (bins in bw) to the tile.
-// off[k]: slot byte offset of row r0 + k, or kLpfSkip; CHECK = false when every
-// row is known to be valid.
-constexpr uint32_t kLpfSkip = 0xffffffffu;
-
-template <int PREC, int RM, int W, bool CHECK>
-__device__ __forceinline__ void lpf_rows8(char* tile, const uint32_t (&bw)[4], int r0,
-                                          uint32_t lane_off, const uint32_t (&off)[8],
-                                          const float (&gv)[8], const float (&hv)[8],
-                                          const uint32_t (&qv)[8]) {
-    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (CHECK && off[k] == kLpfSkip) continue;
-        const uint32_t ad = lpf_addr<W, CS>(bw, r0 + k, lane_off) + off[k];
-        if constexpr (PREC == CBH_PREC_INT16) {
-            // (g code << 32) + h code: both halves stay exact for <= 65536
-            // rows per chunk. The h code (high half of the word) is in
-            // [0, 32767]; the g code (low half) is sign-extended.
-            const uint32_t hq = qv[k] >> 16;
-            const uint32_t gq = (uint32_t)((int32_t)(qv[k] << 16) >> 16);
-            const uint64_t packed = ((uint64_t)gq << 32) | hq;
-            __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(tile + ad),
-                                   (unsigned long long)packed, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad), (double)gv[k],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if constexpr (RM != 0)
-                __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad + W * 8), 1u,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            else
-                __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad + W * 8),
-                                       (double)hv[k], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    }
-}
-
-// One 16-row segment of the lanes-over-features kernel: its bins (this
-// lane's feature), row codes and gradient statistics, loaded with 16-byte
-// loads; add() puts its rows into the tile, 8 at a time.
-template <int PREC, int RM, int MODE>
-struct LpfSeg {
-    uint4 b;
-    uint4 c[2];      // row codes (MODE != 0)
-    uint4 q[4];      // int16 codes
-    float4 g[4], h[4];
-    __device__ __forceinline__ void load(const uint8_t* col, int64_t sstride,
-                                         const uint16_t* rowcode, const HistArgs& a, int64_t t) {
-        const int64_t i = t << 4;
-        b = *reinterpret_cast<const uint4*>(col + t * sstride);
-        if constexpr (MODE != 0) {
-            c[0] = *reinterpret_cast<const uint4*>(rowcode + i);
-            c[1] = *reinterpret_cast<const uint4*>(rowcode + i + 8);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if constexpr (PREC == CBH_PREC_INT16) {
-                q[k] = *reinterpret_cast<const uint4*>(a.gq + i + 4 * k);
-            } else {
-                g[k] = *reinterpret_cast<const float4*>(a.g + i + 4 * k);
-                if constexpr (RM == 0) h[k] = *reinterpret_cast<const float4*>(a.h + i + 4 * k);
-            }
-        }
-    }
-    template <int W>
-    __device__ __forceinline__ void add(char* tile, uint32_t lane_off, uint32_t s0, uint32_t ns,
-                                        uint32_t slot_bytes) const {
-        const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int h2 = 0; h2 < 2; ++h2) {
-            uint32_t off[8];
-            float gv[8], hv[8];
-            uint32_t qv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                off[k] = 0u;
-                if constexpr (MODE != 0) {
-                    const uint4 cc = c[h2];
-                    const uint32_t lw[4] = {cc.x, cc.y, cc.z, cc.w};
-                    const uint32_t code = (lw[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                    const uint32_t sl = code - s0;
-                    off[k] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
-                }
-                const int r = 8 * h2 + k;
-                if constexpr (PREC == CBH_PREC_INT16) {
-                    const uint4 qq = q[r >> 2];
-                    const uint32_t qw[4] = {qq.x, qq.y, qq.z, qq.w};
-                    qv[k] = qw[r & 3];
-                    gv[k] = hv[k] = 0.f;
-                } else {
-                    const float4 gg = g[r >> 2];
-                    const float gw[4] = {gg.x, gg.y, gg.z, gg.w};
-                    gv[k] = gw[r & 3];
-                    hv[k] = 0.f;
-                    if constexpr (RM == 0) {
-                        const float4 hh = h[r >> 2];
-                        const float hw[4] = {hh.x, hh.y, hh.z, hh.w};
-                        hv[k] = hw[r & 3];
-                    }
-                    qv[k] = 0u;
-                }
-            }
-            lpf_rows8<PREC, RM, W, MODE == 2>(tile, bw, 8 * h2, lane_off, off, gv, hv, qv);
-        }
-    }
-};
-
-// MODE 0: one slot (level 0, direct): no per-row reads, no checks.
-// MODE 1: all slots of a direct build in one tile: slot = row code (the leaf).
-// MODE 2: subtraction and/or several slot tiles: slot = row code - first slot
-//         of the tile, rows outside the tile (or with code 0xffff) skipped.
+// Single-problem launch: block -> (slot tile, feature group, chunk), XCD-contiguous.
 template <int PREC, int RM, int W, int MODE>
 __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
-    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
-    constexpr int RG = 64 / W;                  // segments per wave step
     const int64_t per_xcd = (a.n_blocks + 7) / 8;
     int64_t item = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (item >= a.n_blocks) return;
@@ -652,136 +499,22 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     item /= a.n_ltiles;
     const int fg = (int)(item % a.n_fgroups);
     const int64_t chunk = item / a.n_fgroups;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const int fl = lane & (W - 1), rq = lane / W;
-    const int f0 = fg * W;
-    const int nf = min(W, a.F - f0);
-    const bool fok = fl < nf;
-    const int f = f0 + (fok ? fl : 0);
-    const uint8_t* col = a.bins[f];
-    const int64_t sstride = a.seg ? a.seg[f] : 16;
-    const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;               // first slot of the tile
-    const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);       // slots in the tile (<= 64)
-    const uint32_t slot_bytes = (uint32_t)a.B * lpf_record_bytes(W, CS);
-    const uint32_t tile_words = ns * slot_bytes / 4;
-    for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
-    __syncthreads();
-    char* tile = reinterpret_cast<char*>(lds);
-    const int64_t r0 = chunk * a.rows_per_chunk;
-    const int64_t r1 = min(a.n, r0 + a.rows_per_chunk);
-    const int64_t t_full = r1 >> 4;            // segments before this one are full
-    const uint32_t lane_off = (uint32_t)fl * 8u;
-    const uint16_t* rowcode = a.rowcode;
-    const bool vec = ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(a.g) |
-                       reinterpret_cast<uintptr_t>(a.h) | reinterpret_cast<uintptr_t>(a.gq) |
-                       reinterpret_cast<uintptr_t>(rowcode)) & 15) == 0;
-    int64_t t = (r0 >> 4) + int64_t(wave) * RG + rq;
-    const int64_t step = int64_t(nwaves) * RG;
-    if (vec && t < t_full) {
-        // software pipeline: the loads of the next segment are issued before
-        // the atomics of the current one (two register sets, A and B)
-        LpfSeg<PREC, RM, MODE> A, B;
-        A.load(col, sstride, rowcode, a, t);
-        for (;;) {
-            int64_t tn = t + step;
-            if (tn < t_full) B.load(col, sstride, rowcode, a, tn);
-            if (fok) A.template add<W>(tile, lane_off, s0, ns, slot_bytes);
-            t = tn;
-            if (t >= t_full) break;
-            tn = t + step;
-            if (tn < t_full) A.load(col, sstride, rowcode, a, tn);
-            if (fok) B.template add<W>(tile, lane_off, s0, ns, slot_bytes);
-            t = tn;
-            if (t >= t_full) break;
-        }
-    }
-    // the ragged last segment, and everything when a pointer is unaligned:
-    // one row at a time
-    for (; t < ((r1 + 15) >> 4); t += int64_t(nwaves) * RG) {
-        const int64_t i = t << 4;
-        const uint8_t* pb = col + t * sstride;
-        for (int r = 0; r < 16 && i + r < r1; ++r) {
-            const uint32_t bwr[4] = {(uint32_t)pb[r], 0u, 0u, 0u};
-            uint32_t o1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-            float g1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            float h1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            uint32_t q1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-            if constexpr (MODE != 0) {
-                const uint32_t code = rowcode[i + r];
-                const uint32_t sl = code - s0;
-                o1[0] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
-            }
-            if constexpr (PREC == CBH_PREC_INT16) {
-                q1[0] = a.gq[i + r];
-            } else {
-                g1[0] = a.g[i + r];
-                if constexpr (RM == 0) h1[0] = a.h[i + r];
-            }
-            if (fok && o1[0] != kLpfSkip) {
-                // one row: use the per-row routine on a segment holding only this bin
-                constexpr uint32_t CSz = lpf_cell_bytes<PREC>();
-                const uint32_t ad = lpf_addr<W, CSz>(bwr, 0, lane_off) + o1[0];
-                if constexpr (PREC == CBH_PREC_INT16) {
-                    const uint64_t packed =
-                        ((uint64_t)(int64_t)(int16_t)(q1[0] & 0xffffu) << 32) +
-                        ((q1[0] >> 16) & 0x7fffu);
-                    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(tile + ad),
-                                           (unsigned long long)packed, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                } else {
-                    __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad), (double)g1[0],
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if constexpr (RM != 0)
-                        __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad + W * 8), 1u,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    else
-                        __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad + W * 8),
-                                               (double)h1[0], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // write the tile in the partial's [L][F][B][wpc] order; consecutive threads
-    // take consecutive features of one (slot, bin), so the LDS reads are
-    // conflict-free and every thread writes one whole cell
-    uint32_t* part = a.partials + chunk * (int64_t(a.L) * a.F * a.B * a.wpc);
-    const uint32_t cells = ns * (uint32_t)a.B * W;
-    for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) {
-        const uint32_t cfl = c & (W - 1);
-        if ((int)cfl >= nf) continue;
-        const uint32_t sb = c / W;                 // slot * B + bin
-        const uint32_t bin = sb % (uint32_t)a.B, sl = sb / (uint32_t)a.B;
-        // first stat; the second is W * 8 bytes further
-        const char* cell = tile + (size_t)sb * lpf_record_bytes(W, CS) + cfl * 8u;
-        const int64_t o = ((int64_t(s0 + sl) * a.F + f0 + cfl) * a.B + bin) * a.wpc;
-        if constexpr (PREC == CBH_PREC_INT16) {
-            *reinterpret_cast<uint2*>(part + o) = *reinterpret_cast<const uint2*>(cell);
-        } else {
-            const double gs = *reinterpret_cast<const double*>(cell);
-            const float ghi = (float)gs;
-            uint32_t w1;                               // count or h, as stored in the output
-            float hlo = 0.f;
-            if constexpr (RM != 0) {
-                w1 = *reinterpret_cast<const uint32_t*>(cell + W * 8);
-            } else {
-                const double hs = *reinterpret_cast<const double*>(cell + W * 8);
-                const float hhi = (float)hs;
-                hlo = (float)(hs - (double)hhi);
-                w1 = __float_as_uint(hhi);
-            }
-            if constexpr (PREC == CBH_PREC_FP32) {
-                *reinterpret_cast<uint2*>(part + o) = make_uint2(__float_as_uint(ghi), w1);
-            } else {
-                const float glo = (float)(gs - (double)ghi);
-                *reinterpret_cast<uint4*>(part + o) =
-                    make_uint4(__float_as_uint(ghi), __float_as_uint(glo), w1,
-                               RM != 0 ? 0u : __float_as_uint(hlo));
-            }
-        }
-    }
+    LpfBlock b;
+    b.bins = a.bins;
+    b.seg = a.seg;
+    b.g = a.g;
+    b.h = a.h;
+    b.gq = a.gq;
+    b.rowcode = a.rowcode;
+    b.partials = a.partials;
+    b.n = a.n;
+    b.rows_per_chunk = a.rows_per_chunk;
+    b.F = a.F;
+    b.B = a.B;
+    b.L = a.L;
+    b.lt = a.lt;
+    b.wpc = a.wpc;
+    lpf_block<PREC, RM, W, MODE>(b, chunk, fg, lt_i, lds);
 }
 
 void hist_init_attrs(int max_lds) {

@@ -217,14 +217,24 @@ def _batch_setup(cb, probs, prec):
     return bsts
 
 
-@pytest.mark.parametrize("prec", [0, 2])
-def test_batched_matches_single(cb, prec):
+# knobs of the batched plan: the default (lanes over features, one slot tile),
+# a small LDS budget (lanes over features, several slot tiles per level: the
+# row codes outside a tile are skipped) and the rows-over-lanes kernel
+BATCH_KNOBS = {"default": None, "lpf_split": (12288, 1024, 4096, 50, 1, 1, 1, 0),
+               "rows_over_lanes": (65536, 1024, 4096, 50, 4, 2, 0, 0)}
+
+
+@pytest.mark.parametrize("knobs", list(BATCH_KNOBS))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_batched_matches_single(cb, prec, knobs):
     probs = datagen.make_c4(P=5, scale=0.01)
     for p in probs:
         p.depth = 5
     single = _batch_setup(cb, probs, prec)
     batched = _batch_setup(cb, probs, prec)
     ctx = batched[0].ctx
+    if BATCH_KNOBS[knobs] is not None:
+        cb.cbh_set_hist_knobs(ctx, *BATCH_KNOBS[knobs])
     P = len(probs)
     depth = probs[0].depth
     best = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
