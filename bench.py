@@ -370,6 +370,80 @@ def time_form(bst, name, args, rmse):
     }
 
 
+def batch_vs_one_by_one(ctx, probs, hists, lvs, prec, lr, l2, side, timed):
+    """ms per iteration of the problems batched in one plan (one captured
+    graph), and of the same problems each from a one-problem plan and graph
+    replayed one after another (the same kernels, P times the launches)."""
+    import torch
+
+    from paper_1810_11363_amd import cbhip as cb
+    P = len(probs)
+    depth = probs[0].depth
+    best = torch.zeros((P, depth, 4), dtype=torch.int32, device=hists[0].device)
+    plan = cb.cbh_batch_create(ctx, probs, prec, hists, best)
+    singles = [cb.cbh_batch_create(ctx, [probs[i]], prec, [hists[i]], best[i])
+               for i in range(P)]
+    cb.cbh_batch_update(ctx, plan, lr, l2, lvs, True, side.cuda_stream)
+    gr = cb.cbh_graph_capture_iteration(ctx, plan, lr, l2, lvs, side.cuda_stream)
+    grs = [cb.cbh_graph_capture_iteration(ctx, pl, lr, l2, [lvs[i]], side.cuda_stream)
+           for i, pl in enumerate(singles)]
+
+    def one_by_one():
+        for g in grs:
+            cb.cbh_graph_launch(g, side.cuda_stream)
+    with torch.cuda.stream(side):
+        ms_b = timed(lambda: cb.cbh_graph_launch(gr, side.cuda_stream), side)
+        ms_s = timed(one_by_one, side)
+    cb.cbh_sync(ctx, side.cuda_stream)
+    for g in [gr] + grs:
+        cb.cbh_graph_destroy(g)
+    for pl in [plan] + singles:
+        cb.cbh_batch_destroy(pl)
+    return ms_b, ms_s
+
+
+def c2_batches(args, ctx, prec, side, timed):
+    """The 1M-row RMSE problem as a 5-fold cross-validation batch (each fold
+    trains on 4/5 of the rows, numeric borders chosen once on all rows) and
+    as an 8-permutation ordered-boosting batch (8 models, each over its own
+    permutation's ordered-statistic columns, sharing the numeric bins)."""
+    import datagen
+    from paper_1810_11363_amd.booster import GpuBooster
+    t0 = time.perf_counter()
+    base = datagen.make_c2(n=args.c2_rows, s=8)
+    full = GpuBooster.from_problem(base, precision=prec, ctx=ctx).prepare()
+    folds = [GpuBooster.from_problem(q, precision=prec, ctx=ctx,
+                                     borders=full.num_borders).prepare()
+             for q in datagen.cv_folds(base, 5)]
+    states = [full.model_state(r) for r in range(8)]
+    print(f"# cross-validation and permutation batches prepared in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    res = []
+    for name, probs, hists, lvs in [
+            ("cv", [b.probs[0] for b in folds], [b.hist for b in folds],
+             [b.leaf_values for b in folds]),
+            ("perm", [m.prob for m in states], [m.hist for m in states],
+             [m.leaf_values for m in states])]:
+        ms_b, ms_s = batch_vs_one_by_one(ctx, probs, hists, lvs, prec, full.lr, full.l2, side,
+                                         timed)
+        rows = sum(int(p.n) for p in probs)
+        res.append({
+            "problems": len(probs), "rows": rows, "features": full.F, "depth": full.depth,
+            "ms_per_iteration": round(ms_b, 4), "ms_per_tree": round(ms_b / len(probs), 5),
+            "g_row_features_per_s": round(rows * full.F * full.depth / (ms_b / 1e3) / 1e9, 3),
+            "one_plan_per_problem_ms_per_iteration": round(ms_s, 4),
+            "batched_vs_one_plan_per_problem": round(ms_s / ms_b, 3)})
+        print(f"# {name} batch: {ms_b:.3f} ms/iteration, one plan per problem {ms_s:.3f}",
+              file=sys.stderr, flush=True)
+    res[0]["workload"] = (f"5-fold cross-validation of the {args.c2_rows}-row RMSE problem "
+                          f"(110 features x 128 bins, depth 6), one model per fold")
+    res[1]["workload"] = (f"8 ordered-boosting permutations of the {args.c2_rows}-row RMSE "
+                          f"problem, one model per permutation")
+    for b in folds + [full]:
+        b.close()
+    return res[0], res[1]
+
+
 def run_batch(args):
     """The batching workload: P independent RMSE problems (row counts
     log-uniform in [5e3, 2e6]) trained together, one boosting iteration of
@@ -455,6 +529,10 @@ def run_batch(args):
     cb.cbh_batch_destroy(plan)
     for b in bsts:
         b.close()
+    del bsts
+    if args.c2_rows > 0:
+        cv, perm = c2_batches(args, ctx, prec, side, timed)
+        out["cv_batch"], out["perm_batch"] = cv, perm
     cb.cbh_destroy(ctx)
     if not args.no_cpu:
         # the oracle on the smallest problems whose rows add up to ~1e6
@@ -505,6 +583,9 @@ def main():
     ap.add_argument("--batch-p", type=int, default=64, help="problems of the batching workload")
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="row-count scale of the batching workload")
+    ap.add_argument("--c2-rows", type=int, default=1_000_000,
+                    help="rows of the cross-validation and permutation batches of the "
+                         "batching workload (0: leave them out)")
     ap.add_argument("--cpu-rows", type=int, default=None)
     ap.add_argument("--cpu-trees", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true",

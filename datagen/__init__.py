@@ -254,6 +254,27 @@ def _c4_problem(cfg: int, stream: int, n: int, name: str) -> Problem:
     return _finish_targets(p)
 
 
+def cv_folds(p: Problem, k: int = 5, cfg: int = 4, stream: int = 200) -> list[Problem]:
+    """k cross-validation training problems of p: a seeded shuffle of the rows
+    cut into k near-equal parts; problem j trains on the rows outside part j
+    (kept in their original order) with one seeded permutation of its own."""
+    order = rng_for(cfg, stream).permutation(p.n)
+    parts = np.array_split(order, k)
+    out = []
+    for j in range(k):
+        keep = np.ones(p.n, bool)
+        keep[parts[j]] = False
+        rows = np.flatnonzero(keep)
+        m = rows.size
+        perm = rng_for(cfg, stream + 1 + j).permutation(m).astype(np.int32)[None, :]
+        q = Problem(f"{p.name}_fold{j}", np.ascontiguousarray(p.x_num[:, rows]),
+                    np.ascontiguousarray(p.cat[:, rows]), np.ascontiguousarray(p.label[rows]),
+                    perm, p.loss, p.K, depth=p.depth, iterations=p.iterations, lr=p.lr,
+                    l2=p.l2, num_bins=p.num_bins, ts_bins=p.ts_bins, a=p.a)
+        out.append(_finish_targets(q))
+    return out
+
+
 def c4_sizes(P: int = 64, lo: int = 5_000, hi: int = 2_000_000, scale: float = 1.0):
     g = rng_for(4, 0)
     n = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), P))).astype(np.int64)

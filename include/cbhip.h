@@ -345,25 +345,42 @@ int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_la
 typedef struct cbh_batch cbh_batch;
 
 /* A plan for running tree levels of P independent problems together (for
- * example several permutations, folds or separate datasets). The problem
- * descriptors and the histogram buffers are copied to device memory once; the
- * device buffers they point to must stay valid while the plan exists.
+ * example several permutations, folds or separate datasets; the batching of
+ * the s permutations of Sec. 3 and of the many histograms per launch of
+ * Sec. 5). The problem descriptors and the histogram buffers are copied to
+ * device memory once; the device buffers they point to must stay valid while
+ * the plan exists.
  *   probs     host array [P]; every problem must have the same depth and loss
+ *   subtract  != 0: levels >= 1 build only the smaller child of every parent
+ *             and take the other as parent minus child (as
+ *             cbh_build_histograms_sub); applies when every problem has
+ *             K = 1, else ignored. The plan then keeps a second histogram
+ *             buffer per problem, the sides and the row codes in its own
+ *             workspace.
  *   hist      host array [P] of device pointers; hist[p] must hold the level
- *             depth-1 histograms of problem p (size as cbh_build_histograms)
+ *             depth-1 histograms of problem p (size as cbh_build_histograms);
+ *             after a level of the plan it holds that level's histograms if
+ *             depth-1-level is even (else the plan's second buffer does)
  *   best      device cbh_split [P][depth]: split of every problem and level
  * Precision must be CBH_PREC_FP32 or CBH_PREC_TWOFLOAT or CBH_PREC_INT16. */
 int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P,
-                     int32_t precision, void* const* hist, cbh_split* best,
-                     cbh_batch** out);
+                     int32_t precision, int32_t subtract, void* const* hist,
+                     cbh_split* best, cbh_batch** out);
 void cbh_batch_destroy(cbh_batch* batch);
 
 /* One level of every problem of the plan: histograms, score, argmax and the
  * leaf update, with the split written to best[p][level]. The level runs as
  * five launches shared by all problems (histogram tiles of every problem from
  * one work list, partial merge, score of every (problem, feature), argmax per
- * problem, leaf-bit update over every row), so the launch count does not grow
- * with P. The plan uses the rows-over-lanes histogram kernel. */
+ * problem, leaf-bit update over every row), plus, for a level >= 1 built by
+ * subtraction, a first launch over every row that picks each parent's smaller
+ * child and writes the rows' slot codes; the launch count does not grow with
+ * P. When every problem has K = 1 the histogram launch uses the kernel that
+ * spreads the features of a group over the lanes of a wave, with one group
+ * width for all problems of the level; otherwise (or when the histogram knobs
+ * ask for it) the kernel that spreads rows over lanes. Levels must run in
+ * order 0, 1, ..., depth-1 (a level reads the previous level's histograms and
+ * splits). */
 int cbh_batch_level(cbh_ctx* ctx, cbh_batch* batch, int32_t level, double l2,
                     void* stream);
 

@@ -55,7 +55,8 @@ class GpuBooster:
 
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
-                 subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled"):
+                 subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled",
+                 borders=None):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -83,6 +84,13 @@ class GpuBooster:
         self.T = self.y_num.shape[0] if self.F_cat else 0
         self.s = self.perms.shape[0] if self.F_cat else 1
         self.F = self.F_num + self.F_cat * self.T
+        # numeric borders chosen elsewhere (e.g. on the whole dataset before a
+        # split into folds), one float32 array per numeric feature; None: chosen
+        # here from x_num
+        self.given_borders = None if borders is None else [
+            np.ascontiguousarray(v, dtype=np.float32) for v in borders]
+        if self.given_borders is not None and len(self.given_borders) != self.x_num.shape[0]:
+            raise ValueError("borders needs one array per numeric feature")
         self.timings = {}
         self._alloc()
 
@@ -127,9 +135,13 @@ class GpuBooster:
         t0 = time.perf_counter()
         # host border selection, one feature per task (the library call runs
         # without the interpreter lock)
-        with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
-            borders = list(ex.map(lambda f: cb.cbh_select_borders(self.x_num[f], self.num_bins),
-                                  range(self.F_num)))
+        if self.given_borders is not None:
+            borders = self.given_borders
+        else:
+            with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+                borders = list(ex.map(
+                    lambda f: cb.cbh_select_borders(self.x_num[f], self.num_bins),
+                    range(self.F_num)))
         t1 = time.perf_counter()
         self.num_borders = borders
         x_d = torch.from_numpy(self.x_num).to(d)
@@ -349,6 +361,10 @@ class GpuBooster:
                 trees.append(self.tree_record())
         return trees
 
+    def model_state(self, r: int) -> "ModelState":
+        """A further model over permutation r's bins (see ModelState)."""
+        return ModelState(self, r)
+
     def close(self):
         if self.own_ctx and self.ctx:
             torch.cuda.synchronize(self.device)
@@ -360,3 +376,35 @@ class GpuBooster:
             self.close()
         except Exception:
             pass
+
+
+class ModelState:
+    """The per-model device state (gradients, int16 codes, leaf indices,
+    approx, last-level histogram, leaf values) of one more model over the bins
+    of a prepared booster's permutation r; bins, bin counts and labels stay
+    shared with the booster. Ordered boosting keeps one model per permutation
+    (Sec. 3); several such models run side by side through the batched calls
+    (cbh_batch_create with `prob`, `hist` and `leaf_values` of each)."""
+
+    def __init__(self, base: GpuBooster, r: int):
+        if not hasattr(base, "probs"):
+            raise RuntimeError("prepare() the booster first")
+        d, n, K = base.device, base.n, base.K
+        self.base, self.r = base, int(r)
+        self.g = torch.empty((K, n), dtype=torch.float32, device=d)
+        self.h = torch.empty((K, n), dtype=torch.float32, device=d)
+        self.gq = torch.empty((K, n, 2), dtype=torch.int16, device=d)
+        self.grad_scale = torch.zeros((K, 2), dtype=torch.float32, device=d)
+        self.leaf = torch.zeros(n, dtype=torch.uint16, device=d)
+        self.approx = torch.zeros((K, n), dtype=torch.float64, device=d)
+        self.leaf_values = torch.zeros((1 << base.depth, K), dtype=torch.float64, device=d)
+        self.hist = torch.empty(max(256, base._hist_bytes(base.depth - 1)), dtype=torch.uint8,
+                                device=d)
+        p = base.problem(self.r)
+        p.g = self.g.data_ptr()
+        p.h = self.h.data_ptr()
+        p.gq = self.gq.data_ptr()
+        p.grad_scale = self.grad_scale.data_ptr()
+        p.leaf = self.leaf.data_ptr()
+        p.approx = self.approx.data_ptr()
+        self.prob = p

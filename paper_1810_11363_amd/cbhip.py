@@ -88,7 +88,7 @@ def _load():
         "cbh_apply_split": ([vp, C.POINTER(cbh_problem), i32, vp, vp], C.c_int),
         "cbh_update_approx": ([vp, C.POINTER(cbh_problem), vp, i32, vp, dbl, dbl, vp, vp, vp],
                               C.c_int),
-        "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp, C.POINTER(vp)],
+        "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
         "cbh_batch_level": ([vp, vp, i32, dbl, vp], C.c_int),
@@ -256,13 +256,17 @@ def cbh_update_approx(ctx, prob: cbh_problem, hist_last, precision: int, last, l
 
 
 # ------------------------------------------------------------------ batched
-def cbh_batch_create(ctx, probs, precision: int, hist_ptrs, best):
+def cbh_batch_create(ctx, probs, precision: int, hist_ptrs, best, subtract=None):
+    """subtract: None builds levels >= 1 by subtraction for the two-float and
+    int16 forms (not for plain float32), as the single-problem trees do."""
     P = len(probs)
+    if subtract is None:
+        subtract = precision != CBH_PREC_FP32
     arr = (cbh_problem * P)(*probs)
     hp = (C.c_void_p * P)(*[_ptr(h) for h in hist_ptrs])
     out = C.c_void_p()
-    _check(_lib.cbh_batch_create(ctx, arr, P, precision, C.cast(hp, C.c_void_p), _ptr(best),
-                                 C.byref(out)))
+    _check(_lib.cbh_batch_create(ctx, arr, P, precision, int(bool(subtract)),
+                                 C.cast(hp, C.c_void_p), _ptr(best), C.byref(out)))
     return out.value
 
 

@@ -12,6 +12,11 @@
 //   4. one argmax launch (a block per problem),
 //   5. one apply launch over the rows of every problem,
 // so the launch count per level does not grow with the number of problems.
+// With histogram subtraction (one class per problem), levels >= 1 start with
+// a sixth launch over the rows of every problem that picks the smaller child
+// of each parent and writes per-row slot codes; the histogram launch then
+// accumulates only the smaller children and the merge launch writes both
+// children (the larger one as parent minus smaller).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -39,6 +44,10 @@ struct DevProb {
     int64_t n;
     int32_t F, B, K, rmse;
     const int64_t* seg;      // per-feature segment strides, NULL = columns
+    const void* parent;      // subtraction: the previous level's histogram, else NULL
+    uint8_t* side;           // subtraction: [half] smaller child of each parent
+    uint16_t* codes;         // subtraction: [n] per-row slot codes
+    const uint16_t* rowcode; // slot codes the histogram reads (codes, or the leaf)
 };
 
 // One histogram work item: (problem, chunk, feature group, leaf tile) and its plan.
@@ -69,7 +78,12 @@ struct LevelPlan {
     int64_t* d_feat_off = nullptr;     // per problem prefix of features (P+1)
     int64_t rows_total = 0;
     int64_t* d_row_off = nullptr;      // per problem prefix of rows (P+1)
+    int32_t sub = 0;                   // built by subtraction (levels >= 1)
+    int64_t rb_total = 0;              // row blocks of the side/code launch
+    int64_t* d_rb_off = nullptr;       // per problem prefix of row blocks (P+1)
 };
+
+constexpr int64_t kSideRows = 16384;   // rows per block of the side/code launch
 
 }  // namespace cbh
 
@@ -85,7 +99,10 @@ struct cbh_batch {
     std::vector<cbh::LevelPlan> levels;
     int64_t ws_need = 0;
     int64_t fbest_off = 0;
-    void* ws = nullptr;             // plan-owned partial tiles and feature winners
+    int32_t sub = 0;                // levels >= 1 by subtraction
+    void* ws = nullptr;             // plan-owned partial tiles, feature winners and,
+                                    // with subtraction, the second histogram of
+                                    // every problem, sides and row codes
 };
 
 struct cbh_graph {
@@ -137,7 +154,8 @@ __global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __re
 }
 
 // The same work list with the lanes-over-features tile: every problem of the
-// level shares W and the slot mode; the slot codes are the leaf indices.
+// level shares W and the slot mode; L is the number of slots (the leaves, or
+// the parents in a build by subtraction).
 template <int PREC, int RM, int W, int MODE>
 __global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __restrict__ probs,
                                                    const DevTile* __restrict__ tiles,
@@ -156,7 +174,7 @@ __global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __res
     b.g = pr.g;
     b.h = pr.h;
     b.gq = pr.gq;
-    b.rowcode = pr.leaf;
+    b.rowcode = pr.rowcode;
     b.partials = pr.partials;
     b.n = pr.n;
     b.rows_per_chunk = hp.rows_per_chunk;
@@ -187,8 +205,56 @@ __global__ __launch_bounds__(256) void breduce_kernel(const DevProb* __restrict_
          gi += int64_t(gridDim.x) * 256) {
         const int p = find_owner(cell_off, P, gi);
         const DevProb pr = probs[p];
-        merge_cell<PREC>(pr.partials, cell_off[p + 1] - cell_off[p], pr.K, plans[p].n_chunks,
-                         pr.rmse != 0, pr.hist, gi - cell_off[p]);
+        const int64_t cells = cell_off[p + 1] - cell_off[p];
+        const int64_t cell = gi - cell_off[p];
+        if (pr.parent) {
+            // cell = (parent, feature, bin); the partials hold the smaller child
+            const int64_t fbc = int64_t(pr.F) * pr.B;
+            const int64_t half = cells / fbc;
+            const int64_t par = cell / fbc, rest = cell % fbc;
+            const int64_t sd = pr.side[par];
+            merge_cell<PREC>(pr.partials, cells, pr.K, plans[p].n_chunks, pr.rmse != 0, pr.hist,
+                             cell, (par + sd * half) * fbc + rest,
+                             (par + (1 - sd) * half) * fbc + rest, pr.parent);
+        } else {
+            merge_cell<PREC>(pr.partials, cells, pr.K, plans[p].n_chunks, pr.rmse != 0, pr.hist,
+                             cell, cell);
+        }
+    }
+}
+
+// Build by subtraction, first launch: one block per kSideRows rows of a
+// problem. Every block finds the smaller child of each of the problem's
+// `half` parents (at the previous level's split) in LDS; block 0 of the
+// problem stores them. Then each row gets the slot code of the histogram
+// launch: its parent if it lies on the smaller side, else 0xffff (skipped).
+template <int PREC>
+__global__ __launch_bounds__(256) void bside_code_kernel(const DevProb* __restrict__ probs,
+                                                         const int64_t* __restrict__ rb_off,
+                                                         int32_t P, const cbh_split* __restrict__ best,
+                                                         int32_t depth, int32_t level) {
+    extern __shared__ uint8_t sd[];
+    const int p = find_owner(rb_off, P, blockIdx.x);
+    const DevProb pr = probs[p];
+    const int64_t rb = int64_t(blockIdx.x) - rb_off[p];
+    const int64_t half = int64_t(1) << (level - 1);
+    const cbh_split sp = best[int64_t(p) * depth + level - 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t q = wave; q < half; q += 4) {
+        const uint8_t v = parent_side<PREC>(pr.parent, q, sp.feature, sp.border, pr.F, pr.B,
+                                            pr.K, pr.rmse, lane);
+        if (lane == 0) {
+            sd[q] = v;
+            if (rb == 0) pr.side[q] = v;
+        }
+    }
+    __syncthreads();
+    const uint32_t lmask = (uint32_t)half - 1u, shift = (uint32_t)(level - 1);
+    const int64_t i0 = rb * kSideRows, i1 = min(pr.n, i0 + kSideRows);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const uint32_t v = pr.leaf[i];
+        const uint32_t pp = v & lmask;
+        pr.codes[i] = (uint16_t)((((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu);
     }
 }
 
@@ -289,22 +355,42 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     cbh_ctx* ctx = b->ctx;
     LevelPlan& lp = b->levels[level];
     const int L = 1 << level;
+    const int slots = lp.sub ? L / 2 : L;      // histogram slots: parents or leaves
     const int64_t grid = 8 * ((lp.n_tiles + 7) / 8);
     const bool rm = b->probs[0].loss == CBH_LOSS_RMSE;
     const dim3 grd((unsigned)grid), blk(kHistThreads);
     const size_t lds = (size_t)lp.max_lds;
+    if (lp.sub) {
+        const dim3 sg((unsigned)lp.rb_total);
+        const size_t half = (size_t)(L / 2);
+        switch (b->precision) {
+            case CBH_PREC_FP32:
+                bside_code_kernel<CBH_PREC_FP32><<<sg, 256, half, s>>>(
+                    b->d_probs, lp.d_rb_off, b->P, b->best, b->depth, level);
+                break;
+            case CBH_PREC_TWOFLOAT:
+                bside_code_kernel<CBH_PREC_TWOFLOAT><<<sg, 256, half, s>>>(
+                    b->d_probs, lp.d_rb_off, b->P, b->best, b->depth, level);
+                break;
+            default:
+                bside_code_kernel<CBH_PREC_INT16><<<sg, 256, half, s>>>(
+                    b->d_probs, lp.d_rb_off, b->P, b->best, b->depth, level);
+                break;
+        }
+        CBH_LAUNCHED();
+    }
     if (lp.kind == 1) {
         switch (b->precision) {
             case CBH_PREC_FP32:
-                if (rm) launch_blpf<CBH_PREC_FP32, 1>(b, lp, L, grd, lds, s);
-                else launch_blpf<CBH_PREC_FP32, 0>(b, lp, L, grd, lds, s);
+                if (rm) launch_blpf<CBH_PREC_FP32, 1>(b, lp, slots, grd, lds, s);
+                else launch_blpf<CBH_PREC_FP32, 0>(b, lp, slots, grd, lds, s);
                 break;
             case CBH_PREC_TWOFLOAT:
-                if (rm) launch_blpf<CBH_PREC_TWOFLOAT, 1>(b, lp, L, grd, lds, s);
-                else launch_blpf<CBH_PREC_TWOFLOAT, 0>(b, lp, L, grd, lds, s);
+                if (rm) launch_blpf<CBH_PREC_TWOFLOAT, 1>(b, lp, slots, grd, lds, s);
+                else launch_blpf<CBH_PREC_TWOFLOAT, 0>(b, lp, slots, grd, lds, s);
                 break;
             default:
-                launch_blpf<CBH_PREC_INT16, 0>(b, lp, L, grd, lds, s);
+                launch_blpf<CBH_PREC_INT16, 0>(b, lp, slots, grd, lds, s);
                 break;
         }
     } else switch (b->precision) {
@@ -369,6 +455,7 @@ static void free_levels(cbh_batch* b) {
         if (lp.d_cell_off) (void)hipFree(lp.d_cell_off);
         if (lp.d_feat_off) (void)hipFree(lp.d_feat_off);
         if (lp.d_row_off) (void)hipFree(lp.d_row_off);
+        if (lp.d_rb_off) (void)hipFree(lp.d_rb_off);
     }
     b->levels.clear();
 }
@@ -387,7 +474,7 @@ using namespace cbh;
 extern "C" {
 
 int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t precision,
-                     void* const* hist, cbh_split* best, cbh_batch** out) {
+                     int32_t subtract, void* const* hist, cbh_split* best, cbh_batch** out) {
     clear_error();
     CBH_ARG(ctx && probs && hist && best && out, "NULL argument");
     *out = nullptr;
@@ -412,7 +499,13 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
     b->probs.assign(probs, probs + P);
     b->hist.assign(hist, hist + P);
     b->best = best;
-    // workspace layout: [per-level max partials][feature winners]
+    // subtraction needs one class per problem
+    b->sub = subtract != 0 && b->depth > 1;
+    for (int p = 0; p < P; ++p)
+        if (probs[p].K != 1) b->sub = 0;
+    // workspace layout: [per-level max partials][feature winners], and with
+    // subtraction [second histogram per problem][sides per problem][row codes
+    // per problem]
     int64_t max_part = 0, tot_feat = 0;
     for (int p = 0; p < P; ++p) tot_feat += probs[p].n_features;
     for (int lvl = 0; lvl < b->depth; ++lvl) {
@@ -448,14 +541,19 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                                           ctx->max_lds);
             lp.W = std::min(lp.W, hp.fb);
         }
-        lp.mode = L == 1 ? 0 : 1;
+        // a level >= 1 built by subtraction accumulates L/2 parent slots
+        lp.sub = b->sub && lvl > 0 && lp.kind == 1;
+        const int slots = lp.sub ? L / 2 : L;
+        lp.mode = lp.sub ? 2 : (L == 1 ? 0 : 1);
+        std::vector<int64_t> rb_off{0};
         for (int p = 0; p < P; ++p) {
             const cbh_problem& pr = probs[p];
             HistKnobs kb = batch_knobs(pr);
             kb.kernel = lp.kind;
             kb.lpf_w = lp.W;
-            HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, L, precision,
+            HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, slots, precision,
                                     pr.loss == CBH_LOSS_RMSE, ctx->max_lds);
+            rb_off.push_back(rb_off.back() + (pr.n + kSideRows - 1) / kSideRows);
             if (lp.kind == 1 && hp.fb != lp.W) {
                 set_error("batched group width %d differs from %d", hp.fb, lp.W);
                 free_levels(b);
@@ -465,7 +563,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             if (lp.kind == 1 && hp.n_ltiles > 1 && L > 1) lp.mode = 2;
             lp.plans.push_back(hp);
             lp.part_off.push_back(off);
-            off += align_up(int64_t(hp.n_chunks) * L * pr.n_features * pr.max_bins *
+            off += align_up(int64_t(hp.n_chunks) * slots * pr.n_features * pr.max_bins *
                                 hp.words_per_cell * 4,
                             256);
             lp.max_lds = std::max(lp.max_lds, hp.lds_bytes);
@@ -476,7 +574,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             dplans.push_back(LevelPlan::DevHP{hp.fb, hp.lt, hp.n_fgroups, hp.n_ltiles,
                                               hp.n_chunks, hp.words_per_cell, hp.rep, 0,
                                               hp.rows_per_chunk, hp.lds_bytes});
-            cell_off.push_back(cell_off.back() + int64_t(L) * pr.n_features * pr.max_bins);
+            cell_off.push_back(cell_off.back() + int64_t(slots) * pr.n_features * pr.max_bins);
             feat_off.push_back(feat_off.back() + pr.n_features);
             row_off.push_back(row_off.back() + (pr.n + 7) / 8);
         }
@@ -486,11 +584,13 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         lp.cells_total = cell_off.back();
         lp.score_total = feat_off.back();
         lp.rows_total = row_off.back();
+        lp.rb_total = lp.sub ? rb_off.back() : 0;
         int rc = upload(&lp.d_tiles, tiles);
         if (!rc) rc = upload(&lp.d_plans, dplans);
         if (!rc) rc = upload(&lp.d_cell_off, cell_off);
         if (!rc) rc = upload(&lp.d_feat_off, feat_off);
         if (!rc) rc = upload(&lp.d_row_off, row_off);
+        if (!rc && lp.sub) rc = upload(&lp.d_rb_off, rb_off);
         b->levels.push_back(lp);
         if (rc) {
             free_levels(b);
@@ -500,6 +600,26 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
     }
     b->fbest_off = align_up(max_part, 256);
     b->ws_need = b->fbest_off + align_up(tot_feat * (int64_t)sizeof(FeatBest), 256);
+    // subtraction: level l writes hist[p] if depth-1-l is even, else the
+    // second buffer, which therefore holds at most level depth-2
+    std::vector<int64_t> hist2_off(P, 0), side_off(P, 0), code_off(P, 0);
+    if (b->sub) {
+        const int64_t esz = precision == CBH_PREC_FP32 ? 4 : 8;
+        for (int p = 0; p < P; ++p) {
+            hist2_off[p] = b->ws_need;
+            b->ws_need += align_up((int64_t(1) << (b->depth - 2)) * probs[p].n_features *
+                                       probs[p].max_bins * 2 * esz,
+                                   256);
+        }
+        for (int p = 0; p < P; ++p) {
+            side_off[p] = b->ws_need;
+            b->ws_need += align_up(int64_t(1) << (b->depth - 2), 256);
+        }
+        for (int p = 0; p < P; ++p) {
+            code_off[p] = b->ws_need;
+            b->ws_need += align_up(probs[p].n * 2, 256);
+        }
+    }
     // the context workspace must exist before a capture (gradient codes use it)
     int rc = ensure_ws(ctx, 256);
     if (!rc && b->ws_need > ctx->ws_limit) {
@@ -523,14 +643,29 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         const cbh_problem& pr = probs[p];
         dp[p] = DevProb{pr.bins, pr.n_bins, pr.g, pr.h, reinterpret_cast<const uint32_t*>(pr.gq),
                         pr.grad_scale, pr.leaf, hist[p], nullptr, pr.n, pr.n_features,
-                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE, pr.seg_stride};
+                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE, pr.seg_stride,
+                        nullptr, nullptr, nullptr, pr.leaf};
     }
     std::vector<DevProb> all;
     all.reserve(size_t(P) * b->depth);
+    char* wsb = (char*)b->ws;
     for (int lvl = 0; lvl < b->depth; ++lvl)
         for (int p = 0; p < P; ++p) {
             DevProb d = dp[p];
-            d.partials = (uint32_t*)((char*)b->ws + b->levels[lvl].part_off[p]);
+            d.partials = (uint32_t*)(wsb + b->levels[lvl].part_off[p]);
+            if (b->sub) {
+                // ping-pong: the last level lands in hist[p]
+                auto out_of = [&](int l) -> void* {
+                    return ((b->depth - 1 - l) % 2 == 0) ? hist[p] : (void*)(wsb + hist2_off[p]);
+                };
+                d.hist = out_of(lvl);
+                if (b->levels[lvl].sub) {
+                    d.parent = out_of(lvl - 1);
+                    d.side = (uint8_t*)(wsb + side_off[p]);
+                    d.codes = (uint16_t*)(wsb + code_off[p]);
+                    d.rowcode = d.codes;
+                }
+            }
             all.push_back(d);
         }
     rc = upload(&b->d_probs, all);

@@ -382,37 +382,7 @@ __global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __rest
     }
 }
 
-// Smaller child of every parent leaf p at the parent level's split, judged by
-// the parent histogram's second statistic (row count for RMSE, sum of h
-// otherwise) on the split feature; side[p] = 1 if the bit-set side is smaller.
-// With no split every row stayed on the clear side, so the set side is empty.
-// One wave: side of parent p (1 if the bit-set child is the smaller one).
-template <int PREC>
-__device__ __forceinline__ uint8_t parent_side(const void* __restrict__ parent, int64_t p, int f,
-                                               int k, int32_t F, int32_t B, int32_t K,
-                                               int32_t rmse, int lane) {
-    if (f < 0 || f >= F) return 1;
-    double left = 0.0, right = 0.0;
-    for (int b = lane; b < B; b += 64) {
-        const int64_t e = ((p * F + f) * B + b) * 2 * K + 1;   // statistic 1 of class 0
-        double v;
-        if constexpr (PREC == CBH_PREC_FP32)
-            v = rmse ? (double)reinterpret_cast<const uint32_t*>(parent)[e]
-                     : (double)reinterpret_cast<const float*>(parent)[e];
-        else if constexpr (PREC == CBH_PREC_TWOFLOAT)
-            v = rmse ? (double)__float_as_uint(reinterpret_cast<const float2*>(parent)[e].x)
-                     : (double)reinterpret_cast<const float2*>(parent)[e].x;
-        else
-            v = (double)reinterpret_cast<const int64_t*>(parent)[e];
-        if (b <= k) left += v; else right += v;
-    }
-    for (int d = 32; d >= 1; d >>= 1) {
-        left += __shfl_xor(left, d, 64);
-        right += __shfl_xor(right, d, 64);
-    }
-    return right < left ? 1 : 0;
-}
-
+// side[p] of every parent p of a build by subtraction (see parent_side).
 template <int PREC>
 __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ parent,
                                                        const cbh_split* __restrict__ split,

@@ -362,36 +362,56 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
 
 // ------------------------------------------------------------ partial merge
 // Merge cell `cell` (all 2K statistics) over n_chunks partial histograms of
-// `cells` cells each, in chunk order, into the output layout of the precision.
+// `cells` cells each, in chunk order, into cell `dst` of the output layout of
+// the precision. With a parent histogram (a build by subtraction: the partials
+// hold the smaller child of each parent, cell = parent cell), cell `sib` of
+// the output gets parent cell `cell` minus the merged value.
 template <int PREC>
 __device__ __forceinline__ void merge_cell(const uint32_t* __restrict__ part, int64_t cells,
                                            int K, int n_chunks, bool rmse, void* __restrict__ out,
-                                           int64_t cell) {
+                                           int64_t cell, int64_t dst, int64_t sib = -1,
+                                           const void* __restrict__ parent = nullptr) {
     const int wpc = PREC == CBH_PREC_TWOFLOAT ? 4 * K : 2 * K;
     const int64_t cw = cells * wpc;
     for (int c = 0; c < K; ++c) {
         if constexpr (PREC == CBH_PREC_FP32) {
             const int64_t j = cell * wpc + 2 * c;
+            const int64_t jd = dst * wpc + 2 * c, js = sib * wpc + 2 * c;
             float g = 0.f;
             for (int ch = 0; ch < n_chunks; ++ch) g += __uint_as_float(part[ch * cw + j]);
-            reinterpret_cast<float*>(out)[j] = g;
+            reinterpret_cast<float*>(out)[jd] = g;
+            if (sib >= 0)
+                reinterpret_cast<float*>(out)[js] = reinterpret_cast<const float*>(parent)[j] - g;
             if (rmse) {
                 uint32_t cnt = 0;
                 for (int ch = 0; ch < n_chunks; ++ch) cnt += part[ch * cw + j + 1];
-                reinterpret_cast<uint32_t*>(out)[j + 1] = cnt;
+                reinterpret_cast<uint32_t*>(out)[jd + 1] = cnt;
+                if (sib >= 0)
+                    reinterpret_cast<uint32_t*>(out)[js + 1] =
+                        reinterpret_cast<const uint32_t*>(parent)[j + 1] - cnt;
             } else {
                 float hh = 0.f;
                 for (int ch = 0; ch < n_chunks; ++ch) hh += __uint_as_float(part[ch * cw + j + 1]);
-                reinterpret_cast<float*>(out)[j + 1] = hh;
+                reinterpret_cast<float*>(out)[jd + 1] = hh;
+                if (sib >= 0)
+                    reinterpret_cast<float*>(out)[js + 1] =
+                        reinterpret_cast<const float*>(parent)[j + 1] - hh;
             }
         } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
             for (int st = 0; st < 2; ++st) {
                 const int64_t j = cell * wpc + 4 * c + 2 * st;
+                const int64_t o = 2 * c + st;          // float2 index within a cell
                 float2 r;
                 if (st == 1 && rmse) {
                     uint32_t cnt = 0;
                     for (int ch = 0; ch < n_chunks; ++ch) cnt += part[ch * cw + j];
                     r = make_float2(__uint_as_float(cnt), 0.f);
+                    if (sib >= 0) {
+                        const uint32_t pc = __float_as_uint(
+                            reinterpret_cast<const float2*>(parent)[cell * 2 * K + o].x);
+                        reinterpret_cast<float2*>(out)[sib * 2 * K + o] =
+                            make_float2(__uint_as_float(pc - cnt), 0.f);
+                    }
                 } else {
                     float S = 0.f, E = 0.f;
                     for (int ch = 0; ch < n_chunks; ++ch) {
@@ -405,8 +425,18 @@ __device__ __forceinline__ void merge_cell(const uint32_t* __restrict__ part, in
                     }
                     const float hs = S + E;
                     r = make_float2(hs, E - (hs - S));
+                    if (sib >= 0) {
+                        // (P_hi, P_lo) - (hs, lo), TwoSum on the leading parts
+                        const float2 Pv = reinterpret_cast<const float2*>(parent)[cell * 2 * K + o];
+                        const float t = Pv.x - r.x;
+                        const float bp = t - Pv.x;
+                        const float e = ((Pv.x - (t - bp)) + (-r.x - bp)) + (Pv.y - r.y);
+                        const float dh = t + e;
+                        reinterpret_cast<float2*>(out)[sib * 2 * K + o] =
+                            make_float2(dh, e - (dh - t));
+                    }
                 }
-                reinterpret_cast<float2*>(out)[cell * 2 * K + 2 * c + st] = r;
+                reinterpret_cast<float2*>(out)[dst * 2 * K + o] = r;
             }
         } else {
             const uint64_t* P64 = reinterpret_cast<const uint64_t*>(part);
@@ -417,10 +447,48 @@ __device__ __forceinline__ void merge_cell(const uint32_t* __restrict__ part, in
                 hs += (int64_t)(uint32_t)(v & 0xffffffffull);
                 gs += (int64_t)(int32_t)(uint32_t)(v >> 32);
             }
-            reinterpret_cast<int64_t*>(out)[2 * slot] = gs;
-            reinterpret_cast<int64_t*>(out)[2 * slot + 1] = hs;
+            const int64_t sd = dst * K + c;
+            reinterpret_cast<int64_t*>(out)[2 * sd] = gs;
+            reinterpret_cast<int64_t*>(out)[2 * sd + 1] = hs;
+            if (sib >= 0) {
+                const int64_t* Pv = reinterpret_cast<const int64_t*>(parent);
+                const int64_t ss = sib * K + c;
+                reinterpret_cast<int64_t*>(out)[2 * ss] = Pv[2 * slot] - gs;
+                reinterpret_cast<int64_t*>(out)[2 * ss + 1] = Pv[2 * slot + 1] - hs;
+            }
         }
     }
+}
+
+// Smaller child of parent leaf p at the parent level's split (feature f,
+// border k), judged by the parent histogram's second statistic (row count for
+// RMSE, sum of h otherwise) on the split feature, summed by one wave: 1 if the
+// bit-set child is the smaller one. With no split every row stayed on the
+// clear side, so the set side is empty.
+template <int PREC>
+__device__ __forceinline__ uint8_t parent_side(const void* __restrict__ parent, int64_t p, int f,
+                                               int k, int32_t F, int32_t B, int32_t K,
+                                               int32_t rmse, int lane) {
+    if (f < 0 || f >= F) return 1;
+    double left = 0.0, right = 0.0;
+    for (int b = lane; b < B; b += 64) {
+        const int64_t e = ((p * F + f) * B + b) * 2 * K + 1;   // statistic 1 of class 0
+        double v;
+        if constexpr (PREC == CBH_PREC_FP32)
+            v = rmse ? (double)reinterpret_cast<const uint32_t*>(parent)[e]
+                     : (double)reinterpret_cast<const float*>(parent)[e];
+        else if constexpr (PREC == CBH_PREC_TWOFLOAT)
+            v = rmse ? (double)__float_as_uint(reinterpret_cast<const float2*>(parent)[e].x)
+                     : (double)reinterpret_cast<const float2*>(parent)[e].x;
+        else
+            v = (double)reinterpret_cast<const int64_t*>(parent)[e];
+        if (b <= k) left += v; else right += v;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        left += __shfl_xor(left, d, 64);
+        right += __shfl_xor(right, d, 64);
+    }
+    return right < left ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- scoring

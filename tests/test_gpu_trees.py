@@ -224,9 +224,10 @@ BATCH_KNOBS = {"default": None, "lpf_split": (12288, 1024, 4096, 50, 1, 1, 1, 0)
                "rows_over_lanes": (65536, 1024, 4096, 50, 4, 2, 0, 0)}
 
 
+@pytest.mark.parametrize("subtract", [True, False])
 @pytest.mark.parametrize("knobs", list(BATCH_KNOBS))
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_batched_matches_single(cb, prec, knobs):
+def test_batched_matches_single(cb, prec, knobs, subtract):
     probs = datagen.make_c4(P=5, scale=0.01)
     for p in probs:
         p.depth = 5
@@ -239,7 +240,7 @@ def test_batched_matches_single(cb, prec, knobs):
     depth = probs[0].depth
     best = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
     plan = cb.cbh_batch_create(ctx, [b.probs[0] for b in batched], prec,
-                               [b.hist for b in batched], best)
+                               [b.hist for b in batched], best, subtract=subtract)
     try:
         for b in single:
             b.init_gradients()
@@ -274,6 +275,48 @@ def test_batched_matches_single(cb, prec, knobs):
     finally:
         cb.cbh_batch_destroy(plan)
         for b in single + batched:
+            b.close()
+
+
+def test_permutation_models_batched_match_boosters(cb):
+    """Models over the permutations of one booster's bins (ModelState), trained
+    together by the batched calls, grow the same trees as boosters that are
+    each given one of the permutations (int16: every sum exact)."""
+    import copy
+
+    from paper_1810_11363_amd.booster import GpuBooster
+    p = datagen.random_small(seed=21, n=3000, F_num=4, F_cat=2, C=30, depth=4, num_bins=16, s=3)
+    base = GpuBooster.from_problem(p, precision=2).prepare()
+    states = [base.model_state(r) for r in range(3)]
+    singles = []
+    for r in range(3):
+        q = copy.copy(p)
+        q.perms = p.perms[r:r + 1]
+        singles.append(GpuBooster.from_problem(q, precision=2).prepare())
+    ctx, depth = base.ctx, p.depth
+    best = torch.zeros((3, depth, 4), dtype=torch.int32, device=gu.dev())
+    lvs = [m.leaf_values for m in states]
+    plan = cb.cbh_batch_create(ctx, [m.prob for m in states], 2, [m.hist for m in states], best)
+    try:
+        cb.cbh_batch_update(ctx, plan, p.lr, p.l2, lvs, True)
+        for s in singles:
+            s.init_gradients()
+        for it in range(3):
+            for s in singles:
+                s.fit_tree(0)
+            for m in states:
+                cb.cbh_quantize_gradients(ctx, m.prob)
+            for lvl in range(depth):
+                cb.cbh_batch_level(ctx, plan, lvl, p.l2)
+            cb.cbh_batch_update(ctx, plan, p.lr, p.l2, lvs, False)
+            torch.cuda.synchronize()
+            for r, (s, m) in enumerate(zip(singles, states)):
+                assert np.array_equal(s.best.cpu().numpy()[:, :2], best[r].cpu().numpy()[:, :2])
+                assert torch.equal(s.leaf, m.leaf), (it, r)
+                assert torch.equal(s.approx, m.approx), (it, r)
+    finally:
+        cb.cbh_batch_destroy(plan)
+        for b in singles + [base]:
             b.close()
 
 
