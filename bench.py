@@ -1,7 +1,10 @@
 #!/usr/bin/env python3
 """Benchmark: per-tree split search on one MI355X for the 1M-row RMSE workload
-(default; `--workload c3` runs the 10M-row, 200-feature, 255-bin Logloss
-precision workload instead).
+(default). `--workload c3` runs the 10M-row, 200-feature, 255-bin Logloss
+precision workload instead, `--workload c4` the batching workload (64
+independent problems, and the 1M-row problem as cross-validation folds and
+as ordered-boosting permutations), `--workload c5` the 50M-row, 10-class
+MultiClass workload.
 
 A step is one boosting iteration: every level's histogram build, scoring,
 argmax and leaf update, then the leaf solve and the model/gradient update.
@@ -74,7 +77,11 @@ WORKLOADS = {
     "c2": dict(tag="c2_1m_rmse", n=1_000_000, steps=200, cpu_rows=1_000_000, cpu_trees=20),
     "c3": dict(tag="c3_10m_logloss", n=10_000_000, steps=20, cpu_rows=250_000, cpu_trees=2),
     "c4": dict(tag="c4_batch_rmse", n=0, steps=20, cpu_rows=1_000_000, cpu_trees=1),
+    "c5": dict(tag="c5_50m_multiclass", n=50_000_000, steps=3, cpu_rows=100_000, cpu_trees=1,
+               warmup=1, hist_trees=2, autotune="off", compare="fp32", warmup_s=0.0),
 }
+# per-run defaults a workload may override
+RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,int16", warmup_s=1.0)
 
 
 def describe(workload, p, bst):
@@ -83,6 +90,10 @@ def describe(workload, p, bst):
         return (f"1M-row RMSE: n={n}, 100 numeric features at 128 bins + 10 categorical -> "
                 f"{F - 100} ordered-statistic columns per tree, 4 permutations, depth {depth}, "
                 f"lr 0.1, l2 3")
+    if workload == "c5":
+        return (f"50M-row MultiClass: n={n}, 50 numeric features at {bst.B} bins + 20 "
+                f"categorical (cardinality 10..1e6, Zipf 1.05) -> {F - 50} one-vs-rest "
+                f"ordered-statistic columns, K={bst.K} classes, depth {depth}, lr 0.1, l2 3")
     return (f"10M-row precision Logloss: n={n}, {F} uniform numeric features at {bst.B} bins "
             f"(5% exact duplicates), 1% positives, depth {depth}, lr 0.1, l2 3")
 
@@ -571,13 +582,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=list(WORKLOADS), default="c2")
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=5,
+    ap.add_argument("--warmup", type=int, default=None,
                     help="trees grown before the graphs are captured")
-    ap.add_argument("--warmup-s", type=float, default=1.0,
+    ap.add_argument("--warmup-s", type=float, default=None,
                     help="seconds of replayed trees before the timed region")
     ap.add_argument("--precision", choices=list(PRECISIONS), default="twofloat",
                     help="headline histogram form")
-    ap.add_argument("--compare", default="fp32,int16",
+    ap.add_argument("--compare", default=None,
                     help="other forms timed in the same run ('' for none)")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--batch-p", type=int, default=64, help="problems of the batching workload")
@@ -590,11 +601,11 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every call from Python instead of replaying captured trees")
-    ap.add_argument("--hist-trees", type=int, default=40,
+    ap.add_argument("--hist-trees", type=int, default=None,
                     help="trees replayed from graphs with event nodes around every build")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle leg (CPU timing and error vs FP64)")
-    ap.add_argument("--autotune", default="run",
+    ap.add_argument("--autotune", default=None,
                     help="'run' tunes launch plans before each timed region, 'off' keeps "
                          "the defaults, anything else is a cache file to load")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -605,6 +616,9 @@ def main():
     for k in ("steps", "n", "cpu_rows", "cpu_trees"):
         if getattr(args, k) is None:
             setattr(args, k, wl[k])
+    for k, v in RUN_DEFAULTS.items():
+        if getattr(args, k) is None:
+            setattr(args, k, wl.get(k, v))
     if args.copy_calibration:
         import torch
         x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
@@ -616,7 +630,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding over several GPUs is not built)"}))
         sys.exit(2)
     if args.workload == "c4":
         run_batch(args)
@@ -628,7 +642,13 @@ def main():
     from paper_1810_11363_amd.booster import GpuBooster
 
     t_gen = time.perf_counter()
-    p = datagen.make_c2(n=args.n) if args.workload == "c2" else datagen.make_c3(n=args.n)
+    if args.workload == "c5":
+        def progress(done, total):
+            if done % 8 == 0 or done == total:
+                print(f"# generating: {done}/{total} row chunks", file=sys.stderr, flush=True)
+        p = datagen.make_c5(n=args.n, progress=progress)
+    else:
+        p = {"c2": datagen.make_c2, "c3": datagen.make_c3}[args.workload](n=args.n)
     t_gen = time.perf_counter() - t_gen
     print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
     bst = GpuBooster.from_problem(p).prepare()

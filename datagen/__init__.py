@@ -289,31 +289,62 @@ def make_c4(P: int = 64, scale: float = 1.0) -> list[Problem]:
             for i, n in enumerate(c4_sizes(P, scale=scale))]
 
 
-def make_c5(n: int = 50_000_000, n_cat: int = 20, K: int = 10) -> Problem:
+def make_c5(n: int = 50_000_000, n_cat: int = 20, K: int = 10, chunk: int = 1 << 21,
+            workers: int = 16, progress=None) -> Problem:
     """Large MultiClass problem: 50 N(0,1) numeric features at 255 bins, 20
     Zipf(1.05) categorical features with cardinalities 10..1e6, K-class
-    softmax labels from a seeded linear model, depth 10, 100 iterations."""
+    softmax labels from a seeded linear model plus per-category class effects,
+    depth 10, 100 iterations.
+
+    The per-feature tables (category ranks' shuffle, raw values, class
+    effects) and the linear model are drawn once; the rows are drawn in chunks
+    of `chunk` rows, chunk c from its own stream 1000 + c, filled by `workers`
+    threads (numpy's generators release the interpreter lock while filling).
+    `progress(done, total)` is called after each chunk if given."""
+    from concurrent.futures import ThreadPoolExecutor
     cfg = 5
-    gx, gc, gy = rng_for(cfg, 0), rng_for(cfg, 1), rng_for(cfg, 2)
-    x = gx.standard_normal((50, n), dtype=np.float32)
-    ids, cats = [], []
-    for j in range(n_cat):
-        C = int(round(10 ** (1 + 5 * j / max(1, n_cat - 1))))
-        C = min(C, max(2, n))
-        d = zipf_ids(gc, n, C, 1.05)
-        ids.append(d)
-        cats.append(raw_values(gc, C)[d])
+    gc, gy = rng_for(cfg, 1), rng_for(cfg, 2)
+    cards = [min(int(round(10 ** (1 + 5 * j / max(1, n_cat - 1)))), max(2, n))
+             for j in range(n_cat)]
+    cdfs, shuffles, values = [], [], []
+    for C in cards:
+        w = np.arange(1, C + 1, dtype=np.float64) ** -1.05
+        cdf = np.cumsum(w)
+        cdfs.append(cdf / cdf[-1])
+        shuffles.append(gc.permutation(C))
+        values.append(raw_values(gc, C))
     W = gy.standard_normal((50, K)) / math.sqrt(50)
-    logits = x.astype(np.float64).T @ W
-    for d in ids:
-        E = gy.normal(0.0, 0.5, (int(d.max()) + 1, K))
-        logits += E[d]
-    logits -= logits.max(axis=1, keepdims=True)
-    pr = np.exp(logits)
-    pr /= pr.sum(axis=1, keepdims=True)
-    u = gy.random(n)[:, None]
-    y = (np.cumsum(pr, axis=1) < u).sum(axis=1).clip(0, K - 1).astype(np.float32)
-    p = Problem("c5_large_multiclass", x, np.stack(cats), y, _perms(cfg, n, 1),
+    E = [gy.normal(0.0, 0.5, (C, K)) for C in cards]
+    x = np.empty((50, n), np.float32)
+    cats = np.empty((n_cat, n), np.int32)
+    y = np.empty(n, np.float32)
+    n_chunks = (n + chunk - 1) // chunk
+    done = [0]
+
+    def fill(c):
+        r0, r1 = c * chunk, min(n, (c + 1) * chunk)
+        g = rng_for(cfg, 1000 + c)
+        xs = g.standard_normal((50, r1 - r0), dtype=np.float32)
+        x[:, r0:r1] = xs
+        logits = xs.astype(np.float64).T @ W
+        for j in range(n_cat):
+            rank = np.minimum(np.searchsorted(cdfs[j], g.random(r1 - r0), side="right"),
+                              cards[j] - 1)
+            ids = shuffles[j][rank]
+            cats[j, r0:r1] = values[j][ids]
+            logits += E[j][ids]
+        logits -= logits.max(axis=1, keepdims=True)
+        pr = np.exp(logits)
+        pr /= pr.sum(axis=1, keepdims=True)
+        u = g.random(r1 - r0)[:, None]
+        y[r0:r1] = (np.cumsum(pr, axis=1) < u).sum(axis=1).clip(0, K - 1)
+        done[0] += 1
+        if progress is not None:
+            progress(done[0], n_chunks)
+
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        list(ex.map(fill, range(n_chunks)))
+    p = Problem("c5_large_multiclass", x, cats, y, _perms(cfg, n, 1),
                 MULTICLASS, K, depth=10, iterations=100, lr=0.1, l2=3.0,
                 num_bins=255, ts_bins=255, a=1.0)
     return _finish_targets(p)

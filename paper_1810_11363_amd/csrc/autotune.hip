@@ -187,8 +187,8 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
         float best_ms = 1e30f;
         HistKnobs best_kn = ctx->knobs;
         // candidate knob sets: the rows-over-lanes kernel over LDS budget x
-        // replicas, and (K == 1) the features-over-lanes kernel over lane-group
-        // width; both over blocks aimed at x rows per block x partial volume
+        // replicas, and the features-over-lanes kernel over lane-group width;
+        // both over blocks aimed at x rows per block x partial volume
         std::vector<HistKnobs> cands;
         for (int32_t tb : targets)
             for (int64_t mr : min_rows)
@@ -205,14 +205,12 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
                             kn.rep_target = mrp;
                             cands.push_back(kn);
                         }
-                    if (K == 1) {
-                        kn.kernel = 1;
-                        kn.max_rep = kn.rep_target = 1;
-                        kn.lds_budget = ctx->max_lds;
-                        for (int32_t w : lpf_ws) {
-                            kn.lpf_w = w;
-                            cands.push_back(kn);
-                        }
+                    kn.kernel = 1;
+                    kn.max_rep = kn.rep_target = 1;
+                    kn.lds_budget = ctx->max_lds;
+                    for (int32_t w : lpf_ws) {
+                        kn.lpf_w = w;
+                        cands.push_back(kn);
                     }
                 }
         std::set<std::tuple<int, int, int, int64_t, int>> seen;

@@ -175,15 +175,16 @@ __global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __res
     b.h = pr.h;
     b.gq = pr.gq;
     b.rowcode = pr.rowcode;
-    b.partials = pr.partials;
-    b.n = pr.n;
-    b.rows_per_chunk = hp.rows_per_chunk;
     b.F = pr.F;
     b.B = pr.B;
-    b.L = L;
-    b.lt = hp.lt;
     b.wpc = hp.wpc;
-    lpf_block<PREC, RM, W, MODE>(b, tile.chunk, tile.fg, tile.lt_i, lds);
+    b.coff = 0;
+    const int64_t r0 = int64_t(tile.chunk) * hp.rows_per_chunk;
+    const uint32_t s0 = (uint32_t)tile.lt_i * (uint32_t)hp.lt;
+    lpf_block<PREC, RM, W, MODE>(b, r0, min(pr.n, r0 + hp.rows_per_chunk), tile.fg, s0,
+                                 min((uint32_t)hp.lt, (uint32_t)L - s0),
+                                 pr.partials + int64_t(tile.chunk) * (int64_t(L) * pr.F * pr.B * hp.wpc),
+                                 0u, lds);
 }
 
 __device__ __forceinline__ int find_owner(const int64_t* __restrict__ off, int P, int64_t gi) {

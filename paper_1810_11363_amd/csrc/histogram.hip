@@ -67,12 +67,13 @@ HistKnobs knobs_for(const cbh_ctx* ctx, int32_t F, int32_t B, int32_t K, int32_t
 // Plan of the lanes-over-features kernel: the widest lane group W (at most
 // the requested one) whose tile of all slots fits the LDS budget; if even
 // W = 4 does not fit, the slots are split into tiles (rows re-read per tile).
-// Chunks as for the other kernel.
-static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t n_slots,
-                         int32_t precision, int max_lds) {
+// With K classes every class is a block of its own (same tile size). Chunks
+// as for the other kernel.
+static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
+                         int32_t n_slots, int32_t precision, int max_lds) {
     HistPlan p;
     p.kind = 1;
-    p.words_per_cell = words_per_cell(precision, 1);
+    p.words_per_cell = words_per_cell(precision, K);
     const uint32_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
     const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
     int32_t W = kn.lpf_w > 0 ? std::min(kn.lpf_w, 32) : 32;
@@ -85,7 +86,7 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
     p.lt = lt;
     p.n_ltiles = (n_slots + lt - 1) / lt;
     p.n_fgroups = (F + W - 1) / W;
-    const int64_t tiles = int64_t(p.n_fgroups) * p.n_ltiles;
+    const int64_t tiles = int64_t(p.n_fgroups) * p.n_ltiles * K;   // blocks per chunk
     const int64_t part_per_chunk = int64_t(n_slots) * F * B * p.words_per_cell * 4;
     const int64_t c_part = std::max<int64_t>(1, (int64_t(kn.partial_pct) * n * F / 100) /
                                                     std::max<int64_t>(1, part_per_chunk));
@@ -113,7 +114,7 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
 //     to respect the LDS bound on features per block.
 HistPlan plan_hist(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                    int32_t n_leaves, int32_t precision, int32_t rmse, int max_lds) {
-    if (kn.kernel == 1 && K == 1) return plan_lpf(kn, n, F, B, n_leaves, precision, max_lds);
+    if (kn.kernel == 1) return plan_lpf(kn, n, F, B, K, n_leaves, precision, max_lds);
     HistPlan p;
     p.words_per_cell = words_per_cell(precision, K);
     const int64_t cell_bytes = tile_lds_bytes(precision, rmse, K, B, 1);   // LDS per cell
@@ -458,13 +459,17 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
     }
 }
 
-// Single-problem launch: block -> (slot tile, feature group, chunk), XCD-contiguous.
+// Single-problem launch: block -> (class, slot tile, feature group, chunk),
+// XCD-contiguous (the classes of one tile, group and chunk, which read the
+// same bins, are neighbours).
 template <int PREC, int RM, int W, int MODE>
 __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     const int64_t per_xcd = (a.n_blocks + 7) / 8;
     int64_t item = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (item >= a.n_blocks) return;
+    const int c = (int)(item % a.K);
+    item /= a.K;
     const int lt_i = (int)(item % a.n_ltiles);
     item /= a.n_ltiles;
     const int fg = (int)(item % a.n_fgroups);
@@ -472,19 +477,20 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     LpfBlock b;
     b.bins = a.bins;
     b.seg = a.seg;
-    b.g = a.g;
-    b.h = a.h;
-    b.gq = a.gq;
+    b.g = a.g + int64_t(c) * a.n;
+    b.h = a.h ? a.h + int64_t(c) * a.n : nullptr;
+    b.gq = a.gq ? a.gq + int64_t(c) * a.n : nullptr;
     b.rowcode = a.rowcode;
-    b.partials = a.partials;
-    b.n = a.n;
-    b.rows_per_chunk = a.rows_per_chunk;
     b.F = a.F;
     b.B = a.B;
-    b.L = a.L;
-    b.lt = a.lt;
     b.wpc = a.wpc;
-    lpf_block<PREC, RM, W, MODE>(b, chunk, fg, lt_i, lds);
+    b.coff = c * (a.wpc / a.K);
+    const int64_t r0 = chunk * a.rows_per_chunk;
+    const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;
+    lpf_block<PREC, RM, W, MODE>(b, r0, min(a.n, r0 + a.rows_per_chunk), fg, s0,
+                                 min((uint32_t)a.lt, (uint32_t)a.L - s0),
+                                 a.partials + chunk * (int64_t(a.L) * a.F * a.B * a.wpc), 0u,
+                                 lds);
 }
 
 void hist_init_attrs(int max_lds) {

@@ -801,13 +801,13 @@ __host__ __device__ constexpr uint32_t lpf_record_bytes(uint32_t W, uint32_t CS)
 struct LpfBlock {
     const uint8_t* const* bins;
     const int64_t* seg;          // per-feature segment strides, NULL = columns
-    const float* g;
+    const float* g;              // this class's statistics
     const float* h;
     const uint32_t* gq;
     const uint16_t* rowcode;     // per-row slot codes (MODE != 0)
-    uint32_t* partials;          // [chunk][L][F][B][wpc]
-    int64_t n, rows_per_chunk;
-    int32_t F, B, L, lt, wpc;
+    int32_t F, B;
+    int32_t wpc;                 // words per output cell (all classes)
+    int32_t coff;                // words before this class within a cell
 };
 
 // ------------------------------------------- lanes-over-features variant
@@ -950,11 +950,14 @@ struct LpfSeg {
 // MODE 1: all slots of a direct build in one tile: slot = row code (the leaf).
 // MODE 2: subtraction and/or several slot tiles: slot = row code - first slot
 //         of the tile, rows outside the tile (or with code 0xffff) skipped.
-// One block: chunk `chunk` of the rows, feature group fg (W features), slot
-// tile lt_i; lds holds the block's dynamic LDS.
+// One block: rows [r0, r1) (r0 a multiple of 16), feature group fg (W
+// features), slots [s0, s0 + ns) (ns <= 64). The block's partial histogram
+// `part` is [slot - part_slot0][F][B][wpc] words, this class at word coff of
+// each cell; lds holds the block's dynamic LDS.
 template <int PREC, int RM, int W, int MODE>
-__device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t chunk, int fg, int lt_i,
-                                          uint32_t* lds) {
+__device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
+                                          uint32_t s0, uint32_t ns, uint32_t* part,
+                                          uint32_t part_slot0, uint32_t* lds) {
     constexpr uint32_t CS = lpf_cell_bytes<PREC>();
     constexpr int RG = 64 / W;                  // segments per wave step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -966,15 +969,11 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t chunk, int 
     const int f = f0 + (fok ? fl : 0);
     const uint8_t* col = a.bins[f];
     const int64_t sstride = a.seg ? a.seg[f] : 16;
-    const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;               // first slot of the tile
-    const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);       // slots in the tile (<= 64)
     const uint32_t slot_bytes = (uint32_t)a.B * lpf_record_bytes(W, CS);
     const uint32_t tile_words = ns * slot_bytes / 4;
     for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
     __syncthreads();
     char* tile = reinterpret_cast<char*>(lds);
-    const int64_t r0 = chunk * a.rows_per_chunk;
-    const int64_t r1 = min(a.n, r0 + a.rows_per_chunk);
     const int64_t t_full = r1 >> 4;            // segments before this one are full
     const uint32_t lane_off = (uint32_t)fl * 8u;
     const uint16_t* rowcode = a.rowcode;
@@ -1052,7 +1051,6 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t chunk, int 
     // write the tile in the partial's [L][F][B][wpc] order; consecutive threads
     // take consecutive features of one (slot, bin), so the LDS reads are
     // conflict-free and every thread writes one whole cell
-    uint32_t* part = a.partials + chunk * (int64_t(a.L) * a.F * a.B * a.wpc);
     const uint32_t cells = ns * (uint32_t)a.B * W;
     for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) {
         const uint32_t cfl = c & (W - 1);
@@ -1061,7 +1059,8 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t chunk, int 
         const uint32_t bin = sb % (uint32_t)a.B, sl = sb / (uint32_t)a.B;
         // first stat; the second is W * 8 bytes further
         const char* cell = tile + (size_t)sb * lpf_record_bytes(W, CS) + cfl * 8u;
-        const int64_t o = ((int64_t(s0 + sl) * a.F + f0 + cfl) * a.B + bin) * a.wpc;
+        const int64_t o =
+            ((int64_t(s0 + sl - part_slot0) * a.F + f0 + cfl) * a.B + bin) * a.wpc + a.coff;
         if constexpr (PREC == CBH_PREC_INT16) {
             *reinterpret_cast<uint2*>(part + o) = *reinterpret_cast<const uint2*>(cell);
         } else {

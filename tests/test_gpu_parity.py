@@ -314,6 +314,42 @@ def test_histogram_kernels_and_layouts(cb, ctx, case, kcfg, layout, prec):
         assert np.array_equal(got[..., 1::2], want[..., 1::2])
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("kcfg", KERNEL_CONFIGS)
+@pytest.mark.parametrize("case", [(9001, 13, 64, 3, 0), (9001, 13, 64, 3, 3),
+                                  (4099, 6, 255, 10, 2)])
+def test_multiclass_histogram_kernels(cb, ctx, case, kcfg, prec):
+    """K > 1 (MultiClass, 2K statistics per cell) with both kernels and every
+    lane-group width on the tiled layout (the lanes-over-features kernel runs
+    one block per class)."""
+    n, F, B, K, level = case
+    loss = 2
+    nb, bins, leaf, gg, hh, label = _random_level(n + K + level, n, F, B, K, loss, level)
+    p, dev = _device_problem(cb, n, F, B, K, loss, level + 1, nb, bins, leaf, gg, hh, label)
+    p = _tiled_problem(cb, ctx, p, dev, n, F)
+    L = 1 << level
+    esz = 4 if prec == 0 else 8
+    hist = torch.empty(L * F * B * 2 * K * esz, dtype=torch.uint8, device=gu.dev())
+    kernel, w = kcfg
+    cb.cbh_set_hist_knobs(ctx, 160 * 1024, 512, 2048, 100, 8, 8, kernel, w)
+    try:
+        if prec == 2:
+            cb.cbh_quantize_gradients(ctx, p)
+        cb.cbh_build_histograms(ctx, p, level, prec, hist)
+        cb.cbh_sync(ctx)
+    finally:
+        cb.cbh_set_hist_knobs(ctx, 0)
+    got = gu.hist_to_f64(hist, L, F, B, K, prec, False)
+    if prec == 2:
+        rgq, rhq, _ = oracle.grad_codes(gg, hh, True)
+        assert np.array_equal(got, oracle.histogram_int(bins, rgq, rhq, leaf, L, B))
+        return
+    want = oracle.histogram(bins, gg.astype(np.float64), hh.astype(np.float64), leaf, L, B)
+    mag = oracle.histogram(bins, np.abs(gg).astype(np.float64), np.abs(hh).astype(np.float64),
+                           leaf, L, B)
+    assert gu.normalized_err(got, want, mag) <= (gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL)
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("kcfg", [(0, 0), (1, 32), (1, 8)])
 def test_subtraction_kernels_vs_oracle(cb, ctx, kcfg, prec):
