@@ -201,9 +201,11 @@ def snapshot_tree(bst, t, rng, n_feat=4):
     g = bst.g.cpu().numpy().astype(np.float64)
     h = bst.h.cpu().numpy().astype(np.float64) if bst.loss != 0 else np.ones_like(g)
     levels = []
+    # leaf indices on the host from the chosen splits (the device may keep the
+    # rows in leaf order until the last level)
+    leaf = np.zeros(bst.n, np.uint16)
     for lvl in range(bst.depth):
         L = 1 << lvl
-        leaf = bst.leaf.cpu().numpy() if lvl else np.zeros(bst.n, np.uint16)
         bst.build_level_histograms(pr, lvl)
         cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), bst.precision, bst.l2,
                             bst.split_ptr(lvl), None, bst.stream)
@@ -216,8 +218,11 @@ def snapshot_tree(bst, t, rng, n_feat=4):
             if bst.loss != 0:
                 got[..., 1::2] *= sc[:, 1]
         fs = np.sort(rng.choice(bst.F, n_feat, replace=False))
-        levels.append((L, fs, leaf, got[:, fs]))
-        cb.cbh_apply_split(bst.ctx, pr, lvl, bst.split_ptr(lvl), bst.stream)
+        levels.append((L, fs, leaf.copy(), got[:, fs]))
+        f, k = (int(v) for v in bst.best[lvl, :2].cpu().numpy())
+        if 0 <= f < bst.F:
+            leaf |= ((bins[f] > k).astype(np.uint16) << lvl)
+        bst.advance(pr, lvl)
     cb.cbh_update_approx(bst.ctx, pr, bst.hist_ptr(bst.depth - 1), bst.precision,
                          bst.split_ptr(bst.depth - 1), bst.lr, bst.l2, bst.leaf_values, None,
                          bst.stream)
@@ -362,7 +367,8 @@ def time_form(bst, name, args, rmse):
         "G_row_features_per_s": round(rf_per_tree / sec_per_tree / 1e9, 3),
         "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
         "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
-        "hist_subtraction": bool(bst.subtract),
+        "hist_subtraction": bool(bst.subtract) and bst.part is None,
+        "rows_in_leaf_order": bst.part is not None,
         "graph_replay": not args.no_graph,
         "hist_timing": timing,
         "ms_per_tree_while_timing_builds": (round(stamped_tree_ms, 4)
@@ -603,6 +609,8 @@ def main():
                     help="launch every call from Python instead of replaying captured trees")
     ap.add_argument("--hist-trees", type=int, default=None,
                     help="trees replayed from graphs with event nodes around every build")
+    ap.add_argument("--partition", choices=["auto", "on", "off"], default="auto",
+                    help="keep rows in leaf order during a tree (auto: for K > 1)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle leg (CPU timing and error vs FP64)")
     ap.add_argument("--autotune", default=None,
@@ -651,7 +659,8 @@ def main():
         p = {"c2": datagen.make_c2, "c3": datagen.make_c3}[args.workload](n=args.n)
     t_gen = time.perf_counter() - t_gen
     print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
-    bst = GpuBooster.from_problem(p).prepare()
+    part = {"auto": None, "on": True, "off": False}[args.partition]
+    bst = GpuBooster.from_problem(p, partition=part).prepare()
     print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
     rmse = p.loss == datagen.RMSE
     forms = [args.precision] + [f for f in args.compare.split(",") if f and f != args.precision]

@@ -340,6 +340,45 @@ int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_la
                       int32_t precision, const cbh_split* last, double lr, double l2,
                       double* leaf_values_out, int64_t* leaf_counts_out, void* stream);
 
+/* ---- rows in leaf order (deep trees, many classes) ------------------------- */
+
+typedef struct cbh_part cbh_part;
+
+/* Device buffers that keep a problem's rows sorted by leaf during a tree, so
+ * that a level's histograms read every row once whatever the number of
+ * leaves (Sec. 5: each leaf's histogram from its own rows). Holds two copies
+ * of the bins (16-row tiled layout), of the gradient statistics the
+ * histogram reads, of the original row ids and of the leaf indices, all
+ * ceil(n / 16) * 16 rows long, plus per-leaf offsets. The partition is
+ * sized for `prob` (n, features, K, depth, loss) and can serve any problem
+ * of that shape (e.g. every permutation's bins). Owned by the caller of
+ * cbh_part_create; cbh_part_destroy synchronizes the device first.
+ * Returns CBH_ENOMEM if the buffers do not fit. */
+int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out);
+void cbh_part_destroy(cbh_part* part);
+
+/* After the split of `level` (device cbh_split, e.g. from cbh_score_splits)
+ * instead of cbh_apply_split: moves the rows by a stable partition on the
+ * new leaf bit [bin of the split feature > border] (bit 0 first), which with
+ * rows already in leaf order below that bit leaves them sorted by the full
+ * leaf index. Level 0 reads the problem's bins, statistics (float g/h, or the
+ * int16 codes for CBH_PREC_INT16) and the identity row order; level l reads
+ * what level l-1 wrote. At level depth-1 nothing is moved: the leaf index of
+ * every row is written to prob->leaf (original row order), as
+ * cbh_apply_split over all levels would have left it. Levels must run in
+ * order within a tree; the statistics must be those of the tree (for int16,
+ * quantized before level 0). */
+int cbh_part_split(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_t level,
+                   int32_t precision, const cbh_split* split, void* stream);
+
+/* Histograms of level >= 1 from the rows cbh_part_split(level - 1) left in
+ * leaf order (a direct build; same output layout and values as
+ * cbh_build_histograms up to summation order): every slot tile of leaves
+ * reads only its rows. Uses the lanes-over-features kernel (any K) and the
+ * context workspace for partial tiles. */
+int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
+                              int32_t level, int32_t precision, void* hist_out, void* stream);
+
 /* ---- batched, fused levels ------------------------------------------------- */
 
 typedef struct cbh_batch cbh_batch;

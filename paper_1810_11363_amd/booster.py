@@ -56,7 +56,7 @@ class GpuBooster:
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
                  subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled",
-                 borders=None):
+                 borders=None, partition=None):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -72,6 +72,12 @@ class GpuBooster:
         # histogram subtraction at levels >= 1: exact for int16, two-float
         # difference for the compensated form; off for plain float32 by default
         self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
+        # rows kept in leaf order during a tree (levels >= 1 read each row once
+        # whatever the number of leaves, at the cost of moving the rows after
+        # every split): by default for several classes, whose slot tiles
+        # outgrow the LDS soonest; one class keeps subtraction
+        self.partition = int(K) > 1 if partition is None else bool(partition)
+        self.part = None
         self.x_num = np.ascontiguousarray(x_num, dtype=np.float32)
         self.cat = np.ascontiguousarray(cat, dtype=np.int32)
         self.label_h = np.ascontiguousarray(label, dtype=np.float32)
@@ -213,6 +219,8 @@ class GpuBooster:
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
         self._alloc_hists()
         self.probs = [self.problem(r) for r in range(self.s)]
+        if self.partition:
+            self.part = cb.cbh_part_create(self.ctx, self.probs[0])
         return self
 
     def _alloc_hists(self):
@@ -273,11 +281,22 @@ class GpuBooster:
 
     def build_level_histograms(self, pr, level: int):
         ctx, st, prec = self.ctx, self.stream, self.precision
-        if level > 0 and self.subtract:
+        if level > 0 and self.part is not None:
+            cb.cbh_part_build_histograms(ctx, self.part, pr, level, prec, self.hist_ptr(level), st)
+        elif level > 0 and self.subtract:
             cb.cbh_build_histograms_sub(ctx, pr, level, prec, self.hist_ptr(level - 1),
                                         self.split_ptr(level - 1), self.hist_ptr(level), st)
         else:
             cb.cbh_build_histograms(ctx, pr, level, prec, self.hist_ptr(level), st)
+
+    def advance(self, pr, level: int):
+        """Route the rows by the split of `level`: the leaf bit, or the move
+        into leaf order (which writes the leaf indices at the last level)."""
+        if self.part is not None:
+            cb.cbh_part_split(self.ctx, self.part, pr, level, self.precision,
+                              self.split_ptr(level), self.stream)
+        else:
+            cb.cbh_apply_split(self.ctx, pr, level, self.split_ptr(level), self.stream)
 
     def fit_tree(self, t: int, counts: bool = False, events=None):
         """One tree (all levels, leaf solve, approx and gradient update).
@@ -295,7 +314,7 @@ class GpuBooster:
                 events[lvl][1].record(st)
             cb.cbh_score_splits(ctx, pr, lvl, self.hist_ptr(lvl), prec, self.l2,
                                 self.split_ptr(lvl), None, st)
-            cb.cbh_apply_split(ctx, pr, lvl, self.split_ptr(lvl), st)
+            self.advance(pr, lvl)
         cb.cbh_update_approx(ctx, pr, self.hist_ptr(self.depth - 1), prec,
                              self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
                              self.leaf_counts if counts else None, st)
@@ -366,6 +385,10 @@ class GpuBooster:
         return ModelState(self, r)
 
     def close(self):
+        if self.part is not None:
+            torch.cuda.synchronize(self.device)
+            cb.cbh_part_destroy(self.part)
+            self.part = None
         if self.own_ctx and self.ctx:
             torch.cuda.synchronize(self.device)
             cb.cbh_destroy(self.ctx)

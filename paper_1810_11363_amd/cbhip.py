@@ -33,6 +33,7 @@ EXPORTS = [
     "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
+    "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
 ]
 
 
@@ -99,6 +100,11 @@ def _load():
         "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, i32, C.c_char_p, vp], C.c_int),
         "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
         "cbh_set_hist_knobs": ([vp, i32, i32, i64, i32, i32, i32, i32, i32], C.c_int),
+        "cbh_part_create": ([vp, C.POINTER(cbh_problem), C.POINTER(vp)], C.c_int),
+        "cbh_part_destroy": ([vp], None),
+        "cbh_part_split": ([vp, vp, C.POINTER(cbh_problem), i32, i32, vp, vp], C.c_int),
+        "cbh_part_build_histograms": ([vp, vp, C.POINTER(cbh_problem), i32, i32, vp, vp],
+                                      C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -227,6 +233,28 @@ def cbh_build_histograms(ctx, prob: cbh_problem, level: int, precision: int, his
                          stream=None):
     return _check(_lib.cbh_build_histograms(ctx, C.byref(prob), level, precision,
                                             _ptr(hist_out), _stream(stream)))
+
+
+def cbh_part_create(ctx, prob: cbh_problem):
+    out = C.c_void_p()
+    _check(_lib.cbh_part_create(ctx, C.byref(prob), C.byref(out)))
+    return out.value
+
+
+def cbh_part_destroy(part):
+    _lib.cbh_part_destroy(part)
+
+
+def cbh_part_split(ctx, part, prob: cbh_problem, level: int, precision: int, split,
+                   stream=None):
+    return _check(_lib.cbh_part_split(ctx, part, C.byref(prob), level, precision, _ptr(split),
+                                      _stream(stream)))
+
+
+def cbh_part_build_histograms(ctx, part, prob: cbh_problem, level: int, precision: int,
+                              hist_out, stream=None):
+    return _check(_lib.cbh_part_build_histograms(ctx, part, C.byref(prob), level, precision,
+                                                 _ptr(hist_out), _stream(stream)))
 
 
 def cbh_build_histograms_sub(ctx, prob: cbh_problem, level: int, precision: int, parent_hist,

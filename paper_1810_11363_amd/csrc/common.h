@@ -150,5 +150,6 @@ int64_t score_scratch_bytes(const cbh_problem* p);
 // Allow the dynamic-LDS kernels the device's full LDS (called by cbh_create).
 void hist_init_attrs(int max_lds);
 void batch_init_attrs(int max_lds);
+void part_init_attrs(int max_lds);
 
 }  // namespace cbh

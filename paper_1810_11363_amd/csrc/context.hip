@@ -129,6 +129,7 @@ int cbh_create(int device, cbh_ctx** out) {
     }
     hist_init_attrs(c->max_lds);
     batch_init_attrs(c->max_lds);
+    part_init_attrs(c->max_lds);
     *out = c;
     return CBH_OK;
 }

@@ -1,0 +1,752 @@
+// Rows kept in leaf order during a tree (for deep trees and many classes).
+//
+// A level's histograms need, per slot tile, only the rows of the tile's
+// leaves (Sec. 5 builds every leaf's histogram from its own rows). With rows
+// in their original order, a tile of leaf slots that does not fit in LDS
+// beside the others makes every block of every tile scan all rows. Here,
+// after the split of level l is chosen, the rows are moved by a stable
+// partition on the new leaf bit: rows whose bit is 0 first, then rows whose
+// bit is 1, each group in its previous order. Since the rows were already
+// sorted by their leaf index below bit l, they end up sorted by the full
+// leaf index (a least-significant-digit radix step), so the rows of any run
+// of consecutive leaves are one contiguous range.
+//
+// Moved per row: the bins of every feature (16-row tiled layout, staged in
+// LDS so that whole 16-byte segments are written), the gradient statistics
+// the histogram reads, the original row id and the leaf index. Level 0 reads
+// the problem's own arrays; level l writes buffer l % 2 and level l + 1
+// reads it. After the last level's split the leaf index of every row is
+// written back to the problem's leaf array (original order) for the leaf
+// solve and the approx update.
+//
+// The histogram of a partitioned level runs the lanes-over-features tile
+// over the row range of each slot tile only (chunks of the range, one block
+// per chunk x feature group x class), and a merge that sums each slot tile's
+// chunks.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "kernels_dev.h"
+
+namespace cbh {
+
+constexpr int kPartThreads = 256;
+constexpr int64_t kPartRows = 1024;                // positions per partition block
+constexpr int kPartSegs = 64;                      // 16-row segments per partition block
+constexpr int kPartFeat = 16;                      // features staged per LDS round
+constexpr int kPartRegion = 1056;                  // bytes per (run, feature) staging region
+constexpr int kPartLdsLeaves = 4096;               // leaf counters kept in LDS up to this L
+
+}  // namespace cbh
+
+struct cbh_part {
+    cbh_ctx* ctx = nullptr;
+    int64_t n = 0, n_pad = 0, n_pb = 0;
+    int32_t F = 0, K = 0, depth = 0, loss = 0;
+    uint8_t* bins[2] = {nullptr, nullptr};      // tiled [n_pad / 16][F][16]
+    const uint8_t** cols[2] = {nullptr, nullptr};   // device: column f -> bins + 16 f
+    int64_t* seg = nullptr;                     // device [F]: 16 F
+    float* g[2] = {nullptr, nullptr};           // [K][n_pad]
+    float* h[2] = {nullptr, nullptr};           // [K][n_pad] (not for RMSE)
+    uint32_t* gq[2] = {nullptr, nullptr};       // [K][n_pad] int16 code pairs
+    int32_t* order[2] = {nullptr, nullptr};     // original row of each position
+    uint16_t* code[2] = {nullptr, nullptr};     // leaf of each position (0xffff: padding)
+    int64_t* off[2] = {nullptr, nullptr};       // [2^(depth-1) + 1] first position of each leaf
+    uint32_t* zl = nullptr;                     // [2^(depth-2)] rows of each leaf with bit 0
+    int64_t* blk = nullptr;                     // [n_pb + 1] zeros per block, then their prefix
+    int64_t* cp = nullptr;                      // [2^(depth-1) + 1] chunk prefix of slot tiles
+};
+
+namespace cbh {
+
+// Exclusive prefix over 256 threads of one value each; `total` gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* sh,
+                                                       uint32_t& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int i = 0; i < w; ++i) wb += sh[i];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return wb + x - v;
+}
+
+// Exclusive prefix over `count` items by one block of 1024 threads, each
+// taking a contiguous run; get(i) gives item i, put(i, prefix) receives it.
+// Returns the total (in every thread).
+template <class Get, class Put>
+__device__ int64_t block_scan_1024(int64_t count, Get get, Put put, int64_t* sh) {
+    const int64_t per = (count + 1023) / 1024;
+    const int64_t i0 = min(count, int64_t(threadIdx.x) * per), i1 = min(count, i0 + per);
+    int64_t s = 0;
+    for (int64_t i = i0; i < i1; ++i) s += get(i);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 run sums
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t y = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+    }
+    const int64_t total = sh[1023];
+    int64_t run = sh[threadIdx.x] - s;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t v = get(i);
+        put(i, run);
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ bool split_bit(const uint8_t* col, int64_t st, int64_t pos, int k) {
+    return col != nullptr && (int)*seg_ptr(col, st, pos) > k;
+}
+
+// Rows with bit 0 per block (blk) and per current leaf (zl, added).
+__global__ __launch_bounds__(kPartThreads) void part_count_kernel(
+    const uint8_t* const* __restrict__ cols, const int64_t* __restrict__ seg, int32_t F,
+    const cbh_split* __restrict__ split, int64_t n, const uint16_t* __restrict__ code, int32_t L,
+    uint32_t* __restrict__ zl, int64_t* __restrict__ blk) {
+    extern __shared__ uint32_t zc[];
+    __shared__ uint32_t sh[8];
+    const bool lds_cnt = L <= kPartLdsLeaves;
+    if (lds_cnt)
+        for (int i = threadIdx.x; i < L; i += kPartThreads) zc[i] = 0u;
+    __syncthreads();
+    const cbh_split sp = *split;
+    const bool none = sp.feature < 0 || sp.feature >= F;
+    const uint8_t* col = none ? nullptr : cols[sp.feature];
+    const int64_t st = none ? 16 : seg_stride_of(seg, sp.feature);
+    const int64_t p0 = int64_t(blockIdx.x) * kPartRows + int64_t(threadIdx.x) * 4;
+    uint32_t zeros = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t pos = p0 + j;
+        if (pos >= n) break;
+        if (!split_bit(col, st, pos, sp.border)) {
+            ++zeros;
+            const uint32_t lf = code ? (uint32_t)code[pos] : 0u;
+            if (lds_cnt) atomicAdd(&zc[lf], 1u);
+            else atomicAdd(&zl[lf], 1u);
+        }
+    }
+    uint32_t tot;
+    (void)block_excl_scan256(zeros, sh, tot);
+    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+    if (lds_cnt)
+        for (int i = threadIdx.x; i < L; i += kPartThreads)
+            if (zc[i]) atomicAdd(&zl[i], zc[i]);
+}
+
+// One block: block zero counts -> exclusive prefix (blk[n_pb] = all zeros);
+// leaf offsets of the 2L new leaves (leaf v < L: the zeros of old leaf v;
+// v >= L: the ones of old leaf v - L); zl cleared for the next level.
+__global__ __launch_bounds__(1024) void part_scan_kernel(int64_t* __restrict__ blk, int64_t n_pb,
+                                                         uint32_t* __restrict__ zl, int32_t L,
+                                                         const int64_t* __restrict__ off_old,
+                                                         int64_t n, int64_t* __restrict__ off_new) {
+    __shared__ int64_t sh[1024];
+    const int64_t nz = block_scan_1024(
+        n_pb, [&](int64_t i) { return blk[i]; }, [&](int64_t i, int64_t e) { blk[i] = e; }, sh);
+    if (threadIdx.x == 0) blk[n_pb] = nz;
+    auto count = [&](int64_t v) -> int64_t {
+        if (v < L) return (int64_t)zl[v];
+        const int64_t u = v - L;
+        const int64_t old = off_old ? off_old[u + 1] - off_old[u] : n;
+        return old - (int64_t)zl[u];
+    };
+    (void)block_scan_1024(2 * int64_t(L), count, [&](int64_t v, int64_t e) { off_new[v] = e; },
+                          sh);
+    if (threadIdx.x == 0) off_new[2 * L] = n;
+    __syncthreads();
+    for (int i = threadIdx.x; i < L; i += 1024) zl[i] = 0u;
+}
+
+struct PartMove {
+    const uint8_t* const* src_cols;
+    const int64_t* src_seg;
+    uint8_t* dst_bins;             // tiled, segment stride 16 F
+    int32_t F, K, level;
+    const cbh_split* split;
+    int64_t n, n_pad, n_pb;
+    const int64_t* blk;            // exclusive zero prefix per block, total at [n_pb]
+    const int32_t* src_order;      // NULL: identity
+    int32_t* dst_order;
+    const uint16_t* src_code;      // NULL: leaf 0
+    uint16_t* dst_code;
+    const float* src_g;            // each NULL when not moved
+    const float* src_h;
+    const uint32_t* src_gq;
+    int64_t src_stride;            // elements between classes in the source
+    float* dst_g;
+    float* dst_h;
+    uint32_t* dst_gq;
+};
+
+// The stable partition itself, one block per kPartRows positions:
+//   1. wave 0 (lane = 16-row segment) finds the rows' bits and destinations;
+//   2. all threads move row ids, leaf indices and statistics (4 rows each);
+//   3. the bins, kPartFeat features per round: consecutive threads read
+//      consecutive 16-byte (segment, feature) pieces, i.e. each segment's
+//      features contiguously; the bytes are staged in LDS per destination run
+//      (the block's zero rows go to [Zb, Zb + nzb), its one rows to
+//      [O0, O0 + nob)) from the 16-byte segment below the run's start; then
+//      every destination segment is written, features fastest: whole
+//      segments as one 16-byte store, the partial ones at the run ends byte
+//      by byte (the neighbouring block owns their other bytes).
+__global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) {
+    __shared__ __align__(16) uint8_t stage[2 * kPartFeat * kPartRegion];
+    __shared__ int32_t rel[kPartRows];        // destination - base of its run
+    __shared__ uint32_t segbits[kPartSegs], segvalid[kPartSegs];
+    __shared__ uint32_t nzb_sh;
+    const cbh_split sp = *m.split;
+    const bool none = sp.feature < 0 || sp.feature >= m.F;
+    const int64_t P0 = int64_t(blockIdx.x) * kPartRows;
+    const int64_t Zb = m.blk[blockIdx.x], NZ = m.blk[m.n_pb];
+    const int64_t O0 = NZ + (P0 - Zb);
+    const int64_t base[2] = {Zb & ~int64_t(15), O0 & ~int64_t(15)};
+    if (threadIdx.x < 64) {
+        const int sg = threadIdx.x;
+        const uint8_t* scol = none ? nullptr : m.src_cols[sp.feature];
+        const int64_t sst = none ? 16 : seg_stride_of(m.src_seg, sp.feature);
+        const int64_t p0 = P0 + 16 * sg;
+        uint32_t bits = 0u, valid = 0u;
+        for (int j = 0; j < 16; ++j) {
+            const int64_t pos = p0 + j;
+            if (pos >= m.n) break;
+            valid |= 1u << j;
+            if (split_bit(scol, sst, pos, sp.border)) bits |= 1u << j;
+        }
+        const uint32_t zmask = valid & ~bits;
+        const uint32_t nz = (uint32_t)__popc(zmask);
+        uint32_t x = nz;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (sg >= d) x += y;
+        }
+        const uint32_t zt = x - nz;
+        if (sg == 63) nzb_sh = x;
+        segbits[sg] = bits;
+        segvalid[sg] = valid;
+        for (int j = 0; j < 16; ++j) {
+            if (!((valid >> j) & 1u)) break;
+            const int64_t zb = Zb + zt + __popc(zmask & ((1u << j) - 1u));
+            const int r = (bits >> j) & 1u;
+            const int64_t d = r ? NZ + (p0 + j - zb) : zb;
+            rel[16 * sg + j] = (int32_t)(d - base[r]);
+        }
+    }
+    __syncthreads();
+    const int64_t nzb = nzb_sh;
+    const int64_t nvb = min(kPartRows, m.n - P0);
+    const int64_t nob = nvb - nzb;
+    // row ids, leaf indices and statistics
+    for (int i = threadIdx.x; i < nvb; i += kPartThreads) {
+        const int64_t pos = P0 + i;
+        const uint32_t bit = (segbits[i >> 4] >> (i & 15)) & 1u;
+        const int64_t d = base[bit] + rel[i];
+        m.dst_order[d] = m.src_order ? m.src_order[pos] : (int32_t)pos;
+        m.dst_code[d] = (uint16_t)((m.src_code ? (uint32_t)m.src_code[pos] : 0u) |
+                                   (bit << m.level));
+        for (int c = 0; c < m.K; ++c) {
+            const int64_t si = int64_t(c) * m.src_stride + pos, di = int64_t(c) * m.n_pad + d;
+            if (m.dst_g) m.dst_g[di] = m.src_g[si];
+            if (m.dst_h) m.dst_h[di] = m.src_h[si];
+            if (m.dst_gq) m.dst_gq[di] = m.src_gq[si];
+        }
+    }
+    const int64_t run0[2] = {Zb, O0}, run1[2] = {Zb + nzb, O0 + nob};
+    const int64_t s0[2] = {run0[0] >> 4, run0[1] >> 4};
+    const int64_t ns[2] = {nzb ? ((run1[0] + 15) >> 4) - s0[0] : 0,
+                           nob ? ((run1[1] + 15) >> 4) - s0[1] : 0};
+    const int64_t dstride = 16 * int64_t(m.F);
+    const int64_t seg0 = P0 >> 4;
+    for (int f0 = 0; f0 < m.F; f0 += kPartFeat) {
+        const int nfe = min(kPartFeat, m.F - f0);
+        for (int c = threadIdx.x; c < kPartSegs * kPartFeat; c += kPartThreads) {
+            const int sg = c / kPartFeat, fi = c % kPartFeat;
+            const uint32_t valid = segvalid[sg];
+            if (fi >= nfe || !valid) continue;
+            const int f = f0 + fi;
+            const uint8_t* src = m.src_cols[f] + (seg0 + sg) * seg_stride_of(m.src_seg, f);
+            uint32_t w[4];
+            if (valid == 0xffffu && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+                const uint4 v = *reinterpret_cast<const uint4*>(src);
+                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            } else {
+                w[0] = w[1] = w[2] = w[3] = 0u;
+                for (int j = 0; j < 16; ++j)
+                    if ((valid >> j) & 1u) w[j >> 2] |= (uint32_t)src[j] << (8 * (j & 3));
+            }
+            const uint32_t bits = segbits[sg];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (!((valid >> j) & 1u)) continue;
+                const int r = (bits >> j) & 1u;
+                stage[(r * kPartFeat + fi) * kPartRegion + rel[16 * sg + j]] =
+                    (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+            }
+        }
+        __syncthreads();
+        const int64_t nseg = ns[0] + ns[1];
+        for (int64_t it = threadIdx.x; it < nseg * nfe; it += kPartThreads) {
+            const int fi = (int)(it % nfe);
+            const int64_t q = it / nfe;
+            const int r = q < ns[0] ? 0 : 1;
+            const int64_t s = s0[r] + (r ? q - ns[0] : q);
+            const int64_t lo = max(run0[r], 16 * s), hi = min(run1[r], 16 * s + 16);
+            if (lo >= hi) continue;
+            const uint8_t* from = stage + (r * kPartFeat + fi) * kPartRegion + (16 * s - base[r]);
+            uint8_t* to = m.dst_bins + s * dstride + 16 * int64_t(f0 + fi);
+            if (lo == 16 * s && hi == 16 * s + 16) {
+                *reinterpret_cast<uint4*>(to) = *reinterpret_cast<const uint4*>(from);
+            } else {
+                for (int64_t p = lo; p < hi; ++p) to[p - 16 * s] = from[p - 16 * s];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// After the last level's split: leaf index of every row, in original order.
+__global__ __launch_bounds__(256) void part_leaf_kernel(const uint8_t* const* __restrict__ cols,
+                                                        const int64_t* __restrict__ seg, int32_t F,
+                                                        const cbh_split* __restrict__ split,
+                                                        int64_t n, int32_t level,
+                                                        const int32_t* __restrict__ order,
+                                                        const uint16_t* __restrict__ code,
+                                                        uint16_t* __restrict__ leaf) {
+    const cbh_split sp = *split;
+    const bool none = sp.feature < 0 || sp.feature >= F;
+    const uint8_t* col = none ? nullptr : cols[sp.feature];
+    const int64_t st = none ? 16 : seg_stride_of(seg, sp.feature);
+    for (int64_t pos = int64_t(blockIdx.x) * 256 + threadIdx.x; pos < n;
+         pos += int64_t(gridDim.x) * 256) {
+        const uint32_t bit = split_bit(col, st, pos, sp.border) ? 1u : 0u;
+        const int64_t row = order ? order[pos] : pos;
+        leaf[row] = (uint16_t)((code ? (uint32_t)code[pos] : 0u) | (bit << level));
+    }
+}
+
+// Chunks of every slot tile: tile t holds leaves [t lt, min((t+1) lt, L)),
+// i.e. positions [off[t lt], off[...]) and the 16-row segments over them;
+// cp = exclusive prefix of ceil(segments / segs_per_chunk), total at [n_tiles].
+__global__ __launch_bounds__(1024) void part_tiles_kernel(const int64_t* __restrict__ off,
+                                                          int32_t L, int32_t lt, int32_t n_tiles,
+                                                          int64_t segs_per_chunk,
+                                                          int64_t* __restrict__ cp) {
+    __shared__ int64_t sh[1024];
+    auto chunks = [&](int64_t t) -> int64_t {
+        const int64_t a = off[t * lt], b = off[min((t + 1) * int64_t(lt), int64_t(L))];
+        if (a >= b) return 0;
+        return (((b + 15) >> 4) - (a >> 4) + segs_per_chunk - 1) / segs_per_chunk;
+    };
+    const int64_t tot =
+        block_scan_1024(n_tiles, chunks, [&](int64_t t, int64_t e) { cp[t] = e; }, sh);
+    if (threadIdx.x == 0) cp[n_tiles] = tot;
+}
+
+struct PartHist {
+    const uint8_t* const* cols;
+    const int64_t* seg;
+    const float* g;
+    const float* h;
+    const uint32_t* gq;
+    const uint16_t* code;
+    const int64_t* off;
+    const int64_t* cp;
+    uint32_t* partials;            // [chunk][lt][F][B][wpc]
+    int64_t n_pad, n_items, segs_per_chunk;
+    int32_t F, B, K, L, lt, n_tiles, n_fgroups, wpc;
+};
+
+// Block -> (class, feature group, chunk) with the classes of one group and
+// chunk adjacent; the chunk's slot tile by binary search over cp.
+template <int PREC, int RM, int W>
+__global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int64_t per_xcd = (a.n_items + 7) / 8;
+    int64_t item = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (item >= a.n_items) return;
+    const int c = (int)(item % a.K);
+    item /= a.K;
+    const int fg = (int)(item % a.n_fgroups);
+    const int64_t gc = item / a.n_fgroups;
+    if (gc >= a.cp[a.n_tiles]) return;
+    int lo = 0, hi = a.n_tiles - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.cp[mid] <= gc) lo = mid; else hi = mid - 1;
+    }
+    const int t = lo;
+    const int64_t j = gc - a.cp[t];
+    const uint32_t s0 = (uint32_t)t * (uint32_t)a.lt;
+    const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);
+    const int64_t pa = a.off[s0], pb = a.off[s0 + ns];
+    const int64_t sa = (pa >> 4) + j * a.segs_per_chunk;
+    const int64_t sb = min((pb + 15) >> 4, sa + a.segs_per_chunk);
+    LpfBlock b;
+    b.bins = a.cols;
+    b.seg = a.seg;
+    b.g = a.g + int64_t(c) * a.n_pad;
+    b.h = a.h ? a.h + int64_t(c) * a.n_pad : nullptr;
+    b.gq = a.gq ? a.gq + int64_t(c) * a.n_pad : nullptr;
+    b.rowcode = a.code;
+    b.F = a.F;
+    b.B = a.B;
+    b.wpc = a.wpc;
+    b.coff = c * (a.wpc / a.K);
+    lpf_block<PREC, RM, W, 2>(b, sa * 16, sb * 16, fg, s0, ns,
+                              a.partials + gc * (int64_t(a.lt) * a.F * a.B * a.wpc), s0, lds);
+}
+
+// Output cell (leaf, feature, bin): the sum of its slot tile's chunks.
+template <int PREC>
+__global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restrict__ part,
+                                                         const int64_t* __restrict__ cp,
+                                                         int32_t L, int32_t lt, int32_t F,
+                                                         int32_t B, int32_t K, int32_t wpc,
+                                                         int32_t rmse, void* __restrict__ out) {
+    const int64_t fb = int64_t(F) * B, cells = int64_t(L) * fb, cells_lt = int64_t(lt) * fb;
+    for (int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x; cell < cells;
+         cell += int64_t(gridDim.x) * 256) {
+        const int64_t v = cell / fb, rest = cell % fb;
+        const int64_t t = v / lt;
+        const int64_t g0 = cp[t];
+        merge_cell<PREC>(part + g0 * cells_lt * wpc, cells_lt, K, (int)(cp[t + 1] - g0),
+                         rmse != 0, out, (v - t * lt) * fb + rest, cell);
+    }
+}
+
+void part_init_attrs(int max_lds) {
+    const void* fns[] = {
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 0, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 0, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 0, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 0, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 1, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 1, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 1, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_FP32, 1, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 0, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 0, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 0, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 0, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 1, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 1, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 1, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_TWOFLOAT, 1, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 4>};
+    for (const void* f : fns)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+template <int PREC, int RM>
+static void launch_part_hist(const PartHist& a, int W, unsigned grid, size_t lds, hipStream_t s) {
+    switch (W) {
+        case 32: hist_part_kernel<PREC, RM, 32><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 16: hist_part_kernel<PREC, RM, 16><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 8: hist_part_kernel<PREC, RM, 8><<<grid, kHistThreads, lds, s>>>(a); break;
+        default: hist_part_kernel<PREC, RM, 4><<<grid, kHistThreads, lds, s>>>(a); break;
+    }
+}
+
+// Plan of a build over rows in leaf order: a slot tile reads only its own
+// rows, so more tiles cost no re-reads; the widest lane group whose tile of
+// one slot fits the LDS (fewest feature groups, so the statistics are read
+// fewest times), as many slots per tile as fit (at most 64), and chunks of
+// at least min_rows rows sized so that the blocks of the whole level reach
+// target_blocks.
+static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
+                          int32_t L, int32_t precision, int max_lds) {
+    HistPlan p;
+    p.kind = 1;
+    p.words_per_cell = words_per_cell(precision, K);
+    const uint32_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
+    const int64_t budget = max_lds;
+    int32_t W = kn.lpf_w > 0 ? std::min(kn.lpf_w, 32) : 32;
+    while (W > 4 && int64_t(B) * lpf_record_bytes(W, cs) > budget) W /= 2;
+    p.fb = W;
+    const int64_t slot_bytes = int64_t(B) * lpf_record_bytes(W, cs);
+    p.lt = (int32_t)std::max<int64_t>(1, std::min<int64_t>({int64_t(L), 64, budget / slot_bytes}));
+    p.n_ltiles = (L + p.lt - 1) / p.lt;
+    p.n_fgroups = (F + W - 1) / W;
+    const int64_t per_chunk = int64_t(p.n_fgroups) * K;     // blocks per chunk of rows
+    int64_t rows = std::max<int64_t>(kn.min_rows,
+                                     n * per_chunk / std::max<int64_t>(1, kn.target_blocks));
+    rows = align_up(std::min<int64_t>(rows, align_up(n, 16)), 16);
+    if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);
+    p.rows_per_chunk = rows;
+    p.n_chunks = (int32_t)((n + rows - 1) / rows);
+    p.rep = 1;
+    p.lds_bytes = int64_t(p.lt) * slot_bytes;
+    p.n_blocks = (int64_t(p.n_chunks) + p.n_ltiles) * per_chunk;
+    return p;
+}
+
+static void free_part(cbh_part* p) {
+    void* bufs[] = {p->bins[0], p->bins[1], p->cols[0], p->cols[1], p->seg,   p->g[0],
+                    p->g[1],    p->h[0],    p->h[1],    p->gq[0],   p->gq[1], p->order[0],
+                    p->order[1], p->code[0], p->code[1], p->off[0], p->off[1], p->zl,
+                    p->blk,     p->cp};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+static int check_part(const cbh_part* part, const cbh_problem* prob) {
+    CBH_ARG(part != nullptr, "partition is NULL");
+    CBH_ARG(prob->n == part->n && prob->n_features == part->F && prob->K == part->K &&
+                prob->depth == part->depth && prob->loss == part->loss,
+            "problem does not match the partition (n, features, K, depth, loss)");
+    return CBH_OK;
+}
+
+}  // namespace cbh
+
+using namespace cbh;
+
+extern "C" {
+
+int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out) {
+    clear_error();
+    CBH_ARG(ctx && out, "NULL argument");
+    *out = nullptr;
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    CBH_REQUIRE(prob->depth <= 16, CBH_EUNSUPPORTED, "depth must be <= 16");
+    cbh_part* p = new cbh_part();
+    p->ctx = ctx;
+    p->n = prob->n;
+    p->n_pad = align_up(prob->n, 16);
+    p->n_pb = (p->n + kPartRows - 1) / kPartRows;
+    p->F = prob->n_features;
+    p->K = prob->K;
+    p->depth = prob->depth;
+    p->loss = prob->loss;
+    const int64_t np = p->n_pad, F = p->F, K = p->K;
+    const int64_t half = int64_t(1) << std::max(0, p->depth - 1);
+    auto alloc = [&](void** ptr, int64_t bytes) -> bool {
+        if (hipMalloc(ptr, (size_t)std::max<int64_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            return false;
+        }
+        return true;
+    };
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) {
+        ok = alloc((void**)&p->bins[b], np * F) && alloc((void**)&p->cols[b], F * 8) &&
+             alloc((void**)&p->g[b], K * np * 4) && alloc((void**)&p->gq[b], K * np * 4) &&
+             alloc((void**)&p->order[b], np * 4) && alloc((void**)&p->code[b], np * 2) &&
+             alloc((void**)&p->off[b], (2 * half + 1) * 8);
+        if (ok && p->loss != CBH_LOSS_RMSE) ok = alloc((void**)&p->h[b], K * np * 4);
+    }
+    ok = ok && alloc((void**)&p->seg, F * 8) && alloc((void**)&p->zl, half * 4) &&
+         alloc((void**)&p->blk, (p->n_pb + 1) * 8) && alloc((void**)&p->cp, (half + 1) * 8);
+    if (!ok) {
+        free_part(p);
+        delete p;
+        set_error("partition buffers (%lld rows x %lld features) do not fit in device memory",
+                  (long long)prob->n, (long long)F);
+        return CBH_ENOMEM;
+    }
+    // padding positions keep code 0xffff (never a slot), zero statistics
+    std::vector<const uint8_t*> colv(F);
+    std::vector<int64_t> segv(F, 16 * F);
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2; ++b) {
+        for (int64_t f = 0; f < F; ++f) colv[f] = p->bins[b] + 16 * f;
+        if (e == hipSuccess) e = hipMemcpy(p->cols[b], colv.data(), F * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(p->code[b], 0xff, np * 2);
+        if (e == hipSuccess) e = hipMemset(p->g[b], 0, K * np * 4);
+        if (e == hipSuccess) e = hipMemset(p->gq[b], 0, K * np * 4);
+        if (e == hipSuccess && p->h[b]) e = hipMemset(p->h[b], 0, K * np * 4);
+        if (e == hipSuccess) e = hipMemset(p->bins[b], 0, np * F);
+    }
+    if (e == hipSuccess) e = hipMemcpy(p->seg, segv.data(), F * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->zl, 0, half * 4);
+    if (e != hipSuccess) {
+        free_part(p);
+        delete p;
+        set_error("partition set-up failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    *out = p;
+    return CBH_OK;
+}
+
+void cbh_part_destroy(cbh_part* part) {
+    if (!part) return;
+    (void)hipDeviceSynchronize();
+    free_part(part);
+    delete part;
+}
+
+int cbh_part_split(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_t level,
+                   int32_t precision, const cbh_split* split, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && split != nullptr, "NULL argument");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    rc = check_part(part, prob);
+    if (rc) return rc;
+    CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
+    hipStream_t s = (hipStream_t)stream;
+    const int src = (level + 1) & 1, dst = level & 1;   // level l reads (l-1) % 2, writes l % 2
+    const bool first = level == 0;
+    const uint8_t* const* scols = first ? prob->bins : part->cols[src];
+    const int64_t* sseg = first ? prob->seg_stride : part->seg;
+    const int32_t* sorder = first ? nullptr : part->order[src];
+    const uint16_t* scode = first ? nullptr : part->code[src];
+    const int F = part->F;
+    if (level == prob->depth - 1) {
+        const unsigned grid =
+            (unsigned)std::min<int64_t>((part->n + 255) / 256, int64_t(ctx->num_cus) * 16);
+        part_leaf_kernel<<<grid, 256, 0, s>>>(scols, sseg, F, split, part->n, level, sorder, scode,
+                                              prob->leaf);
+        CBH_LAUNCHED();
+        return CBH_OK;
+    }
+    const int32_t L = 1 << level;
+    const size_t cnt_lds = L <= kPartLdsLeaves ? size_t(L) * 4 : 0;
+    part_count_kernel<<<(unsigned)part->n_pb, kPartThreads, cnt_lds, s>>>(
+        scols, sseg, F, split, part->n, scode, L, part->zl, part->blk);
+    CBH_LAUNCHED();
+    part_scan_kernel<<<1, 1024, 0, s>>>(part->blk, part->n_pb, part->zl, L,
+                                         first ? nullptr : part->off[src], part->n, part->off[dst]);
+    CBH_LAUNCHED();
+    PartMove m;
+    m.src_cols = scols;
+    m.src_seg = sseg;
+    m.dst_bins = part->bins[dst];
+    m.F = F;
+    m.K = part->K;
+    m.level = level;
+    m.split = split;
+    m.n = part->n;
+    m.n_pad = part->n_pad;
+    m.n_pb = part->n_pb;
+    m.blk = part->blk;
+    m.src_order = sorder;
+    m.dst_order = part->order[dst];
+    m.src_code = scode;
+    m.dst_code = part->code[dst];
+    const bool q = precision == CBH_PREC_INT16;
+    const bool rm = prob->loss == CBH_LOSS_RMSE;
+    m.src_g = q ? nullptr : (first ? prob->g : part->g[src]);
+    m.src_h = (q || rm) ? nullptr : (first ? prob->h : part->h[src]);
+    m.src_gq = q ? (first ? reinterpret_cast<const uint32_t*>(prob->gq) : part->gq[src]) : nullptr;
+    m.src_stride = first ? prob->n : part->n_pad;
+    m.dst_g = q ? nullptr : part->g[dst];
+    m.dst_h = (q || rm) ? nullptr : part->h[dst];
+    m.dst_gq = q ? part->gq[dst] : nullptr;
+    part_scatter_kernel<<<(unsigned)part->n_pb, kPartThreads, 0, s>>>(m);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
+                              int32_t level, int32_t precision, void* hist_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && hist_out != nullptr, "NULL argument");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    rc = check_part(part, prob);
+    if (rc) return rc;
+    CBH_ARG(level >= 1 && level < prob->depth, "level %d outside [1, depth)", level);
+    hipStream_t s = (hipStream_t)stream;
+    const int src = (level + 1) & 1;   // written by the split of level - 1
+    const int L = 1 << level;
+    const int F = part->F, B = prob->max_bins, K = part->K;
+    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const HistKnobs kn = knobs_for(ctx, F, B, K, level, precision, prob->n, 2);
+    const HistPlan plan = plan_part(kn, prob->n, F, B, K, L, precision, ctx->max_lds);
+    const int64_t spc = std::max<int64_t>(1, plan.rows_per_chunk / 16);
+    const int64_t n_tiles = plan.n_ltiles;
+    const int64_t max_chunks = (part->n_pad / 16 + n_tiles + spc - 1) / spc + n_tiles + 1;
+    const int64_t cell_words = int64_t(plan.lt) * F * B * plan.words_per_cell;
+    rc = ensure_ws(ctx, max_chunks * cell_words * 4);
+    if (rc) return rc;
+    part_tiles_kernel<<<1, 1024, 0, s>>>(part->off[src], L, plan.lt, (int32_t)n_tiles, spc,
+                                          part->cp);
+    CBH_LAUNCHED();
+    PartHist a;
+    const bool q = precision == CBH_PREC_INT16;
+    a.cols = part->cols[src];
+    a.seg = part->seg;
+    a.g = part->g[src];
+    a.h = part->h[src];
+    a.gq = q ? part->gq[src] : nullptr;
+    a.code = part->code[src];
+    a.off = part->off[src];
+    a.cp = part->cp;
+    a.partials = (uint32_t*)ctx->ws;
+    a.n_pad = part->n_pad;
+    a.n_items = max_chunks * plan.n_fgroups * K;
+    a.segs_per_chunk = spc;
+    a.F = F;
+    a.B = B;
+    a.K = K;
+    a.L = L;
+    a.lt = plan.lt;
+    a.n_tiles = (int32_t)n_tiles;
+    a.n_fgroups = plan.n_fgroups;
+    a.wpc = plan.words_per_cell;
+    const unsigned grid = (unsigned)(8 * ((a.n_items + 7) / 8));
+    const size_t lds = (size_t)plan.lds_bytes;
+    switch (precision) {
+        case CBH_PREC_FP32:
+            if (rmse) launch_part_hist<CBH_PREC_FP32, 1>(a, plan.fb, grid, lds, s);
+            else launch_part_hist<CBH_PREC_FP32, 0>(a, plan.fb, grid, lds, s);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            if (rmse) launch_part_hist<CBH_PREC_TWOFLOAT, 1>(a, plan.fb, grid, lds, s);
+            else launch_part_hist<CBH_PREC_TWOFLOAT, 0>(a, plan.fb, grid, lds, s);
+            break;
+        default:
+            launch_part_hist<CBH_PREC_INT16, 0>(a, plan.fb, grid, lds, s);
+            break;
+    }
+    CBH_LAUNCHED();
+    const int64_t cells = int64_t(L) * F * B;
+    const unsigned mg =
+        (unsigned)std::min<int64_t>((cells + 255) / 256, int64_t(ctx->num_cus) * 16);
+    switch (precision) {
+        case CBH_PREC_FP32:
+            part_merge_kernel<CBH_PREC_FP32><<<mg, 256, 0, s>>>(
+                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            part_merge_kernel<CBH_PREC_TWOFLOAT><<<mg, 256, 0, s>>>(
+                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out);
+            break;
+        default:
+            part_merge_kernel<CBH_PREC_INT16><<<mg, 256, 0, s>>>(
+                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out);
+            break;
+    }
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+}  // extern "C"

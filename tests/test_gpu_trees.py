@@ -27,9 +27,10 @@ def cb():
     return cbhip
 
 
-def _booster(cb, p, prec, subtract=None):
+def _booster(cb, p, prec, subtract=None, partition=None):
     from paper_1810_11363_amd.booster import GpuBooster
-    return GpuBooster.from_problem(p, precision=prec, subtract=subtract).prepare()
+    return GpuBooster.from_problem(p, precision=prec, subtract=subtract,
+                                   partition=partition).prepare()
 
 
 def _check_prep(bst, p):
@@ -62,15 +63,15 @@ def _lockstep_tree(cb, bst, t, stats):
         hd = gq[..., 1].astype(np.float64) * sc[:, 1:2] if bst.loss != 0 else h32
     else:
         gd, hd = g32, h32
+    # leaf indices on the host, from the chosen splits (with rows in leaf
+    # order the device keeps them by position until the last level)
+    leaf = np.zeros(n, np.uint16)
     for lvl in range(bst.depth):
         L = 1 << lvl
-        bst.build_level_histograms(pr, lvl)      # subtraction at levels >= 1 if enabled
+        bst.build_level_histograms(pr, lvl)      # subtraction or leaf order if enabled
         hist = bst.hist_ptr(lvl)
         cb.cbh_score_splits(ctx, pr, lvl, hist, prec, L2, bst.split_ptr(lvl))
         cb.cbh_sync(ctx)
-        leaf = bst.leaf.cpu().numpy()
-        if lvl == 0:
-            leaf[:] = 0
         got = gu.hist_to_f64(bst.hists[lvl % 2], L, bst.F, B, K, prec, bst.loss == 0)
         if prec == 2:
             got_deq = got.astype(np.float64).copy()
@@ -92,12 +93,14 @@ def _lockstep_tree(cb, bst, t, stats):
         f, k, _, _ = gu.split_of(bst.best, lvl)
         clear = gu.check_split((f, k), ref, nb)
         stats["ties"] = stats.get("ties", 0) + (not clear)
-        cb.cbh_apply_split(ctx, pr, lvl, bst.split_ptr(lvl))
+        bst.advance(pr, lvl)
         cb.cbh_sync(ctx)
         want_leaf = leaf.copy()
         if f >= 0:
             oracle.apply_split(bins[f], k, lvl, want_leaf)
-        assert np.array_equal(bst.leaf.cpu().numpy(), want_leaf)
+        if bst.part is None or lvl == bst.depth - 1:
+            assert np.array_equal(bst.leaf.cpu().numpy(), want_leaf)
+        leaf = want_leaf
     a0 = bst.approx.cpu().numpy()
     cb.cbh_update_approx(ctx, pr, bst.hist_ptr(bst.depth - 1), prec, bst.split_ptr(bst.depth - 1),
                          bst.lr, L2, bst.leaf_values, bst.leaf_counts)
@@ -134,11 +137,12 @@ def _shrink(p, iters, depth=None):
     return p
 
 
+@pytest.mark.parametrize("partition", [False, True])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("name", list(CASES))
-def test_lockstep_trees(cb, name, prec):
+def test_lockstep_trees(cb, name, prec, partition):
     p = CASES[name]()
-    bst = _booster(cb, p, prec)
+    bst = _booster(cb, p, prec, partition=partition)
     _check_prep(bst, p)
     bst.init_gradients()
     rg, _ = oracle.gradients(p.loss, p.K, np.zeros((p.K, p.n)), p.label)
@@ -157,7 +161,7 @@ def test_subtraction_matches_direct(cb, prec):
     int16 sums and counts, within two-float rounding for the compensated form,
     within float rounding of the parent for plain float32."""
     p = _shrink(datagen.make_c2(n=20011, s=1), iters=1)
-    bst = _booster(cb, p, prec, subtract=True)
+    bst = _booster(cb, p, prec, subtract=True, partition=False)
     bst.init_gradients()
     pr = bst.probs[0]
     if prec == 2:
@@ -208,6 +212,44 @@ def test_independent_run_matches_oracle_c1(cb):
                 pytest.skip(f"near-tie at tree {t} level {lvl}; lock-step test covers it")
     np.testing.assert_allclose(bst.approx.cpu().numpy(), oapprox, rtol=1e-5, atol=1e-6)
     bst.close()
+
+
+PART_CASES = {
+    # deep tree on few rows: many empty and one-row leaves, a ragged last block
+    "deep_small": lambda: datagen.random_small(seed=5, n=3001, F_num=6, F_cat=2, C=40,
+                                               depth=9, num_bins=64, s=2),
+    "logloss_4097": lambda: datagen.random_small(seed=6, n=4097, F_num=5, F_cat=1, C=9,
+                                                 loss=datagen.LOGLOSS, depth=8, num_bins=255),
+    "multiclass": lambda: datagen.random_small(seed=7, n=9000, F_num=4, F_cat=2, C=25,
+                                               loss=datagen.MULTICLASS, K=5, depth=6,
+                                               num_bins=32),
+}
+
+
+@pytest.mark.parametrize("name", list(PART_CASES))
+def test_partition_matches_unpartitioned(cb, name):
+    """Trees grown with the rows kept in leaf order equal those of the
+    original row order: splits, leaf indices, leaf values and approx bit for
+    bit (int16: every histogram sum is exact), over several trees and
+    permutations."""
+    p = PART_CASES[name]()
+    a = _booster(cb, p, 2, partition=False)
+    b = _booster(cb, p, 2, partition=True)
+    try:
+        a.init_gradients()
+        b.init_gradients()
+        for t in range(4):
+            a.fit_tree(t)
+            b.fit_tree(t)
+            torch.cuda.synchronize()
+            ra, rb = a.tree_record(), b.tree_record()
+            assert np.array_equal(ra.splits, rb.splits), t
+            assert torch.equal(a.leaf, b.leaf), t
+            assert np.array_equal(ra.values, rb.values), t
+            assert torch.equal(a.approx, b.approx), t
+    finally:
+        a.close()
+        b.close()
 
 
 # ------------------------------------------------------------ batched/graph
@@ -362,8 +404,8 @@ def test_graph_replay_matches_eager(cb):
             b.close()
 
 
-@pytest.mark.parametrize("prec", [2, 1])
-def test_tree_graph_matches_eager(cb, prec):
+@pytest.mark.parametrize("prec,partition", [(2, False), (1, False), (2, True), (1, True)])
+def test_tree_graph_matches_eager(cb, prec, partition):
     """Whole trees captured once per permutation and replayed (the benchmark's
     timed form) give the trees that eager calls give: bit for bit for int16;
     for the compensated form, whose FP64 LDS sums may round differently run to
@@ -371,8 +413,8 @@ def test_tree_graph_matches_eager(cb, prec):
     with eager reads and synchronisations between replays."""
     p = datagen.make_c2(n=60000)
     p.depth = 5
-    eager = _booster(cb, p, prec)
-    graph = _booster(cb, p, prec)
+    eager = _booster(cb, p, prec, partition=partition)
+    graph = _booster(cb, p, prec, partition=partition)
     try:
         eager.init_gradients()
         graph.init_gradients()
