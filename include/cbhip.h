@@ -345,8 +345,8 @@ int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_la
 typedef struct cbh_part cbh_part;
 
 /* Device buffers that keep a problem's rows sorted by leaf during a tree, so
- * that a level's histograms read every row once whatever the number of
- * leaves (Sec. 5: each leaf's histogram from its own rows). Holds two copies
+ * that a level's histograms (Sec. 5) read every row once whatever the number
+ * of leaves (this library's layout, not the paper's). Holds two copies
  * of the bins (16-row tiled layout), of the gradient statistics the
  * histogram reads, of the original row ids and of the leaf indices, all
  * ceil(n / 16) * 16 rows long, plus per-leaf offsets. The partition is

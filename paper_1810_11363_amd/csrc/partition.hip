@@ -1,9 +1,10 @@
 // Rows kept in leaf order during a tree (for deep trees and many classes).
 //
 // A level's histograms need, per slot tile, only the rows of the tile's
-// leaves (Sec. 5 builds every leaf's histogram from its own rows). With rows
-// in their original order, a tile of leaf slots that does not fit in LDS
-// beside the others makes every block of every tile scan all rows. Here,
+// leaves. With rows in their original order, a tile of leaf slots that does
+// not fit in LDS beside the others makes every block of every tile scan all
+// rows (the histograms of all leaves of a deep level of a many-class problem
+// are far larger than the LDS of the whole chip). So here,
 // after the split of level l is chosen, the rows are moved by a stable
 // partition on the new leaf bit: rows whose bit is 0 first, then rows whose
 // bit is 1, each group in its previous order. Since the rows were already
