@@ -295,6 +295,18 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
                              int32_t precision, const void* parent_hist,
                              const cbh_split* parent_split, void* hist_out, void* stream);
 
+/* cbh_apply_split(level - 1, parent_split) followed by
+ * cbh_build_histograms_sub(level), with the leaf update done in the same pass
+ * over the rows as the row codes of the build where that pass runs (the
+ * lanes-over-features kernel with 2^(level-1) * max_bins <= 16384), else as
+ * a launch of its own before the build. prob->leaf must hold the bits of
+ * levels < level - 1 (the state after cbh_apply_split(level - 2)); on return
+ * it holds bit level - 1 too. Same arguments and results as
+ * cbh_build_histograms_sub. */
+int cbh_apply_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                                   int32_t precision, const void* parent_hist,
+                                   const cbh_split* parent_split, void* hist_out, void* stream);
+
 /* Score every candidate split of the level and keep the best (Sec. 3, first
  * phase). The paper gives no formula; the score is the gain of the
  * L2-regularised second-order objective: splitting every current leaf L by

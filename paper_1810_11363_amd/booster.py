@@ -306,15 +306,23 @@ class GpuBooster:
         ctx, st, prec = self.ctx, self.stream, self.precision
         if prec == cb.CBH_PREC_INT16:
             cb.cbh_quantize_gradients(ctx, pr, st)
+        # with subtraction in the original row order, each level's leaf bit is
+        # set by the next level's build, in its row-code pass
+        fuse = self.part is None and self.subtract
         for lvl in range(self.depth):
             if events is not None:
                 events[lvl][0].record(st)
-            self.build_level_histograms(pr, lvl)
+            if fuse and lvl > 0:
+                cb.cbh_apply_build_histograms_sub(ctx, pr, lvl, prec, self.hist_ptr(lvl - 1),
+                                                  self.split_ptr(lvl - 1), self.hist_ptr(lvl), st)
+            else:
+                self.build_level_histograms(pr, lvl)
             if events is not None:
                 events[lvl][1].record(st)
             cb.cbh_score_splits(ctx, pr, lvl, self.hist_ptr(lvl), prec, self.l2,
                                 self.split_ptr(lvl), None, st)
-            self.advance(pr, lvl)
+            if not fuse or lvl == self.depth - 1:
+                self.advance(pr, lvl)
         cb.cbh_update_approx(ctx, pr, self.hist_ptr(self.depth - 1), prec,
                              self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
                              self.leaf_counts if counts else None, st)

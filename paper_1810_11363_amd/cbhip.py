@@ -28,7 +28,7 @@ EXPORTS = [
     "cbh_select_borders", "cbh_uniform_borders",
     "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
-    "cbh_build_histograms_sub",
+    "cbh_build_histograms_sub", "cbh_apply_build_histograms_sub",
     "cbh_score_splits", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
     "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
@@ -84,6 +84,8 @@ def _load():
         "cbh_build_histograms": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp], C.c_int),
         "cbh_build_histograms_sub": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp, vp, vp],
                                      C.c_int),
+        "cbh_apply_build_histograms_sub": ([vp, C.POINTER(cbh_problem), i32, i32, vp, vp, vp,
+                                            vp], C.c_int),
         "cbh_score_splits": ([vp, C.POINTER(cbh_problem), i32, vp, i32, dbl, vp, vp, vp],
                              C.c_int),
         "cbh_apply_split": ([vp, C.POINTER(cbh_problem), i32, vp, vp], C.c_int),
@@ -262,6 +264,13 @@ def cbh_build_histograms_sub(ctx, prob: cbh_problem, level: int, precision: int,
     return _check(_lib.cbh_build_histograms_sub(ctx, C.byref(prob), level, precision,
                                                 _ptr(parent_hist), _ptr(parent_split),
                                                 _ptr(hist_out), _stream(stream)))
+
+
+def cbh_apply_build_histograms_sub(ctx, prob: cbh_problem, level: int, precision: int,
+                                   parent_hist, parent_split, hist_out, stream=None):
+    return _check(_lib.cbh_apply_build_histograms_sub(ctx, C.byref(prob), level, precision,
+                                                      _ptr(parent_hist), _ptr(parent_split),
+                                                      _ptr(hist_out), _stream(stream)))
 
 
 def cbh_score_splits(ctx, prob: cbh_problem, level: int, hist, precision: int, l2: float,

@@ -136,11 +136,14 @@ int validate_precision(const cbh_problem* p, int32_t precision);
 // kernel in subtraction mode.
 // Subtraction mode (parent != NULL): the call derives the smaller child of
 // every parent from `parent` and `parent_split` into `side` (2^(level-1)
-// bytes) before the build.
+// bytes) before the build; apply_parent: the leaf array does not hold the
+// parent level's bit yet and the call sets it first (fused into the row-code
+// pass where that pass runs).
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
                 const void* parent = nullptr, uint8_t* side = nullptr,
-                uint16_t* codes = nullptr, const cbh_split* parent_split = nullptr);
+                uint16_t* codes = nullptr, const cbh_split* parent_split = nullptr,
+                bool apply_parent = false);
 int64_t hist_code_bytes(const HistPlan& plan, int64_t n, bool sub);
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores,

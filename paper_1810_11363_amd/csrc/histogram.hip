@@ -403,16 +403,21 @@ __global__ __launch_bounds__(256) void sub_side_kernel(const void* __restrict__ 
 // subtraction with few parents): every block first derives the side of every
 // parent into LDS (block 0 also stores them for the merge), then writes
 // code[i] = p = leaf & (half - 1) for rows on the parent's accumulated side,
-// 0xffff otherwise.
-template <int PREC>
+// 0xffff otherwise. APPLY: the leaf array does not hold the parent level's
+// bit yet; the kernel takes it from the split feature's bin (as
+// cbh_apply_split does, overwriting the leaf when the parent is level 0)
+// and stores the updated leaf.
+template <int PREC, bool APPLY>
 __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__ parent,
                                                         const cbh_split* __restrict__ split,
                                                         int64_t half, int32_t F, int32_t B,
                                                         int32_t K, int32_t rmse,
-                                                        const uint16_t* __restrict__ leaf, int64_t n,
+                                                        uint16_t* __restrict__ leaf, int64_t n,
                                                         int64_t rows_per_block, uint32_t shift,
                                                         uint8_t* __restrict__ side,
-                                                        uint16_t* __restrict__ code) {
+                                                        uint16_t* __restrict__ code,
+                                                        const uint8_t* const* __restrict__ bins,
+                                                        const int64_t* __restrict__ seg) {
     extern __shared__ uint8_t sd[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int f = split->feature, k = split->border;
@@ -424,16 +429,36 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
         }
     }
     __syncthreads();
+    const bool has_split = f >= 0 && f < F;
+    const uint8_t* col = (APPLY && has_split) ? bins[f] : nullptr;
+    const int64_t st = (APPLY && has_split) ? seg_stride_of(seg, f) : 16;
     const uint32_t lmask = (uint32_t)half - 1u;
     const int64_t i0 = int64_t(blockIdx.x) * rows_per_block;
     const int64_t i1 = min(n, i0 + rows_per_block);
     // 8 rows per thread and step where the block's rows are 8-aligned
-    const bool vec = ((reinterpret_cast<uintptr_t>(leaf) | reinterpret_cast<uintptr_t>(code)) & 15) == 0;
+    const bool vec = ((reinterpret_cast<uintptr_t>(leaf) | reinterpret_cast<uintptr_t>(code) |
+                       (APPLY ? reinterpret_cast<uintptr_t>(col) & 7 : 0)) & 15) == 0;
     int64_t i = i0;
     if (vec) {
         const int64_t i8 = i0 + ((i1 - i0) & ~int64_t(7));
         for (int64_t j = i0 + 8 * int64_t(threadIdx.x); j < i8; j += 8 * 256) {
-            const uint4 lv = *reinterpret_cast<const uint4*>(leaf + j);
+            uint4 lv = *reinterpret_cast<const uint4*>(leaf + j);
+            if constexpr (APPLY) {
+                // level 0's bit overwrites what the previous tree left
+                if (shift == 0) lv = make_uint4(0u, 0u, 0u, 0u);
+                // the 8 rows' bins: 8 bytes of one 16-row segment
+                uint2 bw = make_uint2(0u, 0u);
+                if (col) bw = *reinterpret_cast<const uint2*>(seg_ptr(col, st, j));
+                const uint32_t bb[2] = {bw.x, bw.y};
+                uint32_t lw2[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const uint32_t bit = col && (int)((bb[r >> 2] >> (8 * (r & 3))) & 255u) > k;
+                    lw2[r >> 1] |= (bit << shift) << (16 * (r & 1));
+                }
+                lv = make_uint4(lw2[0], lw2[1], lw2[2], lw2[3]);
+                *reinterpret_cast<uint4*>(leaf + j) = lv;
+            }
             const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w};
             uint32_t cw[4];
 #pragma unroll
@@ -453,7 +478,12 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
         i = i8;
     }
     for (int64_t j = i + threadIdx.x; j < i1; j += 256) {
-        const uint32_t v = leaf[j];
+        uint32_t v = leaf[j];
+        if constexpr (APPLY) {
+            if (shift == 0) v = 0u;
+            if (col && (int)*seg_ptr(col, st, j) > k) v |= 1u << shift;
+            leaf[j] = (uint16_t)v;
+        }
         const uint32_t pp = v & lmask;
         code[j] = (uint16_t)((((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu);
     }
@@ -589,48 +619,61 @@ static void launch_hist_prec(const HistArgs& a, const HistPlan& plan, int max_ld
 
 template <int PREC>
 static void launch_side_code(const void* parent, const cbh_split* split, int64_t half, int32_t F,
-                             int32_t B, int32_t K, int32_t rmse, const uint16_t* leaf, int64_t n,
+                             int32_t B, int32_t K, int32_t rmse, uint16_t* leaf, int64_t n,
                              uint32_t shift, uint8_t* side, uint16_t* codes, int num_cus,
-                             hipStream_t s) {
+                             hipStream_t s, const cbh_problem* apply) {
     const int64_t rpb = std::max<int64_t>(8192, align_up((n + num_cus - 1) / num_cus, 8));
     const unsigned grid = (unsigned)((n + rpb - 1) / rpb);
-    side_code_kernel<PREC><<<grid, 256, (size_t)half, s>>>(parent, split, half, F, B, K, rmse, leaf,
-                                                           n, rpb, shift, side, codes);
+    if (apply)
+        side_code_kernel<PREC, true><<<grid, 256, (size_t)half, s>>>(
+            parent, split, half, F, B, K, rmse, leaf, n, rpb, shift, side, codes, apply->bins,
+            apply->seg_stride);
+    else
+        side_code_kernel<PREC, false><<<grid, 256, (size_t)half, s>>>(
+            parent, split, half, F, B, K, rmse, leaf, n, rpb, shift, side, codes, nullptr,
+            nullptr);
 }
 
 int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t precision,
                 const HistPlan& plan, void* hist_out, void* partials, hipStream_t s,
                 const void* parent, uint8_t* side, uint16_t* codes,
-                const cbh_split* parent_split) {
+                const cbh_split* parent_split, bool apply_parent) {
     HistArgs a;
     a.rowcode = p->leaf;
     if (parent) {
         const int64_t half = int64_t(1) << (level - 1);
         const int rmse = p->loss == CBH_LOSS_RMSE;
+        const bool fused = plan.kind == 1 && half * p->max_bins <= 16384;
+        if (apply_parent && !fused) {
+            // the parent level's leaf bit first, as cbh_apply_split
+            const int rc = launch_apply(ctx, p, level - 1, parent_split, s);
+            if (rc) return rc;
+        }
         if (plan.kind == 1) {
             if (!codes) {
                 set_error("internal: no row-code buffer for a build by subtraction");
                 return CBH_EINVAL;
             }
             const uint32_t shift = (uint32_t)(level - 1);
-            if (half * p->max_bins <= 16384) {
-                // few parents: sides and codes in one launch
+            if (fused) {
+                // few parents: sides and codes (and the parent's leaf bit) in one launch
+                const cbh_problem* ap = apply_parent ? p : nullptr;
                 switch (precision) {
                     case CBH_PREC_FP32:
                         launch_side_code<CBH_PREC_FP32>(parent, parent_split, half, p->n_features,
                                                         p->max_bins, p->K, rmse, p->leaf, p->n,
-                                                        shift, side, codes, ctx->num_cus, s);
+                                                        shift, side, codes, ctx->num_cus, s, ap);
                         break;
                     case CBH_PREC_TWOFLOAT:
                         launch_side_code<CBH_PREC_TWOFLOAT>(
                             parent, parent_split, half, p->n_features, p->max_bins, p->K, rmse,
-                            p->leaf, p->n, shift, side, codes, ctx->num_cus, s);
+                            p->leaf, p->n, shift, side, codes, ctx->num_cus, s, ap);
                         break;
                     default:
                         launch_side_code<CBH_PREC_INT16>(parent, parent_split, half,
                                                          p->n_features, p->max_bins, p->K, rmse,
                                                          p->leaf, p->n, shift, side, codes,
-                                                         ctx->num_cus, s);
+                                                         ctx->num_cus, s, ap);
                         break;
                 }
                 CBH_LAUNCHED();
@@ -845,10 +888,9 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
                        (hipStream_t)stream);
 }
 
-int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
-                             int32_t precision, const void* parent_hist,
-                             const cbh_split* parent_split, void* hist_out, void* stream) {
-    clear_error();
+static int build_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, int32_t precision,
+                     const void* parent_hist, const cbh_split* parent_split, void* hist_out,
+                     void* stream, bool apply_parent) {
     CBH_ARG(ctx != nullptr, "ctx is NULL");
     int rc = validate_problem(prob);
     if (rc) return rc;
@@ -877,7 +919,23 @@ int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t leve
         code_bytes ? (uint16_t*)((uint8_t*)ctx->ws + part_bytes + align_up(half, 256)) : nullptr;
     hipStream_t s = (hipStream_t)stream;
     return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws, s, parent_hist, side,
-                       codes, parent_split);
+                       codes, parent_split, apply_parent);
+}
+
+int cbh_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                             int32_t precision, const void* parent_hist,
+                             const cbh_split* parent_split, void* hist_out, void* stream) {
+    clear_error();
+    return build_sub(ctx, prob, level, precision, parent_hist, parent_split, hist_out, stream,
+                     false);
+}
+
+int cbh_apply_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                                   int32_t precision, const void* parent_hist,
+                                   const cbh_split* parent_split, void* hist_out, void* stream) {
+    clear_error();
+    return build_sub(ctx, prob, level, precision, parent_hist, parent_split, hist_out, stream,
+                     true);
 }
 
 }  // extern "C"

@@ -672,30 +672,31 @@ __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int 
 
 // Whole-block scoring of feature f over all leaves and classes; writes the
 // per-border scores (optional) and the feature's best/second-best. Needs a
-// block of 256 threads.
-template <int PREC>
+// block of 64 NW threads (NW >= 4); wave w takes the (leaf, class) rows
+// w, w + NW, ..., and the waves' partial scores are added in wave order.
+template <int PREC, int NW = 4>
 __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, float* scores,
                               FeatBest* out) {
-    __shared__ float part[4][256];
-    __shared__ float rs1[4], rs2[4];
-    __shared__ int ri1[4];
+    __shared__ float part[NW][256];
+    __shared__ float rs1[NW], rs2[NW];
+    __shared__ int ri1[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kmax = min(n_bins_f, a.B) - 1;  // candidates k < kmax
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if (kmax > 0) {
         const int items = L * a.K;
-        for (int it = wave; it < items; it += 4) row_terms<PREC>(a, it / a.K, f, it % a.K, lane,
-                                                                  kmax, acc);
+        for (int it = wave; it < items; it += NW) row_terms<PREC>(a, it / a.K, f, it % a.K, lane,
+                                                                   kmax, acc);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) part[wave][4 * lane + j] = acc[j];
     __syncthreads();
-    const int k = threadIdx.x;  // thread k owns border k
+    const int k = threadIdx.x;  // thread k < 256 owns border k
     float s = -INFINITY;
     if (k < kmax) {
         s = part[0][k] + part[1][k];
-        s += part[2][k];
-        s += part[3][k];
+#pragma unroll
+        for (int w = 2; w < NW; ++w) s += part[w][k];
         if (s != s) s = -INFINITY;
     }
     if (scores && k < a.B - 1) scores[int64_t(f) * (a.B - 1) + k] = s;
@@ -714,6 +715,7 @@ __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, flo
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // borders live in the first four waves only
         float b1 = rs1[0], b2 = rs2[0];
         int j = ri1[0];
         for (int w = 1; w < 4; ++w) top2_merge(b1, j, b2, rs1[w], ri1[w], rs2[w]);
@@ -721,12 +723,13 @@ __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, flo
     }
 }
 
-// Reduce F per-feature winners (block of 256) to the level's split.
+// Reduce F per-feature winners (one block, its first 256 threads) to the
+// level's split.
 __device__ inline void argmax_features(const FeatBest* __restrict__ fb, int F, int Bm1,
                                        cbh_split* __restrict__ out) {
     float s1 = -INFINITY, s2 = -INFINITY;
     int i1 = -1;
-    for (int f = threadIdx.x; f < F; f += 256) {
+    for (int f = threadIdx.x; f < F && threadIdx.x < 256; f += 256) {
         const FeatBest e = fb[f];
         top2_merge(s1, i1, s2, e.s1, e.k1 >= 0 ? f * Bm1 + e.k1 : -1, e.s2);
     }
@@ -738,7 +741,7 @@ __device__ inline void argmax_features(const FeatBest* __restrict__ fb, int F, i
         const int j1 = __shfl_xor(i1, d, 64);
         top2_merge(s1, i1, s2, t1, j1, t2);
     }
-    if (lane == 0) {
+    if (lane == 0 && wave < 4) {
         rs1[wave] = s1;
         rs2[wave] = s2;
         ri1[wave] = i1;

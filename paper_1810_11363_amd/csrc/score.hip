@@ -23,14 +23,14 @@
 
 namespace cbh {
 
+constexpr int kScoreWaves = 16;   // (leaf, class) rows in flight per feature
+
 template <int PREC>
-__global__ __launch_bounds__(256) void score_split_kernel(ScoreRow r, const int32_t* n_bins,
-                                                          int32_t L, float* scores,
-                                                          FeatBest* fbest,
-                                                          uint32_t* __restrict__ counter,
-                                                          cbh_split* __restrict__ out) {
+__global__ __launch_bounds__(64 * kScoreWaves) void score_split_kernel(
+    ScoreRow r, const int32_t* n_bins, int32_t L, float* scores, FeatBest* fbest,
+    uint32_t* __restrict__ counter, cbh_split* __restrict__ out) {
     const int f = blockIdx.x;
-    score_feature<PREC>(r, L, f, n_bins[f], scores, &fbest[f]);
+    score_feature<PREC, kScoreWaves>(r, L, f, n_bins[f], scores, &fbest[f]);
     __shared__ uint32_t last;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -67,15 +67,15 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     uint32_t* counter = ctx->d_flags + 1;
     switch (precision) {
         case CBH_PREC_FP32:
-            score_split_kernel<CBH_PREC_FP32><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb,
+            score_split_kernel<CBH_PREC_FP32><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores, fb,
                                                                   counter, best);
             break;
         case CBH_PREC_TWOFLOAT:
-            score_split_kernel<CBH_PREC_TWOFLOAT><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores,
+            score_split_kernel<CBH_PREC_TWOFLOAT><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores,
                                                                       fb, counter, best);
             break;
         default:
-            score_split_kernel<CBH_PREC_INT16><<<r.F, 256, 0, s>>>(r, p->n_bins, L, scores, fb,
+            score_split_kernel<CBH_PREC_INT16><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores, fb,
                                                                    counter, best);
             break;
     }

@@ -392,6 +392,58 @@ def test_subtraction_kernels_vs_oracle(cb, ctx, kcfg, prec):
     assert np.array_equal(got[..., 1::2], want[..., 1::2])
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("kcfg,level,B", [((1, 32), 1, 64), ((1, 32), 3, 64), ((1, 8), 5, 64),
+                                          ((0, 0), 1, 64), ((0, 0), 3, 64), ((1, 4), 8, 255)])
+def test_apply_fused_build_matches_separate(cb, ctx, kcfg, level, B, prec):
+    """cbh_apply_build_histograms_sub (the parent level's leaf bit set in the
+    build's row-code pass, or by its own launch where that pass does not run)
+    equals cbh_apply_split followed by cbh_build_histograms_sub: the same
+    leaf indices and the same histogram bytes."""
+    n, F, loss = 30011, 9, 0
+    nb, bins, leaf, gg, hh, label = _random_level(17 + level, n, F, B, 1, loss, level - 1)
+    if level == 1:
+        # what a previous, deeper tree left: level 0's update must overwrite it
+        leaf = np.random.default_rng(5).integers(0, 512, n).astype(np.uint16)
+    pd = [_device_problem(cb, n, F, B, 1, loss, level + 1, nb, bins, leaf, gg, hh, label)
+          for _ in range(2)]
+    probs = [_tiled_problem(cb, ctx, p, dev, n, F) for p, dev in pd]
+    esz = 8
+    parent = torch.empty((1 << (level - 1)) * F * B * 2 * esz, dtype=torch.uint8, device=gu.dev())
+    child = [torch.empty((1 << level) * F * B * 2 * esz, dtype=torch.uint8, device=gu.dev())
+             for _ in range(2)]
+    best = torch.zeros((level + 1, 4), dtype=torch.int32, device=gu.dev())
+    sp = best.data_ptr() + 16 * (level - 1)
+    kernel, w = kcfg
+    cb.cbh_set_hist_knobs(ctx, 160 * 1024, 512, 2048, 100, 8, 8, kernel, w)
+    try:
+        if prec == 2:
+            for p in probs:
+                cb.cbh_quantize_gradients(ctx, p)
+        cb.cbh_build_histograms(ctx, probs[0], level - 1, prec, parent)
+        cb.cbh_score_splits(ctx, probs[0], level - 1, parent, prec, 3.0, sp)
+        cb.cbh_apply_split(ctx, probs[0], level - 1, sp)
+        cb.cbh_build_histograms_sub(ctx, probs[0], level, prec, parent, sp, child[0])
+        cb.cbh_apply_build_histograms_sub(ctx, probs[1], level, prec, parent, sp, child[1])
+        cb.cbh_sync(ctx)
+    finally:
+        cb.cbh_set_hist_knobs(ctx, 0)
+    assert torch.equal(pd[0][1]["leaf"], pd[1][1]["leaf"])
+    if prec == 2:
+        assert torch.equal(child[0], child[1])
+        return
+    # FP64 LDS sums may round differently from run to run: values within the
+    # two-float tolerance, counts exact
+    L = 1 << level
+    a = gu.hist_to_f64(child[0], L, F, B, 1, prec, True)
+    b = gu.hist_to_f64(child[1], L, F, B, 1, prec, True)
+    assert np.array_equal(a[..., 1], b[..., 1])
+    leaf2 = pd[0][1]["leaf"].cpu().numpy()
+    assert int(leaf2.max()) < L
+    mag = oracle.histogram(bins, np.abs(gg).astype(np.float64), hh.astype(np.float64), leaf2, L, B)
+    assert gu.normalized_err(a, b, mag) <= gu.TWOFLOAT_TOL
+
+
 def test_int16_histogram_deterministic(cb, ctx):
     n, F, B, K, loss, level = 70001, 6, 128, 1, 1, 3
     nb, bins, leaf, gg, hh, label = _random_level(3, n, F, B, K, loss, level)
