@@ -286,7 +286,7 @@ def time_form(bst, name, args, rmse):
         t_tune = time.perf_counter()
         if prec == 2:
             cb.cbh_quantize_gradients(bst.ctx, bst.probs[0], stream)
-        cb.cbh_autotune(bst.ctx, bst.probs[0], prec, bst.subtract, None, stream)
+        cb.cbh_autotune(bst.ctx, bst.probs[0], prec, bst.subtract, args.autotune_save, stream)
         t_tune = time.perf_counter() - t_tune
     elif args.autotune != "off":
         cb.cbh_autotune_load(bst.ctx, args.autotune)
@@ -616,6 +616,9 @@ def main():
     ap.add_argument("--autotune", default=None,
                     help="'run' tunes launch plans before each timed region, 'off' keeps "
                          "the defaults, anything else is a cache file to load")
+    ap.add_argument("--autotune-save", default=None, metavar="PATH",
+                    help="with --autotune run: write the tuned plans of every form to PATH "
+                         "(JSON, loadable with --autotune PATH)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five times (reference "
                          "for hardware byte counters) and exit")

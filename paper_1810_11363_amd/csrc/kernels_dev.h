@@ -953,14 +953,25 @@ struct LpfSeg {
 // MODE 1: all slots of a direct build in one tile: slot = row code (the leaf).
 // MODE 2: subtraction and/or several slot tiles: slot = row code - first slot
 //         of the tile, rows outside the tile (or with code 0xffff) skipped.
-// One block: rows [r0, r1) (r0 a multiple of 16), feature group fg (W
-// features), slots [s0, s0 + ns) (ns <= 64). The block's partial histogram
-// `part` is [slot - part_slot0][F][B][wpc] words, this class at word coff of
-// each cell; lds holds the block's dynamic LDS.
+// One block's tile, in three phases (lpf_block runs them in turn; a caller
+// may accumulate several row ranges, in different modes, into one tile):
+//   lpf_zero        clears the tile of ns slots;
+//   lpf_accumulate  adds rows [r0, r1) (r0 a multiple of 16) of feature
+//                   group fg (W features) for slots [s0, s0 + ns) (ns <= 64);
+//   lpf_flush       writes the tile to the block's partial histogram `part`,
+//                   [slot - part_slot0][F][B][wpc] words, this class at word
+//                   coff of each cell.
+// lds holds the block's dynamic LDS; the phases are separated by barriers.
+template <int PREC, int W>
+__device__ __forceinline__ void lpf_zero(int B, uint32_t ns, uint32_t* lds) {
+    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+    const uint32_t tile_words = ns * (uint32_t)B * lpf_record_bytes(W, CS) / 4;
+    for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
+}
+
 template <int PREC, int RM, int W, int MODE>
-__device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
-                                          uint32_t s0, uint32_t ns, uint32_t* part,
-                                          uint32_t part_slot0, uint32_t* lds) {
+__device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
+                                               uint32_t s0, uint32_t ns, uint32_t* lds) {
     constexpr uint32_t CS = lpf_cell_bytes<PREC>();
     constexpr int RG = 64 / W;                  // segments per wave step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -973,9 +984,6 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t
     const uint8_t* col = a.bins[f];
     const int64_t sstride = a.seg ? a.seg[f] : 16;
     const uint32_t slot_bytes = (uint32_t)a.B * lpf_record_bytes(W, CS);
-    const uint32_t tile_words = ns * slot_bytes / 4;
-    for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
-    __syncthreads();
     char* tile = reinterpret_cast<char*>(lds);
     const int64_t t_full = r1 >> 4;            // segments before this one are full
     const uint32_t lane_off = (uint32_t)fl * 8u;
@@ -1050,7 +1058,16 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t
             }
         }
     }
-    __syncthreads();
+}
+
+template <int PREC, int RM, int W>
+__device__ __forceinline__ void lpf_flush(const LpfBlock& a, int fg, uint32_t s0, uint32_t ns,
+                                          uint32_t* part, uint32_t part_slot0,
+                                          const uint32_t* lds) {
+    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+    const int f0 = fg * W;
+    const int nf = min(W, a.F - f0);
+    const char* tile = reinterpret_cast<const char*>(lds);
     // write the tile in the partial's [L][F][B][wpc] order; consecutive threads
     // take consecutive features of one (slot, bin), so the LDS reads are
     // conflict-free and every thread writes one whole cell
@@ -1089,6 +1106,17 @@ __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t
             }
         }
     }
+}
+
+template <int PREC, int RM, int W, int MODE>
+__device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
+                                          uint32_t s0, uint32_t ns, uint32_t* part,
+                                          uint32_t part_slot0, uint32_t* lds) {
+    lpf_zero<PREC, W>(a.B, ns, lds);
+    __syncthreads();
+    lpf_accumulate<PREC, RM, W, MODE>(a, r0, r1, fg, s0, ns, lds);
+    __syncthreads();
+    lpf_flush<PREC, RM, W>(a, fg, s0, ns, part, part_slot0, lds);
 }
 
 }  // namespace cbh

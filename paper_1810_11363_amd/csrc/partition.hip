@@ -407,8 +407,25 @@ __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
     b.B = a.B;
     b.wpc = a.wpc;
     b.coff = c * (a.wpc / a.K);
-    lpf_block<PREC, RM, W, 2>(b, sa * 16, sb * 16, fg, s0, ns,
-                              a.partials + gc * (int64_t(a.lt) * a.F * a.B * a.wpc), s0, lds);
+    lpf_zero<PREC, W>(a.B, ns, lds);
+    __syncthreads();
+    // With one slot per tile, every row of a segment inside the tile's range
+    // is in the slot: no per-row code is needed there (mode 0). Only the
+    // tile's first and last segments can hold rows of neighbouring leaves (or
+    // padding rows): mode 2 checks their codes.
+    const bool head = ns == 1 && j == 0 && (pa & 15) != 0;
+    const bool tail = ns == 1 && sb == ((pb + 15) >> 4) && (pb & 15) != 0;
+    const int64_t ia = sa + (head ? 1 : 0), ib = sb - (tail ? 1 : 0);
+    if (ns == 1 && ia < ib) {
+        if (head) lpf_accumulate<PREC, RM, W, 2>(b, sa * 16, ia * 16, fg, s0, ns, lds);
+        lpf_accumulate<PREC, RM, W, 0>(b, ia * 16, ib * 16, fg, s0, ns, lds);
+        if (tail) lpf_accumulate<PREC, RM, W, 2>(b, ib * 16, sb * 16, fg, s0, ns, lds);
+    } else {
+        lpf_accumulate<PREC, RM, W, 2>(b, sa * 16, sb * 16, fg, s0, ns, lds);
+    }
+    __syncthreads();
+    lpf_flush<PREC, RM, W>(b, fg, s0, ns, a.partials + gc * (int64_t(a.lt) * a.F * a.B * a.wpc),
+                           s0, lds);
 }
 
 // Output cell (leaf, feature, bin): the sum of its slot tile's chunks.
@@ -468,20 +485,21 @@ static void launch_part_hist(const PartHist& a, int W, unsigned grid, size_t lds
 // Plan of a build over rows in leaf order: a slot tile reads only its own
 // rows, so more tiles cost no re-reads; the widest lane group whose tile of
 // one slot fits the LDS (fewest feature groups, so the statistics are read
-// fewest times), as many slots per tile as fit (at most 64), and chunks of
-// at least min_rows rows sized so that the blocks of the whole level reach
-// target_blocks.
+// fewest times), as many slots per tile as the LDS budget holds (at least
+// one, at most 64; one slot lets the block skip the row codes inside its
+// range), and chunks of at least min_rows rows sized so that the blocks of
+// the whole level reach target_blocks.
 static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                           int32_t L, int32_t precision, int max_lds) {
     HistPlan p;
     p.kind = 1;
     p.words_per_cell = words_per_cell(precision, K);
     const uint32_t cs = precision == CBH_PREC_INT16 ? 8 : 16;
-    const int64_t budget = max_lds;
     int32_t W = kn.lpf_w > 0 ? std::min(kn.lpf_w, 32) : 32;
-    while (W > 4 && int64_t(B) * lpf_record_bytes(W, cs) > budget) W /= 2;
+    while (W > 4 && int64_t(B) * lpf_record_bytes(W, cs) > max_lds) W /= 2;
     p.fb = W;
     const int64_t slot_bytes = int64_t(B) * lpf_record_bytes(W, cs);
+    const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
     p.lt = (int32_t)std::max<int64_t>(1, std::min<int64_t>({int64_t(L), 64, budget / slot_bytes}));
     p.n_ltiles = (L + p.lt - 1) / p.lt;
     p.n_fgroups = (F + W - 1) / W;
