@@ -367,8 +367,8 @@ def time_form(bst, name, args, rmse):
         "G_row_features_per_s": round(rf_per_tree / sec_per_tree / 1e9, 3),
         "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
         "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
-        "hist_subtraction": bool(bst.subtract) and bst.part is None,
-        "rows_in_leaf_order": bst.part is not None,
+        "hist_subtraction": bool(bst.subtract) and not bst.use_part,
+        "rows_in_leaf_order": bool(bst.use_part),
         "graph_replay": not args.no_graph,
         "hist_timing": timing,
         "ms_per_tree_while_timing_builds": (round(stamped_tree_ms, 4)
@@ -610,7 +610,8 @@ def main():
     ap.add_argument("--hist-trees", type=int, default=None,
                     help="trees replayed from graphs with event nodes around every build")
     ap.add_argument("--partition", choices=["auto", "on", "off"], default="auto",
-                    help="keep rows in leaf order during a tree (auto: for K > 1)")
+                    help="keep rows in leaf order during a tree (auto: for K > 1, and for depth >= 8 "
+                         "in the float forms)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle leg (CPU timing and error vs FP64)")
     ap.add_argument("--autotune", default=None,

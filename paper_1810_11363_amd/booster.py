@@ -74,10 +74,12 @@ class GpuBooster:
         self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
         # rows kept in leaf order during a tree (levels >= 1 read each row once
         # whatever the number of leaves, at the cost of moving the rows after
-        # every split): by default for several classes, whose slot tiles
-        # outgrow the LDS soonest; one class keeps subtraction
-        self.partition = int(K) > 1 if partition is None else bool(partition)
+        # every split). None: for several classes, and for deep trees (depth
+        # >= 8) in the float forms; the int16 form of one class keeps
+        # subtraction in the original order, which is cheaper there
+        self.partition = partition if partition is None else bool(partition)
         self.part = None
+        self.use_part = False
         self.x_num = np.ascontiguousarray(x_num, dtype=np.float32)
         self.cat = np.ascontiguousarray(cat, dtype=np.int32)
         self.label_h = np.ascontiguousarray(label, dtype=np.float32)
@@ -219,9 +221,18 @@ class GpuBooster:
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
         self._alloc_hists()
         self.probs = [self.problem(r) for r in range(self.s)]
-        if self.partition:
+        if self.partition or (self.partition is None and (self.K > 1 or self.depth >= 8)):
             self.part = cb.cbh_part_create(self.ctx, self.probs[0])
+        self._choose_order()
         return self
+
+    def _choose_order(self):
+        if self.part is None:
+            self.use_part = False
+        elif self.partition is not None:
+            self.use_part = bool(self.partition)
+        else:
+            self.use_part = self.K > 1 or self.precision != cb.CBH_PREC_INT16
 
     def _alloc_hists(self):
         hb = max(256, self._hist_bytes(self.depth - 1))
@@ -234,6 +245,7 @@ class GpuBooster:
         self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
         self.graphs = []      # captured trees point at the old buffers
         self._alloc_hists()
+        self._choose_order()
 
     def problem(self, r: int) -> cb.cbh_problem:
         p = cb.cbh_problem()
@@ -281,7 +293,7 @@ class GpuBooster:
 
     def build_level_histograms(self, pr, level: int):
         ctx, st, prec = self.ctx, self.stream, self.precision
-        if level > 0 and self.part is not None:
+        if level > 0 and self.use_part:
             cb.cbh_part_build_histograms(ctx, self.part, pr, level, prec, self.hist_ptr(level), st)
         elif level > 0 and self.subtract:
             cb.cbh_build_histograms_sub(ctx, pr, level, prec, self.hist_ptr(level - 1),
@@ -292,7 +304,7 @@ class GpuBooster:
     def advance(self, pr, level: int):
         """Route the rows by the split of `level`: the leaf bit, or the move
         into leaf order (which writes the leaf indices at the last level)."""
-        if self.part is not None:
+        if self.use_part:
             cb.cbh_part_split(self.ctx, self.part, pr, level, self.precision,
                               self.split_ptr(level), self.stream)
         else:
@@ -308,7 +320,7 @@ class GpuBooster:
             cb.cbh_quantize_gradients(ctx, pr, st)
         # with subtraction in the original row order, each level's leaf bit is
         # set by the next level's build, in its row-code pass
-        fuse = self.part is None and self.subtract
+        fuse = not self.use_part and self.subtract
         for lvl in range(self.depth):
             if events is not None:
                 events[lvl][0].record(st)

@@ -36,7 +36,6 @@ constexpr int kPartThreads = 256;
 constexpr int64_t kPartRows = 1024;                // positions per partition block
 constexpr int kPartSegs = 64;                      // 16-row segments per partition block
 constexpr int kPartFeat = 16;                      // features staged per LDS round
-constexpr int kPartRegion = 1056;                  // bytes per (run, feature) staging region
 constexpr int kPartLdsLeaves = 4096;               // leaf counters kept in LDS up to this L
 
 }  // namespace cbh
@@ -194,18 +193,26 @@ struct PartMove {
 };
 
 // The stable partition itself, one block per kPartRows positions:
-//   1. wave 0 (lane = 16-row segment) finds the rows' bits and destinations;
+//   1. wave 0 (lane = 16-row segment) finds the rows' bits and destinations,
+//      and for each destination run the source row of every destination
+//      (inv);
 //   2. all threads move row ids, leaf indices and statistics (4 rows each);
 //   3. the bins, kPartFeat features per round: consecutive threads read
-//      consecutive 16-byte (segment, feature) pieces, i.e. each segment's
-//      features contiguously; the bytes are staged in LDS per destination run
-//      (the block's zero rows go to [Zb, Zb + nzb), its one rows to
-//      [O0, O0 + nob)) from the 16-byte segment below the run's start; then
-//      every destination segment is written, features fastest: whole
+//      consecutive 16-byte (segment, feature) pieces (each segment's features
+//      contiguously) and store them unchanged in LDS, one row of bytes per
+//      feature (rows padded so that different features fall on different
+//      banks; the next round's pieces are loaded while this one is written).
+//      Then every destination segment of the block's two runs (its zero rows
+//      go to [Zb, Zb + nzb), its one rows to [O0, O0 + nob)) is gathered
+//      byte by byte through inv and written, features fastest: whole
 //      segments as one 16-byte store, the partial ones at the run ends byte
 //      by byte (the neighbouring block owns their other bytes).
+constexpr int kPartSrcRow = kPartRows + 16;   // bytes per staged feature (65 x 16)
+constexpr int kPartRun = kPartRows + 32;      // destination slots per run
+
 __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) {
-    __shared__ __align__(16) uint8_t stage[2 * kPartFeat * kPartRegion];
+    __shared__ __align__(16) uint8_t stage[kPartFeat * kPartSrcRow];
+    __shared__ uint16_t inv[2][kPartRun];      // source row of destination base + i
     __shared__ int32_t rel[kPartRows];        // destination - base of its run
     __shared__ uint32_t segbits[kPartSegs], segvalid[kPartSegs];
     __shared__ uint32_t nzb_sh;
@@ -244,7 +251,9 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
             const int64_t zb = Zb + zt + __popc(zmask & ((1u << j) - 1u));
             const int r = (bits >> j) & 1u;
             const int64_t d = r ? NZ + (p0 + j - zb) : zb;
-            rel[16 * sg + j] = (int32_t)(d - base[r]);
+            const int32_t rl = (int32_t)(d - base[r]);
+            rel[16 * sg + j] = rl;
+            inv[r][rl] = (uint16_t)(16 * sg + j);
         }
     }
     __syncthreads();
@@ -272,33 +281,43 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
                            nob ? ((run1[1] + 15) >> 4) - s0[1] : 0};
     const int64_t dstride = 16 * int64_t(m.F);
     const int64_t seg0 = P0 >> 4;
-    for (int f0 = 0; f0 < m.F; f0 += kPartFeat) {
+    // thread t owns pieces c = t + 256 q (q < 4) of a round: segment c / 16,
+    // feature f0 + c % 16
+    constexpr int kPieces = kPartSegs * kPartFeat / kPartThreads;
+    uint4 w[kPieces];
+    auto load_round = [&](int f0) {
         const int nfe = min(kPartFeat, m.F - f0);
-        for (int c = threadIdx.x; c < kPartSegs * kPartFeat; c += kPartThreads) {
+#pragma unroll
+        for (int q = 0; q < kPieces; ++q) {
+            const int c = threadIdx.x + kPartThreads * q;
             const int sg = c / kPartFeat, fi = c % kPartFeat;
             const uint32_t valid = segvalid[sg];
+            w[q] = make_uint4(0u, 0u, 0u, 0u);
             if (fi >= nfe || !valid) continue;
             const int f = f0 + fi;
             const uint8_t* src = m.src_cols[f] + (seg0 + sg) * seg_stride_of(m.src_seg, f);
-            uint32_t w[4];
             if (valid == 0xffffu && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
-                const uint4 v = *reinterpret_cast<const uint4*>(src);
-                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+                w[q] = *reinterpret_cast<const uint4*>(src);
             } else {
-                w[0] = w[1] = w[2] = w[3] = 0u;
+                uint32_t t[4] = {0u, 0u, 0u, 0u};
                 for (int j = 0; j < 16; ++j)
-                    if ((valid >> j) & 1u) w[j >> 2] |= (uint32_t)src[j] << (8 * (j & 3));
-            }
-            const uint32_t bits = segbits[sg];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (!((valid >> j) & 1u)) continue;
-                const int r = (bits >> j) & 1u;
-                stage[(r * kPartFeat + fi) * kPartRegion + rel[16 * sg + j]] =
-                    (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+                    if ((valid >> j) & 1u) t[j >> 2] |= (uint32_t)src[j] << (8 * (j & 3));
+                w[q] = make_uint4(t[0], t[1], t[2], t[3]);
             }
         }
+    };
+    load_round(0);
+    for (int f0 = 0; f0 < m.F; f0 += kPartFeat) {
+        const int nfe = min(kPartFeat, m.F - f0);
+#pragma unroll
+        for (int q = 0; q < kPieces; ++q) {
+            const int c = threadIdx.x + kPartThreads * q;
+            const int sg = c / kPartFeat, fi = c % kPartFeat;
+            if (fi >= nfe || !segvalid[sg]) continue;
+            *reinterpret_cast<uint4*>(stage + fi * kPartSrcRow + 16 * sg) = w[q];
+        }
         __syncthreads();
+        if (f0 + kPartFeat < m.F) load_round(f0 + kPartFeat);
         const int64_t nseg = ns[0] + ns[1];
         for (int64_t it = threadIdx.x; it < nseg * nfe; it += kPartThreads) {
             const int fi = (int)(it % nfe);
@@ -307,12 +326,17 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
             const int64_t s = s0[r] + (r ? q - ns[0] : q);
             const int64_t lo = max(run0[r], 16 * s), hi = min(run1[r], 16 * s + 16);
             if (lo >= hi) continue;
-            const uint8_t* from = stage + (r * kPartFeat + fi) * kPartRegion + (16 * s - base[r]);
+            const uint8_t* srow = stage + fi * kPartSrcRow;
+            const uint16_t* iv = inv[r] + (16 * s - base[r]);
             uint8_t* to = m.dst_bins + s * dstride + 16 * int64_t(f0 + fi);
             if (lo == 16 * s && hi == 16 * s + 16) {
-                *reinterpret_cast<uint4*>(to) = *reinterpret_cast<const uint4*>(from);
+                uint32_t t[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int p = 0; p < 16; ++p)
+                    t[p >> 2] |= (uint32_t)srow[iv[p]] << (8 * (p & 3));
+                *reinterpret_cast<uint4*>(to) = make_uint4(t[0], t[1], t[2], t[3]);
             } else {
-                for (int64_t p = lo; p < hi; ++p) to[p - 16 * s] = from[p - 16 * s];
+                for (int64_t p = lo; p < hi; ++p) to[p - 16 * s] = srow[iv[p - 16 * s]];
             }
         }
         __syncthreads();

@@ -98,7 +98,7 @@ def _lockstep_tree(cb, bst, t, stats):
         want_leaf = leaf.copy()
         if f >= 0:
             oracle.apply_split(bins[f], k, lvl, want_leaf)
-        if bst.part is None or lvl == bst.depth - 1:
+        if not bst.use_part or lvl == bst.depth - 1:
             assert np.array_equal(bst.leaf.cpu().numpy(), want_leaf)
         leaf = want_leaf
     a0 = bst.approx.cpu().numpy()
