@@ -235,8 +235,10 @@ def snapshot_tree(bst, t, rng, n_feat=4):
 def oracle_error(snap):
     """Largest error of the snapshot's histograms against the FP64 oracle,
     normalised by the sum of magnitudes of each bin's terms; for int16 codes
-    also the largest g-sum error over its quantisation bound n_bin * s_g / 2
-    (each code rounds g to the nearest multiple of s_g), which must be <= 1."""
+    also the largest g-sum error over its quantisation bound
+    n_bin * s_g * (1/2 + 2^-9), which must be <= 1: each code is
+    rint(fl(g / s_g)), and the float32 quotient is within 2^-24 |g / s_g| <=
+    2^-9 of g / s_g."""
     import numpy as np
 
     import oracle
@@ -250,7 +252,7 @@ def oracle_error(snap):
         if snap["scale"] is not None:
             one = np.ones_like(snap["g"])
             cnt = oracle.histogram(bins, one, one, leaf, L, snap["B"])[..., 1::2]
-            bound = cnt * snap["scale"][:, 0] / 2
+            bound = cnt * snap["scale"][:, 0] * (0.5 + 2.0**-9)
             err = np.abs(got[..., 0::2] - want[..., 0::2])
             q = float((err[bound > 0] / bound[bound > 0]).max())
             worst_q = q if worst_q is None else max(worst_q, q)
