@@ -382,8 +382,8 @@ def time_form(bst, name, args, rmse):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(name, args.workload),
-                     "kernel": "cbh_build_histograms / cbh_build_histograms_sub "
-                               "(LDS histogram + partial merge)",
+                     "kernel": "cbh_build_histograms / cbh_apply_build_histograms_sub / "
+                               "cbh_part_build_histograms (LDS histogram + partial merge)",
                      "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
                      "avg_launch_ms": round(float(hist_ms.mean()), 5)},
     }
@@ -585,6 +585,25 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
+    MiB: the bandwidth a streaming kernel reaches on this GPU."""
+    import torch
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return round(2 * (mib << 20) / sec / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -691,7 +710,7 @@ def main():
         "config": {"workload": describe(args.workload, p, bst),
                    "precision": args.precision, "features_per_tree": F, "bins": bst.B,
                    "rows": n},
-        "roofline": head["roofline"],
+        "roofline": dict(head["roofline"], copy_gbs=copy_bandwidth()),
         "forms": results,
         "vs_plain_fp32": (round(results["fp32"]["sec_per_tree"] / head["sec_per_tree"], 3)
                           if "fp32" in results else None),

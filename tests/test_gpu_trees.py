@@ -520,3 +520,71 @@ def test_full_size_c2_sampled(cb):
     m = magG > 0
     assert np.max(np.abs(gv - rv)[m] * (rH + bst.l2)[m] / magG[m]) <= gu.FP32_TOL
     bst.close()
+
+
+# ------------------------------------------ full-size 10M and 50M workloads
+def _sampled_tree_check(cb, bst, prec, n_feat, rng):
+    """Grow one tree level by level with the booster's own calls (its default
+    row order and plans) and check, at every level, sampled features against
+    the oracle and every feature's totals against the leaf totals; leaf
+    indices are tracked on the host from the chosen splits."""
+    pr = bst.probs[0]
+    if prec == 2:
+        cb.cbh_quantize_gradients(bst.ctx, pr, bst.stream)
+    torch.cuda.synchronize()
+    bins = bst.bins_host(0)
+    K, n = bst.K, bst.n
+    g32, h32 = bst.g.cpu().numpy(), bst.h.cpu().numpy()
+    if prec == 2:
+        rgq, rhq, _ = oracle.grad_codes(g32, h32, True)
+        assert np.array_equal(bst.gq.cpu().numpy()[..., 0], rgq)
+        assert np.array_equal(bst.gq.cpu().numpy()[..., 1], rhq)
+    leaf = np.zeros(n, np.uint16)
+    for lvl in range(bst.depth):
+        L = 1 << lvl
+        bst.build_level_histograms(pr, lvl)
+        cb.cbh_score_splits(bst.ctx, pr, lvl, bst.hist_ptr(lvl), prec, bst.l2,
+                            bst.split_ptr(lvl), None, bst.stream)
+        torch.cuda.synchronize()
+        got = gu.hist_to_f64(bst.hists[lvl % 2], L, bst.F, bst.B, K, prec, False)
+        fs = np.sort(rng.choice(bst.F, n_feat, replace=False))
+        if prec == 2:
+            want = oracle.histogram_int(bins[fs], rgq, rhq, leaf, L, bst.B)
+            assert np.array_equal(got[:, fs], want), lvl
+        else:
+            g64, h64 = g32.astype(np.float64), h32.astype(np.float64)
+            want = oracle.histogram(bins[fs], g64, h64, leaf, L, bst.B)
+            mag = oracle.histogram(bins[fs], np.abs(g64), h64, leaf, L, bst.B)
+            tol = gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL
+            assert gu.normalized_err(got[:, fs], want, mag) <= tol, lvl
+        # every feature's h totals per (leaf, class) agree (unsampled features too)
+        tot = got[..., 1::2].sum(axis=2)                    # [L][F][K]
+        scale = np.abs(tot).max() + 1e-30
+        assert np.max(np.abs(tot - tot[:, :1])) <= (0 if prec == 2 else 1e-9) * scale, lvl
+        f, k = (int(v) for v in bst.best[lvl, :2].cpu().numpy())
+        if 0 <= f < bst.F:
+            leaf |= ((bins[f] > k).astype(np.uint16) << lvl)
+        bst.advance(pr, lvl)
+    torch.cuda.synchronize()
+    assert np.array_equal(bst.leaf.cpu().numpy(), leaf)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,prec", [("c3_10m", 1), ("c5_50m", 2)])
+def test_full_size_sampled_deep(cb, name, prec):
+    """The 10M-row precision workload (compensated form, rows in leaf order)
+    and the 50M-row MultiClass workload (int16 form, rows in leaf order) at
+    full size in the benchmark's default row order and plans: one tree, every
+    level's histograms on sampled features against the oracle (int16 bit for
+    bit with the GPU's own codes, which must equal the oracle's), totals
+    across features, and the final leaf indices."""
+    p = datagen.make_c3() if name == "c3_10m" else datagen.make_c5()
+    bst = _booster(cb, p, prec)
+    try:
+        assert bst.use_part
+        bst.init_gradients()
+        bst.fit_tree(0)          # one tree first, so the gradients are not the initial ones
+        torch.cuda.synchronize()
+        _sampled_tree_check(cb, bst, prec, 3, np.random.default_rng(7))
+    finally:
+        bst.close()
