@@ -622,7 +622,9 @@ static void launch_side_code(const void* parent, const cbh_split* split, int64_t
                              int32_t B, int32_t K, int32_t rmse, uint16_t* leaf, int64_t n,
                              uint32_t shift, uint8_t* side, uint16_t* codes, int num_cus,
                              hipStream_t s, const cbh_problem* apply) {
-    const int64_t rpb = std::max<int64_t>(8192, align_up((n + num_cus - 1) / num_cus, 8));
+    // about four blocks per CU: each block first derives every parent's side
+    // (a few KB of the parent histogram from L2), then streams its rows
+    const int64_t rpb = std::max<int64_t>(2048, align_up((n + 4 * num_cus - 1) / (4 * num_cus), 8));
     const unsigned grid = (unsigned)((n + rpb - 1) / rpb);
     if (apply)
         side_code_kernel<PREC, true><<<grid, 256, (size_t)half, s>>>(
