@@ -523,6 +523,9 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             HistKnobs kb = kn;
             kb.target_blocks = std::max<int32_t>(
                 64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
+            // the lanes-over-features tile needs no replicas: give it the whole
+            // LDS, as the autotuner does (unless the knobs are forced)
+            if (kb.kernel == 1 && !ctx->force_knobs) kb.lds_budget = ctx->max_lds;
             return kb;
         };
         // One histogram kernel serves the whole level: lanes over features
