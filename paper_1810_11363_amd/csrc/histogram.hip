@@ -91,7 +91,11 @@ static HistPlan plan_lpf(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, i
     const int64_t c_part = std::max<int64_t>(1, (int64_t(kn.partial_pct) * n * F / 100) /
                                                     std::max<int64_t>(1, part_per_chunk));
     const int64_t c_rows = std::max<int64_t>(1, n / std::max<int64_t>(1, kn.min_rows));
-    const int64_t c_fill = std::max<int64_t>(1, (kn.target_blocks + tiles - 1) / tiles);
+    // the K class blocks of one (chunk, group, tile) read the same bins, which
+    // stay in L2 only if their row range is short: with several classes, 8
+    // times as many blocks
+    const int64_t target = int64_t(kn.target_blocks) * (K > 1 ? 8 : 1);
+    const int64_t c_fill = std::max<int64_t>(1, (target + tiles - 1) / tiles);
     const int64_t chunks = std::min(std::min(c_part, c_rows), c_fill);
     int64_t rows = align_up((n + chunks - 1) / chunks, 16);
     if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);

@@ -512,7 +512,7 @@ static void launch_part_hist(const PartHist& a, int W, unsigned grid, size_t lds
 // fewest times), as many slots per tile as the LDS budget holds (at least
 // one, at most 64; one slot lets the block skip the row codes inside its
 // range), and chunks of at least min_rows rows sized so that the blocks of
-// the whole level reach target_blocks.
+// the whole level reach target_blocks (8 times that with several classes).
 static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
                           int32_t L, int32_t precision, int max_lds) {
     HistPlan p;
@@ -528,8 +528,11 @@ static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, 
     p.n_ltiles = (L + p.lt - 1) / p.lt;
     p.n_fgroups = (F + W - 1) / W;
     const int64_t per_chunk = int64_t(p.n_fgroups) * K;     // blocks per chunk of rows
-    int64_t rows = std::max<int64_t>(kn.min_rows,
-                                     n * per_chunk / std::max<int64_t>(1, kn.target_blocks));
+    // the K class blocks of one (chunk, feature group) read the same bins,
+    // which stay in L2 only if their row range is short: with several
+    // classes, 8 times as many blocks
+    const int64_t target = int64_t(std::max<int32_t>(1, kn.target_blocks)) * (K > 1 ? 8 : 1);
+    int64_t rows = std::max<int64_t>(kn.min_rows, n * per_chunk / target);
     rows = align_up(std::min<int64_t>(rows, align_up(n, 16)), 16);
     if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);
     p.rows_per_chunk = rows;
