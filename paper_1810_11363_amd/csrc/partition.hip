@@ -452,21 +452,81 @@ __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
                            s0, lds);
 }
 
-// Output cell (leaf, feature, bin): the sum of its slot tile's chunks.
+// Output (cell, class) units (cell = leaf, feature, bin): the sum of the
+// unit's slot tile's chunks, in chunk order, with the arithmetic of the other
+// merges (two-float: TwoSum of the (hi, lo) parts). One thread per unit, so
+// consecutive threads read the consecutive classes' words of a cell.
 template <int PREC>
 __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restrict__ part,
                                                          const int64_t* __restrict__ cp,
                                                          int32_t L, int32_t lt, int32_t F,
                                                          int32_t B, int32_t K, int32_t wpc,
                                                          int32_t rmse, void* __restrict__ out) {
-    const int64_t fb = int64_t(F) * B, cells = int64_t(L) * fb, cells_lt = int64_t(lt) * fb;
-    for (int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x; cell < cells;
-         cell += int64_t(gridDim.x) * 256) {
+    const int64_t fb = int64_t(F) * B, cells_lt = int64_t(lt) * fb;
+    const int64_t units = int64_t(L) * fb * K;
+    const int64_t cw = cells_lt * wpc;                  // words per chunk partial
+    for (int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x; u < units;
+         u += int64_t(gridDim.x) * 256) {
+        const int64_t cell = u / K;
+        const int c = (int)(u % K);
         const int64_t v = cell / fb, rest = cell % fb;
         const int64_t t = v / lt;
         const int64_t g0 = cp[t];
-        merge_cell<PREC>(part + g0 * cells_lt * wpc, cells_lt, K, (int)(cp[t + 1] - g0),
-                         rmse != 0, out, (v - t * lt) * fb + rest, cell);
+        const int nch = (int)(cp[t + 1] - g0);
+        const uint32_t* p = part + g0 * cw + ((v - t * lt) * fb + rest) * wpc;
+        if constexpr (PREC == CBH_PREC_FP32) {
+            float g = 0.f, hh = 0.f;
+            uint32_t cnt = 0;
+            for (int ch = 0; ch < nch; ++ch) {
+                const uint2 w = *reinterpret_cast<const uint2*>(p + ch * cw + 2 * c);
+                g += __uint_as_float(w.x);
+                if (rmse) cnt += w.y; else hh += __uint_as_float(w.y);
+            }
+            reinterpret_cast<float*>(out)[cell * 2 * K + 2 * c] = g;
+            if (rmse) reinterpret_cast<uint32_t*>(out)[cell * 2 * K + 2 * c + 1] = cnt;
+            else reinterpret_cast<float*>(out)[cell * 2 * K + 2 * c + 1] = hh;
+        } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
+            float S[2] = {0.f, 0.f}, E[2] = {0.f, 0.f};
+            uint32_t cnt = 0;
+            for (int ch = 0; ch < nch; ++ch) {
+                const uint4 w = *reinterpret_cast<const uint4*>(p + ch * cw + 4 * c);
+                const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int st = 0; st < 2; ++st) {
+                    if (st == 1 && rmse) {
+                        cnt += ww[2];
+                        continue;
+                    }
+                    const float hi = __uint_as_float(ww[2 * st]);
+                    const float lo = __uint_as_float(ww[2 * st + 1]);
+                    const float tt = S[st] + hi;
+                    const float bp = tt - S[st];
+                    const float e = (S[st] - (tt - bp)) + (hi - bp);
+                    S[st] = tt;
+                    E[st] += e + lo;
+                }
+            }
+            float2 r[2];
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const float hs = S[st] + E[st];
+                r[st] = make_float2(hs, E[st] - (hs - S[st]));
+            }
+            if (rmse) r[1] = make_float2(__uint_as_float(cnt), 0.f);
+            float2* o = reinterpret_cast<float2*>(out) + cell * 2 * K + 2 * c;
+            o[0] = r[0];
+            o[1] = r[1];
+        } else {
+            int64_t gs = 0, hs = 0;
+            for (int ch = 0; ch < nch; ++ch) {
+                const uint64_t w = *reinterpret_cast<const uint64_t*>(p + ch * cw + 2 * c);
+                hs += (int64_t)(uint32_t)(w & 0xffffffffull);
+                gs += (int64_t)(int32_t)(uint32_t)(w >> 32);
+            }
+            int64_t* o = reinterpret_cast<int64_t*>(out) + 2 * (cell * K + c);
+            o[0] = gs;
+            o[1] = hs;
+        }
     }
 }
 
@@ -771,9 +831,9 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
             break;
     }
     CBH_LAUNCHED();
-    const int64_t cells = int64_t(L) * F * B;
+    const int64_t units = int64_t(L) * F * B * K;
     const unsigned mg =
-        (unsigned)std::min<int64_t>((cells + 255) / 256, int64_t(ctx->num_cus) * 16);
+        (unsigned)std::min<int64_t>((units + 255) / 256, int64_t(ctx->num_cus) * 16);
     switch (precision) {
         case CBH_PREC_FP32:
             part_merge_kernel<CBH_PREC_FP32><<<mg, 256, 0, s>>>(
