@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void bside_code_kernel(const DevProb* __restri
     const uint32_t lmask = (uint32_t)half - 1u, shift = (uint32_t)(level - 1);
     const int64_t i0 = rb * kSideRows, i1 = min(pr.n, i0 + kSideRows);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const uint32_t v = pr.leaf[i];
+        const uint32_t v = gld_u16(pr.leaf + i);
         const uint32_t pp = v & lmask;
         pr.codes[i] = (uint16_t)((((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu);
     }

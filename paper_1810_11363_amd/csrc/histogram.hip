@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
                 if (shift == 0) lv = make_uint4(0u, 0u, 0u, 0u);
                 // the 8 rows' bins: 8 bytes of one 16-row segment
                 uint2 bw = make_uint2(0u, 0u);
-                if (col) bw = *reinterpret_cast<const uint2*>(seg_ptr(col, st, j));
+                if (col) bw = gld_u2(seg_ptr(col, st, j));
                 const uint32_t bb[2] = {bw.x, bw.y};
                 uint32_t lw2[4] = {lv.x, lv.y, lv.z, lv.w};
 #pragma unroll

@@ -12,6 +12,35 @@
 
 namespace cbh {
 
+// ------------------------------------------------------------ global loads
+// Loads through pointers the compiler cannot place in global memory (bin
+// columns reached through a pointer table, fields of device-resident problem
+// descriptors) otherwise become flat loads. A flat load counts against both
+// the vector-memory and the LDS counters, so every later wait has to drain
+// both: a load issued early for the next segment then blocks the LDS updates
+// of the current one. These helpers load through the global address space.
+typedef unsigned int gv4u __attribute__((ext_vector_type(4)));
+typedef unsigned int gv2u __attribute__((ext_vector_type(2)));
+typedef float gv4f __attribute__((ext_vector_type(4)));
+#define CBH_GLOBAL(T) const __attribute__((address_space(1))) T*
+__device__ __forceinline__ uint4 gld_u4(const void* p) {
+    const gv4u v = *(CBH_GLOBAL(gv4u))(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 gld_u2(const void* p) {
+    const gv2u v = *(CBH_GLOBAL(gv2u))(p);
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ float4 gld_f4(const void* p) {
+    const gv4f v = *(CBH_GLOBAL(gv4f))(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t gld_u32(const void* p) { return *(CBH_GLOBAL(uint32_t))(p); }
+__device__ __forceinline__ uint32_t gld_u16(const void* p) { return *(CBH_GLOBAL(uint16_t))(p); }
+__device__ __forceinline__ uint32_t gld_u8(const void* p) { return *(CBH_GLOBAL(uint8_t))(p); }
+__device__ __forceinline__ float gld_f32(const void* p) { return *(CBH_GLOBAL(float))(p); }
+#undef CBH_GLOBAL
+
 // ------------------------------------------------------------ histogram tile
 // One block accumulates rows [r0, r1) of features [f0, f0 + nf) for leaves
 // [l0, l0 + lt) into an LDS tile, then writes the tile into `part`, the
@@ -882,8 +911,18 @@ __device__ __forceinline__ void lpf_rows8(char* tile, const uint32_t (&bw)[4], i
 // One 16-row segment of the lanes-over-features kernel: its bins (this
 // lane's feature), row codes and gradient statistics, loaded with 16-byte
 // loads; add() puts its rows into the tile, 8 at a time.
+// s_waitcnt immediate that waits until at most n vector-memory loads are
+// outstanding and leaves the export and LDS counters alone (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int vm_wait_imm(int n) {
+    return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14);
+}
+
 template <int PREC, int RM, int MODE>
 struct LpfSeg {
+    // 16-byte loads per segment (bins, row codes, statistics)
+    static constexpr int kLoads =
+        1 + (MODE != 0 ? 2 : 0) + 4 + ((PREC != CBH_PREC_INT16 && RM == 0) ? 4 : 0);
     uint4 b;
     uint4 c[2];      // row codes (MODE != 0)
     uint4 q[4];      // int16 codes
@@ -891,20 +930,27 @@ struct LpfSeg {
     __device__ __forceinline__ void load(const uint8_t* col, int64_t sstride,
                                          const uint16_t* rowcode, const LpfBlock& a, int64_t t) {
         const int64_t i = t << 4;
-        b = *reinterpret_cast<const uint4*>(col + t * sstride);
+        b = gld_u4(col + t * sstride);
         if constexpr (MODE != 0) {
-            c[0] = *reinterpret_cast<const uint4*>(rowcode + i);
-            c[1] = *reinterpret_cast<const uint4*>(rowcode + i + 8);
+            c[0] = gld_u4(rowcode + i);
+            c[1] = gld_u4(rowcode + i + 8);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if constexpr (PREC == CBH_PREC_INT16) {
-                q[k] = *reinterpret_cast<const uint4*>(a.gq + i + 4 * k);
+                q[k] = gld_u4(a.gq + i + 4 * k);
             } else {
-                g[k] = *reinterpret_cast<const float4*>(a.g + i + 4 * k);
-                if constexpr (RM == 0) h[k] = *reinterpret_cast<const float4*>(a.h + i + 4 * k);
+                g[k] = gld_f4(a.g + i + 4 * k);
+                if constexpr (RM == 0) h[k] = gld_f4(a.h + i + 4 * k);
             }
         }
+    }
+    // Wait for this segment's loads while the other register set's kLoads
+    // loads, issued after them, stay in flight. Called on every path before
+    // add(): the compiler's own waits, merged over add()'s branches, would
+    // otherwise drain the next segment's loads too.
+    __device__ __forceinline__ static void wait_mine() {
+        __builtin_amdgcn_s_waitcnt(vm_wait_imm(kLoads));
     }
     template <int W>
     __device__ __forceinline__ void add(char* tile, uint32_t lane_off, uint32_t s0, uint32_t ns,
@@ -923,7 +969,10 @@ struct LpfSeg {
                     const uint32_t lw[4] = {cc.x, cc.y, cc.z, cc.w};
                     const uint32_t code = (lw[k >> 1] >> (16 * (k & 1))) & 0xffffu;
                     const uint32_t sl = code - s0;
-                    off[k] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
+                    // slot offsets stay below the LDS size: 24-bit products
+                    // (full rate, where a 32-bit multiply is quarter rate)
+                    off[k] = MODE == 1 ? __umul24(code, slot_bytes)
+                                       : (sl < ns ? __umul24(sl, slot_bytes) : kLpfSkip);
                 }
                 const int r = 8 * h2 + k;
                 if constexpr (PREC == CBH_PREC_INT16) {
@@ -995,17 +1044,23 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
     const int64_t step = int64_t(nwaves) * RG;
     if (vec && t < t_full) {
         // software pipeline: the loads of the next segment are issued before
-        // the atomics of the current one (two register sets, A and B)
+        // the atomics of the current one (two register sets, A and B). The
+        // loads are unconditional (past the end they re-read the last full
+        // segment and are not used): a load under a branch would make the
+        // compiler's wait before the atomics drain it too.
+        const int64_t t_last = t_full - 1;
         LpfSeg<PREC, RM, MODE> A, B;
         A.load(col, sstride, rowcode, a, t);
         for (;;) {
             int64_t tn = t + step;
-            if (tn < t_full) B.load(col, sstride, rowcode, a, tn);
+            B.load(col, sstride, rowcode, a, min(tn, t_last));
+            LpfSeg<PREC, RM, MODE>::wait_mine();
             if (fok) A.template add<W>(tile, lane_off, s0, ns, slot_bytes);
             t = tn;
             if (t >= t_full) break;
             tn = t + step;
-            if (tn < t_full) A.load(col, sstride, rowcode, a, tn);
+            A.load(col, sstride, rowcode, a, min(tn, t_last));
+            LpfSeg<PREC, RM, MODE>::wait_mine();
             if (fok) B.template add<W>(tile, lane_off, s0, ns, slot_bytes);
             t = tn;
             if (t >= t_full) break;
@@ -1017,21 +1072,21 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
         const int64_t i = t << 4;
         const uint8_t* pb = col + t * sstride;
         for (int r = 0; r < 16 && i + r < r1; ++r) {
-            const uint32_t bwr[4] = {(uint32_t)pb[r], 0u, 0u, 0u};
+            const uint32_t bwr[4] = {gld_u8(pb + r), 0u, 0u, 0u};
             uint32_t o1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
             float g1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float h1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             uint32_t q1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
             if constexpr (MODE != 0) {
-                const uint32_t code = rowcode[i + r];
+                const uint32_t code = gld_u16(rowcode + i + r);
                 const uint32_t sl = code - s0;
                 o1[0] = MODE == 1 ? code * slot_bytes : (sl < ns ? sl * slot_bytes : kLpfSkip);
             }
             if constexpr (PREC == CBH_PREC_INT16) {
-                q1[0] = a.gq[i + r];
+                q1[0] = gld_u32(a.gq + i + r);
             } else {
-                g1[0] = a.g[i + r];
-                if constexpr (RM == 0) h1[0] = a.h[i + r];
+                g1[0] = gld_f32(a.g + i + r);
+                if constexpr (RM == 0) h1[0] = gld_f32(a.h + i + r);
             }
             if (fok && o1[0] != kLpfSkip) {
                 // one row: use the per-row routine on a segment holding only this bin

@@ -297,11 +297,11 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
             const int f = f0 + fi;
             const uint8_t* src = m.src_cols[f] + (seg0 + sg) * seg_stride_of(m.src_seg, f);
             if (valid == 0xffffu && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
-                w[q] = *reinterpret_cast<const uint4*>(src);
+                w[q] = gld_u4(src);
             } else {
                 uint32_t t[4] = {0u, 0u, 0u, 0u};
                 for (int j = 0; j < 16; ++j)
-                    if ((valid >> j) & 1u) t[j >> 2] |= (uint32_t)src[j] << (8 * (j & 3));
+                    if ((valid >> j) & 1u) t[j >> 2] |= gld_u8(src + j) << (8 * (j & 3));
                 w[q] = make_uint4(t[0], t[1], t[2], t[3]);
             }
         }
