@@ -395,18 +395,24 @@ struct PartHist {
     int32_t F, B, K, L, lt, n_tiles, n_fgroups, wpc;
 };
 
-// Block -> (class, feature group, chunk) with the classes of one group and
-// chunk adjacent; the chunk's slot tile by binary search over cp.
+// Block -> (class, feature group, chunk). Chunks go to the XCDs in turn
+// (chunk gc to XCD gc mod 8; block b runs on XCD b mod 8), and each chunk's
+// group and class blocks are neighbours on its XCD, the classes of one group
+// adjacent (they read the same bins). Leaves, and so chunks, differ in size,
+// and neighbouring leaves tend to be alike (they share their high split
+// bits): a contiguous range of chunks per XCD would leave some XCDs with far
+// more rows than others. The chunk's slot tile is found by binary search
+// over cp.
 template <int PREC, int RM, int W>
 __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
     extern __shared__ __align__(16) uint32_t lds[];
-    const int64_t per_xcd = (a.n_items + 7) / 8;
-    int64_t item = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (item >= a.n_items) return;
-    const int c = (int)(item % a.K);
-    item /= a.K;
-    const int fg = (int)(item % a.n_fgroups);
-    const int64_t gc = item / a.n_fgroups;
+    const int64_t per_gc = int64_t(a.n_fgroups) * a.K;
+    const int64_t bx = blockIdx.x >> 3;
+    const int64_t gc = (bx / per_gc) * 8 + (blockIdx.x & 7);
+    if (gc * per_gc >= a.n_items) return;
+    const int64_t r = bx % per_gc;
+    const int c = (int)(r % a.K);
+    const int fg = (int)(r / a.K);
     if (gc >= a.cp[a.n_tiles]) return;
     int lo = 0, hi = a.n_tiles - 1;
     while (lo < hi) {
@@ -815,7 +821,7 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     a.n_tiles = (int32_t)n_tiles;
     a.n_fgroups = plan.n_fgroups;
     a.wpc = plan.words_per_cell;
-    const unsigned grid = (unsigned)(8 * ((a.n_items + 7) / 8));
+    const unsigned grid = (unsigned)(8 * ((max_chunks + 7) / 8) * plan.n_fgroups * K);
     const size_t lds = (size_t)plan.lds_bytes;
     switch (precision) {
         case CBH_PREC_FP32:
