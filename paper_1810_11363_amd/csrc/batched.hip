@@ -58,6 +58,44 @@ struct DevTile {
     int32_t chunk;
 };
 
+// The tiles of one row chunk of one problem (its feature groups and slot
+// tiles, which read the same rows) and their work, rows x features x slot
+// tiles.
+struct TileGroup {
+    int64_t work;
+    int32_t prob, chunk, n_fgroups, n_ltiles;
+};
+
+// Work list of a level. The launches run the first eighth of the list on
+// XCD 0, the next on XCD 1, and so on (block b runs on XCD b mod 8). Problems
+// differ in size, so the groups are dealt out by work: largest first, each to
+// the XCD with the least work so far; every XCD's share is then padded with
+// empty tiles (prob = -1) to a common length. A group stays on one XCD, where
+// its tiles share the rows' statistics and row codes in L2.
+static void deal_tiles(std::vector<TileGroup>& groups, std::vector<DevTile>& tiles) {
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const TileGroup& a, const TileGroup& b) { return a.work > b.work; });
+    std::vector<DevTile> share[8];
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const TileGroup& gr : groups) {
+        int x = 0;
+        for (int k = 1; k < 8; ++k)
+            if (load[k] < load[x]) x = k;
+        load[x] += gr.work;
+        for (int fg = 0; fg < gr.n_fgroups; ++fg)
+            for (int lt = 0; lt < gr.n_ltiles; ++lt)
+                share[x].push_back(DevTile{gr.prob, fg, lt, gr.chunk});
+    }
+    size_t len = 0;
+    for (const auto& v : share) len = std::max(len, v.size());
+    tiles.clear();
+    tiles.reserve(8 * len);
+    for (auto& v : share) {
+        v.resize(len, DevTile{-1, 0, 0, 0});
+        tiles.insert(tiles.end(), v.begin(), v.end());
+    }
+}
+
 struct LevelPlan {
     std::vector<HistPlan> plans;       // per problem
     std::vector<int64_t> part_off;     // per problem, bytes into workspace
@@ -123,6 +161,7 @@ __global__ __launch_bounds__(kHistThreads) void bhist_kernel(const DevProb* __re
     const int64_t ti = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (ti >= n_tiles) return;
     const DevTile tile = tiles[ti];
+    if (tile.prob < 0) return;
     const DevProb pr = probs[tile.prob];
     const LevelPlan::DevHP hp = plans[tile.prob];
     TileArgs t;
@@ -166,6 +205,7 @@ __global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __res
     const int64_t ti = int64_t(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (ti >= n_tiles) return;
     const DevTile tile = tiles[ti];
+    if (tile.prob < 0) return;
     const DevProb pr = probs[tile.prob];
     const LevelPlan::DevHP hp = plans[tile.prob];
     LpfBlock b;
@@ -513,6 +553,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         LevelPlan lp;
         const int L = 1 << lvl;
         std::vector<DevTile> tiles;
+        std::vector<TileGroup> groups;
         std::vector<LevelPlan::DevHP> dplans;
         std::vector<int64_t> cell_off{0}, feat_off{0}, row_off{0};
         int64_t off = 0;
@@ -571,10 +612,11 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                                 hp.words_per_cell * 4,
                             256);
             lp.max_lds = std::max(lp.max_lds, hp.lds_bytes);
-            for (int ch = 0; ch < hp.n_chunks; ++ch)
-                for (int fg = 0; fg < hp.n_fgroups; ++fg)
-                    for (int lt = 0; lt < hp.n_ltiles; ++lt)
-                        tiles.push_back(DevTile{p, fg, lt, ch});
+            for (int ch = 0; ch < hp.n_chunks; ++ch) {
+                const int64_t rows = std::min(hp.rows_per_chunk, pr.n - ch * hp.rows_per_chunk);
+                groups.push_back(TileGroup{rows * pr.n_features * hp.n_ltiles, p, ch,
+                                           hp.n_fgroups, hp.n_ltiles});
+            }
             dplans.push_back(LevelPlan::DevHP{hp.fb, hp.lt, hp.n_fgroups, hp.n_ltiles,
                                               hp.n_chunks, hp.words_per_cell, hp.rep, 0,
                                               hp.rows_per_chunk, hp.lds_bytes});
@@ -584,6 +626,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         }
         lp.part_bytes = off;
         max_part = std::max(max_part, off);
+        deal_tiles(groups, tiles);
         lp.n_tiles = (int64_t)tiles.size();
         lp.cells_total = cell_off.back();
         lp.score_total = feat_off.back();
