@@ -50,6 +50,7 @@ def _declare(L):
     L.orc_update_approx.argtypes = [i64, i32, vp, vp, dbl, vp]
     L.orc_grad_codes.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp]
     L.orc_histogram_int.argtypes = [i64, i32, vp, i32, i32, vp, vp, vp, i32, vp]
+    L.orc_apply_model.argtypes = [i64, i32, vp, i32, i32, i32, vp, vp, vp, dbl, vp]
     L.orc_num_threads.restype = C.c_int
 
 
@@ -181,6 +182,25 @@ def update_approx(approx, leaf, values, lr: float):
     leaf = _c(leaf, np.uint16)
     values = _c(values, np.float64)
     lib().orc_update_approx(leaf.size, K, _p(leaf), _p(values), float(lr), _p(approx))
+    return approx
+
+
+def apply_model(bins, feat, border, values, lr: float, approx):
+    """In place: approx[c][i] += lr * values[t][leaf_t(i)][c] for every tree t in
+    order, leaf_t(i) = sum_l 2^l [bins[feat[t][l]][i] > border[t][l]] (Sec. 4).
+    bins [F][n] uint8, feat / border [T][d] int32, values [T][2^d][K] float64,
+    approx [K][n] float64."""
+    bins = _c(bins, np.uint8)
+    F, n = bins.shape
+    feat = _c(feat, np.int32)
+    border = _c(border, np.int32)
+    T, d = feat.shape
+    assert border.shape == (T, d) and (T == 0 or (feat.min() >= 0 and feat.max() < F))
+    values = _c(values, np.float64).reshape(T, 1 << d, -1)
+    K = values.shape[2]
+    assert approx.dtype == np.float64 and approx.flags.c_contiguous and approx.size == K * n
+    lib().orc_apply_model(n, F, _p(bins), T, d, K, _p(feat), _p(border), _p(values),
+                          float(lr), _p(approx))
     return approx
 
 

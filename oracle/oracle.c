@@ -333,6 +333,32 @@ void orc_update_approx(int64_t n, int32_t K, const uint16_t* leaf,
             approx[(int64_t)c * n + i] += lr * values[(int64_t)leaf[i] * K + c];
 }
 
+/* Model apply, the scorer of Sec. 4: for tree t of depth d the leaf of a row
+ * is the binary vector sum_i 2^i * B(x, f(t, i)), where the binary feature
+ * of level i is [bin_{feat[t][i]} > border[t][i]]; the row's approx gains
+ * lr * values[t][leaf][c] for every class c, tree after tree in model
+ * order, exactly as a sequence of model updates would add them.
+ * bins is column-major [F][n]; values is [T][2^d][K]; approx is [K][n].     */
+void orc_apply_model(int64_t n, int32_t F, const uint8_t* bins, int32_t T, int32_t d,
+                     int32_t K, const int32_t* feat, const int32_t* border,
+                     const double* values, double lr, double* approx) {
+    (void)F;
+    const int64_t n_leaves = (int64_t)1 << d;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t t = 0; t < T; ++t) {
+            int64_t leaf = 0;
+            for (int32_t l = 0; l < d; ++l) {
+                const int32_t f = feat[(int64_t)t * d + l];
+                const int32_t b = bins[(int64_t)f * n + i];
+                if (b > border[(int64_t)t * d + l]) leaf |= (int64_t)1 << l;
+            }
+            for (int32_t c = 0; c < K; ++c)
+                approx[(int64_t)c * n + i] +=
+                    lr * values[((int64_t)t * n_leaves + leaf) * K + c];
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* int16 gradient codes. Not in the paper: a per-tree scale s = max|g| / 32767
  * (and s_h = max h / 32767), code = round-half-even(g / s). This turns a

@@ -399,3 +399,94 @@ def test_boosting_reduces_training_loss(oracle_lib):
     ll = -np.mean(y * np.log(pr) + (1 - y) * np.log(1 - pr))
     assert ll < np.log(2) - 0.01
     assert all(t.counts.sum() == p.n for t in trees)
+
+
+# ---------------------------------------------------------------- model apply
+def _model_of(trees, depth):
+    """(feat, border, values) of oracle trees; a level without a split (feature
+    -1) never sets its bit, which border 255 reproduces."""
+    T = len(trees)
+    feat = np.zeros((T, depth), np.int32)
+    border = np.full((T, depth), 255, np.int32)
+    for t, tr in enumerate(trees):
+        for l, (f, k, _, _) in enumerate(tr.splits):
+            if f >= 0:
+                feat[t, l], border[t, l] = f, k
+    values = np.stack([tr.values for tr in trees])
+    return feat, border, values
+
+
+def test_apply_model_reproduces_training_approx(oracle_lib):
+    """Sec. 4 scorer against the training loop: applying the trained trees to
+    the training rows adds, row by row and tree by tree, exactly the leaf
+    values the model updates of Algorithm 1 added (leaves found there by the
+    level-by-level split rule)."""
+    from oracle import boost
+    o = oracle_lib
+    p = datagen.make_c1(n=2000)
+    p.iterations = 6
+    trees, approx, prep = boost.fit(p)
+    bins, _ = prep.tree_features(0)          # one permutation: every tree's features
+    feat, border, values = _model_of(trees, p.depth)
+    a = np.zeros_like(approx)
+    o.apply_model(bins, feat, border, values, p.lr, a)
+    assert np.array_equal(a, approx)
+
+
+def test_apply_model_reproduces_multiclass_training(oracle_lib):
+    """The same for K = 3 classes: the value table is [T][2^d][K]."""
+    from oracle import boost
+    o = oracle_lib
+    g0 = np.random.default_rng(31)
+    n, F, B, K, d = 1500, 5, 16, 3, 3
+    bins = g0.integers(0, B, (F, n)).astype(np.uint8)
+    label = ((bins[0] > 7).astype(np.int64) + (bins[1] > 11)).astype(np.float32)
+    nb = np.full(F, B, np.int32)
+    approx = np.zeros((K, n))
+    trees = [boost.fit_tree(bins, nb, approx, label, 2, K, d, 0.3, 1.0, B) for _ in range(4)]
+    feat, border, values = _model_of(trees, d)
+    a = np.zeros((K, n))
+    o.apply_model(bins, feat, border, values, 0.3, a)
+    assert np.array_equal(a, approx)
+
+
+def test_apply_model_constant_leaves(oracle_lib):
+    """Border -1 sets every bit (leaf 2^d - 1), border 255 none (leaf 0): the
+    model is then a constant per class."""
+    o = oracle_lib
+    g0 = np.random.default_rng(32)
+    n, F, T, d, K = 40, 3, 5, 4, 2
+    bins = g0.integers(0, 256, (F, n)).astype(np.uint8)
+    feat = g0.integers(0, F, (T, d)).astype(np.int32)
+    values = g0.normal(size=(T, 1 << d, K))
+    for bval, leaf in ((-1, (1 << d) - 1), (255, 0)):
+        a0 = g0.normal(size=(K, n))
+        a = a0.copy()
+        o.apply_model(bins, feat, np.full((T, d), bval, np.int32), values, 0.5, a)
+        want = a0.copy()
+        for t in range(T):
+            want += 0.5 * values[t, leaf][:, None]
+        assert np.array_equal(a, want)
+
+
+def test_apply_model_splits_over_trees_and_classes(oracle_lib):
+    """Applying trees 0..T-1 equals applying 0..j-1 and then j..T-1; a class's
+    output depends only on that class's leaf values."""
+    o = oracle_lib
+    g0 = np.random.default_rng(33)
+    n, F, T, d, K = 300, 6, 7, 3, 3
+    bins = g0.integers(0, 32, (F, n)).astype(np.uint8)
+    feat = g0.integers(0, F, (T, d)).astype(np.int32)
+    border = g0.integers(-1, 32, (T, d)).astype(np.int32)
+    values = g0.normal(size=(T, 1 << d, K))
+    a = np.zeros((K, n))
+    o.apply_model(bins, feat, border, values, 0.1, a)
+    b = np.zeros((K, n))
+    o.apply_model(bins, feat[:3], border[:3], values[:3], 0.1, b)
+    o.apply_model(bins, feat[3:], border[3:], values[3:], 0.1, b)
+    assert np.array_equal(a, b)
+    v2 = values.copy()
+    v2[..., 1] = 0.0
+    c = np.zeros((K, n))
+    o.apply_model(bins, feat, border, v2, 0.1, c)
+    assert np.array_equal(c[[0, 2]], a[[0, 2]]) and not c[1].any()
