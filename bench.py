@@ -79,6 +79,7 @@ WORKLOADS = {
     "c4": dict(tag="c4_batch_rmse", n=0, steps=20, cpu_rows=1_000_000, cpu_trees=1),
     "c5": dict(tag="c5_50m_multiclass", n=50_000_000, steps=3, cpu_rows=100_000, cpu_trees=1,
                warmup=1, hist_trees=2, autotune="off", compare="fp32", warmup_s=0.0),
+    "apply": dict(tag="apply_100k_8000_trees", n=100_000, steps=20, cpu_rows=20_000, cpu_trees=0),
 }
 # per-run defaults a workload may override
 RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,int16", warmup_s=1.0)
@@ -585,6 +586,98 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_apply(args):
+    """Model apply, the scorer of Sec. 4 (cbh_apply_model), on a stand-in for
+    the paper's scorer comparison: a test set of the shape it scores (10^5
+    rows x 2000 features, here at 128 bins in the 16-row tiled layout) and a
+    model of 8000 oblivious trees of depth 6 with seeded random splits and
+    leaf values. One step applies the whole model to every row."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1810_11363_amd import cbhip as cb
+    n, F, B, T, d = args.n, 2000, 128, 8000, 6
+    dev = torch.device("cuda:0")
+    ns = (n + 15) // 16
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11363)
+    tiled = torch.randint(0, B, (ns, F, 16), dtype=torch.uint8, device=dev, generator=gen)
+    table = torch.tensor([tiled.data_ptr() + 16 * f for f in range(F)], dtype=torch.int64,
+                         device=dev)
+    seg = torch.full((F,), 16 * F, dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(11364)
+    feat = rng.integers(0, F, (T, d)).astype(np.int32)
+    border = rng.integers(0, B - 1, (T, d)).astype(np.int32)
+    values = rng.normal(size=(T, 1 << d, 1))
+    lr = 0.1
+    dfeat = torch.from_numpy(feat).to(dev)
+    dborder = torch.from_numpy(border).to(dev)
+    dvalues = torch.from_numpy(values).to(dev)
+    approx = torch.zeros((1, n), dtype=torch.float64, device=dev)
+    ctx = cb.cbh_create(0)
+
+    def step():
+        cb.cbh_apply_model(ctx, table, seg, n, F, 1, T, d, dfeat, dborder, dvalues, lr, approx)
+
+    for _ in range(2):
+        step()
+    cb.cbh_sync(ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    cb.cbh_sync(ctx)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    sec = e0.elapsed_time(e1) / 1e3 / args.steps
+    # parity on a row sample: one apply from zero, against the oracle
+    approx.zero_()
+    step()
+    cb.cbh_sync(ctx)
+    m = min(n, args.cpu_rows)
+    sample = tiled[: (m + 15) // 16].permute(1, 0, 2).reshape(F, -1)[:, :m].cpu().numpy()
+    got = approx[0, :m].cpu().numpy()
+    t1 = time.perf_counter()
+    want = oracle.apply_model(sample, feat, border, values, lr, np.zeros((1, m)))
+    cpu_s = time.perf_counter() - t1
+    cb.cbh_destroy(ctx)
+    algo_bytes = n * F + 16 * n + feat.nbytes + border.nbytes + values.nbytes
+    achieved = algo_bytes / sec / 1e9
+    out = {
+        "metric": "model apply throughput (rows x trees per second)",
+        "value": round(n * T / sec / 1e9, 3),
+        "unit": "G row-trees/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "ms_per_step": round(sec * 1e3, 4),
+        "wall_ms_per_step": round(wall * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"model apply: {n} rows x {F} features at {B} bins (16-row "
+                               f"tiled), {T} oblivious trees of depth {d}, K=1",
+                   "rows": n, "features": F, "trees": T, "depth": d},
+        "parity": {"rows_checked": m, "bit_exact": bool(np.array_equal(got, want[0]))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "kernel": "cbh_apply_model (apply_model_kernel)",
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": round(sec * 1e3, 4)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = {"value": round(m * T / cpu_s / 1e9, 4), "unit": "G row-trees/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{m} of {n} rows, the whole model; "
+                                         f"oracle {cpu_s:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5):
     """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
     MiB: the bandwidth a streaming kernel reaches on this GPU."""
@@ -667,6 +760,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         run_batch(args)
+        return
+    if args.workload == "apply":
+        run_apply(args)
         return
 
     import torch  # noqa: F401

@@ -352,6 +352,40 @@ int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_la
                       int32_t precision, const cbh_split* last, double lr, double l2,
                       double* leaf_values_out, int64_t* leaf_counts_out, void* stream);
 
+/* Model apply, the scorer of Sec. 4 ("Fast scorer"): for a model of n_trees
+ * oblivious trees of depth d, tree t's leaf for row i is the binary vector
+ *   leaf_t(i) = sum_{l < d} 2^l [bin_{f(t,l)}(i) > k(t,l)],
+ * and for every class c
+ *   approx[c][i] += lr * leaf_values[t][leaf_t(i)][c]
+ * in double, tree after tree in model order: exactly the additions that the
+ * model updates (cbh_update_approx) made while the trees were grown, so
+ * applying a trained model to its training rows reproduces the training
+ * approx bit for bit.
+ *   bins, seg_stride  as in cbh_problem: device array of n_features device
+ *                     pointers to uint8 bins (16-row segments `seg_stride`
+ *                     bytes apart; seg_stride NULL = plain columns)
+ *   n                 rows (0: nothing to do)
+ *   K                 classes, 1..16 (1 for RMSE and Logloss)
+ *   n_trees, depth    T >= 0 (0: nothing to do), 1 <= d <= 16
+ *   split_feature     device int32 [T][d]: f(t, l), in [0, n_features)
+ *   split_border      device int32 [T][d]: k(t, l); any int32 (-1 sets the
+ *                     bit on every row, 255 on none)
+ *   leaf_values       device double [T][2^d][K]
+ *   lr                finite scale of every leaf value (the learning rate
+ *                     the values were trained with; 1 for values already
+ *                     scaled)
+ *   approx            device double [K][n], read and written
+ * A split feature outside [0, n_features) is taken as a bit of 0 on every
+ * row and reported by cbh_sync (the call itself cannot see device arrays).
+ * The rows of a launch are independent; approx must not overlap the other
+ * arrays. Errors: CBH_EINVAL (NULL pointers, n or n_trees < 0, lr not
+ * finite), CBH_EUNSUPPORTED (K or depth out of range, n >= 2^38 with
+ * K > 1).                                                                  */
+int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride,
+                    int64_t n, int32_t n_features, int32_t K, int32_t n_trees, int32_t depth,
+                    const int32_t* split_feature, const int32_t* split_border,
+                    const double* leaf_values, double lr, double* approx, void* stream);
+
 /* ---- rows in leaf order (deep trees, many classes) ------------------------- */
 
 typedef struct cbh_part cbh_part;

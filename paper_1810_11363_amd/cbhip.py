@@ -34,6 +34,7 @@ EXPORTS = [
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
+    "cbh_apply_model",
 ]
 
 
@@ -91,6 +92,8 @@ def _load():
         "cbh_apply_split": ([vp, C.POINTER(cbh_problem), i32, vp, vp], C.c_int),
         "cbh_update_approx": ([vp, C.POINTER(cbh_problem), vp, i32, vp, dbl, dbl, vp, vp, vp],
                               C.c_int),
+        "cbh_apply_model": ([vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp],
+                            C.c_int),
         "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
@@ -290,6 +293,16 @@ def cbh_update_approx(ctx, prob: cbh_problem, hist_last, precision: int, last, l
                                          _ptr(last), float(lr), float(l2),
                                          _ptr(leaf_values_out), _ptr(leaf_counts_out),
                                          _stream(stream)))
+
+
+def cbh_apply_model(ctx, bins, seg_stride, n: int, n_features: int, K: int, n_trees: int,
+                    depth: int, split_feature, split_border, leaf_values, lr: float, approx,
+                    stream=None):
+    return _check(_lib.cbh_apply_model(ctx, _ptr(bins), _ptr(seg_stride), int(n),
+                                       int(n_features), int(K), int(n_trees), int(depth),
+                                       _ptr(split_feature), _ptr(split_border),
+                                       _ptr(leaf_values), float(lr), _ptr(approx),
+                                       _stream(stream)))
 
 
 # ------------------------------------------------------------------ batched

@@ -52,6 +52,7 @@ void clear_error();
 enum : uint32_t {
     FLAG_NAN_INPUT = 1u,
     FLAG_BAD_INDEX = 2u,
+    FLAG_BAD_SPLIT = 4u,
 };
 
 // ------------------------------------------------------- launch geometry

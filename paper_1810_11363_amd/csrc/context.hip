@@ -182,6 +182,7 @@ int cbh_sync(cbh_ctx* ctx, void* stream) {
         std::string msg = "device reported:";
         if (flags & FLAG_NAN_INPUT) msg += " NaN feature value (binned as 0);";
         if (flags & FLAG_BAD_INDEX) msg += " permutation entry outside [0, n);";
+        if (flags & FLAG_BAD_SPLIT) msg += " model split feature outside [0, F) (bit taken as 0);";
         set_error("%s", msg.c_str());
         return CBH_EDEVICE;
     }

@@ -10,9 +10,12 @@
 // update: approx += lr * v[leaf] in double (Algorithm 1 adds each tree to the
 // model), then g = dLoss/da and h = d2Loss/da2 at the new approx in double,
 // stored as float.
+// apply_model: the scorer of Sec. 4 over a whole model, from the bins.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
+#include "kernels_dev.h"
 
 namespace cbh {
 
@@ -268,9 +271,165 @@ int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_las
 
 }  // namespace cbh
 
+namespace cbh {
+
+// Model apply (Sec. 4, "Fast scorer"): tree t's leaf for a row is the
+// binary vector sum_i 2^i [bin_{f(t,i)} > k(t,i)], and the row's approx gains
+// lr * v[t][leaf][c], tree after tree in model order (the additions of the
+// model updates that built the trees, in the same order and precision).
+// The model goes through in chunks of trees, two launches per chunk:
+//   model_leaves_kernel  one block row per tree of the chunk: each thread
+//                        finds the leaves of 4 consecutive rows (one 32-bit
+//                        load per level gives their 4 bins; the tree's splits
+//                        are the same for the whole block, so they and the
+//                        column pointers come through scalar loads) and
+//                        stores them as uint16 [tree][row];
+//   model_sum_kernel     one thread per row adds the chunk's trees in order,
+//                        8 trees' leaves and values loaded before their adds.
+// Every (tree, row) leaf is independent, so the first launch has T x n / 4
+// threads of work where a single pass over the rows would have n / 4, each
+// walking the whole model.
+struct ApplyArgs {
+    const uint8_t* const* bins;
+    const int64_t* seg;
+    int64_t n;
+    int32_t F, K, d, t0, nt;
+    const int32_t* feat;
+    const int32_t* border;
+    const double* values;
+    double lr;
+    double* approx;
+    uint16_t* leaves;              // [nt][n]
+    uint32_t* flags;
+};
+
+__global__ __launch_bounds__(256) void model_leaves_kernel(ApplyArgs a) {
+    const int64_t i0 = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+    const int tl = blockIdx.y;
+    if (i0 >= a.n) return;
+    const int nr = (int)min<int64_t>(4, a.n - i0);
+    const int64_t t = a.t0 + tl;
+    uint32_t lf[4] = {0u, 0u, 0u, 0u};
+    bool bad = false;
+    for (int l = 0; l < a.d; ++l) {
+        const int f = a.feat[t * a.d + l];
+        const int k = a.border[t * a.d + l];
+        if ((unsigned)f >= (unsigned)a.F) {
+            bad = true;
+            continue;
+        }
+        const uint8_t* col = a.bins[f];
+        const int64_t st = a.seg ? a.seg[f] : 16;
+        const uint8_t* p = col + (i0 >> 4) * st + (i0 & 15);
+        uint32_t w = 0u;
+        if (nr == 4 && ((reinterpret_cast<uintptr_t>(p) & 3) == 0)) {
+            w = gld_u32(p);
+        } else {
+            for (int r = 0; r < nr; ++r) w |= gld_u8(seg_ptr(col, st, i0 + r)) << (8 * r);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lf[r] |= ((int)((w >> (8 * r)) & 255u) > k ? 1u : 0u) << l;
+    }
+    uint16_t* out = a.leaves + int64_t(tl) * a.n + i0;
+    if (nr == 4 && ((reinterpret_cast<uintptr_t>(out) & 7) == 0)) {
+        *reinterpret_cast<uint2*>(out) = make_uint2(lf[0] | (lf[1] << 16), lf[2] | (lf[3] << 16));
+    } else {
+        for (int r = 0; r < nr; ++r) out[r] = (uint16_t)lf[r];
+    }
+    if (bad && threadIdx.x == 0 && blockIdx.x == 0) atomicOr(a.flags, FLAG_BAD_SPLIT);
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void model_sum_kernel(ApplyArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int K = KC == 1 ? 1 : a.K;
+    const int64_t nl = int64_t(1) << a.d;
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = c < K ? a.approx[int64_t(c) * a.n + i] : 0.0;
+    constexpr int U = 8;
+    int tl = 0;
+    for (; tl + U <= a.nt; tl += U) {
+        uint32_t lf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) lf[u] = a.leaves[int64_t(tl + u) * a.n + i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double* v = a.values + ((int64_t(a.t0 + tl + u) * nl) + lf[u]) * K;
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+                if (c < K) acc[c] = acc[c] + a.lr * v[c];
+        }
+    }
+    for (; tl < a.nt; ++tl) {
+        const uint32_t lf = a.leaves[int64_t(tl) * a.n + i];
+        const double* v = a.values + ((int64_t(a.t0 + tl) * nl) + lf) * K;
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c < K) acc[c] = acc[c] + a.lr * v[c];
+    }
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+        if (c < K) a.approx[int64_t(c) * a.n + i] = acc[c];
+}
+
+}  // namespace cbh
+
 using namespace cbh;
 
 extern "C" {
+
+int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride,
+                    int64_t n, int32_t n_features, int32_t K, int32_t n_trees, int32_t depth,
+                    const int32_t* split_feature, const int32_t* split_border,
+                    const double* leaf_values, double lr, double* approx, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n < (int64_t(1) << 40), "n must be in [0, 2^40)");
+    CBH_ARG(n_features >= 1, "n_features must be >= 1");
+    CBH_REQUIRE(K >= 1 && K <= CBH_MAX_K, CBH_EUNSUPPORTED, "K must be in [1, 16] (got %d)", K);
+    CBH_ARG(n_trees >= 0, "n_trees must be >= 0");
+    CBH_REQUIRE(depth >= 1 && depth <= CBH_MAX_DEPTH, CBH_EUNSUPPORTED,
+                "depth must be in [1, 16] (got %d)", depth);
+    CBH_ARG(std::isfinite(lr), "lr must be finite");
+    if (n == 0 || n_trees == 0) return CBH_OK;
+    CBH_ARG(bins && split_feature && split_border && leaf_values && approx, "NULL argument");
+    // one thread per row in the summing launch: the grid must stay below 2^31
+    CBH_REQUIRE(n < (int64_t(1) << 38), CBH_EUNSUPPORTED, "n must be < 2^38");
+    // trees per chunk: their leaves ([chunk][n] uint16) stay within 256 MB of
+    // workspace
+    const int64_t per = std::max<int64_t>(1, (int64_t(256) << 20) / (2 * n));
+    const int32_t chunk = (int32_t)std::min<int64_t>({int64_t(n_trees), per, 65535});
+    int rc = ensure_ws(ctx, int64_t(chunk) * n * 2);
+    if (rc) return rc;
+    ApplyArgs a;
+    a.bins = bins;
+    a.seg = seg_stride;
+    a.n = n;
+    a.F = n_features;
+    a.K = K;
+    a.d = depth;
+    a.feat = split_feature;
+    a.border = split_border;
+    a.values = leaf_values;
+    a.lr = lr;
+    a.approx = approx;
+    a.leaves = (uint16_t*)ctx->ws;
+    a.flags = ctx->d_flags;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t t0 = 0; t0 < n_trees; t0 += chunk) {
+        a.t0 = t0;
+        a.nt = std::min(chunk, n_trees - t0);
+        model_leaves_kernel<<<dim3((unsigned)((n + 1023) / 1024), (unsigned)a.nt), 256, 0, s>>>(a);
+        CBH_LAUNCHED();
+        const unsigned grid = (unsigned)((n + 255) / 256);
+        if (K == 1) model_sum_kernel<1><<<grid, 256, 0, s>>>(a);
+        else model_sum_kernel<CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        CBH_LAUNCHED();
+    }
+    return CBH_OK;
+}
 
 int cbh_apply_split(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, const cbh_split* best,
                     void* stream) {
