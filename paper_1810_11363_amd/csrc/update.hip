@@ -283,9 +283,11 @@ namespace cbh {
 //                        load per level gives their 4 bins; the tree's splits
 //                        are the same for the whole block, so they and the
 //                        column pointers come through scalar loads) and
-//                        stores them as uint16 [tree][row];
+//                        stores them as [tree][row] (uint8 up to depth 8,
+//                        else uint16);
 //   model_sum_kernel     one thread per row adds the chunk's trees in order,
-//                        8 trees' leaves and values loaded before their adds.
+//                        16 (one class) or 8 trees' leaves and values loaded
+//                        before their adds.
 // Every (tree, row) leaf is independent, so the first launch has T x n / 4
 // threads of work where a single pass over the rows would have n / 4, each
 // walking the whole model.
@@ -299,10 +301,11 @@ struct ApplyArgs {
     const double* values;
     double lr;
     double* approx;
-    uint16_t* leaves;              // [nt][n]
+    void* leaves;                  // [nt][n] of LT: uint8 for depth <= 8, else uint16
     uint32_t* flags;
 };
 
+template <typename LT>
 __global__ __launch_bounds__(256) void model_leaves_kernel(ApplyArgs a) {
     const int64_t i0 = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
     const int tl = blockIdx.y;
@@ -330,16 +333,19 @@ __global__ __launch_bounds__(256) void model_leaves_kernel(ApplyArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) lf[r] |= ((int)((w >> (8 * r)) & 255u) > k ? 1u : 0u) << l;
     }
-    uint16_t* out = a.leaves + int64_t(tl) * a.n + i0;
-    if (nr == 4 && ((reinterpret_cast<uintptr_t>(out) & 7) == 0)) {
-        *reinterpret_cast<uint2*>(out) = make_uint2(lf[0] | (lf[1] << 16), lf[2] | (lf[3] << 16));
+    LT* out = reinterpret_cast<LT*>(a.leaves) + int64_t(tl) * a.n + i0;
+    if (nr == 4 && ((reinterpret_cast<uintptr_t>(out) & (4 * sizeof(LT) - 1)) == 0)) {
+        if constexpr (sizeof(LT) == 1)
+            *reinterpret_cast<uint32_t*>(out) = lf[0] | (lf[1] << 8) | (lf[2] << 16) | (lf[3] << 24);
+        else
+            *reinterpret_cast<uint2*>(out) = make_uint2(lf[0] | (lf[1] << 16), lf[2] | (lf[3] << 16));
     } else {
-        for (int r = 0; r < nr; ++r) out[r] = (uint16_t)lf[r];
+        for (int r = 0; r < nr; ++r) out[r] = (LT)lf[r];
     }
     if (bad && threadIdx.x == 0 && blockIdx.x == 0) atomicOr(a.flags, FLAG_BAD_SPLIT);
 }
 
-template <int KC>
+template <typename LT, int KC>
 __global__ __launch_bounds__(256) void model_sum_kernel(ApplyArgs a) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= a.n) return;
@@ -348,12 +354,13 @@ __global__ __launch_bounds__(256) void model_sum_kernel(ApplyArgs a) {
     double acc[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[c] = c < K ? a.approx[int64_t(c) * a.n + i] : 0.0;
-    constexpr int U = 8;
+    const LT* leaves = reinterpret_cast<const LT*>(a.leaves);
+    constexpr int U = KC == 1 ? 16 : 8;
     int tl = 0;
     for (; tl + U <= a.nt; tl += U) {
         uint32_t lf[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) lf[u] = a.leaves[int64_t(tl + u) * a.n + i];
+        for (int u = 0; u < U; ++u) lf[u] = leaves[int64_t(tl + u) * a.n + i];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const double* v = a.values + ((int64_t(a.t0 + tl + u) * nl) + lf[u]) * K;
@@ -363,7 +370,7 @@ __global__ __launch_bounds__(256) void model_sum_kernel(ApplyArgs a) {
         }
     }
     for (; tl < a.nt; ++tl) {
-        const uint32_t lf = a.leaves[int64_t(tl) * a.n + i];
+        const uint32_t lf = leaves[int64_t(tl) * a.n + i];
         const double* v = a.values + ((int64_t(a.t0 + tl) * nl) + lf) * K;
 #pragma unroll
         for (int c = 0; c < KC; ++c)
@@ -397,11 +404,12 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
     CBH_ARG(bins && split_feature && split_border && leaf_values && approx, "NULL argument");
     // one thread per row in the summing launch: the grid must stay below 2^31
     CBH_REQUIRE(n < (int64_t(1) << 38), CBH_EUNSUPPORTED, "n must be < 2^38");
-    // trees per chunk: their leaves ([chunk][n] uint16) stay within 256 MB of
-    // workspace
-    const int64_t per = std::max<int64_t>(1, (int64_t(256) << 20) / (2 * n));
+    // trees per chunk: their leaves ([chunk][n], one byte each up to depth 8,
+    // else two) stay within 256 MB of workspace
+    const int64_t lb = depth <= 8 ? 1 : 2;
+    const int64_t per = std::max<int64_t>(1, (int64_t(256) << 20) / (lb * n));
     const int32_t chunk = (int32_t)std::min<int64_t>({int64_t(n_trees), per, 65535});
-    int rc = ensure_ws(ctx, int64_t(chunk) * n * 2);
+    int rc = ensure_ws(ctx, int64_t(chunk) * n * lb);
     if (rc) return rc;
     ApplyArgs a;
     a.bins = bins;
@@ -415,17 +423,25 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
     a.values = leaf_values;
     a.lr = lr;
     a.approx = approx;
-    a.leaves = (uint16_t*)ctx->ws;
+    a.leaves = ctx->ws;
     a.flags = ctx->d_flags;
     hipStream_t s = (hipStream_t)stream;
     for (int32_t t0 = 0; t0 < n_trees; t0 += chunk) {
         a.t0 = t0;
         a.nt = std::min(chunk, n_trees - t0);
-        model_leaves_kernel<<<dim3((unsigned)((n + 1023) / 1024), (unsigned)a.nt), 256, 0, s>>>(a);
-        CBH_LAUNCHED();
+        const dim3 lg((unsigned)((n + 1023) / 1024), (unsigned)a.nt);
         const unsigned grid = (unsigned)((n + 255) / 256);
-        if (K == 1) model_sum_kernel<1><<<grid, 256, 0, s>>>(a);
-        else model_sum_kernel<CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        if (lb == 1) {
+            model_leaves_kernel<uint8_t><<<lg, 256, 0, s>>>(a);
+            CBH_LAUNCHED();
+            if (K == 1) model_sum_kernel<uint8_t, 1><<<grid, 256, 0, s>>>(a);
+            else model_sum_kernel<uint8_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        } else {
+            model_leaves_kernel<uint16_t><<<lg, 256, 0, s>>>(a);
+            CBH_LAUNCHED();
+            if (K == 1) model_sum_kernel<uint16_t, 1><<<grid, 256, 0, s>>>(a);
+            else model_sum_kernel<uint16_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        }
         CBH_LAUNCHED();
     }
     return CBH_OK;
