@@ -204,6 +204,17 @@ def apply_model(bins, feat, border, values, lr: float, approx):
     return approx
 
 
+def combine_categories(cat_a, cat_b):
+    """Dense ids of category pairs (the perfect hash of feature combinations,
+    Sec. 2): equal pairs share an id, ids 0..m-1 in increasing order of
+    ((uint32) a, (uint32) b). Returns (ids int32 [n], m)."""
+    a = np.ascontiguousarray(cat_a, np.int32).view(np.uint32).astype(np.uint64)
+    b = np.ascontiguousarray(cat_b, np.int32).view(np.uint32).astype(np.uint64)
+    key = (a << np.uint64(32)) | b
+    uniq, inv = np.unique(key, return_inverse=True)
+    return inv.astype(np.int32).reshape(-1), int(uniq.size)
+
+
 def grad_codes(g32, h32, with_h: bool):
     """int16 gradient codes with per-class scales (float32 decisions)."""
     g32 = _c(g32, np.float32)

@@ -490,3 +490,41 @@ def test_apply_model_splits_over_trees_and_classes(oracle_lib):
     c = np.zeros((K, n))
     o.apply_model(bins, feat, border, v2, 0.1, c)
     assert np.array_equal(c[[0, 2]], a[[0, 2]]) and not c[1].any()
+
+
+# ------------------------------------------------------ category combinations
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_combine_categories_brute_force(oracle_lib, seed):
+    """Sec. 2 "Feature combinations": a pair of categorical values is a new
+    category. Brute force: the sorted set of distinct pairs (as unsigned 32-bit
+    values) numbers them; every row gets its pair's rank."""
+    o = oracle_lib
+    g0 = np.random.default_rng(40 + seed)
+    n = int(g0.integers(1, 60))
+    a = g0.choice(np.array([-3, 0, 2, 7, 2 ** 31 - 1, -(2 ** 31)], np.int32), n)
+    b = g0.integers(-2, 3, n).astype(np.int32)
+    ids, m = o.combine_categories(a, b)
+    u32 = lambda v: int(v) & 0xffffffff
+    pairs = sorted({(u32(x), u32(y)) for x, y in zip(a, b)})
+    rank = {p: i for i, p in enumerate(pairs)}
+    assert m == len(pairs)
+    assert [rank[(u32(x), u32(y))] for x, y in zip(a, b)] == ids.tolist()
+
+
+def test_combine_categories_ts_groups(oracle_lib):
+    """The ordered statistics of the combination (Eq. 1 over its ids) count
+    exactly the earlier rows that share both values."""
+    o = oracle_lib
+    g0 = np.random.default_rng(44)
+    n = 200
+    a = g0.integers(0, 4, n).astype(np.int32)
+    b = g0.integers(0, 3, n).astype(np.int32)
+    y = g0.integers(0, 2, n).astype(np.int64)
+    perm = g0.permutation(n).astype(np.int32)
+    ids, _ = o.combine_categories(a, b)
+    num, den, _, _ = o.ordered_ts(ids, perm, y, 0, 1.0, 0.5)
+    for p in range(n):
+        r = perm[p]
+        prev = perm[:p]
+        same = prev[(a[prev] == a[r]) & (b[prev] == b[r])]
+        assert den[r] == same.size and num[r] == y[same].sum()
