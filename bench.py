@@ -80,6 +80,8 @@ WORKLOADS = {
     "c5": dict(tag="c5_50m_multiclass", n=50_000_000, steps=3, cpu_rows=100_000, cpu_trees=1,
                warmup=1, hist_trees=2, autotune="off", compare="fp32", warmup_s=0.0),
     "apply": dict(tag="apply_100k_8000_trees", n=100_000, steps=20, cpu_rows=20_000, cpu_trees=0),
+    "combine": dict(tag="combine_10m_pairs", n=10_000_000, steps=10, cpu_rows=1_000_000,
+                    cpu_trees=0),
 }
 # per-run defaults a workload may override
 RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,int16", warmup_s=1.0)
@@ -678,6 +680,103 @@ def run_apply(args):
     print(json.dumps(out), flush=True)
 
 
+def run_combine(args):
+    """Feature combinations (Sec. 2; perfect hashes by radix sort, Sec. 5): the
+    dense ids of a pair of categorical features and the ordered statistics of
+    the combination for one permutation. Columns of the shape of the large
+    workload's categorical features: cardinalities 10^3 and 10^6, Zipf(1.05)
+    frequencies. One step = cbh_combine_categories + cbh_compute_ordered_ts
+    (one 0/1 target, no bins)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    from paper_1810_11363_amd import cbhip as cb
+    n = args.n
+    g = np.random.default_rng(1810)
+    a = datagen.zipf_ids(g, n, 1000, 1.05).astype(np.int32)
+    b = datagen.zipf_ids(g, n, 1_000_000, 1.05).astype(np.int32)
+    y = (g.random(n) < 0.3).astype(np.int64)
+    perm = g.permutation(n).astype(np.int32)
+    dev = torch.device("cuda:0")
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    dy, dp = torch.from_numpy(y).to(dev), torch.from_numpy(perm).to(dev)
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    m = torch.empty(1, dtype=torch.int64, device=dev)
+    num = torch.empty(n, dtype=torch.int64, device=dev)
+    den = torch.empty(n, dtype=torch.int32, device=dev)
+    ts = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx = cb.cbh_create(0)
+
+    def step():
+        cb.cbh_combine_categories(ctx, da, db, n, ids, m)
+        cb.cbh_compute_ordered_ts(ctx, ids, dp, n, dy, 1, 0, 1, 1.0, [0.3], None, 0,
+                                  num_out=num, den_out=den, ts_out=ts)
+
+    for _ in range(2):
+        step()
+    cb.cbh_sync(ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        cb.cbh_combine_categories(ctx, da, db, n, ids, m)
+    e1.record()
+    for _ in range(args.steps):
+        step()
+    e2.record()
+    cb.cbh_sync(ctx)
+    torch.cuda.synchronize()
+    comb = e0.elapsed_time(e1) / 1e3 / args.steps
+    sec = e1.elapsed_time(e2) / 1e3 / args.steps
+    got_ids = ids.cpu().numpy()
+    got_ts = ts.cpu().numpy()
+    n_distinct = int(m.item())
+    cb.cbh_destroy(ctx)
+    rid, rm = oracle.combine_categories(a, b)
+    parity_ids = bool(rm == n_distinct and np.array_equal(got_ids, rid))
+    # the oracle on a row sample: combination ids and the statistics
+    k = min(n, args.cpu_rows)
+    sp = np.random.default_rng(1811).permutation(k).astype(np.int32)
+    t0 = time.perf_counter()
+    sid, _ = oracle.combine_categories(a[:k], b[:k])
+    _, _, st, _ = oracle.ordered_ts(sid, sp, y[:k], 0, 1.0, 0.3)
+    cpu_s = time.perf_counter() - t0
+    algo_bytes = 8 * n + 4 * n                     # the two columns in, the ids out
+    out = {
+        "metric": "feature combination: pair ids + ordered statistics (rows per second)",
+        "value": round(n / sec / 1e6, 2),
+        "unit": "M rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "ms_per_step": round(sec * 1e3, 4),
+        "combine_ms": round(comb * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32/int64/f64",
+        "data": "synthetic",
+        "config": {"workload": f"pair of categorical columns, {n} rows, cardinalities 1e3 and "
+                               f"1e6, Zipf(1.05); {n_distinct} distinct pairs; one permutation, "
+                               f"one 0/1 target",
+                   "rows": n, "distinct_pairs": n_distinct},
+        "parity": {"ids_bit_exact": parity_ids},
+        "roofline": {"bound": "hbm", "achieved": round(algo_bytes / comb / 1e9, 1),
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(algo_bytes / comb / 1e9 / 8000.0, 4), "traffic": None,
+                     "kernel": "cbh_combine_categories (8 radix passes + scan)",
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": round(comb * 1e3, 4)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = {"value": round(k / cpu_s / 1e6, 3), "unit": "M rows/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {k} of {n} rows; oracle {cpu_s:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5):
     """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
     MiB: the bandwidth a streaming kernel reaches on this GPU."""
@@ -763,6 +862,9 @@ def main():
         return
     if args.workload == "apply":
         run_apply(args)
+        return
+    if args.workload == "combine":
+        run_combine(args)
         return
 
     import torch  # noqa: F401

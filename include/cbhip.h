@@ -255,6 +255,25 @@ int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm
                            int32_t n_ts_borders, int64_t* num_out, int32_t* den_out,
                            uint8_t* ts_bin_out, double* ts_out, void* stream);
 
+/* Dense ids of category pairs: the perfect hash the paper uses for
+ * combinations of categorical features (Sec. 2, "Feature combinations": the
+ * values of a combination are numbered on the fly; Sec. 5, "Categorical
+ * features": the perfect hashes are built with a radix sort). The
+ * combination's ordered statistics are then those of one categorical
+ * feature, see cbh_compute_ordered_ts. Rows with equal (cat_a, cat_b) get equal ids,
+ * rows with different pairs different ids; the ids are 0 .. n_distinct - 1
+ * in increasing order of the pair compared as unsigned 32-bit values
+ * ((uint32)cat_a first, then (uint32)cat_b). Combinations of more features
+ * chain the call: combine(combine(a, b), c).
+ *   cat_a, cat_b    device int32 [n]: raw category values (any int32)
+ *   n               0 .. 2^31 - 1 (0: nothing to do)
+ *   ids_out         device int32 [n]
+ *   n_distinct_out  device int64 [1]: number of distinct pairs
+ * Uses workspace of about 40 * n bytes. Errors: CBH_EINVAL on NULL or n out
+ * of range. */
+int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* cat_b, int64_t n,
+                           int32_t* ids_out, int64_t* n_distinct_out, void* stream);
+
 /* ---- per-tree and per-level calls (the split search) -------------------- */
 
 /* int16 gradient codes for CBH_PREC_INT16: per class, s_g = max|g| / 32767

@@ -34,7 +34,7 @@ EXPORTS = [
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
-    "cbh_apply_model",
+    "cbh_apply_model", "cbh_combine_categories",
 ]
 
 
@@ -94,6 +94,7 @@ def _load():
                               C.c_int),
         "cbh_apply_model": ([vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp],
                             C.c_int),
+        "cbh_combine_categories": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
         "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
@@ -369,3 +370,9 @@ def cbh_set_hist_knobs(ctx, lds_budget=0, target_blocks=512, min_rows=32768, par
 
 def cbh_autotune_load(ctx, cache_path: str):
     return _check(_lib.cbh_autotune_load(ctx, cache_path.encode()))
+
+
+def cbh_combine_categories(ctx, cat_a, cat_b, n: int, ids_out, n_distinct_out, stream=None):
+    return _check(_lib.cbh_combine_categories(ctx, _ptr(cat_a), _ptr(cat_b), int(n),
+                                              _ptr(ids_out), _ptr(n_distinct_out),
+                                              _stream(stream)))

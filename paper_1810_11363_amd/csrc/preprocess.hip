@@ -342,6 +342,55 @@ __global__ __launch_bounds__(256) void tile_bins_kernel(const uint8_t* const* __
     }
 }
 
+// Dense ids of category pairs, the perfect hash the paper applies to
+// combinations of categorical features (Sec. 2, "Feature combinations": the
+// values of a combination get ids on the fly; Sec. 5, "Categorical
+// features": perfect hashes built with a radix sort). The combination's
+// ordered statistics are then computed like those of one feature. Rows are sorted by (a, b) as unsigned 32-bit values with two
+// rounds of the stable LSD radix sort (by b, then by a), a row starts a new
+// id where its pair differs from the previous row's, and an exclusive scan
+// of those starts numbers the ids in increasing pair order.
+__global__ void pair_first_keys_kernel(const int32_t* __restrict__ b, int64_t n,
+                                       uint32_t* __restrict__ keys, int32_t* __restrict__ rows) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        keys[i] = (uint32_t)b[i];
+        rows[i] = (int32_t)i;
+    }
+}
+
+__global__ void pair_second_keys_kernel(const int32_t* __restrict__ a,
+                                        const int32_t* __restrict__ rows, int64_t n,
+                                        uint32_t* __restrict__ keys) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x)
+        keys[p] = (uint32_t)a[rows[p]];
+}
+
+__global__ void pair_heads_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                  const int32_t* __restrict__ rows, int64_t n,
+                                  int64_t* __restrict__ head) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        int64_t h = 1;
+        if (p > 0) {
+            const int32_t r = rows[p], q = rows[p - 1];
+            h = (a[r] != a[q] || b[r] != b[q]) ? 1 : 0;
+        }
+        head[p] = h;
+    }
+}
+
+__global__ void pair_ids_kernel(const int32_t* __restrict__ rows, const int64_t* __restrict__ head,
+                                const int64_t* __restrict__ excl, int64_t n,
+                                int32_t* __restrict__ ids, int64_t* __restrict__ n_distinct) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        ids[rows[p]] = (int32_t)(excl[p] + head[p] - 1);
+        if (p == n - 1) *n_distinct = excl[p] + head[p];
+    }
+}
+
 static int grid_for(int64_t n, int per_block, int cap = 16384) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -482,6 +531,77 @@ int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm
             ts_out ? ts_out + int64_t(t) * n : nullptr);
         CBH_LAUNCHED();
     }
+    return CBH_OK;
+}
+
+int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* cat_b, int64_t n,
+                           int32_t* ids_out, int64_t* n_distinct_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(cat_a && cat_b && ids_out && n_distinct_out, "NULL argument");
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    const int64_t cnt_elems = 256 * n_tiles;
+    const int64_t cnt_tiles = (cnt_elems + kTile - 1) / kTile;
+    const int64_t max_tiles = std::max(n_tiles, cnt_tiles);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = off; off += align_up(bytes, 256); return o; };
+    const int64_t o_k0 = take(4 * n), o_k1 = take(4 * n), o_v0 = take(4 * n),
+                  o_v1 = take(4 * n), o_head = take(8 * n), o_excl = take(8 * n),
+                  o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
+                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
+    int rc = ensure_ws(ctx, off);
+    if (rc != CBH_OK) return rc;
+    char* w = (char*)ctx->ws;
+    uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
+    int32_t* rows[2] = {(int32_t*)(w + o_v0), (int32_t*)(w + o_v1)};
+    int64_t* head = (int64_t*)(w + o_head);
+    int64_t* excl = (int64_t*)(w + o_excl);
+    int64_t* counts = (int64_t*)(w + o_cnt);
+    int64_t* offs = (int64_t*)(w + o_off);
+    SegPair* agg = (SegPair*)(w + o_agg);
+    int64_t* car = (int64_t*)(w + o_car);
+    hipStream_t s = (hipStream_t)stream;
+    auto scan = [&](const int64_t* values, int64_t len, int64_t* out) -> int {
+        const int64_t tiles = (len + kTile - 1) / kTile;
+        const ScanSrc src{0, values, nullptr, nullptr, nullptr};
+        seg_reduce_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, agg);
+        seg_carry_kernel<<<1, 256, 0, s>>>(agg, tiles, car);
+        seg_scan_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, car, out);
+        CBH_LAUNCHED();
+        return CBH_OK;
+    };
+    int cur = 0;
+    auto sort32 = [&]() -> int {
+        for (int shift = 0; shift < 32; shift += 8) {
+            radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], n, shift,
+                                                                          n_tiles, counts);
+            CBH_LAUNCHED();
+            int r = scan(counts, cnt_elems, offs);
+            if (r != CBH_OK) return r;
+            radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
+                keys[cur], rows[cur], n, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1]);
+            CBH_LAUNCHED();
+            cur ^= 1;
+        }
+        return CBH_OK;
+    };
+    const int gs = grid_for(n, 256, ctx->num_cus * 8);
+    pair_first_keys_kernel<<<gs, 256, 0, s>>>(cat_b, n, keys[0], rows[0]);
+    CBH_LAUNCHED();
+    rc = sort32();                       // rows by b
+    if (rc != CBH_OK) return rc;
+    pair_second_keys_kernel<<<gs, 256, 0, s>>>(cat_a, rows[cur], n, keys[cur]);
+    CBH_LAUNCHED();
+    rc = sort32();                       // then stably by a: rows by (a, b)
+    if (rc != CBH_OK) return rc;
+    pair_heads_kernel<<<gs, 256, 0, s>>>(cat_a, cat_b, rows[cur], n, head);
+    CBH_LAUNCHED();
+    rc = scan(head, n, excl);
+    if (rc != CBH_OK) return rc;
+    pair_ids_kernel<<<gs, 256, 0, s>>>(rows[cur], head, excl, n, ids_out, n_distinct_out);
+    CBH_LAUNCHED();
     return CBH_OK;
 }
 

@@ -653,3 +653,63 @@ def test_workspace_limit(cb):
     finally:
         torch.cuda.synchronize()
         cb.cbh_destroy(c)
+
+
+# ------------------------------------------------------ category combinations
+def _combine_gpu(cb, ctx, a, b):
+    dev = gu.dev()
+    n = a.size
+    da = torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(dev)
+    db = torch.from_numpy(np.ascontiguousarray(b, np.int32)).to(dev)
+    ids = torch.full((max(n, 1),), -1, dtype=torch.int32, device=dev)
+    m = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    cb.cbh_combine_categories(ctx, da, db, n, ids, m)
+    cb.cbh_sync(ctx)
+    return ids[:n].cpu().numpy(), int(m.item())
+
+
+@pytest.mark.parametrize("n,Ca,Cb", [(1, 1, 1), (5, 3, 2), (4095, 10, 10), (4096, 100, 7),
+                                     (4097, 4097, 3), (100003, 1000, 1000),
+                                     (300007, 50000, 20)])
+def test_combine_categories_bit_exact(cb, ctx, n, Ca, Cb):
+    g = np.random.default_rng(n + 7 * Ca + Cb)
+    va = g.choice(2**32, size=min(Ca, n), replace=False).astype(np.int64) - 2**31
+    vb = g.choice(2**32, size=min(Cb, n), replace=False).astype(np.int64) - 2**31
+    # Zipf-like category frequencies
+    pa = 1.0 / np.arange(1, va.size + 1) ** 1.1
+    a = va.astype(np.int32)[g.choice(va.size, n, p=pa / pa.sum())]
+    b = vb.astype(np.int32)[g.integers(0, vb.size, n)]
+    ids, m = _combine_gpu(cb, ctx, a, b)
+    rid, rm = oracle.combine_categories(a, b)
+    assert m == rm and np.array_equal(ids, rid)
+
+
+def test_combine_categories_chain_and_ts(cb, ctx):
+    """A three-feature combination by chaining, then its ordered statistics
+    (Eq. 1 over the combination's ids) on the GPU against the oracle."""
+    g = np.random.default_rng(5)
+    n = 60001
+    a = g.integers(0, 50, n).astype(np.int32)
+    b = g.integers(0, 20, n).astype(np.int32)
+    c = g.integers(-5, 5, n).astype(np.int32)
+    ab, _ = _combine_gpu(cb, ctx, a, b)
+    abc, m = _combine_gpu(cb, ctx, ab, c)
+    r_ab, _ = oracle.combine_categories(a, b)
+    r_abc, rm = oracle.combine_categories(r_ab, c)
+    assert m == rm and np.array_equal(abc, r_abc)
+    perm = g.permutation(n).astype(np.int32)
+    y = g.integers(0, 2, n).astype(np.int64)[None, :]
+    borders = oracle.ts_borders(0.0, 1.0, 15)
+    num, den, ts, tb = _ts_gpu(cb, ctx, abc, perm, y, 0, 1.0, [0.5], borders)
+    rn, rd, rt, rb = oracle.ordered_ts(r_abc, perm, y[0], 0, 1.0, 0.5, borders)
+    assert np.array_equal(num[0], rn) and np.array_equal(den, rd)
+    assert np.array_equal(ts[0], rt) and np.array_equal(tb[0], rb)
+
+
+def test_combine_categories_args(cb, ctx):
+    x = torch.zeros(8, dtype=torch.int32, device=gu.dev())
+    cb.cbh_combine_categories(ctx, None, None, 0, None, None)        # n = 0: nothing
+    with pytest.raises(cb.CbhError):
+        cb.cbh_combine_categories(ctx, x, None, 8, x, x)
+    with pytest.raises(cb.CbhError):
+        cb.cbh_combine_categories(ctx, x, x, -1, x, x)
