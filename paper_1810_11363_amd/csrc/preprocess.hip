@@ -367,18 +367,20 @@ __global__ void pair_second_keys_kernel(const int32_t* __restrict__ a,
         keys[p] = (uint32_t)a[rows[p]];
 }
 
-__global__ void pair_heads_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
-                                  const int32_t* __restrict__ rows, int64_t n,
-                                  int64_t* __restrict__ head) {
-    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
-         p += int64_t(gridDim.x) * blockDim.x) {
-        int64_t h = 1;
-        if (p > 0) {
-            const int32_t r = rows[p], q = rows[p - 1];
-            h = (a[r] != a[q] || b[r] != b[q]) ? 1 : 0;
-        }
-        head[p] = h;
-    }
+// A row starts a new id where its pair differs from the previous row's: a
+// comes sorted from the second sort; b is gathered once per row, and the
+// previous row's b comes from the neighbouring lane (first lane of a wave:
+// a second gather).
+__global__ __launch_bounds__(256) void pair_heads_kernel(const uint32_t* __restrict__ a_sorted,
+                                                         const int32_t* __restrict__ b,
+                                                         const int32_t* __restrict__ rows,
+                                                         int64_t n, int64_t* __restrict__ head) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool act = p < n;
+    const int32_t bp = act ? b[rows[p]] : 0;
+    int32_t bq = __shfl_up(bp, 1, 64);
+    if (act && p > 0 && (threadIdx.x & 63) == 0) bq = b[rows[p - 1]];
+    if (act) head[p] = (p == 0 || a_sorted[p] != a_sorted[p - 1] || bp != bq) ? 1 : 0;
 }
 
 __global__ void pair_ids_kernel(const int32_t* __restrict__ rows, const int64_t* __restrict__ head,
@@ -596,7 +598,8 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
     CBH_LAUNCHED();
     rc = sort32();                       // then stably by a: rows by (a, b)
     if (rc != CBH_OK) return rc;
-    pair_heads_kernel<<<gs, 256, 0, s>>>(cat_a, cat_b, rows[cur], n, head);
+    pair_heads_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(keys[cur], cat_b, rows[cur],
+                                                                   n, head);
     CBH_LAUNCHED();
     rc = scan(head, n, excl);
     if (rc != CBH_OK) return rc;
