@@ -686,7 +686,7 @@ def run_combine(args):
     the combination for one permutation. Columns of the shape of the large
     workload's categorical features: cardinalities 10^3 and 10^6, Zipf(1.05)
     frequencies. One step = cbh_combine_categories + cbh_compute_ordered_ts
-    (one 0/1 target, no bins)."""
+    (one 0/1 target, no bins) + cbh_category_counts."""
     import numpy as np
     import torch
 
@@ -707,12 +707,14 @@ def run_combine(args):
     num = torch.empty(n, dtype=torch.int64, device=dev)
     den = torch.empty(n, dtype=torch.int32, device=dev)
     ts = torch.empty(n, dtype=torch.float64, device=dev)
+    cnt = torch.empty(n, dtype=torch.int32, device=dev)
     ctx = cb.cbh_create(0)
 
     def step():
         cb.cbh_combine_categories(ctx, da, db, n, ids, m)
         cb.cbh_compute_ordered_ts(ctx, ids, dp, n, dy, 1, 0, 1, 1.0, [0.3], None, 0,
                                   num_out=num, den_out=den, ts_out=ts)
+        cb.cbh_category_counts(ctx, ids, n, cnt)
 
     for _ in range(2):
         step()
@@ -732,11 +734,13 @@ def run_combine(args):
     comb = e0.elapsed_time(e1) / 1e3 / args.steps
     sec = e1.elapsed_time(e2) / 1e3 / args.steps
     got_ids = ids.cpu().numpy()
+    got_cnt = cnt.cpu().numpy()
     got_ts = ts.cpu().numpy()
     n_distinct = int(m.item())
     cb.cbh_destroy(ctx)
     rid, rm = oracle.combine_categories(a, b)
     parity_ids = bool(rm == n_distinct and np.array_equal(got_ids, rid))
+    parity_cnt = bool(np.array_equal(got_cnt, oracle.category_counts(rid)))
     # the oracle on a row sample: combination ids and the statistics
     k = min(n, args.cpu_rows)
     sp = np.random.default_rng(1811).permutation(k).astype(np.int32)
@@ -746,7 +750,7 @@ def run_combine(args):
     cpu_s = time.perf_counter() - t0
     algo_bytes = 8 * n + 4 * n                     # the two columns in, the ids out
     out = {
-        "metric": "feature combination: pair ids + ordered statistics (rows per second)",
+        "metric": "feature combination: pair ids + ordered statistics + counts (rows/s)",
         "value": round(n / sec / 1e6, 2),
         "unit": "M rows/s",
         "n_gpus": 1,
@@ -762,7 +766,7 @@ def run_combine(args):
                                f"1e6, Zipf(1.05); {n_distinct} distinct pairs; one permutation, "
                                f"one 0/1 target",
                    "rows": n, "distinct_pairs": n_distinct},
-        "parity": {"ids_bit_exact": parity_ids},
+        "parity": {"ids_bit_exact": parity_ids, "counts_bit_exact": parity_cnt},
         "roofline": {"bound": "hbm", "achieved": round(algo_bytes / comb / 1e9, 1),
                      "peak": 8000.0, "unit": "GB/s",
                      "frac": round(algo_bytes / comb / 1e9 / 8000.0, 4), "traffic": None,

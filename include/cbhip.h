@@ -274,6 +274,19 @@ int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm
 int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* cat_b, int64_t n,
                            int32_t* ids_out, int64_t* n_distinct_out, void* stream);
 
+/* The counter statistic (Sec. 2, "Feature combinations": a category, or a
+ * combination, replaced by the number of its appearances in the dataset):
+ *   counts_out[i] = #{ j : ids[j] == ids[i] }.
+ *   ids         device int32 [n], dense ids in [0, n) (for instance from
+ *               cbh_combine_categories); an id outside [0, n) is counted
+ *               nowhere, gets count 0, and is reported by cbh_sync
+ *   n           0 .. 2^31 - 1 (0: nothing to do)
+ *   counts_out  device int32 [n]
+ * Uses workspace of 4 * n bytes. Errors: CBH_EINVAL on NULL or n out of
+ * range. */
+int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* counts_out,
+                        void* stream);
+
 /* ---- per-tree and per-level calls (the split search) -------------------- */
 
 /* int16 gradient codes for CBH_PREC_INT16: per class, s_g = max|g| / 32767

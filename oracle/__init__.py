@@ -215,6 +215,12 @@ def combine_categories(cat_a, cat_b):
     return inv.astype(np.int32).reshape(-1), int(uniq.size)
 
 
+def category_counts(ids):
+    """The counter statistic (Sec. 2): each row's number of rows with its id."""
+    ids = np.ascontiguousarray(ids, np.int64).reshape(-1)
+    return np.bincount(ids, minlength=1)[ids].astype(np.int32)
+
+
 def grad_codes(g32, h32, with_h: bool):
     """int16 gradient codes with per-class scales (float32 decisions)."""
     g32 = _c(g32, np.float32)

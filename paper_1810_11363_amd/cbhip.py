@@ -34,7 +34,7 @@ EXPORTS = [
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
-    "cbh_apply_model", "cbh_combine_categories",
+    "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts",
 ]
 
 
@@ -95,6 +95,7 @@ def _load():
         "cbh_apply_model": ([vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp],
                             C.c_int),
         "cbh_combine_categories": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
+        "cbh_category_counts": ([vp, vp, i64, vp, vp], C.c_int),
         "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
@@ -376,3 +377,8 @@ def cbh_combine_categories(ctx, cat_a, cat_b, n: int, ids_out, n_distinct_out, s
     return _check(_lib.cbh_combine_categories(ctx, _ptr(cat_a), _ptr(cat_b), int(n),
                                               _ptr(ids_out), _ptr(n_distinct_out),
                                               _stream(stream)))
+
+
+def cbh_category_counts(ctx, ids, n: int, counts_out, stream=None):
+    return _check(_lib.cbh_category_counts(ctx, _ptr(ids), int(n), _ptr(counts_out),
+                                           _stream(stream)))

@@ -393,6 +393,58 @@ __global__ void pair_ids_kernel(const int32_t* __restrict__ rows, const int64_t*
     }
 }
 
+// The counter statistic (Sec. 2: a category, or a combination of
+// categories, replaced by its number of appearances in the dataset): per
+// dense id, the number of rows that carry it, then that count per row.
+__global__ void zero_i32_kernel(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+// Frequent ids (a Zipf-distributed category) would serialise many atomics
+// on one address: the lanes of a wave that share the id of its first
+// pending lane add their count with one atomic, up to four ids per wave
+// step; the rest add one each.
+__global__ void id_count_kernel(const int32_t* __restrict__ ids, int64_t n,
+                                int32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
+    bool bad = false;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t v = ids[i];
+        bool pending = true;
+        if (v < 0 || v >= n) {
+            bad = true;
+            pending = false;
+        }
+        for (int it = 0; it < 4; ++it) {
+            const uint64_t act = __ballot(pending);
+            if (act == 0) break;
+            const int leader = __ffsll((unsigned long long)act) - 1;
+            const int32_t lv = __shfl(v, leader, 64);
+            const bool mine = pending && v == lv;
+            const uint64_t same = __ballot(mine);
+            if (mine) {
+                if (lane == leader) atomicAdd(&cnt[lv], (int32_t)__popcll(same));
+                pending = false;
+            }
+        }
+        if (pending) atomicAdd(&cnt[v], 1);
+    }
+    if (bad) atomicOr(flags, FLAG_BAD_INDEX);
+}
+
+__global__ void id_count_gather_kernel(const int32_t* __restrict__ ids, int64_t n,
+                                       const int32_t* __restrict__ cnt,
+                                       int32_t* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t v = ids[i];
+        out[i] = (v >= 0 && v < n) ? cnt[v] : 0;
+    }
+}
+
 static int grid_for(int64_t n, int per_block, int cap = 16384) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -604,6 +656,27 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
     rc = scan(head, n, excl);
     if (rc != CBH_OK) return rc;
     pair_ids_kernel<<<gs, 256, 0, s>>>(rows[cur], head, excl, n, ids_out, n_distinct_out);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* counts_out,
+                        void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(ids && counts_out, "NULL argument");
+    int rc = ensure_ws(ctx, 4 * n);
+    if (rc != CBH_OK) return rc;
+    int32_t* cnt = (int32_t*)ctx->ws;
+    hipStream_t s = (hipStream_t)stream;
+    const int gs = grid_for(n, 256, ctx->num_cus * 8);
+    zero_i32_kernel<<<gs, 256, 0, s>>>(cnt, n);
+    CBH_LAUNCHED();
+    id_count_kernel<<<gs, 256, 0, s>>>(ids, n, cnt, ctx->d_flags);
+    CBH_LAUNCHED();
+    id_count_gather_kernel<<<gs, 256, 0, s>>>(ids, n, cnt, counts_out);
     CBH_LAUNCHED();
     return CBH_OK;
 }

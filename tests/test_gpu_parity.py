@@ -713,3 +713,31 @@ def test_combine_categories_args(cb, ctx):
         cb.cbh_combine_categories(ctx, x, None, 8, x, x)
     with pytest.raises(cb.CbhError):
         cb.cbh_combine_categories(ctx, x, x, -1, x, x)
+
+
+@pytest.mark.parametrize("n,C", [(1, 1), (17, 3), (4097, 4097), (200003, 1000)])
+def test_category_counts_bit_exact(cb, ctx, n, C):
+    """Counter statistic of combination ids (Zipf-like: one very frequent id)."""
+    g = np.random.default_rng(n + C)
+    p = 1.0 / np.arange(1, C + 1) ** 1.05
+    a = g.choice(C, n, p=p / p.sum()).astype(np.int32)
+    b = g.integers(0, 3, n).astype(np.int32)
+    ids, m = _combine_gpu(cb, ctx, a, b)
+    dev = gu.dev()
+    di = torch.from_numpy(ids).to(dev)
+    out = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    cb.cbh_category_counts(ctx, di, n, out)
+    cb.cbh_sync(ctx)
+    rid, _ = oracle.combine_categories(a, b)
+    assert np.array_equal(out.cpu().numpy(), oracle.category_counts(rid))
+
+
+def test_category_counts_bad_id_reported(cb, ctx):
+    dev = gu.dev()
+    ids = torch.tensor([0, 1, 5, 1], dtype=torch.int32, device=dev)     # 5 >= n
+    out = torch.full((4,), -1, dtype=torch.int32, device=dev)
+    cb.cbh_category_counts(ctx, ids, 4, out)
+    with pytest.raises(cb.CbhError):
+        cb.cbh_sync(ctx)
+    cb.cbh_sync(ctx)
+    assert out.cpu().tolist() == [1, 2, 0, 2]

@@ -528,3 +528,14 @@ def test_combine_categories_ts_groups(oracle_lib):
         prev = perm[:p]
         same = prev[(a[prev] == a[r]) & (b[prev] == b[r])]
         assert den[r] == same.size and num[r] == y[same].sum()
+
+
+def test_category_counts_brute_force(oracle_lib):
+    """The counter statistic (Sec. 2): a row's value is the number of rows
+    that share its category, counted here pair by pair."""
+    o = oracle_lib
+    g0 = np.random.default_rng(45)
+    ids = g0.integers(0, 7, 60).astype(np.int32)
+    got = o.category_counts(ids)
+    assert [sum(1 for y in ids if y == x) for x in ids] == got.tolist()
+    assert got.sum() == sum(c * c for c in np.unique(ids, return_counts=True)[1])
