@@ -278,7 +278,7 @@ namespace cbh {
 // lr * v[t][leaf][c], tree after tree in model order (the additions of the
 // model updates that built the trees, in the same order and precision).
 // The model goes through in chunks of trees, two launches per chunk:
-//   model_leaves_kernel  one block row per tree of the chunk: each thread
+//   model_leaves_kernel  one block per (row block, tree of the chunk): each thread
 //                        finds the leaves of 4 consecutive rows (one 32-bit
 //                        load per level gives their 4 bins; the tree's splits
 //                        are the same for the whole block, so they and the
@@ -305,10 +305,15 @@ struct ApplyArgs {
     uint32_t* flags;
 };
 
+// Block b runs on XCD b mod 8. Row block rb (1024 rows) goes to XCD rb mod
+// 8 with all the chunk's trees in turn, so its bins of every feature (1 KB
+// per feature) stay in that XCD's L2 while the trees read them.
 template <typename LT>
 __global__ __launch_bounds__(256) void model_leaves_kernel(ApplyArgs a) {
-    const int64_t i0 = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
-    const int tl = blockIdx.y;
+    const int64_t j = blockIdx.x >> 3;
+    const int64_t rb = (j / a.nt) * 8 + (blockIdx.x & 7);
+    const int tl = (int)(j % a.nt);
+    const int64_t i0 = (rb * 256 + threadIdx.x) * 4;
     if (i0 >= a.n) return;
     const int nr = (int)min<int64_t>(4, a.n - i0);
     const int64_t t = a.t0 + tl;
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(256) void model_leaves_kernel(ApplyArgs a) {
     } else {
         for (int r = 0; r < nr; ++r) out[r] = (LT)lf[r];
     }
-    if (bad && threadIdx.x == 0 && blockIdx.x == 0) atomicOr(a.flags, FLAG_BAD_SPLIT);
+    if (bad && threadIdx.x == 0 && rb == 0) atomicOr(a.flags, FLAG_BAD_SPLIT);
 }
 
 template <typename LT, int KC>
@@ -408,7 +413,12 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
     // else two) stay within 256 MB of workspace
     const int64_t lb = depth <= 8 ? 1 : 2;
     const int64_t per = std::max<int64_t>(1, (int64_t(256) << 20) / (lb * n));
-    const int32_t chunk = (int32_t)std::min<int64_t>({int64_t(n_trees), per, 65535});
+    // the leaf launch has one block per (1024-row block, tree), row blocks
+    // padded to a multiple of 8: at most 2^31 - 1 blocks
+    const int64_t rblocks = align_up((n + 1023) / 1024, 8);
+    const int64_t per_grid = std::max<int64_t>(1, int64_t(INT32_MAX) / rblocks);
+    const int32_t chunk =
+        (int32_t)std::min<int64_t>({int64_t(n_trees), per, per_grid, 65535});
     int rc = ensure_ws(ctx, int64_t(chunk) * n * lb);
     if (rc) return rc;
     ApplyArgs a;
@@ -429,7 +439,7 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
     for (int32_t t0 = 0; t0 < n_trees; t0 += chunk) {
         a.t0 = t0;
         a.nt = std::min(chunk, n_trees - t0);
-        const dim3 lg((unsigned)((n + 1023) / 1024), (unsigned)a.nt);
+        const unsigned lg = (unsigned)(rblocks * a.nt);
         const unsigned grid = (unsigned)((n + 255) / 256);
         if (lb == 1) {
             model_leaves_kernel<uint8_t><<<lg, 256, 0, s>>>(a);
