@@ -400,6 +400,29 @@ class GpuBooster:
                 trees.append(self.tree_record())
         return trees
 
+    def predict(self, trees, approx=None) -> torch.Tensor:
+        """Apply recorded trees (`tree_record`, in fit order) to this booster's
+        rows with cbh_apply_model: approx [K][n] float64 on the device (zeros
+        when not given) gains lr * the tree's leaf value, tree after tree,
+        each tree reading the feature table of its own permutation. Applied
+        to the trees of `fit`, this gives the training approx bit for bit."""
+        d = self.device
+        if approx is None:
+            approx = torch.zeros((self.K, self.n), dtype=torch.float64, device=d)
+        for t, tr in enumerate(trees):
+            r = t % self.s
+            feat = tr.splits[:, 0].astype(np.int32).copy()
+            border = tr.splits[:, 1].astype(np.int32).copy()
+            none = (feat < 0) | (feat >= self.F)       # a level without a split sets no bit
+            feat[none], border[none] = 0, 255
+            df = torch.from_numpy(feat).to(d)
+            db = torch.from_numpy(border).to(d)
+            dv = torch.from_numpy(np.ascontiguousarray(tr.values, np.float64)).to(d)
+            seg = self.seg_table[r] if self.seg_table is not None else None
+            cb.cbh_apply_model(self.ctx, self.col_table[r], seg, self.n, self.F, self.K, 1,
+                               self.depth, df, db, dv, self.lr, approx, self.stream)
+        return approx
+
     def model_state(self, r: int) -> "ModelState":
         """A further model over permutation r's bins (see ModelState)."""
         return ModelState(self, r)

@@ -588,3 +588,19 @@ def test_full_size_sampled_deep(cb, name, prec):
         _sampled_tree_check(cb, bst, prec, 3, np.random.default_rng(7))
     finally:
         bst.close()
+
+
+@pytest.mark.parametrize("name,prec,partition", [("deep_small", 1, True), ("logloss_4097", 2, False),
+                                                 ("multiclass", 1, True), ("multiclass", 0, False)])
+def test_predict_reproduces_training_approx(cb, name, prec, partition):
+    """Applying the recorded trees of a GPU fit (cbh_apply_model, each tree on
+    its permutation's features) to the training rows gives the training
+    approx bit for bit: the same leaves and the same additions in order."""
+    p = PART_CASES[name]()
+    bst = _booster(cb, p, prec, partition=partition)
+    trees = bst.fit(6)
+    got = bst.predict(trees)
+    torch.cuda.synchronize()
+    cb.cbh_sync(bst.ctx)
+    assert np.array_equal(got.cpu().numpy(), bst.approx.cpu().numpy())
+    bst.close()
