@@ -9,7 +9,7 @@
 //
 // Kernel 1: one block per feature; each wave takes (leaf, class) rows of the
 // histogram, one lane per 4 consecutive bins, forms bin prefixes with a wave
-// scan, and accumulates the per-border terms in registers. The four waves'
+// scan, and accumulates the per-border terms in registers. The waves'
 // partial scores are added in wave order (deterministic), then the block
 // keeps its best and second-best border. The last block to finish (a
 // device counter, reset by that block, so the launch needs no clearing and
@@ -23,14 +23,17 @@
 
 namespace cbh {
 
-constexpr int kScoreWaves = 16;   // (leaf, class) rows in flight per feature
+// (leaf, class) rows in flight per feature: 16 waves once a feature has more
+// than 4 rows, else 4 (a smaller block for the short early levels)
+constexpr int kScoreWaves = 16;
+constexpr int kScoreWavesSmall = 4;
 
-template <int PREC>
-__global__ __launch_bounds__(64 * kScoreWaves) void score_split_kernel(
+template <int PREC, int NW>
+__global__ __launch_bounds__(64 * NW) void score_split_kernel(
     ScoreRow r, const int32_t* n_bins, int32_t L, float* scores, FeatBest* fbest,
     uint32_t* __restrict__ counter, cbh_split* __restrict__ out) {
     const int f = blockIdx.x;
-    score_feature<PREC, kScoreWaves>(r, L, f, n_bins[f], scores, &fbest[f]);
+    score_feature<PREC, NW>(r, L, f, n_bins[f], scores, &fbest[f]);
     __shared__ uint32_t last;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -65,20 +68,20 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     const int L = 1 << level;
     FeatBest* fb = (FeatBest*)scratch;
     uint32_t* counter = ctx->d_flags + 1;
+    const bool small = int64_t(L) * r.K <= kScoreWavesSmall;
+#define CBH_SCORE(P)                                                                      \
+    if (small)                                                                            \
+        score_split_kernel<P, kScoreWavesSmall><<<r.F, 64 * kScoreWavesSmall, 0, s>>>(    \
+            r, p->n_bins, L, scores, fb, counter, best);                                  \
+    else                                                                                  \
+        score_split_kernel<P, kScoreWaves><<<r.F, 64 * kScoreWaves, 0, s>>>(              \
+            r, p->n_bins, L, scores, fb, counter, best);
     switch (precision) {
-        case CBH_PREC_FP32:
-            score_split_kernel<CBH_PREC_FP32><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores, fb,
-                                                                  counter, best);
-            break;
-        case CBH_PREC_TWOFLOAT:
-            score_split_kernel<CBH_PREC_TWOFLOAT><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores,
-                                                                      fb, counter, best);
-            break;
-        default:
-            score_split_kernel<CBH_PREC_INT16><<<r.F, 64 * kScoreWaves, 0, s>>>(r, p->n_bins, L, scores, fb,
-                                                                   counter, best);
-            break;
+        case CBH_PREC_FP32: CBH_SCORE(CBH_PREC_FP32) break;
+        case CBH_PREC_TWOFLOAT: CBH_SCORE(CBH_PREC_TWOFLOAT) break;
+        default: CBH_SCORE(CBH_PREC_INT16) break;
     }
+#undef CBH_SCORE
     CBH_LAUNCHED();
     return CBH_OK;
 }
