@@ -410,9 +410,10 @@ int cbh_update_approx(cbh_ctx* ctx, const cbh_problem* prob, const void* hist_la
  * A split feature outside [0, n_features) is taken as a bit of 0 on every
  * row and reported by cbh_sync (the call itself cannot see device arrays).
  * The rows of a launch are independent; approx must not overlap the other
- * arrays. Errors: CBH_EINVAL (NULL pointers, n or n_trees < 0, lr not
- * finite), CBH_EUNSUPPORTED (K or depth out of range, n >= 2^38 with
- * K > 1).                                                                  */
+ * arrays. Uses workspace for one chunk of trees' leaves (at most 256 MB,
+ * at least one tree: n bytes, or 2n from depth 9). Errors: CBH_EINVAL (NULL
+ * pointers, n or n_trees < 0, lr not finite), CBH_EUNSUPPORTED (K or depth
+ * out of range, n >= 2^38), CBH_ENOMEM (workspace).                        */
 int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride,
                     int64_t n, int32_t n_features, int32_t K, int32_t n_trees, int32_t depth,
                     const int32_t* split_feature, const int32_t* split_border,
