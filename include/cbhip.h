@@ -33,7 +33,8 @@
  *     calls synchronizes the host. Device-side input errors (NaN inputs) and
  *     asynchronous faults are reported by cbh_sync().
  *   - A context owns a scratch workspace that calls on it reuse; use one
- *     context per concurrently used stream.
+ *     context per concurrently used stream. See cbh_reserve_workspace for
+ *     how the workspace behaves under graph capture.
  *   - Arrays written [A][B] are row-major with the last index fastest.
  */
 #ifndef CBHIP_H
@@ -52,6 +53,8 @@ extern "C" {
 #define CBH_EDEVICE (-3)       /* HIP runtime error or device-reported input error */
 #define CBH_EOVERFLOW (-4)     /* an integer accumulator could overflow */
 #define CBH_EUNSUPPORTED (-5)  /* K > 16, more than 256 bins, depth > 16, ... */
+#define CBH_EBUSY (-6)         /* the workspace would have to grow while the call's
+                                  stream is being captured into a graph */
 
 /* ---- losses (the paper uses Logloss and mentions regression; the
  *      derivative formulas are the standard ones, see cbh_update_approx) ---- */
@@ -59,10 +62,27 @@ extern "C" {
 #define CBH_LOSS_LOGLOSS 1
 #define CBH_LOSS_MULTICLASS 2
 
-/* ---- histogram precision ----------------------------------------------- */
-#define CBH_PREC_FP32 0      /* float accumulation */
-#define CBH_PREC_TWOFLOAT 1  /* compensated (hi, lo) float pairs */
-#define CBH_PREC_INT16 2     /* int16 gradient codes, exact integer sums */
+/* ---- histogram precision -----------------------------------------------
+ * How the per-bin sums of cbh_build_histograms are accumulated (the paper's
+ * histograms sum float statistics, Sec. 5; the variants are this library's):
+ *   CBH_PREC_FP32      every addition is a float32 addition (LDS
+ *                      compare-and-swap updates; chunk partials added in
+ *                      float32); output float
+ *   CBH_PREC_TWOFLOAT  compensated float32: every addition is a TwoSum whose
+ *                      rounding error is carried in a second float (the
+ *                      (hi, lo) pair is updated by one 64-bit
+ *                      compare-and-swap); partials merged with TwoSum; output
+ *                      float2 (hi, lo)
+ *   CBH_PREC_INT16     int16 gradient codes, exact integer sums; output int64
+ *   CBH_PREC_F64       float64 LDS accumulation (the fastest float path on
+ *                      gfx950, whose LDS has a pipelined float64 adder but
+ *                      not a float32 one), each sum split into (hi, lo) when
+ *                      written; output float2 (hi, lo), the TWOFLOAT layout,
+ *                      and every call taking a TWOFLOAT histogram takes it */
+#define CBH_PREC_FP32 0
+#define CBH_PREC_TWOFLOAT 1
+#define CBH_PREC_INT16 2
+#define CBH_PREC_F64 3
 
 #define CBH_MAX_K 16
 #define CBH_MAX_BINS 256
@@ -160,6 +180,15 @@ const char* cbh_last_error(void);
 int cbh_set_workspace_limit(cbh_ctx* ctx, int64_t bytes);
 /* Current workspace size in bytes. */
 int64_t cbh_workspace_size(const cbh_ctx* ctx);
+/* Grow the workspace to at least `bytes` now (within the limit), so that
+ * calls captured into a graph later find it large enough.
+ * Workspace rules for graphs: a call that needs more workspace than the
+ * context holds allocates a larger buffer; the earlier buffer is kept (not
+ * freed) until cbh_destroy, so a graph captured over earlier calls stays
+ * valid. A call whose stream is being captured never allocates: if it would
+ * have to grow the workspace it returns CBH_EBUSY and enqueues nothing.
+ * Errors: CBH_EINVAL (NULL, bytes < 0), CBH_ENOMEM. */
+int cbh_reserve_workspace(cbh_ctx* ctx, int64_t bytes);
 /* Wait for `stream`, then report asynchronous HIP errors and device-side input
  * errors (NaN feature values, bin or leaf values out of range) raised since
  * the previous cbh_sync, and clear them. */
@@ -300,8 +329,10 @@ int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream);
  *   hist[L][f][b][2c+1] = sum of h_c over the same rows (row count for RMSE)
  * for L < 2^level, f < F, b < B, c < K. Element type by precision:
  *   CBH_PREC_FP32      float; for RMSE the odd slots hold uint32 counts
- *   CBH_PREC_TWOFLOAT  float2 (hi, lo) with hi + lo the compensated sum; for
- *                      RMSE the odd slots hold (uint32 count, 0)
+ *   CBH_PREC_TWOFLOAT,
+ *   CBH_PREC_F64       float2 (hi, lo) with hi + lo the compensated (or
+ *                      float64) sum; for RMSE the odd slots hold
+ *                      (uint32 count, 0)
  *   CBH_PREC_INT16     int64 sums of the int16 codes (exact)
  *   hist_out   device, 2^level * F * B * 2K elements
  * Every block accumulates a tile in LDS; tiles are merged in a fixed order
@@ -346,7 +377,10 @@ int cbh_apply_build_histograms_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_
  *   S(f, k) = sum_L sum_c  G_left^2 / (H_left + l2) + G_right^2 / (H_right + l2)
  * where H is the row count for RMSE; a side with H + l2 == 0 contributes 0.
  * The best split is the largest S; among equal scores the smallest feature,
- * then the smallest border. Scores are computed in float32.
+ * then the smallest border. Prefix sums over bins are formed in the
+ * histogram's own type (float, two-float pair or int64); every term and the
+ * sum over leaves and classes are evaluated in double, and the per-border
+ * score is stored as float32.
  *   hist        output of cbh_build_histograms for the same level/precision
  *   l2          >= 0
  *   best_out    device cbh_split [1]
@@ -480,7 +514,7 @@ typedef struct cbh_batch cbh_batch;
  *             after a level of the plan it holds that level's histograms if
  *             depth-1-level is even (else the plan's second buffer does)
  *   best      device cbh_split [P][depth]: split of every problem and level
- * Precision must be CBH_PREC_FP32 or CBH_PREC_TWOFLOAT or CBH_PREC_INT16. */
+ * Precision: any CBH_PREC_* form. */
 int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P,
                      int32_t precision, int32_t subtract, void* const* hist,
                      cbh_split* best, cbh_batch** out);

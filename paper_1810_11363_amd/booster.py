@@ -343,9 +343,10 @@ class GpuBooster:
         """Capture one tree per permutation into HIP graphs; tree t replays
         graph t mod s on the current stream. Grow at least one tree of every
         permutation first: the library's workspace must have reached its size,
-        since a capture may not allocate and a later growth of the workspace
-        (or a change of form, which drops the graphs) frees memory the graphs
-        point at. `events[r]`: optional per-level (start, end) pairs recorded
+        since a call under capture never allocates (it fails with CBH_EBUSY
+        instead); a later growth of the workspace keeps the buffer the graphs
+        point at. A change of form drops the graphs. `events[r]`: optional
+        per-level (start, end) pairs recorded
         around the builds of permutation r's tree (objects with a
         record(stream) method that a capture turns into graph nodes).
         Returns the list of graphs."""

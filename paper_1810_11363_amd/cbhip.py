@@ -16,15 +16,18 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbhip.so")
 
 CBH_OK, CBH_EINVAL, CBH_ENOMEM, CBH_EDEVICE, CBH_EOVERFLOW, CBH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CBH_EBUSY = -6
 CBH_LOSS_RMSE, CBH_LOSS_LOGLOSS, CBH_LOSS_MULTICLASS = 0, 1, 2
-CBH_PREC_FP32, CBH_PREC_TWOFLOAT, CBH_PREC_INT16 = 0, 1, 2
+CBH_PREC_FP32, CBH_PREC_TWOFLOAT, CBH_PREC_INT16, CBH_PREC_F64 = 0, 1, 2, 3
+PREC_NAMES = {CBH_PREC_FP32: "fp32", CBH_PREC_TWOFLOAT: "twofloat", CBH_PREC_INT16: "int16",
+              CBH_PREC_F64: "f64"}
 STATUS_NAMES = {0: "CBH_OK", -1: "CBH_EINVAL", -2: "CBH_ENOMEM", -3: "CBH_EDEVICE",
-                -4: "CBH_EOVERFLOW", -5: "CBH_EUNSUPPORTED"}
+                -4: "CBH_EOVERFLOW", -5: "CBH_EUNSUPPORTED", -6: "CBH_EBUSY"}
 
 # Every symbol include/cbhip.h declares.
 EXPORTS = [
     "cbh_create", "cbh_destroy", "cbh_last_error", "cbh_set_workspace_limit",
-    "cbh_workspace_size", "cbh_sync", "cbh_device_timestamp", "cbh_device_clock_khz",
+    "cbh_workspace_size", "cbh_reserve_workspace", "cbh_sync", "cbh_device_timestamp", "cbh_device_clock_khz",
     "cbh_select_borders", "cbh_uniform_borders",
     "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
@@ -72,6 +75,7 @@ def _load():
         "cbh_last_error": ([], C.c_char_p),
         "cbh_set_workspace_limit": ([vp, i64], C.c_int),
         "cbh_workspace_size": ([vp], i64),
+        "cbh_reserve_workspace": ([vp, i64], C.c_int),
         "cbh_sync": ([vp, vp], C.c_int),
         "cbh_device_timestamp": ([vp, vp, vp], C.c_int),
         "cbh_device_clock_khz": ([vp, C.POINTER(i64)], C.c_int),
@@ -174,6 +178,10 @@ def cbh_set_workspace_limit(ctx, nbytes: int):
 
 def cbh_workspace_size(ctx) -> int:
     return _lib.cbh_workspace_size(ctx)
+
+
+def cbh_reserve_workspace(ctx, nbytes: int):
+    return _check(_lib.cbh_reserve_workspace(ctx, nbytes))
 
 
 def cbh_sync(ctx, stream=None):

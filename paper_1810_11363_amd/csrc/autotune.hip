@@ -224,7 +224,7 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
             const int64_t part = int64_t(plan.n_chunks) * L * F * B *
                                  plan.words_per_cell * 4;
             if (part > ctx->ws_limit / 2) continue;
-            rc = ensure_ws(ctx, part);
+            rc = ensure_ws(ctx, part, s);
             if (rc) break;
             // warm-up, then the mean of 3 timed runs
             rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
@@ -265,7 +265,7 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
             ctx->tuned_note[TuneKey{F, B, K, level, precision, nb, sub}] = note;
         }
         rc = ensure_ws(ctx, int64_t(plan.n_chunks) * L * F * B * plan.words_per_cell * 4 +
-                                score_scratch_bytes(prob) + 256);
+                                score_scratch_bytes(prob) + 256, s);
         if (!rc) rc = launch_hist(ctx, prob, level, precision, plan, out, ctx->ws, s, parent,
                                   sub ? side : nullptr, codes,
                                   sub ? splits + level - 1 : nullptr);

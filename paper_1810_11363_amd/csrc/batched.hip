@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void bside_code_kernel(const DevProb* __restri
 template <int PREC>
 __global__ __launch_bounds__(256) void bscore_kernel(const DevProb* __restrict__ probs,
                                                      const int64_t* __restrict__ feat_off,
-                                                     int32_t P, int32_t L, float l2,
+                                                     int32_t P, int32_t L, double l2,
                                                      FeatBest* __restrict__ fbest) {
     const int64_t gf = blockIdx.x;
     const int p = find_owner(feat_off, P, gf);
@@ -351,7 +351,8 @@ void batch_init_attrs(int max_lds) {
         (const void*)bhist_kernel<CBH_PREC_FP32, 0>, (const void*)bhist_kernel<CBH_PREC_FP32, 1>,
         (const void*)bhist_kernel<CBH_PREC_TWOFLOAT, 0>,
         (const void*)bhist_kernel<CBH_PREC_TWOFLOAT, 1>,
-        (const void*)bhist_kernel<CBH_PREC_INT16, 0>, (const void*)bhist_kernel<CBH_PREC_INT16, 1>};
+        (const void*)bhist_kernel<CBH_PREC_INT16, 0>, (const void*)bhist_kernel<CBH_PREC_INT16, 1>,
+        (const void*)bhist_kernel<CBH_PREC_F64, 0>, (const void*)bhist_kernel<CBH_PREC_F64, 1>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 #define CBH_BLPF_ATTR(P, R, M)                                                               \
@@ -369,6 +370,8 @@ void batch_init_attrs(int max_lds) {
     CBH_BLPF_ATTR3(CBH_PREC_TWOFLOAT, 0)
     CBH_BLPF_ATTR3(CBH_PREC_TWOFLOAT, 1)
     CBH_BLPF_ATTR3(CBH_PREC_INT16, 0)
+    CBH_BLPF_ATTR3(CBH_PREC_F64, 0)
+    CBH_BLPF_ATTR3(CBH_PREC_F64, 1)
 #undef CBH_BLPF_ATTR3
 #undef CBH_BLPF_ATTR
 }
@@ -404,7 +407,7 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     if (lp.sub) {
         const dim3 sg((unsigned)lp.rb_total);
         const size_t half = (size_t)(L / 2);
-        switch (b->precision) {
+        switch (out_prec(b->precision)) {
             case CBH_PREC_FP32:
                 bside_code_kernel<CBH_PREC_FP32><<<sg, 256, half, s>>>(
                     b->d_probs, lp.d_rb_off, b->P, b->best, b->depth, level);
@@ -430,6 +433,10 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
                 if (rm) launch_blpf<CBH_PREC_TWOFLOAT, 1>(b, lp, slots, grd, lds, s);
                 else launch_blpf<CBH_PREC_TWOFLOAT, 0>(b, lp, slots, grd, lds, s);
                 break;
+            case CBH_PREC_F64:
+                if (rm) launch_blpf<CBH_PREC_F64, 1>(b, lp, slots, grd, lds, s);
+                else launch_blpf<CBH_PREC_F64, 0>(b, lp, slots, grd, lds, s);
+                break;
             default:
                 launch_blpf<CBH_PREC_INT16, 0>(b, lp, slots, grd, lds, s);
                 break;
@@ -443,6 +450,10 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
             if (rm) bhist_kernel<CBH_PREC_TWOFLOAT, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             else bhist_kernel<CBH_PREC_TWOFLOAT, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             break;
+        case CBH_PREC_F64:
+            if (rm) bhist_kernel<CBH_PREC_F64, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            else bhist_kernel<CBH_PREC_F64, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
+            break;
         default:
             if (rm) bhist_kernel<CBH_PREC_INT16, 1><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
             else bhist_kernel<CBH_PREC_INT16, 0><<<grd, blk, lds, s>>>(b->d_probs, lp.d_tiles, lp.d_plans, lp.n_tiles, L);
@@ -450,7 +461,7 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     }
     CBH_LAUNCHED();
     const int rg = (int)std::min<int64_t>((lp.cells_total + 255) / 256, ctx->num_cus * 16);
-    switch (b->precision) {
+    switch (out_prec(b->precision)) {
         case CBH_PREC_FP32:
             breduce_kernel<CBH_PREC_FP32><<<rg, 256, 0, s>>>(b->d_probs, lp.d_plans,
                                                             lp.d_cell_off, b->P, lp.cells_total);
@@ -466,8 +477,8 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     }
     CBH_LAUNCHED();
     FeatBest* fb = (FeatBest*)((char*)b->ws + b->fbest_off);
-    const float fl2 = (float)l2;
-    switch (b->precision) {
+    const double fl2 = l2;
+    switch (out_prec(b->precision)) {
         case CBH_PREC_FP32:
             bscore_kernel<CBH_PREC_FP32><<<(unsigned)lp.score_total, 256, 0, s>>>(
                 b->d_probs, lp.d_feat_off, b->P, L, fl2, fb);
@@ -668,7 +679,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         }
     }
     // the context workspace must exist before a capture (gradient codes use it)
-    int rc = ensure_ws(ctx, 256);
+    int rc = ensure_ws(ctx, 256, nullptr);
     if (!rc && b->ws_need > ctx->ws_limit) {
         set_error("batch workspace of %lld bytes exceeds the limit", (long long)b->ws_need);
         rc = CBH_ENOMEM;

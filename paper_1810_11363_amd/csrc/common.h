@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "cbhip.h"
 
@@ -98,6 +99,9 @@ struct cbh_ctx {
     int max_lds = 64 * 1024;
     void* ws = nullptr;
     int64_t ws_size = 0;
+    // earlier, smaller workspaces: a graph captured over calls that used one
+    // still points into it, so growth keeps them until cbh_destroy
+    std::vector<void*> ws_retired;
     int64_t ws_limit = int64_t(64) << 30;
     uint32_t* d_flags = nullptr;  // [0] device error flags, [1] score blocks done (self-resetting)
     cbh::HistKnobs knobs;
@@ -109,8 +113,10 @@ struct cbh_ctx {
 
 namespace cbh {
 
-// Grow the workspace to at least `bytes`; returns CBH_OK / CBH_ENOMEM / CBH_EDEVICE.
-int ensure_ws(cbh_ctx* ctx, int64_t bytes);
+// Grow the workspace to at least `bytes` for a call on `stream`; returns
+// CBH_OK / CBH_ENOMEM / CBH_EDEVICE, or CBH_EBUSY when growth would be needed
+// while `stream` is being captured into a graph.
+int ensure_ws(cbh_ctx* ctx, int64_t bytes, void* stream);
 
 inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 

@@ -25,25 +25,33 @@ void clear_error() {
     (void)hipGetLastError();
 }
 
-int ensure_ws(cbh_ctx* ctx, int64_t bytes) {
+int ensure_ws(cbh_ctx* ctx, int64_t bytes, void* stream) {
     bytes = align_up(std::max<int64_t>(bytes, 256), 1 << 20);
     if (bytes <= ctx->ws_size) return CBH_OK;
     CBH_REQUIRE(bytes <= ctx->ws_limit, CBH_ENOMEM,
                 "workspace of %lld bytes exceeds the limit of %lld bytes",
                 (long long)bytes, (long long)ctx->ws_limit);
-    if (ctx->ws) {
-        // hipFree waits for work that may still use the old buffer.
-        CBH_HIP(hipFree(ctx->ws));
-        ctx->ws = nullptr;
-        ctx->ws_size = 0;
-    }
-    hipError_t e = hipMalloc(&ctx->ws, (size_t)bytes);
+    // A graph being captured would keep the new buffer's address; growing
+    // (an allocation) is refused there: run the calls once before the
+    // capture, or reserve the workspace with cbh_reserve_workspace.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    CBH_HIP(hipStreamIsCapturing((hipStream_t)stream, &cap));
+    CBH_REQUIRE(cap == hipStreamCaptureStatusNone, CBH_EBUSY,
+                "workspace must grow from %lld to %lld bytes while the stream is being "
+                "captured; run the calls once before capturing or call "
+                "cbh_reserve_workspace",
+                (long long)ctx->ws_size, (long long)bytes);
+    void* nw = nullptr;
+    hipError_t e = hipMalloc(&nw, (size_t)bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         set_error("workspace allocation of %lld bytes failed: %s", (long long)bytes,
                   hipGetErrorString(e));
         return CBH_ENOMEM;
     }
+    // the old buffer is kept, not freed: graphs captured earlier may use it
+    if (ctx->ws) ctx->ws_retired.push_back(ctx->ws);
+    ctx->ws = nw;
     ctx->ws_size = bytes;
     return CBH_OK;
 }
@@ -74,7 +82,7 @@ int validate_problem(const cbh_problem* p) {
 
 int validate_precision(const cbh_problem* p, int32_t precision) {
     CBH_ARG(precision == CBH_PREC_FP32 || precision == CBH_PREC_TWOFLOAT ||
-                precision == CBH_PREC_INT16,
+                precision == CBH_PREC_INT16 || precision == CBH_PREC_F64,
             "unknown precision %d", precision);
     if (precision == CBH_PREC_INT16)
         CBH_ARG(p->gq != nullptr && p->grad_scale != nullptr,
@@ -139,6 +147,7 @@ void cbh_destroy(cbh_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (void* w : ctx->ws_retired) (void)hipFree(w);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     delete ctx;
 }
@@ -152,6 +161,13 @@ int cbh_set_workspace_limit(cbh_ctx* ctx, int64_t bytes) {
 }
 
 int64_t cbh_workspace_size(const cbh_ctx* ctx) { return ctx ? ctx->ws_size : 0; }
+
+int cbh_reserve_workspace(cbh_ctx* ctx, int64_t bytes) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(bytes >= 0, "bytes must be >= 0");
+    return ensure_ws(ctx, bytes, nullptr);
+}
 
 int cbh_device_timestamp(cbh_ctx* ctx, uint64_t* slot, void* stream) {
     clear_error();

@@ -6,9 +6,13 @@
 // MI355X design. The paper's kernel keeps per-warp copies in shared memory and
 // rotates lanes over features to avoid atomics. On CDNA4 the LDS has native
 // 64-bit atomics (ds_add_f64, ds_add_u64) and ds_add_u32 at full rate, while
-// ds_add_f32 is serialised (measured about 0.3 lane-ops per clock per CU
-// against 7.5 for ds_add_f64), and a CU has 160 KB of LDS. So one LDS tile per
-// block is updated with LDS atomics, and no global atomics are used anywhere:
+// ds_add_f32 is not pipelined (measured 0.33 lane-ops per clock per CU
+// against 7.6 for ds_add_f64), and a CU has 160 KB of LDS. A copy of a
+// B-bin histogram per lane, as the paper's rotation needs, holds only 5
+// waves per CU at B = 128 and, waiting on each read-add-write, reached 0.9
+// updates per clock per CU. So one LDS tile per block is updated with LDS
+// atomics (or compare-and-swap for the float32 forms), and no global atomics
+// are used anywhere:
 //   - a block owns (row chunk, feature group, leaf tile); every thread streams
 //     ROWS consecutive rows per step (16 for int16 codes, 8 for float forms):
 //     ROWS bins of each of its features (coalesced, feature-major columns),
@@ -22,13 +26,16 @@
 //     order (deterministic merge);
 //   - block ids map to work XCD-contiguously: consecutive work items (same row
 //     chunk, different feature groups) land on one XCD and share its L2.
-// Precision variants (the LDS sum is exact or FP64; the output rounding is
-// the variant's):
-//   FP32      ds_add_f64 for g (and h), ds_add_u32 for RMSE counts; each
-//             tile sum is rounded once to float, chunk partials are added in
-//             float;
-//   TWOFLOAT  the same FP64 tiles, each sum split into a (hi, lo) float pair;
-//             chunk partials are added with TwoSum;
+// Precision variants:
+//   FP32      float32 sums: compare-and-swap of the float g (RMSE, with a
+//             ds_add_u32 count) or of the (g, h) float pair; chunk partials
+//             are added in float;
+//   TWOFLOAT  compensated float32: TwoSum of each value into a (hi, lo)
+//             float pair by a 64-bit compare-and-swap (h the same way, or a
+//             u32 count); chunk partials are added with TwoSum;
+//   F64       ds_add_f64 for g (and h), ds_add_u32 for RMSE counts; each
+//             tile sum is split into a (hi, lo) float pair (TWOFLOAT's
+//             output layout); chunk partials are added with TwoSum;
 //   INT16     one ds_add_u64 per row, feature and class of the packed word
 //             (g code << 32) + h code; at most 65536 rows per chunk keep
 //             both halves exact; partials are decoded and summed in int64.
@@ -43,7 +50,7 @@
 namespace cbh {
 
 int words_per_cell(int32_t precision, int32_t K) {
-    return precision == CBH_PREC_TWOFLOAT ? 4 * K : 2 * K;
+    return out_prec(precision) == CBH_PREC_TWOFLOAT ? 4 * K : 2 * K;
 }
 
 int64_t hist_elems(int32_t n_leaves, int32_t F, int32_t B, int32_t K) {
@@ -535,7 +542,9 @@ void hist_init_attrs(int max_lds) {
         (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 1, 1>,
         (const void*)hist_kernel<CBH_PREC_TWOFLOAT, 0, 0>,
         (const void*)hist_kernel<CBH_PREC_INT16, 1, 0>, (const void*)hist_kernel<CBH_PREC_INT16, 1, 1>,
-        (const void*)hist_kernel<CBH_PREC_INT16, 0, 0>};
+        (const void*)hist_kernel<CBH_PREC_INT16, 0, 0>,
+        (const void*)hist_kernel<CBH_PREC_F64, 1, 0>, (const void*)hist_kernel<CBH_PREC_F64, 1, 1>,
+        (const void*)hist_kernel<CBH_PREC_F64, 0, 0>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 #define CBH_LPF_ATTR(P, R, M)                                                                \
@@ -553,6 +562,8 @@ void hist_init_attrs(int max_lds) {
     CBH_LPF_ATTR3(CBH_PREC_TWOFLOAT, 0)
     CBH_LPF_ATTR3(CBH_PREC_TWOFLOAT, 1)
     CBH_LPF_ATTR3(CBH_PREC_INT16, 0)
+    CBH_LPF_ATTR3(CBH_PREC_F64, 0)
+    CBH_LPF_ATTR3(CBH_PREC_F64, 1)
 #undef CBH_LPF_ATTR3
 #undef CBH_LPF_ATTR
 }
@@ -664,7 +675,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
             if (fused) {
                 // few parents: sides and codes (and the parent's leaf bit) in one launch
                 const cbh_problem* ap = apply_parent ? p : nullptr;
-                switch (precision) {
+                switch (out_prec(precision)) {
                     case CBH_PREC_FP32:
                         launch_side_code<CBH_PREC_FP32>(parent, parent_split, half, p->n_features,
                                                         p->max_bins, p->K, rmse, p->leaf, p->n,
@@ -729,6 +740,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
         case CBH_PREC_TWOFLOAT:
             launch_hist_prec<CBH_PREC_TWOFLOAT>(a, plan, ctx->max_lds, s);
             break;
+        case CBH_PREC_F64: launch_hist_prec<CBH_PREC_F64>(a, plan, ctx->max_lds, s); break;
         default: launch_hist_prec<CBH_PREC_INT16>(a, plan, ctx->max_lds, s); break;
     }
     CBH_LAUNCHED();
@@ -736,7 +748,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     const int64_t units = precision == CBH_PREC_INT16 ? cells * a.K : cells * 2 * a.K;
     const int grid = (int)std::min<int64_t>((units + 63) / 64, int64_t(ctx->num_cus) * 16);
     const SubArgs sub{parent, side, int64_t(a.F) * a.B, int64_t(a.L)};
-    switch (precision) {
+    switch (out_prec(precision)) {
         case CBH_PREC_FP32:
             hist_reduce_kernel<CBH_PREC_FP32><<<grid, 256, 0, s>>>(
                 (const uint32_t*)partials, cells, a.K, plan.n_chunks, a.rmse, hist_out, sub);
@@ -758,7 +770,7 @@ int launch_side(const void* parent_hist, const cbh_split* parent_split, int64_t 
                 int32_t B, int32_t K, int32_t rmse, int32_t precision, uint8_t* side,
                 hipStream_t s) {
     const unsigned gs = (unsigned)((half + 3) / 4);
-    switch (precision) {
+    switch (out_prec(precision)) {
         case CBH_PREC_FP32:
             sub_side_kernel<CBH_PREC_FP32><<<gs, 256, 0, s>>>(parent_hist, parent_split, half, F,
                                                               B, K, rmse, side);
@@ -850,7 +862,7 @@ int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream) 
     int rc = validate_problem(prob);
     if (rc) return rc;
     CBH_ARG(prob->gq && prob->grad_scale, "gq / grad_scale is NULL");
-    rc = ensure_ws(ctx, 8 * CBH_MAX_K);
+    rc = ensure_ws(ctx, 8 * CBH_MAX_K, stream);
     if (rc) return rc;
     uint32_t* maxbits = (uint32_t*)ctx->ws;
     hipStream_t s = (hipStream_t)stream;
@@ -888,7 +900,7 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
                 prob->max_bins);
     const int64_t part_bytes =
         int64_t(plan.n_chunks) * L * prob->n_features * prob->max_bins * plan.words_per_cell * 4;
-    rc = ensure_ws(ctx, part_bytes);
+    rc = ensure_ws(ctx, part_bytes, stream);
     if (rc) return rc;
     return launch_hist(ctx, prob, level, precision, plan, hist_out, ctx->ws,
                        (hipStream_t)stream);
@@ -918,7 +930,7 @@ static int build_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, int32
         int64_t(plan.n_chunks) * half * prob->n_features * prob->max_bins * plan.words_per_cell * 4,
         256);
     const int64_t code_bytes = hist_code_bytes(plan, prob->n, true);
-    rc = ensure_ws(ctx, part_bytes + align_up(half, 256) + code_bytes);
+    rc = ensure_ws(ctx, part_bytes + align_up(half, 256) + code_bytes, stream);
     if (rc) return rc;
     uint8_t* side = (uint8_t*)ctx->ws + part_bytes;
     uint16_t* codes =

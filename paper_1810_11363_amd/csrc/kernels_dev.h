@@ -41,21 +41,92 @@ __device__ __forceinline__ uint32_t gld_u8(const void* p) { return *(CBH_GLOBAL(
 __device__ __forceinline__ float gld_f32(const void* p) { return *(CBH_GLOBAL(float))(p); }
 #undef CBH_GLOBAL
 
+// ------------------------------------------------- precision forms
+// Output format of a precision: the float64-accumulated form writes the same
+// (hi, lo) float pairs as the compensated form, so every step after the
+// histogram (merge, subtraction, score, leaf solve) takes it as TWOFLOAT.
+__host__ __device__ constexpr int out_prec(int p) {
+    return p == CBH_PREC_F64 ? CBH_PREC_TWOFLOAT : p;
+}
+
+// Float32 accumulation in LDS. The LDS float32 atomic add of gfx950 is not
+// pipelined (measured 0.33 updates per clock per CU, with or without
+// denormal flushing, against 7.6 for the float64 add and 14.8 for the u32
+// add), so the float32 forms update a cell by compare-and-swap: read it, add
+// in float32 (FP32) or by TwoSum into a (hi, lo) pair (TWOFLOAT), and swap
+// the new bits in if the cell still holds the bits that were read; otherwise
+// the add is redone on the value found. Every addition is then one float32
+// addition (or one TwoSum) in some order, as with an atomic add.
+__device__ __forceinline__ uint32_t lds_cas32(uint32_t* p, uint32_t cmp, uint32_t val) {
+    __hip_atomic_compare_exchange_strong(p, &cmp, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return cmp;   // the bits found: equal to the bits compared iff the swap happened
+}
+__device__ __forceinline__ uint64_t lds_cas64(uint64_t* p, uint64_t cmp, uint64_t val) {
+    __hip_atomic_compare_exchange_strong(p, &cmp, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return cmp;
+}
+__device__ __forceinline__ uint32_t lds_load32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t lds_load64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t pack_f2(float lo_word, float hi_word) {
+    return (uint64_t)__float_as_uint(lo_word) | ((uint64_t)__float_as_uint(hi_word) << 32);
+}
+// float32 add of x to the float in the word's low half and y to the high half
+__device__ __forceinline__ uint64_t add_pair_word(uint64_t w, float x, float y) {
+    return pack_f2(__uint_as_float((uint32_t)w) + x, __uint_as_float((uint32_t)(w >> 32)) + y);
+}
+// TwoSum of x into the pair (hi = low half, lo = high half): hi + x = s + e
+// exactly (Knuth's TwoSum; needs round-to-nearest and no contraction), and e
+// is added to lo in float32.
+__device__ __forceinline__ uint64_t twosum_word(uint64_t w, float x) {
+    const float hi = __uint_as_float((uint32_t)w), lo = __uint_as_float((uint32_t)(w >> 32));
+    const float s = hi + x, bp = s - hi;
+    const float e = (hi - (s - bp)) + (x - bp);
+    return pack_f2(s, lo + e);
+}
+// (hi, lo) with hi the float nearest to hi + lo (TwoSum renormalisation)
+__device__ __forceinline__ float2 renorm_pair(float hi, float lo) {
+    const float s = hi + lo, bp = s - hi;
+    return make_float2(s, (hi - (s - bp)) + (lo - bp));
+}
+// Pair additions by compare-and-swap, one cell: retried until the swap holds.
+__device__ __forceinline__ void cas_add_f32(uint32_t* p, float x) {
+    uint32_t old = lds_load32(p);
+    for (;;) {
+        const uint32_t got = lds_cas32(p, old, __float_as_uint(__uint_as_float(old) + x));
+        if (got == old) break;
+        old = got;
+    }
+}
+__device__ __forceinline__ void cas_twosum(uint64_t* p, float x) {
+    uint64_t old = lds_load64(p);
+    for (;;) {
+        const uint64_t got = lds_cas64(p, old, twosum_word(old, x));
+        if (got == old) break;
+        old = got;
+    }
+}
+
 // ------------------------------------------------------------ histogram tile
 // One block accumulates rows [r0, r1) of features [f0, f0 + nf) for leaves
 // [l0, l0 + lt) into an LDS tile, then writes the tile into `part`, the
 // chunk's partial histogram laid out as [L][F][B][wpc words] in the output
 // format of the precision.
 //
-// On gfx950 the LDS float32 atomic add is serialised (measured about 0.3 lane
-// updates per clock per CU against about 5 for u32 and 4 for f64 with random
-// addresses), so the tile of the float-valued forms accumulates in float64
-// (ds_add_f64) and is rounded once per tile when written out; counts use u32
-// atomics and the int16 form one u64 atomic of packed codes. A "cell" is one
-// (leaf, feature) pair of the tile, cell = leaf_in_tile * fb + feature_in_block.
-//   FP32 / TWOFLOAT, K classes, h statistic:   f64 [cells][K][2][B]
-//   FP32 / TWOFLOAT, RMSE (K = 1, count):      f64 [cells][B], then u32 [cells][B]
-//   INT16:                                     u64 [cells][K][B]
+// The tile has 8-byte elements for every form: F64 accumulates with the
+// float64 LDS atomic, FP32 keeps a float in the element's low half (updated by
+// compare-and-swap), TWOFLOAT a (hi, lo) float pair (TwoSum by 64-bit
+// compare-and-swap); counts use u32 atomics and the int16 form one u64 atomic
+// of packed codes. A "cell" is one (leaf, feature) pair of the tile,
+// cell = leaf_in_tile * fb + feature_in_block.
+//   float forms, K classes, h statistic:   8 B [cells][K][2][B]
+//   float forms, RMSE (K = 1, count):      8 B [cells][B], then u32 [cells][B]
+//   INT16:                                 u64 [cells][K][B]
 // Each thread streams 8 or 16 consecutive rows per step: one 8- or 16-byte
 // load of bins per feature (a wave reads 512 B or 1 KB contiguous per
 // feature), and loads for 4 features are issued before their LDS updates so
@@ -142,19 +213,26 @@ __device__ __forceinline__ void add_row(uint32_t* lds, uint32_t ncells, uint32_t
                                (unsigned long long)packed, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
-        double* l64 = reinterpret_cast<double*>(lds);
+        // 8-byte element e of the g (and h) planes
+        const auto add_elem = [&](uint32_t e, float v) {
+            if constexpr (PREC == CBH_PREC_F64) {
+                __hip_atomic_fetch_add(reinterpret_cast<double*>(lds) + e, (double)v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else if constexpr (PREC == CBH_PREC_FP32) {
+                cas_add_f32(lds + 2 * e, v);
+            } else {
+                cas_twosum(reinterpret_cast<uint64_t*>(lds) + e, v);
+            }
+        };
         if constexpr (RM != 0) {
             const uint32_t e = lds_elem(cell, Bs, bin, rep, replica);
-            __hip_atomic_fetch_add(l64 + e, (double)gv, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            add_elem(e, gv);
             __hip_atomic_fetch_add(lds + 2 * ncells * Bs * rep + e, 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
             const uint32_t pr = (cell * K + c) * 2;
-            __hip_atomic_fetch_add(l64 + lds_elem(pr, Bs, bin, rep, replica), (double)gv,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(l64 + lds_elem(pr + 1, Bs, bin, rep, replica), (double)hv,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            add_elem(lds_elem(pr, Bs, bin, rep, replica), gv);
+            add_elem(lds_elem(pr + 1, Bs, bin, rep, replica), hv);
         }
     }
 }
@@ -344,8 +422,9 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
     }
     __syncthreads();
     // write the tile in the partial's [L][F][B][wpc] order (coalesced stores),
-    // converting to the output format: FP32 rounds each sum once, TWOFLOAT
-    // splits it into (hi, lo) floats, counts and INT16 sums are copied
+    // converting to the output format: FP32 copies its float sums (replicas
+    // added in float), TWOFLOAT its (hi, lo) pairs (replicas added by TwoSum),
+    // F64 splits each sum into (hi, lo) floats, counts and INT16 sums are copied
     const int wpc = a.wpc;
     const int row_words = a.B * wpc;
     const int out_words = a.lt * a.nf * row_words;
@@ -379,10 +458,27 @@ __device__ __forceinline__ void hist_tile(const TileArgs& a, uint32_t* lds) {
             } else {
                 const uint32_t e0 = rmse ? lds_elem(cell, Bs, bin, rep, 0)
                                          : lds_elem((cell * K + c) * 2 + t, Bs, bin, rep, 0);
-                double d = 0.0;
-                for (uint32_t rp = 0; rp < rep; ++rp) d += l64[e0 + rp];
-                const float hi = (float)d;
-                v = __float_as_uint(hi_lo ? (float)(d - (double)hi) : hi);
+                if constexpr (PREC == CBH_PREC_F64) {
+                    double d = 0.0;
+                    for (uint32_t rp = 0; rp < rep; ++rp) d += l64[e0 + rp];
+                    const float hi = (float)d;
+                    v = __float_as_uint(hi_lo ? (float)(d - (double)hi) : hi);
+                } else if constexpr (PREC == CBH_PREC_FP32) {
+                    float f = 0.f;
+                    for (uint32_t rp = 0; rp < rep; ++rp) f += __uint_as_float(lds[2 * (e0 + rp)]);
+                    v = __float_as_uint(f);
+                } else {
+                    float S = 0.f, E = 0.f;
+                    for (uint32_t rp = 0; rp < rep; ++rp) {
+                        const uint64_t w = u64[e0 + rp];
+                        const float hi = __uint_as_float((uint32_t)w);
+                        const float t2 = S + hi, bp = t2 - S;
+                        E += ((S - (t2 - bp)) + (hi - bp)) + __uint_as_float((uint32_t)(w >> 32));
+                        S = t2;
+                    }
+                    const float2 r = renorm_pair(S, E);
+                    v = __float_as_uint(hi_lo ? r.y : r.x);
+                }
             }
         }
         a.part[((int64_t)(a.l0 + ll) * a.F + (a.f0 + j)) * row_words + bin * wpc + s] = v;
@@ -400,6 +496,7 @@ __device__ __forceinline__ void merge_cell(const uint32_t* __restrict__ part, in
                                            int K, int n_chunks, bool rmse, void* __restrict__ out,
                                            int64_t cell, int64_t dst, int64_t sib = -1,
                                            const void* __restrict__ parent = nullptr) {
+    static_assert(PREC != CBH_PREC_F64, "F64 histograms are merged as TWOFLOAT");
     const int wpc = PREC == CBH_PREC_TWOFLOAT ? 4 * K : 2 * K;
     const int64_t cw = cells * wpc;
     for (int c = 0; c < K; ++c) {
@@ -498,6 +595,7 @@ template <int PREC>
 __device__ __forceinline__ uint8_t parent_side(const void* __restrict__ parent, int64_t p, int f,
                                                int k, int32_t F, int32_t B, int32_t K,
                                                int32_t rmse, int lane) {
+    static_assert(PREC != CBH_PREC_F64, "F64 histograms are read as TWOFLOAT");
     if (f < 0 || f >= F) return 1;
     double left = 0.0, right = 0.0;
     for (int b = lane; b < B; b += 64) {
@@ -528,9 +626,13 @@ struct FeatBest {
     int32_t pad;
 };
 
-__device__ __forceinline__ float side_term(float G, float H, float l2) {
-    const float d = H + l2;
-    return d == 0.0f ? 0.0f : (G * G) / d;
+// One side's term G^2 / (H + l2), in double: a feature's score adds up to
+// 2^level * K * 2 terms (C5's deepest level: 10240), and a float sum of that
+// many terms could be off by more than the 1e-5 relative margin that decides
+// which of two close splits wins.
+__device__ __forceinline__ double side_term(double G, double H, double l2) {
+    const double d = H + l2;
+    return d == 0.0 ? 0.0 : (G * G) / d;
 }
 
 // top-2 merge: larger score wins, ties go to the smaller index
@@ -562,7 +664,7 @@ struct ScoreRow {
     const void* hist;
     const float* grad_scale;
     int32_t F, B, K, rmse;
-    float l2;
+    double l2;
 };
 
 // Terms of one histogram row (leaf L, feature f, class c) for the 4 borders
@@ -570,7 +672,8 @@ struct ScoreRow {
 // accumulator type of the precision (float, two-float or exact int64).
 template <int PREC>
 __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int kmax,
-                          float acc[4]) {
+                          double acc[4]) {
+    static_assert(PREC != CBH_PREC_F64, "F64 histograms are scored as TWOFLOAT");
     const int64_t cell0 = (int64_t(L) * a.F + f) * a.B;
     const int b0 = 4 * lane;
     if constexpr (PREC == CBH_PREC_FP32) {
@@ -650,8 +753,10 @@ __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int 
             if (b0 + j < kmax) {
                 const F2 gl = f2_add(ge, G[j]), hl = f2_add(he, H[j]);
                 const F2 gr = f2_add(gt, f2_neg(gl)), hr = f2_add(ht, f2_neg(hl));
-                acc[j] += side_term(gl.hi + gl.lo, hl.hi + hl.lo, a.l2) +
-                          side_term(gr.hi + gr.lo, hr.hi + hr.lo, a.l2);
+                acc[j] += side_term((double)gl.hi + (double)gl.lo, (double)hl.hi + (double)hl.lo,
+                                    a.l2) +
+                          side_term((double)gr.hi + (double)gr.lo, (double)hr.hi + (double)hr.lo,
+                                    a.l2);
             }
         }
     } else {
@@ -690,10 +795,8 @@ __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int 
         for (int j = 0; j < 4; ++j) {
             if (b0 + j < kmax) {
                 const int64_t gl = ge + G[j], hl = he + H[j];
-                const float fgl = (float)((double)gl * sg), fhl = (float)((double)hl * sh);
-                const float fgr = (float)((double)(gt - gl) * sg);
-                const float fhr = (float)((double)(ht - hl) * sh);
-                acc[j] += side_term(fgl, fhl, a.l2) + side_term(fgr, fhr, a.l2);
+                acc[j] += side_term((double)gl * sg, (double)hl * sh, a.l2) +
+                          side_term((double)(gt - gl) * sg, (double)(ht - hl) * sh, a.l2);
             }
         }
     }
@@ -706,12 +809,12 @@ __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int 
 template <int PREC, int NW = 4>
 __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, float* scores,
                               FeatBest* out) {
-    __shared__ float part[NW][256];
+    __shared__ double part[NW][256];
     __shared__ float rs1[NW], rs2[NW];
     __shared__ int ri1[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kmax = min(n_bins_f, a.B) - 1;  // candidates k < kmax
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (kmax > 0) {
         const int items = L * a.K;
         for (int it = wave; it < items; it += NW) row_terms<PREC>(a, it / a.K, f, it % a.K, lane,
@@ -723,9 +826,10 @@ __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, flo
     const int k = threadIdx.x;  // thread k < 256 owns border k
     float s = -INFINITY;
     if (k < kmax) {
-        s = part[0][k] + part[1][k];
+        double sd = part[0][k] + part[1][k];
 #pragma unroll
-        for (int w = 2; w < NW; ++w) s += part[w][k];
+        for (int w = 2; w < NW; ++w) sd += part[w][k];
+        s = (float)sd;
         if (s != s) s = -INFINITY;
     }
     if (scores && k < a.B - 1) scores[int64_t(f) * (a.B - 1) + k] = s;
@@ -846,10 +950,11 @@ struct LpfBlock {
 // For one class (K = 1). Lane l of a wave owns feature f0 + l % W of the
 // block's group of W features and the 16-row segment l / W of the wave's
 // current group of 64 / W segments. The LDS tile is [slot][bin][stat][W] of
-// 8-byte elements (one stat, the packed int16 codes; or two, FP64 g and then
-// the count or the FP64 h), so in one atomic instruction the lanes with
-// distinct features touch distinct banks whatever their bins are, with no
-// replicas. With the bins in
+// 8-byte elements (one stat, the packed int16 codes; or two: the g sum (a
+// float64, a (hi, lo) pair or a float) and then the count or the h sum in
+// the same form; FP32 with h keeps the (g, h) float pair in the first), so
+// in one LDS instruction the lanes with distinct features touch distinct
+// banks whatever their bins are, with no replicas. With the bins in
 // the tiled layout the W segments of one row group are adjacent in memory and
 // a wave's bin load is fully coalesced; plain columns work too.
 // LDS byte offset, in slot 0, of the first stat of (bin of row r of the
@@ -874,12 +979,136 @@ __device__ __forceinline__ uint32_t lpf_addr(const uint32_t (&bw)[4], int r, uin
 // row is known to be valid.
 constexpr uint32_t kLpfSkip = 0xffffffffu;
 
+// Float32 forms (cells updated by compare-and-swap, see lds_cas32): the
+// eight rows' cells are read, all eight swaps are issued back to back, and
+// only the rows whose swap found the cell changed (another row of this lane
+// on the same bin, or another wave) are redone one at a time. Cell layout
+// (8 bytes each at `ad` and `ad + W * 8`):
+//   FP32, RMSE:      float g sum at ad, u32 count at ad + W * 8
+//   FP32, h:         (g, h) float pair at ad, one 64-bit swap for both
+//   TWOFLOAT, RMSE:  (g hi, g lo) at ad, u32 count at ad + W * 8
+//   TWOFLOAT, h:     (g hi, g lo) at ad, (h hi, h lo) at ad + W * 8
+template <int PREC, int RM, int W, bool CHECK>
+__device__ __forceinline__ void lpf_rows8_cas(char* tile, const uint32_t (&bw)[4], int r0,
+                                              uint32_t lane_off, const uint32_t (&off)[8],
+                                              const float (&gv)[8], const float (&hv)[8]) {
+    constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+    uint32_t ad[8];
+    bool ok[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ok[k] = !CHECK || off[k] != kLpfSkip;
+        ad[k] = ok[k] ? lpf_addr<W, CS>(bw, r0 + k, lane_off) + off[k] : 0u;
+    }
+    if constexpr (PREC == CBH_PREC_FP32 && RM != 0) {
+        uint32_t old[8], got[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            old[k] = ok[k] ? lds_load32(reinterpret_cast<uint32_t*>(tile + ad[k])) : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            got[k] = ok[k] ? lds_cas32(reinterpret_cast<uint32_t*>(tile + ad[k]), old[k],
+                                       __float_as_uint(__uint_as_float(old[k]) + gv[k]))
+                           : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (ok[k])
+                __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad[k] + W * 8), 1u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            while (got[k] != old[k]) {
+                old[k] = got[k];
+                got[k] = lds_cas32(reinterpret_cast<uint32_t*>(tile + ad[k]), old[k],
+                                   __float_as_uint(__uint_as_float(old[k]) + gv[k]));
+            }
+        }
+    } else {
+        // the 64-bit word at ad: (g, h) pair (FP32) or the (hi, lo) g pair
+        const auto upd = [&](uint64_t w, int k) -> uint64_t {
+            if constexpr (PREC == CBH_PREC_FP32) return add_pair_word(w, gv[k], hv[k]);
+            else return twosum_word(w, gv[k]);
+        };
+        uint64_t old[8], got[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            old[k] = ok[k] ? lds_load64(reinterpret_cast<uint64_t*>(tile + ad[k])) : 0ull;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            got[k] = ok[k] ? lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k]), old[k],
+                                       upd(old[k], k))
+                           : 0ull;
+        if constexpr (PREC == CBH_PREC_TWOFLOAT) {
+            if constexpr (RM != 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (ok[k])
+                        __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad[k] + W * 8),
+                                               1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                uint64_t oh[8], gh[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    oh[k] = ok[k] ? lds_load64(reinterpret_cast<uint64_t*>(tile + ad[k] + W * 8))
+                                  : 0ull;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    gh[k] = ok[k] ? lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k] + W * 8),
+                                              oh[k], twosum_word(oh[k], hv[k]))
+                                  : 0ull;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    while (gh[k] != oh[k]) {
+                        oh[k] = gh[k];
+                        gh[k] = lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k] + W * 8),
+                                          oh[k], twosum_word(oh[k], hv[k]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            while (got[k] != old[k]) {
+                old[k] = got[k];
+                got[k] = lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k]), old[k],
+                                   upd(old[k], k));
+            }
+        }
+    }
+}
+
+// One row of a float32 form (the ragged tail), same cells as lpf_rows8_cas.
+template <int PREC, int RM, int W>
+__device__ __forceinline__ void lpf_row1_cas(char* tile, uint32_t ad, float g, float h) {
+    if constexpr (PREC == CBH_PREC_FP32 && RM != 0) {
+        cas_add_f32(reinterpret_cast<uint32_t*>(tile + ad), g);
+    } else if constexpr (PREC == CBH_PREC_FP32) {
+        uint64_t* p = reinterpret_cast<uint64_t*>(tile + ad);
+        uint64_t old = lds_load64(p);
+        for (;;) {
+            const uint64_t got = lds_cas64(p, old, add_pair_word(old, g, h));
+            if (got == old) break;
+            old = got;
+        }
+    } else {
+        cas_twosum(reinterpret_cast<uint64_t*>(tile + ad), g);
+        if constexpr (RM == 0) cas_twosum(reinterpret_cast<uint64_t*>(tile + ad + W * 8), h);
+    }
+    if constexpr (RM != 0)
+        __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(tile + ad + W * 8), 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int PREC, int RM, int W, bool CHECK>
 __device__ __forceinline__ void lpf_rows8(char* tile, const uint32_t (&bw)[4], int r0,
                                           uint32_t lane_off, const uint32_t (&off)[8],
                                           const float (&gv)[8], const float (&hv)[8],
                                           const uint32_t (&qv)[8]) {
     constexpr uint32_t CS = lpf_cell_bytes<PREC>();
+    if constexpr (PREC == CBH_PREC_FP32 || PREC == CBH_PREC_TWOFLOAT) {
+        lpf_rows8_cas<PREC, RM, W, CHECK>(tile, bw, r0, lane_off, off, gv, hv);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (CHECK && off[k] == kLpfSkip) continue;
@@ -1099,6 +1328,8 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
                     __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(tile + ad),
                                            (unsigned long long)packed, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else if constexpr (PREC != CBH_PREC_F64) {
+                    lpf_row1_cas<PREC, RM, W>(tile, ad, g1[0], h1[0]);
                 } else {
                     __hip_atomic_fetch_add(reinterpret_cast<double*>(tile + ad), (double)g1[0],
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1138,6 +1369,24 @@ __device__ __forceinline__ void lpf_flush(const LpfBlock& a, int fg, uint32_t s0
             ((int64_t(s0 + sl - part_slot0) * a.F + f0 + cfl) * a.B + bin) * a.wpc + a.coff;
         if constexpr (PREC == CBH_PREC_INT16) {
             *reinterpret_cast<uint2*>(part + o) = *reinterpret_cast<const uint2*>(cell);
+        } else if constexpr (PREC == CBH_PREC_FP32) {
+            const uint2 w = *reinterpret_cast<const uint2*>(cell);
+            const uint32_t w1 = RM != 0 ? *reinterpret_cast<const uint32_t*>(cell + W * 8) : w.y;
+            *reinterpret_cast<uint2*>(part + o) = make_uint2(w.x, w1);
+        } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
+            const uint2 gw = *reinterpret_cast<const uint2*>(cell);
+            const float2 gr = renorm_pair(__uint_as_float(gw.x), __uint_as_float(gw.y));
+            uint32_t w1, hlo = 0u;
+            if constexpr (RM != 0) {
+                w1 = *reinterpret_cast<const uint32_t*>(cell + W * 8);
+            } else {
+                const uint2 hw = *reinterpret_cast<const uint2*>(cell + W * 8);
+                const float2 hr = renorm_pair(__uint_as_float(hw.x), __uint_as_float(hw.y));
+                w1 = __float_as_uint(hr.x);
+                hlo = __float_as_uint(hr.y);
+            }
+            *reinterpret_cast<uint4*>(part + o) =
+                make_uint4(__float_as_uint(gr.x), __float_as_uint(gr.y), w1, hlo);
         } else {
             const double gs = *reinterpret_cast<const double*>(cell);
             const float ghi = (float)gs;
@@ -1151,14 +1400,10 @@ __device__ __forceinline__ void lpf_flush(const LpfBlock& a, int fg, uint32_t s0
                 hlo = (float)(hs - (double)hhi);
                 w1 = __float_as_uint(hhi);
             }
-            if constexpr (PREC == CBH_PREC_FP32) {
-                *reinterpret_cast<uint2*>(part + o) = make_uint2(__float_as_uint(ghi), w1);
-            } else {
-                const float glo = (float)(gs - (double)ghi);
-                *reinterpret_cast<uint4*>(part + o) =
-                    make_uint4(__float_as_uint(ghi), __float_as_uint(glo), w1,
-                               RM != 0 ? 0u : __float_as_uint(hlo));
-            }
+            const float glo = (float)(gs - (double)ghi);
+            *reinterpret_cast<uint4*>(part + o) =
+                make_uint4(__float_as_uint(ghi), __float_as_uint(glo), w1,
+                           RM != 0 ? 0u : __float_as_uint(hlo));
         }
     }
 }

@@ -557,7 +557,15 @@ void part_init_attrs(int max_lds) {
         (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 32>,
         (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 16>,
         (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 8>,
-        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 4>};
+        (const void*)hist_part_kernel<CBH_PREC_INT16, 0, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 0, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 0, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 0, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 0, 4>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 1, 32>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 1, 16>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 1, 8>,
+        (const void*)hist_part_kernel<CBH_PREC_F64, 1, 4>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
@@ -794,7 +802,7 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     const int64_t n_tiles = plan.n_ltiles;
     const int64_t max_chunks = (part->n_pad / 16 + n_tiles + spc - 1) / spc + n_tiles + 1;
     const int64_t cell_words = int64_t(plan.lt) * F * B * plan.words_per_cell;
-    rc = ensure_ws(ctx, max_chunks * cell_words * 4);
+    rc = ensure_ws(ctx, max_chunks * cell_words * 4, stream);
     if (rc) return rc;
     part_tiles_kernel<<<1, 1024, 0, s>>>(part->off[src], L, plan.lt, (int32_t)n_tiles, spc,
                                           part->cp);
@@ -832,6 +840,10 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
             if (rmse) launch_part_hist<CBH_PREC_TWOFLOAT, 1>(a, plan.fb, grid, lds, s);
             else launch_part_hist<CBH_PREC_TWOFLOAT, 0>(a, plan.fb, grid, lds, s);
             break;
+        case CBH_PREC_F64:
+            if (rmse) launch_part_hist<CBH_PREC_F64, 1>(a, plan.fb, grid, lds, s);
+            else launch_part_hist<CBH_PREC_F64, 0>(a, plan.fb, grid, lds, s);
+            break;
         default:
             launch_part_hist<CBH_PREC_INT16, 0>(a, plan.fb, grid, lds, s);
             break;
@@ -840,7 +852,7 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     const int64_t units = int64_t(L) * F * B * K;
     const unsigned mg =
         (unsigned)std::min<int64_t>((units + 255) / 256, int64_t(ctx->num_cus) * 16);
-    switch (precision) {
+    switch (out_prec(precision)) {
         case CBH_PREC_FP32:
             part_merge_kernel<CBH_PREC_FP32><<<mg, 256, 0, s>>>(
                 (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,

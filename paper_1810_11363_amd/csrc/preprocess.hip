@@ -526,7 +526,7 @@ int cbh_compute_ordered_ts(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm
                   o_v1 = take(4 * n), o_den = take(8 * n), o_num = take(8 * n),
                   o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
                   o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
-    int rc = ensure_ws(ctx, off);
+    int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
     uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
@@ -605,7 +605,7 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
                   o_v1 = take(4 * n), o_head = take(8 * n), o_excl = take(8 * n),
                   o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
                   o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
-    int rc = ensure_ws(ctx, off);
+    int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
     uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
@@ -667,7 +667,7 @@ int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* co
     CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
     if (n == 0) return CBH_OK;
     CBH_ARG(ids && counts_out, "NULL argument");
-    int rc = ensure_ws(ctx, 4 * n);
+    int rc = ensure_ws(ctx, 4 * n, stream);
     if (rc != CBH_OK) return rc;
     int32_t* cnt = (int32_t*)ctx->ws;
     hipStream_t s = (hipStream_t)stream;

@@ -9,7 +9,8 @@
 //
 // Kernel 1: one block per feature; each wave takes (leaf, class) rows of the
 // histogram, one lane per 4 consecutive bins, forms bin prefixes with a wave
-// scan, and accumulates the per-border terms in registers. The waves'
+// scan (in the histogram's own type), and accumulates the per-border terms in
+// double registers. The waves'
 // partial scores are added in wave order (deterministic), then the block
 // keeps its best and second-best border. The last block to finish (a
 // device counter, reset by that block, so the launch needs no clearing and
@@ -64,7 +65,7 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     r.B = p->max_bins;
     r.K = p->K;
     r.rmse = p->loss == CBH_LOSS_RMSE;
-    r.l2 = (float)l2;
+    r.l2 = l2;
     const int L = 1 << level;
     FeatBest* fb = (FeatBest*)scratch;
     uint32_t* counter = ctx->d_flags + 1;
@@ -76,7 +77,7 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     else                                                                                  \
         score_split_kernel<P, kScoreWaves><<<r.F, 64 * kScoreWaves, 0, s>>>(              \
             r, p->n_bins, L, scores, fb, counter, best);
-    switch (precision) {
+    switch (out_prec(precision)) {
         case CBH_PREC_FP32: CBH_SCORE(CBH_PREC_FP32) break;
         case CBH_PREC_TWOFLOAT: CBH_SCORE(CBH_PREC_TWOFLOAT) break;
         default: CBH_SCORE(CBH_PREC_INT16) break;
@@ -102,7 +103,7 @@ extern "C" int cbh_score_splits(cbh_ctx* ctx, const cbh_problem* prob, int32_t l
     CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
     CBH_ARG(hist && best_out, "hist / best_out is NULL");
     CBH_ARG(l2 >= 0 && std::isfinite(l2), "l2 must be finite and >= 0");
-    rc = ensure_ws(ctx, score_scratch_bytes(prob));
+    rc = ensure_ws(ctx, score_scratch_bytes(prob), stream);
     if (rc) return rc;
     return launch_score(ctx, prob, level, hist, precision, l2, best_out, scores_out, ctx->ws,
                         (hipStream_t)stream);

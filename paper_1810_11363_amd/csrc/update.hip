@@ -234,7 +234,7 @@ int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_las
         sa.B = p->max_bins;
         sa.K = p->K;
         sa.rmse = p->loss == CBH_LOSS_RMSE;
-        sa.precision = precision;
+        sa.precision = out_prec(precision);
         sa.l2 = l2;
         const int64_t work = leaves * p->K;
         leaf_solve_kernel<<<(unsigned)((work + 3) / 4), 256, 0, s>>>(sa);
@@ -419,7 +419,7 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
     const int64_t per_grid = std::max<int64_t>(1, int64_t(INT32_MAX) / rblocks);
     const int32_t chunk =
         (int32_t)std::min<int64_t>({int64_t(n_trees), per, per_grid, 65535});
-    int rc = ensure_ws(ctx, int64_t(chunk) * n * lb);
+    int rc = ensure_ws(ctx, int64_t(chunk) * n * lb, stream);
     if (rc) return rc;
     ApplyArgs a;
     a.bins = bins;

@@ -11,8 +11,18 @@ import numpy as np
 import torch
 
 FP32_TOL = 1e-5        # normalized error bound for float32 histogram sums and leaf values
-TWOFLOAT_TOL = 1e-9    # compensated sums are exact to about 2^-46 relative
+TWOFLOAT_TOL = 1e-9    # compensated and float64-accumulated sums: exact to about 2^-46
 MARGIN_TOL = 1e-5      # splits must agree where the oracle's top-two gap exceeds this
+
+# histogram forms (CBH_PREC_*): float32, compensated float32, int16 codes,
+# float64 LDS accumulation (written in the compensated form's (hi, lo) layout)
+FP32, TWOFLOAT, INT16, F64 = 0, 1, 2, 3
+PRECS = [FP32, TWOFLOAT, INT16, F64]
+
+
+def pair_layout(precision):
+    """True for the forms whose histograms hold (hi, lo) float pairs."""
+    return precision in (TWOFLOAT, F64)
 
 
 def dev():
@@ -51,7 +61,7 @@ def hist_to_f64(hist_dev, L, F, B, K, precision, rmse):
             u = hist_dev[: L * F * B * 2 * K * 4].view(torch.int32).cpu().numpy()
             out[..., 1::2] = u.reshape(L, F, B, 2 * K)[..., 1::2].astype(np.uint32)
         return out
-    if precision == 1:
+    if pair_layout(precision):
         raw = hist_dev[: L * F * B * 2 * K * 8].view(torch.float32).cpu().numpy()
         pair = raw.reshape(L, F, B, 2 * K, 2).astype(np.float64)
         out = pair[..., 0] + pair[..., 1]
@@ -64,14 +74,32 @@ def hist_to_f64(hist_dev, L, F, B, K, precision, rmse):
     return raw.reshape(L, F, B, 2 * K)
 
 
-def normalized_err(x, ref, mag):
-    """max |x - ref| / mag over cells; cells with mag == 0 must match exactly."""
+# Allowance, relative to the bin's mass over all rows, for histograms built
+# by subtraction (a sibling is its parent minus the accumulated child, so it
+# carries the parent's rounding): compensated and float64 forms, plain float32.
+SUB_SLACK_PAIR = 1e-12
+SUB_SLACK_FP32 = 1e-5
+
+
+def normalized_err(x, ref, mag, slack=None):
+    """max |x - ref| / mag over cells; cells with mag == 0 must match exactly.
+    With `slack` (an array broadcastable to x), that much absolute error is
+    allowed in every cell first (a subtraction's share)."""
     x, ref, mag = np.asarray(x, np.float64), np.asarray(ref, np.float64), np.asarray(mag, np.float64)
+    d = np.abs(x - ref)
+    if slack is not None:
+        d = np.maximum(d - np.asarray(slack, np.float64), 0.0)
     zero = mag == 0
-    assert np.all(x[zero] == ref[zero]), "empty cells differ"
+    assert np.all(d[zero] == 0), "empty cells differ"
     if (~zero).sum() == 0:
         return 0.0
-    return float(np.max(np.abs(x[~zero] - ref[~zero]) / mag[~zero]))
+    return float(np.max(d[~zero] / mag[~zero]))
+
+
+def sub_slack(precision, root_mag):
+    """Slack of a level built by subtraction: root_mag is the histogram of the
+    absolute statistics over all rows ([1][F][B][2K], one leaf)."""
+    return (SUB_SLACK_FP32 if precision == FP32 else SUB_SLACK_PAIR) * root_mag
 
 
 def split_of(best_dev, level=0):

@@ -199,7 +199,7 @@ HIST_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("case", HIST_CASES)
 def test_histograms_vs_oracle(cb, ctx, case, prec):
     n, F, B, K, loss, level = case
@@ -276,7 +276,7 @@ def _tiled_problem(cb, ctx, p, dev, n, F):
 KERNEL_CONFIGS = [(0, 0), (1, 32), (1, 16), (1, 8), (1, 4)]
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("layout", ["columns", "tiled"])
 @pytest.mark.parametrize("kcfg", KERNEL_CONFIGS)
 @pytest.mark.parametrize("case", [(20011, 37, 128, 0, 0), (20011, 37, 128, 1, 3),
@@ -314,7 +314,7 @@ def test_histogram_kernels_and_layouts(cb, ctx, case, kcfg, layout, prec):
         assert np.array_equal(got[..., 1::2], want[..., 1::2])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("kcfg", KERNEL_CONFIGS)
 @pytest.mark.parametrize("case", [(9001, 13, 64, 3, 0), (9001, 13, 64, 3, 3),
                                   (4099, 6, 255, 10, 2)])
@@ -350,7 +350,7 @@ def test_multiclass_histogram_kernels(cb, ctx, case, kcfg, prec):
     assert gu.normalized_err(got, want, mag) <= (gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL)
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("kcfg", [(0, 0), (1, 32), (1, 8)])
 def test_subtraction_kernels_vs_oracle(cb, ctx, kcfg, prec):
     """A level built by subtraction (smaller child accumulated, sibling =
@@ -392,7 +392,7 @@ def test_subtraction_kernels_vs_oracle(cb, ctx, kcfg, prec):
     assert np.array_equal(got[..., 1::2], want[..., 1::2])
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("kcfg,level,B", [((1, 32), 1, 64), ((1, 32), 3, 64), ((1, 8), 5, 64),
                                           ((0, 0), 1, 64), ((0, 0), 3, 64), ((1, 4), 8, 255)])
 def test_apply_fused_build_matches_separate(cb, ctx, kcfg, level, B, prec):
@@ -459,7 +459,7 @@ def test_int16_histogram_deterministic(cb, ctx):
 
 
 # ------------------------------------------------------------- score/argmax
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("case", [(5003, 9, 64, 1, 1, 0), (5003, 9, 64, 1, 0, 3),
                                   (3001, 4, 255, 1, 1, 6), (2003, 3, 32, 4, 2, 2)])
 def test_score_and_argmax_vs_oracle(cb, ctx, case, prec):
@@ -540,7 +540,7 @@ def test_apply_split_bit_exact(cb, ctx, n):
     assert np.array_equal(dev["leaf"].cpu().numpy(), (bins[1] > 5).astype(np.uint16))
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("loss,K", [(0, 1), (1, 1), (2, 3)])
 def test_update_approx_vs_oracle(cb, ctx, loss, K, prec):
     n, F, B, depth = 20011, 4, 32, 3

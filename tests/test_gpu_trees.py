@@ -86,7 +86,11 @@ def _lockstep_tree(cb, bst, t, stats):
         else:
             want = oracle.histogram(bins, gd, hd, leaf, L, B)
             mag = oracle.histogram(bins, np.abs(gd), np.abs(hd), leaf, L, B)
-            e = gu.normalized_err(got, want, mag)
+            slack = None
+            if lvl >= 1 and bst.subtract and not bst.use_part:
+                root = oracle.histogram(bins, np.abs(gd), np.abs(hd), np.zeros(n, np.uint16), 1, B)
+                slack = gu.sub_slack(prec, root)
+            e = gu.normalized_err(got, want, mag, slack)
             stats["hist_err"] = max(stats.get("hist_err", 0.0), e)
             assert e <= (gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL)
         ref = oracle.score(got, nb, L2)
@@ -138,7 +142,7 @@ def _shrink(p, iters, depth=None):
 
 
 @pytest.mark.parametrize("partition", [False, True])
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 @pytest.mark.parametrize("name", list(CASES))
 def test_lockstep_trees(cb, name, prec, partition):
     p = CASES[name]()
@@ -155,7 +159,7 @@ def test_lockstep_trees(cb, name, prec, partition):
     bst.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 def test_subtraction_matches_direct(cb, prec):
     """Level histograms by subtraction equal the direct build: bit for bit for
     int16 sums and counts, within two-float rounding for the compensated form,
@@ -182,8 +186,11 @@ def test_subtraction_matches_direct(cb, prec):
         else:
             leaf = bst.leaf.cpu().numpy() if lvl else np.zeros(bst.n, np.uint16)
             mag = oracle.histogram(bst.bins_host(0), np.abs(g), np.ones_like(g), leaf, L, bst.B)
-            if prec == 1:
-                assert gu.normalized_err(a[..., 0], b[..., 0], mag[..., 0]) <= 1e-9
+            if gu.pair_layout(prec):
+                root = oracle.histogram(bst.bins_host(0), np.abs(g), np.ones_like(g),
+                                        np.zeros(bst.n, np.uint16), 1, bst.B)
+                slack = gu.sub_slack(prec, root[..., 0])
+                assert gu.normalized_err(a[..., 0], b[..., 0], mag[..., 0], slack) <= 1e-9
             else:
                 # float differences carry the rounding of every ancestor level:
                 # judge them against the bin's mass over all rows (level 0)
@@ -203,14 +210,24 @@ def test_independent_run_matches_oracle_c1(cb):
     bst = _booster(cb, p, 0)
     trees = bst.fit(p.iterations)
     otrees, oapprox, _ = boost.fit(p)
+    # trees are compared up to the first near-tie (after it the two runs may
+    # legitimately grow different trees); at least the first tree must be
+    # compared in full, so the check cannot vanish
+    compared, tie = 0, None
     for t, (gt, ot) in enumerate(zip(trees, otrees)):
         for lvl in range(p.depth):
             f, k, s1, s2 = ot.splits[lvl]
-            if s1 - s2 > gu.MARGIN_TOL * abs(s1):
-                assert tuple(gt.splits[lvl]) == (f, k), (t, lvl)
-            else:
-                pytest.skip(f"near-tie at tree {t} level {lvl}; lock-step test covers it")
-    np.testing.assert_allclose(bst.approx.cpu().numpy(), oapprox, rtol=1e-5, atol=1e-6)
+            if s1 - s2 <= gu.MARGIN_TOL * abs(s1):
+                tie = (t, lvl)
+                break
+            assert tuple(gt.splits[lvl]) == (f, k), (t, lvl)
+            compared += 1
+        if tie:
+            break
+    print("levels compared", compared, "first near-tie", tie)
+    assert compared >= p.depth
+    if tie is None:
+        np.testing.assert_allclose(bst.approx.cpu().numpy(), oapprox, rtol=1e-5, atol=1e-6)
     bst.close()
 
 
@@ -268,7 +285,7 @@ BATCH_KNOBS = {"default": None, "lpf_split": (12288, 1024, 4096, 50, 1, 1, 1, 0)
 
 @pytest.mark.parametrize("subtract", [True, False])
 @pytest.mark.parametrize("knobs", list(BATCH_KNOBS))
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", gu.PRECS)
 def test_batched_matches_single(cb, prec, knobs, subtract):
     probs = datagen.make_c4(P=5, scale=0.01)
     for p in probs:
@@ -287,6 +304,7 @@ def test_batched_matches_single(cb, prec, knobs, subtract):
         for b in single:
             b.init_gradients()
         cb.cbh_batch_update(ctx, plan, 0.1, 3.0, [b.leaf_values for b in batched], True)
+        diverged, checked = set(), 0
         for it in range(3):
             for b in single:
                 b.fit_tree(0)
@@ -298,25 +316,138 @@ def test_batched_matches_single(cb, prec, knobs, subtract):
             cb.cbh_batch_update(ctx, plan, 0.1, 3.0, [b.leaf_values for b in batched], False)
             torch.cuda.synchronize()
             for i, (s, b) in enumerate(zip(single, batched)):
+                if i in diverged:
+                    continue
                 sb = s.best.cpu().numpy()[:, :2]
                 bb = best[i].cpu().numpy()[:, :2]
                 if prec == 2:
                     assert np.array_equal(sb, bb), (it, i)
                     assert torch.equal(s.leaf, b.leaf)
                     assert torch.equal(s.approx, b.approx)
-                else:
-                    # float32 sums differ in order between the two launch plans:
-                    # splits must agree wherever the single run's margin is clear
-                    sc = s.best.cpu().numpy()[:, 2:].view(np.float32)
-                    for lvl in range(depth):
-                        if sc[lvl, 1] > gu.MARGIN_TOL * abs(sc[lvl, 0]):
-                            assert np.array_equal(sb[lvl], bb[lvl]), (it, i, lvl)
-                        else:
-                            return
-                    torch.testing.assert_close(s.approx, b.approx, rtol=1e-5, atol=1e-6)
+                    checked += 1
+                    continue
+                # float sums differ in order between the two launch plans:
+                # splits must agree wherever the single run's margin is clear;
+                # after a near-tie the two runs of that problem may grow
+                # different trees, so that problem is compared no further
+                sc = s.best.cpu().numpy()[:, 2:].view(np.float32)
+                for lvl in range(depth):
+                    if sc[lvl, 1] > gu.MARGIN_TOL * abs(sc[lvl, 0]):
+                        assert np.array_equal(sb[lvl], bb[lvl]), (it, i, lvl)
+                    elif not np.array_equal(sb[lvl], bb[lvl]):
+                        diverged.add(i)
+                        break
+                if i in diverged:
+                    continue
+                torch.testing.assert_close(s.approx, b.approx, rtol=1e-5, atol=1e-6)
+                checked += 1
+        # most (problem, iteration) pairs are compared in full
+        assert checked >= 2 * P, (checked, diverged)
     finally:
         cb.cbh_batch_destroy(plan)
         for b in single + batched:
+            b.close()
+
+
+@pytest.mark.parametrize("subtract", [False, True])
+@pytest.mark.parametrize("prec", gu.PRECS)
+def test_batched_lockstep_oracle_c4(cb, prec, subtract):
+    """cbh_batch_level against the oracle, problem by problem and level by
+    level, at the batching workload's shape (54 columns at 64 bins, RMSE,
+    log-uniform row counts, scaled down): every level's histograms where the
+    caller's buffer holds them (every level without subtraction, every other
+    level with it; int16 bit for bit), the split by the margin rule on the
+    oracle's scores of the GPU's histogram (of the oracle's own where the
+    plan's second buffer holds it), the leaf indices after every level, then
+    leaf values and counts, and approx bit for bit given the leaf values. The
+    oracle follows the GPU's split (lock-step)."""
+    from oracle import boost
+    probs = datagen.make_c4(P=6, scale=0.02)
+    bsts = _batch_setup(cb, probs, prec)
+    preps = [boost.prepare(p) for p in probs]
+    ctx = bsts[0].ctx
+    P, depth, l2, lr = len(probs), probs[0].depth, probs[0].l2, probs[0].lr
+    for b, pp in zip(bsts, preps):
+        assert np.array_equal(b.bins_host(0), pp.tree_features(0)[0])
+    best = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    lvs = [b.leaf_values for b in bsts]
+    plan = cb.cbh_batch_create(ctx, [b.probs[0] for b in bsts], prec, [b.hist for b in bsts],
+                               best, subtract=subtract)
+    ties = 0
+    try:
+        cb.cbh_batch_update(ctx, plan, lr, l2, lvs, True)
+        for it in range(2):
+            if prec == 2:
+                for b in bsts:
+                    cb.cbh_quantize_gradients(ctx, b.probs[0])
+            torch.cuda.synchronize()
+            gd, codes, leaves = [], [], []
+            for b in bsts:
+                g32 = b.g.cpu().numpy().astype(np.float64)
+                if prec == 2:
+                    gq = b.gq.cpu().numpy()
+                    sc = b.grad_scale.cpu().numpy().astype(np.float64)
+                    rgq, rhq, _ = oracle.grad_codes(b.g.cpu().numpy(), None, False)
+                    assert np.array_equal(gq[..., 0], rgq)
+                    codes.append((rgq, rhq, sc))
+                    gd.append(gq[..., 0].astype(np.float64) * sc[:, 0:1])
+                else:
+                    gd.append(g32)
+                leaves.append(np.zeros(b.n, np.uint16))
+            for lvl in range(depth):
+                L = 1 << lvl
+                cb.cbh_batch_level(ctx, plan, lvl, l2)
+                torch.cuda.synchronize()
+                own = (not subtract) or (depth - 1 - lvl) % 2 == 0
+                for i, b in enumerate(bsts):
+                    bins, nb = preps[i].tree_features(0)
+                    ones = np.ones_like(gd[i])
+                    f, k = (int(v) for v in best[i, lvl, :2].cpu().numpy())
+                    if own:
+                        got = gu.hist_to_f64(b.hist, L, b.F, b.B, 1, prec, True)
+                        if prec == 2:
+                            rgq, rhq, sc = codes[i]
+                            want = oracle.histogram_int(bins, rgq, rhq, leaves[i], L, b.B)
+                            assert np.array_equal(got, want), (it, i, lvl)
+                            got = got.astype(np.float64)
+                            got[..., 0] *= sc[0, 0]
+                        else:
+                            want = oracle.histogram(bins, gd[i], ones, leaves[i], L, b.B)
+                            mag = oracle.histogram(bins, np.abs(gd[i]), ones, leaves[i], L, b.B)
+                            assert np.array_equal(got[..., 1], want[..., 1]), (it, i, lvl)
+                            tol = gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL
+                            slack = None
+                            if subtract and lvl >= 1:
+                                root = oracle.histogram(bins, np.abs(gd[i]), ones,
+                                                        np.zeros(b.n, np.uint16), 1, b.B)
+                                slack = gu.sub_slack(prec, root)
+                            err = gu.normalized_err(got, want, mag, slack)
+                            assert err <= tol, (it, i, lvl, err)
+                    else:
+                        got = oracle.histogram(bins, gd[i], ones, leaves[i], L, b.B)
+                    ties += not gu.check_split((f, k), oracle.score(got, nb, l2), nb)
+                    if f >= 0:
+                        oracle.apply_split(bins[f], k, lvl, leaves[i])
+                    assert np.array_equal(b.leaf.cpu().numpy(), leaves[i]), (it, i, lvl)
+            a0 = [b.approx.cpu().numpy() for b in bsts]
+            cb.cbh_batch_update(ctx, plan, lr, l2, lvs, False)
+            torch.cuda.synchronize()
+            for i, b in enumerate(bsts):
+                ones = np.ones_like(gd[i])
+                rv, rG, rH, rc = oracle.leaf_values(leaves[i], gd[i], ones, 1 << depth, l2)
+                gv = b.leaf_values.cpu().numpy()
+                magG = oracle.leaf_values(leaves[i], np.abs(gd[i]), ones, 1 << depth, l2)[1]
+                m = magG > 0
+                err = np.abs(gv - rv)[m] * (rH + l2)[m] / magG[m]
+                assert err.max() <= (gu.FP32_TOL if prec == 0 else 1e-9), (it, i)
+                a1 = a0[i].copy()
+                oracle.update_approx(a1, leaves[i], gv, lr)
+                assert np.array_equal(b.approx.cpu().numpy(), a1), (it, i)
+        print("near-ties", ties, "of", 2 * P * depth)
+        assert ties <= P * depth // 4
+    finally:
+        cb.cbh_batch_destroy(plan)
+        for b in bsts:
             b.close()
 
 
@@ -404,13 +535,16 @@ def test_graph_replay_matches_eager(cb):
             b.close()
 
 
-@pytest.mark.parametrize("prec,partition", [(2, False), (1, False), (2, True), (1, True)])
+@pytest.mark.parametrize("prec,partition", [(2, False), (1, False), (2, True), (1, True),
+                                            (3, False), (3, True)])
 def test_tree_graph_matches_eager(cb, prec, partition):
     """Whole trees captured once per permutation and replayed (the benchmark's
     timed form) give the trees that eager calls give: bit for bit for int16;
-    for the compensated form, whose FP64 LDS sums may round differently run to
-    run, the same splits and leaf values within 1e-9. Every replay is checked,
-    with eager reads and synchronisations between replays."""
+    for the compensated and float64 forms, whose LDS sums may round
+    differently run to run, the same splits and leaf values within 1e-9 up to
+    the first near-tie (after one, the runs may grow different trees). Every
+    replay is checked, with eager reads and synchronisations between
+    replays."""
     p = datagen.make_c2(n=60000)
     p.depth = 5
     eager = _booster(cb, p, prec, partition=partition)
@@ -423,6 +557,7 @@ def test_tree_graph_matches_eager(cb, prec, partition):
             eager.fit_tree(t)
             graph.fit_tree(t)
         graph.capture_trees()
+        replayed = 0
         for t in range(s, 3 * s):
             eager.fit_tree(t)
             graph.replay_tree(t)
@@ -433,14 +568,22 @@ def test_tree_graph_matches_eager(cb, prec, partition):
                 assert np.array_equal(re.values, rg.values), t
                 assert torch.equal(eager.approx, graph.approx), t
             else:
+                tie = None
                 for lvl in range(p.depth):
                     if not np.array_equal(re.splits[lvl], rg.splits[lvl]):
                         assert re.scores[lvl, 1] < gu.MARGIN_TOL * abs(re.scores[lvl, 0]), t
-                        return
+                        tie = lvl
+                        break
+                if tie is not None:
+                    print("near-tie at tree", t, "level", tie)
+                    break
                 np.testing.assert_allclose(rg.values, re.values, rtol=1e-9, atol=1e-12)
                 torch.testing.assert_close(graph.approx, eager.approx, rtol=1e-9, atol=1e-12)
+                replayed += 1
             # eager work between replays
             assert int(graph.leaf.to(torch.int32).max().item()) < (1 << p.depth)
+        # the first replayed tree at least was compared in full
+        assert prec == 2 or replayed >= 1
     finally:
         eager.close()
         graph.close()
@@ -533,6 +676,8 @@ def _sampled_tree_check(cb, bst, prec, n_feat, rng):
         cb.cbh_quantize_gradients(bst.ctx, pr, bst.stream)
     torch.cuda.synchronize()
     bins = bst.bins_host(0)
+    nb = bst.nbins_table[0].cpu().numpy()
+    stats = {"ties": 0}
     K, n = bst.K, bst.n
     g32, h32 = bst.g.cpu().numpy(), bst.h.cpu().numpy()
     if prec == 2:
@@ -561,12 +706,29 @@ def _sampled_tree_check(cb, bst, prec, n_feat, rng):
         tot = got[..., 1::2].sum(axis=2)                    # [L][F][K]
         scale = np.abs(tot).max() + 1e-30
         assert np.max(np.abs(tot - tot[:, :1])) <= (0 if prec == 2 else 1e-9) * scale, lvl
+        # the split: the oracle scores the GPU's whole histogram (in float64,
+        # int16 sums scaled back) and the margin rule decides
         f, k = (int(v) for v in bst.best[lvl, :2].cpu().numpy())
+        if prec == 2:
+            sc = bst.grad_scale.cpu().numpy().astype(np.float64)    # [K][2]
+            if bst.loss == 0:
+                sc[:, 1] = 1.0                                       # h is the row count
+            got = got.astype(np.float64)
+            got *= np.stack([sc[:, 0], sc[:, 1]], axis=1).reshape(-1)
+        ref = oracle.score(got, nb, bst.l2)
+        del got
+        clear = gu.check_split((f, k), ref, nb)
+        print(f"level {lvl}: split {(f, k)} clear margin {clear}")
+        stats["ties"] += not clear
         if 0 <= f < bst.F:
             leaf |= ((bins[f] > k).astype(np.uint16) << lvl)
         bst.advance(pr, lvl)
     torch.cuda.synchronize()
     assert np.array_equal(bst.leaf.cpu().numpy(), leaf)
+    # a weak signal leaves many levels without a clear margin (the score sums
+    # every leaf's term, so a small gain is a small fraction of it); those
+    # splits were checked to be within the margin of the best
+    print("levels without a clear margin:", stats["ties"], "of", bst.depth)
 
 
 @pytest.mark.timeout(900)
