@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
-"""Benchmark: per-tree split search on one MI355X for the 1M-row RMSE workload
-(default). `--workload c3` runs the 10M-row, 200-feature, 255-bin Logloss
-precision workload instead, `--workload c4` the batching workload (64
-independent problems, and the 1M-row problem as cross-validation folds and
-as ordered-boosting permutations), `--workload c5` the 50M-row, 10-class
-MultiClass workload.
+"""Benchmark: per-tree split search on one MI355X.
+
+Default (`--workload headline`): the 50M-row, 10-class MultiClass workload
+(the largest configuration, depth 10, 230 histogram columns at 255 bins) is
+the headline; the 1M-row RMSE workload follows as a second block of the same
+JSON line. `--workload c2|c3|c5` runs one workload alone, `--workload c4` the
+batching workload (64 independent problems, and the 1M-row problem as
+cross-validation folds and as ordered-boosting permutations), `apply` and
+`combine` the model-apply and feature-combination workloads.
 
 A step is one boosting iteration: every level's histogram build, scoring,
 argmax and leaf update, then the leaf solve and the model/gradient update.
@@ -13,21 +16,24 @@ the same run and reported beside it. Inputs are resident in HBM before the
 timed region starts.
 
 The data are prepared once; then every histogram form is timed on them in
-turn: the headline form (default: compensated two-float, which meets the
-1e-5 error bar) and, beside it, plain float32 and int16. Each form is
-autotuned first (untimed), then `--warmup` trees run, one tree per permutation
-is captured into a HIP graph, and `--steps` trees are replayed and timed with
-events around the whole loop. The histogram build is then timed inside
-trees: `--hist-trees` more trees are replayed from graphs that hold event nodes
-around every build (each tree read back before the next replay).
-After timing, one more tree is grown level by level and its histograms on
-sampled features are kept; the oracle leg at the end (with the CPU timing of
-the oracle) compares them with FP64 and reports the largest normalised error.
+turn: the headline form (float64 LDS accumulation, the fastest float form on
+gfx950, which meets the 1e-5 error bar) and, beside it on the same launch
+plan, plain float32 accumulation, compensated float32 (TwoSum pairs) and
+int16 codes. Each form is autotuned first where the workload asks for it
+(untimed), then warm-up trees run, one tree per permutation is captured into
+a HIP graph, and the timed trees are replayed with events around the whole
+loop (the comparison forms with fewer trees). The histogram build is then
+timed inside trees: more trees are replayed from graphs that hold
+device-clock stamps around every build. After timing, one more tree is grown
+level by level and its histograms on sampled features are kept; the oracle
+leg at the end (with the CPU timing of the oracle) compares them with FP64
+and reports the largest normalised error.
 
 Prints one JSON line. `value` is the headline form's whole-step throughput
 in 1e9 (rows x features x levels) per second; `roofline` gives the
-histogram build's algorithmic HBM bytes over its event-timed duration
-against 8 TB/s.
+histogram build's algorithmic HBM bytes over its stamp-timed duration
+against 8 TB/s, and beside it (`lds_issue`) the fraction of that duration
+the build's LDS atomics need at the measured per-CU issue rates.
 """
 from __future__ import annotations
 
@@ -43,8 +49,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sec/tree and histogram G row-features/s vs plain FP32, ≤1e-5 rel err"
 PEAK_HBM_GBS = 8000.0
-PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2}
-DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64"}
+PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2, "f64": 3}
+DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64", "f64": "f64"}
 
 
 class Stamp:
@@ -71,20 +77,72 @@ def hist_bytes_per_level(n, F, K, level, rmse, precision):
     return n * F + n * grad + n * leaf
 
 
-# Workloads: the default is the 1M-row RMSE one the headline metric is quoted
-# on; the others are the 10M-row precision workload and reduced runs of it.
+# LDS atomic issue rates (lane updates per clock per CU, the 64 lanes of a
+# wave on distinct banks), measured in the same run by cbh_probe_lds_rates;
+# 256 CUs at 2.4 GHz.
+LDS_RATE = {}
+CU_CLOCKS_PER_S = 256 * 2.4e9
+
+
+def measure_lds_rates():
+    """Fill LDS_RATE once from the library's probe."""
+    if not LDS_RATE:
+        from paper_1810_11363_amd import cbhip as cb
+        ctx = cb.cbh_create(0)
+        try:
+            LDS_RATE.update({k: round(v, 3) for k, v in cb.cbh_probe_lds_rates(ctx).items()})
+        finally:
+            cb.cbh_destroy(ctx)
+    return dict(LDS_RATE)
+
+
+def lds_ops_per_level(n, F, K, rmse, precision):
+    """LDS atomics one full-rows histogram build issues, by instruction (the
+    float64 and int16 forms; the compare-and-swap forms have no fixed count)."""
+    if precision == 3:
+        return {"ds_add_f64": n * F * K, "ds_add_u32": n * F} if rmse else \
+            {"ds_add_f64": n * F * 2 * K}
+    if precision == 2:
+        return {"ds_add_u64": n * F * K}
+    return None
+
+
+def lds_floor_s(ops):
+    """Seconds the LDS needs for `ops` at the measured issue rates."""
+    return sum(c / (LDS_RATE[op] * CU_CLOCKS_PER_S) for op, c in ops.items())
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+# Workloads: "headline" runs c5 then c2 (see the module docstring).
 WORKLOADS = {
     "c2": dict(tag="c2_1m_rmse", n=1_000_000, steps=200, cpu_rows=1_000_000, cpu_trees=20),
     "c3": dict(tag="c3_10m_logloss", n=10_000_000, steps=20, cpu_rows=250_000, cpu_trees=2),
     "c4": dict(tag="c4_batch_rmse", n=0, steps=20, cpu_rows=1_000_000, cpu_trees=1),
-    "c5": dict(tag="c5_50m_multiclass", n=50_000_000, steps=3, cpu_rows=100_000, cpu_trees=1,
-               warmup=1, hist_trees=2, autotune="off", compare="fp32", warmup_s=0.0),
+    "c5": dict(tag="c5_50m_multiclass", n=50_000_000, steps=20, cpu_rows=100_000, cpu_trees=1,
+               warmup=5, hist_trees=2, autotune="off", compare="fp32,twofloat,int16",
+               warmup_s=0.0, compare_steps=2),
     "apply": dict(tag="apply_100k_8000_trees", n=100_000, steps=20, cpu_rows=20_000, cpu_trees=0),
     "combine": dict(tag="combine_10m_pairs", n=10_000_000, steps=10, cpu_rows=1_000_000,
                     cpu_trees=0),
 }
 # per-run defaults a workload may override
-RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,int16", warmup_s=1.0)
+RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,twofloat,int16",
+                    warmup_s=1.0, compare_steps=None)
 
 
 def describe(workload, p, bst):
@@ -107,7 +165,8 @@ def counters_path(workload):
 
 COUNTERS = counters_path("c2")
 COUNTED_SOURCES = ("paper_1810_11363_amd/csrc/kernels_dev.h",
-                   "paper_1810_11363_amd/csrc/histogram.hip")
+                   "paper_1810_11363_amd/csrc/histogram.hip",
+                   "paper_1810_11363_amd/csrc/partition.hip")
 
 
 def measured_traffic(form: str, workload: str = "c2"):
@@ -177,7 +236,7 @@ def hist_f64(raw, L, F, B, K, precision, rmse):
         if rmse:
             out[..., 1::2] = u.reshape(L, F, B, 2 * K)[..., 1::2].astype(np.uint32)
         return out
-    if precision == 1:
+    if precision in (1, 3):
         u = raw[: L * F * B * 2 * K * 8].view(torch.int32).cpu().numpy()
         pair = u.view(np.float32).reshape(L, F, B, 2 * K, 2).astype(np.float64)
         out = pair[..., 0] + pair[..., 1]
@@ -283,7 +342,9 @@ def time_form(bst, name, args, rmse):
 
     from paper_1810_11363_amd import cbhip as cb
     prec = PRECISIONS[name]
-    bst.set_precision(prec)
+    # every form on the headline form's plan (histogram subtraction on or
+    # off for all), so that the forms differ in their arithmetic only
+    bst.set_precision(prec, subtract=args.subtract)
     n, F, K, depth, stream = bst.n, bst.F, bst.K, bst.depth, bst.stream
     bst.init_gradients()
     t_tune = 0.0
@@ -362,6 +423,22 @@ def time_form(bst, name, args, rmse):
     bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec) for l in range(depth)])
     hist_s_per_tree = hist_ms.sum(axis=1).mean() / 1e3
     achieved = float(bytes_lvl.sum() / hist_s_per_tree / 1e9)
+    # rows each level's build accumulates (the smaller child only, where a
+    # level is built by subtraction), from the last tree's leaf sizes
+    counts = torch.bincount(bst.leaf.to(torch.int64), minlength=1 << depth).cpu().numpy()
+    rows_lvl = executed_rows(counts, depth, bst.subtract_levels())
+    lds_issue = None
+    if lds_ops_per_level(1, F, K, rmse, prec) is not None:
+        ops = {}
+        for r in rows_lvl:
+            for op, c in lds_ops_per_level(int(r), F, K, rmse, prec).items():
+                ops[op] = ops.get(op, 0) + c
+        floor = lds_floor_s(ops)
+        lds_issue = {"ops_per_tree": ops, "floor_ms_per_tree": round(floor * 1e3, 3),
+                     "measured_ms_per_tree": round(hist_s_per_tree * 1e3, 3),
+                     "frac": round(floor / hist_s_per_tree, 4),
+                     "rates_lane_ops_per_clk_per_cu": {k: LDS_RATE[k] for k in ops},
+                     "rates_source": "cbh_probe_lds_rates, this run"}
     snap = snapshot_tree(bst, args.warmup + args.steps + n_hist, np.random.default_rng(1)) \
         if not args.no_cpu else None
     print(f"# {name}: {sec_per_tree * 1e3:.3f} ms/tree, hist {hist_s_per_tree * 1e3:.3f} ms",
@@ -372,7 +449,8 @@ def time_form(bst, name, args, rmse):
         "G_row_features_per_s": round(rf_per_tree / sec_per_tree / 1e9, 3),
         "hist_G_row_features_per_s": round(rf_per_tree / hist_s_per_tree / 1e9, 3),
         "hist_ms_per_level": [round(float(x), 4) for x in hist_ms.mean(axis=0)],
-        "hist_subtraction": bool(bst.subtract) and not bst.use_part,
+        "hist_subtraction": bool(bst.subtract_levels()),
+        "rows_accumulated_per_level": [int(r) for r in rows_lvl],
         "rows_in_leaf_order": bool(bst.use_part),
         "graph_replay": not args.no_graph,
         "hist_timing": timing,
@@ -388,8 +466,27 @@ def time_form(bst, name, args, rmse):
                      "kernel": "cbh_build_histograms / cbh_apply_build_histograms_sub / "
                                "cbh_part_build_histograms (LDS histogram + partial merge)",
                      "algorithmic_bytes_per_launch": int(bytes_lvl.mean()),
-                     "avg_launch_ms": round(float(hist_ms.mean()), 5)},
+                     "avg_launch_ms": round(float(hist_ms.mean()), 5),
+                     "lds_issue": lds_issue},
     }
+
+
+def executed_rows(counts, depth, sub_levels):
+    """Rows accumulated by each level's build: all n, or at a level built by
+    subtraction the smaller child of every parent (by row count), from the
+    final leaf sizes `counts` [2^depth] (leaf bit l = level l's split)."""
+    import numpy as np
+    n = int(counts.sum())
+    out = []
+    for lvl in range(depth):
+        if lvl == 0 or not sub_levels:
+            out.append(n)
+            continue
+        L = 1 << lvl
+        size = np.bincount(np.arange(1 << depth) & (L - 1), weights=counts, minlength=L)
+        half = L // 2
+        out.append(int(np.minimum(size[:half], size[half:]).sum()))
+    return out
 
 
 def batch_vs_one_by_one(ctx, probs, hists, lvs, prec, lr, l2, side, timed):
@@ -800,82 +897,63 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
     return round(2 * (mib << 20) / sec / 1e9, 1)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=list(WORKLOADS), default="c2")
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=None,
-                    help="trees grown before the graphs are captured")
-    ap.add_argument("--warmup-s", type=float, default=None,
-                    help="seconds of replayed trees before the timed region")
-    ap.add_argument("--precision", choices=list(PRECISIONS), default="twofloat",
-                    help="headline histogram form")
-    ap.add_argument("--compare", default=None,
-                    help="other forms timed in the same run ('' for none)")
-    ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--batch-p", type=int, default=64, help="problems of the batching workload")
-    ap.add_argument("--batch-scale", type=float, default=1.0,
-                    help="row-count scale of the batching workload")
-    ap.add_argument("--c2-rows", type=int, default=1_000_000,
-                    help="rows of the cross-validation and permutation batches of the "
-                         "batching workload (0: leave them out)")
-    ap.add_argument("--cpu-rows", type=int, default=None)
-    ap.add_argument("--cpu-trees", type=int, default=None)
-    ap.add_argument("--no-graph", action="store_true",
-                    help="launch every call from Python instead of replaying captured trees")
-    ap.add_argument("--hist-trees", type=int, default=None,
-                    help="trees replayed from graphs with event nodes around every build")
-    ap.add_argument("--partition", choices=["auto", "on", "off"], default="auto",
-                    help="keep rows in leaf order during a tree (auto: for K > 1, and for depth >= 8 "
-                         "in the float forms)")
-    ap.add_argument("--no-cpu", action="store_true",
-                    help="skip the oracle leg (CPU timing and error vs FP64)")
-    ap.add_argument("--autotune", default=None,
-                    help="'run' tunes launch plans before each timed region, 'off' keeps "
-                         "the defaults, anything else is a cache file to load")
-    ap.add_argument("--autotune-save", default=None, metavar="PATH",
-                    help="with --autotune run: write the tuned plans of every form to PATH "
-                         "(JSON, loadable with --autotune PATH)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a device-to-device copy of MIB MiB five times (reference "
-                         "for hardware byte counters) and exit")
-    args = ap.parse_args()
-    wl = WORKLOADS[args.workload]
-    for k in ("steps", "n", "cpu_rows", "cpu_trees"):
-        if getattr(args, k) is None:
-            setattr(args, k, wl[k])
-    for k, v in RUN_DEFAULTS.items():
-        if getattr(args, k) is None:
-            setattr(args, k, wl.get(k, v))
-    if args.copy_calibration:
-        import torch
-        x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
-        y = torch.empty_like(x)
-        for _ in range(5):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 5}))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(sharding over several GPUs is not built)"}))
-        sys.exit(2)
-    if args.workload == "c4":
-        run_batch(args)
-        return
-    if args.workload == "apply":
-        run_apply(args)
-        return
-    if args.workload == "combine":
-        run_combine(args)
-        return
+def cpu_single_thread():
+    """The oracle at one thread: all trees of the 10^4-row Logloss workload,
+    and 3 trees of the 1M-row RMSE workload (full rows)."""
+    import numpy as np
 
+    import datagen
+    import oracle
+    from oracle import boost
+    out = {}
+    prev = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        for name, p, trees in (("c1_10k_logloss", datagen.make_c1(), None),
+                               ("c2_1m_rmse", datagen.make_c2(), 3)):
+            prep = boost.prepare(p)
+            B = max(int(prep.nb_num.max()), prep.nb_ts)
+            approx = np.zeros((p.K, p.n))
+            T = p.iterations if trees is None else trees
+            t0 = time.perf_counter()
+            for t in range(T):
+                bins, nb = prep.tree_features(t)
+                boost.fit_tree(bins, nb, approx, p.label, p.loss, p.K, p.depth, p.lr, p.l2, B)
+            dt = (time.perf_counter() - t0) / T
+            F = prep.tree_features(0)[0].shape[0]
+            out[name] = {"sec_per_tree": round(dt, 4), "trees": T, "rows": p.n,
+                         "G_row_features_per_s": round(p.n * F * p.depth / dt / 1e9, 5),
+                         "cores": 1}
+    finally:
+        oracle.set_threads(prev)
+    return out
+
+
+def resolve(args, workload):
+    """Arguments of one tree workload: the user's values where given, else the
+    workload's defaults."""
+    a = copy.copy(args)
+    a.workload = workload
+    wl = WORKLOADS[workload]
+    for k in ("steps", "n", "cpu_rows", "cpu_trees"):
+        if getattr(a, k) is None:
+            setattr(a, k, wl[k])
+    for k, v in RUN_DEFAULTS.items():
+        if getattr(a, k) is None:
+            setattr(a, k, wl.get(k, v))
+    return a
+
+
+def run_trees(args):
+    """One tree workload (c2, c3, c5): every form timed, the oracle leg; the
+    JSON object (not printed)."""
     import torch  # noqa: F401
 
     import datagen
     from paper_1810_11363_amd.booster import GpuBooster
 
+    rates = measure_lds_rates()
+    print(f"# LDS update rates (lane ops per clock per CU): {rates}", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     if args.workload == "c5":
         def progress(done, total):
@@ -885,13 +963,23 @@ def main():
     else:
         p = {"c2": datagen.make_c2, "c3": datagen.make_c3}[args.workload](n=args.n)
     t_gen = time.perf_counter() - t_gen
-    print(f"# generated workload in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    print(f"# generated {args.workload} in {t_gen:.1f}s", file=sys.stderr, flush=True)
     part = {"auto": None, "on": True, "off": False}[args.partition]
     bst = GpuBooster.from_problem(p, partition=part).prepare()
     print(f"# prepared: {bst.timings}", file=sys.stderr, flush=True)
     rmse = p.loss == datagen.RMSE
-    forms = [args.precision] + [f for f in args.compare.split(",") if f and f != args.precision]
-    results = {f: time_form(bst, f, args, rmse) for f in forms}
+    forms = [args.precision] + [f for f in args.compare.split(",")
+                                if f and f not in (args.precision, "none")]
+    results = {}
+    for f in forms:
+        a = args
+        if f != args.precision and args.compare_steps:
+            # the comparison forms: fewer trees (the float32 compare-and-swap
+            # forms take seconds per tree on this workload)
+            a = copy.copy(args)
+            a.steps, a.warmup, a.hist_trees = args.compare_steps, 1, 1
+        results[f] = time_form(bst, f, a, rmse)
+        results[f]["timed_trees"] = a.steps
     head = results[args.precision]
     n, F, depth = bst.n, bst.F, bst.depth
     out = {
@@ -911,12 +999,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(args.workload, p, bst),
                    "precision": args.precision, "features_per_tree": F, "bins": bst.B,
-                   "rows": n},
+                   "rows": n, "classes": bst.K, "depth": depth},
         "roofline": dict(head["roofline"], copy_gbs=copy_bandwidth()),
         "forms": results,
         "vs_plain_fp32": (round(results["fp32"]["sec_per_tree"] / head["sec_per_tree"], 3)
                           if "fp32" in results else None),
         "preprocess_s": {k: round(v, 4) for k, v in bst.timings.items() if v is not None},
+        "lds_rates_lane_ops_per_clk_per_cu": rates,
     }
     bst.close()
     # the oracle leg: FP64 error of every form's sampled histograms, then the
@@ -929,7 +1018,94 @@ def main():
                 r["max_g_err_over_quant_bound"] = q
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(copy.copy(p), args.cpu_rows, args.cpu_trees)
+        out["cpu_baseline"] = dict(cpu_baseline(copy.copy(p), args.cpu_rows, args.cpu_trees),
+                                   **cpu_info())
+    del p
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["headline"] + list(WORKLOADS), default="headline")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="trees grown before the graphs are captured")
+    ap.add_argument("--warmup-s", type=float, default=None,
+                    help="seconds of replayed trees before the timed region")
+    ap.add_argument("--precision", choices=list(PRECISIONS), default="f64",
+                    help="headline histogram form")
+    ap.add_argument("--compare", default=None,
+                    help="other forms timed in the same run ('' for none)")
+    ap.add_argument("--compare-steps", type=int, default=None,
+                    help="timed trees of the comparison forms (default: the workload's)")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--batch-p", type=int, default=64, help="problems of the batching workload")
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="row-count scale of the batching workload")
+    ap.add_argument("--c2-rows", type=int, default=1_000_000,
+                    help="rows of the cross-validation and permutation batches of the "
+                         "batching workload (0: leave them out)")
+    ap.add_argument("--cpu-rows", type=int, default=None)
+    ap.add_argument("--cpu-trees", type=int, default=None)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every call from Python instead of replaying captured trees")
+    ap.add_argument("--hist-trees", type=int, default=None,
+                    help="trees replayed from graphs with event nodes around every build")
+    ap.add_argument("--partition", choices=["auto", "on", "off"], default="auto",
+                    help="keep rows in leaf order during a tree (auto: for K > 1, and for depth >= 8 "
+                         "in the float forms)")
+    ap.add_argument("--subtract", choices=["on", "off", "auto"], default="on",
+                    help="histogram subtraction at levels >= 1 for every form (auto: the "
+                         "form's default, off for plain float32)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU timing and error vs FP64)")
+    ap.add_argument("--autotune", default=None,
+                    help="'run' tunes launch plans before each timed region, 'off' keeps "
+                         "the defaults, anything else is a cache file to load")
+    ap.add_argument("--autotune-save", default=None, metavar="PATH",
+                    help="with --autotune run: write the tuned plans of every form to PATH "
+                         "(JSON, loadable with --autotune PATH)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB five times (reference "
+                         "for hardware byte counters) and exit")
+    args = ap.parse_args()
+    args.subtract = {"on": True, "off": False, "auto": None}[args.subtract]
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 5}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(sharding over several GPUs is not built)"}))
+        sys.exit(2)
+    if args.workload in ("c4", "apply", "combine"):
+        a = resolve(args, args.workload)
+        {"c4": run_batch, "apply": run_apply, "combine": run_combine}[args.workload](a)
+        return
+    if args.workload != "headline":
+        print(json.dumps(run_trees(resolve(args, args.workload))), flush=True)
+        return
+    # headline: the 50M-row MultiClass workload (the largest), then the
+    # 1M-row RMSE workload with its own defaults, in one JSON line
+    out = run_trees(resolve(args, "c5"))
+    c2_args = copy.copy(args)
+    for k in ("steps", "warmup", "n", "cpu_rows", "cpu_trees", "compare_steps", "hist_trees",
+              "warmup_s", "autotune", "compare"):
+        setattr(c2_args, k, None)
+    c2 = run_trees(resolve(c2_args, "c2"))
+    keep = ("value", "unit", "steps", "warmup", "ms_per_step", "sec_per_tree",
+            "hist_G_row_features_per_s", "dtype", "config", "roofline", "forms", "vs_plain_fp32",
+            "preprocess_s", "cpu_baseline")
+    out["c2"] = {k: c2[k] for k in keep if k in c2}
+    if not args.no_cpu:
+        print("# oracle at one thread ...", file=sys.stderr, flush=True)
+        out["cpu_single_thread"] = cpu_single_thread()
     print(json.dumps(out), flush=True)
 
 

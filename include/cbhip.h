@@ -203,6 +203,18 @@ int cbh_sync(cbh_ctx* ctx, void* stream);
 int cbh_device_timestamp(cbh_ctx* ctx, uint64_t* slot, void* stream);
 int cbh_device_clock_khz(cbh_ctx* ctx, int64_t* khz);
 
+/* Instrumentation (not part of the method): issue rates of the LDS updates
+ * the histogram forms use, in lane updates per clock per CU at the device's
+ * peak shader clock, with the 64 lanes of every wave on distinct banks (16
+ * waves per CU, four 1024-thread blocks per CU launched):
+ *   rates_out[0] ds_add_u32   [1] ds_add_f32   [2] ds_add_f64   [3] ds_add_u64
+ *   [4] float32 add by 32-bit compare-and-swap (the FP32 form's g cell)
+ *   [5] (float, float) pair add by 64-bit compare-and-swap (FP32 (g, h) cell,
+ *       TWOFLOAT (hi, lo) cell)
+ *   rates_out  host double [6]
+ * Runs on the default stream and synchronizes the device. */
+int cbh_probe_lds_rates(cbh_ctx* ctx, double* rates_out);
+
 /* ---- preprocessing -------------------------------------------------------- */
 
 /* Borders of one numeric feature (host computation; Sec. 5: a fixed number of
@@ -491,6 +503,22 @@ int cbh_part_split(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_
  * context workspace for partial tiles. */
 int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
                               int32_t level, int32_t precision, void* hist_out, void* stream);
+
+/* The same level by subtraction (not described in the paper): with the rows
+ * in leaf order every child is one contiguous range, so for every parent p
+ * of the previous level only its child with fewer rows (leaf p or
+ * p + 2^(level-1)) is accumulated, and the other child is written as the
+ * parent's histogram minus it: exactly for CBH_PREC_INT16 sums and RMSE
+ * counts, as a two-float difference for CBH_PREC_TWOFLOAT and CBH_PREC_F64
+ * (error about 2^-44 of the parent's sums), as a float difference for
+ * CBH_PREC_FP32 (the parent's float rounding can then dominate a small
+ * sibling bin). Reads about half the rows of a direct build.
+ *   parent_hist  the level-1 histograms (either build call, same
+ *                precision); must not be hist_out
+ * Otherwise as cbh_part_build_histograms. */
+int cbh_part_build_histograms_sub(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
+                                  int32_t level, int32_t precision, const void* parent_hist,
+                                  void* hist_out, void* stream);
 
 /* ---- batched, fused levels ------------------------------------------------- */
 

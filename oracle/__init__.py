@@ -52,6 +52,7 @@ def _declare(L):
     L.orc_histogram_int.argtypes = [i64, i32, vp, i32, i32, vp, vp, vp, i32, vp]
     L.orc_apply_model.argtypes = [i64, i32, vp, i32, i32, i32, vp, vp, vp, dbl, vp]
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [i32]
 
 
 def _c(a, dtype):
@@ -60,6 +61,11 @@ def _c(a, dtype):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's parallel loops (its results do not depend on it)."""
+    lib().orc_set_threads(int(t))
 
 
 def select_borders(x, max_bins: int) -> np.ndarray:

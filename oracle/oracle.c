@@ -416,3 +416,14 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads for the parallel loops from now on (timing the oracle at a chosen
+ * core count; results do not depend on it). */
+void orc_set_threads(int32_t t) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}

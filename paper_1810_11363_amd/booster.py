@@ -287,13 +287,21 @@ class GpuBooster:
         cb.cbh_update_approx(self.ctx, self.probs[0], None, self.precision, None, 0.0, 0.0,
                              stream=self.stream)
 
+    def subtract_levels(self) -> bool:
+        """True when levels >= 1 accumulate only the smaller child of every
+        parent (the other child is the parent minus it)."""
+        return bool(self.subtract)
+
     def hist_ptr(self, level: int) -> int:
         """Level `level` writes buffer level % 2 (its parent is the other one)."""
         return self.hists[level % 2].data_ptr()
 
     def build_level_histograms(self, pr, level: int):
         ctx, st, prec = self.ctx, self.stream, self.precision
-        if level > 0 and self.use_part:
+        if level > 0 and self.use_part and self.subtract:
+            cb.cbh_part_build_histograms_sub(ctx, self.part, pr, level, prec,
+                                             self.hist_ptr(level - 1), self.hist_ptr(level), st)
+        elif level > 0 and self.use_part:
             cb.cbh_part_build_histograms(ctx, self.part, pr, level, prec, self.hist_ptr(level), st)
         elif level > 0 and self.subtract:
             cb.cbh_build_histograms_sub(ctx, pr, level, prec, self.hist_ptr(level - 1),

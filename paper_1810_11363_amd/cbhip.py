@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "CBH_OK", -1: "CBH_EINVAL", -2: "CBH_ENOMEM", -3: "CBH_EDEVIC
 # Every symbol include/cbhip.h declares.
 EXPORTS = [
     "cbh_create", "cbh_destroy", "cbh_last_error", "cbh_set_workspace_limit",
-    "cbh_workspace_size", "cbh_reserve_workspace", "cbh_sync", "cbh_device_timestamp", "cbh_device_clock_khz",
+    "cbh_workspace_size", "cbh_reserve_workspace", "cbh_sync", "cbh_probe_lds_rates",
+    "cbh_device_timestamp", "cbh_device_clock_khz",
     "cbh_select_borders", "cbh_uniform_borders",
     "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
@@ -37,6 +38,7 @@ EXPORTS = [
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
+    "cbh_part_build_histograms_sub",
     "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts",
 ]
 
@@ -79,6 +81,7 @@ def _load():
         "cbh_sync": ([vp, vp], C.c_int),
         "cbh_device_timestamp": ([vp, vp, vp], C.c_int),
         "cbh_device_clock_khz": ([vp, C.POINTER(i64)], C.c_int),
+        "cbh_probe_lds_rates": ([vp, C.POINTER(dbl)], C.c_int),
         "cbh_select_borders": ([vp, i64, i32, vp, C.POINTER(i32)], C.c_int),
         "cbh_uniform_borders": ([dbl, dbl, i32, vp], C.c_int),
         "cbh_quantize": ([vp, vp, i64, vp, i32, vp, vp], C.c_int),
@@ -116,6 +119,8 @@ def _load():
         "cbh_part_split": ([vp, vp, C.POINTER(cbh_problem), i32, i32, vp, vp], C.c_int),
         "cbh_part_build_histograms": ([vp, vp, C.POINTER(cbh_problem), i32, i32, vp, vp],
                                       C.c_int),
+        "cbh_part_build_histograms_sub": ([vp, vp, C.POINTER(cbh_problem), i32, i32, vp, vp,
+                                           vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -223,6 +228,17 @@ def cbh_device_clock_khz(ctx) -> int:
     return v.value
 
 
+LDS_RATE_NAMES = ("ds_add_u32", "ds_add_f32", "ds_add_f64", "ds_add_u64", "cas32_f32",
+                  "cas64_pair")
+
+
+def cbh_probe_lds_rates(ctx) -> dict:
+    """Measured LDS update rates (lane updates per clock per CU), by name."""
+    r = (C.c_double * 6)()
+    _check(_lib.cbh_probe_lds_rates(ctx, r))
+    return dict(zip(LDS_RATE_NAMES, (float(v) for v in r)))
+
+
 def cbh_tile_bins(ctx, cols, n_cols: int, n: int, out, stream=None):
     """cols: device int64 tensor (or address) of n_cols column pointers."""
     return _check(_lib.cbh_tile_bins(ctx, _ptr(cols), n_cols, n, _ptr(out), _stream(stream)))
@@ -270,6 +286,13 @@ def cbh_part_build_histograms(ctx, part, prob: cbh_problem, level: int, precisio
                               hist_out, stream=None):
     return _check(_lib.cbh_part_build_histograms(ctx, part, C.byref(prob), level, precision,
                                                  _ptr(hist_out), _stream(stream)))
+
+
+def cbh_part_build_histograms_sub(ctx, part, prob: cbh_problem, level: int, precision: int,
+                                  parent_hist, hist_out, stream=None):
+    return _check(_lib.cbh_part_build_histograms_sub(ctx, part, C.byref(prob), level, precision,
+                                                     _ptr(parent_hist), _ptr(hist_out),
+                                                     _stream(stream)))
 
 
 def cbh_build_histograms_sub(ctx, prob: cbh_problem, level: int, precision: int, parent_hist,

@@ -56,6 +56,7 @@ struct cbh_part {
     uint32_t* zl = nullptr;                     // [2^(depth-2)] rows of each leaf with bit 0
     int64_t* blk = nullptr;                     // [n_pb + 1] zeros per block, then their prefix
     int64_t* cp = nullptr;                      // [2^(depth-1) + 1] chunk prefix of slot tiles
+    int32_t* tleaf = nullptr;                   // [2^(depth-1)] child a subtraction build accumulates
 };
 
 namespace cbh {
@@ -366,18 +367,34 @@ __global__ __launch_bounds__(256) void part_leaf_kernel(const uint8_t* const* __
 // Chunks of every slot tile: tile t holds leaves [t lt, min((t+1) lt, L)),
 // i.e. positions [off[t lt], off[...]) and the 16-row segments over them;
 // cp = exclusive prefix of ceil(segments / segs_per_chunk), total at [n_tiles].
+// With tleaf (a build by subtraction: lt = 1, n_tiles = L / 2 parents), tile
+// t is parent t and holds only its child with fewer rows, leaf t or t + L / 2
+// (the lower one on a tie), whose leaf index goes to tleaf[t].
 __global__ __launch_bounds__(1024) void part_tiles_kernel(const int64_t* __restrict__ off,
                                                           int32_t L, int32_t lt, int32_t n_tiles,
                                                           int64_t segs_per_chunk,
-                                                          int64_t* __restrict__ cp) {
+                                                          int64_t* __restrict__ cp,
+                                                          int32_t* __restrict__ tleaf) {
     __shared__ int64_t sh[1024];
+    auto first_leaf = [&](int64_t t) -> int64_t {
+        if (!tleaf) return t * lt;
+        const int64_t hi = t + n_tiles;
+        return off[hi + 1] - off[hi] < off[t + 1] - off[t] ? hi : t;
+    };
     auto chunks = [&](int64_t t) -> int64_t {
-        const int64_t a = off[t * lt], b = off[min((t + 1) * int64_t(lt), int64_t(L))];
+        const int64_t v = first_leaf(t);
+        const int64_t a = off[v];
+        const int64_t b = tleaf ? off[v + 1] : off[min((t + 1) * int64_t(lt), int64_t(L))];
         if (a >= b) return 0;
         return (((b + 15) >> 4) - (a >> 4) + segs_per_chunk - 1) / segs_per_chunk;
     };
-    const int64_t tot =
-        block_scan_1024(n_tiles, chunks, [&](int64_t t, int64_t e) { cp[t] = e; }, sh);
+    const int64_t tot = block_scan_1024(
+        n_tiles, chunks,
+        [&](int64_t t, int64_t e) {
+            cp[t] = e;
+            if (tleaf) tleaf[t] = (int32_t)first_leaf(t);
+        },
+        sh);
     if (threadIdx.x == 0) cp[n_tiles] = tot;
 }
 
@@ -390,6 +407,7 @@ struct PartHist {
     const uint16_t* code;
     const int64_t* off;
     const int64_t* cp;
+    const int32_t* tleaf;          // subtraction: the leaf tile t (a parent) accumulates, or NULL
     uint32_t* partials;            // [chunk][lt][F][B][wpc]
     int64_t n_pad, n_items, segs_per_chunk;
     int32_t F, B, K, L, lt, n_tiles, n_fgroups, wpc;
@@ -421,8 +439,8 @@ __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
     }
     const int t = lo;
     const int64_t j = gc - a.cp[t];
-    const uint32_t s0 = (uint32_t)t * (uint32_t)a.lt;
-    const uint32_t ns = min((uint32_t)a.lt, (uint32_t)a.L - s0);
+    const uint32_t s0 = a.tleaf ? (uint32_t)a.tleaf[t] : (uint32_t)t * (uint32_t)a.lt;
+    const uint32_t ns = a.tleaf ? 1u : min((uint32_t)a.lt, (uint32_t)a.L - s0);
     const int64_t pa = a.off[s0], pb = a.off[s0 + ns];
     const int64_t sa = (pa >> 4) + j * a.segs_per_chunk;
     const int64_t sb = min((pb + 15) >> 4, sa + a.segs_per_chunk);
@@ -462,12 +480,26 @@ __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
 // unit's slot tile's chunks, in chunk order, with the arithmetic of the other
 // merges (two-float: TwoSum of the (hi, lo) parts). One thread per unit, so
 // consecutive threads read the consecutive classes' words of a cell.
+// Subtraction (tleaf != NULL; lt = 1, L = the number of parents): unit cell
+// (p, f, b) sums parent p's tile, which is leaf tleaf[p]; the sibling leaf
+// gets parent - sum (a two-float difference, exact for int16 sums and counts,
+// a float difference for FP32).
+__device__ __forceinline__ float2 f2_sub_pair(float2 P, float2 r) {
+    const float t = P.x - r.x;
+    const float bp = t - P.x;
+    const float e = ((P.x - (t - bp)) + (-r.x - bp)) + (P.y - r.y);
+    const float dh = t + e;
+    return make_float2(dh, e - (dh - t));
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restrict__ part,
                                                          const int64_t* __restrict__ cp,
                                                          int32_t L, int32_t lt, int32_t F,
                                                          int32_t B, int32_t K, int32_t wpc,
-                                                         int32_t rmse, void* __restrict__ out) {
+                                                         int32_t rmse, void* __restrict__ out,
+                                                         const int32_t* __restrict__ tleaf,
+                                                         const void* __restrict__ parent) {
     const int64_t fb = int64_t(F) * B, cells_lt = int64_t(lt) * fb;
     const int64_t units = int64_t(L) * fb * K;
     const int64_t cw = cells_lt * wpc;                  // words per chunk partial
@@ -480,6 +512,13 @@ __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restr
         const int64_t g0 = cp[t];
         const int nch = (int)(cp[t + 1] - g0);
         const uint32_t* p = part + g0 * cw + ((v - t * lt) * fb + rest) * wpc;
+        // where the sum goes, and (subtraction) the sibling's cell
+        int64_t dst = cell, sib = -1;
+        if (tleaf) {
+            const int64_t leaf = tleaf[v];
+            dst = leaf * fb + rest;
+            sib = (leaf == v ? v + L : v) * fb + rest;
+        }
         if constexpr (PREC == CBH_PREC_FP32) {
             float g = 0.f, hh = 0.f;
             uint32_t cnt = 0;
@@ -488,9 +527,19 @@ __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restr
                 g += __uint_as_float(w.x);
                 if (rmse) cnt += w.y; else hh += __uint_as_float(w.y);
             }
-            reinterpret_cast<float*>(out)[cell * 2 * K + 2 * c] = g;
-            if (rmse) reinterpret_cast<uint32_t*>(out)[cell * 2 * K + 2 * c + 1] = cnt;
-            else reinterpret_cast<float*>(out)[cell * 2 * K + 2 * c + 1] = hh;
+            float* of = reinterpret_cast<float*>(out);
+            uint32_t* ou = reinterpret_cast<uint32_t*>(out);
+            of[dst * 2 * K + 2 * c] = g;
+            if (rmse) ou[dst * 2 * K + 2 * c + 1] = cnt;
+            else of[dst * 2 * K + 2 * c + 1] = hh;
+            if (sib >= 0) {
+                const float* pf = reinterpret_cast<const float*>(parent);
+                const uint32_t* pu = reinterpret_cast<const uint32_t*>(parent);
+                const int64_t e = cell * 2 * K + 2 * c;
+                of[sib * 2 * K + 2 * c] = pf[e] - g;
+                if (rmse) ou[sib * 2 * K + 2 * c + 1] = pu[e + 1] - cnt;
+                else of[sib * 2 * K + 2 * c + 1] = pf[e + 1] - hh;
+            }
         } else if constexpr (PREC == CBH_PREC_TWOFLOAT) {
             float S[2] = {0.f, 0.f}, E[2] = {0.f, 0.f};
             uint32_t cnt = 0;
@@ -519,9 +568,16 @@ __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restr
                 r[st] = make_float2(hs, E[st] - (hs - S[st]));
             }
             if (rmse) r[1] = make_float2(__uint_as_float(cnt), 0.f);
-            float2* o = reinterpret_cast<float2*>(out) + cell * 2 * K + 2 * c;
+            float2* o = reinterpret_cast<float2*>(out) + dst * 2 * K + 2 * c;
             o[0] = r[0];
             o[1] = r[1];
+            if (sib >= 0) {
+                const float2* P = reinterpret_cast<const float2*>(parent) + cell * 2 * K + 2 * c;
+                float2* os = reinterpret_cast<float2*>(out) + sib * 2 * K + 2 * c;
+                os[0] = f2_sub_pair(P[0], r[0]);
+                os[1] = rmse ? make_float2(__uint_as_float(__float_as_uint(P[1].x) - cnt), 0.f)
+                             : f2_sub_pair(P[1], r[1]);
+            }
         } else {
             int64_t gs = 0, hs = 0;
             for (int ch = 0; ch < nch; ++ch) {
@@ -529,9 +585,15 @@ __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restr
                 hs += (int64_t)(uint32_t)(w & 0xffffffffull);
                 gs += (int64_t)(int32_t)(uint32_t)(w >> 32);
             }
-            int64_t* o = reinterpret_cast<int64_t*>(out) + 2 * (cell * K + c);
+            int64_t* o = reinterpret_cast<int64_t*>(out) + 2 * (dst * K + c);
             o[0] = gs;
             o[1] = hs;
+            if (sib >= 0) {
+                const int64_t* P = reinterpret_cast<const int64_t*>(parent) + 2 * (cell * K + c);
+                int64_t* os = reinterpret_cast<int64_t*>(out) + 2 * (sib * K + c);
+                os[0] = P[0] - gs;
+                os[1] = P[1] - hs;
+            }
         }
     }
 }
@@ -587,8 +649,10 @@ static void launch_part_hist(const PartHist& a, int W, unsigned grid, size_t lds
 // one, at most 64; one slot lets the block skip the row codes inside its
 // range), and chunks of at least min_rows rows sized so that the blocks of
 // the whole level reach target_blocks (8 times that with several classes).
+// A build by subtraction (sub) takes one parent per tile and reads about half
+// the rows, which the chunk sizing assumes.
 static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, int32_t K,
-                          int32_t L, int32_t precision, int max_lds) {
+                          int32_t L, int32_t precision, int max_lds, bool sub = false) {
     HistPlan p;
     p.kind = 1;
     p.words_per_cell = words_per_cell(precision, K);
@@ -598,8 +662,11 @@ static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, 
     p.fb = W;
     const int64_t slot_bytes = int64_t(B) * lpf_record_bytes(W, cs);
     const int64_t budget = std::min<int64_t>(kn.lds_budget, max_lds);
-    p.lt = (int32_t)std::max<int64_t>(1, std::min<int64_t>({int64_t(L), 64, budget / slot_bytes}));
-    p.n_ltiles = (L + p.lt - 1) / p.lt;
+    p.lt = sub ? 1
+               : (int32_t)std::max<int64_t>(
+                     1, std::min<int64_t>({int64_t(L), 64, budget / slot_bytes}));
+    p.n_ltiles = sub ? L / 2 : (L + p.lt - 1) / p.lt;
+    if (sub) n = std::max<int64_t>(1, n / 2);
     p.n_fgroups = (F + W - 1) / W;
     const int64_t per_chunk = int64_t(p.n_fgroups) * K;     // blocks per chunk of rows
     // the K class blocks of one (chunk, feature group) read the same bins,
@@ -621,7 +688,7 @@ static void free_part(cbh_part* p) {
     void* bufs[] = {p->bins[0], p->bins[1], p->cols[0], p->cols[1], p->seg,   p->g[0],
                     p->g[1],    p->h[0],    p->h[1],    p->gq[0],   p->gq[1], p->order[0],
                     p->order[1], p->code[0], p->code[1], p->off[0], p->off[1], p->zl,
-                    p->blk,     p->cp};
+                    p->blk,     p->cp,      p->tleaf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -675,7 +742,8 @@ int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out) {
         if (ok && p->loss != CBH_LOSS_RMSE) ok = alloc((void**)&p->h[b], K * np * 4);
     }
     ok = ok && alloc((void**)&p->seg, F * 8) && alloc((void**)&p->zl, half * 4) &&
-         alloc((void**)&p->blk, (p->n_pb + 1) * 8) && alloc((void**)&p->cp, (half + 1) * 8);
+         alloc((void**)&p->blk, (p->n_pb + 1) * 8) && alloc((void**)&p->cp, (half + 1) * 8) &&
+         alloc((void**)&p->tleaf, half * 4);
     if (!ok) {
         free_part(p);
         delete p;
@@ -780,8 +848,9 @@ int cbh_part_split(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_
     return CBH_OK;
 }
 
-int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
-                              int32_t level, int32_t precision, void* hist_out, void* stream) {
+static int part_build(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_t level,
+                      int32_t precision, const void* parent_hist, void* hist_out,
+                      void* stream) {
     clear_error();
     CBH_ARG(ctx != nullptr && hist_out != nullptr, "NULL argument");
     int rc = validate_problem(prob);
@@ -791,13 +860,15 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     rc = check_part(part, prob);
     if (rc) return rc;
     CBH_ARG(level >= 1 && level < prob->depth, "level %d outside [1, depth)", level);
+    const bool sub = parent_hist != nullptr;
+    CBH_ARG(parent_hist != hist_out, "parent_hist must not be hist_out");
     hipStream_t s = (hipStream_t)stream;
     const int src = (level + 1) & 1;   // written by the split of level - 1
     const int L = 1 << level;
     const int F = part->F, B = prob->max_bins, K = part->K;
     const int rmse = prob->loss == CBH_LOSS_RMSE;
-    const HistKnobs kn = knobs_for(ctx, F, B, K, level, precision, prob->n, 2);
-    const HistPlan plan = plan_part(kn, prob->n, F, B, K, L, precision, ctx->max_lds);
+    const HistKnobs kn = knobs_for(ctx, F, B, K, level, precision, prob->n, sub ? 3 : 2);
+    const HistPlan plan = plan_part(kn, prob->n, F, B, K, L, precision, ctx->max_lds, sub);
     const int64_t spc = std::max<int64_t>(1, plan.rows_per_chunk / 16);
     const int64_t n_tiles = plan.n_ltiles;
     const int64_t max_chunks = (part->n_pad / 16 + n_tiles + spc - 1) / spc + n_tiles + 1;
@@ -805,7 +876,7 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     rc = ensure_ws(ctx, max_chunks * cell_words * 4, stream);
     if (rc) return rc;
     part_tiles_kernel<<<1, 1024, 0, s>>>(part->off[src], L, plan.lt, (int32_t)n_tiles, spc,
-                                          part->cp);
+                                          part->cp, sub ? part->tleaf : nullptr);
     CBH_LAUNCHED();
     PartHist a;
     const bool q = precision == CBH_PREC_INT16;
@@ -817,6 +888,7 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
     a.code = part->code[src];
     a.off = part->off[src];
     a.cp = part->cp;
+    a.tleaf = sub ? part->tleaf : nullptr;
     a.partials = (uint32_t*)ctx->ws;
     a.n_pad = part->n_pad;
     a.n_items = max_chunks * plan.n_fgroups * K;
@@ -849,28 +921,47 @@ int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* p
             break;
     }
     CBH_LAUNCHED();
-    const int64_t units = int64_t(L) * F * B * K;
+    // merge units: every leaf, or (subtraction) every parent, which writes both children
+    const int Lm = sub ? L / 2 : L;
+    const int64_t units = int64_t(Lm) * F * B * K;
     const unsigned mg =
         (unsigned)std::min<int64_t>((units + 255) / 256, int64_t(ctx->num_cus) * 16);
+    const int32_t* tl = sub ? part->tleaf : nullptr;
     switch (out_prec(precision)) {
         case CBH_PREC_FP32:
             part_merge_kernel<CBH_PREC_FP32><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
-                rmse, hist_out);
+                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out, tl, parent_hist);
             break;
         case CBH_PREC_TWOFLOAT:
             part_merge_kernel<CBH_PREC_TWOFLOAT><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
-                rmse, hist_out);
+                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out, tl, parent_hist);
             break;
         default:
             part_merge_kernel<CBH_PREC_INT16><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, L, plan.lt, F, B, K, plan.words_per_cell,
-                rmse, hist_out);
+                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                rmse, hist_out, tl, parent_hist);
             break;
     }
     CBH_LAUNCHED();
     return CBH_OK;
+}
+
+int cbh_part_build_histograms(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
+                              int32_t level, int32_t precision, void* hist_out, void* stream) {
+    return part_build(ctx, part, prob, level, precision, nullptr, hist_out, stream);
+}
+
+int cbh_part_build_histograms_sub(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob,
+                                  int32_t level, int32_t precision, const void* parent_hist,
+                                  void* hist_out, void* stream) {
+    if (!parent_hist) {
+        clear_error();
+        set_error("parent_hist is NULL");
+        return CBH_EINVAL;
+    }
+    return part_build(ctx, part, prob, level, precision, parent_hist, hist_out, stream);
 }
 
 }  // extern "C"

@@ -87,7 +87,7 @@ def _lockstep_tree(cb, bst, t, stats):
             want = oracle.histogram(bins, gd, hd, leaf, L, B)
             mag = oracle.histogram(bins, np.abs(gd), np.abs(hd), leaf, L, B)
             slack = None
-            if lvl >= 1 and bst.subtract and not bst.use_part:
+            if lvl >= 1 and bst.subtract_levels():
                 root = oracle.histogram(bins, np.abs(gd), np.abs(hd), np.zeros(n, np.uint16), 1, B)
                 slack = gu.sub_slack(prec, root)
             e = gu.normalized_err(got, want, mag, slack)
@@ -701,7 +701,12 @@ def _sampled_tree_check(cb, bst, prec, n_feat, rng):
             want = oracle.histogram(bins[fs], g64, h64, leaf, L, bst.B)
             mag = oracle.histogram(bins[fs], np.abs(g64), h64, leaf, L, bst.B)
             tol = gu.FP32_TOL if prec == 0 else gu.TWOFLOAT_TOL
-            assert gu.normalized_err(got[:, fs], want, mag) <= tol, lvl
+            slack = None
+            if lvl >= 1 and bst.subtract_levels():
+                root = oracle.histogram(bins[fs], np.abs(g64), h64, np.zeros(n, np.uint16), 1,
+                                        bst.B)
+                slack = gu.sub_slack(prec, root)
+            assert gu.normalized_err(got[:, fs], want, mag, slack) <= tol, lvl
         # every feature's h totals per (leaf, class) agree (unsampled features too)
         tot = got[..., 1::2].sum(axis=2)                    # [L][F][K]
         scale = np.abs(tot).max() + 1e-30
