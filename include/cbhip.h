@@ -401,6 +401,22 @@ int cbh_score_splits(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
                      const void* hist, int32_t precision, double l2,
                      cbh_split* best_out, float* scores_out, void* stream);
 
+/* cbh_score_splits for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results, bit for bit, with the per-feature winners and
+ * the last-block counter kept in a static device array of the library
+ * (1 MB per GPU, held until the process ends) instead of the context's
+ * workspace, which this call never touches or grows. The call allocates
+ * nothing and issues no memset: the counter is cleared once by cbh_create and
+ * reset by every launch's last block.
+ *   n_features  at most 65536 (else CBH_EINVAL, nothing enqueued)
+ * Every call on a GPU, from any context, shares that GPU's array: calls that
+ * overlap on one GPU (concurrent streams) race and must not be issued.
+ * Otherwise as cbh_score_splits. */
+int cbh_score_splits_noalloc(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                             const void* hist, int32_t precision, double l2,
+                             cbh_split* best_out, float* scores_out, void* stream);
+
 /* Apply the chosen split: leaf[i] |= (bins[f][i] > k) << level for the split
  * read from device memory (Sec. 4); at level 0, leaf[i] = (bins[f][i] > k).
  * If best->feature < 0 the bit stays clear for every row. */

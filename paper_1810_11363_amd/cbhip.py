@@ -33,7 +33,7 @@ EXPORTS = [
     "cbh_quantize", "cbh_tile_bins",
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
     "cbh_build_histograms_sub", "cbh_apply_build_histograms_sub",
-    "cbh_score_splits", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
+    "cbh_score_splits", "cbh_score_splits_noalloc", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
     "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
@@ -96,6 +96,8 @@ def _load():
                                             vp], C.c_int),
         "cbh_score_splits": ([vp, C.POINTER(cbh_problem), i32, vp, i32, dbl, vp, vp, vp],
                              C.c_int),
+        "cbh_score_splits_noalloc": ([vp, C.POINTER(cbh_problem), i32, vp, i32, dbl, vp, vp,
+                                      vp], C.c_int),
         "cbh_apply_split": ([vp, C.POINTER(cbh_problem), i32, vp, vp], C.c_int),
         "cbh_update_approx": ([vp, C.POINTER(cbh_problem), vp, i32, vp, dbl, dbl, vp, vp, vp],
                               C.c_int),
@@ -314,6 +316,13 @@ def cbh_score_splits(ctx, prob: cbh_problem, level: int, hist, precision: int, l
     return _check(_lib.cbh_score_splits(ctx, C.byref(prob), level, _ptr(hist), precision,
                                         float(l2), _ptr(best_out), _ptr(scores_out),
                                         _stream(stream)))
+
+
+def cbh_score_splits_noalloc(ctx, prob: cbh_problem, level: int, hist, precision: int, l2: float,
+                             best_out, scores_out=None, stream=None):
+    return _check(_lib.cbh_score_splits_noalloc(ctx, C.byref(prob), level, _ptr(hist),
+                                                precision, float(l2), _ptr(best_out),
+                                                _ptr(scores_out), _stream(stream)))
 
 
 def cbh_apply_split(ctx, prob: cbh_problem, level: int, best, stream=None):

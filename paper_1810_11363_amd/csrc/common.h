@@ -104,6 +104,7 @@ struct cbh_ctx {
     std::vector<void*> ws_retired;
     int64_t ws_limit = int64_t(64) << 30;
     uint32_t* d_flags = nullptr;  // [0] device error flags, [1] score blocks done (self-resetting)
+    void* score_static = nullptr; // device address of the static score scratch on this device
     cbh::HistKnobs knobs;
     std::map<cbh::TuneKey, cbh::HistKnobs> tuned;
     std::map<cbh::TuneKey, std::string> tuned_note;   // chosen plan and its time, for the cache file
@@ -152,9 +153,13 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
                 uint16_t* codes = nullptr, const cbh_split* parent_split = nullptr,
                 bool apply_parent = false);
 int64_t hist_code_bytes(const HistPlan& plan, int64_t n, bool sub);
+// counter: the self-resetting last-block counter (NULL: the context's)
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores,
-                 void* scratch, hipStream_t s);
+                 void* scratch, hipStream_t s, uint32_t* counter = nullptr);
+// Device address of score.hip's static scratch on the context's device (at
+// cbh_create, with that device current).
+int score_static_init(cbh_ctx* ctx);
 int64_t score_scratch_bytes(const cbh_problem* p);
 
 // Allow the dynamic-LDS kernels the device's full LDS (called by cbh_create).

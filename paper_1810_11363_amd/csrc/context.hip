@@ -138,6 +138,12 @@ int cbh_create(int device, cbh_ctx** out) {
     hist_init_attrs(c->max_lds);
     batch_init_attrs(c->max_lds);
     part_init_attrs(c->max_lds);
+    const int rc = score_static_init(c);
+    if (rc != CBH_OK) {
+        (void)hipFree(c->d_flags);
+        delete c;
+        return rc;
+    }
     *out = c;
     return CBH_OK;
 }

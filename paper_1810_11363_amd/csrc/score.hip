@@ -54,10 +54,35 @@ int64_t score_scratch_bytes(const cbh_problem* p) {
     return align_up(int64_t(p->n_features) * sizeof(FeatBest), 256);
 }
 
+// Scratch of cbh_score_splits_noalloc (the entry point for callers that
+// cannot allocate device memory): the last-block counter in the first 256
+// bytes, then one FeatBest per feature, for at most kStaticScoreFeatures
+// features (1 MB). Every GPU holds its own copy until the process ends; in
+// host code the array's name is not a device address, so the library keeps
+// the address hipGetSymbolAddress returns for each device (in its context)
+// and passes that to the kernels.
+constexpr int64_t kStaticScoreFeatures = 65536;
+constexpr int64_t kStaticScoreBytes = 256 + kStaticScoreFeatures * sizeof(FeatBest);
+static __device__ __align__(256) unsigned char scratch[kStaticScoreBytes];
+
+int score_static_init(cbh_ctx* ctx) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        set_error("hipGetSymbolAddress of the static score scratch failed: %s",
+                  hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    // the counter must start at zero; the kernel's last block resets it
+    CBH_HIP(hipMemset(ptr, 0, 256));
+    ctx->score_static = ptr;
+    return CBH_OK;
+}
+
 int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* hist,
                  int32_t precision, double l2, cbh_split* best, float* scores, void* scratch,
-                 hipStream_t s) {
-    (void)ctx;
+                 hipStream_t s, uint32_t* counter_in) {
     ScoreRow r;
     r.hist = hist;
     r.grad_scale = p->grad_scale;
@@ -68,7 +93,7 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     r.l2 = l2;
     const int L = 1 << level;
     FeatBest* fb = (FeatBest*)scratch;
-    uint32_t* counter = ctx->d_flags + 1;
+    uint32_t* counter = counter_in ? counter_in : ctx->d_flags + 1;
     const bool small = int64_t(L) * r.K <= kScoreWavesSmall;
 #define CBH_SCORE(P)                                                                      \
     if (small)                                                                            \
@@ -107,4 +132,26 @@ extern "C" int cbh_score_splits(cbh_ctx* ctx, const cbh_problem* prob, int32_t l
     if (rc) return rc;
     return launch_score(ctx, prob, level, hist, precision, l2, best_out, scores_out, ctx->ws,
                         (hipStream_t)stream);
+}
+
+extern "C" int cbh_score_splits_noalloc(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
+                                        const void* hist, int32_t precision, double l2,
+                                        cbh_split* best_out, float* scores_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
+    CBH_ARG(hist && best_out, "hist / best_out is NULL");
+    CBH_ARG(l2 >= 0 && std::isfinite(l2), "l2 must be finite and >= 0");
+    CBH_ARG(prob->n_features <= kStaticScoreFeatures,
+            "cbh_score_splits_noalloc takes at most %lld features (got %d); use "
+            "cbh_score_splits",
+            (long long)kStaticScoreFeatures, prob->n_features);
+    CBH_ARG(ctx->score_static != nullptr, "the context has no static score scratch");
+    unsigned char* base = static_cast<unsigned char*>(ctx->score_static);
+    return launch_score(ctx, prob, level, hist, precision, l2, best_out, scores_out, base + 256,
+                        (hipStream_t)stream, reinterpret_cast<uint32_t*>(base));
 }
