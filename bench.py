@@ -53,19 +53,6 @@ PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2, "f64": 3}
 DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64", "f64": "f64"}
 
 
-class Stamp:
-    """Duck-typed event for the booster's fit_tree: record() enqueues the
-    library's device-clock stamp into one slot of a device buffer, which a
-    stream capture turns into a graph node (events cannot be recorded inside
-    a HIP graph)."""
-
-    def __init__(self, cb, ctx, buf, idx):
-        self.cb, self.ctx, self.ptr = cb, ctx, buf.data_ptr() + 8 * idx
-
-    def record(self, stream):
-        self.cb.cbh_device_timestamp(self.ctx, self.ptr, stream)
-
-
 def hist_bytes_per_level(n, F, K, level, rmse, precision):
     """Algorithmic bytes one histogram build must read: the bin of every
     (row, feature), the row's gradient statistics and (after level 0) its leaf."""
@@ -390,23 +377,22 @@ def time_form(bst, name, args, rmse):
         timing = "device-clock stamps around every build, captured in the tree graphs"
         khz = cb.cbh_device_clock_khz(bst.ctx)
         buf = torch.zeros(n_hist * depth * 2, dtype=torch.int64, device=bst.device)
-        timed = []
-        for s in range(n_hist):
-            stamps = [(Stamp(cb, bst.ctx, buf, (s * depth + l) * 2),
-                       Stamp(cb, bst.ctx, buf, (s * depth + l) * 2 + 1)) for l in range(depth)]
-            timed.append(bst.capture_tree(args.warmup + args.steps + s, events=stamps))
+        timed = [bst.capture_tree(args.warmup + args.steps + s,
+                                  stamps=buf.data_ptr() + 8 * 2 * depth * s)
+                 for s in range(n_hist)]
         warm_for(bst, args.warmup_s, args.warmup, False)   # settle again after the captures
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(stream):
             e0.record(stream)
             for g in timed:
-                g.replay()
+                cb.cbh_graph_launch(g, stream)
             e1.record(stream)
         torch.cuda.synchronize()
         stamped_tree_ms = e0.elapsed_time(e1) / n_hist
         v = buf.view(n_hist, depth, 2).cpu().numpy()
         hist_ms[:] = (v[:, :, 1] - v[:, :, 0]) / khz
-        del timed
+        for g in timed:
+            cb.cbh_graph_destroy(g)
     else:
         stamped_tree_ms = None
         timing = "events around the builds of eagerly launched trees"
@@ -531,23 +517,28 @@ def c2_batches(args, ctx, prec, side, timed):
     t0 = time.perf_counter()
     base = datagen.make_c2(n=args.c2_rows, s=8)
     full = GpuBooster.from_problem(base, precision=prec, ctx=ctx).prepare()
-    folds = [GpuBooster.from_problem(q, precision=prec, ctx=ctx,
-                                     borders=full.num_borders).prepare()
-             for q in datagen.cv_folds(base, 5)]
+    # the folds: row weights over one booster's rows (0 on each fold's held-out
+    # rows), each fold with its own permutation's statistic columns; the
+    # numeric bins are binned once for all folds
+    cvq, w = datagen.cv_fold_weights(datagen.make_c2(n=args.c2_rows, s=1), 5)
+    cvb = GpuBooster.from_problem(cvq, precision=prec, ctx=ctx).prepare()
+    fold_states = [cvb.model_state(j, weight=w[j]) for j in range(5)]
     states = [full.model_state(r) for r in range(8)]
     print(f"# cross-validation and permutation batches prepared in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     res = []
     for name, probs, hists, lvs in [
-            ("cv", [b.probs[0] for b in folds], [b.hist for b in folds],
-             [b.leaf_values for b in folds]),
+            ("cv", [m.prob for m in fold_states], [m.hist for m in fold_states],
+             [m.leaf_values for m in fold_states]),
             ("perm", [m.prob for m in states], [m.hist for m in states],
              [m.leaf_values for m in states])]:
         ms_b, ms_s = batch_vs_one_by_one(ctx, probs, hists, lvs, prec, full.lr, full.l2, side,
                                          timed)
         rows = sum(int(p.n) for p in probs)
+        train_rows = int((w > 0).sum()) if name == "cv" else rows
         res.append({
-            "problems": len(probs), "rows": rows, "features": full.F, "depth": full.depth,
+            "problems": len(probs), "rows": rows, "training_rows": train_rows,
+            "features": full.F, "depth": full.depth,
             "ms_per_iteration": round(ms_b, 4), "ms_per_tree": round(ms_b / len(probs), 5),
             "g_row_features_per_s": round(rows * full.F * full.depth / (ms_b / 1e3) / 1e9, 3),
             "one_plan_per_problem_ms_per_iteration": round(ms_s, 4),
@@ -555,10 +546,11 @@ def c2_batches(args, ctx, prec, side, timed):
         print(f"# {name} batch: {ms_b:.3f} ms/iteration, one plan per problem {ms_s:.3f}",
               file=sys.stderr, flush=True)
     res[0]["workload"] = (f"5-fold cross-validation of the {args.c2_rows}-row RMSE problem "
-                          f"(110 features x 128 bins, depth 6), one model per fold")
+                          f"(110 features x 128 bins, depth 6), one model per fold: row "
+                          f"weights (0 on the fold's held-out rows) over the shared rows")
     res[1]["workload"] = (f"8 ordered-boosting permutations of the {args.c2_rows}-row RMSE "
                           f"problem, one model per permutation")
-    for b in folds + [full]:
+    for b in (cvb, full):
         b.close()
     return res[0], res[1]
 
@@ -598,7 +590,7 @@ def run_batch(args):
 
     def seq_iter():
         for g in graphs:
-            g.replay()
+            cb.cbh_graph_launch(g, side)
     # batched
     best = torch.zeros((P, depth, 4), dtype=torch.int32, device=dev)
     plan = cb.cbh_batch_create(ctx, [b.probs[0] for b in bsts], prec, [b.hist for b in bsts],
@@ -645,6 +637,8 @@ def run_batch(args):
         "batched_vs_sequential": round(ms_seq / ms_batch, 3),
     }
     cb.cbh_graph_destroy(gr)
+    for g in graphs:
+        cb.cbh_graph_destroy(g)
     cb.cbh_batch_destroy(plan)
     for b in bsts:
         b.close()

@@ -275,6 +275,30 @@ def cv_folds(p: Problem, k: int = 5, cfg: int = 4, stream: int = 200) -> list[Pr
     return out
 
 
+def cv_fold_weights(p: Problem, k: int = 5, cfg: int = 4, stream: int = 200):
+    """The same k folds as cv_folds, as row weights over p's rows: returns
+    (q, w) with w float32 [k][n] (0 on fold j's held-out rows, else 1) and q a
+    copy of p whose k permutations are the folds' own: fold j's training rows
+    in the order of cv_folds' permutation of them, then its held-out rows, so
+    that the training rows' ordered statistics count training rows only."""
+    order = rng_for(cfg, stream).permutation(p.n)
+    parts = np.array_split(order, k)
+    perms = np.empty((k, p.n), np.int32)
+    w = np.ones((k, p.n), np.float32)
+    for j in range(k):
+        keep = np.ones(p.n, bool)
+        keep[parts[j]] = False
+        rows = np.flatnonzero(keep)
+        sub = rng_for(cfg, stream + 1 + j).permutation(rows.size)
+        perms[j] = np.concatenate([rows[sub], np.sort(parts[j])]).astype(np.int32)
+        w[j, parts[j]] = 0.0
+    import copy
+    q = copy.copy(p)
+    q.name = f"{p.name}_cv{k}"
+    q.perms = perms
+    return q, w
+
+
 def c4_sizes(P: int = 64, lo: int = 5_000, hi: int = 2_000_000, scale: float = 1.0):
     g = rng_for(4, 0)
     n = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), P))).astype(np.int64)

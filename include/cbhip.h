@@ -132,7 +132,17 @@ typedef struct cbh_ctx cbh_ctx;
  *               16 f and seg_stride[f] = 16 F: then the 16-row segments of
  *               consecutive features are adjacent, which the histogram
  *               kernel that gives lanes of a wave different features reads
- *               with full coalescing. The values are not checked.          */
+ *               with full coalescing. The values are not checked.
+ *   weight      device float [n] or NULL: row weights w_i >= 0 (row i's loss
+ *               counts w_i times). cbh_update_approx then writes w_i g_i and
+ *               w_i h_i, and for RMSE h_i = w_i, so the second statistic of
+ *               the histograms is the sum of weights instead of the row
+ *               count (every call then treats RMSE like the h-carrying
+ *               losses: h must be given). A cross-validation fold is the
+ *               whole problem with weight 0 on its held-out rows: the folds
+ *               read the same rows and bins (nothing is gathered or copied),
+ *               and the held-out rows' approx are the fold model's
+ *               predictions for them. Leaf counts still count every row.  */
 typedef struct cbh_problem {
     int64_t n;
     int32_t n_features;
@@ -151,6 +161,7 @@ typedef struct cbh_problem {
     uint16_t* leaf;
     double* approx;
     const int64_t* seg_stride;
+    const float* weight;
 } cbh_problem;
 
 /* Result of the split search of one level (device memory).
@@ -481,9 +492,55 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
                     const int32_t* split_feature, const int32_t* split_border,
                     const double* leaf_values, double lr, double* approx, void* stream);
 
-/* ---- rows in leaf order (deep trees, many classes) ------------------------- */
+/* ---- one whole tree --------------------------------------------------------- */
 
 typedef struct cbh_part cbh_part;
+
+/* One tree of Algorithm 1 in one call: every level's histograms, score,
+ * argmax and row routing (Sec. 3 first phase, Sec. 4), then the leaf solve
+ * and the approx/gradient update (Sec. 3 second phase), enqueued on `stream`
+ * exactly as the per-level calls would be:
+ *   - CBH_PREC_INT16: cbh_quantize_gradients first;
+ *   - level 0: cbh_build_histograms; level l >= 1: with a partition,
+ *     cbh_part_build_histograms_sub (subtract != 0) or
+ *     cbh_part_build_histograms; without one, cbh_apply_build_histograms_sub
+ *     (subtract != 0, which also sets level l-1's leaf bit) or
+ *     cbh_build_histograms;
+ *   - then cbh_score_splits into best[l], and the rows are routed by that
+ *     split: cbh_part_split with a partition, else cbh_apply_split (with
+ *     subtraction only at the last level, the others being set by the next
+ *     build);
+ *   - finally cbh_update_approx with the last level's histograms.
+ *   part         a partition for prob's shape (cbh_part_create), or NULL for
+ *                the original row order
+ *   hist         host array [2] of device buffers, each large enough for the
+ *                level depth-1 histograms; level l writes hist[l % 2]
+ *   best         device cbh_split [depth]
+ *   leaf_values  device double [2^depth][K]; leaf_counts: device int64
+ *                [2^depth] or NULL
+ *   stamps       device uint64 [2 depth] or NULL: instrumentation, the
+ *                device clock (cbh_device_timestamp) before and after every
+ *                level's histogram build
+ * Errors as the calls it makes; a failing call stops the sequence (calls
+ * before it stay enqueued). */
+int cbh_fit_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part, int32_t precision,
+                 int32_t subtract, void* const* hist, cbh_split* best, double lr, double l2,
+                 double* leaf_values, int64_t* leaf_counts, uint64_t* stamps, void* stream);
+
+/* The same tree captured into a HIP graph that the library owns (launch it
+ * with cbh_graph_launch on any stream, free it with cbh_graph_destroy). Grow
+ * one tree of the same shape first, so that the context workspace has its
+ * size: a call under capture does not allocate (CBH_EBUSY). The graph keeps
+ * the problem's device pointers, the partition and the buffers. `stream`
+ * must not be the default stream. */
+typedef struct cbh_graph cbh_graph;
+int cbh_graph_capture_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part,
+                           int32_t precision, int32_t subtract, void* const* hist,
+                           cbh_split* best, double lr, double l2, double* leaf_values,
+                           int64_t* leaf_counts, uint64_t* stamps, void* stream,
+                           cbh_graph** out);
+
+/* ---- rows in leaf order (deep trees, many classes) ------------------------- */
 
 /* Device buffers that keep a problem's rows sorted by leaf during a tree, so
  * that a level's histograms (Sec. 5) read every row once whatever the number
@@ -579,6 +636,11 @@ void cbh_batch_destroy(cbh_batch* batch);
  * splits). */
 int cbh_batch_level(cbh_ctx* ctx, cbh_batch* batch, int32_t level, double l2,
                     void* stream);
+/* A one-call form, level(ctx, probs, P, level, precision, l2, best_out,
+ * stream), is cbh_batch_create once for the set of problems (it copies their
+ * descriptors to the device and sizes the plan's workspace: the allocation a
+ * per-level call could not make under graph capture) and then this call per
+ * level; the split of problem p at the level is best[p][level]. */
 
 /* Finish the trees of every problem of the plan (as cbh_update_approx with the
  * level depth-1 histograms and splits); leaf_values is a host array [P] of
@@ -590,7 +652,6 @@ int cbh_batch_update(cbh_ctx* ctx, cbh_batch* batch, double lr, double l2,
 /* Capture one whole boosting iteration of the plan (reset leaves, every
  * level, the leaf solve and the approx/gradient update) into a HIP graph and
  * return an executable graph that replays it on `stream`. */
-typedef struct cbh_graph cbh_graph;
 int cbh_graph_capture_iteration(cbh_ctx* ctx, cbh_batch* batch, double lr, double l2,
                                 double* const* leaf_values, void* stream,
                                 cbh_graph** out);

@@ -243,7 +243,8 @@ class GpuBooster:
         """Switch the histogram form; keeps the prepared bins and statistics."""
         self.precision = int(precision)
         self.subtract = (self.precision != cb.CBH_PREC_FP32) if subtract is None else bool(subtract)
-        self.graphs = []      # captured trees point at the old buffers
+        torch.cuda.synchronize(self.device)
+        self.drop_graphs()    # captured trees point at the old buffers
         self._alloc_hists()
         self._choose_order()
 
@@ -319,10 +320,17 @@ class GpuBooster:
             cb.cbh_apply_split(self.ctx, pr, level, self.split_ptr(level), self.stream)
 
     def fit_tree(self, t: int, counts: bool = False, events=None):
-        """One tree (all levels, leaf solve, approx and gradient update).
-        `events`: optional list of (start, end) CUDA events per level recorded
-        around each histogram build."""
+        """One tree (all levels, leaf solve, approx and gradient update) in one
+        library call (cbh_fit_tree). `events`: optional list of (start, end)
+        objects with a record(stream) method, recorded around each level's
+        histogram build; then the levels are issued one call at a time."""
         pr = self.probs[t % self.s]
+        if events is None:
+            cb.cbh_fit_tree(self.ctx, pr, self.part if self.use_part else None, self.precision,
+                            self.subtract, self.hists, self.best, self.lr, self.l2,
+                            self.leaf_values, self.leaf_counts if counts else None, None,
+                            self.stream)
+            return
         ctx, st, prec = self.ctx, self.stream, self.precision
         if prec == cb.CBH_PREC_INT16:
             cb.cbh_quantize_gradients(ctx, pr, st)
@@ -330,15 +338,13 @@ class GpuBooster:
         # set by the next level's build, in its row-code pass
         fuse = not self.use_part and self.subtract
         for lvl in range(self.depth):
-            if events is not None:
-                events[lvl][0].record(st)
+            events[lvl][0].record(st)
             if fuse and lvl > 0:
                 cb.cbh_apply_build_histograms_sub(ctx, pr, lvl, prec, self.hist_ptr(lvl - 1),
                                                   self.split_ptr(lvl - 1), self.hist_ptr(lvl), st)
             else:
                 self.build_level_histograms(pr, lvl)
-            if events is not None:
-                events[lvl][1].record(st)
+            events[lvl][1].record(st)
             cb.cbh_score_splits(ctx, pr, lvl, self.hist_ptr(lvl), prec, self.l2,
                                 self.split_ptr(lvl), None, st)
             if not fuse or lvl == self.depth - 1:
@@ -347,53 +353,42 @@ class GpuBooster:
                              self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
                              self.leaf_counts if counts else None, st)
 
-    def capture_trees(self, events=None):
-        """Capture one tree per permutation into HIP graphs; tree t replays
-        graph t mod s on the current stream. Grow at least one tree of every
-        permutation first: the library's workspace must have reached its size,
-        since a call under capture never allocates (it fails with CBH_EBUSY
-        instead); a later growth of the workspace keeps the buffer the graphs
-        point at. A change of form drops the graphs. `events[r]`: optional
-        per-level (start, end) pairs recorded
-        around the builds of permutation r's tree (objects with a
-        record(stream) method that a capture turns into graph nodes).
-        Returns the list of graphs."""
-        graphs = []
-        cap = torch.cuda.Stream(self.device)       # default priority
-        eager = self.stream
-        torch.cuda.synchronize(self.device)
-        try:
-            self.stream = cap
-            for r in range(self.s):
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=cap):
-                    self.fit_tree(r, events=None if events is None else events[r])
-                graphs.append(g)
-        finally:
-            self.stream = eager
-        torch.cuda.synchronize(self.device)
-        if events is None:
-            self.graphs = graphs
-        return graphs
-
-    def capture_tree(self, t: int, events=None):
-        """One graph of tree t (permutation t mod s), with optional per-level
-        (start, end) records around the builds (see capture_trees)."""
+    def _capture(self, t: int, stamps=None):
+        """A library-owned graph of tree t (cbh_graph_capture_tree), captured
+        on a side stream of default priority."""
         cap = torch.cuda.Stream(self.device)
-        eager = self.stream
         torch.cuda.synchronize(self.device)
-        g = torch.cuda.CUDAGraph()
-        try:
-            self.stream = cap
-            with torch.cuda.graph(g, stream=cap):
-                self.fit_tree(t, events=events)
-        finally:
-            self.stream = eager
+        g = cb.cbh_graph_capture_tree(self.ctx, self.probs[t % self.s],
+                                      self.part if self.use_part else None, self.precision,
+                                      self.subtract, self.hists, self.best, self.lr, self.l2,
+                                      self.leaf_values, None, stamps, cap)
         torch.cuda.synchronize(self.device)
         return g
 
+    def capture_trees(self):
+        """Capture one tree per permutation into library-owned HIP graphs; tree
+        t replays graph t mod s on the booster's stream. Grow at least one tree
+        of every permutation first: the library's workspace must have reached
+        its size, since a call under capture never allocates (it fails with
+        CBH_EBUSY instead); a later growth of the workspace keeps the buffer
+        the graphs point at. A change of form drops the graphs."""
+        self.drop_graphs()
+        self.graphs = [self._capture(r) for r in range(self.s)]
+        return self.graphs
+
+    def capture_tree(self, t: int, stamps=None):
+        """One graph of tree t (permutation t mod s); `stamps`: device uint64
+        [2 depth] receiving the device clock before and after every build.
+        The caller launches it (cb.cbh_graph_launch) and destroys it."""
+        return self._capture(t, stamps)
+
+    def drop_graphs(self):
+        for g in self.graphs:
+            cb.cbh_graph_destroy(g)
+        self.graphs = []
+
     def replay_tree(self, t: int):
-        self.graphs[t % self.s].replay()
+        cb.cbh_graph_launch(self.graphs[t % self.s], self.stream)
 
     def tree_record(self) -> TreeRecord:
         b = self.best.cpu().numpy()
@@ -432,11 +427,16 @@ class GpuBooster:
                                self.depth, df, db, dv, self.lr, approx, self.stream)
         return approx
 
-    def model_state(self, r: int) -> "ModelState":
-        """A further model over permutation r's bins (see ModelState)."""
-        return ModelState(self, r)
+    def model_state(self, r: int, weight=None) -> "ModelState":
+        """A further model over permutation r's bins (see ModelState);
+        `weight`: optional float32 [n] row weights (a cross-validation fold:
+        0 on its held-out rows)."""
+        return ModelState(self, r, weight)
 
     def close(self):
+        if self.graphs:
+            torch.cuda.synchronize(self.device)
+            self.drop_graphs()
         if self.part is not None:
             torch.cuda.synchronize(self.device)
             cb.cbh_part_destroy(self.part)
@@ -461,11 +461,15 @@ class ModelState:
     (Sec. 3); several such models run side by side through the batched calls
     (cbh_batch_create with `prob`, `hist` and `leaf_values` of each)."""
 
-    def __init__(self, base: GpuBooster, r: int):
+    def __init__(self, base: GpuBooster, r: int, weight=None):
         if not hasattr(base, "probs"):
             raise RuntimeError("prepare() the booster first")
         d, n, K = base.device, base.n, base.K
         self.base, self.r = base, int(r)
+        self.weight = None
+        if weight is not None:
+            self.weight = torch.as_tensor(np.ascontiguousarray(weight, np.float32)).to(d)
+            assert self.weight.numel() == n
         self.g = torch.empty((K, n), dtype=torch.float32, device=d)
         self.h = torch.empty((K, n), dtype=torch.float32, device=d)
         self.gq = torch.empty((K, n, 2), dtype=torch.int16, device=d)
@@ -482,4 +486,5 @@ class ModelState:
         p.grad_scale = self.grad_scale.data_ptr()
         p.leaf = self.leaf.data_ptr()
         p.approx = self.approx.data_ptr()
+        p.weight = self.weight.data_ptr() if self.weight is not None else None
         self.prob = p

@@ -36,6 +36,7 @@ EXPORTS = [
     "cbh_score_splits", "cbh_score_splits_noalloc", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
     "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
+    "cbh_fit_tree", "cbh_graph_capture_tree",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
     "cbh_part_build_histograms_sub",
@@ -50,7 +51,7 @@ class cbh_problem(C.Structure):
         ("loss", C.c_int32), ("depth", C.c_int32), ("reserved", C.c_int32),
         ("label", C.c_void_p), ("g", C.c_void_p), ("h", C.c_void_p),
         ("gq", C.c_void_p), ("grad_scale", C.c_void_p), ("leaf", C.c_void_p),
-        ("approx", C.c_void_p), ("seg_stride", C.c_void_p),
+        ("approx", C.c_void_p), ("seg_stride", C.c_void_p), ("weight", C.c_void_p),
     ]
 
 
@@ -112,6 +113,10 @@ def _load():
         "cbh_batch_update": ([vp, vp, dbl, dbl, vp, i32, vp], C.c_int),
         "cbh_graph_capture_iteration": ([vp, vp, dbl, dbl, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_launch": ([vp, vp], C.c_int),
+        "cbh_fit_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl, vp, vp,
+                          vp, vp], C.c_int),
+        "cbh_graph_capture_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl,
+                                    vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_destroy": ([vp], None),
         "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, i32, C.c_char_p, vp], C.c_int),
         "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
@@ -385,6 +390,32 @@ def cbh_graph_capture_iteration(ctx, batch, lr: float, l2: float, leaf_values, s
     _check(_lib.cbh_graph_capture_iteration(ctx, batch, float(lr), float(l2),
                                             C.cast(lv, C.c_void_p), _stream(stream),
                                             C.byref(out)))
+    return out.value
+
+
+def _two(hist):
+    arr = (C.c_void_p * 2)(_ptr(hist[0]), _ptr(hist[1]))
+    return arr
+
+
+def cbh_fit_tree(ctx, prob: cbh_problem, part, precision: int, subtract: bool, hist, best,
+                 lr: float, l2: float, leaf_values, leaf_counts=None, stamps=None, stream=None):
+    arr = _two(hist)
+    return _check(_lib.cbh_fit_tree(ctx, C.byref(prob), part, precision, int(bool(subtract)),
+                                    C.cast(arr, C.c_void_p), _ptr(best), float(lr), float(l2),
+                                    _ptr(leaf_values), _ptr(leaf_counts), _ptr(stamps),
+                                    _stream(stream)))
+
+
+def cbh_graph_capture_tree(ctx, prob: cbh_problem, part, precision: int, subtract: bool, hist,
+                           best, lr: float, l2: float, leaf_values, leaf_counts=None,
+                           stamps=None, stream=None):
+    arr = _two(hist)
+    out = C.c_void_p()
+    _check(_lib.cbh_graph_capture_tree(ctx, C.byref(prob), part, precision, int(bool(subtract)),
+                                       C.cast(arr, C.c_void_p), _ptr(best), float(lr), float(l2),
+                                       _ptr(leaf_values), _ptr(leaf_counts), _ptr(stamps),
+                                       _stream(stream), C.byref(out)))
     return out.value
 
 

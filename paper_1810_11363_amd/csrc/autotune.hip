@@ -150,7 +150,7 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int F = prob->n_features, B = prob->max_bins, K = prob->K;
-    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const int rmse = count_stat(prob);
     std::vector<int32_t> budgets;
     for (int32_t v : {32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, 160 * 1024})
         if (v <= ctx->max_lds) budgets.push_back(v);

@@ -143,10 +143,6 @@ struct cbh_batch {
                                     // every problem, sides and row codes
 };
 
-struct cbh_graph {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-};
 
 namespace cbh {
 
@@ -401,7 +397,7 @@ static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_
     const int L = 1 << level;
     const int slots = lp.sub ? L / 2 : L;      // histogram slots: parents or leaves
     const int64_t grid = 8 * ((lp.n_tiles + 7) / 8);
-    const bool rm = b->probs[0].loss == CBH_LOSS_RMSE;
+    const bool rm = count_stat(&b->probs[0]);
     const dim3 grd((unsigned)grid), blk(kHistThreads);
     const size_t lds = (size_t)lp.max_lds;
     if (lp.sub) {
@@ -538,8 +534,10 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         if (rc) return rc;
         CBH_ARG(probs[p].depth == probs[0].depth, "every problem needs the same depth");
         CBH_ARG(probs[p].loss == probs[0].loss, "every problem needs the same loss");
+        CBH_ARG(count_stat(&probs[p]) == count_stat(&probs[0]),
+                "either every RMSE problem has row weights or none has");
         CBH_ARG(hist[p] != nullptr, "hist[%d] is NULL", p);
-        CBH_REQUIRE(tile_lds_bytes(precision, probs[p].loss == CBH_LOSS_RMSE, probs[p].K,
+        CBH_REQUIRE(tile_lds_bytes(precision, count_stat(&probs[p]), probs[p].K,
                                    probs[p].max_bins, 1) <= ctx->max_lds,
                     CBH_EUNSUPPORTED, "a (leaf, feature) tile of problem %d does not fit in LDS", p);
     }
@@ -593,7 +591,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                 break;
             }
             const HistPlan hp = plan_hist(kb, probs[p].n, probs[p].n_features, probs[p].max_bins,
-                                          1, L, precision, probs[p].loss == CBH_LOSS_RMSE,
+                                          1, L, precision, count_stat(&probs[p]),
                                           ctx->max_lds);
             lp.W = std::min(lp.W, hp.fb);
         }
@@ -608,7 +606,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             kb.kernel = lp.kind;
             kb.lpf_w = lp.W;
             HistPlan hp = plan_hist(kb, pr.n, pr.n_features, pr.max_bins, pr.K, slots, precision,
-                                    pr.loss == CBH_LOSS_RMSE, ctx->max_lds);
+                                    count_stat(&pr), ctx->max_lds);
             rb_off.push_back(rb_off.back() + (pr.n + kSideRows - 1) / kSideRows);
             if (lp.kind == 1 && hp.fb != lp.W) {
                 set_error("batched group width %d differs from %d", hp.fb, lp.W);
@@ -701,7 +699,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         const cbh_problem& pr = probs[p];
         dp[p] = DevProb{pr.bins, pr.n_bins, pr.g, pr.h, reinterpret_cast<const uint32_t*>(pr.gq),
                         pr.grad_scale, pr.leaf, hist[p], nullptr, pr.n, pr.n_features,
-                        pr.max_bins, pr.K, pr.loss == CBH_LOSS_RMSE, pr.seg_stride,
+                        pr.max_bins, pr.K, count_stat(&pr), pr.seg_stride,
                         nullptr, nullptr, nullptr, pr.leaf};
     }
     std::vector<DevProb> all;

@@ -112,6 +112,12 @@ struct cbh_ctx {
     cbh::HistKnobs forced;
 };
 
+// An instantiated HIP graph owned by the library (cbh_graph_capture_*).
+struct cbh_graph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
 namespace cbh {
 
 // Grow the workspace to at least `bytes` for a call on `stream`; returns
@@ -120,6 +126,12 @@ namespace cbh {
 int ensure_ws(cbh_ctx* ctx, int64_t bytes, void* stream);
 
 inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// The histograms' second statistic is a row count (RMSE without row
+// weights); otherwise it is the sum of h.
+inline bool count_stat(const cbh_problem* p) {
+    return p->loss == CBH_LOSS_RMSE && p->weight == nullptr;
+}
 
 // Histogram planning (histogram.hip).
 int words_per_cell(int32_t precision, int32_t K);

@@ -76,7 +76,7 @@ int validate_problem(const cbh_problem* p) {
         CBH_ARG(p->K == 1, "K must be 1 for RMSE and Logloss (got %d)", p->K);
     }
     CBH_ARG(p->label && p->g && p->leaf && p->approx, "label/g/leaf/approx is NULL");
-    CBH_ARG(p->loss == CBH_LOSS_RMSE || p->h != nullptr, "h is NULL");
+    CBH_ARG(count_stat(p) || p->h != nullptr, "h is NULL (needed unless RMSE without weights)");
     return CBH_OK;
 }
 

@@ -659,7 +659,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     a.rowcode = p->leaf;
     if (parent) {
         const int64_t half = int64_t(1) << (level - 1);
-        const int rmse = p->loss == CBH_LOSS_RMSE;
+        const int rmse = count_stat(p);
         const bool fused = plan.kind == 1 && half * p->max_bins <= 16384;
         if (apply_parent && !fused) {
             // the parent level's leaf bit first, as cbh_apply_split
@@ -733,7 +733,7 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
     a.n_fgroups = plan.n_fgroups;
     a.n_ltiles = plan.n_ltiles;
     a.wpc = plan.words_per_cell;
-    a.rmse = p->loss == CBH_LOSS_RMSE;
+    a.rmse = count_stat(p);
     a.rep = plan.rep;
     switch (precision) {
         case CBH_PREC_FP32: launch_hist_prec<CBH_PREC_FP32>(a, plan, ctx->max_lds, s); break;
@@ -866,7 +866,7 @@ int cbh_quantize_gradients(cbh_ctx* ctx, const cbh_problem* prob, void* stream) 
     if (rc) return rc;
     uint32_t* maxbits = (uint32_t*)ctx->ws;
     hipStream_t s = (hipStream_t)stream;
-    const int with_h = prob->loss != CBH_LOSS_RMSE;
+    const int with_h = !count_stat(prob);
     zero_u32_kernel<<<1, 64, 0, s>>>(maxbits, 2 * prob->K);
     const int gx = (int)std::min<int64_t>((prob->n + 255) / 256, ctx->num_cus * 4);
     const int gm = (int)std::min<int64_t>((prob->n + 255) / 256, ctx->num_cus);
@@ -892,7 +892,7 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
     const int L = 1 << level;
     const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
                                    precision, prob->n, 0);
-    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const int rmse = count_stat(prob);
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, L,
                                     precision, rmse, ctx->max_lds);
     CBH_REQUIRE(tile_lds_bytes(precision, rmse, prob->K, prob->max_bins, 1) <= ctx->max_lds,
@@ -920,7 +920,7 @@ static int build_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, int32
     const int half = 1 << (level - 1);
     const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
                                    precision, prob->n, 1);
-    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const int rmse = count_stat(prob);
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, half,
                                     precision, rmse, ctx->max_lds);
     CBH_REQUIRE(tile_lds_bytes(precision, rmse, prob->K, prob->max_bins, 1) <= ctx->max_lds,

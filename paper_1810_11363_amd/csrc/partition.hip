@@ -698,6 +698,8 @@ static int check_part(const cbh_part* part, const cbh_problem* prob) {
     CBH_ARG(prob->n == part->n && prob->n_features == part->F && prob->K == part->K &&
                 prob->depth == part->depth && prob->loss == part->loss,
             "problem does not match the partition (n, features, K, depth, loss)");
+    CBH_ARG(count_stat(prob) || part->h[0] != nullptr,
+            "the partition holds no h (made for RMSE without row weights), the problem needs it");
     return CBH_OK;
 }
 
@@ -739,7 +741,7 @@ int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out) {
              alloc((void**)&p->g[b], K * np * 4) && alloc((void**)&p->gq[b], K * np * 4) &&
              alloc((void**)&p->order[b], np * 4) && alloc((void**)&p->code[b], np * 2) &&
              alloc((void**)&p->off[b], (2 * half + 1) * 8);
-        if (ok && p->loss != CBH_LOSS_RMSE) ok = alloc((void**)&p->h[b], K * np * 4);
+        if (ok && !count_stat(prob)) ok = alloc((void**)&p->h[b], K * np * 4);
     }
     ok = ok && alloc((void**)&p->seg, F * 8) && alloc((void**)&p->zl, half * 4) &&
          alloc((void**)&p->blk, (p->n_pb + 1) * 8) && alloc((void**)&p->cp, (half + 1) * 8) &&
@@ -835,7 +837,7 @@ int cbh_part_split(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int32_
     m.src_code = scode;
     m.dst_code = part->code[dst];
     const bool q = precision == CBH_PREC_INT16;
-    const bool rm = prob->loss == CBH_LOSS_RMSE;
+    const bool rm = count_stat(prob);
     m.src_g = q ? nullptr : (first ? prob->g : part->g[src]);
     m.src_h = (q || rm) ? nullptr : (first ? prob->h : part->h[src]);
     m.src_gq = q ? (first ? reinterpret_cast<const uint32_t*>(prob->gq) : part->gq[src]) : nullptr;
@@ -866,7 +868,7 @@ static int part_build(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int
     const int src = (level + 1) & 1;   // written by the split of level - 1
     const int L = 1 << level;
     const int F = part->F, B = prob->max_bins, K = part->K;
-    const int rmse = prob->loss == CBH_LOSS_RMSE;
+    const int rmse = count_stat(prob);
     const HistKnobs kn = knobs_for(ctx, F, B, K, level, precision, prob->n, sub ? 3 : 2);
     const HistPlan plan = plan_part(kn, prob->n, F, B, K, L, precision, ctx->max_lds, sub);
     const int64_t spc = std::max<int64_t>(1, plan.rows_per_chunk / 16);

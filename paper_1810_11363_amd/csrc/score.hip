@@ -89,7 +89,7 @@ int launch_score(cbh_ctx* ctx, const cbh_problem* p, int32_t level, const void* 
     r.F = p->n_features;
     r.B = p->max_bins;
     r.K = p->K;
-    r.rmse = p->loss == CBH_LOSS_RMSE;
+    r.rmse = count_stat(p);
     r.l2 = l2;
     const int L = 1 << level;
     FeatBest* fb = (FeatBest*)scratch;

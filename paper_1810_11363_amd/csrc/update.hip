@@ -129,6 +129,7 @@ struct UpdArgs {
     const uint16_t* leaf;
     const double* values;
     const float* label;
+    const float* weight;      // row weights or NULL
     double* approx;
     float* g;
     float* h;
@@ -145,6 +146,9 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs a) {
          i += int64_t(gridDim.x) * 256) {
         const double y = (double)a.label[i];
         const int64_t Lf = a.add ? (a.leaf[i] & a.lmask) : 0;
+        // with row weights the loss of row i counts w times: so do g and h
+        // (RMSE: h = w, the second statistic becomes the sum of weights)
+        const double w = a.weight ? (double)a.weight[i] : 1.0;
         if constexpr (LOSS != CBH_LOSS_MULTICLASS) {
             double ap = a.approx[i];
             if (a.add) {
@@ -152,11 +156,21 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs a) {
                 a.approx[i] = ap;
             }
             if constexpr (LOSS == CBH_LOSS_RMSE) {
-                a.g[i] = (float)(ap - y);
+                if (a.weight) {
+                    a.g[i] = (float)(w * (ap - y));
+                    a.h[i] = (float)w;
+                } else {
+                    a.g[i] = (float)(ap - y);
+                }
             } else {
                 const double p = 1.0 / (1.0 + exp(-ap));
-                a.g[i] = (float)(p - y);
-                a.h[i] = (float)(p * (1.0 - p));
+                if (a.weight) {
+                    a.g[i] = (float)(w * (p - y));
+                    a.h[i] = (float)(w * (p * (1.0 - p)));
+                } else {
+                    a.g[i] = (float)(p - y);
+                    a.h[i] = (float)(p * (1.0 - p));
+                }
             }
         } else {
             double av[CBH_MAX_K];
@@ -175,8 +189,9 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs a) {
             const int yc = (int)y;
             for (int c = 0; c < K; ++c) {
                 const double p = exp(av[c] - mx) / z;
-                a.g[int64_t(c) * a.n + i] = (float)(p - (c == yc ? 1.0 : 0.0));
-                a.h[int64_t(c) * a.n + i] = (float)(p * (1.0 - p));
+                const double gc = p - (c == yc ? 1.0 : 0.0), hc = p * (1.0 - p);
+                a.g[int64_t(c) * a.n + i] = (float)(a.weight ? w * gc : gc);
+                a.h[int64_t(c) * a.n + i] = (float)(a.weight ? w * hc : hc);
             }
         }
     }
@@ -233,7 +248,7 @@ int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_las
         sa.F = p->n_features;
         sa.B = p->max_bins;
         sa.K = p->K;
-        sa.rmse = p->loss == CBH_LOSS_RMSE;
+        sa.rmse = count_stat(p);
         sa.precision = out_prec(precision);
         sa.l2 = l2;
         const int64_t work = leaves * p->K;
@@ -244,6 +259,7 @@ int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_las
     ua.leaf = p->leaf;
     ua.values = leaf_values;
     ua.label = p->label;
+    ua.weight = p->weight;
     ua.approx = p->approx;
     ua.g = p->g;
     ua.h = p->h;

@@ -589,6 +589,122 @@ def test_tree_graph_matches_eager(cb, prec, partition):
         graph.close()
 
 
+@pytest.mark.parametrize("prec", [gu.F64, gu.INT16, gu.FP32])
+def test_weighted_fold_matches_oracle_on_training_rows(cb, prec):
+    """A cross-validation fold as row weights over the shared rows (weight 0 on
+    the held-out rows): its gradients vanish on the held-out rows (RMSE h is
+    the weight), every level's histograms equal the oracle's over the
+    training rows alone (int16: bit for bit given the codes), the splits
+    follow the margin rule, the leaf values are the training rows' Newton
+    steps, and the held-out rows get their leaves' values (their predictions)."""
+    from oracle import boost
+    p = datagen.make_c2(n=20011, s=1)
+    p.depth = 5
+    q, w = datagen.cv_fold_weights(p, 5)
+    base = _booster(cb, q, prec, partition=False)
+    try:
+        j = 2
+        st = base.model_state(j, weight=w[j])
+        pr = st.prob
+        ctx, B, F, n, L2 = base.ctx, base.B, base.F, base.n, base.l2
+        train = w[j] > 0
+        cb.cbh_update_approx(ctx, pr, None, prec, None, 0.0, 0.0)
+        if prec == gu.INT16:
+            cb.cbh_quantize_gradients(ctx, pr)
+        torch.cuda.synchronize()
+        g = st.g.cpu().numpy().astype(np.float64)
+        h = st.h.cpu().numpy().astype(np.float64)
+        assert np.all(g[:, ~train] == 0) and np.all(h[:, ~train] == 0)
+        assert np.all(h[:, train] == 1)
+        bins = boost.prepare(q).tree_features(j)[0]
+        assert np.array_equal(base.bins_host(j), bins)
+        nb = base.nbins_table[j].cpu().numpy()
+        hist = torch.empty_like(base.hists[0])
+        best = torch.zeros((p.depth, 4), dtype=torch.int32, device=gu.dev())
+        leaf = np.zeros(n, np.uint16)
+        tb, tg, th = bins[:, train], g[:, train], h[:, train]
+        for lvl in range(p.depth):
+            L = 1 << lvl
+            cb.cbh_build_histograms(ctx, pr, lvl, prec, hist)
+            cb.cbh_score_splits(ctx, pr, lvl, hist, prec, L2, best[lvl])
+            cb.cbh_sync(ctx)
+            got = gu.hist_to_f64(hist, L, F, B, 1, prec, False)
+            if prec == gu.INT16:
+                rgq, rhq, sc = oracle.grad_codes(st.g.cpu().numpy(), st.h.cpu().numpy(), True)
+                want = oracle.histogram_int(tb, rgq[:, train], rhq[:, train], leaf[train], L, B)
+                assert np.array_equal(got, want), lvl
+                got = got.astype(np.float64) * np.array([sc[0, 0], sc[0, 1]])
+            else:
+                want = oracle.histogram(tb, tg, th, leaf[train], L, B)
+                mag = oracle.histogram(tb, np.abs(tg), th, leaf[train], L, B)
+                assert gu.normalized_err(got, want, mag) <= (gu.FP32_TOL if prec == 0
+                                                             else gu.TWOFLOAT_TOL), lvl
+            f, k = (int(v) for v in best[lvl, :2].cpu().numpy())
+            gu.check_split((f, k), oracle.score(got, nb, L2), nb)
+            cb.cbh_apply_split(ctx, pr, lvl, best[lvl])
+            if f >= 0:
+                oracle.apply_split(bins[f], k, lvl, leaf)
+        cb.cbh_update_approx(ctx, pr, hist, prec, best[p.depth - 1], q.lr, L2, st.leaf_values)
+        cb.cbh_sync(ctx)
+        assert np.array_equal(st.leaf.cpu().numpy(), leaf)
+        gd = tg if prec != gu.INT16 else None
+        if gd is not None:
+            rv, rG, rH, rc = oracle.leaf_values(leaf[train], tg, th, 1 << p.depth, L2)
+            gv = st.leaf_values.cpu().numpy()
+            magG = oracle.leaf_values(leaf[train], np.abs(tg), th, 1 << p.depth, L2)[1]
+            m = magG > 0
+            err = np.abs(gv - rv)[m] * (rH + L2)[m] / magG[m]
+            assert err.max() <= (gu.FP32_TOL if prec == 0 else 1e-9)
+        # every row, held-out ones too, moved by its leaf's value
+        a1 = np.zeros((1, n))
+        oracle.update_approx(a1, leaf, st.leaf_values.cpu().numpy(), q.lr)
+        assert np.array_equal(st.approx.cpu().numpy(), a1)
+        assert np.any(a1[0, ~train] != 0)
+    finally:
+        base.close()
+
+
+class _NoRecord:
+    def record(self, stream):
+        pass
+
+
+@pytest.mark.parametrize("prec,partition", [(2, False), (2, True), (3, True)])
+def test_fit_tree_call_matches_level_calls(cb, prec, partition):
+    """cbh_fit_tree (one call per tree) enqueues what the per-level calls
+    enqueue: the same trees, leaf values and approx, bit for bit."""
+    p = datagen.make_c2(n=30011, s=2)
+    p.depth = 5
+    one = _booster(cb, p, prec, partition=partition)
+    lev = _booster(cb, p, prec, partition=partition)
+    try:
+        one.init_gradients()
+        lev.init_gradients()
+        ev = [(_NoRecord(), _NoRecord()) for _ in range(p.depth)]
+        for t in range(4):
+            one.fit_tree(t)
+            lev.fit_tree(t, events=ev)
+            torch.cuda.synchronize()
+            a, b = one.tree_record(), lev.tree_record()
+            if prec == 2:
+                assert np.array_equal(a.splits, b.splits), t
+                assert np.array_equal(a.values, b.values), t
+                assert torch.equal(one.approx, lev.approx), t
+                continue
+            # float64 LDS sums may round differently run to run: the trees
+            # agree up to a near-tie, after which the runs may differ
+            diff = [l for l in range(p.depth) if not np.array_equal(a.splits[l], b.splits[l])]
+            if diff:
+                l = diff[0]
+                assert a.scores[l, 1] < gu.MARGIN_TOL * abs(a.scores[l, 0]), (t, l)
+                assert t > 0, "the first tree differs"
+                break
+            np.testing.assert_allclose(a.values, b.values, rtol=1e-9, atol=1e-12)
+    finally:
+        one.close()
+        lev.close()
+
+
 @pytest.mark.parametrize("prec,subtract", [(0, False), (2, True)])
 def test_autotune_roundtrip(cb, tmp_path, prec, subtract):
     p = datagen.make_c3(n=40000, F=16)
