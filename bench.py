@@ -598,9 +598,16 @@ def run_batch(args):
     lvs = [b.leaf_values for b in bsts]
     cb.cbh_batch_update(ctx, plan, lr, l2, lvs, True, side.cuda_stream)
     gr = cb.cbh_graph_capture_iteration(ctx, plan, lr, l2, lvs, side.cuda_stream)
+    # the same plan with every level as one persistent launch, for comparison
+    cb.cbh_batch_set_fused(plan, True)
+    gr_fused = cb.cbh_graph_capture_iteration(ctx, plan, lr, l2, lvs, side.cuda_stream)
+    cb.cbh_batch_set_fused(plan, False)
 
     def batch_iter():
         cb.cbh_graph_launch(gr, side.cuda_stream)
+
+    def batch_iter_fused():
+        cb.cbh_graph_launch(gr_fused, side.cuda_stream)
 
     def timed(fn, stream_obj):
         t_end = time.perf_counter() + args.warmup_s
@@ -618,6 +625,7 @@ def run_batch(args):
 
     with torch.cuda.stream(side):
         ms_batch = timed(batch_iter, side)
+        ms_fused = timed(batch_iter_fused, side)
         ms_seq = timed(seq_iter, side)
     cb.cbh_sync(ctx, side.cuda_stream)
     out = {
@@ -635,8 +643,12 @@ def run_batch(args):
                    "precision": args.precision, "problems": P, "rows": rows},
         "sequential_ms_per_iteration": round(ms_seq, 4),
         "batched_vs_sequential": round(ms_seq / ms_batch, 3),
+        "level_launches": "separate launches per level (cbh_batch_level, the default)",
+        "fused_launch_ms_per_iteration": round(ms_fused, 4),
+        "fused_vs_separate_launches": round(ms_batch / ms_fused, 3),
     }
     cb.cbh_graph_destroy(gr)
+    cb.cbh_graph_destroy(gr_fused)
     for g in graphs:
         cb.cbh_graph_destroy(g)
     cb.cbh_batch_destroy(plan)

@@ -622,8 +622,19 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P,
 void cbh_batch_destroy(cbh_batch* batch);
 
 /* One level of every problem of the plan: histograms, score, argmax and the
- * leaf update, with the split written to best[p][level]. The level runs as
- * five launches shared by all problems (histogram tiles of every problem from
+ * leaf update, with the split written to best[p][level].
+ * When cbh_batch_set_fused turned it on, every problem has one class and the
+ * level uses the lanes-over-features histogram (the default plan), the whole
+ * level is one launch of persistent blocks: the blocks claim
+ * work items in order, first (with subtraction) the row codes, then the
+ * histogram tiles of the work list dealt to the 8 XCDs (block b takes XCD
+ * b mod 8's share), then per problem the merges, the per-feature scores, the
+ * argmax and the leaf-bit updates; per-problem counters make each item wait
+ * for the items it reads (no grid-wide barrier: every awaited item was
+ * claimed earlier by a running block). A wait that does not end within a few
+ * seconds gives up and raises a device error that cbh_sync reports. The
+ * launch leaves its counters cleared, so it replays from a graph.
+ * Otherwise the level runs as five launches shared by all problems (histogram tiles of every problem from
  * one work list, partial merge, score of every (problem, feature), argmax per
  * problem, leaf-bit update over every row), plus, for a level >= 1 built by
  * subtraction, a first launch over every row that picks each parent's smaller
@@ -636,6 +647,14 @@ void cbh_batch_destroy(cbh_batch* batch);
  * splits). */
 int cbh_batch_level(cbh_ctx* ctx, cbh_batch* batch, int32_t level, double l2,
                     void* stream);
+/* Level launches of the plan: fused != 0 runs every level that allows it as
+ * the one persistent launch described at cbh_batch_level, 0 (the default) as
+ * the separate launches. Results are the same (bit for bit for int16). The
+ * persistent launch keeps one 1024-thread block per CU through the merge,
+ * score and update stages, which the separate launches run as many smaller
+ * blocks, so it only pays where a level's launches are short enough for the
+ * gaps between them to dominate. */
+int cbh_batch_set_fused(cbh_batch* batch, int32_t fused);
 /* A one-call form, level(ctx, probs, P, level, precision, l2, best_out,
  * stream), is cbh_batch_create once for the set of problems (it copies their
  * descriptors to the device and sizes the plan's workspace: the allocation a

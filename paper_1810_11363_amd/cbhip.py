@@ -34,7 +34,7 @@ EXPORTS = [
     "cbh_compute_ordered_ts", "cbh_quantize_gradients", "cbh_build_histograms",
     "cbh_build_histograms_sub", "cbh_apply_build_histograms_sub",
     "cbh_score_splits", "cbh_score_splits_noalloc", "cbh_apply_split", "cbh_update_approx", "cbh_batch_create",
-    "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update",
+    "cbh_batch_destroy", "cbh_batch_level", "cbh_batch_update", "cbh_batch_set_fused",
     "cbh_graph_capture_iteration", "cbh_graph_launch", "cbh_graph_destroy",
     "cbh_fit_tree", "cbh_graph_capture_tree",
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
@@ -110,6 +110,7 @@ def _load():
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
         "cbh_batch_level": ([vp, vp, i32, dbl, vp], C.c_int),
+        "cbh_batch_set_fused": ([vp, i32], C.c_int),
         "cbh_batch_update": ([vp, vp, dbl, dbl, vp, i32, vp], C.c_int),
         "cbh_graph_capture_iteration": ([vp, vp, dbl, dbl, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_launch": ([vp, vp], C.c_int),
@@ -381,6 +382,10 @@ def cbh_batch_update(ctx, batch, lr: float, l2: float, leaf_values, init: bool, 
     return _check(_lib.cbh_batch_update(ctx, batch, float(lr), float(l2),
                                         C.cast(lv, C.c_void_p), int(bool(init)),
                                         _stream(stream)))
+
+
+def cbh_batch_set_fused(batch, fused: bool):
+    return _check(_lib.cbh_batch_set_fused(batch, int(bool(fused))))
 
 
 def cbh_graph_capture_iteration(ctx, batch, lr: float, l2: float, leaf_values, stream=None):

@@ -119,9 +119,21 @@ struct LevelPlan {
     int32_t sub = 0;                   // built by subtraction (levels >= 1)
     int64_t rb_total = 0;              // row blocks of the side/code launch
     int64_t* d_rb_off = nullptr;       // per problem prefix of row blocks (P+1)
+    // the fused launch (kind 1): problem order of its merge, score, argmax
+    // and apply items, their prefixes in that order, tiles per problem, and
+    // the level's counters (bytes into the plan workspace)
+    int32_t* d_order = nullptr;
+    int32_t* d_hcount = nullptr;
+    int64_t* d_goff = nullptr;
+    int64_t* d_soff = nullptr;
+    int64_t* d_xoff = nullptr;
+    int64_t cnt_off = 0;
 };
 
 constexpr int64_t kSideRows = 16384;   // rows per block of the side/code launch
+// LDS the fused launch keeps out of the histogram tile (its own small
+// static arrays); the tile budget of a batched plan leaves this much free
+constexpr int kFusedStaticLds = 1024;
 
 }  // namespace cbh
 
@@ -138,6 +150,7 @@ struct cbh_batch {
     int64_t ws_need = 0;
     int64_t fbest_off = 0;
     int32_t sub = 0;                // levels >= 1 by subtraction
+    int32_t fused = 0;              // one launch per level where the level allows it
     void* ws = nullptr;             // plan-owned partial tiles, feature winners and,
                                     // with subtraction, the second histogram of
                                     // every problem, sides and row codes
@@ -342,6 +355,251 @@ __global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__
     }
 }
 
+// ------------------------------------------------ one fused launch per level
+// The whole level of every problem in one launch of persistent blocks, with
+// no grid-wide barrier. The blocks claim work items in order from queues:
+//   C  (subtraction only) per kSideRows rows of a problem: every parent's
+//      smaller child and the rows' slot codes (as bside_code_kernel); every
+//      block waits once for all of them before its histogram tiles;
+//   H  histogram tiles, from 8 queues holding the dealt work list's 8 XCD
+//      shares (block b takes queue b mod 8, the XCD it runs on);
+//   G  then, from one queue: merge items (kFusedMergeCells cells of a
+//      problem), score items (kFusedScoreFeatures features of a problem),
+//      argmax items (one problem) and apply items (kFusedApplyRows rows of a
+//      problem), the
+//      problems in the order their histogram tiles finish in the dealt list.
+// An item waits until every item it reads from is done: per-problem "done"
+// counters, raised by each item after its writes are published, gate the
+// stage that follows (a merge waits for its problem's H tiles, a score for
+// its merges, the argmax for its scores, an apply for its argmax). Every
+// item waited on was claimed earlier by a running block that
+// waits only on still earlier items, so the earliest unfinished item can
+// always run: the waits end. A wait is nonetheless bounded (it raises
+// FLAG_FUSED_WAIT, reported by cbh_sync, and gives up). The last block to
+// leave resets every counter for the next launch, so the launch replays from
+// a graph with no clearing.
+constexpr int kFusedMergeCells = 16384;
+constexpr int64_t kFusedApplyRows = 65536;
+constexpr int kFusedScoreFeatures = 8;    // features per score item
+// counters: [0] C head, [1..8] H heads, [9] G head, [10] blocks out,
+// [11] C items done, then 5 per problem (C, H, M, S, A done)
+constexpr int kFusedCounters = 16;
+
+struct FusedArgs {
+    const DevProb* probs;
+    const DevTile* tiles;
+    const LevelPlan::DevHP* plans;
+    const int64_t* cell_off;     // per problem prefix of merge cells (P+1)
+    const int64_t* feat_off;     // per problem prefix of features (P+1)
+    const int64_t* rb_off;       // per problem prefix of C items (P+1), or NULL
+    const int64_t* g_off;        // per queue position: prefix of merge items (P+1)
+    const int64_t* s_off;        // per queue position: prefix of score items (P+1), each
+                                 // kFusedScoreFeatures features
+    const int64_t* x_off;        // per queue position: prefix of apply items (P+1)
+    const int32_t* order;        // problem at each queue position
+    const int32_t* h_count;      // histogram tiles per problem
+    FeatBest* fbest;
+    cbh_split* best;
+    uint32_t* cnt;               // this level's counters
+    uint32_t* err;               // device error flags
+    int64_t n_tiles;             // a multiple of 8
+    int64_t rb_total;
+    int32_t P, L, slots, depth, level;
+    double l2;
+};
+
+template <int PREC, int RM, int W, int MODE>
+__global__ __launch_bounds__(kHistThreads) void bfused_kernel(FusedArgs a) {
+    constexpr int OP = out_prec(PREC);
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ int64_t s_item;
+    const int P = a.P;
+    uint32_t* done = a.cnt + kFusedCounters;            // [5][P]: C, H, M, S, A
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    auto claim = [&](uint32_t* head) -> int64_t {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(head, 1u);
+        __syncthreads();
+        return s_item;
+    };
+    // One thread polls (relaxed, coherent at device scope) and then takes one
+    // acquire fence for the block; the barrier orders the other waves' reads
+    // after it. A signal: the barrier completes every wave's stores to L2,
+    // then one release fence and the count.
+    auto wait_for = [&](uint32_t* c, uint32_t target) {
+        if (threadIdx.x == 0) {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(4);
+                if (++spins == (1u << 24)) {
+                    atomicOr(a.err, FLAG_FUSED_WAIT);
+                    break;
+                }
+            }
+            __threadfence();
+        }
+        __syncthreads();
+    };
+    auto signal = [&](uint32_t* c) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(c, 1u);
+        }
+    };
+    // ---- C: sides and row codes (levels >= 1 by subtraction)
+    if (a.rb_total > 0) {
+        const int64_t half = int64_t(1) << (a.level - 1);
+        for (;;) {
+            const int64_t i = claim(a.cnt + 0);
+            if (i >= a.rb_total) break;
+            const int p = find_owner(a.rb_off, P, i);
+            const DevProb pr = a.probs[p];
+            const int64_t rb = i - a.rb_off[p];
+            const cbh_split sp = a.best[int64_t(p) * a.depth + a.level - 1];
+            uint8_t* sd = reinterpret_cast<uint8_t*>(lds);
+            for (int64_t q = wave; q < half; q += nwaves) {
+                const uint8_t v = parent_side<OP>(pr.parent, q, sp.feature, sp.border, pr.F,
+                                                  pr.B, pr.K, pr.rmse, lane);
+                if (lane == 0) {
+                    sd[q] = v;
+                    if (rb == 0) pr.side[q] = v;
+                }
+            }
+            __syncthreads();
+            const uint32_t lmask = (uint32_t)half - 1u, shift = (uint32_t)(a.level - 1);
+            const int64_t i0 = rb * kSideRows, i1 = min(pr.n, i0 + kSideRows);
+            for (int64_t r = i0 + threadIdx.x; r < i1; r += blockDim.x) {
+                const uint32_t v = gld_u16(pr.leaf + r);
+                const uint32_t pp = v & lmask;
+                pr.codes[r] =
+                    (uint16_t)((((v >> shift) & 1u) == (uint32_t)sd[pp]) ? pp : 0xffffu);
+            }
+            signal(a.cnt + 11);
+        }
+        // every block claims C items before any H tile, so waiting once for
+        // all of them costs one fence per block, not one per tile
+        wait_for(a.cnt + 11, (uint32_t)a.rb_total);
+    }
+    // ---- H: histogram tiles of this block's XCD share
+    {
+        const int x = blockIdx.x & 7;
+        const int64_t per = a.n_tiles / 8;
+        for (;;) {
+            const int64_t j = claim(a.cnt + 1 + x);
+            if (j >= per) break;
+            const DevTile tile = a.tiles[x * per + j];
+            if (tile.prob < 0) continue;
+            const int p = tile.prob;
+            const DevProb pr = a.probs[p];
+            const LevelPlan::DevHP hp = a.plans[p];
+            LpfBlock b;
+            b.bins = pr.bins;
+            b.seg = pr.seg;
+            b.g = pr.g;
+            b.h = pr.h;
+            b.gq = pr.gq;
+            b.rowcode = pr.rowcode;
+            b.F = pr.F;
+            b.B = pr.B;
+            b.wpc = hp.wpc;
+            b.coff = 0;
+            const int64_t r0 = int64_t(tile.chunk) * hp.rows_per_chunk;
+            const uint32_t s0 = (uint32_t)tile.lt_i * (uint32_t)hp.lt;
+            __syncthreads();
+            lpf_block<PREC, RM, W, MODE>(
+                b, r0, min(pr.n, r0 + hp.rows_per_chunk), tile.fg, s0,
+                min((uint32_t)hp.lt, (uint32_t)a.slots - s0),
+                pr.partials + int64_t(tile.chunk) * (int64_t(a.slots) * pr.F * pr.B * hp.wpc),
+                0u, lds);
+            signal(done + P + p);
+        }
+    }
+    // ---- G: merges, scores, argmax and leaf bits, problem by problem
+    const int64_t nM = a.g_off[P], nS = a.s_off[P], nX = a.x_off[P];
+    const int64_t total = nM + nS + P + nX;
+    for (;;) {
+        const int64_t i = claim(a.cnt + 9);
+        if (i >= total) break;
+        if (i < nM) {
+            const int k = find_owner(a.g_off, P, i);
+            const int p = a.order[k];
+            wait_for(done + P + p, (uint32_t)a.h_count[p]);
+            const DevProb pr = a.probs[p];
+            const int64_t cells = a.cell_off[p + 1] - a.cell_off[p];
+            const int64_t c0 = (i - a.g_off[k]) * kFusedMergeCells;
+            const int64_t c1 = min(cells, c0 + kFusedMergeCells);
+            for (int64_t cell = c0 + threadIdx.x; cell < c1; cell += blockDim.x) {
+                const int nch = a.plans[p].n_chunks;
+                if (pr.parent) {
+                    const int64_t fbc = int64_t(pr.F) * pr.B;
+                    const int64_t half = cells / fbc;
+                    const int64_t par = cell / fbc, rest = cell % fbc;
+                    const int64_t sd = pr.side[par];
+                    merge_cell<OP>(pr.partials, cells, pr.K, nch, pr.rmse != 0, pr.hist, cell,
+                                   (par + sd * half) * fbc + rest,
+                                   (par + (1 - sd) * half) * fbc + rest, pr.parent);
+                } else {
+                    merge_cell<OP>(pr.partials, cells, pr.K, nch, pr.rmse != 0, pr.hist, cell,
+                                   cell);
+                }
+            }
+            signal(done + 2 * P + p);
+        } else if (i < nM + nS) {
+            const int64_t si = i - nM;
+            const int k = find_owner(a.s_off, P, si);
+            const int p = a.order[k];
+            wait_for(done + 2 * P + p, (uint32_t)(a.g_off[k + 1] - a.g_off[k]));
+            const DevProb pr = a.probs[p];
+            ScoreRow r;
+            r.hist = pr.hist;
+            r.grad_scale = pr.grad_scale;
+            r.F = pr.F;
+            r.B = pr.B;
+            r.K = pr.K;
+            r.rmse = pr.rmse;
+            r.l2 = a.l2;
+            const int f0 = (int)(si - a.s_off[k]) * kFusedScoreFeatures;
+            const int f1 = min(pr.F, f0 + kFusedScoreFeatures);
+            for (int f = f0; f < f1; ++f) {
+                __syncthreads();
+                score_feature_in<OP, 16>(r, a.L, f, pr.n_bins[f], nullptr,
+                                         &a.fbest[a.feat_off[p] + f],
+                                         reinterpret_cast<ScoreLds<16>*>(lds));
+            }
+            signal(done + 3 * P + p);
+        } else if (i < nM + nS + P) {
+            const int k = (int)(i - nM - nS);
+            const int p = a.order[k];
+            wait_for(done + 3 * P + p, (uint32_t)(a.s_off[k + 1] - a.s_off[k]));
+            argmax_features(a.fbest + a.feat_off[p], a.probs[p].F, a.probs[p].B - 1,
+                            &a.best[int64_t(p) * a.depth + a.level]);
+            signal(done + 4 * P + p);
+        } else {
+            const int64_t xi = i - nM - nS - P;
+            const int k = find_owner(a.x_off, P, xi);
+            const int p = a.order[k];
+            wait_for(done + 4 * P + p, 1u);
+            const DevProb pr = a.probs[p];
+            const cbh_split sp = a.best[int64_t(p) * a.depth + a.level];
+            const int64_t x0 = (xi - a.x_off[k]) * kFusedApplyRows;
+            const int64_t x1 = min(pr.n, x0 + kFusedApplyRows);
+            for (int64_t i0 = x0 + int64_t(threadIdx.x) * 8; i0 < x1; i0 += int64_t(blockDim.x) * 8)
+                apply_rows(pr.bins, pr.seg, pr.F, sp, pr.leaf, i0, min(x1, i0 + 8), a.level);
+        }
+    }
+    // the last block out resets the counters for the next launch
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(a.cnt + 10, 1u) == gridDim.x - 1) {
+            for (int k = 0; k < kFusedCounters + 5 * P; ++k) a.cnt[k] = 0u;
+            __threadfence();
+        }
+    }
+}
+
 void batch_init_attrs(int max_lds) {
     const void* fns[] = {
         (const void*)bhist_kernel<CBH_PREC_FP32, 0>, (const void*)bhist_kernel<CBH_PREC_FP32, 1>,
@@ -370,6 +628,26 @@ void batch_init_attrs(int max_lds) {
     CBH_BLPF_ATTR3(CBH_PREC_F64, 1)
 #undef CBH_BLPF_ATTR3
 #undef CBH_BLPF_ATTR
+#define CBH_FUSED_ATTR(P, R, M)                                                              \
+    {                                                                                        \
+        const void* l[] = {(const void*)bfused_kernel<P, R, 32, M>,                          \
+                           (const void*)bfused_kernel<P, R, 16, M>,                          \
+                           (const void*)bfused_kernel<P, R, 8, M>,                           \
+                           (const void*)bfused_kernel<P, R, 4, M>};                          \
+        for (const void* f : l)                                                              \
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,          \
+                                      max_lds - kFusedStaticLds);                            \
+    }
+#define CBH_FUSED_ATTR3(P, R) CBH_FUSED_ATTR(P, R, 0) CBH_FUSED_ATTR(P, R, 1) CBH_FUSED_ATTR(P, R, 2)
+    CBH_FUSED_ATTR3(CBH_PREC_FP32, 0)
+    CBH_FUSED_ATTR3(CBH_PREC_FP32, 1)
+    CBH_FUSED_ATTR3(CBH_PREC_TWOFLOAT, 0)
+    CBH_FUSED_ATTR3(CBH_PREC_TWOFLOAT, 1)
+    CBH_FUSED_ATTR3(CBH_PREC_INT16, 0)
+    CBH_FUSED_ATTR3(CBH_PREC_F64, 0)
+    CBH_FUSED_ATTR3(CBH_PREC_F64, 1)
+#undef CBH_FUSED_ATTR3
+#undef CBH_FUSED_ATTR
 }
 
 template <int PREC, int RM, int MODE>
@@ -391,9 +669,84 @@ static void launch_blpf(const cbh_batch* b, const LevelPlan& lp, int L, dim3 grd
     else launch_blpf_mode<PREC, RM, 2>(b, lp, L, grd, lds, s);
 }
 
+template <int PREC, int RM, int MODE>
+static void launch_fused_mode(const FusedArgs& fa, int W, dim3 grd, size_t lds, hipStream_t s) {
+    switch (W) {
+        case 32: bfused_kernel<PREC, RM, 32, MODE><<<grd, kHistThreads, lds, s>>>(fa); break;
+        case 16: bfused_kernel<PREC, RM, 16, MODE><<<grd, kHistThreads, lds, s>>>(fa); break;
+        case 8: bfused_kernel<PREC, RM, 8, MODE><<<grd, kHistThreads, lds, s>>>(fa); break;
+        default: bfused_kernel<PREC, RM, 4, MODE><<<grd, kHistThreads, lds, s>>>(fa); break;
+    }
+}
+
+template <int PREC, int RM>
+static void launch_fused(const FusedArgs& fa, const LevelPlan& lp, dim3 grd, size_t lds,
+                         hipStream_t s) {
+    if (lp.mode == 0) launch_fused_mode<PREC, RM, 0>(fa, lp.W, grd, lds, s);
+    else if (lp.mode == 1) launch_fused_mode<PREC, RM, 1>(fa, lp.W, grd, lds, s);
+    else launch_fused_mode<PREC, RM, 2>(fa, lp.W, grd, lds, s);
+}
+
+// The level as one persistent launch (bfused_kernel): as many blocks as the
+// chip holds at once, a multiple of 8 (the XCD queues).
+static int batch_level_fused(cbh_batch* b, int32_t level, double l2, hipStream_t s) {
+    cbh_ctx* ctx = b->ctx;
+    LevelPlan& lp = b->levels[level];
+    const int L = 1 << level;
+    FusedArgs fa;
+    fa.probs = b->d_probs;
+    fa.tiles = lp.d_tiles;
+    fa.plans = lp.d_plans;
+    fa.cell_off = lp.d_cell_off;
+    fa.feat_off = lp.d_feat_off;
+    fa.rb_off = lp.sub ? lp.d_rb_off : nullptr;
+    fa.g_off = lp.d_goff;
+    fa.s_off = lp.d_soff;
+    fa.x_off = lp.d_xoff;
+    fa.order = lp.d_order;
+    fa.h_count = lp.d_hcount;
+    fa.fbest = (FeatBest*)((char*)b->ws + b->fbest_off);
+    fa.best = b->best;
+    fa.cnt = (uint32_t*)((char*)b->ws + lp.cnt_off);
+    fa.err = ctx->d_flags;
+    fa.n_tiles = lp.n_tiles;
+    fa.rb_total = lp.sub ? lp.rb_total : 0;
+    fa.P = b->P;
+    fa.L = L;
+    fa.slots = lp.sub ? L / 2 : L;
+    fa.depth = b->depth;
+    fa.level = level;
+    fa.l2 = l2;
+    const int64_t lds = std::max<int64_t>({lp.max_lds, (int64_t)sizeof(ScoreLds<16>),
+                                           int64_t(L / 2)});
+    const int per_cu = lds + kFusedStaticLds <= ctx->max_lds / 2 ? 2 : 1;
+    const dim3 grd((unsigned)(8 * ((int64_t(ctx->num_cus) * per_cu + 7) / 8)));
+    const bool rm = count_stat(&b->probs[0]);
+    switch (b->precision) {
+        case CBH_PREC_FP32:
+            if (rm) launch_fused<CBH_PREC_FP32, 1>(fa, lp, grd, (size_t)lds, s);
+            else launch_fused<CBH_PREC_FP32, 0>(fa, lp, grd, (size_t)lds, s);
+            break;
+        case CBH_PREC_TWOFLOAT:
+            if (rm) launch_fused<CBH_PREC_TWOFLOAT, 1>(fa, lp, grd, (size_t)lds, s);
+            else launch_fused<CBH_PREC_TWOFLOAT, 0>(fa, lp, grd, (size_t)lds, s);
+            break;
+        case CBH_PREC_F64:
+            if (rm) launch_fused<CBH_PREC_F64, 1>(fa, lp, grd, (size_t)lds, s);
+            else launch_fused<CBH_PREC_F64, 0>(fa, lp, grd, (size_t)lds, s);
+            break;
+        default:
+            launch_fused<CBH_PREC_INT16, 0>(fa, lp, grd, (size_t)lds, s);
+            break;
+    }
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
 static int batch_level_launch(cbh_batch* b, int32_t level, double l2, hipStream_t s) {
     cbh_ctx* ctx = b->ctx;
     LevelPlan& lp = b->levels[level];
+    if (b->fused && lp.kind == 1) return batch_level_fused(b, level, l2, s);
     const int L = 1 << level;
     const int slots = lp.sub ? L / 2 : L;      // histogram slots: parents or leaves
     const int64_t grid = 8 * ((lp.n_tiles + 7) / 8);
@@ -504,6 +857,9 @@ static void free_levels(cbh_batch* b) {
         if (lp.d_feat_off) (void)hipFree(lp.d_feat_off);
         if (lp.d_row_off) (void)hipFree(lp.d_row_off);
         if (lp.d_rb_off) (void)hipFree(lp.d_rb_off);
+        for (void* q : {(void*)lp.d_order, (void*)lp.d_hcount, (void*)lp.d_goff,
+                        (void*)lp.d_soff, (void*)lp.d_xoff})
+            if (q) (void)hipFree(q);
     }
     b->levels.clear();
 }
@@ -575,7 +931,7 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
                 64, (int32_t)(int64_t(kn.target_blocks) * 1 / std::max(1, std::min(P, 8))));
             // the lanes-over-features tile needs no replicas: give it the whole
             // LDS, as the autotuner does (unless the knobs are forced)
-            if (kb.kernel == 1 && !ctx->force_knobs) kb.lds_budget = ctx->max_lds;
+            if (kb.kernel == 1 && !ctx->force_knobs) kb.lds_budget = ctx->max_lds - kFusedStaticLds;
             return kb;
         };
         // One histogram kernel serves the whole level: lanes over features
@@ -637,6 +993,28 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         max_part = std::max(max_part, off);
         deal_tiles(groups, tiles);
         lp.n_tiles = (int64_t)tiles.size();
+        // fused launch: problems ordered by where their last tile sits in
+        // the XCD shares (the earliest finished first), item prefixes in that order
+        std::vector<int32_t> order(P), hcount(P, 0);
+        std::vector<int64_t> last(P, -1), goff{0}, soff{0}, xoff{0};
+        const int64_t per_x = lp.n_tiles / 8;
+        for (int64_t ti = 0; ti < lp.n_tiles; ++ti) {
+            const DevTile& t = tiles[ti];
+            if (t.prob < 0) continue;
+            ++hcount[t.prob];
+            last[t.prob] = std::max(last[t.prob], per_x ? ti % per_x : ti);
+        }
+        for (int p = 0; p < P; ++p) order[p] = p;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return last[x] < last[y]; });
+        for (int k = 0; k < P; ++k) {
+            const int p = order[k];
+            const int64_t cells = cell_off[p + 1] - cell_off[p];
+            goff.push_back(goff.back() + (cells + kFusedMergeCells - 1) / kFusedMergeCells);
+            soff.push_back(soff.back() +
+                           (probs[p].n_features + kFusedScoreFeatures - 1) / kFusedScoreFeatures);
+            xoff.push_back(xoff.back() + (probs[p].n + kFusedApplyRows - 1) / kFusedApplyRows);
+        }
         lp.cells_total = cell_off.back();
         lp.score_total = feat_off.back();
         lp.rows_total = row_off.back();
@@ -647,6 +1025,11 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         if (!rc) rc = upload(&lp.d_feat_off, feat_off);
         if (!rc) rc = upload(&lp.d_row_off, row_off);
         if (!rc && lp.sub) rc = upload(&lp.d_rb_off, rb_off);
+        if (!rc && lp.kind == 1) rc = upload(&lp.d_order, order);
+        if (!rc && lp.kind == 1) rc = upload(&lp.d_hcount, hcount);
+        if (!rc && lp.kind == 1) rc = upload(&lp.d_goff, goff);
+        if (!rc && lp.kind == 1) rc = upload(&lp.d_soff, soff);
+        if (!rc && lp.kind == 1) rc = upload(&lp.d_xoff, xoff);
         b->levels.push_back(lp);
         if (rc) {
             free_levels(b);
@@ -656,6 +1039,11 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
     }
     b->fbest_off = align_up(max_part, 256);
     b->ws_need = b->fbest_off + align_up(tot_feat * (int64_t)sizeof(FeatBest), 256);
+    // counters of the fused launches, one set per level
+    const int64_t cnt_bytes = align_up(int64_t(kFusedCounters + 5 * P) * 4, 256);
+    const int64_t cnt_base = b->ws_need;
+    for (int lvl = 0; lvl < b->depth; ++lvl) b->levels[lvl].cnt_off = cnt_base + lvl * cnt_bytes;
+    b->ws_need += b->depth * cnt_bytes;
     // subtraction: level l writes hist[p] if depth-1-l is even, else the
     // second buffer, which therefore holds at most level depth-2
     std::vector<int64_t> hist2_off(P, 0), side_off(P, 0), code_off(P, 0);
@@ -686,6 +1074,13 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
         (void)hipGetLastError();
         set_error("batch workspace allocation of %lld bytes failed", (long long)b->ws_need);
         rc = CBH_ENOMEM;
+    }
+    // the fused launches' counters start at zero (each launch leaves them so)
+    if (!rc && hipMemset((char*)b->ws + cnt_base, 0, (size_t)(b->depth * cnt_bytes)) !=
+                   hipSuccess) {
+        (void)hipGetLastError();
+        set_error("clearing the batch counters failed");
+        rc = CBH_EDEVICE;
     }
     if (rc) {
         free_levels(b);
@@ -754,6 +1149,13 @@ int cbh_batch_level(cbh_ctx* ctx, cbh_batch* b, int32_t level, double l2, void* 
     const int rc = batch_level_launch(b, level, l2, (hipStream_t)stream);
     b->d_probs = const_cast<DevProb*>(saved);
     return rc;
+}
+
+int cbh_batch_set_fused(cbh_batch* b, int32_t fused) {
+    clear_error();
+    CBH_ARG(b != nullptr, "batch is NULL");
+    b->fused = fused != 0;
+    return CBH_OK;
 }
 
 int cbh_batch_update(cbh_ctx* ctx, cbh_batch* b, double lr, double l2, double* const* leaf_values,

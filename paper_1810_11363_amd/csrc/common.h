@@ -54,6 +54,7 @@ enum : uint32_t {
     FLAG_NAN_INPUT = 1u,
     FLAG_BAD_INDEX = 2u,
     FLAG_BAD_SPLIT = 4u,
+    FLAG_FUSED_WAIT = 8u,
 };
 
 // ------------------------------------------------------- launch geometry

@@ -205,6 +205,8 @@ int cbh_sync(cbh_ctx* ctx, void* stream) {
         if (flags & FLAG_NAN_INPUT) msg += " NaN feature value (binned as 0);";
         if (flags & FLAG_BAD_INDEX) msg += " permutation entry outside [0, n);";
         if (flags & FLAG_BAD_SPLIT) msg += " model split feature outside [0, F) (bit taken as 0);";
+        if (flags & FLAG_FUSED_WAIT)
+            msg += " a fused batched level gave up waiting for an earlier stage (results invalid);";
         set_error("%s", msg.c_str());
         return CBH_EDEVICE;
     }

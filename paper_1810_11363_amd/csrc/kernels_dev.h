@@ -802,16 +802,27 @@ __device__ void row_terms(const ScoreRow& a, int L, int f, int c, int lane, int 
     }
 }
 
+// LDS of score_feature: per-wave partial scores and per-wave winners.
+template <int NW>
+struct ScoreLds {
+    double part[NW][256];
+    float rs1[NW], rs2[NW];
+    int ri1[NW];
+};
+
 // Whole-block scoring of feature f over all leaves and classes; writes the
 // per-border scores (optional) and the feature's best/second-best. Needs a
 // block of 64 NW threads (NW >= 4); wave w takes the (leaf, class) rows
 // w, w + NW, ..., and the waves' partial scores are added in wave order.
-template <int PREC, int NW = 4>
-__device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, float* scores,
-                              FeatBest* out) {
-    __shared__ double part[NW][256];
-    __shared__ float rs1[NW], rs2[NW];
-    __shared__ int ri1[NW];
+// `sh`: the block's LDS for it (a kernel whose dynamic LDS serves other work
+// passes a part of it).
+template <int PREC, int NW>
+__device__ void score_feature_in(const ScoreRow& a, int L, int f, int n_bins_f, float* scores,
+                                 FeatBest* out, ScoreLds<NW>* sh) {
+    double (&part)[NW][256] = sh->part;
+    float (&rs1)[NW] = sh->rs1;
+    float (&rs2)[NW] = sh->rs2;
+    int (&ri1)[NW] = sh->ri1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kmax = min(n_bins_f, a.B) - 1;  // candidates k < kmax
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -854,6 +865,13 @@ __device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, flo
         for (int w = 1; w < 4; ++w) top2_merge(b1, j, b2, rs1[w], ri1[w], rs2[w]);
         *out = FeatBest{b1, j, b2, 0};
     }
+}
+
+template <int PREC, int NW = 4>
+__device__ void score_feature(const ScoreRow& a, int L, int f, int n_bins_f, float* scores,
+                              FeatBest* out) {
+    __shared__ ScoreLds<NW> sh;
+    score_feature_in<PREC, NW>(a, L, f, n_bins_f, scores, out, &sh);
 }
 
 // Reduce F per-feature winners (one block, its first 256 threads) to the

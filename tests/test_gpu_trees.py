@@ -451,6 +451,68 @@ def test_batched_lockstep_oracle_c4(cb, prec, subtract):
             b.close()
 
 
+@pytest.mark.parametrize("prec,subtract", [(2, True), (2, False), (3, True), (0, False)])
+def test_fused_level_matches_separate_launches(cb, prec, subtract):
+    """The one-launch level (persistent blocks with per-problem counters) and
+    the separate launches of the same plan give the same splits, leaf indices
+    and approx: bit for bit for int16; for the float forms (LDS sums that may
+    round differently run to run) the same splits up to a near-tie, and
+    approx within rounding. Several iterations, so the launch's self-clearing
+    counters are exercised across launches."""
+    probs = datagen.make_c4(P=7, scale=0.01)
+    fused = _batch_setup(cb, probs, prec)
+    sep = _batch_setup(cb, probs, prec)
+    P, depth = len(probs), probs[0].depth
+    ctx_f, ctx_s = fused[0].ctx, sep[0].ctx
+    best_f = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    best_s = torch.zeros((P, depth, 4), dtype=torch.int32, device=gu.dev())
+    plan_f = cb.cbh_batch_create(ctx_f, [b.probs[0] for b in fused], prec,
+                                 [b.hist for b in fused], best_f, subtract=subtract)
+    plan_s = cb.cbh_batch_create(ctx_s, [b.probs[0] for b in sep], prec, [b.hist for b in sep],
+                                 best_s, subtract=subtract)
+    cb.cbh_batch_set_fused(plan_f, True)
+    cb.cbh_batch_set_fused(plan_s, False)
+    try:
+        cb.cbh_batch_update(ctx_f, plan_f, 0.1, 3.0, [b.leaf_values for b in fused], True)
+        cb.cbh_batch_update(ctx_s, plan_s, 0.1, 3.0, [b.leaf_values for b in sep], True)
+        diverged = set()
+        for it in range(4):
+            for bs, c in ((fused, ctx_f), (sep, ctx_s)):
+                if prec == 2:
+                    for b in bs:
+                        cb.cbh_quantize_gradients(c, b.probs[0])
+            for lvl in range(depth):
+                cb.cbh_batch_level(ctx_f, plan_f, lvl, 3.0)
+                cb.cbh_batch_level(ctx_s, plan_s, lvl, 3.0)
+            cb.cbh_batch_update(ctx_f, plan_f, 0.1, 3.0, [b.leaf_values for b in fused], False)
+            cb.cbh_batch_update(ctx_s, plan_s, 0.1, 3.0, [b.leaf_values for b in sep], False)
+            cb.cbh_sync(ctx_f)
+            cb.cbh_sync(ctx_s)
+            for i, (f, s) in enumerate(zip(fused, sep)):
+                if prec == 2:
+                    assert torch.equal(best_f[i, :, :2], best_s[i, :, :2]), (it, i)
+                    assert torch.equal(f.leaf, s.leaf), (it, i)
+                    assert torch.equal(f.approx, s.approx), (it, i)
+                    continue
+                if i in diverged:
+                    continue
+                bf, bsp = best_f[i].cpu().numpy(), best_s[i].cpu().numpy()
+                sc = bsp[:, 2:].view(np.float32)
+                for lvl in range(depth):
+                    if not np.array_equal(bf[lvl, :2], bsp[lvl, :2]):
+                        assert sc[lvl, 1] < gu.MARGIN_TOL * abs(sc[lvl, 0]), (it, i, lvl)
+                        diverged.add(i)
+                        break
+                if i not in diverged:
+                    torch.testing.assert_close(f.approx, s.approx, rtol=1e-5, atol=1e-6)
+        assert len(diverged) < P
+    finally:
+        cb.cbh_batch_destroy(plan_f)
+        cb.cbh_batch_destroy(plan_s)
+        for b in fused + sep:
+            b.close()
+
+
 def test_permutation_models_batched_match_boosters(cb):
     """Models over the permutations of one booster's bins (ModelState), trained
     together by the batched calls, grow the same trees as boosters that are
@@ -493,7 +555,11 @@ def test_permutation_models_batched_match_boosters(cb):
             b.close()
 
 
-def test_graph_replay_matches_eager(cb):
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_replay_matches_eager(cb, fused):
+    """A captured iteration replayed four times (the persistent one-launch
+    levels too, whose counters must come back cleared) against eager
+    separate launches: int16, so bit for bit."""
     probs = datagen.make_c4(P=3, scale=0.005)
     for p in probs:
         p.depth = 4
@@ -507,6 +573,7 @@ def test_graph_replay_matches_eager(cb):
                                  [b.hist for b in eager], best_e)
     plan_g = cb.cbh_batch_create(ctx, [b.probs[0] for b in graph], 2, [b.hist for b in graph],
                                  best_g)
+    cb.cbh_batch_set_fused(plan_g, fused)
     stream = torch.cuda.Stream()
     try:
         cb.cbh_batch_update(eager[0].ctx, plan_e, 0.1, 3.0, [b.leaf_values for b in eager], True)
