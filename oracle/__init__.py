@@ -51,6 +51,12 @@ def _declare(L):
     L.orc_grad_codes.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp]
     L.orc_histogram_int.argtypes = [i64, i32, vp, i32, i32, vp, vp, vp, i32, vp]
     L.orc_apply_model.argtypes = [i64, i32, vp, i32, i32, i32, vp, vp, vp, dbl, vp]
+    L.orc_ordered_models.argtypes = [i64]
+    L.orc_ordered_models.restype = i32
+    L.orc_ordered_offset.argtypes = [i64, i32]
+    L.orc_ordered_offset.restype = i64
+    L.orc_ordered_gradients.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp]
+    L.orc_ordered_update.argtypes = [i32, i32, i64, vp, vp, vp, i32, dbl, dbl, vp, vp]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [i32]
 
@@ -250,3 +256,47 @@ def histogram_int(bins, gq, hq, leaf, n_leaves: int, B: int):
     out = np.empty((n_leaves, F, B, 2 * K), np.int64)
     lib().orc_histogram_int(n, F, _p(bins), B, K, _p(gq), _p(hq), _p(leaf), n_leaves, _p(out))
     return out
+
+
+def ordered_models(n: int) -> int:
+    """Number M of supporting approximations ordered boosting keeps for n
+    positions (Sec. 3): model m learns from the first 2^(m-1) positions
+    (none for m = 0) and is kept for the first min(n, 2^m)."""
+    return int(lib().orc_ordered_models(int(n)))
+
+
+def ordered_offsets(n: int) -> np.ndarray:
+    """off[m] for m = 0..M: where model m's values start in a support row of
+    S = off[M] doubles (position order)."""
+    M = ordered_models(n)
+    return np.array([lib().orc_ordered_offset(int(n), m) for m in range(M + 1)], np.int64)
+
+
+def ordered_gradients(loss: int, K: int, perm, label, support):
+    """(g, h) float64 [K][n] in row order: row perm[p] at the model that
+    position p reads."""
+    perm = _c(perm, np.int32)
+    label = _c(label, np.float32)
+    n = perm.size
+    support = _c(support, np.float64).reshape(K, -1)
+    g = np.empty((K, n), np.float64)
+    h = np.empty((K, n), np.float64)
+    lib().orc_ordered_gradients(loss, K, n, _p(perm), _p(label), _p(support), _p(g), _p(h))
+    return g, h
+
+
+def ordered_update(loss: int, K: int, perm, label, leaf, n_leaves: int, lr: float,
+                   l2: float, support):
+    """In place on support [K][S] (float64, C order): every supporting model
+    takes its own leaf values for the tree whose row leaves are given and adds
+    them to its kept positions. Returns the values [M][n_leaves][K]."""
+    perm = _c(perm, np.int32)
+    label = _c(label, np.float32)
+    leaf = _c(leaf, np.uint16)
+    n = perm.size
+    assert support.dtype == np.float64 and support.flags.c_contiguous
+    M = ordered_models(n)
+    vals = np.empty((M, n_leaves, K), np.float64)
+    lib().orc_ordered_update(loss, K, n, _p(perm), _p(label), _p(leaf), int(n_leaves),
+                             float(lr), float(l2), _p(support), _p(vals))
+    return vals

@@ -333,6 +333,113 @@ void orc_update_approx(int64_t n, int32_t K, const uint16_t* leaf,
             approx[(int64_t)c * n + i] += lr * values[(int64_t)leaf[i] * K + c];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Ordered boosting's supporting approximations (Sec. 3). Algorithm 1 keeps,
+ * for one permutation, a model per position that never learns from that
+ * position; the O(s n) relaxation keeps about log2(n) of them instead: model
+ * i learns from the first 2^i positions, is maintained for the first
+ * 2^(i+1), and a position's gradient for choosing the next tree structure is
+ * taken at the model indexed by the floor of log2 of the position. All
+ * models share the tree structures (the leaf of every row comes from the
+ * tree built on those gradients); each model takes its own leaf values.
+ * Reading, with 0-based positions p = 0..n-1 (perm[p] = row at position p):
+ *   model m = 0..M-1 learns from the positions below T_m (T_0 = 0,
+ *   T_m = 2^(m-1)) and is kept for the positions below min(n, 2^m);
+ *   position p reads model m(p) = 0 for p = 0 and floor(log2 p) + 1
+ *   otherwise, so T_m(p) <= p: the model a position reads never saw it;
+ *   M = 1 for n = 1, else floor(log2(n-1)) + 2 (the model position n-1 reads
+ *   is the last one).
+ * Model m's leaf values are the Newton steps -G/(H+l2) of its own gradients
+ * summed over its learning positions per leaf; every kept position then
+ * gains lr * value of its leaf. support is [K][S] with model m at offset
+ * off_m = sum over m' < m of min(n, 2^m'), in position order; S = off_M,
+ * which is below 4n.                                                        */
+int32_t orc_ordered_models(int64_t n) {
+    if (n <= 1) return 1;
+    int32_t fl = 0;
+    while (((int64_t)1 << (fl + 1)) <= n - 1) ++fl;   /* floor(log2(n-1)) */
+    return fl + 2;
+}
+
+static int64_t ord_keep(int64_t n, int32_t m) {
+    int64_t c = (int64_t)1 << m;
+    return c < n ? c : n;
+}
+
+static int64_t ord_learn(int32_t m) { return m == 0 ? 0 : (int64_t)1 << (m - 1); }
+
+int64_t orc_ordered_offset(int64_t n, int32_t m) {
+    int64_t off = 0;
+    for (int32_t j = 0; j < m; ++j) off += ord_keep(n, j);
+    return off;
+}
+
+static int32_t ord_model_of(int64_t p) {
+    if (p == 0) return 0;
+    int32_t fl = 0;
+    while (((int64_t)1 << (fl + 1)) <= p) ++fl;          /* floor(log2 p) */
+    return fl + 1;
+}
+
+/* Gradients for choosing the next tree: row perm[p] gets the loss
+ * derivatives at model m(p)'s value for position p. g, h are [K][n] in
+ * dataset (row) order.                                                      */
+void orc_ordered_gradients(int32_t loss, int32_t K, int64_t n, const int32_t* perm,
+                           const float* label, const double* support, double* g,
+                           double* h) {
+    int64_t S = orc_ordered_offset(n, orc_ordered_models(n));
+    double* a = (double*)malloc(sizeof(double) * (size_t)K * n);
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t e = orc_ordered_offset(n, ord_model_of(p)) + p;
+        for (int32_t c = 0; c < K; ++c)
+            a[(int64_t)c * n + perm[p]] = support[(int64_t)c * S + e];
+    }
+    orc_gradients(loss, K, n, a, label, g, h);
+    free(a);
+}
+
+/* After a tree's structure is fixed (leaf in row order): every model takes
+ * its leaf values from its learning positions and adds them to its kept
+ * positions. values_out (nullable) is [M][n_leaves][K].                     */
+void orc_ordered_update(int32_t loss, int32_t K, int64_t n, const int32_t* perm,
+                        const float* label, const uint16_t* leaf, int32_t n_leaves,
+                        double lr, double l2, double* support, double* values_out) {
+    int32_t M = orc_ordered_models(n);
+    int64_t S = orc_ordered_offset(n, M);
+    double* a = (double*)malloc(sizeof(double) * (size_t)K * n);
+    float* y = (float*)malloc(sizeof(float) * (size_t)n);
+    uint16_t* lf = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)n);
+    double* g = (double*)malloc(sizeof(double) * (size_t)K * n);
+    double* h = (double*)malloc(sizeof(double) * (size_t)K * n);
+    double* G = (double*)malloc(sizeof(double) * (size_t)n_leaves * K);
+    double* H = (double*)malloc(sizeof(double) * (size_t)n_leaves * K);
+    double* v = (double*)malloc(sizeof(double) * (size_t)n_leaves * K);
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_leaves);
+    for (int32_t m = 0; m < M; ++m) {
+        int64_t off = orc_ordered_offset(n, m), t = ord_learn(m), keep = ord_keep(n, m);
+        /* the model's learning positions as a small dataset of their own */
+        for (int64_t j = 0; j < t; ++j) {
+            y[j] = label[perm[j]];
+            lf[j] = leaf[perm[j]];
+            for (int32_t c = 0; c < K; ++c)
+                a[(int64_t)c * t + j] = support[(int64_t)c * S + off + j];
+        }
+        if (t > 0) {
+            orc_gradients(loss, K, t, a, y, g, h);
+            orc_leaf_values(t, K, n_leaves, lf, g, h, l2, G, H, cnt, v);
+        } else {
+            for (int64_t j = 0; j < (int64_t)n_leaves * K; ++j) v[j] = 0.0;
+        }
+        for (int64_t j = 0; j < keep; ++j)
+            for (int32_t c = 0; c < K; ++c)
+                support[(int64_t)c * S + off + j] += lr * v[(int64_t)leaf[perm[j]] * K + c];
+        if (values_out)
+            memcpy(values_out + (int64_t)m * n_leaves * K, v,
+                   sizeof(double) * (size_t)n_leaves * K);
+    }
+    free(a); free(y); free(lf); free(g); free(h); free(G); free(H); free(v); free(cnt);
+}
+
 /* Model apply, the scorer of Sec. 4: for tree t of depth d the leaf of a row
  * is the binary vector sum_i 2^i * B(x, f(t, i)), where the binary feature
  * of level i is [bin_{feat[t][i]} > border[t][i]]; the row's approx gains

@@ -72,3 +72,44 @@ def best_by_objective(objs):
         if v <= best + tol:
             return key, best
     raise AssertionError
+
+
+def _loss_derivs(loss, K, a, y):
+    """First and second loss derivatives at a [K][m] for labels y [m]:
+    RMSE 1/2 (a-y)^2, Logloss with p = sigmoid(a), MultiClass with softmax
+    p (diagonal second derivative)."""
+    if loss == 0:
+        return a - y[None, :], np.ones_like(a)
+    if loss == 1:
+        p = 1.0 / (1.0 + np.exp(-a))
+        return p - y[None, :], p * (1.0 - p)
+    e = np.exp(a - a.max(axis=0, keepdims=True))
+    p = e / e.sum(axis=0, keepdims=True)
+    t = np.zeros_like(a)
+    t[y.astype(np.int64), np.arange(a.shape[1])] = 1.0
+    return p - t, p * (1.0 - p)
+
+
+def algorithm1_models(loss, K, y_pos, leaves_pos, n_leaves, lr, l2):
+    """Algorithm 1 of Sec. 3 with every model sharing the given tree
+    structures: model i (i = 0..n) learns from positions 0..i-1 only, and
+    after every tree each model adds its own Newton leaf values (from its
+    learning positions' gradients at its own approximation) to its value at
+    every position. y_pos [n] and the trees' leaves leaves_pos [T][n] are in
+    permutation (position) order. Returns the approximations [n+1][K][n].
+    O(n^2) per tree: for tiny n only."""
+    n = y_pos.size
+    models = np.zeros((n + 1, K, n))
+    for leaf in leaves_pos:
+        for i in range(n + 1):
+            G = np.zeros((n_leaves, K))
+            H = np.zeros((n_leaves, K))
+            if i > 0:
+                g, h = _loss_derivs(loss, K, models[i][:, :i], y_pos[:i])
+                for j in range(i):
+                    G[leaf[j]] += g[:, j]
+                    H[leaf[j]] += h[:, j]
+            d = H + l2
+            v = np.where(d == 0.0, 0.0, -G / np.where(d == 0.0, 1.0, d))
+            models[i] += lr * v[leaf].T
+    return models

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import datagen
+import oracle
 from tests import brute
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -539,3 +540,126 @@ def test_category_counts_brute_force(oracle_lib):
     got = o.category_counts(ids)
     assert [sum(1 for y in ids if y == x) for x in ids] == got.tolist()
     assert got.sum() == sum(c * c for c in np.unique(ids, return_counts=True)[1])
+
+
+# ---------------------------------------------------------------------------
+# Ordered boosting's supporting approximations (Sec. 3)
+
+def _read_model_of_each_position(n):
+    """Fill every (model, position) value of the support with a distinct code
+    and read back, through the RMSE gradient at label 0, which value each
+    position's gradient takes."""
+    off = oracle.ordered_offsets(n)
+    S = int(off[-1])
+    support = np.arange(S, dtype=np.float64)[None, :]
+    perm = np.random.default_rng(n).permutation(n).astype(np.int32)
+    g, _ = oracle.ordered_gradients(0, 1, perm, np.zeros(n, np.float32), support)
+    code = g[0, perm]                      # value read by position p (row perm[p])
+    m = np.searchsorted(off, code, side="right") - 1
+    return off, m, code - off[m]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 9, 64, 65, 1000, 4097])
+def test_ordered_support_layout(oracle_lib, n):
+    """Sizes of the relaxation: model m is kept for min(n, 2^m) positions,
+    the total stays below 4n, and position p reads its own entry of model
+    floor(log2 p) + 1 (model 0 for p = 0), which learns only from positions
+    below 2^floor(log2 p) <= p."""
+    off, m, j = _read_model_of_each_position(n)
+    M = oracle.ordered_models(n)
+    assert len(off) == M + 1
+    assert np.array_equal(np.diff(off), np.minimum(n, 2 ** np.arange(M)))
+    assert off[-1] < 4 * n
+    p = np.arange(n)
+    assert np.array_equal(j, p)
+    want = np.array([0 if q == 0 else int(q).bit_length() for q in range(n)])
+    assert np.array_equal(m, want)
+    learn = np.where(m == 0, 0, 2.0 ** (m - 1))
+    assert np.all(learn <= p)
+    assert m.max() == M - 1
+
+
+def _ordered_run(loss, K, n, trees, depth, seed, lr=0.3, l2=1.0):
+    g = np.random.default_rng(seed)
+    perm = g.permutation(n).astype(np.int32)
+    if loss == 0:
+        y = g.normal(size=n).astype(np.float32)
+    elif loss == 1:
+        y = (g.random(n) < 0.4).astype(np.float32)
+    else:
+        y = g.integers(0, K, n).astype(np.float32)
+    leaves = g.integers(0, 1 << depth, (trees, n)).astype(np.uint16)   # row order
+    S = int(oracle.ordered_offsets(n)[-1])
+    support = np.zeros((K, S))
+    grads = []
+    for t in range(trees):
+        grads.append(oracle.ordered_gradients(loss, K, perm, y, support))
+        oracle.ordered_update(loss, K, perm, y, leaves[t], 1 << depth, lr, l2, support)
+    return perm, y, leaves, support, grads
+
+
+@pytest.mark.parametrize("loss,K,n", [(0, 1, 37), (1, 1, 64), (2, 3, 29), (1, 1, 1), (0, 1, 2)])
+def test_ordered_matches_algorithm1_brute_force(oracle_lib, loss, K, n):
+    """Every supporting model equals the model of Algorithm 1 (brute force,
+    one model per position, shared tree structures) that learns from the same
+    first 2^(m-1) positions, at every position it is kept for; and the
+    gradient a position gets before each tree is the one of that model."""
+    depth, trees, lr, l2 = 2, 3, 0.3, 1.0
+    perm, y, leaves, support, grads = _ordered_run(loss, K, n, trees, depth, 11 + n)
+    models = brute.algorithm1_models(loss, K, y[perm], leaves[:, perm], 1 << depth, lr, l2)
+    off = oracle.ordered_offsets(n)
+    for m in range(len(off) - 1):
+        learn = 0 if m == 0 else 2 ** (m - 1)
+        keep = int(off[m + 1] - off[m])
+        np.testing.assert_allclose(support[:, off[m]:off[m] + keep], models[learn][:, :keep],
+                                   rtol=1e-12, atol=1e-14)
+    # the gradients before the last tree, from the brute-force models
+    before = brute.algorithm1_models(loss, K, y[perm], leaves[:-1, perm], 1 << depth, lr, l2)
+    p = np.arange(n)
+    read = np.array([0 if q == 0 else 2 ** (int(q).bit_length() - 1) for q in p])
+    a = before[read, :, p].T                     # [K][n] in position order
+    gb, hb = brute._loss_derivs(loss, K, a, y[perm])
+    np.testing.assert_allclose(grads[-1][0][:, perm], gb, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(grads[-1][1][:, perm], hb, rtol=1e-12, atol=1e-14)
+
+
+def test_ordered_gradient_never_sees_its_own_or_later_labels(oracle_lib):
+    """Unbiasedness (Sec. 3): the approximation behind position p's gradient
+    is unchanged, bit for bit, when the labels of positions p..n-1 change."""
+    n, K, loss = 200, 1, 1
+    perm, y, leaves, support, _ = _ordered_run(loss, K, n, 4, 3, 5)
+    for p0 in (1, 7, 64, 130):
+        y2 = y.copy()
+        y2[perm[p0:]] = 1.0 - y2[perm[p0:]]
+        S = support.shape[1]
+        s2 = np.zeros((K, S))
+        for t in range(4):
+            oracle.ordered_update(loss, K, perm, y2, leaves[t], 8, 0.3, 1.0, s2)
+        _, mm, _ = _read_model_of_each_position(n)
+        off = oracle.ordered_offsets(n)
+        e = off[mm] + np.arange(n)
+        assert np.array_equal(support[0, e[:p0 + 1]], s2[0, e[:p0 + 1]]), p0
+        # later positions whose model learned from a changed label can move
+        learn = np.where(mm == 0, 0, 2 ** np.maximum(mm - 1, 0))
+        moved = learn > p0
+        if moved.any():
+            assert not np.array_equal(support[0, e[moved]], s2[0, e[moved]]), p0
+
+
+def test_ordered_single_leaf_rmse_is_prefix_mean(oracle_lib):
+    """One tree with one leaf, RMSE, l2 = 0, lr = 1: model m's value is the
+    mean label of its learning positions (0 for model 0), at every position
+    it is kept for."""
+    n = 300
+    g = np.random.default_rng(3)
+    perm = g.permutation(n).astype(np.int32)
+    y = g.normal(size=n).astype(np.float32)
+    off = oracle.ordered_offsets(n)
+    support = np.zeros((1, int(off[-1])))
+    vals = oracle.ordered_update(0, 1, perm, y, np.zeros(n, np.uint16), 1, 1.0, 0.0, support)
+    yp = y[perm].astype(np.float64)
+    for m in range(len(off) - 1):
+        learn = 0 if m == 0 else 2 ** (m - 1)
+        want = yp[:learn].mean() if learn else 0.0
+        assert vals[m, 0, 0] == pytest.approx(want, rel=1e-13, abs=1e-15)
+        np.testing.assert_allclose(support[0, off[m]:off[m + 1]], want, rtol=1e-13, atol=1e-15)
