@@ -540,6 +540,84 @@ int cbh_graph_capture_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part
                            int64_t* leaf_counts, uint64_t* stamps, void* stream,
                            cbh_graph** out);
 
+/* ---- ordered boosting (Sec. 3) ---------------------------------------------- */
+
+/* The supporting approximations of one permutation (Sec. 3, Algorithm 1 and
+ * its O(s n) relaxation). Algorithm 1 keeps for every position a model that
+ * never learns from it; the relaxation keeps about log2(n) models, all with
+ * the tree structures of the trees grown, and takes a row's gradient for
+ * choosing the next tree structure from the one that did not learn from it.
+ * Reading of the relaxation, with 0-based positions p (perm[p] = row at
+ * position p):
+ *   model m = 0..M-1 learns from the positions below T_m (T_0 = 0,
+ *   T_m = 2^(m-1)) and is kept for the positions below min(n, 2^m);
+ *   the row at position p takes its gradient at model m(p) = bit length of p
+ *   (0 for p = 0), which learned from positions below 2^floor(log2 p) <= p;
+ *   M = cbh_ordered_models(n) = 1 for n = 1, floor(log2(n-1)) + 2 otherwise.
+ * After each tree every model takes the Newton leaf values -G/(H+l2) of its
+ * own gradients summed over its learning positions, per leaf of the tree,
+ * and adds lr times them at every position it is kept for. The model that is
+ * kept for prediction (prob->approx; the second phase of Sec. 3) takes its
+ * leaf values from its own gradients over all rows.
+ * Several permutations (s in Sec. 3) are several cbh_ordered, each with its
+ * own support: a tree grown on one permutation's gradients (and its TS
+ * columns) is added to the supporting models of every permutation.
+ *   n        positions, equal to the problem's n
+ *   perm     device int32 [n], a permutation of 0..n-1 (an entry outside
+ *            [0, n) is skipped and reported by cbh_sync)
+ *   support  device double [K][S], S = cbh_ordered_support_size(n) (< 4n):
+ *            model m's values from cbh_ordered_offset(n, m) on, in position
+ *            order; all zero before the first tree (approx 0, Algorithm 1) */
+typedef struct cbh_ordered {
+    int64_t n;
+    const int32_t* perm;
+    double* support;
+} cbh_ordered;
+
+/* M, model m's offset (m = 0..M; offset M = S) and S; 0 / -1 / 0 for n < 1 or
+ * an m outside [0, M]. Host only, no context needed. */
+int32_t cbh_ordered_models(int64_t n);
+int64_t cbh_ordered_offset(int64_t n, int32_t m);
+int64_t cbh_ordered_support_size(int64_t n);
+
+/* prob->g and prob->h (h not for RMSE without weights) of every row, in row
+ * order, at the model its position reads: the gradients that choose the
+ * next tree structure. The first tree calls this on a zero support.
+ * Errors: CBH_EINVAL for a NULL argument or ord->n != prob->n;
+ * CBH_EUNSUPPORTED for row weights or 2^depth * K > 4096. */
+int cbh_ordered_gradients(cbh_ctx* ctx, const cbh_ordered* ord, const cbh_problem* prob,
+                          void* stream);
+
+/* After a tree's structure is fixed (prob->leaf holds every row's final
+ * leaf): with leaf_values, the kept model's leaf values from prob->approx's
+ * own gradients over all rows, and prob->approx += lr * value of the row's
+ * leaf; every supporting model of `ord` takes its own leaf values and
+ * update; then prob->g / prob->h for the next tree as cbh_ordered_gradients
+ * for `ord`. With s permutations a tree is one call with leaf_values and
+ * s - 1 calls without (prob->approx untouched), the next tree's permutation
+ * last, so that its gradients are the ones left in prob->g / prob->h.
+ *   leaf_values     device double [2^depth][K]: the kept model's values, or
+ *                   NULL to leave the kept model alone
+ *   support_values  device double [M][2^depth][K] or NULL: every supporting
+ *                   model's values
+ * Sums are in double (LDS) in an order that may vary between runs; the
+ * values are exact up to that rounding. Uses the context workspace (about
+ * 6 bytes per row plus 16 bytes per leaf and class per 2048 learning
+ * entries). Errors as cbh_ordered_gradients. */
+int cbh_ordered_update(cbh_ctx* ctx, const cbh_ordered* ord, const cbh_problem* prob,
+                       double lr, double l2, double* leaf_values, double* support_values,
+                       void* stream);
+
+/* One tree of ordered boosting in one call: the levels exactly as
+ * cbh_fit_tree (prob->g / prob->h must hold the ordered gradients, from
+ * cbh_ordered_gradients before the first tree and from the previous call
+ * after that), then cbh_ordered_update (with leaf_values, required here) in
+ * place of cbh_update_approx. */
+int cbh_fit_tree_ordered(cbh_ctx* ctx, const cbh_problem* prob, const cbh_ordered* ord,
+                         cbh_part* part, int32_t precision, int32_t subtract,
+                         void* const* hist, cbh_split* best, double lr, double l2,
+                         double* leaf_values, double* support_values, void* stream);
+
 /* ---- rows in leaf order (deep trees, many classes) ------------------------- */
 
 /* Device buffers that keep a problem's rows sorted by leaf during a tree, so

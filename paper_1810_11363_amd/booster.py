@@ -56,7 +56,7 @@ class GpuBooster:
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
                  subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled",
-                 borders=None, partition=None):
+                 borders=None, partition=None, ordered=False):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -100,6 +100,9 @@ class GpuBooster:
         if self.given_borders is not None and len(self.given_borders) != self.x_num.shape[0]:
             raise ValueError("borders needs one array per numeric feature")
         self.timings = {}
+        # ordered boosting (Sec. 3): tree structures chosen on the gradients of
+        # the supporting approximations of permutation t mod s
+        self.ordered = bool(ordered)
         self._alloc()
 
     @classmethod
@@ -129,6 +132,14 @@ class GpuBooster:
         self.leaf_values = torch.zeros((1 << self.depth, K), dtype=torch.float64, device=d)
         self.leaf_counts = torch.zeros(1 << self.depth, dtype=torch.int64, device=d)
         self.n_borders = np.zeros(self.F_num, np.int32)
+        if self.ordered:
+            S = cb.cbh_ordered_support_size(n)
+            self.support = [torch.zeros((K, S), dtype=torch.float64, device=d)
+                            for _ in range(self.s)]
+            self.perm_d = [torch.from_numpy(self.perms[r] if self.F_cat else np.arange(
+                n, dtype=np.int32)).to(d) for r in range(self.s)]
+            self.ords = [cb.make_ordered(n, self.perm_d[r], self.support[r])
+                         for r in range(self.s)]
 
     def _hist_bytes(self, level: int) -> int:
         esz = 4 if self.precision == cb.CBH_PREC_FP32 else 8
@@ -285,8 +296,30 @@ class GpuBooster:
 
     def init_gradients(self):
         self.approx.zero_()
+        if self.ordered:
+            for sup in self.support:
+                sup.zero_()
+            cb.cbh_ordered_gradients(self.ctx, self.ords[0], self.probs[0], self.stream)
+            return
         cb.cbh_update_approx(self.ctx, self.probs[0], None, self.precision, None, 0.0, 0.0,
                              stream=self.stream)
+
+    def _ordered_tree(self, t: int):
+        """Ordered tree t: levels on permutation t mod s's gradients, the kept
+        model and that permutation's support in the same call, then the other
+        permutations' supports, the next tree's permutation last (its
+        gradients are the ones left in g, h)."""
+        r, nxt = t % self.s, (t + 1) % self.s
+        pr = self.probs[r]
+        cb.cbh_fit_tree_ordered(self.ctx, pr, self.ords[r], self.part if self.use_part else None,
+                                self.precision, self.subtract, self.hists, self.best, self.lr,
+                                self.l2, self.leaf_values, None, self.stream)
+        rest = [q for q in range(self.s) if q not in (r, nxt)]
+        if nxt != r:
+            rest.append(nxt)
+        for q in rest:
+            cb.cbh_ordered_update(self.ctx, self.ords[q], pr, self.lr, self.l2, None, None,
+                                  self.stream)
 
     def subtract_levels(self) -> bool:
         """True when levels >= 1 accumulate only the smaller child of every
@@ -325,6 +358,11 @@ class GpuBooster:
         objects with a record(stream) method, recorded around each level's
         histogram build; then the levels are issued one call at a time."""
         pr = self.probs[t % self.s]
+        if self.ordered:
+            if events is not None or counts:
+                raise ValueError("ordered trees take no events or counts")
+            self._ordered_tree(t)
+            return
         if events is None:
             cb.cbh_fit_tree(self.ctx, pr, self.part if self.use_part else None, self.precision,
                             self.subtract, self.hists, self.best, self.lr, self.l2,

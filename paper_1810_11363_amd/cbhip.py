@@ -41,6 +41,8 @@ EXPORTS = [
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
     "cbh_part_build_histograms_sub",
     "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts",
+    "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
+    "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
 ]
 
 
@@ -53,6 +55,10 @@ class cbh_problem(C.Structure):
         ("gq", C.c_void_p), ("grad_scale", C.c_void_p), ("leaf", C.c_void_p),
         ("approx", C.c_void_p), ("seg_stride", C.c_void_p), ("weight", C.c_void_p),
     ]
+
+
+class cbh_ordered(C.Structure):
+    _fields_ = [("n", C.c_int64), ("perm", C.c_void_p), ("support", C.c_void_p)]
 
 
 class cbh_split(C.Structure):
@@ -119,6 +125,15 @@ def _load():
         "cbh_graph_capture_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl,
                                     vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_destroy": ([vp], None),
+        "cbh_ordered_models": ([i64], i32),
+        "cbh_ordered_offset": ([i64, i32], i64),
+        "cbh_ordered_support_size": ([i64], i64),
+        "cbh_ordered_gradients": ([vp, C.POINTER(cbh_ordered), C.POINTER(cbh_problem), vp],
+                                  C.c_int),
+        "cbh_ordered_update": ([vp, C.POINTER(cbh_ordered), C.POINTER(cbh_problem), dbl, dbl,
+                                vp, vp, vp], C.c_int),
+        "cbh_fit_tree_ordered": ([vp, C.POINTER(cbh_problem), C.POINTER(cbh_ordered), vp, i32,
+                                  i32, vp, vp, dbl, dbl, vp, vp, vp], C.c_int),
         "cbh_autotune": ([vp, C.POINTER(cbh_problem), i32, i32, C.c_char_p, vp], C.c_int),
         "cbh_autotune_load": ([vp, C.c_char_p], C.c_int),
         "cbh_set_hist_knobs": ([vp, i32, i32, i64, i32, i32, i32, i32, i32], C.c_int),
@@ -422,6 +437,45 @@ def cbh_graph_capture_tree(ctx, prob: cbh_problem, part, precision: int, subtrac
                                        _ptr(leaf_values), _ptr(leaf_counts), _ptr(stamps),
                                        _stream(stream), C.byref(out)))
     return out.value
+
+
+def cbh_ordered_models(n: int) -> int:
+    return int(_lib.cbh_ordered_models(int(n)))
+
+
+def cbh_ordered_offset(n: int, m: int) -> int:
+    return int(_lib.cbh_ordered_offset(int(n), int(m)))
+
+
+def cbh_ordered_support_size(n: int) -> int:
+    return int(_lib.cbh_ordered_support_size(int(n)))
+
+
+def make_ordered(n: int, perm, support) -> cbh_ordered:
+    return cbh_ordered(n=int(n), perm=_ptr(perm), support=_ptr(support))
+
+
+def cbh_ordered_gradients(ctx, ord_: cbh_ordered, prob: cbh_problem, stream=None):
+    return _check(_lib.cbh_ordered_gradients(ctx, C.byref(ord_), C.byref(prob),
+                                             _stream(stream)))
+
+
+def cbh_ordered_update(ctx, ord_: cbh_ordered, prob: cbh_problem, lr: float, l2: float,
+                       leaf_values, support_values=None, stream=None):
+    return _check(_lib.cbh_ordered_update(ctx, C.byref(ord_), C.byref(prob), float(lr),
+                                          float(l2), _ptr(leaf_values), _ptr(support_values),
+                                          _stream(stream)))
+
+
+def cbh_fit_tree_ordered(ctx, prob: cbh_problem, ord_: cbh_ordered, part, precision: int,
+                         subtract: bool, hist, best, lr: float, l2: float, leaf_values,
+                         support_values=None, stream=None):
+    arr = _two(hist)
+    return _check(_lib.cbh_fit_tree_ordered(ctx, C.byref(prob), C.byref(ord_), part, precision,
+                                            int(bool(subtract)), C.cast(arr, C.c_void_p),
+                                            _ptr(best), float(lr), float(l2),
+                                            _ptr(leaf_values), _ptr(support_values),
+                                            _stream(stream)))
 
 
 def cbh_graph_launch(graph, stream=None):

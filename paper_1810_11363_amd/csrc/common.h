@@ -128,6 +128,12 @@ int ensure_ws(cbh_ctx* ctx, int64_t bytes, void* stream);
 
 inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// Ordered boosting (ordered.hip): argument checks, and the update of the kept
+// model and the supporting approximations after a tree.
+int validate_ordered(const cbh_ctx* ctx, const cbh_ordered* ord, const cbh_problem* p);
+int ordered_update(cbh_ctx* ctx, const cbh_ordered* ord, const cbh_problem* p, double lr,
+                   double l2, double* leaf_values, double* support_values, hipStream_t s);
+
 // The histograms' second statistic is a row count (RMSE without row
 // weights); otherwise it is the sum of h.
 inline bool count_stat(const cbh_problem* p) {

@@ -11,7 +11,9 @@
 //     bit is set in the build's own row pass (cbh_apply_build_histograms_sub);
 //   after every level the rows are routed by its split (the leaf bit, or the
 //     move into leaf order, which writes the leaf indices at the last level);
-//   the leaf solve and the approx and gradient update.
+//   the leaf solve and the approx and gradient update (for ordered boosting,
+//   the update of the kept model and of the supporting approximations, and
+//   the ordered gradients for the next tree).
 #include <cmath>
 
 #include "common.h"
@@ -20,7 +22,8 @@ namespace cbh {
 
 static int fit_tree(cbh_ctx* ctx, const cbh_problem* p, cbh_part* part, int32_t precision,
                     int32_t subtract, void* const* hist, cbh_split* best, double lr, double l2,
-                    double* leaf_values, int64_t* leaf_counts, uint64_t* stamps, void* stream) {
+                    double* leaf_values, int64_t* leaf_counts, uint64_t* stamps, void* stream,
+                    const cbh_ordered* ord = nullptr, double* support_values = nullptr) {
     const int depth = p->depth;
     auto h = [&](int lvl) { return hist[lvl & 1]; };
     int rc = CBH_OK;
@@ -52,7 +55,10 @@ static int fit_tree(cbh_ctx* ctx, const cbh_problem* p, cbh_part* part, int32_t 
             rc = cbh_apply_split(ctx, p, lvl, best + lvl, stream);
         }
     }
-    if (!rc)
+    if (!rc && ord)
+        rc = ordered_update(ctx, ord, p, lr, l2, leaf_values, support_values,
+                            (hipStream_t)stream);
+    else if (!rc)
         rc = cbh_update_approx(ctx, p, h(depth - 1), precision, best + depth - 1, lr, l2,
                                leaf_values, leaf_counts, stream);
     return rc;
@@ -77,6 +83,22 @@ int cbh_fit_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part, int32_t 
     CBH_ARG(std::isfinite(lr) && l2 >= 0 && std::isfinite(l2), "lr / l2 out of range");
     return fit_tree(ctx, prob, part, precision, subtract, hist, best, lr, l2, leaf_values,
                     leaf_counts, stamps, stream);
+}
+
+int cbh_fit_tree_ordered(cbh_ctx* ctx, const cbh_problem* prob, const cbh_ordered* ord,
+                         cbh_part* part, int32_t precision, int32_t subtract,
+                         void* const* hist, cbh_split* best, double lr, double l2,
+                         double* leaf_values, double* support_values, void* stream) {
+    clear_error();
+    CBH_ARG(ctx && hist && hist[0] && hist[1] && best && leaf_values, "NULL argument");
+    CBH_ARG(hist[0] != hist[1], "the two histogram buffers must differ");
+    int rc = validate_ordered(ctx, ord, prob);
+    if (rc) return rc;
+    rc = validate_precision(prob, precision);
+    if (rc) return rc;
+    CBH_ARG(std::isfinite(lr) && l2 >= 0 && std::isfinite(l2), "lr / l2 out of range");
+    return fit_tree(ctx, prob, part, precision, subtract, hist, best, lr, l2, leaf_values,
+                    nullptr, nullptr, stream, ord, support_values);
 }
 
 int cbh_graph_capture_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part,

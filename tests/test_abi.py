@@ -128,3 +128,28 @@ def test_missing_library_fails_loudly(tmp_path):
             "except ImportError as e:\n print('IMPORTERROR', e)\n") % str(tmp_path)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert "IMPORTERROR" in out.stdout and "LOADED" not in out.stdout
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 9, 1000, 1 << 20, (1 << 20) + 1, 10 ** 6])
+def test_ordered_layout_equals_oracle(cb, oracle_lib, n):
+    """The supporting approximations' count and offsets (host-only calls)
+    are those of the oracle's reading of Sec. 3."""
+    M = cb.cbh_ordered_models(n)
+    assert M == oracle_lib.ordered_models(n)
+    if n <= 4097:
+        off = oracle_lib.ordered_offsets(n)
+        assert [cb.cbh_ordered_offset(n, m) for m in range(M + 1)] == off.tolist()
+    assert cb.cbh_ordered_support_size(n) == cb.cbh_ordered_offset(n, M) < 4 * n
+    assert cb.cbh_ordered_offset(n, M + 1) == -1
+    assert cb.cbh_ordered_offset(n, -1) == -1
+    assert cb.cbh_ordered_models(0) == 0 and cb.cbh_ordered_support_size(0) == 0
+
+
+def test_ordered_calls_reject_null_without_launch(cb):
+    p = cb.cbh_problem()
+    o = cb.cbh_ordered()
+    for call in (lambda: cb.cbh_ordered_gradients(None, o, p),
+                 lambda: cb.cbh_ordered_update(None, o, p, 0.1, 3.0, None)):
+        with pytest.raises(cb.CbhError) as err:
+            call()
+        assert err.value.code == cb.CBH_EINVAL
