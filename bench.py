@@ -1013,6 +1013,10 @@ def run_trees(args):
         "preprocess_s": {k: round(v, 4) for k, v in bst.timings.items() if v is not None},
         "lds_rates_lane_ops_per_clk_per_cu": rates,
     }
+    if args.workload == "c2":
+        out["ordered"] = time_ordered(bst, args, rmse)
+        out["ordered"]["vs_plain_tree"] = round(out["ordered"]["ms_per_tree"] /
+                                                head["ms_per_step"], 3)
     bst.close()
     # the oracle leg: FP64 error of every form's sampled histograms, then the
     # oracle timed on a row sample of the same workload
@@ -1028,6 +1032,73 @@ def run_trees(args):
                                    **cpu_info())
     del p
     return out
+
+
+def ordered_update_bytes(n, K, s, rmse):
+    """Algorithmic HBM bytes of one ordered tree's updates (Sec. 3): the kept
+    model once, and per permutation the gather of leaf and label into
+    position order, the sums over every model's learning positions, the
+    update of every kept entry and the next tree's gradients."""
+    import oracle
+    M = oracle.ordered_models(n)
+    S = int(oracle.ordered_offsets(n)[-1])
+    T = (1 << (M - 1)) - 1 if M >= 1 else 0        # learning entries of all models
+    gb = 4 * K * (1 if rmse else 2)                # g (and h) written per row
+    per_perm = 16 * n + T * (6 + 8 * K) + S * (2 + 16 * K) + n * (8 + gb)
+    kept = n * (6 + 8 * K) + n * (2 + 16 * K)
+    return kept + s * per_perm, per_perm, S, M
+
+
+def time_ordered(bst, args, rmse):
+    """Ordered boosting (Sec. 3) on the same problem and form: whole trees
+    (levels on permutation t mod s's supporting gradients, then the kept
+    model and every permutation's supporting models), and the updates alone.
+    Eager launches (the tree is a few library calls), CUDA events on the
+    booster's stream."""
+    import torch
+    from paper_1810_11363_amd import cbhip as cb
+    torch.cuda.synchronize()
+    bst.set_precision(PRECISIONS[args.precision], subtract=args.subtract)
+    bst.drop_graphs()
+    bst.set_ordered(True)
+    bst.init_gradients()
+    steps = max(4, min(args.steps, 20))
+    for t in range(2):
+        bst.fit_tree(t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(bst.stream)
+    for t in range(2, 2 + steps):
+        bst.fit_tree(t)
+    e1.record(bst.stream)
+    torch.cuda.synchronize()
+    ms_tree = e0.elapsed_time(e1) / steps
+    pr = bst.probs[0]
+    e0.record(bst.stream)
+    for _ in range(steps):
+        for q in range(bst.s):
+            cb.cbh_ordered_update(bst.ctx, bst.ords[q], pr, bst.lr, bst.l2,
+                                  bst.leaf_values if q == 0 else None, None, bst.stream)
+    e1.record(bst.stream)
+    torch.cuda.synchronize()
+    cb.cbh_sync(bst.ctx)
+    ms_upd = e0.elapsed_time(e1) / steps
+    total, per_perm, S, M = ordered_update_bytes(bst.n, bst.K, bst.s, rmse)
+    bst.set_ordered(False)
+    bst.init_gradients()
+    gbs = total / (ms_upd * 1e-3) / 1e9
+    return {
+        "what": "ordered boosting (supporting approximations of every permutation, "
+                "cbh_fit_tree_ordered + cbh_ordered_update)",
+        "permutations": bst.s, "models_per_permutation": M, "support_doubles_per_class": S,
+        "timed_trees": steps, "ms_per_tree": round(ms_tree, 4),
+        "update_ms_per_tree": round(ms_upd, 4),
+        "update_algorithmic_bytes_per_tree": total,
+        "update_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                            "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                            "note": "update kernels only, eager launches, event-timed "
+                                    "(launch gaps included)"},
+    }
 
 
 def main():
@@ -1107,7 +1178,7 @@ def main():
     c2 = run_trees(resolve(c2_args, "c2"))
     keep = ("value", "unit", "steps", "warmup", "ms_per_step", "sec_per_tree",
             "hist_G_row_features_per_s", "dtype", "config", "roofline", "forms", "vs_plain_fp32",
-            "preprocess_s", "cpu_baseline")
+            "preprocess_s", "cpu_baseline", "ordered")
     out["c2"] = {k: c2[k] for k in keep if k in c2}
     if not args.no_cpu:
         print("# oracle at one thread ...", file=sys.stderr, flush=True)

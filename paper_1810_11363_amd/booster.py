@@ -133,11 +133,19 @@ class GpuBooster:
         self.leaf_counts = torch.zeros(1 << self.depth, dtype=torch.int64, device=d)
         self.n_borders = np.zeros(self.F_num, np.int32)
         if self.ordered:
+            self._alloc_ordered()
+
+    def _alloc_ordered(self):
+        d, n, K = self.device, self.n, self.K
+        if getattr(self, "ords", None) is None:
             S = cb.cbh_ordered_support_size(n)
             self.support = [torch.zeros((K, S), dtype=torch.float64, device=d)
                             for _ in range(self.s)]
-            self.perm_d = [torch.from_numpy(self.perms[r] if self.F_cat else np.arange(
-                n, dtype=np.int32)).to(d) for r in range(self.s)]
+            # the permutations of the ordered statistics (Sec. 3 uses the same
+            # ones); the identity where the problem brings none
+            self.perm_d = [torch.from_numpy(np.ascontiguousarray(
+                self.perms[r] if r < self.perms.shape[0] else np.arange(n), dtype=np.int32)).to(d)
+                for r in range(self.s)]
             self.ords = [cb.make_ordered(n, self.perm_d[r], self.support[r])
                          for r in range(self.s)]
 
@@ -293,6 +301,13 @@ class GpuBooster:
     # ------------------------------------------------------------------ trees
     def split_ptr(self, level: int) -> int:
         return self.best.data_ptr() + 16 * level
+
+    def set_ordered(self, ordered: bool):
+        """Switch between ordered boosting (Sec. 3) and plain boosting; call
+        init_gradients before the next tree."""
+        self.ordered = bool(ordered)
+        if self.ordered:
+            self._alloc_ordered()
 
     def init_gradients(self):
         self.approx.zero_()
