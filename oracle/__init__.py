@@ -57,6 +57,7 @@ def _declare(L):
     L.orc_ordered_offset.restype = i64
     L.orc_ordered_gradients.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp]
     L.orc_ordered_update.argtypes = [i32, i32, i64, vp, vp, vp, i32, dbl, dbl, vp, vp]
+    L.orc_pack_bins.argtypes = [vp, i64, i32, vp]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [i32]
 
@@ -300,3 +301,13 @@ def ordered_update(loss: int, K: int, perm, label, leaf, n_leaves: int, lr: floa
     lib().orc_ordered_update(loss, K, n, _p(perm), _p(label), _p(leaf), int(n_leaves),
                              float(lr), float(l2), _p(support), _p(vals))
     return vals
+
+
+def pack_bins(bins, bits: int) -> np.ndarray:
+    """The packed column (ceil(n/16) * 2 * bits bytes) of one feature's byte
+    bins."""
+    bins = _c(bins, np.uint8)
+    n = bins.size
+    out = np.empty(((n + 15) // 16) * 2 * bits, np.uint8)
+    lib().orc_pack_bins(_p(bins), n, int(bits), _p(out))
+    return out

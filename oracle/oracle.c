@@ -334,6 +334,31 @@ void orc_update_approx(int64_t n, int32_t K, const uint16_t* leaf,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Packed bins (Sec. 5 keeps features of at most 15 bins in 4 bits and
+ * binary features in 1 bit). The paper fixes the widths, not a byte layout;
+ * the layout here is the GPU library's documented one, written out byte by
+ * byte: rows are taken in segments of 16, a segment is 2 * bits bytes;
+ * 4 bits: row r of a segment (k = r / 8, q = r % 8) is nibble q / 4 (0 low,
+ * 1 high) of byte 4k + q % 4; 1 bit: row r is bit r % 8 of byte r / 8.
+ * Rows past n are 0; values are masked to the width. out has
+ * ceil(n/16) * 2 * bits bytes.                                              */
+void orc_pack_bins(const uint8_t* bins, int64_t n, int32_t bits, uint8_t* out) {
+    int64_t nseg = (n + 15) / 16;
+    memset(out, 0, (size_t)(nseg * 2 * bits));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t seg = i / 16;
+        int r = (int)(i % 16);
+        unsigned v = bins[i] & ((1u << bits) - 1u);
+        if (bits == 4) {
+            int k = r / 8, q = r % 8;
+            out[seg * 8 + 4 * k + q % 4] |= (uint8_t)(v << (4 * (q / 4)));
+        } else {
+            out[seg * 2 + r / 8] |= (uint8_t)(v << (r % 8));
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Ordered boosting's supporting approximations (Sec. 3). Algorithm 1 keeps,
  * for one permutation, a model per position that never learns from that
  * position; the O(s n) relaxation keeps about log2(n) of them instead: model

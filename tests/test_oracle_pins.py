@@ -663,3 +663,37 @@ def test_ordered_single_leaf_rmse_is_prefix_mean(oracle_lib):
         want = yp[:learn].mean() if learn else 0.0
         assert vals[m, 0, 0] == pytest.approx(want, rel=1e-13, abs=1e-15)
         np.testing.assert_allclose(support[0, off[m]:off[m + 1]], want, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Packed bins (Sec. 5 widths; the library's byte layout)
+
+def test_pack_bins_hand_examples(oracle_lib):
+    """Bytes written out by hand from the documented layout."""
+    for case in _gold("packed_bins_hand.json")["cases"]:
+        got = oracle_lib.pack_bins(np.array(case["bins"], np.uint8), case["bits"])
+        want = np.array([int(b, 16) for b in case["bytes_hex"]], np.uint8)
+        assert np.array_equal(got, want), case
+
+
+@pytest.mark.parametrize("bits", [4, 1])
+def test_pack_bins_keeps_every_bin(oracle_lib, bits):
+    """Every row's bin can be read back from its nibble or bit (sizes 1..70),
+    and changing one row's bin changes exactly its own bits."""
+    g = np.random.default_rng(bits)
+    for n in list(range(1, 40)) + [63, 64, 65, 70]:
+        b = g.integers(0, 1 << bits, n).astype(np.uint8)
+        packed = oracle_lib.pack_bins(b, bits)
+        assert packed.size == ((n + 15) // 16) * 2 * bits
+        bitsarr = np.unpackbits(packed, bitorder="little")
+        # per row, the set of bit positions its value occupies
+        for i in range(n):
+            b2 = b.copy()
+            b2[i] = b[i] ^ ((1 << bits) - 1)
+            diff = np.flatnonzero(bitsarr != np.unpackbits(oracle_lib.pack_bins(b2, bits),
+                                                           bitorder="little"))
+            assert diff.size == bits, (n, i)
+            seg, r = divmod(i, 16)
+            assert np.all(diff // (16 * bits) == seg)
+        # total set bits = sum of popcounts of the values
+        assert int(bitsarr.sum()) == int(sum(bin(int(v)).count("1") for v in b))
