@@ -111,6 +111,21 @@ typedef struct cbh_ctx cbh_ctx;
  *               (MultiClass, 2 <= K <= 16)
  *   loss        CBH_LOSS_*
  *   depth       tree depth d, 1 <= d <= 16
+ *   bin_bits    0 or 8: a byte per bin (bins as described above); 4 or 1:
+ *               packed bins (Sec. 5 stores features of at most 15 bins in 4
+ *               bits and binary features in 1 bit). Packed: every feature of
+ *               the problem has that width (n_bins[f] <= 2^bin_bits, so
+ *               max_bins <= 16 or 2), bins[f] is a plain column of
+ *               ceil(n/16) segments of 2 * bin_bits bytes (8-byte aligned
+ *               for 4 bits, 2-byte for 1 bit; cbh_pack_bins writes it) and
+ *               seg_stride must be NULL. 4 bits: 32-bit word k (k = 0, 1) of
+ *               a segment holds rows 8k..8k+3 of the segment in the low
+ *               nibbles of its bytes 0..3 and rows 8k+4..8k+7 in the high
+ *               nibbles; 1 bit: bit r of the segment's little-endian 16-bit
+ *               word is row r. The histogram, subtraction, score, split,
+ *               update, whole-tree and ordered calls take packed problems;
+ *               the leaf-ordered (cbh_part_*), batched (cbh_batch_*) and
+ *               autotuning calls return CBH_EUNSUPPORTED for them.
  *   label       device float [n]: target (RMSE), 0/1 (Logloss) or class index
  *               (MultiClass)
  *   g, h        device float [K][n]: first and second derivatives of the
@@ -152,7 +167,7 @@ typedef struct cbh_problem {
     int32_t K;
     int32_t loss;
     int32_t depth;
-    int32_t reserved;
+    int32_t bin_bits;
     const float* label;
     float* g;
     float* h;
@@ -338,6 +353,17 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
  * range. */
 int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* counts_out,
                         void* stream);
+
+/* Packed bins from byte bins (Sec. 5 feature packing; layout at
+ * cbh_problem.bin_bits): feature f's bins (the byte layout of
+ * cbh_problem.bins with seg_stride, n rows) are written to packed[f], a
+ * device buffer of ceil(n/16) * 2 * bits bytes, rows past n as 0.
+ *   bins, packed  device arrays of n_features device pointers
+ *   bits          4 or 1
+ * A bin value >= 2^bits is stored masked and reported by cbh_sync. */
+int cbh_pack_bins(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride,
+                  int32_t n_features, int64_t n, int32_t bits, uint8_t* const* packed,
+                  void* stream);
 
 /* ---- per-tree and per-level calls (the split search) -------------------- */
 

@@ -40,7 +40,7 @@ EXPORTS = [
     "cbh_autotune", "cbh_autotune_load", "cbh_set_hist_knobs",
     "cbh_part_create", "cbh_part_destroy", "cbh_part_split", "cbh_part_build_histograms",
     "cbh_part_build_histograms_sub",
-    "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts",
+    "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts", "cbh_pack_bins",
     "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
 ]
@@ -50,7 +50,7 @@ class cbh_problem(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("n_features", C.c_int32), ("max_bins", C.c_int32),
         ("bins", C.c_void_p), ("n_bins", C.c_void_p), ("K", C.c_int32),
-        ("loss", C.c_int32), ("depth", C.c_int32), ("reserved", C.c_int32),
+        ("loss", C.c_int32), ("depth", C.c_int32), ("bin_bits", C.c_int32),
         ("label", C.c_void_p), ("g", C.c_void_p), ("h", C.c_void_p),
         ("gq", C.c_void_p), ("grad_scale", C.c_void_p), ("leaf", C.c_void_p),
         ("approx", C.c_void_p), ("seg_stride", C.c_void_p), ("weight", C.c_void_p),
@@ -125,6 +125,7 @@ def _load():
         "cbh_graph_capture_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl,
                                     vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_destroy": ([vp], None),
+        "cbh_pack_bins": ([vp, vp, vp, i32, i64, i32, vp, vp], C.c_int),
         "cbh_ordered_models": ([i64], i32),
         "cbh_ordered_offset": ([i64, i32], i64),
         "cbh_ordered_support_size": ([i64], i64),
@@ -437,6 +438,12 @@ def cbh_graph_capture_tree(ctx, prob: cbh_problem, part, precision: int, subtrac
                                        _ptr(leaf_values), _ptr(leaf_counts), _ptr(stamps),
                                        _stream(stream), C.byref(out)))
     return out.value
+
+
+def cbh_pack_bins(ctx, bins_table, seg_stride, n_features: int, n: int, bits: int,
+                  packed_table, stream=None):
+    return _check(_lib.cbh_pack_bins(ctx, _ptr(bins_table), _ptr(seg_stride), int(n_features),
+                                     int(n), int(bits), _ptr(packed_table), _stream(stream)))
 
 
 def cbh_ordered_models(n: int) -> int:

@@ -146,6 +146,9 @@ int cbh_autotune(cbh_ctx* ctx, const cbh_problem* prob, int32_t precision, int32
     CBH_ARG(ctx != nullptr, "ctx is NULL");
     int rc = validate_problem(prob);
     if (rc) return rc;
+    CBH_REQUIRE(!packed_bins(prob), CBH_EUNSUPPORTED,
+                "autotuning takes byte bins (packed bins have one kernel and its default plan)");
+    if (rc) return rc;
     rc = validate_precision(prob, precision);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;

@@ -886,6 +886,9 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
     for (int p = 0; p < P; ++p) {
         int rc = validate_problem(&probs[p]);
         if (rc) return rc;
+        CBH_REQUIRE(!packed_bins(&probs[p]), CBH_EUNSUPPORTED,
+                    "batched plans take byte bins (problem %d has packed bins)", p);
+        if (rc) return rc;
         rc = validate_precision(&probs[p], precision);
         if (rc) return rc;
         CBH_ARG(probs[p].depth == probs[0].depth, "every problem needs the same depth");

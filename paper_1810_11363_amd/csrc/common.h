@@ -55,6 +55,7 @@ enum : uint32_t {
     FLAG_BAD_INDEX = 2u,
     FLAG_BAD_SPLIT = 4u,
     FLAG_FUSED_WAIT = 8u,
+    FLAG_PACK_RANGE = 16u,
 };
 
 // ------------------------------------------------------- launch geometry
@@ -139,6 +140,9 @@ int ordered_update(cbh_ctx* ctx, const cbh_ordered* ord, const cbh_problem* p, d
 inline bool count_stat(const cbh_problem* p) {
     return p->loss == CBH_LOSS_RMSE && p->weight == nullptr;
 }
+
+// Bins packed below a byte per row (bin_bits 4 or 1).
+inline bool packed_bins(const cbh_problem* p) { return p->bin_bits == 4 || p->bin_bits == 1; }
 
 // Histogram planning (histogram.hip).
 int words_per_cell(int32_t precision, int32_t K);

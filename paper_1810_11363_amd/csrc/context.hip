@@ -77,6 +77,13 @@ int validate_problem(const cbh_problem* p) {
     }
     CBH_ARG(p->label && p->g && p->leaf && p->approx, "label/g/leaf/approx is NULL");
     CBH_ARG(count_stat(p) || p->h != nullptr, "h is NULL (needed unless RMSE without weights)");
+    CBH_ARG(p->bin_bits == 0 || p->bin_bits == 8 || p->bin_bits == 4 || p->bin_bits == 1,
+            "bin_bits must be 0 or 8 (bytes), 4 or 1 (got %d)", p->bin_bits);
+    if (packed_bins(p)) {
+        CBH_REQUIRE(p->max_bins <= (1 << p->bin_bits), CBH_EUNSUPPORTED,
+                    "max_bins %d does not fit in %d-bit bins", p->max_bins, p->bin_bits);
+        CBH_ARG(p->seg_stride == nullptr, "packed bins are plain columns (seg_stride NULL)");
+    }
     return CBH_OK;
 }
 
@@ -205,6 +212,8 @@ int cbh_sync(cbh_ctx* ctx, void* stream) {
         if (flags & FLAG_NAN_INPUT) msg += " NaN feature value (binned as 0);";
         if (flags & FLAG_BAD_INDEX) msg += " permutation entry outside [0, n);";
         if (flags & FLAG_BAD_SPLIT) msg += " model split feature outside [0, F) (bit taken as 0);";
+        if (flags & FLAG_PACK_RANGE)
+            msg += " bin value too large for the packed width (stored masked);";
         if (flags & FLAG_FUSED_WAIT)
             msg += " a fused batched level gave up waiting for an earlier stage (results invalid);";
         set_error("%s", msg.c_str());

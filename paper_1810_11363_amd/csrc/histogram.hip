@@ -196,6 +196,7 @@ struct HistArgs {
     // lanes-over-features kernel: per-row slot codes (the leaf in a direct
     // build; the parent, or 0xffff for the larger child's rows, in subtraction)
     const uint16_t* rowcode;
+    int32_t bits;           // bins per byte layout: 8, or packed 4 / 1 (lanes-over-features only)
 };
 
 template <int PREC, int KT, int RM>
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(256) void side_code_kernel(const void* __restrict__
 // Single-problem launch: block -> (class, slot tile, feature group, chunk),
 // XCD-contiguous (the classes of one tile, group and chunk, which read the
 // same bins, are neighbours).
-template <int PREC, int RM, int W, int MODE>
+template <int PREC, int RM, int W, int MODE, int BITS>
 __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     const int64_t per_xcd = (a.n_blocks + 7) / 8;
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(kHistThreads) void hist_lpf_kernel(HistArgs a) {
     b.coff = c * (a.wpc / a.K);
     const int64_t r0 = chunk * a.rows_per_chunk;
     const uint32_t s0 = (uint32_t)lt_i * (uint32_t)a.lt;
-    lpf_block<PREC, RM, W, MODE>(b, r0, min(a.n, r0 + a.rows_per_chunk), fg, s0,
+    lpf_block<PREC, RM, W, MODE, BITS>(b, r0, min(a.n, r0 + a.rows_per_chunk), fg, s0,
                                  min((uint32_t)a.lt, (uint32_t)a.L - s0),
                                  a.partials + chunk * (int64_t(a.L) * a.F * a.B * a.wpc), 0u,
                                  lds);
@@ -547,15 +548,17 @@ void hist_init_attrs(int max_lds) {
         (const void*)hist_kernel<CBH_PREC_F64, 0, 0>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-#define CBH_LPF_ATTR(P, R, M)                                                                \
+#define CBH_LPF_ATTRB(P, R, M, BT)                                                           \
     {                                                                                        \
-        const void* l[] = {(const void*)hist_lpf_kernel<P, R, 32, M>,                        \
-                           (const void*)hist_lpf_kernel<P, R, 16, M>,                        \
-                           (const void*)hist_lpf_kernel<P, R, 8, M>,                         \
-                           (const void*)hist_lpf_kernel<P, R, 4, M>};                        \
+        const void* l[] = {(const void*)hist_lpf_kernel<P, R, 32, M, BT>,                    \
+                           (const void*)hist_lpf_kernel<P, R, 16, M, BT>,                    \
+                           (const void*)hist_lpf_kernel<P, R, 8, M, BT>,                     \
+                           (const void*)hist_lpf_kernel<P, R, 4, M, BT>};                    \
         for (const void* f : l)                                                              \
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds); \
     }
+#define CBH_LPF_ATTR(P, R, M) CBH_LPF_ATTRB(P, R, M, 8) CBH_LPF_ATTRB(P, R, M, 4) \
+    CBH_LPF_ATTRB(P, R, M, 1)
 #define CBH_LPF_ATTR3(P, R) CBH_LPF_ATTR(P, R, 0) CBH_LPF_ATTR(P, R, 1) CBH_LPF_ATTR(P, R, 2)
     CBH_LPF_ATTR3(CBH_PREC_FP32, 0)
     CBH_LPF_ATTR3(CBH_PREC_FP32, 1)
@@ -566,6 +569,7 @@ void hist_init_attrs(int max_lds) {
     CBH_LPF_ATTR3(CBH_PREC_F64, 1)
 #undef CBH_LPF_ATTR3
 #undef CBH_LPF_ATTR
+#undef CBH_LPF_ATTRB
 }
 
 // Row codes for a lanes-over-features build by subtraction: the parent
@@ -584,16 +588,23 @@ __global__ __launch_bounds__(256) void slot_code_kernel(const uint16_t* __restri
     }
 }
 
-template <int PREC, int RM, int MODE>
-static void launch_lpf_mode(const HistArgs& a, const HistPlan& plan, hipStream_t s) {
+template <int PREC, int RM, int MODE, int BITS>
+static void launch_lpf_bits(const HistArgs& a, const HistPlan& plan, hipStream_t s) {
     const unsigned grid = (unsigned)(8 * ((plan.n_blocks + 7) / 8));
     const size_t lds = (size_t)plan.lds_bytes;
     switch (plan.fb) {
-        case 32: hist_lpf_kernel<PREC, RM, 32, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
-        case 16: hist_lpf_kernel<PREC, RM, 16, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
-        case 8: hist_lpf_kernel<PREC, RM, 8, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
-        default: hist_lpf_kernel<PREC, RM, 4, MODE><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 32: hist_lpf_kernel<PREC, RM, 32, MODE, BITS><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 16: hist_lpf_kernel<PREC, RM, 16, MODE, BITS><<<grid, kHistThreads, lds, s>>>(a); break;
+        case 8: hist_lpf_kernel<PREC, RM, 8, MODE, BITS><<<grid, kHistThreads, lds, s>>>(a); break;
+        default: hist_lpf_kernel<PREC, RM, 4, MODE, BITS><<<grid, kHistThreads, lds, s>>>(a); break;
     }
+}
+
+template <int PREC, int RM, int MODE>
+static void launch_lpf_mode(const HistArgs& a, const HistPlan& plan, hipStream_t s) {
+    if (a.bits == 4) launch_lpf_bits<PREC, RM, MODE, 4>(a, plan, s);
+    else if (a.bits == 1) launch_lpf_bits<PREC, RM, MODE, 1>(a, plan, s);
+    else launch_lpf_bits<PREC, RM, MODE, 8>(a, plan, s);
 }
 
 template <int PREC, int RM>
@@ -657,10 +668,18 @@ int launch_hist(cbh_ctx* ctx, const cbh_problem* p, int32_t level, int32_t preci
                 const cbh_split* parent_split, bool apply_parent) {
     HistArgs a;
     a.rowcode = p->leaf;
+    a.bits = packed_bins(p) ? p->bin_bits : 8;
+    if (packed_bins(p) && plan.kind != 1) {
+        set_error("internal: packed bins need the lanes-over-features histogram");
+        return CBH_EINVAL;
+    }
     if (parent) {
         const int64_t half = int64_t(1) << (level - 1);
         const int rmse = count_stat(p);
-        const bool fused = plan.kind == 1 && half * p->max_bins <= 16384;
+        // (the one-launch side/code pass sets the parent's leaf bit from byte
+        // bins only; packed bins take the separate apply)
+        const bool fused = plan.kind == 1 && half * p->max_bins <= 16384 &&
+                           !(apply_parent && packed_bins(p));
         if (apply_parent && !fused) {
             // the parent level's leaf bit first, as cbh_apply_split
             const int rc = launch_apply(ctx, p, level - 1, parent_split, s);
@@ -890,8 +909,9 @@ int cbh_build_histograms(cbh_ctx* ctx, const cbh_problem* prob, int32_t level,
     CBH_ARG(level >= 0 && level < prob->depth, "level %d outside [0, depth)", level);
     CBH_ARG(hist_out != nullptr, "hist_out is NULL");
     const int L = 1 << level;
-    const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
-                                   precision, prob->n, 0);
+    HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
+                             precision, prob->n, 0);
+    if (packed_bins(prob)) kn.kernel = 1;
     const int rmse = count_stat(prob);
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, L,
                                     precision, rmse, ctx->max_lds);
@@ -918,8 +938,9 @@ static int build_sub(cbh_ctx* ctx, const cbh_problem* prob, int32_t level, int32
     CBH_ARG(parent_hist && parent_split && hist_out, "NULL histogram or split");
     CBH_ARG(parent_hist != hist_out, "parent_hist and hist_out must not be the same buffer");
     const int half = 1 << (level - 1);
-    const HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
-                                   precision, prob->n, 1);
+    HistKnobs kn = knobs_for(ctx, prob->n_features, prob->max_bins, prob->K, level,
+                             precision, prob->n, 1);
+    if (packed_bins(prob)) kn.kernel = 1;
     const int rmse = count_stat(prob);
     const HistPlan plan = plan_hist(kn, prob->n, prob->n_features, prob->max_bins, prob->K, half,
                                     precision, rmse, ctx->max_lds);

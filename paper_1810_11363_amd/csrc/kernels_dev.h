@@ -137,6 +137,50 @@ __device__ __forceinline__ const uint8_t* seg_ptr(const uint8_t* base, int64_t s
                                                    int64_t i) {
     return base + (i >> 4) * stride + (i & 15);
 }
+// Packed bins (cbh_problem.bin_bits 4 or 1; Sec. 5 stores features of at most
+// 15 bins in 4 bits and binary ones in 1 bit): a 16-row segment of a feature
+// is 2 * BITS bytes. 4 bits: 32-bit word k (k = 0, 1) of the segment holds
+// rows 8k..8k+3 in the low nibbles of its bytes 0..3 and rows 8k+4..8k+7 in
+// the high nibbles, so two masks give four rows per byte lane; 1 bit: bit r
+// of the segment's little-endian 16-bit word is row r.
+template <int BITS>
+constexpr int seg_bytes() { return 2 * BITS; }
+
+// 4 bits x -> bytes 0..3 holding bit 0..3 of x (x < 16: the four shifted
+// copies x, x << 7, x << 14, x << 21 do not overlap)
+__device__ __forceinline__ uint32_t spread4(uint32_t x) {
+    return __umul24(x, 0x204081u) & 0x01010101u;
+}
+
+// The 16 bins of the segment at p, row r in byte r.
+template <int BITS>
+__device__ __forceinline__ uint4 load_seg16(const uint8_t* p) {
+    if constexpr (BITS == 8) {
+        return gld_u4(p);
+    } else if constexpr (BITS == 4) {
+        const uint2 w = gld_u2(p);
+        return make_uint4(w.x & 0x0f0f0f0fu, (w.x >> 4) & 0x0f0f0f0fu, w.y & 0x0f0f0f0fu,
+                          (w.y >> 4) & 0x0f0f0f0fu);
+    } else {
+        const uint32_t b = gld_u16(p);
+        return make_uint4(spread4(b & 15u), spread4((b >> 4) & 15u), spread4((b >> 8) & 15u),
+                          spread4((b >> 12) & 15u));
+    }
+}
+
+// Bin of row r (0..15) of the segment at p.
+template <int BITS>
+__device__ __forceinline__ uint32_t seg_bin(const uint8_t* p, int r) {
+    if constexpr (BITS == 8) {
+        return gld_u8(p + r);
+    } else if constexpr (BITS == 4) {
+        const int q = r & 7;
+        return (gld_u8(p + 4 * (r >> 3) + (q & 3)) >> (4 * (q >> 2))) & 15u;
+    } else {
+        return (gld_u8(p + (r >> 3)) >> (r & 7)) & 1u;
+    }
+}
+
 __device__ __forceinline__ int64_t seg_stride_of(const int64_t* seg, int f) {
     return seg ? seg[f] : 16;
 }
@@ -1165,7 +1209,7 @@ constexpr int vm_wait_imm(int n) {
     return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14);
 }
 
-template <int PREC, int RM, int MODE>
+template <int PREC, int RM, int MODE, int BITS = 8>
 struct LpfSeg {
     // 16-byte loads per segment (bins, row codes, statistics)
     static constexpr int kLoads =
@@ -1177,7 +1221,7 @@ struct LpfSeg {
     __device__ __forceinline__ void load(const uint8_t* col, int64_t sstride,
                                          const uint16_t* rowcode, const LpfBlock& a, int64_t t) {
         const int64_t i = t << 4;
-        b = gld_u4(col + t * sstride);
+        b = load_seg16<BITS>(col + t * sstride);
         if constexpr (MODE != 0) {
             c[0] = gld_u4(rowcode + i);
             c[1] = gld_u4(rowcode + i + 8);
@@ -1265,7 +1309,7 @@ __device__ __forceinline__ void lpf_zero(int B, uint32_t ns, uint32_t* lds) {
     for (uint32_t i = threadIdx.x; i < tile_words; i += blockDim.x) lds[i] = 0u;
 }
 
-template <int PREC, int RM, int W, int MODE>
+template <int PREC, int RM, int W, int MODE, int BITS = 8>
 __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
                                                uint32_t s0, uint32_t ns, uint32_t* lds) {
     constexpr uint32_t CS = lpf_cell_bytes<PREC>();
@@ -1278,15 +1322,16 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
     const bool fok = fl < nf;
     const int f = f0 + (fok ? fl : 0);
     const uint8_t* col = a.bins[f];
-    const int64_t sstride = a.seg ? a.seg[f] : 16;
+    const int64_t sstride = a.seg ? a.seg[f] : seg_bytes<BITS>();
     const uint32_t slot_bytes = (uint32_t)a.B * lpf_record_bytes(W, CS);
     char* tile = reinterpret_cast<char*>(lds);
     const int64_t t_full = r1 >> 4;            // segments before this one are full
     const uint32_t lane_off = (uint32_t)fl * 8u;
     const uint16_t* rowcode = a.rowcode;
-    const bool vec = ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(a.g) |
-                       reinterpret_cast<uintptr_t>(a.h) | reinterpret_cast<uintptr_t>(a.gq) |
-                       reinterpret_cast<uintptr_t>(rowcode)) & 15) == 0;
+    const bool vec = ((reinterpret_cast<uintptr_t>(col) & (seg_bytes<BITS>() - 1)) |
+                      ((reinterpret_cast<uintptr_t>(a.g) | reinterpret_cast<uintptr_t>(a.h) |
+                        reinterpret_cast<uintptr_t>(a.gq) | reinterpret_cast<uintptr_t>(rowcode)) &
+                       15)) == 0;
     int64_t t = (r0 >> 4) + int64_t(wave) * RG + rq;
     const int64_t step = int64_t(nwaves) * RG;
     if (vec && t < t_full) {
@@ -1296,18 +1341,18 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
         // segment and are not used): a load under a branch would make the
         // compiler's wait before the atomics drain it too.
         const int64_t t_last = t_full - 1;
-        LpfSeg<PREC, RM, MODE> A, B;
+        LpfSeg<PREC, RM, MODE, BITS> A, B;
         A.load(col, sstride, rowcode, a, t);
         for (;;) {
             int64_t tn = t + step;
             B.load(col, sstride, rowcode, a, min(tn, t_last));
-            LpfSeg<PREC, RM, MODE>::wait_mine();
+            LpfSeg<PREC, RM, MODE, BITS>::wait_mine();
             if (fok) A.template add<W>(tile, lane_off, s0, ns, slot_bytes);
             t = tn;
             if (t >= t_full) break;
             tn = t + step;
             A.load(col, sstride, rowcode, a, min(tn, t_last));
-            LpfSeg<PREC, RM, MODE>::wait_mine();
+            LpfSeg<PREC, RM, MODE, BITS>::wait_mine();
             if (fok) B.template add<W>(tile, lane_off, s0, ns, slot_bytes);
             t = tn;
             if (t >= t_full) break;
@@ -1319,7 +1364,7 @@ __device__ __forceinline__ void lpf_accumulate(const LpfBlock& a, int64_t r0, in
         const int64_t i = t << 4;
         const uint8_t* pb = col + t * sstride;
         for (int r = 0; r < 16 && i + r < r1; ++r) {
-            const uint32_t bwr[4] = {gld_u8(pb + r), 0u, 0u, 0u};
+            const uint32_t bwr[4] = {seg_bin<BITS>(pb, r), 0u, 0u, 0u};
             uint32_t o1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
             float g1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float h1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1426,13 +1471,13 @@ __device__ __forceinline__ void lpf_flush(const LpfBlock& a, int fg, uint32_t s0
     }
 }
 
-template <int PREC, int RM, int W, int MODE>
+template <int PREC, int RM, int W, int MODE, int BITS = 8>
 __device__ __forceinline__ void lpf_block(const LpfBlock& a, int64_t r0, int64_t r1, int fg,
                                           uint32_t s0, uint32_t ns, uint32_t* part,
                                           uint32_t part_slot0, uint32_t* lds) {
     lpf_zero<PREC, W>(a.B, ns, lds);
     __syncthreads();
-    lpf_accumulate<PREC, RM, W, MODE>(a, r0, r1, fg, s0, ns, lds);
+    lpf_accumulate<PREC, RM, W, MODE, BITS>(a, r0, r1, fg, s0, ns, lds);
     __syncthreads();
     lpf_flush<PREC, RM, W>(a, fg, s0, ns, part, part_slot0, lds);
 }

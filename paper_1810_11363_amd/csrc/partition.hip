@@ -700,6 +700,8 @@ static int check_part(const cbh_part* part, const cbh_problem* prob) {
             "problem does not match the partition (n, features, K, depth, loss)");
     CBH_ARG(count_stat(prob) || part->h[0] != nullptr,
             "the partition holds no h (made for RMSE without row weights), the problem needs it");
+    CBH_REQUIRE(!packed_bins(prob), CBH_EUNSUPPORTED,
+                "leaf-ordered rows take byte bins (the problem has packed bins)");
     return CBH_OK;
 }
 
@@ -714,6 +716,9 @@ int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out) {
     CBH_ARG(ctx && out, "NULL argument");
     *out = nullptr;
     int rc = validate_problem(prob);
+    if (rc) return rc;
+    CBH_REQUIRE(!packed_bins(prob), CBH_EUNSUPPORTED,
+                "leaf-ordered rows take byte bins (the problem has packed bins)");
     if (rc) return rc;
     CBH_REQUIRE(prob->depth <= 16, CBH_EUNSUPPORTED, "depth must be <= 16");
     cbh_part* p = new cbh_part();

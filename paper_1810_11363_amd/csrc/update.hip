@@ -19,6 +19,7 @@
 
 namespace cbh {
 
+template <int BITS>
 __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* __restrict__ bins,
                                                           const int64_t* __restrict__ seg,
                                                           int32_t F, const cbh_split* __restrict__ best,
@@ -33,34 +34,91 @@ __global__ __launch_bounds__(256) void apply_split_kernel(const uint8_t* const* 
         k = 255;
     }
     const uint8_t* __restrict__ col = bins[f];
-    const int64_t sstride = seg ? seg[f] : 16;   // bytes between 16-row segments
+    // bytes between 16-row segments (packed bins: plain columns)
+    const int64_t sstride = seg ? seg[f] : seg_bytes<BITS>();
     const uint32_t bit = 1u << level;
     const int64_t n8 = n / 8;
-    const bool vec = ((reinterpret_cast<uintptr_t>(col) & 7) == 0);
+    const bool vec = ((reinterpret_cast<uintptr_t>(col) & (BITS == 8 ? 7 : 3)) == 0);
     const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const int64_t stride = int64_t(gridDim.x) * 256;
     if (vec) {
         for (int64_t q = tid; q < n8; q += stride) {
-            // rows 8q .. 8q+7 lie in one 16-row segment
-            const uint2 b = *reinterpret_cast<const uint2*>(col + (q >> 1) * sstride + 8 * (q & 1));
+            // rows 8q .. 8q+7 lie in one 16-row segment: half of it
+            const uint8_t* half = col + (q >> 1) * sstride;
+            uint32_t bv[8];
+            if constexpr (BITS == 8) {
+                const uint2 b = *reinterpret_cast<const uint2*>(half + 8 * (q & 1));
+#pragma unroll
+                for (int r = 0; r < 8; ++r) bv[r] = ((r < 4 ? b.x : b.y) >> (8 * (r & 3))) & 255u;
+            } else if constexpr (BITS == 4) {
+                const uint32_t w = *reinterpret_cast<const uint32_t*>(half + 4 * (q & 1));
+#pragma unroll
+                for (int r = 0; r < 8; ++r) bv[r] = (w >> (8 * (r & 3) + 4 * (r >> 2))) & 15u;
+            } else {
+                const uint32_t b = half[q & 1];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) bv[r] = (b >> r) & 1u;
+            }
             uint4 l = level == 0 ? make_uint4(0u, 0u, 0u, 0u)
                                  : reinterpret_cast<const uint4*>(leaf)[q];
             uint32_t lw[4] = {l.x, l.y, l.z, l.w};
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const uint32_t bv = ((r < 4 ? b.x : b.y) >> (8 * (r & 3))) & 255u;
-                if ((int)bv > k) lw[r >> 1] |= bit << (16 * (r & 1));
-            }
+            for (int r = 0; r < 8; ++r)
+                if ((int)bv[r] > k) lw[r >> 1] |= bit << (16 * (r & 1));
             reinterpret_cast<uint4*>(leaf)[q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
         }
         for (int64_t i = n8 * 8 + tid; i < n; i += stride) {
             const uint32_t old = level == 0 ? 0u : leaf[i];
-            leaf[i] = (uint16_t)(old | (((int)col[(i >> 4) * sstride + (i & 15)] > k) ? bit : 0u));
+            const uint32_t bv = seg_bin<BITS>(col + (i >> 4) * sstride, (int)(i & 15));
+            leaf[i] = (uint16_t)(old | (((int)bv > k) ? bit : 0u));
         }
     } else {
         for (int64_t i = tid; i < n; i += stride) {
             const uint32_t old = level == 0 ? 0u : leaf[i];
-            leaf[i] = (uint16_t)(old | (((int)col[(i >> 4) * sstride + (i & 15)] > k) ? bit : 0u));
+            const uint32_t bv = seg_bin<BITS>(col + (i >> 4) * sstride, (int)(i & 15));
+            leaf[i] = (uint16_t)(old | (((int)bv > k) ? bit : 0u));
+        }
+    }
+}
+
+// Packed bins from byte bins (cbh_pack_bins): one thread per (feature,
+// 16-row segment); rows past n pack as 0.
+template <int BITS>
+__global__ __launch_bounds__(256) void pack_bins_kernel(const uint8_t* const* __restrict__ bins,
+                                                        const int64_t* __restrict__ seg,
+                                                        uint8_t* const* __restrict__ out,
+                                                        int32_t F, int64_t n, int64_t n_seg,
+                                                        uint32_t* __restrict__ flags) {
+    const int64_t total = n_seg * F;
+    for (int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * 256) {
+        const int f = (int)(t / n_seg);
+        const int64_t sg = t - int64_t(f) * n_seg;
+        const uint8_t* src = bins[f] + sg * seg_stride_of(seg, f);
+        const int rows = (int)min<int64_t>(16, n - sg * 16);
+        uint32_t v[16];
+        bool over = false;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            v[r] = r < rows ? (uint32_t)src[r] : 0u;
+            over |= v[r] >= (1u << BITS);
+            v[r] &= (1u << BITS) - 1u;
+        }
+        if (over) atomicOr(flags, FLAG_PACK_RANGE);
+        // byte stores: the output columns need no alignment
+        uint8_t* dst = out[f] + sg * seg_bytes<BITS>();
+        if constexpr (BITS == 4) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    dst[4 * k + j] = (uint8_t)(v[8 * k + j] | (v[8 * k + 4 + j] << 4));
+        } else {
+            uint32_t b = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) b |= v[r] << r;
+            dst[0] = (uint8_t)b;
+            dst[1] = (uint8_t)(b >> 8);
         }
     }
 }
@@ -228,8 +286,16 @@ static int grid_rows(const cbh_ctx* ctx, int64_t n, int per_thread = 1) {
 
 int launch_apply(const cbh_ctx* ctx, const cbh_problem* p, int32_t level, const cbh_split* best,
                  hipStream_t s) {
-    apply_split_kernel<<<grid_rows(ctx, p->n, 8), 256, 0, s>>>(p->bins, p->seg_stride, p->n_features, best,
-                                                               p->leaf, p->n, level);
+    const unsigned g = grid_rows(ctx, p->n, 8);
+    if (p->bin_bits == 4)
+        apply_split_kernel<4><<<g, 256, 0, s>>>(p->bins, p->seg_stride, p->n_features, best,
+                                                p->leaf, p->n, level);
+    else if (p->bin_bits == 1)
+        apply_split_kernel<1><<<g, 256, 0, s>>>(p->bins, p->seg_stride, p->n_features, best,
+                                                p->leaf, p->n, level);
+    else
+        apply_split_kernel<8><<<g, 256, 0, s>>>(p->bins, p->seg_stride, p->n_features, best,
+                                                p->leaf, p->n, level);
     CBH_LAUNCHED();
     return CBH_OK;
 }
@@ -470,6 +536,28 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
         }
         CBH_LAUNCHED();
     }
+    return CBH_OK;
+}
+
+int cbh_pack_bins(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride,
+                  int32_t n_features, int64_t n, int32_t bits, uint8_t* const* packed,
+                  void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && bins != nullptr && packed != nullptr, "NULL argument");
+    CBH_ARG(n >= 1 && n_features >= 1, "n and n_features must be >= 1");
+    CBH_ARG(bits == 4 || bits == 1, "bits must be 4 or 1 (got %d)", bits);
+    const int64_t n_seg = (n + 15) / 16;
+    const int64_t total = n_seg * n_features;
+    const unsigned g = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((total + 255) / 256, int64_t(ctx->num_cus) * 16));
+    hipStream_t s = (hipStream_t)stream;
+    if (bits == 4)
+        pack_bins_kernel<4><<<g, 256, 0, s>>>(bins, seg_stride, packed, n_features, n, n_seg,
+                                              ctx->d_flags);
+    else
+        pack_bins_kernel<1><<<g, 256, 0, s>>>(bins, seg_stride, packed, n_features, n, n_seg,
+                                              ctx->d_flags);
+    CBH_LAUNCHED();
     return CBH_OK;
 }
 
