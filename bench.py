@@ -53,15 +53,16 @@ PRECISIONS = {"fp32": 0, "twofloat": 1, "int16": 2, "f64": 3}
 DTYPES = {"fp32": "f32", "twofloat": "f32x2", "int16": "i16->i64", "f64": "f64"}
 
 
-def hist_bytes_per_level(n, F, K, level, rmse, precision):
+def hist_bytes_per_level(n, F, K, level, rmse, precision, bin_bits=8):
     """Algorithmic bytes one histogram build must read: the bin of every
-    (row, feature), the row's gradient statistics and (after level 0) its leaf."""
+    (row, feature) (a byte, or bin_bits bits when packed), the row's gradient
+    statistics and (after level 0) its leaf."""
     if precision == 2:
         grad = 4 * K                       # int16 (g, h) code pair
     else:
         grad = 4 * K if rmse else 8 * K    # g (and h) float32
     leaf = 2 if level > 0 else 0
-    return n * F + n * grad + n * leaf
+    return n * F * bin_bits // 8 + n * grad + n * leaf
 
 
 # LDS atomic issue rates (lane updates per clock per CU, the 64 lanes of a
@@ -126,6 +127,8 @@ WORKLOADS = {
     "apply": dict(tag="apply_100k_8000_trees", n=100_000, steps=20, cpu_rows=20_000, cpu_trees=0),
     "combine": dict(tag="combine_10m_pairs", n=10_000_000, steps=10, cpu_rows=1_000_000,
                     cpu_trees=0),
+    "packed": dict(tag="packed_10m_logloss", n=10_000_000, steps=20, cpu_rows=0, cpu_trees=0,
+                   hist_trees=4, autotune="off", warmup_s=0.5),
 }
 # per-run defaults a workload may override
 RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,twofloat,int16",
@@ -406,7 +409,8 @@ def time_form(bst, name, args, rmse):
                       for s in range(n_hist)]
     sec_per_tree = total_ms / 1e3 / args.steps
     rf_per_tree = n * F * depth
-    bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec) for l in range(depth)])
+    bytes_lvl = np.array([hist_bytes_per_level(n, F, K, l, rmse, prec, bst.bin_bits)
+                          for l in range(depth)])
     hist_s_per_tree = hist_ms.sum(axis=1).mean() / 1e3
     achieved = float(bytes_lvl.sum() / hist_s_per_tree / 1e9)
     # rows each level's build accumulates (the smaller child only, where a
@@ -1101,6 +1105,50 @@ def time_ordered(bst, args, rmse):
     }
 
 
+def run_packed(args):
+    """Packed bins (Sec. 5) on the dense numeric workload: the same data
+    quantized to 15 bins read as bytes and as 4-bit packed bins, and to 2 bins
+    (binary) as bytes and as 1-bit packed bins; the headline form and int16
+    on each layout, subtraction on, rows in their original order."""
+    import torch  # noqa: F401
+
+    import datagen
+    from paper_1810_11363_amd.booster import GpuBooster
+
+    measure_lds_rates()
+    p = datagen.make_c3(n=args.n)
+    print(f"# generated {p.name}: n={p.label.size}", file=sys.stderr, flush=True)
+    forms = [args.precision] + (["int16"] if args.precision != "int16" else [])
+    out = {"metric": "sec/tree on packed and byte bins", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"10M-row Logloss, {p.x_num.shape[0]} uniform numeric "
+                                  f"features quantized to 15 and to 2 bins, depth {p.depth}",
+                      "rows": int(p.label.size)},
+           "layouts": {}}
+    a = copy.copy(args)
+    a.no_cpu = True
+    for nb, bits in ((15, 4), (2, 1)):
+        p.num_bins = nb
+        bst = GpuBooster.from_problem(p, partition=False).prepare()
+        for b in (8, bits):
+            bst.set_bin_bits(b)
+            for f in forms:
+                r = time_form(bst, f, a, False)
+                r.pop("_snapshot", None)
+                key = f"{nb}_bins_{'bytes' if b == 8 else f'{b}_bit'}_{f}"
+                out["layouts"][key] = {k: r[k] for k in (
+                    "sec_per_tree", "hist_ms_per_level", "hist_G_row_features_per_s",
+                    "rows_accumulated_per_level", "roofline")}
+                print(f"# {key}: {r['sec_per_tree'] * 1e3:.3f} ms/tree", file=sys.stderr,
+                      flush=True)
+        bst.close()
+    L = out["layouts"]
+    for nb, bits in ((15, 4), (2, 1)):
+        for f in forms:
+            k8, kp = f"{nb}_bins_bytes_{f}", f"{nb}_bins_{bits}_bit_{f}"
+            L[kp]["speedup_vs_bytes"] = round(L[k8]["sec_per_tree"] / L[kp]["sec_per_tree"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1161,9 +1209,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(sharding over several GPUs is not built)"}))
         sys.exit(2)
-    if args.workload in ("c4", "apply", "combine"):
+    if args.workload in ("c4", "apply", "combine", "packed"):
         a = resolve(args, args.workload)
-        {"c4": run_batch, "apply": run_apply, "combine": run_combine}[args.workload](a)
+        {"c4": run_batch, "apply": run_apply, "combine": run_combine,
+         "packed": run_packed}[args.workload](a)
         return
     if args.workload != "headline":
         print(json.dumps(run_trees(resolve(args, args.workload))), flush=True)

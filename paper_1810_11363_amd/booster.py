@@ -103,6 +103,9 @@ class GpuBooster:
         # ordered boosting (Sec. 3): tree structures chosen on the gradients of
         # the supporting approximations of permutation t mod s
         self.ordered = bool(ordered)
+        # bins read by the trees: 8 (bytes) or packed 4 / 1 bits (set_bin_bits)
+        self.bin_bits = 8
+        self._packed = {}
         self._alloc()
 
     @classmethod
@@ -267,6 +270,35 @@ class GpuBooster:
         self._alloc_hists()
         self._choose_order()
 
+    def set_bin_bits(self, bits: int):
+        """Trees read packed bins (Sec. 5: 4 bits for features of at most 15
+        bins, 1 bit for binary ones) or bytes (8). Packed columns are made
+        once per width from the byte layout, which stays for the checks."""
+        bits = int(bits)
+        if bits not in (8, 4, 1):
+            raise ValueError("bits must be 8, 4 or 1")
+        if bits != 8:
+            if self.B > (1 << bits):
+                raise ValueError(f"{self.B} bins do not fit in {bits} bits")
+            if self.part is not None:
+                raise ValueError("packed bins take no leaf-ordered rows (partition=False)")
+        torch.cuda.synchronize(self.device)
+        self.drop_graphs()
+        if bits != 8 and bits not in self._packed:
+            n, F = self.n, self.F
+            nseg = (n + 15) // 16
+            pk = torch.empty((self.s, F, nseg * 2 * bits), dtype=torch.uint8, device=self.device)
+            tables = torch.tensor([[pk[r, f].data_ptr() for f in range(F)] for r in range(self.s)],
+                                  dtype=torch.int64, device=self.device)
+            for r in range(self.s):
+                seg = self.seg_table[r] if self.seg_table is not None else None
+                cb.cbh_pack_bins(self.ctx, self.col_table[r], seg, F, n, bits, tables[r],
+                                 self.stream)
+            cb.cbh_sync(self.ctx, self.stream)
+            self._packed[bits] = (pk, tables)
+        self.bin_bits = bits
+        self.probs = [self.problem(r) for r in range(self.s)]
+
     def problem(self, r: int) -> cb.cbh_problem:
         p = cb.cbh_problem()
         p.n = self.n
@@ -285,6 +317,10 @@ class GpuBooster:
         p.leaf = self.leaf.data_ptr()
         p.approx = self.approx.data_ptr()
         p.seg_stride = self.seg_table[r].data_ptr() if self.seg_table is not None else None
+        if self.bin_bits != 8:
+            p.bins = self._packed[self.bin_bits][1][r].data_ptr()
+            p.seg_stride = None
+            p.bin_bits = self.bin_bits
         return p
 
     def bins_host(self, r: int) -> np.ndarray:
