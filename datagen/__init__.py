@@ -63,6 +63,7 @@ class Problem:
     y_shift: int = 0
     ts_lo: float = 0.0
     ts_hi: float = 1.0
+    extra_priors: list = field(default_factory=list)  # priors beside priors[t], every target
 
     @property
     def n(self) -> int:
@@ -396,6 +397,46 @@ def random_small(seed: int, n: int, F_num: int = 3, F_cat: int = 1, C: int = 5,
                 iterations=3, lr=0.1, l2=1.0, num_bins=num_bins,
                 ts_bins=num_bins, a=1.0)
     return _finish_targets(p)
+
+
+def make_interactions(n: int = 20_000, loss: int = LOGLOSS, K: int = 1, seed: int = 0,
+                      depth: int = 4, C: tuple = (6, 8, 5), s: int = 1,
+                      extra_priors: tuple = (0.0, 1.0)) -> Problem:
+    """A workload whose target depends on pairs of categories (the case
+    feature combinations exist for, Sec. 2): 3 numeric N(0,1) features at 16
+    bins, categorical features of small cardinalities C (Zipf(1.1)), and a
+    target driven by a seeded effect table of the (c0, c1) pair, another of
+    (c1, c2) crossed with the sign of x0, plus a small numeric term. Statistic
+    columns use the problem's prior and the extra priors. Logloss (0/1),
+    RMSE (real) or MultiClass (K classes)."""
+    cfg = 6
+    g = np.random.default_rng(np.random.SeedSequence([BASE_SEED, cfg, 1000 + seed]))
+    x = g.standard_normal((3, n), dtype=np.float32)
+    ids = [zipf_ids(g, n, c, 1.1) for c in C]
+    cats = [raw_values(g, c)[d] for c, d in zip(C, ids)]
+    t01 = g.normal(0.0, 1.5, (C[0], C[1], max(K, 1)))
+    t12 = g.normal(0.0, 1.0, (C[1], C[2], max(K, 1)))
+    sgn = np.where(x[0] > 0, 1.0, -1.0)[:, None]
+    z = t01[ids[0], ids[1]] + sgn * t12[ids[1], ids[2]] + 0.3 * x[1].astype(np.float64)[:, None]
+    if loss == RMSE:
+        y = (z[:, 0] + g.normal(0.0, 0.1, n)).astype(np.float32)
+    elif loss == LOGLOSS:
+        y = (g.random(n) < _sigmoid(z[:, 0])).astype(np.float32)
+    else:
+        e = np.exp(z - z.max(axis=1, keepdims=True))
+        pr = e / e.sum(axis=1, keepdims=True)
+        y = (pr.cumsum(axis=1) < g.random(n)[:, None]).sum(axis=1).clip(0, K - 1)
+        y = y.astype(np.float32)
+    p = Problem(f"interactions_{seed}", x, np.stack(cats), y, _perms(cfg, n, s, 3 + 10 * seed),
+                loss, K if loss == MULTICLASS else 1, depth=depth, iterations=5, lr=0.1,
+                l2=3.0, num_bins=16, ts_bins=16, a=1.0)
+    p = _finish_targets(p)
+    if loss != RMSE:
+        p.extra_priors = list(extra_priors)
+    else:
+        # extra priors in target units: the ends of the target range
+        p.extra_priors = [p.ts_lo, p.ts_hi][: len(extra_priors)]
+    return p
 
 
 CONFIGS = {

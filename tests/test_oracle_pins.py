@@ -697,3 +697,163 @@ def test_pack_bins_keeps_every_bin(oracle_lib, bits):
             assert np.all(diff // (16 * bits) == seg)
         # total set bits = sum of popcounts of the values
         assert int(bitsarr.sum()) == int(sum(bin(int(v)).count("1") for v in b))
+
+
+# ---------------------------------------------------------------------------
+# Greedy feature combinations and several priors (Sec. 2)
+
+def _brute_ts_bins(keys, perm, y_num, y_shift, a, prior, borders):
+    """Eq. (1) row by row over hashable per-row keys (any grouping values):
+    a row's statistic counts the strictly earlier positions with its key."""
+    sums, cnts = {}, {}
+    out = np.zeros(len(keys), np.uint8)
+    for r in perm:
+        k = keys[r]
+        num, den = sums.get(k, 0), cnts.get(k, 0)
+        ts = (float(num) * 2.0 ** -y_shift + a * prior) / (float(den) + a)
+        out[r] = sum(1 for b in borders if ts > b)
+        sums[k] = num + int(y_num[r])
+        cnts[k] = den + 1
+    return out
+
+
+def _brute_candidates(p, prep, t, splits):
+    """The candidate columns of a tree after the given splits, built without
+    the oracle's combination code: a combination's value per row is the
+    nested tuple of its parts' values, statistics are counted row by row."""
+    from oracle import boost
+    base_bins, _ = prep.tree_features(t)
+    F_num, T, Q = p.n_num, p.n_targets, prep.n_priors
+    F_base = base_bins.shape[0]
+    pl = boost.prior_lists(p)
+    perm = p.perms[t % p.perms.shape[0]]
+    combo_keys, cols = [], [base_bins[f] for f in range(F_base)]
+    for f, k in splits:
+        if f < 0:
+            v = [0] * p.n
+        elif f < F_num:
+            v = [int(b > k) for b in cols[f]]
+        elif f < F_base:
+            v = [int(x) for x in p.cat[(f - F_num) // (T * Q)]]
+        else:
+            j, c = divmod((f - F_base) // (T * Q), p.n_cat)
+            v = combo_keys[j][c]
+        level = []
+        for c in range(p.n_cat):
+            keys = [(v[i], int(p.cat[c][i])) for i in range(p.n)]
+            level.append(keys)
+            for tt in range(T):
+                for q in range(Q):
+                    cols.append(_brute_ts_bins(keys, perm, p.y_num[tt], p.y_shift, p.a,
+                                               pl[tt][q], prep.ts_borders))
+        combo_keys.append(level)
+    return np.stack(cols)
+
+
+@pytest.mark.parametrize("loss,K,seed", [(1, 1, 0), (0, 1, 1), (2, 3, 2)])
+def test_combination_candidates_brute_force(oracle_lib, loss, K, seed):
+    """Sec. 2 "Feature combinations": after each split, the split's value
+    (a categorical feature, a combination, or a numeric split's two values)
+    crossed with every categorical feature gives new candidate columns whose
+    ordered statistics (every target, every prior) count the earlier rows of
+    the same combined value. Forced split sequences reach every kind of
+    element: numeric, statistic column, combination column, no split."""
+    from oracle import boost
+    p = datagen.make_interactions(n=48, loss=loss, K=K, seed=seed, C=(3, 4, 2), depth=5)
+    prep = boost.prepare(p)
+    ct0 = boost.CombinationTree(prep, p, 0)
+    F_base = ct0.F_base
+    TQ = ct0.TQ
+    seqs = [
+        [(0, 7), (p.n_num, 5), (F_base + TQ, 3), (F_base + 4 * TQ + 1, 9)],
+        [(p.n_num + TQ + 1, 2), (-1, -1), (F_base + 2 * TQ, 1), (1, 3)],
+    ]
+    for seq in seqs:
+        ct = boost.CombinationTree(prep, p, 0)
+        for lvl, (f, k) in enumerate(seq):
+            ct.add_split(f, k)
+            bins, nb = ct.features()
+            want = _brute_candidates(p, prep, 0, seq[: lvl + 1])
+            assert bins.shape == want.shape == (F_base + (lvl + 1) * p.n_cat * TQ, p.n)
+            assert np.array_equal(bins, want), f"level {lvl}"
+            assert np.all(nb[F_base:] == prep.nb_ts)
+
+
+def test_combination_tree_splits_are_brute_force_best(oracle_lib):
+    """Every level of a combination tree takes the best split over that
+    level's candidates, scored by brute force with children built from rows;
+    the first level considers the tree's own columns only."""
+    from oracle import boost
+    p = datagen.make_interactions(n=40, loss=0, seed=3, C=(3, 3, 2), depth=3)
+    p.extra_priors = []
+    prep = boost.prepare(p)
+    approx = np.zeros((1, p.n))
+    B = max(int(prep.nb_num.max()), prep.nb_ts)
+    tree, ct = boost.fit_tree_combinations(prep, p, 0, approx, B)
+    g, h = oracle_lib.gradients(p.loss, p.K, np.zeros((1, p.n)), p.label)
+    leaf = np.zeros(p.n, np.uint16)
+    seq = []
+    for lvl, (f, k, _, _) in enumerate(tree.splits):
+        bins = _brute_candidates(p, prep, 0, seq)
+        nb = np.concatenate([prep.tree_features(0)[1],
+                             np.full(bins.shape[0] - ct.F_base, prep.nb_ts, np.int32)])
+        objs = brute.split_objectives(bins, nb, g, h, leaf, 1 << lvl, p.l2)
+        (bf, bk), _ = brute.best_by_objective(objs)
+        assert (f, k) == (bf, bk), f"level {lvl}"
+        if lvl == 0:
+            assert bins.shape[0] == ct.F_base
+        oracle_lib.apply_split(bins[f], k, lvl, leaf)
+        seq.append((f, k))
+
+
+def test_combination_with_itself_is_the_feature(oracle_lib):
+    """A categorical feature crossed with itself has the feature's own groups,
+    so its statistic columns equal the feature's; without categorical
+    features a combination tree is the classic tree."""
+    from oracle import boost
+    p = datagen.make_interactions(n=3000, loss=1, seed=4)
+    prep = boost.prepare(p)
+    ct = boost.CombinationTree(prep, p, 0)
+    for c in range(p.n_cat):
+        ct2 = boost.CombinationTree(prep, p, 0)
+        ct2.add_split(p.n_num + c * ct.TQ, 0)
+        bins, _ = ct2.features()
+        got = bins[ct.F_base + c * ct.TQ: ct.F_base + (c + 1) * ct.TQ]
+        want = bins[p.n_num + c * ct.TQ: p.n_num + (c + 1) * ct.TQ]
+        assert np.array_equal(got, want)
+    q = datagen.random_small(7, 300, F_num=4, F_cat=0, depth=4)
+    prep_q = boost.prepare(q)
+    tr_c, ap_c, _ = boost.fit(q, iterations=2, prep=prep_q, combinations=True)
+    tr_p, ap_p, _ = boost.fit(q, iterations=2, prep=prep_q)
+    assert [t.splits for t in tr_c] == [t.splits for t in tr_p]
+    assert np.array_equal(ap_c, ap_p)
+
+
+def test_several_priors_closed_form(oracle_lib):
+    """Sec. 2: one statistic column per prior. For one grouping, two priors
+    differ by a (P1 - P2) / (den + a) in every row (Eq. 1 is affine in P);
+    a category seen once has no earlier rows, so its statistic is the prior."""
+    o = oracle_lib
+    g0 = np.random.default_rng(46)
+    n = 500
+    cat = g0.integers(0, 9, n).astype(np.int32)
+    cat[:20] = 100 + np.arange(20)                  # singletons
+    y = g0.integers(0, 2, n).astype(np.int64)
+    perm = g0.permutation(n).astype(np.int32)
+    a = 2.0
+    res = {P: o.ordered_ts(cat, perm, y, 0, a, P) for P in (0.0, 0.25, 1.0)}
+    for P1, P2 in ((0.0, 1.0), (0.25, 0.0)):
+        _, den, t1, _ = res[P1]
+        _, _, t2, _ = res[P2]
+        np.testing.assert_allclose(t1 - t2, a * (P1 - P2) / (den + a), rtol=0, atol=1e-15)
+    for P, (_, den, ts, _) in res.items():
+        assert np.all(den[:20] == 0) and np.all(ts[:20] == P)
+    from oracle import boost
+    p = datagen.make_interactions(n=400, loss=1, seed=5)
+    prep = boost.prepare(p)
+    assert prep.n_priors == 3
+    for c in range(p.n_cat):
+        for q, P in enumerate(boost.prior_lists(p)[0]):
+            _, _, _, tb = o.ordered_ts(p.cat[c], p.perms[0], p.y_num[0], p.y_shift, p.a, P,
+                                       prep.ts_borders)
+            assert np.array_equal(prep.ts_bins[0, c * 3 + q], tb)
