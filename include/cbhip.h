@@ -354,6 +354,60 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
 int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* counts_out,
                         void* stream);
 
+/* Where a tree's split gets its categorical value per row, for greedy
+ * feature combinations (Sec. 2, "Feature combinations": after a split, the
+ * categorical features and combinations present in the tree are combined
+ * with every categorical feature of the dataset, and every split on a
+ * numeric feature counts as a categorical feature of two values). One entry
+ * per histogram feature of the problem the split was chosen on:
+ *   kind CBH_SOURCE_BINS    ptr is the feature's uint8 bins in the layout of
+ *                           cbh_problem.bins (byte bins; bin of row i at
+ *                           ptr + (i / 16) * seg_stride + i % 16); the value
+ *                           is 1 if bin > border, else 0 (a numeric split)
+ *   kind CBH_SOURCE_VALUES  ptr is an int32 [n] column of category values (the
+ *                           raw values of the categorical feature behind a
+ *                           statistic column, or a combination's ids); the
+ *                           value is ptr[i]                                  */
+#define CBH_SOURCE_BINS 0
+#define CBH_SOURCE_VALUES 1
+typedef struct cbh_split_source {
+    const void* ptr;
+    int64_t seg_stride;
+    int32_t kind;
+    int32_t reserved;
+} cbh_split_source;
+
+/* The categorical value of every row under a chosen split (Sec. 2, "Feature
+ * combinations"), read on the device so that no host round trip is needed
+ * between a level's argmax and the next level's combinations:
+ *   values_out[i] = per sources[split->feature] (see cbh_split_source);
+ *                   0 for every row when split->feature < 0 (no split).
+ *   split       device cbh_split (as written by cbh_score_splits)
+ *   sources     device cbh_split_source [n_sources]
+ *   values_out  device int32 [n]
+ * A feature index >= n_sources, an unknown kind or a NULL column writes 0
+ * and is reported by cbh_sync. Errors: CBH_EINVAL on NULL or n out of
+ * [0, 2^31 - 1]. */
+int cbh_split_values(cbh_ctx* ctx, const cbh_split* split, const cbh_split_source* sources,
+                     int32_t n_sources, int64_t n, int32_t* values_out, void* stream);
+
+/* Ordered target statistic of a grouping for one more prior (Sec. 2: several
+ * priors, a feature for each), from the numerators and counts that
+ * cbh_compute_ordered_ts wrote (num_out, den_out) for that grouping:
+ *   ts = (num * 2^-y_shift + a * prior) / (den + a)   (double, this order),
+ *   bin = number of ts_borders strictly below ts.
+ * Bit for bit what cbh_compute_ordered_ts writes when called with `prior`.
+ *   num         device int64 [n]  (one target's numerators)
+ *   den         device int32 [n]
+ *   ts_borders  device double [n_ts_borders] increasing (NULL if no bins)
+ *   ts_bin_out  device uint8 [n] or NULL
+ *   ts_out      device double [n] or NULL (not both NULL)
+ * Errors: CBH_EINVAL on NULL arguments, a <= 0, y_shift outside [0, 62] or
+ * more than 255 borders. */
+int cbh_ts_bins(cbh_ctx* ctx, const int64_t* num, const int32_t* den, int64_t n,
+                int32_t y_shift, double a, double prior, const double* ts_borders,
+                int32_t n_ts_borders, uint8_t* ts_bin_out, double* ts_out, void* stream);
+
 /* Packed bins from byte bins (Sec. 5 feature packing; layout at
  * cbh_problem.bin_bits): feature f's bins (the byte layout of
  * cbh_problem.bins with seg_stride, n rows) are written to packed[f], a

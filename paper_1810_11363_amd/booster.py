@@ -56,7 +56,8 @@ class GpuBooster:
     def __init__(self, *, x_num, cat, label, perms, y_num, y_shift, priors, loss, K, depth,
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
                  subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled",
-                 borders=None, partition=None, ordered=False):
+                 borders=None, partition=None, ordered=False, extra_priors=(),
+                 combinations=False):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -91,7 +92,18 @@ class GpuBooster:
         self.F_num, self.F_cat = self.x_num.shape[0], self.cat.shape[0]
         self.T = self.y_num.shape[0] if self.F_cat else 0
         self.s = self.perms.shape[0] if self.F_cat else 1
-        self.F = self.F_num + self.F_cat * self.T
+        # several priors (Sec. 2): target t's statistic columns use priors[t]
+        # and then every extra prior, one column each
+        self.extra_priors = [float(v) for v in extra_priors]
+        self.Q = 1 + len(self.extra_priors)
+        self.F = self.F_num + self.F_cat * self.T * self.Q
+        # greedy feature combinations (Sec. 2): candidate columns added level
+        # by level from the tree's own splits (direct builds in the original
+        # row order)
+        self.combinations = bool(combinations) and self.F_cat > 0
+        if self.combinations and ordered:
+            raise ValueError("combination trees are built in the plain scheme only")
+        self.F_hist = self.F
         # numeric borders chosen elsewhere (e.g. on the whole dataset before a
         # split into folds), one float32 array per numeric feature; None: chosen
         # here from x_num
@@ -114,7 +126,8 @@ class GpuBooster:
         return cls(x_num=p.x_num, cat=p.cat, label=p.label, perms=p.perms, y_num=p.y_num,
                    y_shift=p.y_shift, priors=p.priors, loss=p.loss, K=p.K, depth=p.depth,
                    lr=p.lr, l2=p.l2, num_bins=p.num_bins, ts_bins=p.ts_bins, a=p.a,
-                   ts_lo=p.ts_lo, ts_hi=p.ts_hi, **kw)
+                   ts_lo=p.ts_lo, ts_hi=p.ts_hi,
+                   extra_priors=getattr(p, "extra_priors", []), **kw)
 
     # ---------------------------------------------------------------- buffers
     def _alloc(self):
@@ -122,8 +135,8 @@ class GpuBooster:
         ld = _ld(n)
         self.ld = ld
         self.num_bins_d = torch.empty((max(self.F_num, 1), ld), dtype=torch.uint8, device=d)
-        self.ts_bins_d = torch.empty((self.s, max(self.F_cat * self.T, 1), ld), dtype=torch.uint8,
-                                     device=d)
+        self.ts_bins_d = torch.empty((self.s, max(self.F_cat * self.T * self.Q, 1), ld),
+                                     dtype=torch.uint8, device=d)
         self.label = torch.from_numpy(self.label_h).to(d)
         self.g = torch.empty((K, n), dtype=torch.float32, device=d)
         self.h = torch.empty((K, n), dtype=torch.float32, device=d)
@@ -154,7 +167,11 @@ class GpuBooster:
 
     def _hist_bytes(self, level: int) -> int:
         esz = 4 if self.precision == cb.CBH_PREC_FP32 else 8
-        return (1 << level) * self.F * self.B * 2 * self.K * esz
+        return (1 << level) * self.F_hist * self.B * 2 * self.K * esz
+
+    def prior_lists(self):
+        """Priors of every statistic target: its own, then the extra ones."""
+        return [[self.priors[t]] + self.extra_priors for t in range(self.T)]
 
     # ----------------------------------------------------------- preprocessing
     def prepare(self):
@@ -198,8 +215,26 @@ class GpuBooster:
             tmp = torch.empty((self.T, n), dtype=torch.uint8, device=d) if self.ld != n else None
             torch.cuda.synchronize(d)
             t4 = time.perf_counter()
+            if self.Q > 1:
+                num_t = torch.empty((self.T, n), dtype=torch.int64, device=d)
+                den_t = torch.empty(n, dtype=torch.int32, device=d)
+                pl = self.prior_lists()
             for r in range(self.s):
                 for c in range(self.F_cat):
+                    if self.Q > 1:
+                        # the grouping once, then one column per (target, prior)
+                        cb.cbh_compute_ordered_ts(self.ctx, cat_d[c], perm_d[r], n, y_d, self.T,
+                                                  self.y_shift, yabs, self.a, self.priors,
+                                                  None, 0, num_out=num_t, den_out=den_t,
+                                                  stream=st)
+                        for t in range(self.T):
+                            for q in range(self.Q):
+                                cb.cbh_ts_bins(self.ctx, num_t[t], den_t, n, self.y_shift,
+                                               self.a, pl[t][q], ts_b, self.ts_bins - 1,
+                                               ts_bin_out=self.ts_bins_d[r, (c * self.T + t)
+                                                                         * self.Q + q],
+                                               stream=st)
+                        continue
                     dst = self.ts_bins_d[r, c * self.T:(c + 1) * self.T]
                     out = tmp if tmp is not None else dst
                     cb.cbh_compute_ordered_ts(self.ctx, cat_d[c], perm_d[r], n, y_d, self.T,
@@ -217,10 +252,10 @@ class GpuBooster:
         cols, nbs = [], []
         for r in range(self.s):
             ptrs = [self.num_bins_d[f].data_ptr() for f in range(self.F_num)]
-            ptrs += [self.ts_bins_d[r, j].data_ptr() for j in range(self.F_cat * self.T)]
+            ptrs += [self.ts_bins_d[r, j].data_ptr() for j in range(self.F_cat * self.T * self.Q)]
             cols.append(ptrs)
-            nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.T, self.ts_bins,
-                                                       np.int32)]))
+            nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.T * self.Q,
+                                                       self.ts_bins, np.int32)]))
         self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
         self.seg_table = None
         if self.layout == "tiled":
@@ -241,20 +276,141 @@ class GpuBooster:
             self.seg_table = torch.full((self.s, self.F), 16 * self.F, dtype=torch.int64,
                                         device=d)
         self.nbins_table = torch.from_numpy(np.stack(nbs).astype(np.int32)).to(d)
+        if self.combinations:
+            self._alloc_combos(ts_b)
         self._alloc_hists()
         self.probs = [self.problem(r) for r in range(self.s)]
+        if self.combinations:
+            self._choose_order()
+            return self
         if self.partition or (self.partition is None and (self.K > 1 or self.depth >= 8)):
             self.part = cb.cbh_part_create(self.ctx, self.probs[0])
         self._choose_order()
         return self
 
     def _choose_order(self):
-        if self.part is None:
+        if self.part is None or self.combinations:
             self.use_part = False
         elif self.partition is not None:
             self.use_part = bool(self.partition)
         else:
             self.use_part = self.K > 1 or self.precision != cb.CBH_PREC_INT16
+
+    def _alloc_combos(self, ts_b):
+        """Device state of combination trees: the combinations' ids and
+        statistic bins (rewritten by every tree), and per permutation the
+        extended column tables (the tree's columns, then every combination
+        column a tree can reach) and the split sources of every column."""
+        d, n, ld = self.device, self.n, self.ld
+        D, Cn, TQ = max(self.depth - 1, 1), self.F_cat, self.T * self.Q
+        self.F_combo = (self.depth - 1) * Cn * TQ
+        self.F_hist = self.F + self.F_combo
+        self.ts_borders_d = ts_b
+        self.cat_d = torch.from_numpy(self.cat).to(d)
+        self.perm_dc = torch.from_numpy(self.perms).to(d)
+        self.y_dc = torch.from_numpy(self.y_num).to(d)
+        self.y_abs = int(np.abs(self.y_num).max()) if self.y_num.size else 0
+        self.combo_ids = torch.zeros((D, Cn, n), dtype=torch.int32, device=d)
+        self.combo_bins = torch.zeros((D, Cn, TQ, ld), dtype=torch.uint8, device=d)
+        self.num_tmp = torch.empty((self.T, n), dtype=torch.int64, device=d)
+        self.den_tmp = torch.empty(n, dtype=torch.int32, device=d)
+        self.elem = torch.empty(n, dtype=torch.int32, device=d)
+        self.ndist = torch.empty(1, dtype=torch.int64, device=d)
+        combo_ptrs = [self.combo_bins[j, c, q].data_ptr() for j in range(self.depth - 1)
+                      for c in range(Cn) for q in range(TQ)]
+        base = self.col_table.cpu().numpy()
+        seg = (self.seg_table.cpu().numpy() if self.seg_table is not None
+               else np.full((self.s, self.F), 16, np.int64))
+        nbb = self.nbins_table.cpu().numpy()
+        self.col_x = torch.tensor(np.concatenate(
+            [base, np.tile(np.array(combo_ptrs, np.int64), (self.s, 1))], axis=1),
+            dtype=torch.int64, device=d)
+        self.seg_x = torch.tensor(np.concatenate(
+            [seg, np.full((self.s, self.F_combo), 16, np.int64)], axis=1), dtype=torch.int64,
+            device=d)
+        self.nb_x = torch.tensor(np.concatenate(
+            [nbb, np.full((self.s, self.F_combo), self.ts_bins, np.int32)], axis=1),
+            dtype=torch.int32, device=d)
+        srcs = []
+        for r in range(self.s):
+            a = np.zeros(self.F_hist, dtype=[("ptr", np.uint64), ("seg", np.int64),
+                                              ("kind", np.int32), ("res", np.int32)])
+            for f in range(self.F_hist):
+                if f < self.F_num:
+                    a[f] = (base[r, f], seg[r, f], cb.CBH_SOURCE_BINS, 0)
+                elif f < self.F:
+                    c = (f - self.F_num) // TQ
+                    a[f] = (self.cat_d[c].data_ptr(), 0, cb.CBH_SOURCE_VALUES, 0)
+                else:
+                    j, c = divmod((f - self.F) // TQ, Cn)
+                    a[f] = (self.combo_ids[j, c].data_ptr(), 0, cb.CBH_SOURCE_VALUES, 0)
+            srcs.append(torch.from_numpy(a.view(np.uint8).copy()).to(d))
+        self.src_x = srcs
+
+    def combo_problem(self, r: int, level: int) -> cb.cbh_problem:
+        """The problem a combination tree of permutation r sees at `level`:
+        the tree's columns and the combination columns of the levels above."""
+        p = self.problem(r)
+        p.bins = self.col_x[r].data_ptr()
+        p.seg_stride = self.seg_x[r].data_ptr()
+        p.n_bins = self.nb_x[r].data_ptr()
+        p.n_features = self.F + level * self.F_cat * self.T * self.Q
+        return p
+
+    def combo_level(self, t: int, level: int):
+        """Histograms (direct, every candidate) and the split of `level`."""
+        pr = self.combo_problem(t % self.s, level)
+        if level == 0 and self.precision == cb.CBH_PREC_INT16:
+            cb.cbh_quantize_gradients(self.ctx, pr, self.stream)
+        cb.cbh_build_histograms(self.ctx, pr, level, self.precision, self.hist_ptr(level),
+                                self.stream)
+        cb.cbh_score_splits(self.ctx, pr, level, self.hist_ptr(level), self.precision, self.l2,
+                            self.split_ptr(level), None, self.stream)
+
+    def combo_advance(self, t: int, level: int):
+        """Set the level's leaf bit; then the split's value per row (on the
+        device, from the split itself) is combined with every categorical
+        feature, and each combination's statistic bins (every target and
+        prior, the tree's permutation) become candidates below."""
+        r = t % self.s
+        pr = self.combo_problem(r, level)
+        ctx, st, n = self.ctx, self.stream, self.n
+        cb.cbh_apply_split(ctx, pr, level, self.split_ptr(level), st)
+        if level + 1 >= self.depth:
+            return
+        cb.cbh_split_values(ctx, self.split_ptr(level), self.src_x[r], pr.n_features, n,
+                            self.elem, st)
+        pl = self.prior_lists()
+        for c in range(self.F_cat):
+            ids = self.combo_ids[level, c]
+            cb.cbh_combine_categories(ctx, self.elem, self.cat_d[c], n, ids, self.ndist, st)
+            cb.cbh_compute_ordered_ts(ctx, ids, self.perm_dc[r], n, self.y_dc, self.T,
+                                      self.y_shift, self.y_abs, self.a, self.priors, None, 0,
+                                      num_out=self.num_tmp, den_out=self.den_tmp, stream=st)
+            for t_ in range(self.T):
+                for q in range(self.Q):
+                    cb.cbh_ts_bins(ctx, self.num_tmp[t_], self.den_tmp, n, self.y_shift, self.a,
+                                   pl[t_][q], self.ts_borders_d, self.ts_bins - 1,
+                                   ts_bin_out=self.combo_bins[level, c, t_ * self.Q + q],
+                                   stream=st)
+
+    def _combo_tree(self, t: int, counts: bool = False):
+        for lvl in range(self.depth):
+            self.combo_level(t, lvl)
+            self.combo_advance(t, lvl)
+        pr = self.combo_problem(t % self.s, self.depth - 1)
+        cb.cbh_update_approx(self.ctx, pr, self.hist_ptr(self.depth - 1), self.precision,
+                             self.split_ptr(self.depth - 1), self.lr, self.l2, self.leaf_values,
+                             self.leaf_counts if counts else None, self.stream)
+
+    def combo_bins_host(self, level: int) -> np.ndarray:
+        """uint8 [level * F_cat * T * Q][n]: the combination columns that are
+        candidates at `level` (for checks)."""
+        m = level * self.F_cat * self.T * self.Q
+        if m == 0:
+            return np.zeros((0, self.n), np.uint8)
+        cols = self.combo_bins[:level].reshape(-1, self.ld)[:, : self.n]
+        return cols.cpu().numpy()
 
     def _alloc_hists(self):
         hb = max(256, self._hist_bytes(self.depth - 1))
@@ -282,6 +438,8 @@ class GpuBooster:
                 raise ValueError(f"{self.B} bins do not fit in {bits} bits")
             if self.part is not None:
                 raise ValueError("packed bins take no leaf-ordered rows (partition=False)")
+            if self.combinations:
+                raise ValueError("combination trees read byte bins")
         torch.cuda.synchronize(self.device)
         self.drop_graphs()
         if bits != 8 and bits not in self._packed:
@@ -409,6 +567,11 @@ class GpuBooster:
         objects with a record(stream) method, recorded around each level's
         histogram build; then the levels are issued one call at a time."""
         pr = self.probs[t % self.s]
+        if self.combinations:
+            if events is not None:
+                raise ValueError("combination trees take no events")
+            self._combo_tree(t, counts)
+            return
         if self.ordered:
             if events is not None or counts:
                 raise ValueError("ordered trees take no events or counts")
@@ -445,6 +608,8 @@ class GpuBooster:
     def _capture(self, t: int, stamps=None):
         """A library-owned graph of tree t (cbh_graph_capture_tree), captured
         on a side stream of default priority."""
+        if self.combinations:
+            raise ValueError("combination trees run eagerly (no tree graphs)")
         cap = torch.cuda.Stream(self.device)
         torch.cuda.synchronize(self.device)
         g = cb.cbh_graph_capture_tree(self.ctx, self.probs[t % self.s],
@@ -500,6 +665,8 @@ class GpuBooster:
         each tree reading the feature table of its own permutation. Applied
         to the trees of `fit`, this gives the training approx bit for bit."""
         d = self.device
+        if self.combinations:
+            raise ValueError("predict takes trees without combination columns")
         if approx is None:
             approx = torch.zeros((self.K, self.n), dtype=torch.float64, device=d)
         for t, tr in enumerate(trees):

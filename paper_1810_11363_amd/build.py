@@ -26,7 +26,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["context.hip", "preprocess.hip", "histogram.hip", "score.hip", "update.hip",
            "batched.hip", "autotune.hip", "partition.hip", "instrument.hip", "tree.hip",
-           "ordered.hip"]
+           "ordered.hip", "combos.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-fhip-fp32-correctly-rounded-divide-sqrt",

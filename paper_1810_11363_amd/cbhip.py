@@ -43,6 +43,7 @@ EXPORTS = [
     "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts", "cbh_pack_bins",
     "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
+    "cbh_split_values", "cbh_ts_bins",
 ]
 
 
@@ -64,6 +65,14 @@ class cbh_ordered(C.Structure):
 class cbh_split(C.Structure):
     _fields_ = [("feature", C.c_int32), ("border", C.c_int32), ("score", C.c_float),
                 ("margin", C.c_float)]
+
+
+CBH_SOURCE_BINS, CBH_SOURCE_VALUES = 0, 1
+
+
+class cbh_split_source(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("seg_stride", C.c_int64), ("kind", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class CbhError(RuntimeError):
@@ -112,6 +121,8 @@ def _load():
                             C.c_int),
         "cbh_combine_categories": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
         "cbh_category_counts": ([vp, vp, i64, vp, vp], C.c_int),
+        "cbh_split_values": ([vp, vp, vp, i32, i64, vp, vp], C.c_int),
+        "cbh_ts_bins": ([vp, vp, vp, i64, i32, dbl, dbl, vp, i32, vp, vp, vp], C.c_int),
         "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
         "cbh_batch_destroy": ([vp], None),
@@ -519,3 +530,15 @@ def cbh_combine_categories(ctx, cat_a, cat_b, n: int, ids_out, n_distinct_out, s
 def cbh_category_counts(ctx, ids, n: int, counts_out, stream=None):
     return _check(_lib.cbh_category_counts(ctx, _ptr(ids), int(n), _ptr(counts_out),
                                            _stream(stream)))
+
+
+def cbh_split_values(ctx, split, sources, n_sources: int, n: int, values_out, stream=None):
+    return _check(_lib.cbh_split_values(ctx, _ptr(split), _ptr(sources), int(n_sources), int(n),
+                                        _ptr(values_out), _stream(stream)))
+
+
+def cbh_ts_bins(ctx, num, den, n: int, y_shift: int, a: float, prior: float, ts_borders,
+                n_ts_borders: int, ts_bin_out=None, ts_out=None, stream=None):
+    return _check(_lib.cbh_ts_bins(ctx, _ptr(num), _ptr(den), int(n), int(y_shift), float(a),
+                                   float(prior), _ptr(ts_borders), int(n_ts_borders),
+                                   _ptr(ts_bin_out), _ptr(ts_out), _stream(stream)))

@@ -96,6 +96,35 @@ def normalized_err(x, ref, mag, slack=None):
     return float(np.max(d[~zero] / mag[~zero]))
 
 
+def cell_bound(precision, counts):
+    """Normalised error bound of a histogram cell of m rows in a form:
+    float32 sums in any order are within (m - 1) u of the sum of magnitudes
+    (u = 2^-24, first order), so large cells may exceed FP32_TOL; the
+    compensated form carries every addition's error exactly in a float32
+    low word whose own roundings add up to about (m u)^2; the float64 form
+    stays below TWOFLOAT_TOL for any m here."""
+    m = np.asarray(counts, np.float64)
+    u = 2.0 ** -24
+    if precision == FP32:
+        return np.maximum(FP32_TOL, (m - 1.0) * u)
+    if precision == TWOFLOAT:
+        return np.maximum(TWOFLOAT_TOL, (m * u) ** 2)
+    return np.full_like(m, TWOFLOAT_TOL)
+
+
+def bound_ratio(x, ref, mag, counts, precision):
+    """Largest ratio of a cell's normalised error to its bound (cell_bound);
+    counts broadcast to x. <= 1 passes."""
+    x, ref, mag = np.asarray(x, np.float64), np.asarray(ref, np.float64), np.asarray(mag, np.float64)
+    d = np.abs(x - ref)
+    zero = mag == 0
+    assert np.all(d[zero] == 0), "empty cells differ"
+    if (~zero).sum() == 0:
+        return 0.0
+    bound = np.broadcast_to(cell_bound(precision, counts), x.shape)
+    return float(np.max(d[~zero] / mag[~zero] / bound[~zero]))
+
+
 def sub_slack(precision, root_mag):
     """Slack of a level built by subtraction: root_mag is the histogram of the
     absolute statistics over all rows ([1][F][B][2K], one leaf)."""

@@ -153,3 +153,12 @@ def test_ordered_calls_reject_null_without_launch(cb):
         with pytest.raises(cb.CbhError) as err:
             call()
         assert err.value.code == cb.CBH_EINVAL
+
+
+def test_combination_calls_reject_null_without_launch(cb):
+    L = cb.lib()
+    assert L.cbh_split_values(None, None, None, 0, 10, None, None) == cb.CBH_EINVAL
+    assert "ctx" in cb.cbh_last_error()
+    assert L.cbh_ts_bins(None, None, None, 10, 0, 1.0, 0.5, None, 0, None, None,
+                         None) == cb.CBH_EINVAL
+    assert C.sizeof(cb.cbh_split_source) == 24
