@@ -129,6 +129,8 @@ WORKLOADS = {
                     cpu_trees=0),
     "packed": dict(tag="packed_10m_logloss", n=10_000_000, steps=20, cpu_rows=0, cpu_trees=0,
                    hist_trees=4, autotune="off", warmup_s=0.5),
+    "combotrees": dict(tag="combo_trees_1m_rmse", n=1_000_000, steps=10, warmup=2,
+                       cpu_rows=20_000, cpu_trees=0),
 }
 # per-run defaults a workload may override
 RUN_DEFAULTS = dict(warmup=5, hist_trees=40, autotune="run", compare="fp32,twofloat,int16",
@@ -888,6 +890,99 @@ def run_combine(args):
     print(json.dumps(out), flush=True)
 
 
+def run_combo_trees(args):
+    """Trees with greedy feature combinations and three priors per statistic
+    (Sec. 2) on the 1M-row RMSE workload: after every split, the split's
+    value per row is crossed with each of the 10 categorical features (perfect
+    hash, ordered statistics for every prior) and the combinations join the
+    candidates of the levels below; every level builds its histograms over
+    all candidates directly. Beside it, plain trees on the same columns (the
+    three priors, no combinations), grown eagerly as well."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1810_11363_amd import cbhip as cb
+    from paper_1810_11363_amd.booster import GpuBooster
+
+    p = datagen.make_c2(n=args.n)
+    p.extra_priors = [p.ts_lo, p.ts_hi]
+    prec = PRECISIONS[args.precision]
+    out = {"metric": "sec/tree with greedy feature combinations (Sec. 2)", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.precision],
+           "data": "synthetic",
+           "config": {"workload": f"1M-row RMSE: n={p.n}, 100 numeric features at 128 bins + "
+                                  f"10 categorical with 3 priors each (mean, min and max of "
+                                  f"the target) -> 130 columns per tree before combinations, "
+                                  f"4 permutations, depth {p.depth}",
+                      "rows": p.n, "depth": p.depth, "precision": args.precision}}
+    res = {}
+    for mode in ("combinations", "plain"):
+        bst = GpuBooster.from_problem(p, precision=prec, combinations=mode == "combinations",
+                                      partition=False).prepare()
+        bst.init_gradients()
+        for t in range(args.warmup):
+            bst.fit_tree(t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bst.stream)
+        for t in range(args.warmup, args.warmup + args.steps):
+            bst.fit_tree(t)
+        e1.record(bst.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        r = {"ms_per_tree": round(ms, 3), "features_per_tree_level0": bst.F}
+        if mode == "combinations":
+            # where a tree's time goes: per level, histograms + score, then
+            # the leaf bit and the next level's combination columns
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                  for _ in range(bst.depth)]
+            t = args.warmup + args.steps
+            chosen = 0
+            for lvl in range(bst.depth):
+                ev[lvl][0].record(bst.stream)
+                bst.combo_level(t, lvl)
+                ev[lvl][1].record(bst.stream)
+                bst.combo_advance(t, lvl)
+                ev[lvl][2].record(bst.stream)
+            torch.cuda.synchronize()
+            r["hist_score_ms_per_level"] = [round(e[0].elapsed_time(e[1]), 3) for e in ev]
+            r["combination_columns_ms_per_level"] = [round(e[1].elapsed_time(e[2]), 3)
+                                                     for e in ev]
+            r["candidates_per_level"] = [bst.F + lvl * bst.F_cat * bst.T * bst.Q
+                                         for lvl in range(bst.depth)]
+            b = bst.best.cpu().numpy()
+            chosen = int((b[:, 0] >= bst.F).sum())
+            r["combination_splits_in_last_tree"] = chosen
+        res[mode] = r
+        print(f"# {mode}: {ms:.3f} ms/tree", file=sys.stderr, flush=True)
+        bst.close()
+    out["modes"] = res
+    out["value"] = res["combinations"]["ms_per_tree"] / 1e3
+    out["unit"] = "s/tree"
+    out["ms_per_step"] = res["combinations"]["ms_per_tree"]
+    out["combinations_vs_plain"] = round(res["combinations"]["ms_per_tree"]
+                                         / res["plain"]["ms_per_tree"], 2)
+    if not args.no_cpu:
+        from oracle import boost
+        k = args.cpu_rows
+        q = datagen.make_c2(n=k)
+        q.extra_priors = [q.ts_lo, q.ts_hi]
+        prep = boost.prepare(q)
+        approx = np.zeros((1, k))
+        B = max(int(prep.nb_num.max()), prep.nb_ts)
+        t0 = time.perf_counter()
+        boost.fit_tree_combinations(prep, q, 0, approx, B)
+        cpu_s = time.perf_counter() - t0
+        import oracle as orc
+        out["cpu_baseline"] = {"value": round(cpu_s * p.n / k, 3), "unit": "s/tree (scaled)",
+                               "cores": orc.num_threads(), "kind": "oracle",
+                               "sample": f"one combination tree on a {k}-row draw of the same "
+                                         f"workload, {cpu_s:.2f} s, scaled by rows"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5):
     """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
     MiB: the bandwidth a streaming kernel reaches on this GPU."""
@@ -1209,10 +1304,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(sharding over several GPUs is not built)"}))
         sys.exit(2)
-    if args.workload in ("c4", "apply", "combine", "packed"):
+    if args.workload in ("c4", "apply", "combine", "packed", "combotrees"):
         a = resolve(args, args.workload)
         {"c4": run_batch, "apply": run_apply, "combine": run_combine,
-         "packed": run_packed}[args.workload](a)
+         "packed": run_packed, "combotrees": run_combo_trees}[args.workload](a)
         return
     if args.workload != "headline":
         print(json.dumps(run_trees(resolve(args, args.workload))), flush=True)

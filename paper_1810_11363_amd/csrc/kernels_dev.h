@@ -1050,6 +1050,57 @@ constexpr uint32_t kLpfSkip = 0xffffffffu;
 //   FP32, h:         (g, h) float pair at ad, one 64-bit swap for both
 //   TWOFLOAT, RMSE:  (g hi, g lo) at ad, u32 count at ad + W * 8
 //   TWOFLOAT, h:     (g hi, g lo) at ad, (h hi, h lo) at ad + W * 8
+// FP32 with an h statistic: the (g, h) pair of a cell is one 64-bit word,
+// updated by compare-and-swap. A lane's rows that land in one cell are
+// first added in float32 in row order onto the first of them, which then
+// makes the one compare-and-swap for the cell: compare-and-swaps of one lane
+// on one address would otherwise fail one after the other (each retry a full
+// LDS round trip). The sums stay float32 additions. (Measured: this pays
+// where many rows of a segment share a bin, as with the statistic columns
+// of the many-class workload, and costs more than it saves elsewhere, so
+// the count form and the compensated form keep one swap per row.)
+template <int W>
+__device__ __forceinline__ void lpf_rows8_pair_f32(char* tile, const uint32_t (&ad)[8],
+                                                   const bool (&ok)[8], const float (&gv)[8],
+                                                   const float (&hv)[8]) {
+    float ag[8], ah[8];
+    bool lead[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ag[k] = gv[k];
+        ah[k] = hv[k];
+        lead[k] = ok[k];
+    }
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+            if (lead[j] && lead[k] && ad[j] == ad[k]) {
+                ag[j] = ag[j] + ag[k];
+                ah[j] = ah[j] + ah[k];
+                lead[k] = false;
+            }
+        }
+    }
+    uint64_t old[8], got[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        old[k] = lead[k] ? lds_load64(reinterpret_cast<uint64_t*>(tile + ad[k])) : 0ull;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        got[k] = lead[k] ? lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k]), old[k],
+                                     add_pair_word(old[k], ag[k], ah[k]))
+                         : 0ull;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        while (got[k] != old[k]) {
+            old[k] = got[k];
+            got[k] = lds_cas64(reinterpret_cast<uint64_t*>(tile + ad[k]), old[k],
+                               add_pair_word(old[k], ag[k], ah[k]));
+        }
+    }
+}
+
 template <int PREC, int RM, int W, bool CHECK>
 __device__ __forceinline__ void lpf_rows8_cas(char* tile, const uint32_t (&bw)[4], int r0,
                                               uint32_t lane_off, const uint32_t (&off)[8],
@@ -1061,6 +1112,10 @@ __device__ __forceinline__ void lpf_rows8_cas(char* tile, const uint32_t (&bw)[4
     for (int k = 0; k < 8; ++k) {
         ok[k] = !CHECK || off[k] != kLpfSkip;
         ad[k] = ok[k] ? lpf_addr<W, CS>(bw, r0 + k, lane_off) + off[k] : 0u;
+    }
+    if constexpr (PREC == CBH_PREC_FP32 && RM == 0) {
+        lpf_rows8_pair_f32<W>(tile, ad, ok, gv, hv);
+        return;
     }
     if constexpr (PREC == CBH_PREC_FP32 && RM != 0) {
         uint32_t old[8], got[8];
