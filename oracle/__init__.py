@@ -217,6 +217,23 @@ def apply_model(bins, feat, border, values, lr: float, approx):
     return approx
 
 
+def binarize(bins, bin_feature, bin_border) -> np.ndarray:
+    """The scorer's binary features (Sec. 4: every (feature, border) pair a
+    model uses becomes one binary feature of every row): uint32
+    [n_binary][ceil(n/32)], bit r of word w = [bins[f_j][32 w + r] > k_j],
+    rows past n zero."""
+    bins = np.asarray(bins, np.uint8)
+    n = bins.shape[1]
+    nw = (n + 31) // 32
+    out = np.zeros((len(bin_feature), nw), np.uint32)
+    weight = np.uint32(1) << np.arange(32, dtype=np.uint32)
+    for j, (f, k) in enumerate(zip(bin_feature, bin_border)):
+        b = np.zeros(nw * 32, np.uint32)
+        b[:n] = bins[int(f)].astype(np.int64) > int(k)
+        out[j] = (b.reshape(nw, 32) * weight).sum(axis=1, dtype=np.uint64).astype(np.uint32)
+    return out
+
+
 def combine_categories(cat_a, cat_b):
     """Dense ids of category pairs (the perfect hash of feature combinations,
     Sec. 2): equal pairs share an id, ids 0..m-1 in increasing order of

@@ -857,3 +857,50 @@ def test_several_priors_closed_form(oracle_lib):
             _, _, _, tb = o.ordered_ts(p.cat[c], p.perms[0], p.y_num[0], p.y_shift, p.a, P,
                                        prep.ts_borders)
             assert np.array_equal(prep.ts_bins[0, c * 3 + q], tb)
+
+
+# ---------------------------------------------------------------------------
+# The scorer's binary features (Sec. 4)
+
+def test_binarize_hand_example(oracle_lib):
+    """Two features of 35 rows: bit r of word w is [bin of row 32 w + r >
+    border]; rows past n are 0."""
+    bins = np.zeros((2, 35), np.uint8)
+    bins[0, [0, 3, 31, 32, 34]] = 5
+    bins[1] = np.arange(35) % 4
+    bits = oracle_lib.binarize(bins, [0, 1, 1, 0], [4, 2, -1, 5])
+    assert bits.shape == (4, 2)
+    assert bits[0].tolist() == [(1 << 0) | (1 << 3) | (1 << 31), (1 << 0) | (1 << 2)]
+    threes = sum(1 << r for r in range(32) if r % 4 == 3)
+    assert bits[1].tolist() == [threes, 0]          # rows 32..34 have bins 0, 1, 2
+    assert bits[2].tolist() == [0xFFFFFFFF, 0b111]
+    assert bits[3].tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 1000])
+def test_binarize_unpacks_to_the_comparisons(oracle_lib, n):
+    """Reading the words back bit by bit (little-endian bytes unpacked with
+    numpy) gives the comparisons of every row, and a model's leaf indices
+    built from those bits equal the ones built from the bins."""
+    g0 = np.random.default_rng(n)
+    F = 5
+    bins = g0.integers(0, 20, (F, n)).astype(np.uint8)
+    bf = g0.integers(0, F, 12).astype(np.int32)
+    bk = g0.integers(-1, 21, 12).astype(np.int32)
+    bits = oracle_lib.binarize(bins, bf, bk)
+    unpacked = np.unpackbits(bits.astype("<u4").view(np.uint8), axis=1,
+                             bitorder="little")[:, :n]
+    assert np.array_equal(unpacked, (bins[bf].astype(np.int64) > bk[:, None]).astype(np.uint8))
+    assert not np.unpackbits(bits.astype("<u4").view(np.uint8), axis=1,
+                             bitorder="little")[:, n:].any()
+    T, d, K = 7, 3, 2
+    sb = g0.integers(0, 12, (T, d)).astype(np.int32)
+    vals = g0.standard_normal((T, 1 << d, K))
+    a1 = np.zeros((K, n))
+    oracle_lib.apply_model(bins, bf[sb], bk[sb], vals, 0.1, a1)
+    a2 = np.zeros((K, n))
+    for t in range(T):
+        leaf = sum(unpacked[sb[t, l]].astype(np.int64) << l for l in range(d))
+        for c in range(K):
+            a2[c] = a2[c] + 0.1 * vals[t, leaf, c]
+    assert np.array_equal(a1, a2)
