@@ -752,6 +752,46 @@ def run_apply(args):
     m = min(n, args.cpu_rows)
     sample = cols[:, :m].cpu().numpy()
     got = approx[0, :m].cpu().numpy()
+    # the two steps of Sec. 4: binarize the model's (feature, border) pairs
+    # once, then the leaves from the bits
+    pairs = np.stack([feat.reshape(-1), border.reshape(-1)], 1).astype(np.int64)
+    uniq, inv = np.unique(pairs, axis=0, return_inverse=True)
+    nb = int(uniq.shape[0])
+    dbf = torch.from_numpy(uniq[:, 0].astype(np.int32)).to(dev)
+    dbk = torch.from_numpy(uniq[:, 1].astype(np.int32)).to(dev)
+    dsb = torch.from_numpy(inv.reshape(T, d).astype(np.int32)).to(dev)
+    bits = torch.empty((nb, (n + 31) // 32), dtype=torch.int32, device=dev)
+    approx_b = torch.zeros((1, n), dtype=torch.float64, device=dev)
+
+    def step_bin():
+        cb.cbh_binarize(ctx, table, seg, n, F, nb, dbf, dbk, bits)
+        cb.cbh_apply_model_binarized(ctx, bits, n, nb, 1, T, d, dsb, dvalues, lr, approx_b)
+
+    for _ in range(2):
+        step_bin()
+    cb.cbh_sync(ctx)
+    e2, e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e2.record()
+    for _ in range(args.steps):
+        cb.cbh_binarize(ctx, table, seg, n, F, nb, dbf, dbk, bits)
+    e3.record()
+    for _ in range(args.steps):
+        step_bin()
+    e4.record()
+    cb.cbh_sync(ctx)
+    torch.cuda.synchronize()
+    sec_binarize = e2.elapsed_time(e3) / 1e3 / args.steps
+    sec_bin = e3.elapsed_time(e4) / 1e3 / args.steps
+    approx_b.zero_()
+    step_bin()
+    cb.cbh_sync(ctx)
+    got_b = approx_b[0, :m].cpu().numpy()
+    binarized = {"ms_per_step": round(sec_bin * 1e3, 4),
+                 "binarize_ms": round(sec_binarize * 1e3, 4),
+                 "binary_features": nb,
+                 "value": round(n * T / sec_bin / 1e9, 3), "unit": "G row-trees/s",
+                 "vs_bins": round(sec / sec_bin, 3)}
     t1 = time.perf_counter()
     want = oracle.apply_model(sample, feat, border, values, lr, np.zeros((1, m)))
     cpu_s = time.perf_counter() - t1
@@ -774,7 +814,9 @@ def run_apply(args):
         "config": {"workload": f"model apply: {n} rows x {F} features at {B} bins (plain "
                                f"columns), {T} oblivious trees of depth {d}, K=1",
                    "rows": n, "features": F, "trees": T, "depth": d},
-        "parity": {"rows_checked": m, "bit_exact": bool(np.array_equal(got, want[0]))},
+        "parity": {"rows_checked": m, "bit_exact": bool(np.array_equal(got, want[0])),
+                   "binarized_bit_exact": bool(np.array_equal(got_b, want[0]))},
+        "binarized": binarized,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
                      "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
                      "kernel": "cbh_apply_model (model_leaves_kernel + model_sum_kernel)",

@@ -572,6 +572,42 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
                     const int32_t* split_feature, const int32_t* split_border,
                     const double* leaf_values, double lr, double* approx, void* stream);
 
+/* The scorer of Sec. 4 in its two steps: every binary feature the model
+ * uses is evaluated once for every row into a vector of bits, and each
+ * tree's leaf index of a row is then read from those bits.
+ *
+ * cbh_binarize: binary feature j = (bin_feature[j], bin_border[j]); for
+ * every row i,
+ *   bit (i % 32) of bits_out[j][i / 32] = [bin of row i of feature
+ *                                          bin_feature[j] > bin_border[j]],
+ * bits of rows >= n in the last word 0.
+ *   bins, seg_stride  the layout of cbh_problem.bins (byte bins; seg_stride
+ *                     NULL: plain columns)
+ *   bin_feature, bin_border  device int32 [n_binary]; binary features of one
+ *                     feature given next to each other share the loads of
+ *                     its bins
+ *   bits_out          device uint32 [n_binary][ceil(n / 32)]
+ * A feature index outside [0, n_features) gives a word of zeros and is
+ * reported by cbh_sync.
+ *
+ * cbh_apply_model_binarized: as cbh_apply_model, with the split of tree t
+ * at level l given as the binary feature split_binary[t][l] (device int32
+ * [n_trees][depth], an index into the binarized features of `bits`):
+ *   approx[c][i] += lr * leaf_values[t][sum_l 2^l bit(split_binary[t][l], i)][c]
+ * for t = 0 .. n_trees - 1 in order, in double. With the binary features
+ * of the model's (feature, border) pairs this is bit for bit
+ * cbh_apply_model's result. An index outside [0, n_binary) reads bit 0 and
+ * is reported by cbh_sync. Uses workspace as cbh_apply_model. Errors:
+ * CBH_EINVAL on NULL or out-of-range sizes, CBH_EUNSUPPORTED for K or depth
+ * out of range. */
+int cbh_binarize(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride, int64_t n,
+                 int32_t n_features, int32_t n_binary, const int32_t* bin_feature,
+                 const int32_t* bin_border, uint32_t* bits_out, void* stream);
+int cbh_apply_model_binarized(cbh_ctx* ctx, const uint32_t* bits, int64_t n, int32_t n_binary,
+                              int32_t K, int32_t n_trees, int32_t depth,
+                              const int32_t* split_binary, const double* leaf_values, double lr,
+                              double* approx, void* stream);
+
 /* ---- one whole tree --------------------------------------------------------- */
 
 typedef struct cbh_part cbh_part;

@@ -43,7 +43,7 @@ EXPORTS = [
     "cbh_apply_model", "cbh_combine_categories", "cbh_category_counts", "cbh_pack_bins",
     "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
-    "cbh_split_values", "cbh_ts_bins",
+    "cbh_split_values", "cbh_ts_bins", "cbh_binarize", "cbh_apply_model_binarized",
 ]
 
 
@@ -122,6 +122,9 @@ def _load():
         "cbh_combine_categories": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
         "cbh_category_counts": ([vp, vp, i64, vp, vp], C.c_int),
         "cbh_split_values": ([vp, vp, vp, i32, i64, vp, vp], C.c_int),
+        "cbh_binarize": ([vp, vp, vp, i64, i32, i32, vp, vp, vp, vp], C.c_int),
+        "cbh_apply_model_binarized": ([vp, vp, i64, i32, i32, i32, i32, vp, vp, dbl, vp, vp],
+                                      C.c_int),
         "cbh_ts_bins": ([vp, vp, vp, i64, i32, dbl, dbl, vp, i32, vp, vp, vp], C.c_int),
         "cbh_batch_create": ([vp, C.POINTER(cbh_problem), i32, i32, i32, vp, vp, C.POINTER(vp)],
                              C.c_int),
@@ -542,3 +545,18 @@ def cbh_ts_bins(ctx, num, den, n: int, y_shift: int, a: float, prior: float, ts_
     return _check(_lib.cbh_ts_bins(ctx, _ptr(num), _ptr(den), int(n), int(y_shift), float(a),
                                    float(prior), _ptr(ts_borders), int(n_ts_borders),
                                    _ptr(ts_bin_out), _ptr(ts_out), _stream(stream)))
+
+
+def cbh_binarize(ctx, bins, seg_stride, n: int, n_features: int, n_binary: int, bin_feature,
+                 bin_border, bits_out, stream=None):
+    return _check(_lib.cbh_binarize(ctx, _ptr(bins), _ptr(seg_stride), int(n), int(n_features),
+                                    int(n_binary), _ptr(bin_feature), _ptr(bin_border),
+                                    _ptr(bits_out), _stream(stream)))
+
+
+def cbh_apply_model_binarized(ctx, bits, n: int, n_binary: int, K: int, n_trees: int,
+                              depth: int, split_binary, leaf_values, lr: float, approx,
+                              stream=None):
+    return _check(_lib.cbh_apply_model_binarized(
+        ctx, _ptr(bits), int(n), int(n_binary), int(K), int(n_trees), int(depth),
+        _ptr(split_binary), _ptr(leaf_values), float(lr), _ptr(approx), _stream(stream)))

@@ -468,6 +468,130 @@ __global__ __launch_bounds__(256) void model_sum_kernel(ApplyArgs a) {
         if (c < K) a.approx[int64_t(c) * a.n + i] = acc[c];
 }
 
+// ------------------------------------------------- binarized model apply
+// The scorer of Sec. 4 in its two steps. First every binary feature the
+// model uses, (feature bf[j], border bk[j]), is evaluated once for every row
+// into a bit vector: bits[j][w] bit r = [bin of row 32 w + r > bk[j]]
+// (binarize_kernel). Then a tree's leaf index of a row is the binary vector
+// sum_l 2^l B(row, s(t, l)) read from those bits (model_leaves_bits_kernel),
+// and the leaves are summed as in cbh_apply_model.
+constexpr int kBinJ = 8;   // binary features per binarize block
+
+// One thread per 32-row word, kBinJ consecutive binary features per block:
+// a feature's 32 bins are loaded once for the run of its binary features
+// among the block's kBinJ (features given next to each other share loads).
+__global__ __launch_bounds__(256) void binarize_kernel(
+    const uint8_t* const* __restrict__ bins, const int64_t* __restrict__ seg, int64_t n,
+    int32_t F, int32_t nb, const int32_t* __restrict__ bf, const int32_t* __restrict__ bk,
+    int64_t nw, int64_t wblocks, uint32_t* __restrict__ bits, uint32_t* flags) {
+    const int64_t jb = int64_t(blockIdx.x) / wblocks;
+    const int64_t w = (int64_t(blockIdx.x) % wblocks) * 256 + threadIdx.x;
+    if (w >= nw) return;
+    const int64_t i0 = w * 32;
+    const int nr = (int)min<int64_t>(32, n - i0);
+    int prev = -1;
+    uint32_t v[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};   // the 32 bins, 4 per word
+    bool bad = false;
+    for (int jj = 0; jj < kBinJ; ++jj) {
+        const int64_t j = jb * kBinJ + jj;
+        if (j >= nb) break;
+        const int f = bf[j];
+        const int k = bk[j];
+        uint32_t word = 0u;
+        if ((unsigned)f >= (unsigned)F) {
+            bad = true;
+        } else {
+            if (f != prev) {
+                const uint8_t* col = bins[f];
+                const int64_t st = seg ? seg[f] : 16;
+                const uint8_t* p0 = col + (i0 >> 4) * st;
+                const uint8_t* p1 = p0 + st;
+                if (nr == 32 && ((reinterpret_cast<uintptr_t>(col) | (uintptr_t)st) & 15) == 0) {
+                    const uint4 a = gld_u4(p0), b = gld_u4(p1);
+                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = 0u;
+                    for (int r = 0; r < nr; ++r)
+                        v[r >> 2] |= gld_u8((r < 16 ? p0 : p1) + (r & 15)) << (8 * (r & 3));
+                }
+                prev = f;
+            }
+#pragma unroll
+            for (int r = 0; r < 32; ++r)
+                word |= (((int)((v[r >> 2] >> (8 * (r & 3))) & 255u) > k) ? 1u : 0u) << r;
+            if (nr < 32) word &= (1u << nr) - 1u;
+        }
+        bits[j * nw + w] = word;
+    }
+    if (bad && threadIdx.x == 0) atomicOr(flags, FLAG_BAD_SPLIT);
+}
+
+// One thread per (tree of the chunk, 32-row word): the tree's depth bit
+// words of the word's rows give its 32 leaf indices, stored [tree][row].
+struct ApplyBitsArgs {
+    const uint32_t* bits;
+    int64_t n, nw;
+    int32_t nb, d, t0, nt;
+    int64_t wblocks;
+    const int32_t* split;     // [tree][depth] binary feature index
+    void* leaves;
+    uint32_t* flags;
+};
+
+template <typename LT>
+__global__ __launch_bounds__(256) void model_leaves_bits_kernel(ApplyBitsArgs a) {
+    const int tl = (int)(int64_t(blockIdx.x) / a.wblocks);
+    const int64_t w = (int64_t(blockIdx.x) % a.wblocks) * 256 + threadIdx.x;
+    if (w >= a.nw) return;
+    const int64_t t = a.t0 + tl;
+    uint32_t wd[CBH_MAX_DEPTH];
+    bool bad = false;
+#pragma unroll
+    for (int l = 0; l < CBH_MAX_DEPTH; ++l) {
+        wd[l] = 0u;
+        if (l < a.d) {
+            const int j = a.split[t * a.d + l];
+            if ((unsigned)j >= (unsigned)a.nb) bad = true;
+            else wd[l] = a.bits[int64_t(j) * a.nw + w];
+        }
+    }
+    const int64_t i0 = w * 32;
+    const int nr = (int)min<int64_t>(32, a.n - i0);
+    LT* out = reinterpret_cast<LT*>(a.leaves) + int64_t(tl) * a.n + i0;
+    if constexpr (sizeof(LT) == 1) {
+        uint32_t o[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            uint32_t x = 0u;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int r = 4 * q + b;
+                uint32_t lf = 0u;
+#pragma unroll
+                for (int l = 0; l < 8; ++l) lf |= ((wd[l] >> r) & 1u) << l;
+                x |= lf << (8 * b);
+            }
+            o[q] = x;
+        }
+        if (nr == 32 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+            reinterpret_cast<uint4*>(out)[0] = make_uint4(o[0], o[1], o[2], o[3]);
+            reinterpret_cast<uint4*>(out)[1] = make_uint4(o[4], o[5], o[6], o[7]);
+        } else {
+            for (int r = 0; r < nr; ++r) out[r] = (LT)((o[r >> 2] >> (8 * (r & 3))) & 255u);
+        }
+    } else {
+        for (int r = 0; r < nr; ++r) {
+            uint32_t lf = 0u;
+#pragma unroll
+            for (int l = 0; l < CBH_MAX_DEPTH; ++l) lf |= ((wd[l] >> r) & 1u) << l;
+            out[r] = (LT)lf;
+        }
+    }
+    if (bad && threadIdx.x == 0) atomicOr(a.flags, FLAG_BAD_SPLIT);
+}
+
 }  // namespace cbh
 
 using namespace cbh;
@@ -530,6 +654,97 @@ int cbh_apply_model(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg
             else model_sum_kernel<uint8_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);
         } else {
             model_leaves_kernel<uint16_t><<<lg, 256, 0, s>>>(a);
+            CBH_LAUNCHED();
+            if (K == 1) model_sum_kernel<uint16_t, 1><<<grid, 256, 0, s>>>(a);
+            else model_sum_kernel<uint16_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        }
+        CBH_LAUNCHED();
+    }
+    return CBH_OK;
+}
+
+int cbh_binarize(cbh_ctx* ctx, const uint8_t* const* bins, const int64_t* seg_stride, int64_t n,
+                 int32_t n_features, int32_t n_binary, const int32_t* bin_feature,
+                 const int32_t* bin_border, uint32_t* bits_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n < (int64_t(1) << 40), "n must be in [0, 2^40)");
+    CBH_ARG(n_features >= 1, "n_features must be >= 1");
+    CBH_ARG(n_binary >= 0, "n_binary must be >= 0");
+    if (n == 0 || n_binary == 0) return CBH_OK;
+    CBH_ARG(bins && bin_feature && bin_border && bits_out, "NULL argument");
+    const int64_t nw = (n + 31) / 32;
+    const int64_t wblocks = (nw + 255) / 256;
+    const int64_t blocks = wblocks * ((n_binary + kBinJ - 1) / kBinJ);
+    CBH_REQUIRE(blocks <= INT32_MAX, CBH_EUNSUPPORTED, "too many (binary feature, row) words");
+    binarize_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(
+        bins, seg_stride, n, n_features, n_binary, bin_feature, bin_border, nw, wblocks, bits_out,
+        ctx->d_flags);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_apply_model_binarized(cbh_ctx* ctx, const uint32_t* bits, int64_t n, int32_t n_binary,
+                              int32_t K, int32_t n_trees, int32_t depth,
+                              const int32_t* split_binary, const double* leaf_values, double lr,
+                              double* approx, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n < (int64_t(1) << 38), "n must be in [0, 2^38)");
+    CBH_ARG(n_binary >= 1, "n_binary must be >= 1");
+    CBH_REQUIRE(K >= 1 && K <= CBH_MAX_K, CBH_EUNSUPPORTED, "K must be in [1, 16] (got %d)", K);
+    CBH_ARG(n_trees >= 0, "n_trees must be >= 0");
+    CBH_REQUIRE(depth >= 1 && depth <= CBH_MAX_DEPTH, CBH_EUNSUPPORTED,
+                "depth must be in [1, 16] (got %d)", depth);
+    CBH_ARG(std::isfinite(lr), "lr must be finite");
+    if (n == 0 || n_trees == 0) return CBH_OK;
+    CBH_ARG(bits && split_binary && leaf_values && approx, "NULL argument");
+    const int64_t lb = depth <= 8 ? 1 : 2;
+    const int64_t nw = (n + 31) / 32;
+    const int64_t wblocks = (nw + 255) / 256;
+    const int64_t per = std::max<int64_t>(1, (int64_t(256) << 20) / (lb * n));
+    const int64_t per_grid = std::max<int64_t>(1, int64_t(INT32_MAX) / wblocks);
+    const int32_t chunk =
+        (int32_t)std::min<int64_t>({int64_t(n_trees), per, per_grid, 65535});
+    int rc = ensure_ws(ctx, int64_t(chunk) * n * lb, stream);
+    if (rc) return rc;
+    ApplyBitsArgs b;
+    b.bits = bits;
+    b.n = n;
+    b.nw = nw;
+    b.nb = n_binary;
+    b.d = depth;
+    b.wblocks = wblocks;
+    b.split = split_binary;
+    b.leaves = ctx->ws;
+    b.flags = ctx->d_flags;
+    ApplyArgs a;   // the summing launch's arguments (bins and splits unused)
+    a.bins = nullptr;
+    a.seg = nullptr;
+    a.n = n;
+    a.F = 0;
+    a.K = K;
+    a.d = depth;
+    a.feat = nullptr;
+    a.border = nullptr;
+    a.values = leaf_values;
+    a.lr = lr;
+    a.approx = approx;
+    a.leaves = ctx->ws;
+    a.flags = ctx->d_flags;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t t0 = 0; t0 < n_trees; t0 += chunk) {
+        b.t0 = a.t0 = t0;
+        b.nt = a.nt = std::min(chunk, n_trees - t0);
+        const unsigned lg = (unsigned)(wblocks * b.nt);
+        const unsigned grid = (unsigned)((n + 255) / 256);
+        if (lb == 1) {
+            model_leaves_bits_kernel<uint8_t><<<lg, 256, 0, s>>>(b);
+            CBH_LAUNCHED();
+            if (K == 1) model_sum_kernel<uint8_t, 1><<<grid, 256, 0, s>>>(a);
+            else model_sum_kernel<uint8_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);
+        } else {
+            model_leaves_bits_kernel<uint16_t><<<lg, 256, 0, s>>>(b);
             CBH_LAUNCHED();
             if (K == 1) model_sum_kernel<uint16_t, 1><<<grid, 256, 0, s>>>(a);
             else model_sum_kernel<uint16_t, CBH_MAX_K><<<grid, 256, 0, s>>>(a);

@@ -164,3 +164,68 @@ def test_apply_model_arguments(cb, ctx):
     with pytest.raises(cb.CbhError):
         cb.cbh_apply_model(ctx, None, None, 8, 3, 1, 5, 4, a, a, a, float("inf"), a)
     cb.cbh_sync(ctx)
+
+
+def _binary_table(feat, border):
+    """The model's distinct (feature, border) pairs in (feature, border)
+    order, and every split's index among them."""
+    pairs = np.stack([feat.reshape(-1), border.reshape(-1)], 1).astype(np.int64)
+    uniq, inv = np.unique(pairs, axis=0, return_inverse=True)
+    return (uniq[:, 0].astype(np.int32), uniq[:, 1].astype(np.int32),
+            inv.reshape(feat.shape).astype(np.int32))
+
+
+@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("case", APPLY_CASES)
+def test_binarized_apply_bit_exact(cb, ctx, case, tiled):
+    """Sec. 4's two steps: cbh_binarize's bits equal the oracle's binary
+    features, and the model applied from them equals the oracle's model
+    apply (and so cbh_apply_model) bit for bit."""
+    n, F, T, d, K, B = case
+    g0 = np.random.default_rng(hash(case) % 10009)
+    bins = g0.integers(0, B, (F, n)).astype(np.uint8)
+    feat, border, values = _random_model(g0, F, T, d, K, B)
+    a0 = g0.normal(size=(K, n))
+    bf, bk, sb = _binary_table(feat, border)
+    nb = bf.size
+    nw = (n + 31) // 32
+    table, seg, keep = _device_bins(bins, tiled)
+    dev = gu.dev()
+    bits = torch.full((nb, nw), 0x5A5A5A5A, dtype=torch.int32, device=dev)
+    cb.cbh_binarize(ctx, table, seg, n, F, nb, gu.to_dev(bf), gu.to_dev(bk), bits)
+    cb.cbh_sync(ctx)
+    want_bits = oracle.binarize(bins, bf, bk)
+    assert np.array_equal(bits.cpu().numpy().view(np.uint32), want_bits)
+    da = gu.to_dev(a0)
+    cb.cbh_apply_model_binarized(ctx, bits, n, nb, K, T, d, gu.to_dev(sb),
+                                 gu.to_dev(values), 0.1, da)
+    cb.cbh_sync(ctx)
+    want = a0.copy()
+    oracle.apply_model(bins, feat, border, values, 0.1, want)
+    assert np.array_equal(da.cpu().numpy(), want)
+    del keep
+
+
+def test_binarized_apply_reports_bad_indices(cb, ctx):
+    """A binary feature outside the features gives zero bits, a split index
+    outside the binary features reads bit 0; both are reported by cbh_sync."""
+    n, F = 100, 3
+    g0 = np.random.default_rng(5)
+    bins = g0.integers(0, 8, (F, n)).astype(np.uint8)
+    table, seg, keep = _device_bins(bins, False)
+    bits = torch.zeros((2, 4), dtype=torch.int32, device=gu.dev())
+    cb.cbh_binarize(ctx, table, seg, n, F, 2, gu.to_dev(np.array([0, 7], np.int32)),
+                    gu.to_dev(np.array([3, 3], np.int32)), bits)
+    with pytest.raises(cb.CbhError):
+        cb.cbh_sync(ctx)
+    got = bits.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got[0], oracle.binarize(bins, [0], [3])[0]) and not got[1].any()
+    vals = np.arange(4, dtype=np.float64).reshape(1, 4, 1)
+    da = torch.zeros((1, n), dtype=torch.float64, device=gu.dev())
+    cb.cbh_apply_model_binarized(ctx, bits, n, 2, 1, 1, 2,
+                                 gu.to_dev(np.array([[0, 5]], np.int32)), gu.to_dev(vals), 1.0, da)
+    with pytest.raises(cb.CbhError):
+        cb.cbh_sync(ctx)
+    want = (bins[0] > 3).astype(np.float64)           # leaf = bit 0 only
+    assert np.array_equal(da.cpu().numpy()[0], want)
+    del keep
