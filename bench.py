@@ -974,7 +974,21 @@ def run_combo_trees(args):
         e1.record(bst.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
-        r = {"ms_per_tree": round(ms, 3), "features_per_tree_level0": bst.F}
+        # the same trees replayed from graphs (one per permutation)
+        bst.capture_trees()
+        for t in range(args.warmup):
+            bst.replay_tree(t)
+        torch.cuda.synchronize()
+        e0.record(bst.stream)
+        for t in range(args.warmup, args.warmup + args.steps):
+            bst.replay_tree(t)
+        e1.record(bst.stream)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+        bst.drop_graphs()
+        r = {"ms_per_tree_eager": round(ms, 3), "ms_per_tree": round(ms_graph, 3),
+             "features_per_tree_level0": bst.F}
+        ms = ms_graph
         if mode == "combinations":
             # where a tree's time goes: per level, histograms + score, then
             # the leaf bit and the next level's combination columns

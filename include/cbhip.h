@@ -656,6 +656,20 @@ int cbh_graph_capture_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part
                            int64_t* leaf_counts, uint64_t* stamps, void* stream,
                            cbh_graph** out);
 
+/* Capture any sequence of library calls into one library-owned graph:
+ * cbh_graph_begin starts capturing `stream` (this thread only); every call
+ * then issued on `stream` is recorded, not run; cbh_graph_end stops and
+ * instantiates the graph, which cbh_graph_launch replays and
+ * cbh_graph_destroy frees. The recorded calls keep the pointers they were
+ * given (and the context workspace as it was: a call that would have to
+ * grow it under capture fails with CBH_EBUSY, see cbh_reserve_workspace),
+ * so the caller keeps those buffers alive while the graph exists. A call
+ * that fails under capture leaves the capture to be ended: cbh_graph_end
+ * then returns CBH_EDEVICE and no graph. Used for the level loops a caller
+ * drives itself, such as trees with feature combinations. */
+int cbh_graph_begin(cbh_ctx* ctx, void* stream);
+int cbh_graph_end(cbh_ctx* ctx, void* stream, cbh_graph** out);
+
 /* ---- ordered boosting (Sec. 3) ---------------------------------------------- */
 
 /* The supporting approximations of one permutation (Sec. 3, Algorithm 1 and

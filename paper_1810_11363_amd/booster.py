@@ -609,7 +609,24 @@ class GpuBooster:
         """A library-owned graph of tree t (cbh_graph_capture_tree), captured
         on a side stream of default priority."""
         if self.combinations:
-            raise ValueError("combination trees run eagerly (no tree graphs)")
+            if stamps is not None:
+                raise ValueError("combination trees take no stamps")
+            # the level loop is driven from here: its library calls are
+            # recorded between cbh_graph_begin and cbh_graph_end
+            cap = torch.cuda.Stream(self.device)
+            torch.cuda.synchronize(self.device)
+            own = self.stream
+            self.stream = cap
+            try:
+                cb.cbh_graph_begin(self.ctx, cap)
+                try:
+                    self._combo_tree(t)
+                finally:
+                    g = cb.cbh_graph_end(self.ctx, cap)
+            finally:
+                self.stream = own
+            torch.cuda.synchronize(self.device)
+            return g
         cap = torch.cuda.Stream(self.device)
         torch.cuda.synchronize(self.device)
         g = cb.cbh_graph_capture_tree(self.ctx, self.probs[t % self.s],

@@ -44,6 +44,7 @@ EXPORTS = [
     "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
     "cbh_split_values", "cbh_ts_bins", "cbh_binarize", "cbh_apply_model_binarized",
+    "cbh_graph_begin", "cbh_graph_end",
 ]
 
 
@@ -134,6 +135,8 @@ def _load():
         "cbh_batch_update": ([vp, vp, dbl, dbl, vp, i32, vp], C.c_int),
         "cbh_graph_capture_iteration": ([vp, vp, dbl, dbl, vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_graph_launch": ([vp, vp], C.c_int),
+        "cbh_graph_begin": ([vp, vp], C.c_int),
+        "cbh_graph_end": ([vp, vp, C.POINTER(vp)], C.c_int),
         "cbh_fit_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl, vp, vp,
                           vp, vp], C.c_int),
         "cbh_graph_capture_tree": ([vp, C.POINTER(cbh_problem), vp, i32, i32, vp, vp, dbl, dbl,
@@ -560,3 +563,13 @@ def cbh_apply_model_binarized(ctx, bits, n: int, n_binary: int, K: int, n_trees:
     return _check(_lib.cbh_apply_model_binarized(
         ctx, _ptr(bits), int(n), int(n_binary), int(K), int(n_trees), int(depth),
         _ptr(split_binary), _ptr(leaf_values), float(lr), _ptr(approx), _stream(stream)))
+
+
+def cbh_graph_begin(ctx, stream):
+    return _check(_lib.cbh_graph_begin(ctx, _stream(stream)))
+
+
+def cbh_graph_end(ctx, stream):
+    g = C.c_void_p()
+    _check(_lib.cbh_graph_end(ctx, _stream(stream), C.byref(g)))
+    return g.value

@@ -144,4 +144,38 @@ int cbh_graph_capture_tree(cbh_ctx* ctx, const cbh_problem* prob, cbh_part* part
     return CBH_OK;
 }
 
+int cbh_graph_begin(cbh_ctx* ctx, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(stream != nullptr, "capture needs a non-default stream");
+    CBH_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    return CBH_OK;
+}
+
+int cbh_graph_end(cbh_ctx* ctx, void* stream, cbh_graph** out) {
+    clear_error();
+    CBH_ARG(ctx != nullptr && out != nullptr, "NULL argument");
+    CBH_ARG(stream != nullptr, "capture needs a non-default stream");
+    *out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &graph);
+    if (e != hipSuccess || graph == nullptr) {
+        if (graph) (void)hipGraphDestroy(graph);
+        set_error("hipStreamEndCapture failed: %s (a call failed under capture, or the "
+                  "stream was not capturing)", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    cbh_graph* g = new cbh_graph();
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return CBH_EDEVICE;
+    }
+    g->graph = graph;
+    *out = g;
+    return CBH_OK;
+}
+
 }  // extern "C"

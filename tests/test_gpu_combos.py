@@ -194,3 +194,35 @@ def test_ts_bins_and_split_values(cb, n):
             assert np.array_equal(out.cpu().numpy(), want)
     finally:
         cb.cbh_destroy(ctx)
+
+
+def test_combination_tree_graphs_match_eager(cb):
+    """Combination trees recorded with cbh_graph_begin / cbh_graph_end and
+    replayed equal the eagerly grown trees bit for bit (int16 form: the
+    integer sums do not depend on the order of the atomics)."""
+    from paper_1810_11363_amd.booster import GpuBooster
+    p = datagen.make_interactions(n=20011, loss=1, seed=7, depth=4, s=2)
+    runs = []
+    for graph in (False, True):
+        bst = GpuBooster.from_problem(p, precision=gu.INT16, combinations=True).prepare()
+        bst.init_gradients()
+        out = []
+        if graph:
+            # grow once eagerly on a copy of the state so that the workspace
+            # has its size, then start over and replay
+            bst.fit_tree(0)
+            bst.init_gradients()
+            bst.capture_trees()
+        for t in range(4):
+            if graph:
+                bst.replay_tree(t)
+            else:
+                bst.fit_tree(t)
+            torch.cuda.synchronize()
+            out.append((bst.best.clone(), bst.leaf.clone(), bst.leaf_values.clone(),
+                        bst.approx.clone()))
+        bst.close()
+        runs.append(out)
+    for t, (a, b) in enumerate(zip(*runs)):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y), t
