@@ -365,13 +365,17 @@ int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* co
  *                           ptr + (i / 16) * seg_stride + i % 16); the value
  *                           is 1 if bin > border, else 0 (a numeric split)
  *   kind CBH_SOURCE_VALUES  ptr is an int32 [n] column of category values (the
- *                           raw values of the categorical feature behind a
- *                           statistic column, or a combination's ids); the
- *                           value is ptr[i]                                  */
+ *                           categorical feature behind a statistic column);
+ *                           the value is ptr[i]
+ *   kind CBH_SOURCE_PAIR    ptr and ptr_b are int32 [n] columns: the value is
+ *                           the pair (ptr[i], ptr_b[i]) (a combination of a
+ *                           grouping and a categorical feature)            */
 #define CBH_SOURCE_BINS 0
 #define CBH_SOURCE_VALUES 1
+#define CBH_SOURCE_PAIR 2
 typedef struct cbh_split_source {
     const void* ptr;
+    const void* ptr_b;
     int64_t seg_stride;
     int32_t kind;
     int32_t reserved;
@@ -379,17 +383,69 @@ typedef struct cbh_split_source {
 
 /* The categorical value of every row under a chosen split (Sec. 2, "Feature
  * combinations"), read on the device so that no host round trip is needed
- * between a level's argmax and the next level's combinations:
- *   values_out[i] = per sources[split->feature] (see cbh_split_source);
- *                   0 for every row when split->feature < 0 (no split).
+ * between a level's argmax and the next level's combinations, as a pair of
+ * columns (a, b): rows with equal pairs share the value.
+ *   (a_out[i], b_out[i]) = per sources[split->feature] (see
+ *                          cbh_split_source; b = 0 for the one-column
+ *                          kinds); (0, 0) for every row when
+ *                          split->feature < 0 (no split).
  *   split       device cbh_split (as written by cbh_score_splits)
  *   sources     device cbh_split_source [n_sources]
- *   values_out  device int32 [n]
- * A feature index >= n_sources, an unknown kind or a NULL column writes 0
- * and is reported by cbh_sync. Errors: CBH_EINVAL on NULL or n out of
+ *   a_out, b_out  device int32 [n]
+ * cbh_combine_categories(a_out, b_out) then numbers the values densely. A
+ * feature index >= n_sources, an unknown kind or a NULL column writes
+ * zeros and is reported by cbh_sync. Errors: CBH_EINVAL on NULL or n out of
  * [0, 2^31 - 1]. */
 int cbh_split_values(cbh_ctx* ctx, const cbh_split* split, const cbh_split_source* sources,
-                     int32_t n_sources, int64_t n, int32_t* values_out, void* stream);
+                     int32_t n_sources, int64_t n, int32_t* a_out, int32_t* b_out,
+                     void* stream);
+
+/* Rows of a categorical column grouped by category (Sec. 5, "Categorical
+ * features": the rows are grouped with a radix sort), in permutation order
+ * inside every category, and the dense id of every row's category:
+ *   order_out   device int32 [n] or NULL: the rows in order of (category,
+ *               position in perm); categories in increasing unsigned value
+ *   ids_out     device int32 [n] or NULL: rank of the row's category among
+ *               the distinct values (0 .. n_distinct - 1)
+ *   n_distinct_out  device int64 [1] or NULL
+ *   perm        device int32 [n], perm[p] = row at position p, or NULL for
+ *               the identity
+ * Uses workspace of about 40 * n bytes. */
+int cbh_category_order(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, int64_t n,
+                       int32_t* order_out, int32_t* ids_out, int64_t* n_distinct_out,
+                       void* stream);
+
+/* Ordered target statistics (Eq. 1) of several combinations at once: all
+ * the crossings one level of a combination tree adds (Sec. 2, "Feature
+ * combinations"; Sec. 5: grouping by radix sort and a segmented scan).
+ * Crossing k groups the rows by the pair (e_ids[i], category of row i in
+ * categorical feature k); its statistic for target t and prior q, in
+ * permutation order, is written to ts_bin_out[k][(t * n_priors + q) * ld + i]
+ * as the bin of ts = (num * 2^-y_shift + a * prior) / (den + a) (double,
+ * this order) among ts_borders: bit for bit cbh_compute_ordered_ts on any
+ * dense numbering of the pairs. All crossings share one sort over
+ * n_cross * n elements keyed by (k, e) on e_bits + ceil(log2 n_cross) bits,
+ * the rows of each crossing taken in its feature's category order.
+ *   e_ids       device int32 [n], each in [0, 2^e_bits) (a value out of range
+ *               is masked and reported by cbh_sync)
+ *   c_order     device array of n_cross device int32 [n]: feature k's rows in
+ *               order of (category, position), from cbh_category_order with
+ *               the same permutation
+ *   c_ids       device array of n_cross device int32 [n]: feature k's dense
+ *               category ids (cbh_category_order's ids_out)
+ *   y_num       device int64 [n_targets][n]
+ *   priors      host double [n_targets][n_priors], n_priors <= 8
+ *   ts_bin_out  device array of n_cross device uint8 [n_targets * n_priors][ld]
+ * Errors: CBH_EINVAL on bad arguments, CBH_EUNSUPPORTED when e_bits plus the
+ * crossing index bits exceed 32 or n_cross * n >= 2^31, CBH_EOVERFLOW as
+ * cbh_compute_ordered_ts. Uses workspace of about 33 * n_cross * n bytes. */
+int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
+                             int32_t n_cross, const int32_t* const* c_order,
+                             const int32_t* const* c_ids, int64_t n, const int64_t* y_num,
+                             int32_t n_targets, int32_t y_shift, int64_t y_abs_max, double a,
+                             int32_t n_priors, const double* priors, const double* ts_borders,
+                             int32_t n_ts_borders, uint8_t* const* ts_bin_out, int64_t ld,
+                             void* stream);
 
 /* Ordered target statistic of a grouping for one more prior (Sec. 2: several
  * priors, a feature for each), from the numerators and counts that

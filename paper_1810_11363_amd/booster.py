@@ -297,10 +297,13 @@ class GpuBooster:
             self.use_part = self.K > 1 or self.precision != cb.CBH_PREC_INT16
 
     def _alloc_combos(self, ts_b):
-        """Device state of combination trees: the combinations' ids and
-        statistic bins (rewritten by every tree), and per permutation the
-        extended column tables (the tree's columns, then every combination
-        column a tree can reach) and the split sources of every column."""
+        """Device state of combination trees: every categorical feature's
+        dense ids and, per permutation, its rows in (category, position)
+        order; per level the dense ids of the split's value and the
+        statistic bins of its crossings (rewritten by every tree); per
+        permutation the extended column tables (the tree's columns, then
+        every combination column a tree can reach) and the split source of
+        every column."""
         d, n, ld = self.device, self.n, self.ld
         D, Cn, TQ = max(self.depth - 1, 1), self.F_cat, self.T * self.Q
         self.F_combo = (self.depth - 1) * Cn * TQ
@@ -310,12 +313,26 @@ class GpuBooster:
         self.perm_dc = torch.from_numpy(self.perms).to(d)
         self.y_dc = torch.from_numpy(self.y_num).to(d)
         self.y_abs = int(np.abs(self.y_num).max()) if self.y_num.size else 0
-        self.combo_ids = torch.zeros((D, Cn, n), dtype=torch.int32, device=d)
-        self.combo_bins = torch.zeros((D, Cn, TQ, ld), dtype=torch.uint8, device=d)
-        self.num_tmp = torch.empty((self.T, n), dtype=torch.int64, device=d)
-        self.den_tmp = torch.empty(n, dtype=torch.int32, device=d)
-        self.elem = torch.empty(n, dtype=torch.int32, device=d)
+        self.c_dense = torch.empty((Cn, n), dtype=torch.int32, device=d)
+        self.c_order = torch.empty((self.s, Cn, n), dtype=torch.int32, device=d)
+        for r in range(self.s):
+            for c in range(Cn):
+                cb.cbh_category_order(self.ctx, self.cat_d[c], self.perm_dc[r], n,
+                                      self.c_order[r, c], self.c_dense[c] if r == 0 else None,
+                                      None, self.stream)
+        self.e_dense = torch.zeros((D, n), dtype=torch.int32, device=d)
+        self.e_bits = max(1, int(n - 1).bit_length())
+        self.elem_a = torch.empty(n, dtype=torch.int32, device=d)
+        self.elem_b = torch.empty(n, dtype=torch.int32, device=d)
         self.ndist = torch.empty(1, dtype=torch.int64, device=d)
+        self.combo_bins = torch.zeros((D, Cn, TQ, ld), dtype=torch.uint8, device=d)
+        self.c_order_tab = [torch.tensor([self.c_order[r, c].data_ptr() for c in range(Cn)],
+                                         dtype=torch.int64, device=d) for r in range(self.s)]
+        self.c_ids_tab = torch.tensor([self.c_dense[c].data_ptr() for c in range(Cn)],
+                                      dtype=torch.int64, device=d)
+        self.bins_tab = [torch.tensor([self.combo_bins[j, c].data_ptr() for c in range(Cn)],
+                                      dtype=torch.int64, device=d) for j in range(D)]
+        self.priors_flat = [p for pl in self.prior_lists() for p in pl]
         combo_ptrs = [self.combo_bins[j, c, q].data_ptr() for j in range(self.depth - 1)
                       for c in range(Cn) for q in range(TQ)]
         base = self.col_table.cpu().numpy()
@@ -333,17 +350,19 @@ class GpuBooster:
             dtype=torch.int32, device=d)
         srcs = []
         for r in range(self.s):
-            a = np.zeros(self.F_hist, dtype=[("ptr", np.uint64), ("seg", np.int64),
-                                              ("kind", np.int32), ("res", np.int32)])
+            a = np.zeros(self.F_hist, dtype=[("ptr", np.uint64), ("ptr_b", np.uint64),
+                                              ("seg", np.int64), ("kind", np.int32),
+                                              ("res", np.int32)])
             for f in range(self.F_hist):
                 if f < self.F_num:
-                    a[f] = (base[r, f], seg[r, f], cb.CBH_SOURCE_BINS, 0)
+                    a[f] = (base[r, f], 0, seg[r, f], cb.CBH_SOURCE_BINS, 0)
                 elif f < self.F:
                     c = (f - self.F_num) // TQ
-                    a[f] = (self.cat_d[c].data_ptr(), 0, cb.CBH_SOURCE_VALUES, 0)
+                    a[f] = (self.c_dense[c].data_ptr(), 0, 0, cb.CBH_SOURCE_VALUES, 0)
                 else:
                     j, c = divmod((f - self.F) // TQ, Cn)
-                    a[f] = (self.combo_ids[j, c].data_ptr(), 0, cb.CBH_SOURCE_VALUES, 0)
+                    a[f] = (self.e_dense[j].data_ptr(), self.c_dense[c].data_ptr(), 0,
+                            cb.CBH_SOURCE_PAIR, 0)
             srcs.append(torch.from_numpy(a.view(np.uint8).copy()).to(d))
         self.src_x = srcs
 
@@ -369,9 +388,10 @@ class GpuBooster:
 
     def combo_advance(self, t: int, level: int):
         """Set the level's leaf bit; then the split's value per row (on the
-        device, from the split itself) is combined with every categorical
-        feature, and each combination's statistic bins (every target and
-        prior, the tree's permutation) become candidates below."""
+        device, from the split itself) is numbered densely and crossed with
+        every categorical feature at once (one sort for all crossings), and
+        each crossing's statistic bins (every target and prior, the tree's
+        permutation) become candidates below."""
         r = t % self.s
         pr = self.combo_problem(r, level)
         ctx, st, n = self.ctx, self.stream, self.n
@@ -379,20 +399,14 @@ class GpuBooster:
         if level + 1 >= self.depth:
             return
         cb.cbh_split_values(ctx, self.split_ptr(level), self.src_x[r], pr.n_features, n,
-                            self.elem, st)
-        pl = self.prior_lists()
-        for c in range(self.F_cat):
-            ids = self.combo_ids[level, c]
-            cb.cbh_combine_categories(ctx, self.elem, self.cat_d[c], n, ids, self.ndist, st)
-            cb.cbh_compute_ordered_ts(ctx, ids, self.perm_dc[r], n, self.y_dc, self.T,
-                                      self.y_shift, self.y_abs, self.a, self.priors, None, 0,
-                                      num_out=self.num_tmp, den_out=self.den_tmp, stream=st)
-            for t_ in range(self.T):
-                for q in range(self.Q):
-                    cb.cbh_ts_bins(ctx, self.num_tmp[t_], self.den_tmp, n, self.y_shift, self.a,
-                                   pl[t_][q], self.ts_borders_d, self.ts_bins - 1,
-                                   ts_bin_out=self.combo_bins[level, c, t_ * self.Q + q],
-                                   stream=st)
+                            self.elem_a, self.elem_b, st)
+        cb.cbh_combine_categories(ctx, self.elem_a, self.elem_b, n, self.e_dense[level],
+                                  self.ndist, st)
+        cb.cbh_ordered_ts_crossings(ctx, self.e_dense[level], self.e_bits, self.F_cat,
+                                    self.c_order_tab[r], self.c_ids_tab, n, self.y_dc, self.T,
+                                    self.y_shift, self.y_abs, self.a, self.Q, self.priors_flat,
+                                    self.ts_borders_d, self.ts_bins - 1, self.bins_tab[level],
+                                    self.ld, st)
 
     def _combo_tree(self, t: int, counts: bool = False):
         for lvl in range(self.depth):

@@ -44,7 +44,7 @@ EXPORTS = [
     "cbh_ordered_models", "cbh_ordered_offset", "cbh_ordered_support_size",
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
     "cbh_split_values", "cbh_ts_bins", "cbh_binarize", "cbh_apply_model_binarized",
-    "cbh_graph_begin", "cbh_graph_end",
+    "cbh_graph_begin", "cbh_graph_end", "cbh_category_order", "cbh_ordered_ts_crossings",
 ]
 
 
@@ -68,12 +68,12 @@ class cbh_split(C.Structure):
                 ("margin", C.c_float)]
 
 
-CBH_SOURCE_BINS, CBH_SOURCE_VALUES = 0, 1
+CBH_SOURCE_BINS, CBH_SOURCE_VALUES, CBH_SOURCE_PAIR = 0, 1, 2
 
 
 class cbh_split_source(C.Structure):
-    _fields_ = [("ptr", C.c_void_p), ("seg_stride", C.c_int64), ("kind", C.c_int32),
-                ("reserved", C.c_int32)]
+    _fields_ = [("ptr", C.c_void_p), ("ptr_b", C.c_void_p), ("seg_stride", C.c_int64),
+                ("kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 class CbhError(RuntimeError):
@@ -122,7 +122,10 @@ def _load():
                             C.c_int),
         "cbh_combine_categories": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
         "cbh_category_counts": ([vp, vp, i64, vp, vp], C.c_int),
-        "cbh_split_values": ([vp, vp, vp, i32, i64, vp, vp], C.c_int),
+        "cbh_split_values": ([vp, vp, vp, i32, i64, vp, vp, vp], C.c_int),
+        "cbh_category_order": ([vp, vp, vp, i64, vp, vp, vp, vp], C.c_int),
+        "cbh_ordered_ts_crossings": ([vp, vp, i32, i32, vp, vp, i64, vp, i32, i32, i64, dbl, i32,
+                                      vp, vp, i32, vp, i64, vp], C.c_int),
         "cbh_binarize": ([vp, vp, vp, i64, i32, i32, vp, vp, vp, vp], C.c_int),
         "cbh_apply_model_binarized": ([vp, vp, i64, i32, i32, i32, i32, vp, vp, dbl, vp, vp],
                                       C.c_int),
@@ -538,9 +541,27 @@ def cbh_category_counts(ctx, ids, n: int, counts_out, stream=None):
                                            _stream(stream)))
 
 
-def cbh_split_values(ctx, split, sources, n_sources: int, n: int, values_out, stream=None):
+def cbh_split_values(ctx, split, sources, n_sources: int, n: int, a_out, b_out, stream=None):
     return _check(_lib.cbh_split_values(ctx, _ptr(split), _ptr(sources), int(n_sources), int(n),
-                                        _ptr(values_out), _stream(stream)))
+                                        _ptr(a_out), _ptr(b_out), _stream(stream)))
+
+
+def cbh_category_order(ctx, cat, perm, n: int, order_out=None, ids_out=None,
+                       n_distinct_out=None, stream=None):
+    return _check(_lib.cbh_category_order(ctx, _ptr(cat), _ptr(perm), int(n), _ptr(order_out),
+                                          _ptr(ids_out), _ptr(n_distinct_out), _stream(stream)))
+
+
+def cbh_ordered_ts_crossings(ctx, e_ids, e_bits: int, n_cross: int, c_order, c_ids, n: int,
+                             y_num, n_targets: int, y_shift: int, y_abs_max: int, a: float,
+                             n_priors: int, priors, ts_borders, n_ts_borders: int, ts_bin_out,
+                             ld: int, stream=None):
+    pri = (C.c_double * (n_targets * n_priors))(*[float(p) for p in priors])
+    return _check(_lib.cbh_ordered_ts_crossings(
+        ctx, _ptr(e_ids), int(e_bits), int(n_cross), _ptr(c_order), _ptr(c_ids), int(n),
+        _ptr(y_num), int(n_targets), int(y_shift), int(y_abs_max), float(a), int(n_priors),
+        C.cast(pri, C.c_void_p), _ptr(ts_borders), int(n_ts_borders), _ptr(ts_bin_out), int(ld),
+        _stream(stream)))
 
 
 def cbh_ts_bins(ctx, num, den, n: int, y_shift: int, a: float, prior: float, ts_borders,

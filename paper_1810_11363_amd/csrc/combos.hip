@@ -1,7 +1,8 @@
 // Greedy feature combinations and several priors (Sec. 2, "Feature
 // combinations" and the prior discussion under Eq. 1): the categorical value
 // a tree's split gives every row, and the ordered-statistic bins of a
-// grouping for one more prior from its numerators and counts.
+// grouping for one more prior from its numerators and counts. (The
+// crossings of a level in one sort are in preprocess.hip, beside the sort.)
 #include "common.h"
 
 using namespace cbh;
@@ -13,38 +14,48 @@ int grid_for(int64_t n, int per_block, int cap) {
     return int(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
-// Every row's value under the split `*split`: the split's column is looked up
-// in `src` (device memory) once per thread; a bins column gives
-// [bin > border], a values column its int32 value, no split 0.
+// Every row's value under the split `*split` as a pair (a, b): the split's
+// column is looked up in `src` (device memory) once per thread; a bins
+// column gives ([bin > border], 0), a values column (value, 0), a pair
+// source its two columns, no split (0, 0).
 __global__ __launch_bounds__(256) void split_values_kernel(
     const cbh_split* __restrict__ split, const cbh_split_source* __restrict__ src,
-    int32_t n_src, int64_t n, int32_t* __restrict__ out, uint32_t* __restrict__ flags) {
+    int32_t n_src, int64_t n, int32_t* __restrict__ a_out, int32_t* __restrict__ b_out,
+    uint32_t* __restrict__ flags) {
     const int32_t f = split->feature;
     const int32_t k = split->border;
     int32_t kind = -1;
     const void* ptr = nullptr;
+    const void* ptr_b = nullptr;
     int64_t stride = 16;
     if (f >= 0 && f < n_src) {
         kind = src[f].kind;
         ptr = src[f].ptr;
+        ptr_b = src[f].ptr_b;
         stride = src[f].seg_stride;
     }
-    const bool bad = f >= n_src || (f >= 0 && ((kind != CBH_SOURCE_BINS &&
-                                                kind != CBH_SOURCE_VALUES) || !ptr));
+    const bool bad = f >= n_src ||
+                     (f >= 0 && ((kind != CBH_SOURCE_BINS && kind != CBH_SOURCE_VALUES &&
+                                  kind != CBH_SOURCE_PAIR) ||
+                                 !ptr || (kind == CBH_SOURCE_PAIR && !ptr_b)));
     if (bad) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, FLAG_BAD_SPLIT);
         kind = -1;
     }
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * 256) {
-        int32_t v = 0;
+        int32_t v = 0, w = 0;
         if (kind == CBH_SOURCE_BINS) {
             const uint8_t* b = static_cast<const uint8_t*>(ptr);
             v = int32_t(b[(i >> 4) * stride + (i & 15)]) > k ? 1 : 0;
         } else if (kind == CBH_SOURCE_VALUES) {
             v = static_cast<const int32_t*>(ptr)[i];
+        } else if (kind == CBH_SOURCE_PAIR) {
+            v = static_cast<const int32_t*>(ptr)[i];
+            w = static_cast<const int32_t*>(ptr_b)[i];
         }
-        out[i] = v;
+        a_out[i] = v;
+        b_out[i] = w;
     }
 }
 
@@ -77,16 +88,17 @@ __global__ __launch_bounds__(256) void ts_bins_kernel(
 extern "C" {
 
 int cbh_split_values(cbh_ctx* ctx, const cbh_split* split, const cbh_split_source* sources,
-                     int32_t n_sources, int64_t n, int32_t* values_out, void* stream) {
+                     int32_t n_sources, int64_t n, int32_t* a_out, int32_t* b_out,
+                     void* stream) {
     clear_error();
     CBH_ARG(ctx != nullptr, "ctx is NULL");
     CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
     CBH_ARG(n_sources >= 0, "n_sources must be >= 0");
     if (n == 0) return CBH_OK;
-    CBH_ARG(split && values_out && (sources || n_sources == 0), "NULL argument");
+    CBH_ARG(split && a_out && b_out && (sources || n_sources == 0), "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     split_values_kernel<<<grid_for(n, 256, ctx->num_cus * 8), 256, 0, s>>>(
-        split, sources, n_sources, n, values_out, ctx->d_flags);
+        split, sources, n_sources, n, a_out, b_out, ctx->d_flags);
     CBH_LAUNCHED();
     return CBH_OK;
 }

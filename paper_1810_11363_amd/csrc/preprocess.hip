@@ -18,6 +18,7 @@
 //      value and its bin.
 // The scan is reduce-then-scan over 4096-element tiles (three launches), so no
 // block ever waits on another.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -163,12 +164,15 @@ __global__ void gather_keys_kernel(const int32_t* __restrict__ cat,
 //   0: v = values[i] (plain values array), head = (i == 0)
 //   1: v = 1, head = key change
 //   2: v = y[vals[i]], head = key change
+//   3: v = 1, head = heads[i]
+//   4: v = y[vals[i]], head = heads[i]
 struct ScanSrc {
     int mode;
     const int64_t* values;
     const uint32_t* keys;
     const int32_t* vals;
     const int64_t* y;
+    const uint8_t* heads = nullptr;
 };
 
 struct SegPair {
@@ -182,8 +186,8 @@ __device__ __forceinline__ SegPair seg_op(SegPair a, SegPair b) {
 
 __device__ __forceinline__ SegPair load_elem(const ScanSrc& s, int64_t i) {
     if (s.mode == 0) return SegPair{s.values[i], i == 0};
-    int head = (i == 0) || (s.keys[i] != s.keys[i - 1]);
-    int64_t v = s.mode == 1 ? 1 : s.y[s.vals[i]];
+    int head = s.mode >= 3 ? (int)s.heads[i] : ((i == 0) || (s.keys[i] != s.keys[i - 1]));
+    int64_t v = (s.mode == 1 || s.mode == 3) ? 1 : s.y[s.vals[i]];
     return SegPair{v, head};
 }
 
@@ -445,6 +449,96 @@ __global__ void id_count_gather_kernel(const int32_t* __restrict__ ids, int64_t 
     }
 }
 
+// ------------------------------------------------ crossings of categories
+// A row starts a new category where its sorted key differs from the previous.
+__global__ void key_heads_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                 int64_t* __restrict__ head) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x)
+        head[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
+}
+
+// Crossing k (blockIdx.y) of n rows: element j = k n + i takes row order[k][i]
+// (the rows in order of (category of crossing k, position)); its key is
+// (k << e_bits) | e[row], so a stable sort on the key orders the elements by
+// (crossing, e, category, position).
+__global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits,
+                                  const int32_t* const* __restrict__ order, int64_t n,
+                                  uint32_t* __restrict__ keys, int32_t* __restrict__ rows,
+                                  uint32_t* __restrict__ flags) {
+    const int k = blockIdx.y;
+    const int32_t* ord = order[k];
+    const uint32_t emax = e_bits >= 32 ? 0xffffffffu : ((1u << e_bits) - 1u);
+    bool bad = false;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        int32_t r = ord[i];
+        if (r < 0 || r >= n) {
+            bad = true;
+            r = 0;
+        }
+        uint32_t v = (uint32_t)e[r];
+        if (v > emax) {
+            bad = true;
+            v &= emax;
+        }
+        const int64_t j = int64_t(k) * n + i;
+        keys[j] = (e_bits >= 32 ? 0u : ((uint32_t)k << e_bits)) | v;
+        rows[j] = r;
+    }
+    if (bad) atomicOr(flags, FLAG_BAD_INDEX);
+}
+
+// A sorted element starts a new group where its key (crossing, e) or its
+// category in that crossing differs from the previous element's.
+__global__ void cross_heads_kernel(const uint32_t* __restrict__ keys,
+                                   const int32_t* __restrict__ rows,
+                                   const int32_t* const* __restrict__ cids, int32_t e_bits,
+                                   int64_t N, uint8_t* __restrict__ head) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        bool h = p == 0 || keys[p] != keys[p - 1];
+        if (!h) {
+            const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
+            h = cids[k][rows[p]] != cids[k][rows[p - 1]];
+        }
+        head[p] = h ? 1 : 0;
+    }
+}
+
+struct CrossPriors {
+    double ap[8];     // a * prior of every prior of the target
+};
+
+// Statistic bins of every sorted element for target t and each prior q:
+// ts = (num 2^-y_shift + a P_q) / (den + a), in this order, its bin the
+// number of borders strictly below it, written to out[k][(t Q + q) ld + row].
+__global__ __launch_bounds__(256) void cross_scatter_kernel(
+    const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
+    const int64_t* __restrict__ den_s, const int64_t* __restrict__ num_s, int64_t N,
+    int32_t e_bits, int32_t y_shift, double a, CrossPriors pri, int32_t Q, int32_t t,
+    const double* __restrict__ tsb, int32_t ntsb, uint8_t* const* __restrict__ out, int64_t ld) {
+    __shared__ double sb[256];
+    sb[threadIdx.x] = (int32_t(threadIdx.x) < ntsb) ? tsb[threadIdx.x] : INFINITY;
+    __syncthreads();
+    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < N;
+         p += int64_t(gridDim.x) * 256) {
+        const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
+        const int32_t r = rows[p];
+        const double num = ldexp((double)num_s[p], -y_shift);
+        const double den = (double)den_s[p] + a;
+        uint8_t* o = out[k] + int64_t(t) * Q * ld + r;
+        for (int q = 0; q < Q; ++q) {
+            const double ts = (num + pri.ap[q]) / den;
+            uint32_t pos = 0;
+#pragma unroll
+            for (uint32_t step = 128; step >= 1; step >>= 1)
+                if (sb[pos + step - 1] < ts) pos += step;
+            o[int64_t(q) * ld] = (uint8_t)pos;
+        }
+    }
+}
+
 static int grid_for(int64_t n, int per_block, int cap = 16384) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -678,6 +772,178 @@ int cbh_category_counts(cbh_ctx* ctx, const int32_t* ids, int64_t n, int32_t* co
     CBH_LAUNCHED();
     id_count_gather_kernel<<<gs, 256, 0, s>>>(ids, n, cnt, counts_out);
     CBH_LAUNCHED();
+    return CBH_OK;
+}
+
+int cbh_category_order(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, int64_t n,
+                       int32_t* order_out, int32_t* ids_out, int64_t* n_distinct_out,
+                       void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(cat && (order_out || ids_out), "NULL argument");
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    const int64_t cnt_elems = 256 * n_tiles;
+    const int64_t cnt_tiles = (cnt_elems + kTile - 1) / kTile;
+    const int64_t max_tiles = std::max(n_tiles, cnt_tiles);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = off; off += align_up(bytes, 256); return o; };
+    const int64_t o_k0 = take(4 * n), o_k1 = take(4 * n), o_v0 = take(4 * n),
+                  o_v1 = take(4 * n), o_head = take(8 * n), o_excl = take(8 * n),
+                  o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
+                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles),
+                  o_nd = take(8);
+    int rc = ensure_ws(ctx, off, stream);
+    if (rc != CBH_OK) return rc;
+    char* w = (char*)ctx->ws;
+    uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
+    int32_t* rows[2] = {(int32_t*)(w + o_v0), (int32_t*)(w + o_v1)};
+    int64_t* head = (int64_t*)(w + o_head);
+    int64_t* excl = (int64_t*)(w + o_excl);
+    int64_t* counts = (int64_t*)(w + o_cnt);
+    int64_t* offs = (int64_t*)(w + o_off);
+    SegPair* agg = (SegPair*)(w + o_agg);
+    int64_t* car = (int64_t*)(w + o_car);
+    hipStream_t s = (hipStream_t)stream;
+    const int gs = grid_for(n, 256, ctx->num_cus * 8);
+    if (perm) gather_keys_kernel<<<gs, 256, 0, s>>>(cat, perm, n, keys[0], rows[0], ctx->d_flags);
+    else pair_first_keys_kernel<<<gs, 256, 0, s>>>(cat, n, keys[0], rows[0]);
+    CBH_LAUNCHED();
+    int cur = 0;
+    for (int shift = 0; shift < 32; shift += 8) {
+        radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], n, shift,
+                                                                      n_tiles, counts);
+        CBH_LAUNCHED();
+        const int64_t tiles = (cnt_elems + kTile - 1) / kTile;
+        const ScanSrc src{0, counts, nullptr, nullptr, nullptr};
+        seg_reduce_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, cnt_elems, agg);
+        seg_carry_kernel<<<1, 256, 0, s>>>(agg, tiles, car);
+        seg_scan_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, cnt_elems, car, offs);
+        radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
+            keys[cur], rows[cur], n, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1]);
+        CBH_LAUNCHED();
+        cur ^= 1;
+    }
+    if (order_out)
+        CBH_HIP(hipMemcpyAsync(order_out, rows[cur], 4 * n, hipMemcpyDeviceToDevice, s));
+    if (ids_out || n_distinct_out) {
+        key_heads_kernel<<<gs, 256, 0, s>>>(keys[cur], n, head);
+        const ScanSrc src{0, head, nullptr, nullptr, nullptr};
+        seg_reduce_kernel<<<(unsigned)n_tiles, 256, 0, s>>>(src, n, agg);
+        seg_carry_kernel<<<1, 256, 0, s>>>(agg, n_tiles, car);
+        seg_scan_kernel<<<(unsigned)n_tiles, 256, 0, s>>>(src, n, car, excl);
+        // without ids_out the ids go to the sort's free key buffer
+        int32_t* ids = ids_out ? ids_out : (int32_t*)keys[cur ^ 1];
+        int64_t* nd = n_distinct_out ? n_distinct_out : (int64_t*)(w + o_nd);
+        pair_ids_kernel<<<gs, 256, 0, s>>>(rows[cur], head, excl, n, ids, nd);
+        CBH_LAUNCHED();
+    }
+    return CBH_OK;
+}
+
+int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
+                             int32_t n_cross, const int32_t* const* c_order,
+                             const int32_t* const* c_ids, int64_t n, const int64_t* y_num,
+                             int32_t n_targets, int32_t y_shift, int64_t y_abs_max, double a,
+                             int32_t n_priors, const double* priors, const double* ts_borders,
+                             int32_t n_ts_borders, uint8_t* const* ts_bin_out, int64_t ld,
+                             void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
+    CBH_ARG(n_cross >= 1 && n_cross <= 4096, "n_cross must be in [1, 4096]");
+    CBH_ARG(e_bits >= 0 && e_bits <= 32, "e_bits must be in [0, 32]");
+    int k_bits = 0;
+    while ((1 << k_bits) < n_cross) ++k_bits;
+    CBH_REQUIRE(e_bits + k_bits <= 32, CBH_EUNSUPPORTED,
+                "e_bits + bits of the crossing index must be <= 32 (got %d + %d)", e_bits,
+                k_bits);
+    CBH_REQUIRE(n == 0 || int64_t(n_cross) * n <= int64_t(INT32_MAX), CBH_EUNSUPPORTED,
+                "n_cross * n must be < 2^31");
+    CBH_ARG(n_targets >= 1 && n_targets <= 16, "n_targets must be in [1, 16]");
+    CBH_ARG(n_priors >= 1 && n_priors <= 8, "n_priors must be in [1, 8]");
+    CBH_ARG(y_shift >= 0 && y_shift <= 62, "y_shift must be in [0, 62]");
+    CBH_ARG(y_abs_max >= 0, "y_abs_max must be >= 0");
+    CBH_ARG(a > 0 && std::isfinite(a), "prior weight a must be finite and > 0");
+    CBH_REQUIRE(n_ts_borders >= 0 && n_ts_borders <= 255, CBH_EUNSUPPORTED,
+                "n_ts_borders must be in [0, 255]");
+    CBH_REQUIRE(y_abs_max == 0 || (double)n * (double)y_abs_max < 4.611686018427387904e18,
+                CBH_EOVERFLOW, "n * y_abs_max must be < 2^62 for exact int64 sums");
+    CBH_ARG(ld >= n, "ld must be >= n");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(e_ids && c_order && c_ids && y_num && priors && ts_bin_out, "NULL argument");
+    CBH_ARG(n_ts_borders == 0 || ts_borders, "ts_borders is NULL");
+    for (int i = 0; i < n_targets * n_priors; ++i)
+        CBH_ARG(std::isfinite(priors[i]), "prior not finite");
+    const int64_t N = int64_t(n_cross) * n;
+    const int64_t n_tiles = (N + kTile - 1) / kTile;
+    const int64_t cnt_elems = 256 * n_tiles;
+    const int64_t cnt_tiles = (cnt_elems + kTile - 1) / kTile;
+    const int64_t max_tiles = std::max(n_tiles, cnt_tiles);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = off; off += align_up(bytes, 256); return o; };
+    const int64_t o_k0 = take(4 * N), o_k1 = take(4 * N), o_v0 = take(4 * N),
+                  o_v1 = take(4 * N), o_head = take(N), o_den = take(8 * N),
+                  o_num = take(8 * N), o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
+                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
+    int rc = ensure_ws(ctx, off, stream);
+    if (rc != CBH_OK) return rc;
+    char* w = (char*)ctx->ws;
+    uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
+    int32_t* rows[2] = {(int32_t*)(w + o_v0), (int32_t*)(w + o_v1)};
+    uint8_t* head = (uint8_t*)(w + o_head);
+    int64_t* den_s = (int64_t*)(w + o_den);
+    int64_t* num_s = (int64_t*)(w + o_num);
+    int64_t* counts = (int64_t*)(w + o_cnt);
+    int64_t* offs = (int64_t*)(w + o_off);
+    SegPair* agg = (SegPair*)(w + o_agg);
+    int64_t* car = (int64_t*)(w + o_car);
+    hipStream_t s = (hipStream_t)stream;
+    auto scan = [&](ScanSrc src, int64_t len, int64_t* out) -> int {
+        const int64_t tiles = (len + kTile - 1) / kTile;
+        seg_reduce_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, agg);
+        seg_carry_kernel<<<1, 256, 0, s>>>(agg, tiles, car);
+        seg_scan_kernel<<<(unsigned)tiles, 256, 0, s>>>(src, len, car, out);
+        CBH_LAUNCHED();
+        return CBH_OK;
+    };
+    const int gsx = grid_for(n, 256, std::max(1, ctx->num_cus * 8 / n_cross));
+    cross_keys_kernel<<<dim3(gsx, n_cross), 256, 0, s>>>(e_ids, e_bits, c_order, n, keys[0],
+                                                         rows[0], ctx->d_flags);
+    CBH_LAUNCHED();
+    int cur = 0;
+    const int key_bits = e_bits + k_bits;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], N, shift,
+                                                                      n_tiles, counts);
+        CBH_LAUNCHED();
+        rc = scan(ScanSrc{0, counts, nullptr, nullptr, nullptr}, cnt_elems, offs);
+        if (rc != CBH_OK) return rc;
+        radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
+            keys[cur], rows[cur], N, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1]);
+        CBH_LAUNCHED();
+        cur ^= 1;
+    }
+    const int gs = grid_for(N, 256, ctx->num_cus * 8);
+    cross_heads_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], c_ids, e_bits, N, head);
+    CBH_LAUNCHED();
+    ScanSrc dsrc{3, nullptr, keys[cur], rows[cur], nullptr};
+    dsrc.heads = head;
+    rc = scan(dsrc, N, den_s);
+    if (rc != CBH_OK) return rc;
+    for (int t = 0; t < n_targets; ++t) {
+        ScanSrc nsrc{4, nullptr, keys[cur], rows[cur], y_num + int64_t(t) * n};
+        nsrc.heads = head;
+        rc = scan(nsrc, N, num_s);
+        if (rc != CBH_OK) return rc;
+        CrossPriors pri;
+        for (int q = 0; q < 8; ++q) pri.ap[q] = q < n_priors ? a * priors[t * n_priors + q] : 0.0;
+        cross_scatter_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, e_bits,
+                                                y_shift, a, pri, n_priors, t, ts_borders,
+                                                n_ts_borders, ts_bin_out, ld);
+        CBH_LAUNCHED();
+    }
     return CBH_OK;
 }
 

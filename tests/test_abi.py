@@ -157,8 +157,11 @@ def test_ordered_calls_reject_null_without_launch(cb):
 
 def test_combination_calls_reject_null_without_launch(cb):
     L = cb.lib()
-    assert L.cbh_split_values(None, None, None, 0, 10, None, None) == cb.CBH_EINVAL
+    assert L.cbh_split_values(None, None, None, 0, 10, None, None, None) == cb.CBH_EINVAL
     assert "ctx" in cb.cbh_last_error()
     assert L.cbh_ts_bins(None, None, None, 10, 0, 1.0, 0.5, None, 0, None, None,
                          None) == cb.CBH_EINVAL
-    assert C.sizeof(cb.cbh_split_source) == 24
+    assert C.sizeof(cb.cbh_split_source) == 32
+    assert L.cbh_category_order(None, None, None, 10, None, None, None, None) == cb.CBH_EINVAL
+    assert L.cbh_ordered_ts_crossings(None, None, 20, 2, None, None, 10, None, 1, 0, 1, 1.0, 1,
+                                      None, None, 0, None, 10, None) == cb.CBH_EINVAL

@@ -179,19 +179,23 @@ def test_ts_bins_and_split_values(cb, n):
         ld = (n + 15) // 16 * 16
         bins = g0.integers(0, 40, ld).astype(np.uint8)
         vals = g0.integers(-5, 5, n).astype(np.int32)
-        bins_d, vals_d = gu.to_dev(bins), gu.to_dev(vals)
-        src = np.zeros(2, dtype=[("ptr", np.uint64), ("seg", np.int64), ("kind", np.int32),
-                                 ("res", np.int32)])
-        src[0] = (bins_d.data_ptr(), 16, cb.CBH_SOURCE_BINS, 0)
-        src[1] = (vals_d.data_ptr(), 0, cb.CBH_SOURCE_VALUES, 0)
+        vals2 = g0.integers(0, 9, n).astype(np.int32)
+        bins_d, vals_d, vals2_d = gu.to_dev(bins), gu.to_dev(vals), gu.to_dev(vals2)
+        src = np.zeros(3, dtype=[("ptr", np.uint64), ("ptr_b", np.uint64), ("seg", np.int64),
+                                 ("kind", np.int32), ("res", np.int32)])
+        src[0] = (bins_d.data_ptr(), 0, 16, cb.CBH_SOURCE_BINS, 0)
+        src[1] = (vals_d.data_ptr(), 0, 0, cb.CBH_SOURCE_VALUES, 0)
+        src[2] = (vals_d.data_ptr(), vals2_d.data_ptr(), 0, cb.CBH_SOURCE_PAIR, 0)
         src_d = torch.from_numpy(src.view(np.uint8).copy()).to(d)
-        out = torch.empty(n, dtype=torch.int32, device=d)
-        for f, k, want in ((0, 17, (bins[:n] > 17).astype(np.int32)), (1, 3, vals),
-                           (-1, -1, np.zeros(n, np.int32))):
+        oa = torch.empty(n, dtype=torch.int32, device=d)
+        ob = torch.empty(n, dtype=torch.int32, device=d)
+        zero = np.zeros(n, np.int32)
+        for f, k, wa, wb in ((0, 17, (bins[:n] > 17).astype(np.int32), zero), (1, 3, vals, zero),
+                             (2, 0, vals, vals2), (-1, -1, zero, zero)):
             sp = torch.tensor([f, k, 0, 0], dtype=torch.int32, device=d)
-            cb.cbh_split_values(ctx, sp, src_d, 2, n, out)
+            cb.cbh_split_values(ctx, sp, src_d, 3, n, oa, ob)
             cb.cbh_sync(ctx)
-            assert np.array_equal(out.cpu().numpy(), want)
+            assert np.array_equal(oa.cpu().numpy(), wa) and np.array_equal(ob.cpu().numpy(), wb)
     finally:
         cb.cbh_destroy(ctx)
 
@@ -226,3 +230,57 @@ def test_combination_tree_graphs_match_eager(cb):
     for t, (a, b) in enumerate(zip(*runs)):
         for x, y in zip(a, b):
             assert torch.equal(x, y), t
+
+
+@pytest.mark.parametrize("n", [1, 33, 4099, 100003])
+def test_category_order_and_crossings(cb, n):
+    """cbh_category_order: rows in (category, position) order and dense ids,
+    as the oracle's numbering; cbh_ordered_ts_crossings: every crossing's
+    statistic bins (two targets, three priors) bit for bit those of the
+    oracle's Eq. (1) over the pair's dense ids."""
+    g0 = np.random.default_rng(n + 5)
+    ctx = cb.cbh_create(0)
+    try:
+        d = gu.dev()
+        C = 3
+        cats = [datagen.raw_values(g0, m)[g0.integers(0, m, n)] for m in (4, 50, 1000)]
+        perm = g0.permutation(n).astype(np.int32)
+        e = g0.integers(0, 7, n).astype(np.int32)
+        T, Q = 2, 3
+        y = np.stack([g0.integers(0, 2, n), g0.integers(0, 2, n)]).astype(np.int64)
+        priors = [[0.3, 0.0, 1.0], [0.7, 0.0, 1.0]]
+        tb = oracle.ts_borders(0.0, 1.0, 33)
+        ld = (n + 15) // 16 * 16
+        orders = torch.empty((C, n), dtype=torch.int32, device=d)
+        ids = torch.empty((C, n), dtype=torch.int32, device=d)
+        nd = torch.empty(1, dtype=torch.int64, device=d)
+        for c in range(C):
+            cb.cbh_category_order(ctx, gu.to_dev(cats[c]), gu.to_dev(perm), n, orders[c], ids[c],
+                                  nd)
+            cb.cbh_sync(ctx)
+            want_ids, m = oracle.combine_categories(cats[c], np.zeros(n, np.int32))
+            assert np.array_equal(ids[c].cpu().numpy(), want_ids) and int(nd.item()) == m
+            pos = np.empty(n, np.int64)
+            pos[perm] = np.arange(n)
+            want_order = np.lexsort((pos, want_ids))     # by id, then position
+            assert np.array_equal(orders[c].cpu().numpy(), want_order)
+        out = torch.full((C, T * Q, ld), 255, dtype=torch.uint8, device=d)
+        ord_tab = torch.tensor([orders[c].data_ptr() for c in range(C)], dtype=torch.int64,
+                               device=d)
+        ids_tab = torch.tensor([ids[c].data_ptr() for c in range(C)], dtype=torch.int64, device=d)
+        out_tab = torch.tensor([out[c].data_ptr() for c in range(C)], dtype=torch.int64, device=d)
+        e_bits = 3
+        cb.cbh_ordered_ts_crossings(ctx, gu.to_dev(e), e_bits, C, ord_tab, ids_tab, n,
+                                    gu.to_dev(y), T, 0, 1, 1.0, Q,
+                                    [p for pl in priors for p in pl], gu.to_dev(tb), tb.size,
+                                    out_tab, ld)
+        cb.cbh_sync(ctx)
+        got = out.cpu().numpy()
+        for c in range(C):
+            pid, _ = oracle.combine_categories(e, cats[c])
+            for t in range(T):
+                for q in range(Q):
+                    _, _, _, wb = oracle.ordered_ts(pid, perm, y[t], 0, 1.0, priors[t][q], tb)
+                    assert np.array_equal(got[c, t * Q + q, :n], wb), (c, t, q)
+    finally:
+        cb.cbh_destroy(ctx)
