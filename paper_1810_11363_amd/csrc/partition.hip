@@ -55,7 +55,10 @@ struct cbh_part {
     int64_t* off[2] = {nullptr, nullptr};       // [2^(depth-1) + 1] first position of each leaf
     uint32_t* zl = nullptr;                     // [2^(depth-2)] rows of each leaf with bit 0
     int64_t* blk = nullptr;                     // [n_pb + 1] zeros per block, then their prefix
-    int64_t* cp = nullptr;                      // [2^(depth-1) + 1] chunk prefix of slot tiles
+    int64_t* cp = nullptr;                      // [2^(depth-1) + 1] chunk prefix of slot tiles, in
+                                                // the tiles' processing order
+    int32_t* tord = nullptr;                    // [2 * 2^(depth-1)]: tile at each place of that
+                                                // order, then the place of each tile
     int32_t* tleaf = nullptr;                   // [2^(depth-1)] child a subtraction build accumulates
 };
 
@@ -365,36 +368,74 @@ __global__ __launch_bounds__(256) void part_leaf_kernel(const uint8_t* const* __
 }
 
 // Chunks of every slot tile: tile t holds leaves [t lt, min((t+1) lt, L)),
-// i.e. positions [off[t lt], off[...]) and the 16-row segments over them;
-// cp = exclusive prefix of ceil(segments / segs_per_chunk), total at [n_tiles].
+// i.e. positions [off[t lt], off[...]) and the 16-row segments over them.
 // With tleaf (a build by subtraction: lt = 1, n_tiles = L / 2 parents), tile
 // t is parent t and holds only its child with fewer rows, leaf t or t + L / 2
 // (the lower one on a tie), whose leaf index goes to tleaf[t].
+// The tiles are processed largest first (their rows, descending; ties by
+// index): blocks start in index order, and leaves differ in size by orders
+// of magnitude, so the chunks of a large leaf started last would leave most
+// CUs idle while they finish. tord[q] is the tile at place q, tord[n_tiles +
+// t] the place of tile t, and cp the exclusive prefix of chunks by place
+// (total at [n_tiles]). Beyond kTileSort tiles the order is the index order.
+constexpr int kTileSort = 2048;
+
 __global__ __launch_bounds__(1024) void part_tiles_kernel(const int64_t* __restrict__ off,
                                                           int32_t L, int32_t lt, int32_t n_tiles,
                                                           int64_t segs_per_chunk,
                                                           int64_t* __restrict__ cp,
+                                                          int32_t* __restrict__ tord,
                                                           int32_t* __restrict__ tleaf) {
     __shared__ int64_t sh[1024];
+    __shared__ int64_t rows_sh[kTileSort];
+    __shared__ int32_t ord_sh[kTileSort];
     auto first_leaf = [&](int64_t t) -> int64_t {
         if (!tleaf) return t * lt;
         const int64_t hi = t + n_tiles;
         return off[hi + 1] - off[hi] < off[t + 1] - off[t] ? hi : t;
     };
-    auto chunks = [&](int64_t t) -> int64_t {
+    auto range = [&](int64_t t, int64_t& a, int64_t& b) {
         const int64_t v = first_leaf(t);
-        const int64_t a = off[v];
-        const int64_t b = tleaf ? off[v + 1] : off[min((t + 1) * int64_t(lt), int64_t(L))];
+        a = off[v];
+        b = tleaf ? off[v + 1] : off[min((t + 1) * int64_t(lt), int64_t(L))];
+    };
+    auto chunks = [&](int64_t t) -> int64_t {
+        int64_t a, b;
+        range(t, a, b);
         if (a >= b) return 0;
         return (((b + 15) >> 4) - (a >> 4) + segs_per_chunk - 1) / segs_per_chunk;
     };
+    const bool sorted = n_tiles <= kTileSort;
+    if (sorted) {
+        for (int t = threadIdx.x; t < n_tiles; t += 1024) {
+            int64_t a, b;
+            range(t, a, b);
+            rows_sh[t] = b - a;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < n_tiles; t += 1024) {
+            const int64_t rt = rows_sh[t];
+            int q = 0;
+            for (int u = 0; u < n_tiles; ++u) {
+                const int64_t ru = rows_sh[u];
+                q += (ru > rt || (ru == rt && u < t)) ? 1 : 0;
+            }
+            ord_sh[q] = t;
+            tord[n_tiles + t] = q;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < n_tiles; q += 1024) tord[q] = ord_sh[q];
+    } else {
+        for (int t = threadIdx.x; t < n_tiles; t += 1024) {
+            tord[t] = t;
+            tord[n_tiles + t] = t;
+        }
+    }
     const int64_t tot = block_scan_1024(
-        n_tiles, chunks,
-        [&](int64_t t, int64_t e) {
-            cp[t] = e;
-            if (tleaf) tleaf[t] = (int32_t)first_leaf(t);
-        },
-        sh);
+        n_tiles, [&](int64_t q) { return chunks(sorted ? ord_sh[q] : q); },
+        [&](int64_t q, int64_t e) { cp[q] = e; }, sh);
+    if (tleaf)
+        for (int t = threadIdx.x; t < n_tiles; t += 1024) tleaf[t] = (int32_t)first_leaf(t);
     if (threadIdx.x == 0) cp[n_tiles] = tot;
 }
 
@@ -406,7 +447,8 @@ struct PartHist {
     const uint32_t* gq;
     const uint16_t* code;
     const int64_t* off;
-    const int64_t* cp;
+    const int64_t* cp;             // chunk prefix by place in the processing order
+    const int32_t* tord;           // tile at each place
     const int32_t* tleaf;          // subtraction: the leaf tile t (a parent) accumulates, or NULL
     uint32_t* partials;            // [chunk][lt][F][B][wpc]
     int64_t n_pad, n_items, segs_per_chunk;
@@ -437,8 +479,8 @@ __global__ __launch_bounds__(kHistThreads) void hist_part_kernel(PartHist a) {
         const int mid = (lo + hi + 1) >> 1;
         if (a.cp[mid] <= gc) lo = mid; else hi = mid - 1;
     }
-    const int t = lo;
-    const int64_t j = gc - a.cp[t];
+    const int t = a.tord[lo];
+    const int64_t j = gc - a.cp[lo];
     const uint32_t s0 = a.tleaf ? (uint32_t)a.tleaf[t] : (uint32_t)t * (uint32_t)a.lt;
     const uint32_t ns = a.tleaf ? 1u : min((uint32_t)a.lt, (uint32_t)a.L - s0);
     const int64_t pa = a.off[s0], pb = a.off[s0 + ns];
@@ -495,6 +537,7 @@ __device__ __forceinline__ float2 f2_sub_pair(float2 P, float2 r) {
 template <int PREC>
 __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restrict__ part,
                                                          const int64_t* __restrict__ cp,
+                                                         const int32_t* __restrict__ tplace,
                                                          int32_t L, int32_t lt, int32_t F,
                                                          int32_t B, int32_t K, int32_t wpc,
                                                          int32_t rmse, void* __restrict__ out,
@@ -509,8 +552,9 @@ __global__ __launch_bounds__(256) void part_merge_kernel(const uint32_t* __restr
         const int c = (int)(u % K);
         const int64_t v = cell / fb, rest = cell % fb;
         const int64_t t = v / lt;
-        const int64_t g0 = cp[t];
-        const int nch = (int)(cp[t + 1] - g0);
+        const int64_t q = tplace[t];
+        const int64_t g0 = cp[q];
+        const int nch = (int)(cp[q + 1] - g0);
         const uint32_t* p = part + g0 * cw + ((v - t * lt) * fb + rest) * wpc;
         // where the sum goes, and (subtraction) the sibling's cell
         int64_t dst = cell, sib = -1;
@@ -670,9 +714,12 @@ static HistPlan plan_part(const HistKnobs& kn, int64_t n, int32_t F, int32_t B, 
     p.n_fgroups = (F + W - 1) / W;
     const int64_t per_chunk = int64_t(p.n_fgroups) * K;     // blocks per chunk of rows
     // the K class blocks of one (chunk, feature group) read the same bins,
-    // which stay in L2 only if their row range is short: with several
-    // classes, 8 times as many blocks
-    const int64_t target = int64_t(std::max<int32_t>(1, kn.target_blocks)) * (K > 1 ? 8 : 1);
+    // which stay in L2 only if their row range is short; and leaves differ in
+    // size by orders of magnitude, so short chunks also even out the blocks'
+    // work (measured on 5*10^7 rows, 10 classes, depth 10: 32 times the
+    // block target took the builds of a tree from 257 to 241 ms, at the cost
+    // of more partial tiles to merge)
+    const int64_t target = int64_t(std::max<int32_t>(1, kn.target_blocks)) * (K > 1 ? 32 : 1);
     int64_t rows = std::max<int64_t>(kn.min_rows, n * per_chunk / target);
     rows = align_up(std::min<int64_t>(rows, align_up(n, 16)), 16);
     if (precision == CBH_PREC_INT16) rows = std::min<int64_t>(rows, 65536);
@@ -688,7 +735,7 @@ static void free_part(cbh_part* p) {
     void* bufs[] = {p->bins[0], p->bins[1], p->cols[0], p->cols[1], p->seg,   p->g[0],
                     p->g[1],    p->h[0],    p->h[1],    p->gq[0],   p->gq[1], p->order[0],
                     p->order[1], p->code[0], p->code[1], p->off[0], p->off[1], p->zl,
-                    p->blk,     p->cp,      p->tleaf};
+                    p->blk,     p->cp,      p->tord,    p->tleaf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -750,7 +797,7 @@ int cbh_part_create(cbh_ctx* ctx, const cbh_problem* prob, cbh_part** out) {
     }
     ok = ok && alloc((void**)&p->seg, F * 8) && alloc((void**)&p->zl, half * 4) &&
          alloc((void**)&p->blk, (p->n_pb + 1) * 8) && alloc((void**)&p->cp, (half + 1) * 8) &&
-         alloc((void**)&p->tleaf, half * 4);
+         alloc((void**)&p->tord, 2 * half * 4) && alloc((void**)&p->tleaf, half * 4);
     if (!ok) {
         free_part(p);
         delete p;
@@ -883,7 +930,7 @@ static int part_build(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int
     rc = ensure_ws(ctx, max_chunks * cell_words * 4, stream);
     if (rc) return rc;
     part_tiles_kernel<<<1, 1024, 0, s>>>(part->off[src], L, plan.lt, (int32_t)n_tiles, spc,
-                                          part->cp, sub ? part->tleaf : nullptr);
+                                          part->cp, part->tord, sub ? part->tleaf : nullptr);
     CBH_LAUNCHED();
     PartHist a;
     const bool q = precision == CBH_PREC_INT16;
@@ -895,6 +942,7 @@ static int part_build(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int
     a.code = part->code[src];
     a.off = part->off[src];
     a.cp = part->cp;
+    a.tord = part->tord;
     a.tleaf = sub ? part->tleaf : nullptr;
     a.partials = (uint32_t*)ctx->ws;
     a.n_pad = part->n_pad;
@@ -937,17 +985,20 @@ static int part_build(cbh_ctx* ctx, cbh_part* part, const cbh_problem* prob, int
     switch (out_prec(precision)) {
         case CBH_PREC_FP32:
             part_merge_kernel<CBH_PREC_FP32><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                (const uint32_t*)ctx->ws, part->cp, part->tord + n_tiles, Lm, plan.lt, F, B, K,
+                plan.words_per_cell,
                 rmse, hist_out, tl, parent_hist);
             break;
         case CBH_PREC_TWOFLOAT:
             part_merge_kernel<CBH_PREC_TWOFLOAT><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                (const uint32_t*)ctx->ws, part->cp, part->tord + n_tiles, Lm, plan.lt, F, B, K,
+                plan.words_per_cell,
                 rmse, hist_out, tl, parent_hist);
             break;
         default:
             part_merge_kernel<CBH_PREC_INT16><<<mg, 256, 0, s>>>(
-                (const uint32_t*)ctx->ws, part->cp, Lm, plan.lt, F, B, K, plan.words_per_cell,
+                (const uint32_t*)ctx->ws, part->cp, part->tord + n_tiles, Lm, plan.lt, F, B, K,
+                plan.words_per_cell,
                 rmse, hist_out, tl, parent_hist);
             break;
     }
