@@ -232,11 +232,22 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
         const int64_t sst = none ? 16 : seg_stride_of(m.src_seg, sp.feature);
         const int64_t p0 = P0 + 16 * sg;
         uint32_t bits = 0u, valid = 0u;
-        for (int j = 0; j < 16; ++j) {
-            const int64_t pos = p0 + j;
-            if (pos >= m.n) break;
-            valid |= 1u << j;
-            if (split_bit(scol, sst, pos, sp.border)) bits |= 1u << j;
+        const uint8_t* sb = scol ? scol + (p0 >> 4) * sst : nullptr;
+        if (sb && p0 + 16 <= m.n && ((reinterpret_cast<uintptr_t>(sb) & 15) == 0)) {
+            // the segment's 16 bins of the split feature in one load
+            const uint4 w = gld_u4(sb);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+            valid = 0xffffu;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if ((int)((ws[j >> 2] >> (8 * (j & 3))) & 255u) > sp.border) bits |= 1u << j;
+        } else {
+            for (int j = 0; j < 16; ++j) {
+                const int64_t pos = p0 + j;
+                if (pos >= m.n) break;
+                valid |= 1u << j;
+                if (split_bit(scol, sst, pos, sp.border)) bits |= 1u << j;
+            }
         }
         const uint32_t zmask = valid & ~bits;
         const uint32_t nz = (uint32_t)__popc(zmask);
