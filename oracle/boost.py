@@ -20,8 +20,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (apply_split, best_split, combine_categories, gradients, histogram,
-               leaf_values, ordered_ts, quantize, score, select_borders, ts_borders,
+from . import (apply_split, best_split, category_counts, combine_categories, gradients,
+               histogram, leaf_values, ordered_ts, quantize, score, select_borders, ts_borders,
                update_approx)
 
 
@@ -37,6 +37,9 @@ class Prepared:
     nb_ts: int
     timings: dict = field(default_factory=dict)
     n_priors: int = 1                    # Q statistic columns per (feature, target)
+    counters: bool = False               # one counter column after each feature's statistics
+
+    _n_cat: int = 0
 
     def tree_features(self, t: int):
         """Histogram features of tree t: numeric bins then TS bins of perm t mod s."""
@@ -70,7 +73,9 @@ def prepare(p) -> Prepared:
     T = p.n_targets
     pl = prior_lists(p)
     Q = len(pl[0]) if T else 1
-    ts_bins = np.zeros((s, p.n_cat * T * Q, p.n), np.uint8)
+    cnt = bool(getattr(p, "counters", False))
+    per = T * Q + (1 if cnt else 0)
+    ts_bins = np.zeros((s, p.n_cat * per, p.n), np.uint8)
     ts_num = np.zeros((s, p.n_cat * T, p.n), np.int64)
     ts_den = np.zeros((s, p.n_cat, p.n), np.int32)
     for r in range(s):
@@ -79,13 +84,29 @@ def prepare(p) -> Prepared:
                 for q in range(Q):
                     num, den, _, tbin = ordered_ts(p.cat[c], p.perms[r], p.y_num[j], p.y_shift,
                                                    p.a, pl[j][q], tb)
-                    ts_bins[r, (c * T + j) * Q + q] = tbin
+                    ts_bins[r, c * per + j * Q + q] = tbin
                 ts_num[r, c * T + j] = num
                 ts_den[r, c] = den
+            if cnt:
+                ts_bins[r, c * per + T * Q] = counter_bins(p.cat[c], p.ts_bins)
     t3 = time.perf_counter()
     nb_num = np.array([len(b) + 1 for b in borders], np.int32)
-    return Prepared(num_bins, borders, ts_bins, ts_num, ts_den, tb, nb_num, p.ts_bins,
-                    {"borders_s": t1 - t0, "quantize_s": t2 - t1, "ordered_ts_s": t3 - t2}, Q)
+    prep = Prepared(num_bins, borders, ts_bins, ts_num, ts_den, tb, nb_num, p.ts_bins,
+                    {"borders_s": t1 - t0, "quantize_s": t2 - t1, "ordered_ts_s": t3 - t2}, Q,
+                    cnt)
+    prep._n_cat = p.n_cat
+    return prep
+
+
+def counter_bins(values, n_bins: int) -> np.ndarray:
+    """The counter statistic (Sec. 2: a category, or a combination, replaced
+    by its number of appearances in the dataset) binarized on a log2 scale:
+    bin = floor(log2(count)), at most n_bins - 1 (the paper gives no
+    binarization; Zipf-like counts spread over these bins)."""
+    ids, _ = combine_categories(np.asarray(values, np.int32), np.zeros(len(values), np.int32))
+    cnt = category_counts(ids).astype(np.int64)
+    b = np.floor(np.log2(np.maximum(cnt, 1))).astype(np.int64)
+    return np.minimum(b, n_bins - 1).astype(np.uint8)
 
 
 @dataclass
@@ -125,10 +146,11 @@ class CombinationTree:
     hash) and its ordered statistics, for every target and prior on the
     tree's permutation, become candidates of every later level.
 
-    Candidate order at a level: the tree's own columns (numeric, then the
-    statistic columns by categorical feature, target, prior), then for every
-    earlier level j in order and every categorical feature c in order, the
-    T*Q statistic columns of combination (j, c), by target, then prior.
+    Candidate order at a level: the tree's own columns (numeric, then per
+    categorical feature its statistic columns by target and prior, then its
+    counter column when counters are on), then for every earlier level j in
+    order and every categorical feature c in order, the columns of
+    combination (j, c) in the same order.
     Combinations equal to a column already present (a feature combined with
     itself) stay candidates; equal scores go to the lower index."""
 
@@ -138,7 +160,9 @@ class CombinationTree:
         self.base_bins, self.base_nb = prep.tree_features(t)
         self.F_num = p.n_num
         self.T, self.Q = p.n_targets, prep.n_priors
-        self.TQ = self.T * self.Q
+        self.counters = prep.counters
+        # columns per categorical feature or crossing: statistics, then counter
+        self.TQ = self.T * self.Q + (1 if self.counters else 0)
         self.F_base = self.base_bins.shape[0]
         self.pl = prior_lists(p)
         self.combo_ids = []      # [level j][categorical feature c] int32 [n]
@@ -180,6 +204,8 @@ class CombinationTree:
                     _, _, _, tb = ordered_ts(ids, perm, p.y_num[t], p.y_shift, p.a,
                                              self.pl[t][q], self.prep.ts_borders)
                     self.combo_bins.append(tb)
+            if self.counters:
+                self.combo_bins.append(counter_bins(ids, self.prep.nb_ts))
         self.combo_ids.append(level_ids)
 
 

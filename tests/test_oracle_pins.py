@@ -717,6 +717,16 @@ def _brute_ts_bins(keys, perm, y_num, y_shift, a, prior, borders):
     return out
 
 
+def _brute_counter_bins(keys, n_bins):
+    """Every row's number of rows with its key, on the log2 scale (the bit
+    length of the count, minus one), capped at n_bins - 1."""
+    out = np.zeros(len(keys), np.uint8)
+    for i, k in enumerate(keys):
+        c = sum(1 for x in keys if x == k)
+        out[i] = min(c.bit_length() - 1, n_bins - 1)
+    return out
+
+
 def _brute_candidates(p, prep, t, splits):
     """The candidate columns of a tree after the given splits, built without
     the oracle's combination code: a combination's value per row is the
@@ -724,6 +734,8 @@ def _brute_candidates(p, prep, t, splits):
     from oracle import boost
     base_bins, _ = prep.tree_features(t)
     F_num, T, Q = p.n_num, p.n_targets, prep.n_priors
+    cnt = bool(getattr(p, "counters", False))
+    per = T * Q + (1 if cnt else 0)
     F_base = base_bins.shape[0]
     pl = boost.prior_lists(p)
     perm = p.perms[t % p.perms.shape[0]]
@@ -734,9 +746,9 @@ def _brute_candidates(p, prep, t, splits):
         elif f < F_num:
             v = [int(b > k) for b in cols[f]]
         elif f < F_base:
-            v = [int(x) for x in p.cat[(f - F_num) // (T * Q)]]
+            v = [int(x) for x in p.cat[(f - F_num) // per]]
         else:
-            j, c = divmod((f - F_base) // (T * Q), p.n_cat)
+            j, c = divmod((f - F_base) // per, p.n_cat)
             v = combo_keys[j][c]
         level = []
         for c in range(p.n_cat):
@@ -746,12 +758,15 @@ def _brute_candidates(p, prep, t, splits):
                 for q in range(Q):
                     cols.append(_brute_ts_bins(keys, perm, p.y_num[tt], p.y_shift, p.a,
                                                pl[tt][q], prep.ts_borders))
+            if cnt:
+                cols.append(_brute_counter_bins(keys, prep.nb_ts))
         combo_keys.append(level)
     return np.stack(cols)
 
 
+@pytest.mark.parametrize("counters", [False, True])
 @pytest.mark.parametrize("loss,K,seed", [(1, 1, 0), (0, 1, 1), (2, 3, 2)])
-def test_combination_candidates_brute_force(oracle_lib, loss, K, seed):
+def test_combination_candidates_brute_force(oracle_lib, loss, K, seed, counters):
     """Sec. 2 "Feature combinations": after each split, the split's value
     (a categorical feature, a combination, or a numeric split's two values)
     crossed with every categorical feature gives new candidate columns whose
@@ -760,7 +775,14 @@ def test_combination_candidates_brute_force(oracle_lib, loss, K, seed):
     element: numeric, statistic column, combination column, no split."""
     from oracle import boost
     p = datagen.make_interactions(n=48, loss=loss, K=K, seed=seed, C=(3, 4, 2), depth=5)
+    p.counters = counters
     prep = boost.prepare(p)
+    if counters:
+        # the tree's own counter columns: rows per category, brute force
+        per = p.n_targets * prep.n_priors + 1
+        for c in range(p.n_cat):
+            want = _brute_counter_bins([int(x) for x in p.cat[c]], prep.nb_ts)
+            assert np.array_equal(prep.ts_bins[0, c * per + per - 1], want)
     ct0 = boost.CombinationTree(prep, p, 0)
     F_base = ct0.F_base
     TQ = ct0.TQ
