@@ -436,6 +436,12 @@ int cbh_category_order(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, in
  *   y_num       device int64 [n_targets][n]
  *   priors      host double [n_targets][n_priors], n_priors <= 8
  *   ts_bin_out  device array of n_cross device uint8 [n_targets * n_priors][ld]
+ *   counter_bins  0, or the bins of a counter column written after the
+ *               statistics of every crossing, at column n_targets * n_priors
+ *               (the counter statistic of Sec. 2, also calculated for
+ *               combinations: the number of rows of the row's group, as
+ *               cbh_counter_bins bins it); ts_bin_out then holds
+ *               n_targets * n_priors + 1 columns per crossing
  * Errors: CBH_EINVAL on bad arguments, CBH_EUNSUPPORTED when e_bits plus the
  * crossing index bits exceed 32 or n_cross * n >= 2^31, CBH_EOVERFLOW as
  * cbh_compute_ordered_ts. Uses workspace of about 33 * n_cross * n bytes. */
@@ -444,8 +450,17 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
                              const int32_t* const* c_ids, int64_t n, const int64_t* y_num,
                              int32_t n_targets, int32_t y_shift, int64_t y_abs_max, double a,
                              int32_t n_priors, const double* priors, const double* ts_borders,
-                             int32_t n_ts_borders, uint8_t* const* ts_bin_out, int64_t ld,
-                             void* stream);
+                             int32_t n_ts_borders, int32_t counter_bins,
+                             uint8_t* const* ts_bin_out, int64_t ld, void* stream);
+
+/* Bins of the counter statistic (Sec. 2: a category, or a combination,
+ * replaced by its number of appearances in the dataset; counts from
+ * cbh_category_counts): bin = floor(log2(count)), at most n_bins - 1, and 0
+ * for a count below 1. The paper gives no binarization for it; the log2
+ * scale spreads Zipf-like counts over the bins.
+ *   counts    device int32 [n];  bins_out  device uint8 [n] */
+int cbh_counter_bins(cbh_ctx* ctx, const int32_t* counts, int64_t n, int32_t n_bins,
+                     uint8_t* bins_out, void* stream);
 
 /* Ordered target statistic of a grouping for one more prior (Sec. 2: several
  * priors, a feature for each), from the numerators and counts that

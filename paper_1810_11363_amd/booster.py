@@ -57,7 +57,7 @@ class GpuBooster:
                  lr, l2, num_bins, ts_bins, a, ts_lo, ts_hi, precision=cb.CBH_PREC_FP32,
                  subtract=None, device="cuda:0", ctx=None, stream=None, layout="tiled",
                  borders=None, partition=None, ordered=False, extra_priors=(),
-                 combinations=False):
+                 combinations=False, counters=False):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.graphs = []
@@ -96,7 +96,11 @@ class GpuBooster:
         # and then every extra prior, one column each
         self.extra_priors = [float(v) for v in extra_priors]
         self.Q = 1 + len(self.extra_priors)
-        self.F = self.F_num + self.F_cat * self.T * self.Q
+        # the counter statistic (Sec. 2): one more column per categorical
+        # feature (and per crossing), after its statistic columns
+        self.counters = bool(counters) and self.F_cat > 0
+        self.CPC = self.T * self.Q + (1 if self.counters else 0)
+        self.F = self.F_num + self.F_cat * self.CPC
         # greedy feature combinations (Sec. 2): candidate columns added level
         # by level from the tree's own splits (direct builds in the original
         # row order)
@@ -127,7 +131,8 @@ class GpuBooster:
                    y_shift=p.y_shift, priors=p.priors, loss=p.loss, K=p.K, depth=p.depth,
                    lr=p.lr, l2=p.l2, num_bins=p.num_bins, ts_bins=p.ts_bins, a=p.a,
                    ts_lo=p.ts_lo, ts_hi=p.ts_hi,
-                   extra_priors=getattr(p, "extra_priors", []), **kw)
+                   extra_priors=getattr(p, "extra_priors", []),
+                   counters=getattr(p, "counters", False), **kw)
 
     # ---------------------------------------------------------------- buffers
     def _alloc(self):
@@ -135,7 +140,7 @@ class GpuBooster:
         ld = _ld(n)
         self.ld = ld
         self.num_bins_d = torch.empty((max(self.F_num, 1), ld), dtype=torch.uint8, device=d)
-        self.ts_bins_d = torch.empty((self.s, max(self.F_cat * self.T * self.Q, 1), ld),
+        self.ts_bins_d = torch.empty((self.s, max(self.F_cat * self.CPC, 1), ld),
                                      dtype=torch.uint8, device=d)
         self.label = torch.from_numpy(self.label_h).to(d)
         self.g = torch.empty((K, n), dtype=torch.float32, device=d)
@@ -231,17 +236,26 @@ class GpuBooster:
                             for q in range(self.Q):
                                 cb.cbh_ts_bins(self.ctx, num_t[t], den_t, n, self.y_shift,
                                                self.a, pl[t][q], ts_b, self.ts_bins - 1,
-                                               ts_bin_out=self.ts_bins_d[r, (c * self.T + t)
-                                                                         * self.Q + q],
+                                               ts_bin_out=self.ts_bins_d[r, c * self.CPC
+                                                                         + t * self.Q + q],
                                                stream=st)
                         continue
-                    dst = self.ts_bins_d[r, c * self.T:(c + 1) * self.T]
+                    dst = self.ts_bins_d[r, c * self.CPC:c * self.CPC + self.T]
                     out = tmp if tmp is not None else dst
                     cb.cbh_compute_ordered_ts(self.ctx, cat_d[c], perm_d[r], n, y_d, self.T,
                                               self.y_shift, yabs, self.a, self.priors, ts_b,
                                               self.ts_bins - 1, ts_bin_out=out, stream=st)
                     if tmp is not None:
                         dst[:, :n].copy_(tmp)
+            if self.counters:
+                ids = torch.empty(n, dtype=torch.int32, device=d)
+                cnt = torch.empty(n, dtype=torch.int32, device=d)
+                for c in range(self.F_cat):
+                    cb.cbh_category_order(self.ctx, cat_d[c], None, n, None, ids, None, st)
+                    cb.cbh_category_counts(self.ctx, ids, n, cnt, st)
+                    for r in range(self.s):
+                        cb.cbh_counter_bins(self.ctx, cnt, n, self.ts_bins,
+                                            self.ts_bins_d[r, c * self.CPC + self.T * self.Q], st)
             torch.cuda.synchronize(d)
             t5 = time.perf_counter()
         cb.cbh_sync(self.ctx, st)
@@ -252,9 +266,9 @@ class GpuBooster:
         cols, nbs = [], []
         for r in range(self.s):
             ptrs = [self.num_bins_d[f].data_ptr() for f in range(self.F_num)]
-            ptrs += [self.ts_bins_d[r, j].data_ptr() for j in range(self.F_cat * self.T * self.Q)]
+            ptrs += [self.ts_bins_d[r, j].data_ptr() for j in range(self.F_cat * self.CPC)]
             cols.append(ptrs)
-            nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.T * self.Q,
+            nbs.append(np.concatenate([nb_num, np.full(self.F_cat * self.CPC,
                                                        self.ts_bins, np.int32)]))
         self.col_table = torch.tensor(cols, dtype=torch.int64, device=d)
         self.seg_table = None
@@ -305,7 +319,7 @@ class GpuBooster:
         every combination column a tree can reach) and the split source of
         every column."""
         d, n, ld = self.device, self.n, self.ld
-        D, Cn, TQ = max(self.depth - 1, 1), self.F_cat, self.T * self.Q
+        D, Cn, TQ = max(self.depth - 1, 1), self.F_cat, self.CPC
         self.F_combo = (self.depth - 1) * Cn * TQ
         self.F_hist = self.F + self.F_combo
         self.ts_borders_d = ts_b
@@ -373,7 +387,7 @@ class GpuBooster:
         p.bins = self.col_x[r].data_ptr()
         p.seg_stride = self.seg_x[r].data_ptr()
         p.n_bins = self.nb_x[r].data_ptr()
-        p.n_features = self.F + level * self.F_cat * self.T * self.Q
+        p.n_features = self.F + level * self.F_cat * self.CPC
         return p
 
     def combo_level(self, t: int, level: int):
@@ -406,7 +420,7 @@ class GpuBooster:
                                     self.c_order_tab[r], self.c_ids_tab, n, self.y_dc, self.T,
                                     self.y_shift, self.y_abs, self.a, self.Q, self.priors_flat,
                                     self.ts_borders_d, self.ts_bins - 1, self.bins_tab[level],
-                                    self.ld, st)
+                                    self.ld, self.ts_bins if self.counters else 0, st)
 
     def _combo_tree(self, t: int, counts: bool = False):
         for lvl in range(self.depth):
@@ -420,7 +434,7 @@ class GpuBooster:
     def combo_bins_host(self, level: int) -> np.ndarray:
         """uint8 [level * F_cat * T * Q][n]: the combination columns that are
         candidates at `level` (for checks)."""
-        m = level * self.F_cat * self.T * self.Q
+        m = level * self.F_cat * self.CPC
         if m == 0:
             return np.zeros((0, self.n), np.uint8)
         cols = self.combo_bins[:level].reshape(-1, self.ld)[:, : self.n]

@@ -45,6 +45,7 @@ EXPORTS = [
     "cbh_ordered_gradients", "cbh_ordered_update", "cbh_fit_tree_ordered",
     "cbh_split_values", "cbh_ts_bins", "cbh_binarize", "cbh_apply_model_binarized",
     "cbh_graph_begin", "cbh_graph_end", "cbh_category_order", "cbh_ordered_ts_crossings",
+    "cbh_counter_bins",
 ]
 
 
@@ -125,7 +126,8 @@ def _load():
         "cbh_split_values": ([vp, vp, vp, i32, i64, vp, vp, vp], C.c_int),
         "cbh_category_order": ([vp, vp, vp, i64, vp, vp, vp, vp], C.c_int),
         "cbh_ordered_ts_crossings": ([vp, vp, i32, i32, vp, vp, i64, vp, i32, i32, i64, dbl, i32,
-                                      vp, vp, i32, vp, i64, vp], C.c_int),
+                                      vp, vp, i32, i32, vp, i64, vp], C.c_int),
+        "cbh_counter_bins": ([vp, vp, i64, i32, vp, vp], C.c_int),
         "cbh_binarize": ([vp, vp, vp, i64, i32, i32, vp, vp, vp, vp], C.c_int),
         "cbh_apply_model_binarized": ([vp, vp, i64, i32, i32, i32, i32, vp, vp, dbl, vp, vp],
                                       C.c_int),
@@ -555,13 +557,18 @@ def cbh_category_order(ctx, cat, perm, n: int, order_out=None, ids_out=None,
 def cbh_ordered_ts_crossings(ctx, e_ids, e_bits: int, n_cross: int, c_order, c_ids, n: int,
                              y_num, n_targets: int, y_shift: int, y_abs_max: int, a: float,
                              n_priors: int, priors, ts_borders, n_ts_borders: int, ts_bin_out,
-                             ld: int, stream=None):
+                             ld: int, counter_bins: int = 0, stream=None):
     pri = (C.c_double * (n_targets * n_priors))(*[float(p) for p in priors])
     return _check(_lib.cbh_ordered_ts_crossings(
         ctx, _ptr(e_ids), int(e_bits), int(n_cross), _ptr(c_order), _ptr(c_ids), int(n),
         _ptr(y_num), int(n_targets), int(y_shift), int(y_abs_max), float(a), int(n_priors),
-        C.cast(pri, C.c_void_p), _ptr(ts_borders), int(n_ts_borders), _ptr(ts_bin_out), int(ld),
-        _stream(stream)))
+        C.cast(pri, C.c_void_p), _ptr(ts_borders), int(n_ts_borders), int(counter_bins),
+        _ptr(ts_bin_out), int(ld), _stream(stream)))
+
+
+def cbh_counter_bins(ctx, counts, n: int, n_bins: int, bins_out, stream=None):
+    return _check(_lib.cbh_counter_bins(ctx, _ptr(counts), int(n), int(n_bins), _ptr(bins_out),
+                                        _stream(stream)))
 
 
 def cbh_ts_bins(ctx, num, den, n: int, y_shift: int, a: float, prior: float, ts_borders,

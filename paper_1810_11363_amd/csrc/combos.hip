@@ -83,9 +83,36 @@ __global__ __launch_bounds__(256) void ts_bins_kernel(
     }
 }
 
+// Counter bins: floor(log2(count)) capped at n_bins - 1; 0 for count < 1.
+__global__ __launch_bounds__(256) void counter_bins_kernel(const int32_t* __restrict__ counts,
+                                                           int64_t n, int32_t n_bins,
+                                                           uint8_t* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        const int32_t c = counts[i];
+        const int b = c > 0 ? 31 - __clz((uint32_t)c) : 0;
+        out[i] = (uint8_t)min(b, n_bins - 1);
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+int cbh_counter_bins(cbh_ctx* ctx, const int32_t* counts, int64_t n, int32_t n_bins,
+                     uint8_t* bins_out, void* stream) {
+    clear_error();
+    CBH_ARG(ctx != nullptr, "ctx is NULL");
+    CBH_ARG(n >= 0, "n must be >= 0");
+    CBH_ARG(n_bins >= 1 && n_bins <= 256, "n_bins must be in [1, 256]");
+    if (n == 0) return CBH_OK;
+    CBH_ARG(counts && bins_out, "NULL argument");
+    counter_bins_kernel<<<grid_for(n, 256, ctx->num_cus * 8), 256, 0, (hipStream_t)stream>>>(
+        counts, n, n_bins, bins_out);
+    CBH_LAUNCHED();
+    return CBH_OK;
+}
+
 
 int cbh_split_values(cbh_ctx* ctx, const cbh_split* split, const cbh_split_source* sources,
                      int32_t n_sources, int64_t n, int32_t* a_out, int32_t* b_out,

@@ -539,6 +539,35 @@ __global__ __launch_bounds__(256) void cross_scatter_kernel(
     }
 }
 
+// The counter statistic of every crossing's groups (Sec. 2): the group
+// of sorted element p starts at p - den[p] (den: its exclusive index in the
+// group); the group's last element records the group's size at the start,
+// every element then reads it and writes its bin, floor(log2(size)) capped
+// at n_bins - 1, to out[k][col ld + row].
+__global__ void cross_group_size_kernel(const uint8_t* __restrict__ head,
+                                        const int64_t* __restrict__ den_s, int64_t N,
+                                        uint32_t* __restrict__ size_at_start) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        if (p == N - 1 || head[p + 1]) size_at_start[p - den_s[p]] = (uint32_t)(den_s[p] + 1);
+    }
+}
+
+__global__ void cross_counter_kernel(const uint32_t* __restrict__ keys,
+                                     const int32_t* __restrict__ rows,
+                                     const int64_t* __restrict__ den_s,
+                                     const uint32_t* __restrict__ size_at_start, int64_t N,
+                                     int32_t e_bits, int32_t n_bins, int32_t col,
+                                     uint8_t* const* __restrict__ out, int64_t ld) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
+        const uint32_t c = size_at_start[p - den_s[p]];
+        const int b = c ? 31 - __clz(c) : 0;
+        out[k][int64_t(col) * ld + rows[p]] = (uint8_t)min(b, n_bins - 1);
+    }
+}
+
 static int grid_for(int64_t n, int per_block, int cap = 16384) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -847,8 +876,8 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
                              const int32_t* const* c_ids, int64_t n, const int64_t* y_num,
                              int32_t n_targets, int32_t y_shift, int64_t y_abs_max, double a,
                              int32_t n_priors, const double* priors, const double* ts_borders,
-                             int32_t n_ts_borders, uint8_t* const* ts_bin_out, int64_t ld,
-                             void* stream) {
+                             int32_t n_ts_borders, int32_t counter_bins,
+                             uint8_t* const* ts_bin_out, int64_t ld, void* stream) {
     clear_error();
     CBH_ARG(ctx != nullptr, "ctx is NULL");
     CBH_ARG(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31 - 1]");
@@ -871,6 +900,7 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     CBH_REQUIRE(y_abs_max == 0 || (double)n * (double)y_abs_max < 4.611686018427387904e18,
                 CBH_EOVERFLOW, "n * y_abs_max must be < 2^62 for exact int64 sums");
     CBH_ARG(ld >= n, "ld must be >= n");
+    CBH_ARG(counter_bins >= 0 && counter_bins <= 256, "counter_bins must be in [0, 256]");
     if (n == 0) return CBH_OK;
     CBH_ARG(e_ids && c_order && c_ids && y_num && priors && ts_bin_out, "NULL argument");
     CBH_ARG(n_ts_borders == 0 || ts_borders, "ts_borders is NULL");
@@ -942,6 +972,14 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
         cross_scatter_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, e_bits,
                                                 y_shift, a, pri, n_priors, t, ts_borders,
                                                 n_ts_borders, ts_bin_out, ld);
+        CBH_LAUNCHED();
+    }
+    if (counter_bins > 0) {
+        uint32_t* size_at_start = keys[cur ^ 1];     // free after the sort
+        cross_group_size_kernel<<<gs, 256, 0, s>>>(head, den_s, N, size_at_start);
+        cross_counter_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, size_at_start, N,
+                                                e_bits, counter_bins, n_targets * n_priors,
+                                                ts_bin_out, ld);
         CBH_LAUNCHED();
     }
     return CBH_OK;

@@ -164,4 +164,5 @@ def test_combination_calls_reject_null_without_launch(cb):
     assert C.sizeof(cb.cbh_split_source) == 32
     assert L.cbh_category_order(None, None, None, 10, None, None, None, None) == cb.CBH_EINVAL
     assert L.cbh_ordered_ts_crossings(None, None, 20, 2, None, None, 10, None, 1, 0, 1, 1.0, 1,
-                                      None, None, 0, None, 10, None) == cb.CBH_EINVAL
+                                      None, None, 0, 0, None, 10, None) == cb.CBH_EINVAL
+    assert L.cbh_counter_bins(None, None, 10, 16, None, None) == cb.CBH_EINVAL

@@ -94,6 +94,8 @@ CASES = {
     "logloss": dict(loss=1, K=1, n=20011, seed=0),
     "rmse": dict(loss=0, K=1, n=30001, seed=1),
     "multiclass": dict(loss=2, K=3, n=12007, seed=2),
+    "logloss_counters": dict(loss=1, K=1, n=20011, seed=3, counters=True),
+    "rmse_counters": dict(loss=0, K=1, n=30001, seed=4, counters=True),
 }
 
 
@@ -105,6 +107,7 @@ def test_combination_trees_lockstep(cb, name, prec):
     kw = CASES[name]
     p = datagen.make_interactions(n=kw["n"], loss=kw["loss"], K=kw["K"], seed=kw["seed"],
                                   depth=4, s=2)
+    p.counters = kw.get("counters", False)
     prep = boost.prepare(p)
     bst = GpuBooster.from_problem(p, precision=prec, combinations=True).prepare()
     for r in range(bst.s):
@@ -282,5 +285,33 @@ def test_category_order_and_crossings(cb, n):
                 for q in range(Q):
                     _, _, _, wb = oracle.ordered_ts(pid, perm, y[t], 0, 1.0, priors[t][q], tb)
                     assert np.array_equal(got[c, t * Q + q, :n], wb), (c, t, q)
+    finally:
+        cb.cbh_destroy(ctx)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 65537])
+def test_counter_columns(cb, n):
+    """The counter statistic's columns (a categorical feature's rows per
+    category, log2 bins) of a plain booster equal the oracle's; and
+    cbh_counter_bins on hand counts."""
+    from oracle import boost
+    from paper_1810_11363_amd.booster import GpuBooster
+    p = datagen.make_interactions(n=n, loss=1, seed=9, s=2)
+    p.counters = True
+    prep = boost.prepare(p)
+    bst = GpuBooster.from_problem(p, precision=gu.F64).prepare()
+    for r in range(bst.s):
+        bins, nb = prep.tree_features(r)
+        assert np.array_equal(bst.bins_host(r), bins)
+        assert np.array_equal(bst.nbins_table[r].cpu().numpy(), nb)
+    bst.close()
+    ctx = cb.cbh_create(0)
+    try:
+        counts = np.array([0, 1, 2, 3, 4, 7, 8, 1000, 65536, 2 ** 31 - 1], np.int32)
+        out = torch.empty(counts.size, dtype=torch.uint8, device=gu.dev())
+        cb.cbh_counter_bins(ctx, gu.to_dev(counts), counts.size, 12, out)
+        cb.cbh_sync(ctx)
+        want = [0, 0, 1, 1, 2, 2, 3, 9, 11, 11]
+        assert out.cpu().numpy().tolist() == want
     finally:
         cb.cbh_destroy(ctx)
