@@ -490,19 +490,45 @@ __global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits,
 }
 
 // A sorted element starts a new group where its key (crossing, e) or its
-// category in that crossing differs from the previous element's.
-__global__ void cross_heads_kernel(const uint32_t* __restrict__ keys,
-                                   const int32_t* __restrict__ rows,
-                                   const int32_t* const* __restrict__ cids, int32_t e_bits,
-                                   int64_t N, uint8_t* __restrict__ head) {
-    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
-         p += int64_t(gridDim.x) * blockDim.x) {
-        bool h = p == 0 || keys[p] != keys[p - 1];
-        if (!h) {
-            const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
-            h = cids[k][rows[p]] != cids[k][rows[p - 1]];
+// category in that crossing differs from the previous element's. Each thread
+// gathers its own element's category once; the previous element's comes
+// from LDS (from global memory for a block's first element).
+__global__ __launch_bounds__(256) void cross_heads_kernel(
+    const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
+    const int32_t* const* __restrict__ cids, int32_t e_bits, int64_t N,
+    uint8_t* __restrict__ head) {
+    __shared__ int32_t sc[256];
+    __shared__ uint32_t sk[256];
+    for (int64_t base = int64_t(blockIdx.x) * 256; base < N; base += int64_t(gridDim.x) * 256) {
+        const int64_t p = base + threadIdx.x;
+        uint32_t key = 0u;
+        int32_t c = 0;
+        if (p < N) {
+            key = keys[p];
+            const int k = e_bits >= 32 ? 0 : (int)(key >> e_bits);
+            c = cids[k][rows[p]];
         }
-        head[p] = h ? 1 : 0;
+        sk[threadIdx.x] = key;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        if (p < N) {
+            bool h = p == 0;
+            if (!h) {
+                uint32_t pk;
+                int32_t pc;
+                if (threadIdx.x > 0) {
+                    pk = sk[threadIdx.x - 1];
+                    pc = sc[threadIdx.x - 1];
+                } else {
+                    pk = keys[p - 1];
+                    const int k = e_bits >= 32 ? 0 : (int)(pk >> e_bits);
+                    pc = pk == key ? cids[k][rows[p - 1]] : c;
+                }
+                h = pk != key || pc != c;
+            }
+            head[p] = h ? 1 : 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -512,12 +538,19 @@ struct CrossPriors {
 
 // Statistic bins of every sorted element for target t and each prior q:
 // ts = (num 2^-y_shift + a P_q) / (den + a), in this order, its bin the
-// number of borders strictly below it, written to out[k][(t Q + q) ld + row].
+// number of borders strictly below it. They go to the element's record of
+// cpc bytes, rec[(k n + row) cpc + t Q + q], so that the Q bytes of one
+// element land in one cache line (the rows are in random order here: one
+// byte per column would cost a partial line write each). With counters
+// (size_at_start != NULL, on the last target) the record's byte counter_col
+// gets the counter bin of the element's group: floor(log2(size)) capped at
+// counter_bins - 1, the group starting at p - den[p].
 __global__ __launch_bounds__(256) void cross_scatter_kernel(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
-    const int64_t* __restrict__ den_s, const int64_t* __restrict__ num_s, int64_t N,
+    const int64_t* __restrict__ den_s, const int64_t* __restrict__ num_s, int64_t N, int64_t n,
     int32_t e_bits, int32_t y_shift, double a, CrossPriors pri, int32_t Q, int32_t t,
-    const double* __restrict__ tsb, int32_t ntsb, uint8_t* const* __restrict__ out, int64_t ld) {
+    const double* __restrict__ tsb, int32_t ntsb, const uint32_t* __restrict__ size_at_start,
+    int32_t counter_bins, int32_t counter_col, uint8_t* __restrict__ rec, int32_t cpc) {
     __shared__ double sb[256];
     sb[threadIdx.x] = (int32_t(threadIdx.x) < ntsb) ? tsb[threadIdx.x] : INFINITY;
     __syncthreads();
@@ -525,25 +558,29 @@ __global__ __launch_bounds__(256) void cross_scatter_kernel(
          p += int64_t(gridDim.x) * 256) {
         const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
         const int32_t r = rows[p];
+        const int64_t d = den_s[p];
         const double num = ldexp((double)num_s[p], -y_shift);
-        const double den = (double)den_s[p] + a;
-        uint8_t* o = out[k] + int64_t(t) * Q * ld + r;
+        const double den = (double)d + a;
+        uint8_t* o = rec + (int64_t(k) * n + r) * cpc;
         for (int q = 0; q < Q; ++q) {
             const double ts = (num + pri.ap[q]) / den;
             uint32_t pos = 0;
 #pragma unroll
             for (uint32_t step = 128; step >= 1; step >>= 1)
                 if (sb[pos + step - 1] < ts) pos += step;
-            o[int64_t(q) * ld] = (uint8_t)pos;
+            o[t * Q + q] = (uint8_t)pos;
+        }
+        if (size_at_start) {
+            const uint32_t c = size_at_start[p - d];
+            const int b = c ? 31 - __clz(c) : 0;
+            o[counter_col] = (uint8_t)min(b, counter_bins - 1);
         }
     }
 }
 
 // The counter statistic of every crossing's groups (Sec. 2): the group
 // of sorted element p starts at p - den[p] (den: its exclusive index in the
-// group); the group's last element records the group's size at the start,
-// every element then reads it and writes its bin, floor(log2(size)) capped
-// at n_bins - 1, to out[k][col ld + row].
+// group); the group's last element records the group's size at the start.
 __global__ void cross_group_size_kernel(const uint8_t* __restrict__ head,
                                         const int64_t* __restrict__ den_s, int64_t N,
                                         uint32_t* __restrict__ size_at_start) {
@@ -553,18 +590,20 @@ __global__ void cross_group_size_kernel(const uint8_t* __restrict__ head,
     }
 }
 
-__global__ void cross_counter_kernel(const uint32_t* __restrict__ keys,
-                                     const int32_t* __restrict__ rows,
-                                     const int64_t* __restrict__ den_s,
-                                     const uint32_t* __restrict__ size_at_start, int64_t N,
-                                     int32_t e_bits, int32_t n_bins, int32_t col,
-                                     uint8_t* const* __restrict__ out, int64_t ld) {
-    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
-         p += int64_t(gridDim.x) * blockDim.x) {
-        const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
-        const uint32_t c = size_at_start[p - den_s[p]];
-        const int b = c ? 31 - __clz(c) : 0;
-        out[k][int64_t(col) * ld + rows[p]] = (uint8_t)min(b, n_bins - 1);
+// Records to columns: out[k][c ld + row] = rec[(k n + row) cpc + c]; one
+// thread per row of crossing k = blockIdx.y, so every column's writes are
+// consecutive bytes.
+__global__ __launch_bounds__(256) void cross_unpack_kernel(const uint8_t* __restrict__ rec,
+                                                           int64_t n, int32_t cpc,
+                                                           uint8_t* const* __restrict__ out,
+                                                           int64_t ld) {
+    const int k = blockIdx.y;
+    uint8_t* ok = out[k];
+    const uint8_t* rk = rec + int64_t(k) * n * cpc;
+    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n;
+         r += int64_t(gridDim.x) * 256) {
+        const uint8_t* src = rk + r * cpc;
+        for (int c = 0; c < cpc; ++c) ok[int64_t(c) * ld + r] = src[c];
     }
 }
 
@@ -917,6 +956,8 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
                   o_v1 = take(4 * N), o_head = take(N), o_den = take(8 * N),
                   o_num = take(8 * N), o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
                   o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
+    const int32_t cpc = n_targets * n_priors + (counter_bins > 0 ? 1 : 0);
+    const int64_t o_rec = take(int64_t(cpc) * N);
     int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
@@ -925,6 +966,7 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     uint8_t* head = (uint8_t*)(w + o_head);
     int64_t* den_s = (int64_t*)(w + o_den);
     int64_t* num_s = (int64_t*)(w + o_num);
+    uint8_t* rec = (uint8_t*)(w + o_rec);
     int64_t* counts = (int64_t*)(w + o_cnt);
     int64_t* offs = (int64_t*)(w + o_off);
     SegPair* agg = (SegPair*)(w + o_agg);
@@ -962,6 +1004,12 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     dsrc.heads = head;
     rc = scan(dsrc, N, den_s);
     if (rc != CBH_OK) return rc;
+    uint32_t* size_at_start = nullptr;
+    if (counter_bins > 0) {
+        size_at_start = keys[cur ^ 1];     // free after the sort
+        cross_group_size_kernel<<<gs, 256, 0, s>>>(head, den_s, N, size_at_start);
+        CBH_LAUNCHED();
+    }
     for (int t = 0; t < n_targets; ++t) {
         ScanSrc nsrc{4, nullptr, keys[cur], rows[cur], y_num + int64_t(t) * n};
         nsrc.heads = head;
@@ -969,19 +1017,16 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
         if (rc != CBH_OK) return rc;
         CrossPriors pri;
         for (int q = 0; q < 8; ++q) pri.ap[q] = q < n_priors ? a * priors[t * n_priors + q] : 0.0;
-        cross_scatter_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, e_bits,
-                                                y_shift, a, pri, n_priors, t, ts_borders,
-                                                n_ts_borders, ts_bin_out, ld);
+        const bool last = t == n_targets - 1;
+        cross_scatter_kernel<<<gs, 256, 0, s>>>(
+            keys[cur], rows[cur], den_s, num_s, N, n, e_bits, y_shift, a, pri, n_priors, t,
+            ts_borders, n_ts_borders, last ? size_at_start : nullptr, counter_bins,
+            n_targets * n_priors, rec, cpc);
         CBH_LAUNCHED();
     }
-    if (counter_bins > 0) {
-        uint32_t* size_at_start = keys[cur ^ 1];     // free after the sort
-        cross_group_size_kernel<<<gs, 256, 0, s>>>(head, den_s, N, size_at_start);
-        cross_counter_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, size_at_start, N,
-                                                e_bits, counter_bins, n_targets * n_priors,
-                                                ts_bin_out, ld);
-        CBH_LAUNCHED();
-    }
+    const dim3 ug(grid_for(n, 256, std::max(1, ctx->num_cus * 8 / n_cross)), n_cross);
+    cross_unpack_kernel<<<ug, 256, 0, s>>>(rec, n, cpc, ts_bin_out, ld);
+    CBH_LAUNCHED();
     return CBH_OK;
 }
 
