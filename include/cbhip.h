@@ -444,7 +444,7 @@ int cbh_category_order(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, in
  *               n_targets * n_priors + 1 columns per crossing
  * Errors: CBH_EINVAL on bad arguments, CBH_EUNSUPPORTED when e_bits plus the
  * crossing index bits exceed 32 or n_cross * n >= 2^31, CBH_EOVERFLOW as
- * cbh_compute_ordered_ts. Uses workspace of about (33 + columns per crossing)
+ * cbh_compute_ordered_ts. Uses workspace of about (41 + columns per crossing)
  * * n_cross * n bytes. */
 int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
                              int32_t n_cross, const int32_t* const* c_order,

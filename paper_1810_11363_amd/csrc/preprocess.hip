@@ -166,6 +166,7 @@ __global__ void gather_keys_kernel(const int32_t* __restrict__ cat,
 //   2: v = y[vals[i]], head = key change
 //   3: v = 1, head = heads[i]
 //   4: v = y[vals[i]], head = heads[i]
+//   5: v = values[i], head = heads[i]
 struct ScanSrc {
     int mode;
     const int64_t* values;
@@ -187,7 +188,7 @@ __device__ __forceinline__ SegPair seg_op(SegPair a, SegPair b) {
 __device__ __forceinline__ SegPair load_elem(const ScanSrc& s, int64_t i) {
     if (s.mode == 0) return SegPair{s.values[i], i == 0};
     int head = s.mode >= 3 ? (int)s.heads[i] : ((i == 0) || (s.keys[i] != s.keys[i - 1]));
-    int64_t v = (s.mode == 1 || s.mode == 3) ? 1 : s.y[s.vals[i]];
+    int64_t v = (s.mode == 1 || s.mode == 3) ? 1 : (s.mode == 5 ? s.values[i] : s.y[s.vals[i]]);
     return SegPair{v, head};
 }
 
@@ -539,18 +540,21 @@ struct CrossPriors {
 // Statistic bins of every sorted element for target t and each prior q:
 // ts = (num 2^-y_shift + a P_q) / (den + a), in this order, its bin the
 // number of borders strictly below it. They go to the element's record of
-// cpc bytes, rec[(k n + row) cpc + t Q + q], so that the Q bytes of one
+// stride bytes, rec[(k n + row) stride + t Q + q], so that the bytes of one
 // element land in one cache line (the rows are in random order here: one
 // byte per column would cost a partial line write each). With counters
 // (size_at_start != NULL, on the last target) the record's byte counter_col
 // gets the counter bin of the element's group: floor(log2(size)) capped at
-// counter_bins - 1, the group starting at p - den[p].
+// counter_bins - 1, the group starting at p - den[p]. WHOLE: this pass
+// fills the whole record (one target), written as 32-bit words (the stride
+// a multiple of 4, at most 12 bytes).
+template <bool WHOLE>
 __global__ __launch_bounds__(256) void cross_scatter_kernel(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
     const int64_t* __restrict__ den_s, const int64_t* __restrict__ num_s, int64_t N, int64_t n,
     int32_t e_bits, int32_t y_shift, double a, CrossPriors pri, int32_t Q, int32_t t,
     const double* __restrict__ tsb, int32_t ntsb, const uint32_t* __restrict__ size_at_start,
-    int32_t counter_bins, int32_t counter_col, uint8_t* __restrict__ rec, int32_t cpc) {
+    int32_t counter_bins, int32_t counter_col, uint8_t* __restrict__ rec, int32_t stride) {
     __shared__ double sb[256];
     sb[threadIdx.x] = (int32_t(threadIdx.x) < ntsb) ? tsb[threadIdx.x] : INFINITY;
     __syncthreads();
@@ -561,19 +565,32 @@ __global__ __launch_bounds__(256) void cross_scatter_kernel(
         const int64_t d = den_s[p];
         const double num = ldexp((double)num_s[p], -y_shift);
         const double den = (double)d + a;
-        uint8_t* o = rec + (int64_t(k) * n + r) * cpc;
+        uint8_t* o = rec + (int64_t(k) * n + r) * stride;
+        uint32_t wd[3] = {0u, 0u, 0u};
         for (int q = 0; q < Q; ++q) {
             const double ts = (num + pri.ap[q]) / den;
             uint32_t pos = 0;
 #pragma unroll
             for (uint32_t step = 128; step >= 1; step >>= 1)
                 if (sb[pos + step - 1] < ts) pos += step;
-            o[t * Q + q] = (uint8_t)pos;
+            if constexpr (WHOLE) {
+                const int c = t * Q + q;
+                wd[c >> 2] |= pos << (8 * (c & 3));
+            } else {
+                o[t * Q + q] = (uint8_t)pos;
+            }
         }
         if (size_at_start) {
             const uint32_t c = size_at_start[p - d];
-            const int b = c ? 31 - __clz(c) : 0;
-            o[counter_col] = (uint8_t)min(b, counter_bins - 1);
+            const int b = min(c ? 31 - __clz(c) : 0, counter_bins - 1);
+            if constexpr (WHOLE)
+                wd[counter_col >> 2] |= uint32_t(b) << (8 * (counter_col & 3));
+            else
+                o[counter_col] = (uint8_t)b;
+        }
+        if constexpr (WHOLE) {
+            uint32_t* ow = reinterpret_cast<uint32_t*>(o);
+            for (int j = 0; j < (stride >> 2); ++j) ow[j] = wd[j];
         }
     }
 }
@@ -590,19 +607,31 @@ __global__ void cross_group_size_kernel(const uint8_t* __restrict__ head,
     }
 }
 
-// Records to columns: out[k][c ld + row] = rec[(k n + row) cpc + c]; one
-// thread per row of crossing k = blockIdx.y, so every column's writes are
-// consecutive bytes.
+// The target of every sorted element in sorted order, ys[p] = y[rows[p]]:
+// one random gather, so that both passes of the segmented scan read ys
+// contiguously.
+__global__ void cross_gather_y_kernel(const int32_t* __restrict__ rows,
+                                      const int64_t* __restrict__ y, int64_t N,
+                                      int64_t* __restrict__ ys) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < N;
+         p += int64_t(gridDim.x) * blockDim.x)
+        ys[p] = y[rows[p]];
+}
+
+// Records to columns: out[k][c ld + row] = rec[(k n + row) stride + c] for
+// the cpc columns; one thread per row of crossing k = blockIdx.y, so every
+// column's writes are consecutive bytes.
 __global__ __launch_bounds__(256) void cross_unpack_kernel(const uint8_t* __restrict__ rec,
                                                            int64_t n, int32_t cpc,
+                                                           int32_t stride,
                                                            uint8_t* const* __restrict__ out,
                                                            int64_t ld) {
     const int k = blockIdx.y;
     uint8_t* ok = out[k];
-    const uint8_t* rk = rec + int64_t(k) * n * cpc;
+    const uint8_t* rk = rec + int64_t(k) * n * stride;
     for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n;
          r += int64_t(gridDim.x) * 256) {
-        const uint8_t* src = rk + r * cpc;
+        const uint8_t* src = rk + r * stride;
         for (int c = 0; c < cpc; ++c) ok[int64_t(c) * ld + r] = src[c];
     }
 }
@@ -957,7 +986,10 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
                   o_num = take(8 * N), o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
                   o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
     const int32_t cpc = n_targets * n_priors + (counter_bins > 0 ? 1 : 0);
-    const int64_t o_rec = take(int64_t(cpc) * N);
+    // one target fills a record at once: 32-bit words (at most 9 bytes)
+    const bool whole = n_targets == 1;
+    const int32_t stride = whole ? (cpc + 3) / 4 * 4 : cpc;
+    const int64_t o_rec = take(int64_t(stride) * N), o_ys = take(8 * N);
     int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
@@ -967,6 +999,7 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     int64_t* den_s = (int64_t*)(w + o_den);
     int64_t* num_s = (int64_t*)(w + o_num);
     uint8_t* rec = (uint8_t*)(w + o_rec);
+    int64_t* ys = (int64_t*)(w + o_ys);
     int64_t* counts = (int64_t*)(w + o_cnt);
     int64_t* offs = (int64_t*)(w + o_off);
     SegPair* agg = (SegPair*)(w + o_agg);
@@ -1011,21 +1044,24 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
         CBH_LAUNCHED();
     }
     for (int t = 0; t < n_targets; ++t) {
-        ScanSrc nsrc{4, nullptr, keys[cur], rows[cur], y_num + int64_t(t) * n};
+        cross_gather_y_kernel<<<gs, 256, 0, s>>>(rows[cur], y_num + int64_t(t) * n, N, ys);
+        CBH_LAUNCHED();
+        ScanSrc nsrc{5, ys, nullptr, nullptr, nullptr};
         nsrc.heads = head;
         rc = scan(nsrc, N, num_s);
         if (rc != CBH_OK) return rc;
         CrossPriors pri;
         for (int q = 0; q < 8; ++q) pri.ap[q] = q < n_priors ? a * priors[t * n_priors + q] : 0.0;
         const bool last = t == n_targets - 1;
-        cross_scatter_kernel<<<gs, 256, 0, s>>>(
-            keys[cur], rows[cur], den_s, num_s, N, n, e_bits, y_shift, a, pri, n_priors, t,
-            ts_borders, n_ts_borders, last ? size_at_start : nullptr, counter_bins,
-            n_targets * n_priors, rec, cpc);
+        auto kern = whole ? cross_scatter_kernel<true> : cross_scatter_kernel<false>;
+        kern<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, n, e_bits, y_shift, a,
+                                pri, n_priors, t, ts_borders, n_ts_borders,
+                                last ? size_at_start : nullptr, counter_bins,
+                                n_targets * n_priors, rec, stride);
         CBH_LAUNCHED();
     }
     const dim3 ug(grid_for(n, 256, std::max(1, ctx->num_cus * 8 / n_cross)), n_cross);
-    cross_unpack_kernel<<<ug, 256, 0, s>>>(rec, n, cpc, ts_bin_out, ld);
+    cross_unpack_kernel<<<ug, 256, 0, s>>>(rec, n, cpc, stride, ts_bin_out, ld);
     CBH_LAUNCHED();
     return CBH_OK;
 }
