@@ -424,8 +424,9 @@ int cbh_category_order(cbh_ctx* ctx, const int32_t* cat, const int32_t* perm, in
  * as the bin of ts = (num * 2^-y_shift + a * prior) / (den + a) (double,
  * this order) among ts_borders: bit for bit cbh_compute_ordered_ts on any
  * dense numbering of the pairs. All crossings share one sort over
- * n_cross * n elements keyed by (k, e) on e_bits + ceil(log2 n_cross) bits,
- * the rows of each crossing taken in its feature's category order.
+ * n_cross * n elements keyed by (e, k) on e_bits + ceil(log2 n_cross) bits,
+ * the rows of each crossing taken in its feature's category order (sort
+ * passes over digits that are zero in every key copy instead of sorting).
  *   e_ids       device int32 [n], each in [0, 2^e_bits) (a value out of range
  *               is masked and reported by cbh_sync)
  *   c_order     device array of n_cross device int32 [n]: feature k's rows in

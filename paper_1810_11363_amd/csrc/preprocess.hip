@@ -75,10 +75,44 @@ constexpr int kSortItems = 16;
 constexpr int kTile = kSortThreads * kSortItems;  // 4096 keys per block
 
 // Per-tile digit counts, stored digit-major: counts[d * n_tiles + tile].
+// OR of all keys, as kOrParts per-block partial ORs (no zeroing needed): a
+// sort pass whose 8 digit bits are zero in every key is the identity.
+constexpr int kOrParts = 1024;
+
+__global__ __launch_bounds__(256) void key_or_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                     uint32_t* __restrict__ parts) {
+    __shared__ uint32_t wor[4];
+    uint32_t v = 0u;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256)
+        v |= keys[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) wor[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[blockIdx.x] = wor[0] | wor[1] | wor[2] | wor[3];
+}
+
+// Whether the pass at `shift` sorts anything: some key has a nonzero digit
+// there (always, without the partial ORs). Uniform over the block.
+// (256 threads, 4 parts each.)
+__device__ __forceinline__ bool pass_active(const uint32_t* parts, int shift) {
+    static_assert(kOrParts == 4 * kSortThreads, "four partial ORs per thread");
+    if (!parts) return true;
+    const uint4 q = reinterpret_cast<const uint4*>(parts)[threadIdx.x];
+    const uint32_t v = q.x | q.y | q.z | q.w;
+    return __syncthreads_or(((v >> shift) & 255u) != 0u) != 0;
+}
+
+// Digit counts of one tile of kTile keys (zeros for an identity pass).
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
     const uint32_t* __restrict__ keys, int64_t n, int shift, int64_t n_tiles,
-    int64_t* __restrict__ counts) {
+    int64_t* __restrict__ counts, const uint32_t* __restrict__ or_parts = nullptr) {
     __shared__ uint32_t c[256];
+    if (!pass_active(or_parts, shift)) {
+        counts[int64_t(threadIdx.x) * n_tiles + blockIdx.x] = 0;
+        return;
+    }
     c[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = int64_t(blockIdx.x) * kTile;
@@ -92,17 +126,28 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
 }
 
 // Scatter with stable in-tile ranks. Keys of a tile are visited in 16 rounds
-// of 256 (round-major, thread-minor), so rank order equals input order.
+// of 256 (round-major, thread-minor), so rank order equals input order. An
+// identity pass copies the tile.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals, int64_t n, int shift,
     int64_t n_tiles, const int64_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
-    int32_t* __restrict__ vals_out) {
+    int32_t* __restrict__ vals_out, const uint32_t* __restrict__ or_parts = nullptr) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
+    const int64_t base = int64_t(blockIdx.x) * kTile;
+    if (!pass_active(or_parts, shift)) {
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t i = base + j * kSortThreads + threadIdx.x;
+            if (i < n) {
+                keys_out[i] = keys[i];
+                vals_out[i] = vals[i];
+            }
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     run[threadIdx.x] = 0;
-    const int64_t base = int64_t(blockIdx.x) * kTile;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t goff = offsets[int64_t(threadIdx.x) * n_tiles + blockIdx.x];
     __shared__ int64_t gbase[256];
@@ -221,17 +266,40 @@ __device__ SegPair block_scan(SegPair x, SegPair* total) {
     return x;
 }
 
+// Inclusive segmented scan over the 64 lanes of a wave (lane order).
+__device__ __forceinline__ SegPair wave_incl_scan(SegPair x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        SegPair y = shfl_up_pair(x, d);
+        if (lane >= d) x = seg_op(y, x);
+    }
+    return x;
+}
+
+__device__ __forceinline__ SegPair lane63(SegPair x) {
+    return SegPair{__shfl(x.v, 63, 64), __shfl(x.f, 63, 64)};
+}
+
+// A tile of kTile elements: wave w takes the w-th quarter, 64 consecutive
+// elements per step (one per lane, so every load is coalesced), 16 steps.
+constexpr int kScanSteps = kTile / (4 * 64);
+
 __global__ __launch_bounds__(256) void seg_reduce_kernel(ScanSrc src, int64_t n,
                                                          SegPair* __restrict__ agg) {
-    const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(threadIdx.x) * kSortItems;
-    SegPair acc{0, 0};
-    for (int j = 0; j < kSortItems; ++j) {
-        int64_t i = base + j;
-        if (i < n) acc = seg_op(acc, load_elem(src, i));
+    __shared__ SegPair wagg[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t wbase = int64_t(blockIdx.x) * kTile + int64_t(wave) * (kTile / 4);
+    SegPair run{0, 0};
+    for (int j = 0; j < kScanSteps; ++j) {
+        const int64_t i = wbase + j * 64 + lane;
+        const SegPair x = wave_incl_scan(i < n ? load_elem(src, i) : SegPair{0, 0});
+        run = seg_op(run, lane63(x));
     }
-    SegPair tot;
-    block_scan(acc, &tot);
-    if (threadIdx.x == 0) agg[blockIdx.x] = tot;
+    if (lane == 0) wagg[wave] = run;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        agg[blockIdx.x] = seg_op(seg_op(seg_op(wagg[0], wagg[1]), wagg[2]), wagg[3]);
 }
 
 // Exclusive scan of the tile aggregates by one block; carry[t] is the value
@@ -259,33 +327,39 @@ __global__ __launch_bounds__(256) void seg_carry_kernel(const SegPair* __restric
     }
 }
 
-// Exclusive segmented scan written in sorted order.
+// Exclusive segmented scan written in sorted order (0 at a segment head),
+// the tile laid out over the waves as in seg_reduce_kernel: each step's
+// inclusive wave scan stays in registers until the prefix of the tile's
+// earlier elements (the carry, then the earlier waves) is known.
 __global__ __launch_bounds__(256) void seg_scan_kernel(ScanSrc src, int64_t n,
                                                        const int64_t* __restrict__ carry,
                                                        int64_t* __restrict__ out) {
-    const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(threadIdx.x) * kSortItems;
-    SegPair e[kSortItems];
-    SegPair acc{0, 0};
-    for (int j = 0; j < kSortItems; ++j) {
-        int64_t i = base + j;
-        e[j] = (i < n) ? load_elem(src, i) : SegPair{0, 0};
-        acc = seg_op(acc, e[j]);
-    }
-    SegPair tot;
-    SegPair inc = block_scan(acc, &tot);
-    // exclusive thread prefix, then seed with the tile carry
-    SegPair ex = shfl_up_pair(inc, 1);
-    __shared__ SegPair last[4];
+    __shared__ SegPair wagg[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 63) last[wave] = inc;
+    const int64_t wbase = int64_t(blockIdx.x) * kTile + int64_t(wave) * (kTile / 4);
+    SegPair inc[kScanSteps];
+    uint32_t heads = 0u;
+    SegPair run{0, 0};
+#pragma unroll
+    for (int j = 0; j < kScanSteps; ++j) {
+        const int64_t i = wbase + j * 64 + lane;
+        const SegPair x = i < n ? load_elem(src, i) : SegPair{0, 0};
+        heads |= uint32_t(x.f != 0) << j;
+        inc[j] = wave_incl_scan(x);
+        run = seg_op(run, lane63(inc[j]));
+    }
+    if (lane == 0) wagg[wave] = run;
     __syncthreads();
-    if (lane == 0) ex = (wave == 0) ? SegPair{0, 0} : last[wave - 1];
-    SegPair run = seg_op(SegPair{carry[blockIdx.x], 0}, ex);
-    for (int j = 0; j < kSortItems; ++j) {
-        int64_t i = base + j;
-        SegPair before = e[j].f ? SegPair{0, 1} : run;
-        if (i < n) out[i] = before.v;
-        run = seg_op(run, e[j]);
+    SegPair pre{carry[blockIdx.x], 0};
+    for (int w = 0; w < wave; ++w) pre = seg_op(pre, wagg[w]);
+#pragma unroll
+    for (int j = 0; j < kScanSteps; ++j) {
+        const int64_t i = wbase + j * 64 + lane;
+        SegPair ex = shfl_up_pair(inc[j], 1);
+        if (lane == 0) ex = SegPair{0, 0};
+        const SegPair before = seg_op(pre, ex);
+        if (i < n) out[i] = ((heads >> j) & 1u) ? 0 : before.v;
+        pre = seg_op(pre, lane63(inc[j]));
     }
 }
 
@@ -461,9 +535,11 @@ __global__ void key_heads_kernel(const uint32_t* __restrict__ keys, int64_t n,
 
 // Crossing k (blockIdx.y) of n rows: element j = k n + i takes row order[k][i]
 // (the rows in order of (category of crossing k, position)); its key is
-// (k << e_bits) | e[row], so a stable sort on the key orders the elements by
-// (crossing, e, category, position).
-__global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits,
+// (e[row] << k_bits) | k, so a stable sort on the key orders the elements by
+// (e, crossing, category, position): every (crossing, e, category) group is
+// contiguous and in position order. With e in the high bits, the passes over
+// e's unused high digits (a one-bit split value) find only zeros.
+__global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits, int32_t k_bits,
                                   const int32_t* const* __restrict__ order, int64_t n,
                                   uint32_t* __restrict__ keys, int32_t* __restrict__ rows,
                                   uint32_t* __restrict__ flags) {
@@ -484,7 +560,7 @@ __global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits,
             v &= emax;
         }
         const int64_t j = int64_t(k) * n + i;
-        keys[j] = (e_bits >= 32 ? 0u : ((uint32_t)k << e_bits)) | v;
+        keys[j] = (v << k_bits) | (uint32_t)k;
         rows[j] = r;
     }
     if (bad) atomicOr(flags, FLAG_BAD_INDEX);
@@ -496,8 +572,9 @@ __global__ void cross_keys_kernel(const int32_t* __restrict__ e, int32_t e_bits,
 // from LDS (from global memory for a block's first element).
 __global__ __launch_bounds__(256) void cross_heads_kernel(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
-    const int32_t* const* __restrict__ cids, int32_t e_bits, int64_t N,
+    const int32_t* const* __restrict__ cids, int32_t k_bits, int64_t N,
     uint8_t* __restrict__ head) {
+    const uint32_t kmask = (1u << k_bits) - 1u;
     __shared__ int32_t sc[256];
     __shared__ uint32_t sk[256];
     for (int64_t base = int64_t(blockIdx.x) * 256; base < N; base += int64_t(gridDim.x) * 256) {
@@ -506,8 +583,7 @@ __global__ __launch_bounds__(256) void cross_heads_kernel(
         int32_t c = 0;
         if (p < N) {
             key = keys[p];
-            const int k = e_bits >= 32 ? 0 : (int)(key >> e_bits);
-            c = cids[k][rows[p]];
+            c = cids[key & kmask][rows[p]];
         }
         sk[threadIdx.x] = key;
         sc[threadIdx.x] = c;
@@ -522,8 +598,7 @@ __global__ __launch_bounds__(256) void cross_heads_kernel(
                     pc = sc[threadIdx.x - 1];
                 } else {
                     pk = keys[p - 1];
-                    const int k = e_bits >= 32 ? 0 : (int)(pk >> e_bits);
-                    pc = pk == key ? cids[k][rows[p - 1]] : c;
+                    pc = pk == key ? cids[pk & kmask][rows[p - 1]] : c;
                 }
                 h = pk != key || pc != c;
             }
@@ -552,7 +627,7 @@ template <bool WHOLE>
 __global__ __launch_bounds__(256) void cross_scatter_kernel(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ rows,
     const int64_t* __restrict__ den_s, const int64_t* __restrict__ num_s, int64_t N, int64_t n,
-    int32_t e_bits, int32_t y_shift, double a, CrossPriors pri, int32_t Q, int32_t t,
+    int32_t k_bits, int32_t y_shift, double a, CrossPriors pri, int32_t Q, int32_t t,
     const double* __restrict__ tsb, int32_t ntsb, const uint32_t* __restrict__ size_at_start,
     int32_t counter_bins, int32_t counter_col, uint8_t* __restrict__ rec, int32_t stride) {
     __shared__ double sb[256];
@@ -560,7 +635,7 @@ __global__ __launch_bounds__(256) void cross_scatter_kernel(
     __syncthreads();
     for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < N;
          p += int64_t(gridDim.x) * 256) {
-        const int k = e_bits >= 32 ? 0 : (int)(keys[p] >> e_bits);
+        const int k = (int)(keys[p] & ((1u << k_bits) - 1u));
         const int32_t r = rows[p];
         const int64_t d = den_s[p];
         const double num = ldexp((double)num_s[p], -y_shift);
@@ -795,12 +870,14 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
     const int64_t o_k0 = take(4 * n), o_k1 = take(4 * n), o_v0 = take(4 * n),
                   o_v1 = take(4 * n), o_head = take(8 * n), o_excl = take(8 * n),
                   o_cnt = take(8 * cnt_elems), o_off = take(8 * cnt_elems),
-                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles);
+                  o_agg = take(sizeof(SegPair) * max_tiles), o_car = take(8 * max_tiles),
+                  o_or = take(4 * kOrParts);
     int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
     uint32_t* keys[2] = {(uint32_t*)(w + o_k0), (uint32_t*)(w + o_k1)};
     int32_t* rows[2] = {(int32_t*)(w + o_v0), (int32_t*)(w + o_v1)};
+    uint32_t* or_parts = (uint32_t*)(w + o_or);
     int64_t* head = (int64_t*)(w + o_head);
     int64_t* excl = (int64_t*)(w + o_excl);
     int64_t* counts = (int64_t*)(w + o_cnt);
@@ -818,15 +895,20 @@ int cbh_combine_categories(cbh_ctx* ctx, const int32_t* cat_a, const int32_t* ca
         return CBH_OK;
     };
     int cur = 0;
+    // passes over digits that are zero in every key (small category ids,
+    // a one-bit split value) copy instead of sorting
     auto sort32 = [&]() -> int {
+        key_or_kernel<<<kOrParts, 256, 0, s>>>(keys[cur], n, or_parts);
+        CBH_LAUNCHED();
         for (int shift = 0; shift < 32; shift += 8) {
-            radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], n, shift,
-                                                                          n_tiles, counts);
+            radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
+                keys[cur], n, shift, n_tiles, counts, or_parts);
             CBH_LAUNCHED();
             int r = scan(counts, cnt_elems, offs);
             if (r != CBH_OK) return r;
             radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
-                keys[cur], rows[cur], n, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1]);
+                keys[cur], rows[cur], n, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1],
+                or_parts);
             CBH_LAUNCHED();
             cur ^= 1;
         }
@@ -989,7 +1071,8 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     // one target fills a record at once: 32-bit words (at most 9 bytes)
     const bool whole = n_targets == 1;
     const int32_t stride = whole ? (cpc + 3) / 4 * 4 : cpc;
-    const int64_t o_rec = take(int64_t(stride) * N), o_ys = take(8 * N);
+    const int64_t o_rec = take(int64_t(stride) * N), o_ys = take(8 * N),
+                  o_or = take(4 * kOrParts);
     int rc = ensure_ws(ctx, off, stream);
     if (rc != CBH_OK) return rc;
     char* w = (char*)ctx->ws;
@@ -1000,6 +1083,7 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
     int64_t* num_s = (int64_t*)(w + o_num);
     uint8_t* rec = (uint8_t*)(w + o_rec);
     int64_t* ys = (int64_t*)(w + o_ys);
+    uint32_t* or_parts = (uint32_t*)(w + o_or);
     int64_t* counts = (int64_t*)(w + o_cnt);
     int64_t* offs = (int64_t*)(w + o_off);
     SegPair* agg = (SegPair*)(w + o_agg);
@@ -1014,24 +1098,29 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
         return CBH_OK;
     };
     const int gsx = grid_for(n, 256, std::max(1, ctx->num_cus * 8 / n_cross));
-    cross_keys_kernel<<<dim3(gsx, n_cross), 256, 0, s>>>(e_ids, e_bits, c_order, n, keys[0],
-                                                         rows[0], ctx->d_flags);
+    cross_keys_kernel<<<dim3(gsx, n_cross), 256, 0, s>>>(e_ids, e_bits, k_bits, c_order, n,
+                                                         keys[0], rows[0], ctx->d_flags);
     CBH_LAUNCHED();
     int cur = 0;
     const int key_bits = e_bits + k_bits;
+    // e values of a one-bit split leave the upper digits of e zero: those
+    // passes copy
+    key_or_kernel<<<kOrParts, 256, 0, s>>>(keys[0], N, or_parts);
+    CBH_LAUNCHED();
     for (int shift = 0; shift < key_bits; shift += 8) {
         radix_count_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(keys[cur], N, shift,
-                                                                      n_tiles, counts);
+                                                                      n_tiles, counts, or_parts);
         CBH_LAUNCHED();
         rc = scan(ScanSrc{0, counts, nullptr, nullptr, nullptr}, cnt_elems, offs);
         if (rc != CBH_OK) return rc;
         radix_scatter_kernel<<<(unsigned)n_tiles, kSortThreads, 0, s>>>(
-            keys[cur], rows[cur], N, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1]);
+            keys[cur], rows[cur], N, shift, n_tiles, offs, keys[cur ^ 1], rows[cur ^ 1],
+            or_parts);
         CBH_LAUNCHED();
         cur ^= 1;
     }
     const int gs = grid_for(N, 256, ctx->num_cus * 8);
-    cross_heads_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], c_ids, e_bits, N, head);
+    cross_heads_kernel<<<gs, 256, 0, s>>>(keys[cur], rows[cur], c_ids, k_bits, N, head);
     CBH_LAUNCHED();
     ScanSrc dsrc{3, nullptr, keys[cur], rows[cur], nullptr};
     dsrc.heads = head;
@@ -1054,7 +1143,7 @@ int cbh_ordered_ts_crossings(cbh_ctx* ctx, const int32_t* e_ids, int32_t e_bits,
         for (int q = 0; q < 8; ++q) pri.ap[q] = q < n_priors ? a * priors[t * n_priors + q] : 0.0;
         const bool last = t == n_targets - 1;
         auto kern = whole ? cross_scatter_kernel<true> : cross_scatter_kernel<false>;
-        kern<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, n, e_bits, y_shift, a,
+        kern<<<gs, 256, 0, s>>>(keys[cur], rows[cur], den_s, num_s, N, n, k_bits, y_shift, a,
                                 pri, n_priors, t, ts_borders, n_ts_borders,
                                 last ? size_at_start : nullptr, counter_bins,
                                 n_targets * n_priors, rec, stride);
