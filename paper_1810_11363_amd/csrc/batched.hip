@@ -236,6 +236,43 @@ __global__ __launch_bounds__(kHistThreads) void blpf_kernel(const DevProb* __res
                                  0u, lds);
 }
 
+// Leaf bit of rows [i0, i1) under split sp (i1 - i0 <= 8, i0 a multiple of
+// 8 from the problem's first row): eight rows of one half segment take one
+// 8-byte bins load and one 16-byte leaf load and store where aligned.
+__device__ __forceinline__ void apply_rows8(const uint8_t* const* bins, const int64_t* seg,
+                                           int F, cbh_split sp, uint16_t* leaf, int64_t i0,
+                                           int64_t i1, int level) {
+    int f = sp.feature, k = sp.border;
+    if (f < 0 || f >= F) {
+        if (level != 0) return;
+        f = 0;
+        k = 255;
+    }
+    const uint8_t* col = bins[f];
+    const int64_t stride = seg_stride_of(seg, f);
+    const uint32_t bit = 1u << level;
+    const uint8_t* half = seg_ptr(col, stride, i0);
+    if (i1 - i0 == 8 && (i0 & 7) == 0 && (reinterpret_cast<uintptr_t>(half) & 7) == 0 &&
+        (reinterpret_cast<uintptr_t>(leaf + i0) & 15) == 0) {
+        // eight rows of one half segment: one 8-byte bins load, one 16-byte
+        // leaf load and store
+        const uint2 b = *reinterpret_cast<const uint2*>(half);
+        uint4 l = level == 0 ? make_uint4(0u, 0u, 0u, 0u)
+                             : *reinterpret_cast<const uint4*>(leaf + i0);
+        uint32_t lw[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if ((int)(((r < 4 ? b.x : b.y) >> (8 * (r & 3))) & 255u) > k)
+                lw[r >> 1] |= bit << (16 * (r & 1));
+        *reinterpret_cast<uint4*>(leaf + i0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        return;
+    }
+    for (int64_t i = i0; i < i1; ++i) {
+        const uint32_t old = level == 0 ? 0u : leaf[i];
+        leaf[i] = (uint16_t)(old | (((int)*seg_ptr(col, stride, i) > k) ? bit : 0u));
+    }
+}
+
 __device__ __forceinline__ int find_owner(const int64_t* __restrict__ off, int P, int64_t gi) {
     int lo = 0, hi = P - 1;
     while (lo < hi) {
@@ -350,7 +387,7 @@ __global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__
         const int p = find_owner(row_off, P, gq);
         const DevProb pr = probs[p];
         const int64_t i0 = (gq - row_off[p]) * 8;
-        apply_rows(pr.bins, pr.seg, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
+        apply_rows8(pr.bins, pr.seg, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
                    min(pr.n, i0 + 8), level);
     }
 }
@@ -586,7 +623,7 @@ __global__ __launch_bounds__(kHistThreads) void bfused_kernel(FusedArgs a) {
             const int64_t x0 = (xi - a.x_off[k]) * kFusedApplyRows;
             const int64_t x1 = min(pr.n, x0 + kFusedApplyRows);
             for (int64_t i0 = x0 + int64_t(threadIdx.x) * 8; i0 < x1; i0 += int64_t(blockDim.x) * 8)
-                apply_rows(pr.bins, pr.seg, pr.F, sp, pr.leaf, i0, min(x1, i0 + 8), a.level);
+                apply_rows8(pr.bins, pr.seg, pr.F, sp, pr.leaf, i0, min(x1, i0 + 8), a.level);
         }
     }
     // the last block out resets the counters for the next launch

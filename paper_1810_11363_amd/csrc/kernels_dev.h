@@ -976,22 +976,6 @@ __device__ __forceinline__ void apply_rows(const uint8_t* const* bins, const int
     const uint8_t* col = bins[f];
     const int64_t stride = seg_stride_of(seg, f);
     const uint32_t bit = 1u << level;
-    const uint8_t* half = seg_ptr(col, stride, i0);
-    if (i1 - i0 == 8 && (i0 & 7) == 0 && (reinterpret_cast<uintptr_t>(half) & 7) == 0 &&
-        (reinterpret_cast<uintptr_t>(leaf + i0) & 15) == 0) {
-        // eight rows of one half segment: one 8-byte bins load, one 16-byte
-        // leaf load and store
-        const uint2 b = *reinterpret_cast<const uint2*>(half);
-        uint4 l = level == 0 ? make_uint4(0u, 0u, 0u, 0u)
-                             : *reinterpret_cast<const uint4*>(leaf + i0);
-        uint32_t lw[4] = {l.x, l.y, l.z, l.w};
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-            if ((int)(((r < 4 ? b.x : b.y) >> (8 * (r & 3))) & 255u) > k)
-                lw[r >> 1] |= bit << (16 * (r & 1));
-        *reinterpret_cast<uint4*>(leaf + i0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-        return;
-    }
     for (int64_t i = i0; i < i1; ++i) {
         const uint32_t old = level == 0 ? 0u : leaf[i];
         leaf[i] = (uint16_t)(old | (((int)*seg_ptr(col, stride, i) > k) ? bit : 0u));
