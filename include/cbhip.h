@@ -945,7 +945,10 @@ int cbh_batch_set_fused(cbh_batch* batch, int32_t fused);
 /* Finish the trees of every problem of the plan (as cbh_update_approx with the
  * level depth-1 histograms and splits); leaf_values is a host array [P] of
  * device pointers, each double [2^depth][K] (entries may not be NULL). With
- * init != 0 only the gradients are computed (tree 0). */
+ * init != 0 only the gradients are computed (tree 0). All problems go in two
+ * launches (leaf values, then approx and derivatives); the leaf value
+ * pointers are set on the device by small launches that carry them by value,
+ * so a captured iteration replays with the pointers it was captured with. */
 int cbh_batch_update(cbh_ctx* ctx, cbh_batch* batch, double lr, double l2,
                      double* const* leaf_values, int32_t init, void* stream);
 

@@ -23,6 +23,7 @@
 
 #include "common.h"
 #include "kernels_dev.h"
+#include "update_dev.h"
 
 namespace cbh {
 
@@ -154,6 +155,14 @@ struct cbh_batch {
     void* ws = nullptr;             // plan-owned partial tiles, feature winners and,
                                     // with subtraction, the second histogram of
                                     // every problem, sides and row codes
+    // the tree's second phase for every problem in two launches: per-problem
+    // leaf-solve and update arguments (leaf value pointers set per call) and
+    // the block prefixes of the two launches
+    cbh::SolveArgs* d_solve = nullptr;
+    cbh::UpdArgs* d_upd = nullptr;
+    int64_t* d_solve_off = nullptr;
+    int64_t* d_upd_off = nullptr;
+    int64_t solve_blocks = 0, upd_blocks = 0;
 };
 
 
@@ -390,6 +399,54 @@ __global__ __launch_bounds__(256) void bapply_kernel(const DevProb* __restrict__
         apply_rows8(pr.bins, pr.seg, pr.F, best[int64_t(p) * depth + level], pr.leaf, i0,
                    min(pr.n, i0 + 8), level);
     }
+}
+
+// ------------------------------------------- leaf solve and update, batched
+// Rows per block of the batched update (4 per thread).
+constexpr int64_t kUpdRows = 1024;
+
+// Leaf value pointers of up to 32 problems, passed by value (a captured
+// graph keeps the pointers it was captured with).
+struct ValsChunk {
+    double* v[32];
+    int32_t first, count;
+};
+
+__global__ void bset_vals_kernel(SolveArgs* __restrict__ sa, UpdArgs* __restrict__ ua,
+                                 ValsChunk c) {
+    const int j = threadIdx.x;
+    if (j < c.count) {
+        sa[c.first + j].values = c.v[j];
+        ua[c.first + j].values = c.v[j];
+    }
+}
+
+// Every problem's leaf values: block b belongs to the problem whose block
+// range holds it, one wave per (final leaf, class) as leaf_solve_kernel.
+__global__ __launch_bounds__(256) void bleaf_solve_kernel(const SolveArgs* __restrict__ sa,
+                                                          const int64_t* __restrict__ off,
+                                                          int32_t P, double l2) {
+    const int p = find_owner(off, P, blockIdx.x);
+    SolveArgs a = sa[p];
+    a.l2 = l2;
+    const int64_t t = (int64_t(blockIdx.x) - off[p]) * 4 + (threadIdx.x >> 6);
+    if (t >= (int64_t(1) << a.depth) * a.K) return;
+    leaf_solve_one(a, t, threadIdx.x & 63);
+}
+
+// Every problem's approx update and loss derivatives: kUpdRows rows of one
+// problem per block (add = 0: derivatives of the current approx only).
+template <int LOSS>
+__global__ __launch_bounds__(256) void bupdate_kernel(const UpdArgs* __restrict__ ua,
+                                                      const int64_t* __restrict__ off, int32_t P,
+                                                      double lr, int32_t add) {
+    const int p = find_owner(off, P, blockIdx.x);
+    UpdArgs a = ua[p];
+    a.lr = lr;
+    a.add = add;
+    const int64_t r0 = (int64_t(blockIdx.x) - off[p]) * kUpdRows;
+    const int64_t r1 = min(a.n, r0 + kUpdRows);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) update_row<LOSS>(a, i);
 }
 
 // ------------------------------------------------ one fused launch per level
@@ -1160,8 +1217,34 @@ int cbh_batch_create(cbh_ctx* ctx, const cbh_problem* probs, int32_t P, int32_t 
             all.push_back(d);
         }
     rc = upload(&b->d_probs, all);
+    // the second phase: static arguments of every problem
+    if (!rc) {
+        std::vector<SolveArgs> sv(P);
+        std::vector<UpdArgs> uv(P);
+        std::vector<int64_t> soff{0}, uoff{0};
+        for (int p = 0; p < P; ++p) {
+            const cbh_problem& pr = probs[p];
+            const int64_t leaves = int64_t(1) << pr.depth;
+            sv[p] = SolveArgs{hist[p], best + int64_t(p) * b->depth + (b->depth - 1),
+                              pr.grad_scale, nullptr, pr.depth, pr.n_features, pr.max_bins,
+                              pr.K, (int32_t)count_stat(&pr), out_prec(precision), 0.0};
+            uv[p] = UpdArgs{pr.leaf, nullptr, pr.label, pr.weight, pr.approx, pr.g, pr.h, pr.n,
+                            pr.K, pr.loss, 1, (uint16_t)(leaves - 1), 0.0};
+            soff.push_back(soff.back() + (leaves * pr.K + 3) / 4);
+            uoff.push_back(uoff.back() + (pr.n + kUpdRows - 1) / kUpdRows);
+        }
+        b->solve_blocks = soff.back();
+        b->upd_blocks = uoff.back();
+        rc = upload(&b->d_solve, sv);
+        if (!rc) rc = upload(&b->d_upd, uv);
+        if (!rc) rc = upload(&b->d_solve_off, soff);
+        if (!rc) rc = upload(&b->d_upd_off, uoff);
+    }
     if (rc) {
         free_levels(b);
+        for (void* q : {(void*)b->d_probs, (void*)b->d_solve, (void*)b->d_upd,
+                        (void*)b->d_solve_off, (void*)b->d_upd_off})
+            if (q) (void)hipFree(q);
         (void)hipFree(b->ws);
         delete b;
         return rc;
@@ -1174,7 +1257,9 @@ void cbh_batch_destroy(cbh_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     free_levels(b);
-    if (b->d_probs) (void)hipFree(b->d_probs);
+    for (void* q : {(void*)b->d_probs, (void*)b->d_solve, (void*)b->d_upd,
+                    (void*)b->d_solve_off, (void*)b->d_upd_off})
+        if (q) (void)hipFree(q);
     if (b->ws) (void)hipFree(b->ws);
     delete b;
 }
@@ -1204,19 +1289,38 @@ int cbh_batch_update(cbh_ctx* ctx, cbh_batch* b, double lr, double l2, double* c
     CBH_ARG(ctx && b && b->ctx == ctx, "bad ctx / batch");
     CBH_ARG(init || leaf_values != nullptr, "leaf_values is NULL");
     hipStream_t s = (hipStream_t)stream;
-    for (int p = 0; p < b->P; ++p) {
-        int rc;
-        if (init) {
-            rc = launch_update(ctx, &b->probs[p], nullptr, b->precision, nullptr, lr, l2,
-                               nullptr, nullptr, s);
-        } else {
+    if (!init) {
+        for (int p = 0; p < b->P; ++p)
             CBH_ARG(leaf_values[p] != nullptr, "leaf_values[%d] is NULL", p);
-            rc = launch_update(ctx, &b->probs[p], b->hist[p], b->precision,
-                               b->best + int64_t(p) * b->depth + (b->depth - 1), lr, l2,
-                               leaf_values[p], nullptr, s);
+        // the leaf value pointers (a graph captured here replays with these),
+        // then every problem's leaf values in one launch
+        for (int p0 = 0; p0 < b->P; p0 += 32) {
+            ValsChunk c;
+            c.first = p0;
+            c.count = std::min(32, b->P - p0);
+            for (int j = 0; j < 32; ++j) c.v[j] = j < c.count ? leaf_values[p0 + j] : nullptr;
+            bset_vals_kernel<<<1, 64, 0, s>>>(b->d_solve, b->d_upd, c);
         }
-        if (rc) return rc;
+        bleaf_solve_kernel<<<(unsigned)b->solve_blocks, 256, 0, s>>>(b->d_solve, b->d_solve_off,
+                                                                      b->P, l2);
+        CBH_LAUNCHED();
     }
+    const unsigned ub = (unsigned)b->upd_blocks;
+    const int32_t add = init ? 0 : 1;
+    switch (b->probs[0].loss) {
+        case CBH_LOSS_RMSE:
+            bupdate_kernel<CBH_LOSS_RMSE><<<ub, 256, 0, s>>>(b->d_upd, b->d_upd_off, b->P, lr, add);
+            break;
+        case CBH_LOSS_LOGLOSS:
+            bupdate_kernel<CBH_LOSS_LOGLOSS><<<ub, 256, 0, s>>>(b->d_upd, b->d_upd_off, b->P, lr,
+                                                                add);
+            break;
+        default:
+            bupdate_kernel<CBH_LOSS_MULTICLASS><<<ub, 256, 0, s>>>(b->d_upd, b->d_upd_off, b->P,
+                                                                   lr, add);
+            break;
+    }
+    CBH_LAUNCHED();
     return CBH_OK;
 }
 
