@@ -132,15 +132,46 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(
     const uint8_t* col = none ? nullptr : cols[sp.feature];
     const int64_t st = none ? 16 : seg_stride_of(seg, sp.feature);
     const int64_t p0 = int64_t(blockIdx.x) * kPartRows + int64_t(threadIdx.x) * 4;
-    uint32_t zeros = 0;
+    // this thread's 4 rows (one half of a 16-row segment's quarter): bins
+    // and leaf codes in one load each where aligned
+    uint32_t zbits = 0u, lf[4] = {0u, 0u, 0u, 0u};
+    const uint8_t* pb = col ? seg_ptr(col, st, p0) : nullptr;
+    if (p0 + 4 <= n && (!pb || (reinterpret_cast<uintptr_t>(pb) & 3) == 0) &&
+        (!code || (reinterpret_cast<uintptr_t>(code + p0) & 7) == 0)) {
+        const uint32_t bw = pb ? *reinterpret_cast<const uint32_t*>(pb) : 0u;
+        const uint2 cw = code ? *reinterpret_cast<const uint2*>(code + p0) : make_uint2(0u, 0u);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!(pb && (int)((bw >> (8 * j)) & 255u) > sp.border)) zbits |= 1u << j;
+            lf[j] = ((j < 2 ? cw.x : cw.y) >> (16 * (j & 1))) & 0xffffu;
+        }
+    } else {
+        for (int j = 0; j < 4; ++j) {
+            const int64_t pos = p0 + j;
+            if (pos >= n) break;
+            if (!split_bit(col, st, pos, sp.border)) zbits |= 1u << j;
+            lf[j] = code ? (uint32_t)code[pos] : 0u;
+        }
+    }
+    const uint32_t zeros = (uint32_t)__popc(zbits);
+    // per-leaf zero counts: the rows are in leaf order, so the lanes of a
+    // wave mostly share one leaf; each distinct leaf of a row slot gets one
+    // atomic add of its lanes' sum instead of one add per row
+    const int lane = threadIdx.x & 63;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int64_t pos = p0 + j;
-        if (pos >= n) break;
-        if (!split_bit(col, st, pos, sp.border)) {
-            ++zeros;
-            const uint32_t lf = code ? (uint32_t)code[pos] : 0u;
-            if (lds_cnt) atomicAdd(&zc[lf], 1u);
-            else atomicAdd(&zl[lf], 1u);
+        bool pending = (zbits >> j) & 1u;
+        while (__any(pending)) {
+            const uint64_t act = __ballot(pending);
+            const int leader = __ffsll((unsigned long long)act) - 1;
+            const uint32_t l0 = __shfl(lf[j], leader, 64);
+            const bool mine = pending && lf[j] == l0;
+            const uint32_t cnt = (uint32_t)__popcll(__ballot(mine));
+            if (lane == leader) {
+                if (lds_cnt) atomicAdd(&zc[l0], cnt);
+                else atomicAdd(&zl[l0], cnt);
+            }
+            pending = pending && !mine;
         }
     }
     uint32_t tot;
