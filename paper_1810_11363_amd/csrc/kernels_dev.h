@@ -962,26 +962,6 @@ __device__ inline void argmax_features(const FeatBest* __restrict__ fb, int F, i
     }
 }
 
-// leaf |= [bin > k] << level for rows [i0, i1) (level 0 overwrites); a
-// missing split (f < 0) leaves the bit clear.
-__device__ __forceinline__ void apply_rows(const uint8_t* const* bins, const int64_t* seg,
-                                           int F, cbh_split sp, uint16_t* leaf, int64_t i0,
-                                           int64_t i1, int level) {
-    int f = sp.feature, k = sp.border;
-    if (f < 0 || f >= F) {
-        if (level != 0) return;
-        f = 0;
-        k = 255;
-    }
-    const uint8_t* col = bins[f];
-    const int64_t stride = seg_stride_of(seg, f);
-    const uint32_t bit = 1u << level;
-    for (int64_t i = i0; i < i1; ++i) {
-        const uint32_t old = level == 0 ? 0u : leaf[i];
-        leaf[i] = (uint16_t)(old | (((int)*seg_ptr(col, stride, i) > k) ? bit : 0u));
-    }
-}
-
 // bytes per (slot, bin, feature) over all stats
 template <int PREC>
 __host__ __device__ constexpr uint32_t lpf_cell_bytes() { return PREC == CBH_PREC_INT16 ? 8u : 16u; }
