@@ -306,19 +306,57 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartMove m) 
     const int64_t nzb = nzb_sh;
     const int64_t nvb = min(kPartRows, m.n - P0);
     const int64_t nob = nvb - nzb;
-    // row ids, leaf indices and statistics
-    for (int i = threadIdx.x; i < nvb; i += kPartThreads) {
-        const int64_t pos = P0 + i;
-        const uint32_t bit = (segbits[i >> 4] >> (i & 15)) & 1u;
-        const int64_t d = base[bit] + rel[i];
-        m.dst_order[d] = m.src_order ? m.src_order[pos] : (int32_t)pos;
-        m.dst_code[d] = (uint16_t)((m.src_code ? (uint32_t)m.src_code[pos] : 0u) |
-                                   (bit << m.level));
+    // row ids, leaf indices and statistics: the thread's rows i = t + 256 q,
+    // each class's loads of all of them issued before their stores (source
+    // and destination are different copies)
+    {
+        constexpr int kQ = kPartRows / kPartThreads;
+        int64_t pos[kQ], dst[kQ];
+        bool ok[kQ];
+        uint32_t bitv[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int i = threadIdx.x + kPartThreads * q;
+            ok[q] = i < nvb;
+            pos[q] = P0 + i;
+            bitv[q] = ok[q] ? (segbits[i >> 4] >> (i & 15)) & 1u : 0u;
+            dst[q] = ok[q] ? base[bitv[q]] + rel[i] : 0;
+        }
+        const int32_t* __restrict__ so = m.src_order;
+        const uint16_t* __restrict__ sc = m.src_code;
+        int32_t ov[kQ];
+        uint32_t cv[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            ov[q] = ok[q] ? (so ? so[pos[q]] : (int32_t)pos[q]) : 0;
+            cv[q] = ok[q] && sc ? (uint32_t)sc[pos[q]] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            if (!ok[q]) continue;
+            m.dst_order[dst[q]] = ov[q];
+            m.dst_code[dst[q]] = (uint16_t)(cv[q] | (bitv[q] << m.level));
+        }
+        const float* __restrict__ sg = m.src_g;
+        const float* __restrict__ sh = m.src_h;
+        const uint32_t* __restrict__ sq = m.src_gq;
         for (int c = 0; c < m.K; ++c) {
-            const int64_t si = int64_t(c) * m.src_stride + pos, di = int64_t(c) * m.n_pad + d;
-            if (m.dst_g) m.dst_g[di] = m.src_g[si];
-            if (m.dst_h) m.dst_h[di] = m.src_h[si];
-            if (m.dst_gq) m.dst_gq[di] = m.src_gq[si];
+            const int64_t so_c = int64_t(c) * m.src_stride, do_c = int64_t(c) * m.n_pad;
+            float gv[kQ], hv[kQ];
+            uint32_t qv[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                gv[q] = ok[q] && m.dst_g ? sg[so_c + pos[q]] : 0.f;
+                hv[q] = ok[q] && m.dst_h ? sh[so_c + pos[q]] : 0.f;
+                qv[q] = ok[q] && m.dst_gq ? sq[so_c + pos[q]] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                if (!ok[q]) continue;
+                if (m.dst_g) m.dst_g[do_c + dst[q]] = gv[q];
+                if (m.dst_h) m.dst_h[do_c + dst[q]] = hv[q];
+                if (m.dst_gq) m.dst_gq[do_c + dst[q]] = qv[q];
+            }
         }
     }
     const int64_t run0[2] = {Zb, O0}, run1[2] = {Zb + nzb, O0 + nob};
