@@ -116,21 +116,29 @@ __device__ __forceinline__ void update_row(const UpdArgs& a, int64_t i) {
             }
         }
     } else {
+        // the K approx values loaded before any store (unrolled to the
+        // largest K, so the values stay in registers)
         double av[CBH_MAX_K];
+#pragma unroll
+        for (int c = 0; c < CBH_MAX_K; ++c) av[c] = c < K ? a.approx[int64_t(c) * a.n + i] : 0.0;
         double mx = -INFINITY;
-        for (int c = 0; c < K; ++c) {
-            double v = a.approx[int64_t(c) * a.n + i];
+#pragma unroll
+        for (int c = 0; c < CBH_MAX_K; ++c) {
+            if (c >= K) continue;
             if (a.add) {
-                v = v + a.lr * a.values[Lf * K + c];
-                a.approx[int64_t(c) * a.n + i] = v;
+                av[c] = av[c] + a.lr * a.values[Lf * K + c];
+                a.approx[int64_t(c) * a.n + i] = av[c];
             }
-            av[c] = v;
-            mx = v > mx ? v : mx;
+            mx = av[c] > mx ? av[c] : mx;
         }
         double z = 0.0;
-        for (int c = 0; c < K; ++c) z += exp(av[c] - mx);
+#pragma unroll
+        for (int c = 0; c < CBH_MAX_K; ++c)
+            if (c < K) z += exp(av[c] - mx);
         const int yc = (int)y;
-        for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int c = 0; c < CBH_MAX_K; ++c) {
+            if (c >= K) continue;
             const double p = exp(av[c] - mx) / z;
             const double gc = p - (c == yc ? 1.0 : 0.0), hc = p * (1.0 - p);
             a.g[int64_t(c) * a.n + i] = (float)(a.weight ? w * gc : gc);
