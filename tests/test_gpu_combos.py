@@ -96,6 +96,7 @@ CASES = {
     "multiclass": dict(loss=2, K=3, n=12007, seed=2),
     "logloss_counters": dict(loss=1, K=1, n=20011, seed=3, counters=True),
     "rmse_counters": dict(loss=0, K=1, n=30001, seed=4, counters=True),
+    "multiclass_counters": dict(loss=2, K=3, n=12007, seed=5, counters=True),
 }
 
 
@@ -235,12 +236,15 @@ def test_combination_tree_graphs_match_eager(cb):
             assert torch.equal(x, y), t
 
 
+@pytest.mark.parametrize("counters", [False, True])
 @pytest.mark.parametrize("n", [1, 33, 4099, 100003])
-def test_category_order_and_crossings(cb, n):
+def test_category_order_and_crossings(cb, n, counters):
     """cbh_category_order: rows in (category, position) order and dense ids,
     as the oracle's numbering; cbh_ordered_ts_crossings: every crossing's
     statistic bins (two targets, three priors) bit for bit those of the
-    oracle's Eq. (1) over the pair's dense ids."""
+    oracle's Eq. (1) over the pair's dense ids, and with counters the
+    crossing's counter column (the pair's rows, log2 bins) after them."""
+    from oracle import boost
     g0 = np.random.default_rng(n + 5)
     ctx = cb.cbh_create(0)
     try:
@@ -267,7 +271,9 @@ def test_category_order_and_crossings(cb, n):
             pos[perm] = np.arange(n)
             want_order = np.lexsort((pos, want_ids))     # by id, then position
             assert np.array_equal(orders[c].cpu().numpy(), want_order)
-        out = torch.full((C, T * Q, ld), 255, dtype=torch.uint8, device=d)
+        cpc = T * Q + (1 if counters else 0)
+        nbins = 33
+        out = torch.full((C, cpc, ld), 255, dtype=torch.uint8, device=d)
         ord_tab = torch.tensor([orders[c].data_ptr() for c in range(C)], dtype=torch.int64,
                                device=d)
         ids_tab = torch.tensor([ids[c].data_ptr() for c in range(C)], dtype=torch.int64, device=d)
@@ -276,7 +282,7 @@ def test_category_order_and_crossings(cb, n):
         cb.cbh_ordered_ts_crossings(ctx, gu.to_dev(e), e_bits, C, ord_tab, ids_tab, n,
                                     gu.to_dev(y), T, 0, 1, 1.0, Q,
                                     [p for pl in priors for p in pl], gu.to_dev(tb), tb.size,
-                                    out_tab, ld)
+                                    out_tab, ld, counter_bins=nbins if counters else 0)
         cb.cbh_sync(ctx)
         got = out.cpu().numpy()
         for c in range(C):
@@ -285,6 +291,8 @@ def test_category_order_and_crossings(cb, n):
                 for q in range(Q):
                     _, _, _, wb = oracle.ordered_ts(pid, perm, y[t], 0, 1.0, priors[t][q], tb)
                     assert np.array_equal(got[c, t * Q + q, :n], wb), (c, t, q)
+            if counters:
+                assert np.array_equal(got[c, T * Q, :n], boost.counter_bins(pid, nbins)), c
     finally:
         cb.cbh_destroy(ctx)
 
