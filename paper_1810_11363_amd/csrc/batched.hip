@@ -27,10 +27,6 @@
 
 namespace cbh {
 
-int launch_update(const cbh_ctx* ctx, const cbh_problem* p, const void* hist_last,
-                  int32_t precision, const cbh_split* last, double lr, double l2,
-                  double* leaf_values, int64_t* leaf_counts, hipStream_t s);
-
 // Device descriptor of one problem inside a plan.
 struct DevProb {
     const uint8_t* const* bins;
