@@ -1361,8 +1361,8 @@ def main():
         print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(sharding over several GPUs is not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                          "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if args.workload in ("c4", "apply", "combine", "packed", "combotrees"):
         a = resolve(args, args.workload)
