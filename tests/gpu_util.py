@@ -1,9 +1,9 @@
 """Helpers for GPU tests: device buffers, problem descriptors and error metrics.
 
-Tolerances follow the error model stated in the design doc: a float32 sum is judged
-by its error relative to the sum of the magnitudes of its terms (the
-summation condition number), because cancelling gradient sums make a plain
-relative error unbounded for any float32 accumulation.
+Tolerances follow one error model: a float32 sum is judged by its error
+relative to the sum of the magnitudes of its terms (the summation condition
+number), because cancelling gradient sums make a plain relative error
+unbounded for any float32 accumulation.
 """
 from __future__ import annotations
 
