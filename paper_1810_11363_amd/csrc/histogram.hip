@@ -287,11 +287,22 @@ __global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __rest
             const bool is_count = rmse && (u & 1);
             float fs = 0.f;
             uint32_t cs = 0;
-            if (ok)
-                for (int ch = slice; ch < n_chunks; ch += 4) {
+            if (ok) {
+                int ch = slice;
+                for (; ch + 12 < n_chunks; ch += 16) {
+                    uint32_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = part[(ch + 4 * q) * cw + u];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (is_count) cs += v[q]; else fs += __uint_as_float(v[q]);
+                    }
+                }
+                for (; ch < n_chunks; ch += 4) {
                     const uint32_t v = part[ch * cw + u];
                     if (is_count) cs += v; else fs += __uint_as_float(v);
                 }
+            }
             acc_a[slice][lane] = is_count ? (int64_t)cs : (int64_t)__float_as_uint(fs);
             __syncthreads();
             if (slice == 0 && ok) {
@@ -315,20 +326,35 @@ __global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __rest
             const bool is_count = rmse && (u & 1);
             float S = 0.f, E = 0.f;
             uint32_t cs = 0;
-            if (ok)
-                for (int ch = slice; ch < n_chunks; ch += 4) {
-                    const uint32_t hi_w = part[ch * cw + 2 * u];
+            if (ok) {
+                // this slice's chunks in order, four chunks' words loaded
+                // before their adds (the adds keep the order)
+                auto add1 = [&](uint32_t hi_w, uint32_t lo_w) {
                     if (is_count) {
                         cs += hi_w;
-                        continue;
+                        return;
                     }
                     const float hi = __uint_as_float(hi_w);
-                    const float lo = __uint_as_float(part[ch * cw + 2 * u + 1]);
+                    const float lo = __uint_as_float(lo_w);
                     const float t = S + hi;
                     const float bp = t - S;
                     E += ((S - (t - bp)) + (hi - bp)) + lo;
                     S = t;
+                };
+                int ch = slice;
+                for (; ch + 12 < n_chunks; ch += 16) {
+                    uint2 w[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        w[q] = *reinterpret_cast<const uint2*>(part + (ch + 4 * q) * cw + 2 * u);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) add1(w[q].x, w[q].y);
                 }
+                for (; ch < n_chunks; ch += 4) {
+                    const uint2 w = *reinterpret_cast<const uint2*>(part + ch * cw + 2 * u);
+                    add1(w.x, w.y);
+                }
+            }
             acc_a[slice][lane] = is_count ? (int64_t)cs : (int64_t)__float_as_uint(S);
             acc_b[slice][lane] = (int64_t)__float_as_uint(E);
             __syncthreads();
@@ -370,12 +396,24 @@ __global__ __launch_bounds__(256) void hist_reduce_kernel(const uint32_t* __rest
         } else {
             const uint64_t* P64 = reinterpret_cast<const uint64_t*>(part);
             int64_t gs = 0, hs = 0;
-            if (ok)
-                for (int ch = slice; ch < n_chunks; ch += 4) {
+            if (ok) {
+                int ch = slice;
+                for (; ch + 12 < n_chunks; ch += 16) {
+                    uint64_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = P64[(ch + 4 * q) * (cw / 2) + u];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        hs += (int64_t)(uint32_t)(v[q] & 0xffffffffull);
+                        gs += (int64_t)(int32_t)(uint32_t)(v[q] >> 32);
+                    }
+                }
+                for (; ch < n_chunks; ch += 4) {
                     const uint64_t v = P64[ch * (cw / 2) + u];
                     hs += (int64_t)(uint32_t)(v & 0xffffffffull);
                     gs += (int64_t)(int32_t)(uint32_t)(v >> 32);
                 }
+            }
             acc_a[slice][lane] = gs;
             acc_b[slice][lane] = hs;
             __syncthreads();
